@@ -1,0 +1,53 @@
+"""Seeded input generators: closed, outward, counted as stated."""
+import numpy as np
+import pytest
+
+from paper_2505_06932_amd import inputs as I
+from tests.pins import polyhedron_volume
+
+
+@pytest.mark.parametrize("L,nv,nt", [(0, 12, 20), (4, 2562, 5120), (6, 40962, 81920)])
+def test_icosphere_counts_closed(L, nv, nt):
+    v, t = I.icosphere(L)
+    m = I.Mesh.from_arrays(v, t)
+    assert (m.nv, m.nt) == (nv, nt)
+    assert I.mesh_edges_ok(m)
+    assert m.nv - 3 * m.nt // 2 + m.nt == 2  # Euler characteristic of a sphere
+    assert np.allclose(np.linalg.norm(v, axis=1), 1.0)
+    assert polyhedron_volume(v, t) > 0
+
+
+@pytest.mark.parametrize("f", [1, 2, 5, 16])
+def test_geodesic_counts_closed(f):
+    v, t = I.geodesic_sphere(f)
+    m = I.Mesh.from_arrays(v, t)
+    assert (m.nv, m.nt) == (10 * f * f + 2, 20 * f * f)
+    assert I.mesh_edges_ok(m)
+    assert polyhedron_volume(v, t) > 0
+
+
+def test_workloads_deterministic_and_sized():
+    g1, m1, c1 = I.make_workload("sphere_32", seed=3)
+    g2, m2, c2 = I.make_workload("sphere_32", seed=3)
+    assert np.array_equal(m1.x, m2.x) and np.array_equal(c1, c2)
+    assert (g1.nx, m1.nt) == (32, 5120)
+    assert np.all(np.abs(c1 - 0.5) <= g1.h)
+    g, m, c = I.make_workload("sphere_128", seed=0)
+    assert (g.nx, m.nt) == (128, 81920)
+    r = np.linalg.norm(m.verts() - c, axis=1)
+    assert abs(r.std() - 0.01 * g.h) < 0.1 * 0.01 * g.h  # radial noise of 0.01 h
+
+
+def test_simple_shapes_closed():
+    assert I.mesh_edges_ok(I.box_mesh([0.1, 0.2, 0.3], [0.4, 0.5, 0.9]))
+    assert I.mesh_edges_ok(I.tetra_mesh([0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]))
+    cm = I.subdivided_cube_mesh([0.2, 0.2, 0.2], 0.5, 3)
+    assert I.mesh_edges_ok(cm)
+    assert abs(polyhedron_volume(cm.verts(), cm.tris()) - 0.125) < 1e-15
+
+
+def test_psi_field_discretely_divergence_free():
+    g = I.Grid(16, 16, 8, 0.0, 0.0, 0.0, 1.0 / 16)
+    U, V, W = I.psi_face_velocity(g)
+    div = (U[:, :, 1:] - U[:, :, :-1] + V[:, 1:, :] - V[:, :-1, :] + W[1:] - W[:-1]) / g.h
+    assert np.abs(div).max() < 1e-12
