@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the interfacial-cell coupling on one MI355X.
+
+A step is one pass of the whole hot path over one front: cell lists, exact
+volume fractions (interfacial cells and the dense field), PPIC curvature,
+CSF force on the interfacial cells and vertex-velocity interpolation.  The
+workload is the 128^3 sphere (R = 0.3, icosphere with 6 subdivisions =
+81,920 triangles, radial noise 0.01 h, stream-function face velocities,
+sigma = 1).  Inputs are resident in device memory before timing starts.
+
+Timed region: W warm-up steps, then K steps replayed from a HIP graph of one
+step, bracketed by device synchronisation; value = interfacial cells x K /
+elapsed seconds.  After it, K eager steps with the library's timing events
+give the average duration of each kernel; the PPIC kernel's FP64 work per
+launch over that duration is the roofline figure.  The CPU oracle is then
+timed on the host on the same workload and its outputs are compared with the
+GPU's.  One JSON line goes to stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "interfacial cells/s (volume fraction+PPIC curvature), err vs FP64 oracle"
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic FP64 operations of the PPIC kernel (see the design doc for the
+# count): per ring triangle (centre distance), per weighted triangle (weight,
+# projection, moments, normal-equation update), per cell (vertex normal,
+# frame, 6x6 Cholesky with one refinement step, curvature, normal).
+FLOP_PER_RING_TRI = 17
+FLOP_PER_FIT_TRI = 187
+FLOP_PER_CELL = 530
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="sphere_128")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE={world})", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2505_06932_amd import ftc
+    from paper_2505_06932_amd import inputs as I
+    from paper_2505_06932_amd import pipeline
+
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    K, Wm = args.steps, args.warmup
+
+    grid, mesh, centre = I.make_workload(args.workload, args.seed)
+    U, V, W = I.psi_face_velocity(grid)
+    log(f"[bench] workload={args.workload} grid={grid.nx}^3 nv={mesh.nv} nt={mesh.nt}")
+    step = pipeline.CouplingStep(grid, mesh, U, V, W, sigma=1.0)
+    step.run()
+    torch.cuda.synchronize()
+    n_if, n_pairs = step.cells.count()
+    err = step.cells.last_device_error()
+    if err != ftc.FTC_OK:
+        raise ftc.FTCError(err, "first step")
+    log(f"[bench] interfacial cells={n_if} pieces={n_pairs}")
+
+    # ---------------------------------------------------------------- timed
+    launch = "eager" if args.eager else "hip_graph"
+    graph = None
+    if not args.eager:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step.run()
+        torch.cuda.synchronize()
+
+    def one():
+        if graph is not None:
+            graph.replay()
+        else:
+            step.run()
+
+    for _ in range(Wm):
+        one()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(K):
+        one()
+    ev1.record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1e3 * elapsed / K
+    value = n_if * K / elapsed
+    log(f"[bench] {launch}: {ms_per_step * 1e3:.1f} us/step wall, {gpu_ms / K * 1e3:.1f} us/step events, "
+        f"{value:.3e} cells/s")
+    if step.cells.last_device_error() != ftc.FTC_OK:
+        raise RuntimeError("device error latched during the timed steps")
+
+    # ----------------------------------------------------- per-kernel times
+    step.cells.set_timing(True)
+    sums = {k: 0.0 for k in ftc.KERNELS}
+    for _ in range(K):
+        step.run()
+        for k in ftc.KERNELS:
+            sums[k] += step.cells.kernel_time(k)
+    step.cells.set_timing(False)
+    kern_ms = {k: v / K for k, v in sums.items()}
+    log("[bench] kernel ms: " + ", ".join(f"{k}={v * 1e3:.1f}us" for k, v in kern_ms.items()))
+
+    res = step.results()
+    diag = res["diag"]
+    flops = float(np.sum(FLOP_PER_RING_TRI * diag[:, 1].astype(np.float64)
+                         + FLOP_PER_FIT_TRI * diag[:, 2].astype(np.float64) + FLOP_PER_CELL))
+    ppic_s = kern_ms["ppic"] * 1e-3
+    achieved = flops / ppic_s / 1e12
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"ppic_{args.workload}_traffic.json")
+    digest = source_digest(["paper_2505_06932_amd/csrc/ppic.hip", "paper_2505_06932_amd/csrc/ftc_device.hpp"])
+    if os.path.exists(tfile):
+        with open(tfile) as f:
+            t = json.load(f)
+        if t.get("source_digest") == digest:
+            traffic = t.get("bytes_per_launch")
+    roofline = {"kernel": "k_ppic", "bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": traffic,
+                "flop_per_launch": flops, "avg_launch_ms": kern_ms["ppic"], "source_digest": digest}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "interfacial cells/s", "n_gpus": 1, "steps": K,
+        "warmup": Wm, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "grid": [grid.nx, grid.ny, grid.nz], "triangles": mesh.nt,
+                   "vertices": mesh.nv, "interfacial_cells": n_if, "pieces": n_pairs, "seed": args.seed,
+                   "launch": launch, "step": "cell_lists+volume_fraction+ppic_curvature+csf_force+"
+                                             "interp_vertex_velocity"},
+        "gpu_ms_per_step_events": gpu_ms / K,
+        "kernel_ms": kern_ms,
+        "roofline": roofline,
+    }
+
+    # ---------------------------------------------------------- CPU oracle
+    if not args.no_cpu_baseline:
+        import oracle
+        log("[bench] timing the CPU oracle")
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            cells, offsets, tris = oracle.cell_lists(grid, mesh)
+            alpha, _ = oracle.volume_fraction(grid, mesh)
+            r = oracle.ppic(grid, mesh, cells)
+            force = oracle.csf(grid, alpha, cells, r["kappa"], 1.0)
+            u = oracle.interp(grid, mesh.x, mesh.y, mesh.z, U, V, W)
+            reps += 1
+            if time.perf_counter() - t0 > 10.0 or reps >= 20:
+                break
+        cpu_s = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": len(cells) * reps / cpu_s, "unit": "interfacial cells/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{reps} full steps of {args.workload} (cell lists, volume fraction, PPIC, CSF, "
+                      f"interpolation), {cpu_s:.1f} s; OpenMP over cells/columns/vertices, "
+                      f"cell lists and piece integrals serial; host nproc={os.cpu_count()}"}
+        ok = r["status"] == 0
+        same_lists = bool(np.array_equal(res["cell_ids"], cells) and np.array_equal(res["tri_ids"], tris))
+        out["err_vs_oracle"] = {
+            "cell_lists_identical": same_lists,
+            "decisions_identical": bool(np.array_equal(res["diag"], r["diag"])),
+            "max_abs_alpha": float(np.abs(res["alpha"] - alpha).max()),
+            "max_rel_kappa": float(np.max(np.abs(res["kappa"][ok] - r["kappa"][ok]) / np.abs(r["kappa"][ok]))),
+            "max_rel_force": float(np.abs(res["force"][ok] - force[ok]).max() / np.abs(force[ok]).max()),
+            "max_rel_velocity": float(np.abs(res["u"] - u).max() / np.abs(u).max()),
+            "volume_rel_err": float(abs(math.fsum(res["alpha"].ravel()) * grid.h ** 3 /
+                                        _vpoly(mesh, centre) - 1.0)),
+        }
+        log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} cells/s on {oracle.threads()} threads; "
+            f"errors {out['err_vs_oracle']}")
+    print(json.dumps(out), flush=True)
+
+
+def _vpoly(mesh, centre):
+    import numpy as np
+    v = mesh.verts() - centre
+    t = mesh.tris()
+    a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+    return math.fsum(np.einsum("ij,ij->i", a, np.cross(b, c)) / 6.0)
+
+
+if __name__ == "__main__":
+    main()

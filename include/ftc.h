@@ -1,0 +1,210 @@
+/*
+ * ftc.h -- C ABI of the MI355X (gfx950) library for the sharp front-tracking
+ * coupling restricted to interfacial cells (Gorges, Evrard, Chiodi,
+ * van Wachem, Denner, "Sharp front tracking with geometric interface
+ * reconstruction", arXiv 2505.06932, section 3).
+ *
+ * Conventions for every call below
+ * --------------------------------
+ * - Pointers are DEVICE memory owned by the caller unless marked [host].
+ * - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   Calls only validate host-side arguments and enqueue kernels on `stream`;
+ *   none allocates, frees or synchronises (except ftc_cells_count and
+ *   ftc_last_device_error, which say so), so a sequence of calls can be
+ *   captured into a HIP graph.
+ * - Grid: cubic cells of edge h; cell (i,j,k) is the half-open box
+ *   [x0+i*h, x0+(i+1)*h) x [y0+j*h, ...) x [z0+k*h, ...), linear id
+ *   i + nx*(j + ny*k).  Dense cell fields are FP64 [nz][ny][nx].
+ * - Front: closed triangulated surface, vertices as FP64 SoA x,y,z[nv],
+ *   triangles as int32 corner indices t0,t1,t2[nt], counter-clockwise seen
+ *   from outside (normals point away from the enclosed fluid, the fluid
+ *   where the indicator is 1, paper section 2).  Every vertex must lie at
+ *   least 2 cells inside the grid.
+ * - Per-interfacial-cell outputs are indexed like the cell list
+ *   (ascending linear cell id) and sized to the workspace cell capacity.
+ * - Return values are ftc_status codes.  Host-detectable argument errors
+ *   return immediately and enqueue nothing.  Conditions only the device can
+ *   see (front outside the grid margin, open front, capacity overflow) are
+ *   latched in the workspace and read by ftc_last_device_error; when one is
+ *   latched the outputs of that call are unspecified but no write goes past
+ *   any buffer.
+ * - No C++ exception crosses this boundary.
+ */
+#ifndef FTC_H
+#define FTC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FTC_OK = 0,
+  FTC_EINVAL = -1,    /* bad argument (null pointer, size <= 0, h <= 0, ...) */
+  FTC_EDOMAIN = -2,   /* a vertex lies outside the grid minus a 2-cell margin */
+  FTC_EMESH = -3,     /* front is not closed or not outward oriented          */
+  FTC_ECAPACITY = -4, /* more pairs or cells than the workspace holds         */
+  FTC_ENOMEM = -5,    /* device allocation failed (ftc_cells_create only)     */
+  FTC_EHIP = -6       /* a HIP runtime call failed                            */
+} ftc_status;
+
+typedef struct {
+  int32_t nx, ny, nz; /* cells per axis, each > 4                       */
+  double x0, y0, z0;  /* grid origin (lower corner of cell (0,0,0))      */
+  double h;           /* cell edge, > 0                                  */
+} ftc_grid;
+
+typedef struct {
+  int32_t nv, nt;              /* vertex and triangle counts, > 0        */
+  const double *x, *y, *z;     /* [nv] device                            */
+  const int32_t *t0, *t1, *t2; /* [nt] device, corner indices in [0, nv) */
+} ftc_mesh;
+
+/* Volume-fit parameters (paper section 3.2, after Eq. Wendland): Wendland
+   support radius delta = delta_over_h * h (paper: 2.5), the `rings`-ring of
+   triangles around the closest front vertex (paper: 3), the support grown by
+   the factor `grow` at most `max_iter` times until at least `n_min`
+   triangles carry non-zero weight (paper: "24 to 48"). */
+typedef struct {
+  double delta_over_h;
+  int32_t rings;
+  int32_t n_min;
+  double grow;
+  int32_t max_iter;
+} ftc_ppic_params;
+
+/* Per-cell status bits written by ftc_ppic_curvature. */
+#define FTC_CELL_RANK 1u     /* normal equations singular: kappa, n, coeff = NaN */
+#define FTC_CELL_OVERFLOW 2u /* ring larger than the kernel's stencil limit      */
+
+/* Opaque workspace: the cell lists and every scratch buffer the calls use,
+   allocated once for one grid and maximum front sizes. */
+typedef struct ftc_cells ftc_cells;
+
+/* Allocate a workspace on the current HIP device for `grid` [host] and fronts
+   of up to nv_capacity vertices and nt_capacity triangles, holding up to
+   pair_capacity (cell, triangle) pieces and cell_capacity interfacial
+   cells.  Device memory is about 17 B x pairs + 110 B x cells +
+   40 B x triangles + 30 B x vertices + 12 B x (nx*ny) + nx*ny*nz/4 B.
+   Returns FTC_EINVAL, FTC_ENOMEM or FTC_OK; *out is NULL on failure. */
+ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_capacity,
+                            int32_t nt_capacity, int64_t pair_capacity, int32_t cell_capacity);
+
+/* Free a workspace (synchronises the device first).  NULL is a no-op. */
+void ftc_cells_destroy(ftc_cells* cells);
+
+/* Build the interfacial-cell lists (paper section 3.2: the interfacial cells
+   are those containing the front; sections 1 and 3: the coupling is
+   restricted to them).  A (cell, triangle) pair exists when the triangle's
+   intersection with the closed cell has positive area; a triangle lying
+   exactly in a grid plane belongs to the cell above that plane.  Result, in
+   the workspace: interfacial cells in ascending linear id and, per cell, its
+   triangles in ascending id (CSR).  `grid` must equal the workspace's grid.
+   Latches FTC_EDOMAIN or FTC_ECAPACITY on the device. */
+ftc_status ftc_build_cell_lists(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
+                                void* stream);
+
+/* Copy the interfacial-cell and pair counts of the last build to the host.
+   Synchronises `stream`. */
+ftc_status ftc_cells_count(const ftc_cells* cells, int32_t* n_interfacial /*[host]*/,
+                           int64_t* n_pairs /*[host]*/, void* stream);
+
+/* Device pointers into the workspace: cell_ids[cell_capacity],
+   offsets[cell_capacity+1], tri_ids[pair_capacity], and d_counts[2] =
+   {interfacial cells, pairs} (int32, device), valid until the next build.
+   Any output pointer may be NULL. */
+ftc_status ftc_cells_view(const ftc_cells* cells, const int32_t** cell_ids, const int32_t** offsets,
+                          const int32_t** tri_ids, const int32_t** d_counts);
+
+/* Exact volume fraction alpha_C = |Omega cap C| / h^3 (paper section 3.2,
+   definition of the discrete indicator; polyhedron intersection; full and
+   empty cells), where Omega is the region enclosed by the triangulated
+   front.  By the divergence theorem along z columns: for an interfacial
+   cell, the sum over its pieces p of the integral of (z - z_lo) n_z dA plus
+   h times the wetted area of its upper face, which is the sum of the
+   integrals of n_z dA over all pieces strictly above it in the column.
+   Cells without pieces get 0 or 1 from the same column sum.
+   alpha_if[cell_capacity]: alpha of each interfacial cell (cell-list order).
+   alpha_dense[nx*ny*nz] or NULL: every cell of the grid is written.
+   Latches FTC_EMESH if a column sum is not 0 or h^2 where no piece is
+   (open or inverted front). */
+ftc_status ftc_volume_fraction(const ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
+                               double* alpha_if, double* alpha_dense, void* stream);
+
+/* PPIC curvature (paper section 3.2): for each interfacial cell, the front
+   vertex closest to the cell centre (lowest index on ties), its area-weighted
+   normal n, tangents completing a right-handed frame; the ring neighbourhood
+   of triangles around that vertex; Wendland weights of the triangle-centre
+   distances (Eq. Wendland) with the support grown per `params`; the weighted
+   least-squares volume fit of the paraboloid z = a1 + a2 x + a3 y + a4 x^2 +
+   a5 xy + a6 y^2 (Eqs. volumefit, volumefit2) in that frame; then at the
+   frame origin the mean curvature kappa = 2H (positive for a sphere seen from
+   outside, kappa = 2/r; section 4.1 and appendix A) and the interface normal.
+   Outputs (each [cell_capacity], cell-list order): kappa; nx, ny, nz (unit
+   interface normal, outward); coeff [6][cell_capacity] or NULL (a1..a6 in
+   world units, frame origin at the cell centre); cell_status or NULL
+   (FTC_CELL_* bits); diag [4][cell_capacity] or NULL (closest vertex, ring
+   triangle count, triangles with non-zero weight, support adjustments).
+   `params` [host] NULL means the paper's values {2.5, 3, 24, 1.1, 16}. */
+ftc_status ftc_ppic_curvature(const ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
+                              const ftc_ppic_params* params, double* kappa, double* nx, double* ny,
+                              double* nz, double* coeff, int32_t* cell_status, int32_t* diag,
+                              void* stream);
+
+/* Continuum surface force (paper section 3.3, Eq. csf): S = sigma kappa
+   grad(alpha) on the interfacial cells only, grad(alpha) by central
+   differences of the dense alpha field (alpha_dense[nx*ny*nz]) with spacing
+   h.  fx, fy, fz [cell_capacity], cell-list order. */
+ftc_status ftc_csf_force(const ftc_cells* cells, const ftc_grid* grid, const double* alpha_dense,
+                         const double* kappa, double sigma, double* fx, double* fy, double* fz,
+                         void* stream);
+
+/* Divergence-preserving interpolation (paper section 3.1) of staggered
+   normal face velocities to the front vertices: inside the cell holding the
+   vertex, linear interpolation between opposite faces plus transverse-
+   gradient terms (central differences over the neighbouring faces of the
+   same orientation) and the quadratic correction that makes the
+   interpolant's divergence equal the cell's discrete divergence.
+   U[nz][ny][nx+1], V[nz][ny+1][nx], W[nz+1][ny][nx] (x fastest).
+   ux, uy, uz [mesh->nv].  A vertex whose cell is within 1 cell of the grid
+   boundary gets NaN and latches FTC_EDOMAIN.  `cells` supplies the error
+   latch only. */
+ftc_status ftc_interp_vertex_velocity(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
+                                      const double* U, const double* V, const double* W, double* ux,
+                                      double* uy, double* uz, void* stream);
+
+/* Read and clear the device-latched error of the workspace: *code [host]
+   receives FTC_OK or the first of FTC_ECAPACITY, FTC_EDOMAIN, FTC_EMESH
+   that was latched.  Synchronises `stream`. */
+ftc_status ftc_last_device_error(ftc_cells* cells, int32_t* code, void* stream);
+
+/* Kernel timing, for measurement only.  While enabled, every call records a
+   HIP event on its stream immediately before and after its dominant kernel;
+   ftc_kernel_time then returns the interval of the last such launch.  Keep
+   it disabled while capturing a graph (event records are not captured). */
+typedef enum {
+  FTC_KERNEL_TRI_COUNT = 0,   /* cell lists: per-triangle clip and count      */
+  FTC_KERNEL_VF_PIECES = 1,   /* volume fraction: per-piece integrals         */
+  FTC_KERNEL_COL_WALK = 2,    /* volume fraction: column sums                 */
+  FTC_KERNEL_DENSE_ALPHA = 3, /* volume fraction: dense field write           */
+  FTC_KERNEL_PPIC = 4,        /* PPIC: closest vertex, ring, fit, curvature   */
+  FTC_KERNEL_CSF = 5,         /* CSF force                                    */
+  FTC_KERNEL_INTERP = 6,      /* vertex velocity interpolation                */
+  FTC_KERNEL_COUNT = 7
+} ftc_kernel;
+
+/* Enable (1) or disable (0) the timing events of a workspace. */
+ftc_status ftc_set_timing(ftc_cells* cells, int32_t enable);
+
+/* Milliseconds of the last timed launch of `kernel` (an ftc_kernel value),
+   into *ms [host]; waits for that launch to finish.  FTC_EINVAL if the kernel
+   was never timed. */
+ftc_status ftc_kernel_time(const ftc_cells* cells, int32_t kernel, float* ms);
+
+/* Static text for a status code. */
+const char* ftc_status_str(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

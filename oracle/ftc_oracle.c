@@ -84,6 +84,8 @@ typedef struct { int n; double v[12][3]; } poly_t;
 /* Point where segment p-q crosses the plane x_d = c.  The segment is taken
    from its endpoint with the smaller x_d, so the point does not depend on the
    direction in which the polygon walks the edge. */
+/* A convex polygon cut by one plane gains at most one corner (nine after six
+   planes); the capacity checks below only guard memory. */
 static void cross_point(const double* p, const double* q, int d, double c, double* r) {
   const double* a = p[d] < q[d] ? p : q;
   const double* b = p[d] < q[d] ? q : p;
@@ -99,6 +101,7 @@ static void clip_half(const poly_t* in, poly_t* out, int d, double c, int upper)
     const double* q = in->v[(e + 1) % in->n];
     int pin = upper ? (p[d] <= c) : (p[d] >= c);
     int qin = upper ? (q[d] <= c) : (q[d] >= c);
+    if (out->n + 2 > 12) break;
     if (pin && qin) {
       memcpy(out->v[out->n++], q, sizeof(double) * 3);
     } else if (pin) {

@@ -1,0 +1,289 @@
+// api.hip -- the C ABI declared in include/ftc.h: argument validation,
+// workspace allocation and the launch sequence of each call.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "ftc_ws.hpp"
+
+using ftc::Grid;
+using ftc::Mesh;
+
+namespace {
+
+bool grid_valid(const ftc_grid* g) {
+  return g && g->nx > 4 && g->ny > 4 && g->nz > 4 && g->h > 0.0 && isfinite(g->h) && isfinite(g->x0) &&
+         isfinite(g->y0) && isfinite(g->z0);
+}
+
+bool same_grid(const Grid& a, const ftc_grid* b) {
+  return a.nx == b->nx && a.ny == b->ny && a.nz == b->nz && a.x0 == b->x0 && a.y0 == b->y0 && a.z0 == b->z0 &&
+         a.h == b->h;
+}
+
+Grid to_grid(const ftc_grid* g) { return Grid{g->nx, g->ny, g->nz, g->x0, g->y0, g->z0, g->h}; }
+
+bool mesh_valid(const ftc_mesh* m) {
+  return m && m->nv > 0 && m->nt > 0 && m->x && m->y && m->z && m->t0 && m->t1 && m->t2;
+}
+
+Mesh to_mesh(const ftc_mesh* m) { return Mesh{m->nv, m->nt, m->x, m->y, m->z, m->t0, m->t1, m->t2}; }
+
+bool on_device(const ftc_cells* c) {
+  int dev = -1;
+  return c && hipGetDevice(&dev) == hipSuccess && dev == c->device;
+}
+
+ftc_status hip_status(hipError_t e) { return e == hipSuccess ? FTC_OK : FTC_EHIP; }
+
+template <class T>
+hipError_t alloc(T** p, int64_t n, void** registry, int& nreg) {
+  *p = nullptr;
+  void* raw = nullptr;
+  hipError_t e = hipMalloc(&raw, (size_t)std::max<int64_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  registry[nreg++] = raw;
+  *p = static_cast<T*>(raw);
+  return hipSuccess;
+}
+
+constexpr int kMaxBuffers = 48;
+
+}  // namespace
+
+struct ftc_cells_owner {
+  ftc_cells ws;
+  void* buffers[kMaxBuffers];
+  int nbuf;
+};
+
+extern "C" {
+
+ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_capacity, int32_t nt_capacity,
+                            int64_t pair_capacity, int32_t cell_capacity) {
+  if (!out) return FTC_EINVAL;
+  *out = nullptr;
+  if (!grid_valid(grid) || nv_capacity <= 0 || nt_capacity <= 0 || pair_capacity <= 0 || cell_capacity <= 0)
+    return FTC_EINVAL;
+  const int64_t ncell = (int64_t)grid->nx * grid->ny * grid->nz;
+  const int64_t nwords = (ncell + 31) / 32;
+  const int64_t ncol = (int64_t)grid->nx * grid->ny;
+  // int32 cell ids and offsets; every scanned array within the scan limit
+  if (ncell >= ((int64_t)1 << 31) || pair_capacity >= ((int64_t)1 << 31) || nwords > ftc::kScanMax ||
+      ncol > ftc::kScanMax || nt_capacity > ftc::kScanMax || nv_capacity > ftc::kScanMax ||
+      cell_capacity > ftc::kScanMax || (int64_t)nt_capacity * 3 >= ((int64_t)1 << 31))
+    return FTC_EINVAL;
+
+  ftc_cells_owner* o = new (std::nothrow) ftc_cells_owner();
+  if (!o) return FTC_ENOMEM;
+  ftc_cells& w = o->ws;
+  if (hipGetDevice(&w.device) != hipSuccess) {
+    delete o;
+    return FTC_EHIP;
+  }
+  w.grid = to_grid(grid);
+  w.ncell = ncell;
+  w.nwords = nwords;
+  w.ncol = ncol;
+  w.nv_cap = nv_capacity;
+  w.nt_cap = nt_capacity;
+  w.cell_cap = cell_capacity;
+  w.pair_cap = pair_capacity;
+  const int64_t P = pair_capacity, Cc = cell_capacity, Tc = nt_capacity, Vc = nv_capacity;
+  void** reg = o->buffers;
+  int& n = o->nbuf;
+  n = 0;
+  hipError_t e = hipSuccess;
+#define FTC_ALLOC(field, count) \
+  if (e == hipSuccess) e = alloc(&w.field, (count), reg, n)
+  FTC_ALLOC(counters, ftc::C_COUNT);
+  FTC_ALLOC(scan_tmp, ftc::kScanMaxBlocks);
+  FTC_ALLOC(bitmap, nwords);
+  FTC_ALLOC(word_off, nwords + 1);
+  FTC_ALLOC(tri_off, Tc + 1);
+  FTC_ALLOC(tri_mask, Tc);
+  FTC_ALLOC(pair_cell, P);
+  FTC_ALLOC(pair_tri, P);
+  FTC_ALLOC(cell_ids, Cc);
+  FTC_ALLOC(offsets, Cc + 1);
+  FTC_ALLOC(cursor, Cc);
+  FTC_ALLOC(tri_ids, P);
+  FTC_ALLOC(slot_cell, P);
+  FTC_ALLOC(piece_flux, P);
+  FTC_ALLOC(piece_vol, P);
+  FTC_ALLOC(col_off, ncol + 1);
+  FTC_ALLOC(col_cursor, ncol);
+  FTC_ALLOC(col_cells, Cc);
+  FTC_ALLOC(col_k, Cc);
+  FTC_ALLOC(col_alpha, Cc);
+  FTC_ALLOC(col_below, Cc);
+  FTC_ALLOC(vt_off, Vc + 1);
+  FTC_ALLOC(vt_cursor, Vc);
+  FTC_ALLOC(vt_ids, 3 * Tc);
+  FTC_ALLOC(vb_off, Cc + 1);
+  FTC_ALLOC(vb_cursor, Cc);
+  FTC_ALLOC(vb_ids, Vc);
+  FTC_ALLOC(stray, Vc);
+#undef FTC_ALLOC
+  w.timing = 0;
+  int nev = 0;
+  for (int k = 0; k < FTC_KERNEL_COUNT && e == hipSuccess; ++k) {
+    w.ev_used[k] = 0;
+    e = hipEventCreate(&w.ev_start[k]);
+    if (e == hipSuccess) {
+      e = hipEventCreate(&w.ev_stop[k]);
+      if (e != hipSuccess) (void)hipEventDestroy(w.ev_start[k]);
+    }
+    if (e == hipSuccess) ++nev;
+  }
+  if (e == hipSuccess) e = hipMemset(w.counters, 0, sizeof(int32_t) * ftc::C_COUNT);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    for (int k = 0; k < nev; ++k) {
+      (void)hipEventDestroy(w.ev_start[k]);
+      (void)hipEventDestroy(w.ev_stop[k]);
+    }
+    for (int q = 0; q < n; ++q) (void)hipFree(reg[q]);
+    delete o;
+    return e == hipErrorOutOfMemory ? FTC_ENOMEM : FTC_EHIP;
+  }
+  static_assert(offsetof(ftc_cells_owner, ws) == 0, "owner layout");
+  *out = &o->ws;
+  return FTC_OK;
+}
+
+void ftc_cells_destroy(ftc_cells* cells) {
+  if (!cells) return;
+  ftc_cells_owner* o = reinterpret_cast<ftc_cells_owner*>(cells);
+  (void)hipDeviceSynchronize();
+  for (int k = 0; k < FTC_KERNEL_COUNT; ++k) {
+    (void)hipEventDestroy(o->ws.ev_start[k]);
+    (void)hipEventDestroy(o->ws.ev_stop[k]);
+  }
+  for (int q = 0; q < o->nbuf; ++q) (void)hipFree(o->buffers[q]);
+  delete o;
+}
+
+ftc_status ftc_build_cell_lists(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh, void* stream) {
+  if (!cells || !grid_valid(grid) || !mesh_valid(mesh) || !same_grid(cells->grid, grid)) return FTC_EINVAL;
+  if (mesh->nv > cells->nv_cap || mesh->nt > cells->nt_cap) return FTC_EINVAL;
+  if (!on_device(cells)) return FTC_EINVAL;
+  return hip_status(ftc::launch_cell_lists(cells, to_mesh(mesh), (hipStream_t)stream));
+}
+
+ftc_status ftc_cells_count(const ftc_cells* cells, int32_t* n_interfacial, int64_t* n_pairs, void* stream) {
+  if (!cells || !on_device(cells)) return FTC_EINVAL;
+  int32_t h[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(h, cells->counters, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return FTC_EHIP;
+  if (n_interfacial) *n_interfacial = h[ftc::C_NIF];
+  if (n_pairs) *n_pairs = h[ftc::C_NPAIRS];
+  return FTC_OK;
+}
+
+ftc_status ftc_cells_view(const ftc_cells* cells, const int32_t** cell_ids, const int32_t** offsets,
+                          const int32_t** tri_ids, const int32_t** d_counts) {
+  if (!cells) return FTC_EINVAL;
+  if (cell_ids) *cell_ids = cells->cell_ids;
+  if (offsets) *offsets = cells->offsets;
+  if (tri_ids) *tri_ids = cells->tri_ids;
+  if (d_counts) *d_counts = cells->counters;
+  return FTC_OK;
+}
+
+ftc_status ftc_volume_fraction(const ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh, double* alpha_if,
+                               double* alpha_dense, void* stream) {
+  if (!cells || !grid_valid(grid) || !mesh_valid(mesh) || !same_grid(cells->grid, grid)) return FTC_EINVAL;
+  if (mesh->nv > cells->nv_cap || mesh->nt > cells->nt_cap || (!alpha_if && !alpha_dense)) return FTC_EINVAL;
+  if (!on_device(cells)) return FTC_EINVAL;
+  return hip_status(
+      ftc::launch_volume_fraction(cells, to_mesh(mesh), alpha_if, alpha_dense, (hipStream_t)stream));
+}
+
+ftc_status ftc_ppic_curvature(const ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
+                              const ftc_ppic_params* params, double* kappa, double* nx, double* ny, double* nz,
+                              double* coeff, int32_t* cell_status, int32_t* diag, void* stream) {
+  if (!cells || !grid_valid(grid) || !mesh_valid(mesh) || !same_grid(cells->grid, grid)) return FTC_EINVAL;
+  if (mesh->nv > cells->nv_cap || mesh->nt > cells->nt_cap || !kappa || !nx || !ny || !nz) return FTC_EINVAL;
+  ftc::PPICParams p{2.5, 3, 24, 1.1, 16};
+  if (params) {
+    p = ftc::PPICParams{params->delta_over_h, params->rings, params->n_min, params->grow, params->max_iter};
+    if (!(p.delta_over_h > 0.0) || !isfinite(p.delta_over_h) || p.rings < 1 || p.rings > 4 || p.n_min < 1 ||
+        !(p.grow > 1.0) || !isfinite(p.grow) || p.max_iter < 0 || p.max_iter > 64)
+      return FTC_EINVAL;
+  }
+  if (!on_device(cells)) return FTC_EINVAL;
+  return hip_status(ftc::launch_ppic(cells, to_mesh(mesh), p, kappa, nx, ny, nz, coeff, cell_status, diag,
+                                     (hipStream_t)stream));
+}
+
+ftc_status ftc_csf_force(const ftc_cells* cells, const ftc_grid* grid, const double* alpha_dense, const double* kappa,
+                         double sigma, double* fx, double* fy, double* fz, void* stream) {
+  if (!cells || !grid_valid(grid) || !same_grid(cells->grid, grid) || !alpha_dense || !kappa || !fx || !fy || !fz ||
+      !isfinite(sigma))
+    return FTC_EINVAL;
+  if (!on_device(cells)) return FTC_EINVAL;
+  return hip_status(ftc::launch_csf(cells, alpha_dense, kappa, sigma, fx, fy, fz, (hipStream_t)stream));
+}
+
+ftc_status ftc_interp_vertex_velocity(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh, const double* U,
+                                      const double* V, const double* W, double* ux, double* uy, double* uz,
+                                      void* stream) {
+  if (!cells || !grid_valid(grid) || !mesh || mesh->nv <= 0 || !mesh->x || !mesh->y || !mesh->z || !U || !V || !W ||
+      !ux || !uy || !uz)
+    return FTC_EINVAL;
+  if (!on_device(cells)) return FTC_EINVAL;
+  return hip_status(ftc::launch_interp(cells, to_grid(grid), to_mesh(mesh), U, V, W, ux, uy, uz, (hipStream_t)stream));
+}
+
+ftc_status ftc_last_device_error(ftc_cells* cells, int32_t* code, void* stream) {
+  if (!cells || !code || !on_device(cells)) return FTC_EINVAL;
+  int32_t err = 0;
+  const int32_t zero = 0;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(&err, cells->counters + ftc::C_ERR, sizeof(err), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpyAsync(cells->counters + ftc::C_ERR, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return FTC_EHIP;
+  if (err & ftc::ERR_CAPACITY)
+    *code = FTC_ECAPACITY;
+  else if (err & ftc::ERR_DOMAIN)
+    *code = FTC_EDOMAIN;
+  else if (err & ftc::ERR_MESH)
+    *code = FTC_EMESH;
+  else
+    *code = FTC_OK;
+  return FTC_OK;
+}
+
+ftc_status ftc_set_timing(ftc_cells* cells, int32_t enable) {
+  if (!cells) return FTC_EINVAL;
+  cells->timing = enable ? 1 : 0;
+  return FTC_OK;
+}
+
+ftc_status ftc_kernel_time(const ftc_cells* cells, int32_t kernel, float* ms) {
+  if (!cells || !ms || kernel < 0 || kernel >= FTC_KERNEL_COUNT || !cells->ev_used[kernel]) return FTC_EINVAL;
+  hipError_t e = hipEventSynchronize(cells->ev_stop[kernel]);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, cells->ev_start[kernel], cells->ev_stop[kernel]);
+  return e == hipSuccess ? FTC_OK : FTC_EHIP;
+}
+
+const char* ftc_status_str(int32_t status) {
+  switch (status) {
+    case FTC_OK: return "ok";
+    case FTC_EINVAL: return "invalid argument";
+    case FTC_EDOMAIN: return "front vertex outside the grid margin";
+    case FTC_EMESH: return "front not closed or not outward oriented";
+    case FTC_ECAPACITY: return "workspace capacity exceeded";
+    case FTC_ENOMEM: return "device allocation failed";
+    case FTC_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

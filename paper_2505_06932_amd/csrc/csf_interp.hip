@@ -1,0 +1,111 @@
+// csf_interp.hip -- CSF source on the interfacial cells (paper Eq. csf) and
+// the divergence-preserving interpolation of staggered face velocities to
+// the front vertices (paper section 3.1).  Both are gather kernels bound by
+// memory traffic: one thread per interfacial cell, one thread per vertex.
+#include "ftc_ws.hpp"
+
+namespace ftc {
+namespace {
+
+constexpr int kT = 256;
+
+__global__ __launch_bounds__(kT) void k_csf(Grid g, const int32_t* cell_ids, const double* alpha,
+                                            const double* kappa, double sigma, double* fx, double* fy, double* fz,
+                                            int32_t cell_cap, const int32_t* counters) {
+  const int32_t nif = min(counters[C_NIF], cell_cap);
+  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+  const double inv2h = 1.0 / (2.0 * g.h);
+  for (int32_t c = blockIdx.x * kT + threadIdx.x; c < nif; c += gridDim.x * kT) {
+    const int64_t lin = cell_ids[c];
+    // interfacial cells lie at least two cells inside the grid, so every
+    // neighbour exists
+    const double gx = (alpha[lin + 1] - alpha[lin - 1]) * inv2h;
+    const double gy = (alpha[lin + sy] - alpha[lin - sy]) * inv2h;
+    const double gz = (alpha[lin + sz] - alpha[lin - sz]) * inv2h;
+    const double sk = sigma * kappa[c];
+    fx[c] = sk * gx;
+    fy[c] = sk * gy;
+    fz[c] = sk * gz;
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_interp(Grid g, Mesh m, const double* U, const double* V, const double* W,
+                                               double* ux, double* uy, double* uz, int32_t* counters) {
+  const int32_t v = blockIdx.x * kT + threadIdx.x;
+  if (v >= m.nv) return;
+  const double x = m.x[v], y = m.y[v], z = m.z[v];
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+    atomicOr(&counters[C_ERR], ERR_DOMAIN);
+    ux[v] = uy[v] = uz[v] = NAN;
+    return;
+  }
+  const int64_t i = cell_index(x, g.x0, g.h), j = cell_index(y, g.y0, g.h), k = cell_index(z, g.z0, g.h);
+  if (!(i >= 1 && j >= 1 && k >= 1 && i <= g.nx - 2 && j <= g.ny - 2 && k <= g.nz - 2)) {
+    atomicOr(&counters[C_ERR], ERR_DOMAIN);
+    ux[v] = uy[v] = uz[v] = NAN;
+    return;
+  }
+  const int64_t nx = g.nx, ny = g.ny;
+  // strides of the three staggered arrays (x fastest)
+  const int64_t uy_s = nx + 1, uz_s = (nx + 1) * ny;
+  const int64_t vy_s = nx, vz_s = nx * (ny + 1);
+  const int64_t wy_s = nx, wz_s = nx * ny;
+  const int64_t u0 = i + uy_s * j + uz_s * k;  // U face (i, j, k): lower x face
+  const int64_t v0 = i + vy_s * j + vz_s * k;  // V face (i, j, k): lower y face
+  const int64_t w0 = i + wy_s * j + wz_s * k;  // W face (i, j, k): lower z face
+  const double h = g.h, i2h = 1.0 / (2.0 * h);
+
+  const double Um = U[u0], Up = U[u0 + 1];
+  const double Vm = V[v0], Vp = V[v0 + vy_s];
+  const double Wm = W[w0], Wp = W[w0 + wz_s];
+  // transverse gradients on each face from the faces of the same orientation
+  // in the neighbouring cells
+  const double Uy_m = (U[u0 + uy_s] - U[u0 - uy_s]) * i2h;
+  const double Uy_p = (U[u0 + 1 + uy_s] - U[u0 + 1 - uy_s]) * i2h;
+  const double Uz_m = (U[u0 + uz_s] - U[u0 - uz_s]) * i2h;
+  const double Uz_p = (U[u0 + 1 + uz_s] - U[u0 + 1 - uz_s]) * i2h;
+  const double Vx_m = (V[v0 + 1] - V[v0 - 1]) * i2h;
+  const double Vx_p = (V[v0 + vy_s + 1] - V[v0 + vy_s - 1]) * i2h;
+  const double Vz_m = (V[v0 + vz_s] - V[v0 - vz_s]) * i2h;
+  const double Vz_p = (V[v0 + vy_s + vz_s] - V[v0 + vy_s - vz_s]) * i2h;
+  const double Wx_m = (W[w0 + 1] - W[w0 - 1]) * i2h;
+  const double Wx_p = (W[w0 + wz_s + 1] - W[w0 + wz_s - 1]) * i2h;
+  const double Wy_m = (W[w0 + wy_s] - W[w0 - wy_s]) * i2h;
+  const double Wy_p = (W[w0 + wz_s + wy_s] - W[w0 + wz_s - wy_s]) * i2h;
+
+  const double xm = g.x0 + (double)i * h, xp = g.x0 + (double)(i + 1) * h;
+  const double ym = g.y0 + (double)j * h, yp = g.y0 + (double)(j + 1) * h;
+  const double zm = g.z0 + (double)k * h, zp = g.z0 + (double)(k + 1) * h;
+  const double ax = x - xm, bx = xp - x, ay = y - ym, by = yp - y, az = z - zm, bz = zp - z;
+  const double cx = x - 0.5 * (xm + xp), cy = y - 0.5 * (ym + yp), cz = z - 0.5 * (zm + zp);
+  const double dx = xp - xm, dy = yp - ym, dz = zp - zm;
+
+  ux[v] = (ax * (Up + cy * Uy_p + cz * Uz_p) + bx * (Um + cy * Uy_m + cz * Uz_m)) / dx +
+          bx * ax / (2.0 * dx) * (Vx_p - Vx_m + Wx_p - Wx_m);
+  uy[v] = (ay * (Vp + cx * Vx_p + cz * Vz_p) + by * (Vm + cx * Vx_m + cz * Vz_m)) / dy +
+          by * ay / (2.0 * dy) * (Uy_p - Uy_m + Wy_p - Wy_m);
+  uz[v] = (az * (Wp + cx * Wx_p + cy * Wy_p) + bz * (Wm + cx * Wx_m + cy * Wy_m)) / dz +
+          bz * az / (2.0 * dz) * (Uz_p - Uz_m + Vz_p - Vz_m);
+}
+
+}  // namespace
+
+hipError_t launch_csf(const ftc_cells* ws, const double* alpha, const double* kappa, double sigma, double* fx,
+                      double* fy, double* fz, hipStream_t s) {
+  time_start(ws, FTC_KERNEL_CSF, s);
+  hipLaunchKernelGGL(k_csf, dim3(grid_blocks(ws->cell_cap, kT, 4096)), dim3(kT), 0, s, ws->grid, ws->cell_ids, alpha,
+                     kappa, sigma, fx, fy, fz, ws->cell_cap, ws->counters);
+  time_stop(ws, FTC_KERNEL_CSF, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp(const ftc_cells* ws, const Grid& g, const Mesh& m, const double* U, const double* V,
+                         const double* W, double* ux, double* uy, double* uz, hipStream_t s) {
+  time_start(ws, FTC_KERNEL_INTERP, s);
+  hipLaunchKernelGGL(k_interp, dim3(grid_blocks(m.nv, kT)), dim3(kT), 0, s, g, m, U, V, W, ux, uy, uz,
+                     ws->counters);
+  time_stop(ws, FTC_KERNEL_INTERP, s);
+  return hipGetLastError();
+}
+
+}  // namespace ftc

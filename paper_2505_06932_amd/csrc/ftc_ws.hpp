@@ -1,0 +1,120 @@
+// ftc_ws.hpp -- the workspace behind the opaque ftc_cells handle and the
+// internal launchers of each kernel group.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ftc_device.hpp"
+
+// Counter slots in ftc_cells::counters (device int32).
+namespace ftc {
+enum : int {
+  C_NIF = 0,      // interfacial cells of the last build
+  C_NPAIRS = 1,   // (cell, triangle) pieces of the last build
+  C_ERR = 2,      // latched ERR_* bits
+  C_NSTRAY = 3,   // vertices whose cell holds no piece (PPIC binning)
+  C_COUNT = 8
+};
+}  // namespace ftc
+
+struct ftc_cells {
+  int device;
+  ftc::Grid grid;
+  int64_t ncell, nwords, ncol;
+  int32_t nv_cap, nt_cap, cell_cap;
+  int64_t pair_cap;
+
+  int32_t* counters;  // [C_COUNT]
+  int32_t* scan_tmp;  // block partial sums of the device-wide scans
+
+  // cell lists
+  uint32_t* bitmap;       // [nwords] one bit per grid cell: holds a piece
+  int32_t* word_off;      // [nwords+1] exclusive scan of popcount(bitmap)
+  int32_t* tri_off;       // [nt_cap+1] piece count per triangle -> offsets
+  uint32_t* tri_mask;     // [nt_cap] which of the first 32 candidates hold a piece
+  int32_t* pair_cell;     // [pair_cap] compact cell of each piece (triangle order)
+  int32_t* pair_tri;      // [pair_cap] triangle of each piece (triangle order)
+  int32_t* cell_ids;      // [cell_cap] linear ids, ascending
+  int32_t* offsets;       // [cell_cap+1] CSR offsets into tri_ids
+  int32_t* cursor;        // [cell_cap] scatter cursors
+  int32_t* tri_ids;       // [pair_cap] CSR triangle ids, ascending per cell
+  int32_t* slot_cell;     // [pair_cap] compact cell of each CSR slot
+
+  // volume fraction
+  double* piece_flux;     // [pair_cap] integral of n_z dA per CSR slot
+  double* piece_vol;      // [pair_cap] integral of (z - zlo) n_z dA per CSR slot
+  int32_t* col_off;       // [ncol+1] interfacial cells per (i, j) column -> offsets
+  int32_t* col_cursor;    // [ncol]
+  int32_t* col_cells;     // [cell_cap] compact cells grouped by column, ascending k
+  int32_t* col_k;         // [cell_cap] k of each column slot
+  double* col_alpha;      // [cell_cap] alpha of each column slot
+  double* col_below;      // [cell_cap] alpha of the non-interfacial cells below the slot
+
+  // PPIC
+  int32_t* vt_off;        // [nv_cap+1] triangles per vertex -> offsets
+  int32_t* vt_cursor;     // [nv_cap]
+  int32_t* vt_ids;        // [3*nt_cap] incident triangles, ascending per vertex
+  int32_t* vb_off;        // [cell_cap+1] vertices per interfacial cell -> offsets
+  int32_t* vb_cursor;     // [cell_cap]
+  int32_t* vb_ids;        // [nv_cap] vertices binned by interfacial cell
+  int32_t* stray;         // [nv_cap] vertices in cells without pieces
+
+  // optional timing events around the dominant kernel of each call
+  int timing;
+  hipEvent_t ev_start[FTC_KERNEL_COUNT], ev_stop[FTC_KERNEL_COUNT];
+  int ev_used[FTC_KERNEL_COUNT];
+};
+
+namespace ftc {
+
+// Device-wide exclusive scan of n int32 values (in place: data[0..n) becomes
+// the exclusive prefix sums and data[n] the total); the total is also copied
+// to *total_out when non-null.  Supports n <= kScanMax.
+constexpr int64_t kScanBlock = 2048;
+constexpr int64_t kScanMaxBlocks = 8192;
+constexpr int64_t kScanMax = kScanBlock * kScanMaxBlocks;
+hipError_t scan_exclusive(int32_t* data, int64_t n, int32_t* tmp, int32_t* total_out, hipStream_t s);
+// Same, with inputs popcount(words[i]) (output to out[0..n], total to out[n]).
+hipError_t scan_popcount(const uint32_t* words, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out,
+                         hipStream_t s);
+
+hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s);
+hipError_t launch_volume_fraction(const ftc_cells* ws, const Mesh& m, double* alpha_if, double* alpha_dense,
+                                  hipStream_t s);
+
+struct PPICParams {
+  double delta_over_h;
+  int32_t rings, n_min;
+  double grow;
+  int32_t max_iter;
+};
+hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, double* kappa, double* nx,
+                       double* ny, double* nz, double* coeff, int32_t* cell_status, int32_t* diag,
+                       hipStream_t s);
+hipError_t launch_csf(const ftc_cells* ws, const double* alpha, const double* kappa, double sigma, double* fx,
+                      double* fy, double* fz, hipStream_t s);
+hipError_t launch_interp(const ftc_cells* ws, const Grid& g, const Mesh& m, const double* U, const double* V,
+                         const double* W, double* ux, double* uy, double* uz, hipStream_t s);
+
+// Record the start / stop event of kernel `k` when timing is enabled.
+inline void time_start(const ftc_cells* ws, int k, hipStream_t s) {
+  if (ws->timing) (void)hipEventRecord(ws->ev_start[k], s);
+}
+inline void time_stop(const ftc_cells* ws, int k, hipStream_t s) {
+  if (ws->timing) {
+    (void)hipEventRecord(ws->ev_stop[k], s);
+    const_cast<ftc_cells*>(ws)->ev_used[k] = 1;
+  }
+}
+
+inline int32_t grid_blocks(int64_t n, int threads, int64_t cap = 1 << 20) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int32_t)b;
+}
+
+}  // namespace ftc

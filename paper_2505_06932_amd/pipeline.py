@@ -1,0 +1,95 @@
+"""One coupling step over device-resident inputs: the five library calls in
+order (cell lists, volume fraction, PPIC curvature, CSF, vertex velocities),
+with every output allocated once so that a step allocates nothing and can be
+captured into a HIP graph."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import ftc
+from . import inputs as I
+
+
+class CouplingStep:
+    def __init__(self, grid: I.Grid, mesh: I.Mesh, U=None, V=None, W=None, sigma: float = 1.0,
+                 params: ftc.PPICParams | None = None, margin: float = 1.25,
+                 pair_capacity: int | None = None, cell_capacity: int | None = None):
+        self.grid = grid
+        self.sigma = float(sigma)
+        self.params = params
+        self.mesh = ftc.DeviceMesh.from_host(mesh)
+        dev = "cuda"
+        if U is None:
+            U, V, W = I.uniform_face_velocity(grid, (0.0, 0.0, 0.0))
+        f64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+        self.U, self.V, self.W = f64(U).reshape(-1), f64(V).reshape(-1), f64(W).reshape(-1)
+        nv, nt = mesh.nv, mesh.nt
+        if pair_capacity is None or cell_capacity is None:
+            # size the workspace from probing builds, doubling the capacities
+            # while they overflow
+            pc, cc = 8 * nt + 4096, int(min(grid.ncell, 4 * nt + 4096))
+            for _ in range(12):
+                probe = ftc.Cells(grid, nv, nt, pc, cc)
+                ftc.build_cell_lists(probe, grid, self.mesh)
+                n_if, n_p = probe.count()
+                err = probe.last_device_error()
+                probe.close()
+                if err != ftc.FTC_ECAPACITY:
+                    break
+                pc, cc = 2 * pc, int(min(grid.ncell, 2 * cc))
+            if err != ftc.FTC_OK:
+                raise ftc.FTCError(err, "probing build")
+            pair_capacity = pair_capacity or int(n_p * margin) + 256
+            cell_capacity = cell_capacity or int(min(grid.ncell, n_if * margin + 256))
+        self.cells = ftc.Cells(grid, nv, nt, pair_capacity, cell_capacity)
+        cap = self.cells.cell_capacity
+        z = lambda n, dt=torch.float64: torch.zeros(n, dtype=dt, device=dev)
+        self.alpha_if = z(cap)
+        self.alpha = z(grid.ncell)
+        self.kappa, self.nx, self.ny, self.nz = z(cap), z(cap), z(cap), z(cap)
+        self.coeff = z(6 * cap)
+        self.status = z(cap, torch.int32)
+        self.diag = z(4 * cap, torch.int32)
+        self.fx, self.fy, self.fz = z(cap), z(cap), z(cap)
+        self.ux, self.uy, self.uz = z(nv), z(nv), z(nv)
+
+    # the hot path, split so that callers can time its parts
+    def cells_and_alpha(self, stream=None):
+        ftc.build_cell_lists(self.cells, self.grid, self.mesh, stream)
+        ftc.volume_fraction(self.cells, self.grid, self.mesh, self.alpha_if, self.alpha, stream)
+
+    def curvature(self, stream=None, diagnostics=True):
+        ftc.ppic_curvature(self.cells, self.grid, self.mesh, self.kappa, self.nx, self.ny, self.nz,
+                           self.coeff if diagnostics else None, self.status,
+                           self.diag if diagnostics else None, self.params, stream)
+
+    def forces_and_velocities(self, stream=None):
+        ftc.csf_force(self.cells, self.grid, self.alpha, self.kappa, self.sigma, self.fx, self.fy, self.fz,
+                      stream)
+        ftc.interp_vertex_velocity(self.cells, self.grid, self.mesh, self.U, self.V, self.W, self.ux,
+                                   self.uy, self.uz, stream)
+
+    def run(self, stream=None, diagnostics=True):
+        self.cells_and_alpha(stream)
+        self.curvature(stream, diagnostics)
+        self.forces_and_velocities(stream)
+
+    def results(self):
+        """Host copies of every output, trimmed to the live counts."""
+        torch.cuda.synchronize()
+        n_if, n_p = self.cells.count()
+        cap = self.cells.cell_capacity
+        cell_ids, offsets, tri_ids = self.cells.lists()
+        h = lambda t: t.detach().cpu().numpy()
+        return dict(
+            n_if=n_if, n_pairs=n_p, cell_ids=h(cell_ids).astype(np.int64), offsets=h(offsets).astype(np.int64),
+            tri_ids=h(tri_ids), alpha_if=h(self.alpha_if)[:n_if],
+            alpha=h(self.alpha).reshape(self.grid.nz, self.grid.ny, self.grid.nx),
+            kappa=h(self.kappa)[:n_if],
+            normal=np.stack([h(self.nx)[:n_if], h(self.ny)[:n_if], h(self.nz)[:n_if]], 1),
+            coeff=h(self.coeff).reshape(6, cap)[:, :n_if].T, status=h(self.status)[:n_if],
+            diag=h(self.diag).reshape(4, cap)[:, :n_if].T,
+            force=np.stack([h(self.fx)[:n_if], h(self.fy)[:n_if], h(self.fz)[:n_if]], 1),
+            u=np.stack([h(self.ux), h(self.uy), h(self.uz)], 1),
+            error=self.cells.last_device_error())
