@@ -84,8 +84,8 @@ typedef struct ftc_cells ftc_cells;
 /* Allocate a workspace on the current HIP device for `grid` [host] and fronts
    of up to nv_capacity vertices and nt_capacity triangles, holding up to
    pair_capacity (cell, triangle) pieces and cell_capacity interfacial
-   cells.  Device memory is about 17 B x pairs + 110 B x cells +
-   40 B x triangles + 30 B x vertices + 12 B x (nx*ny) + nx*ny*nz/4 B.
+   cells.  Device memory is about 36 B x pairs + 80 B x cells +
+   24 B x triangles + 8 B x vertices + 8 B x (nx*ny) + nx*ny*nz/4 B.
    Returns FTC_EINVAL, FTC_ENOMEM or FTC_OK; *out is NULL on failure. */
 ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_capacity,
                             int32_t nt_capacity, int64_t pair_capacity, int32_t cell_capacity);

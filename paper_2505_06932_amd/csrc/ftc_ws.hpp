@@ -13,7 +13,6 @@ enum : int {
   C_NIF = 0,      // interfacial cells of the last build
   C_NPAIRS = 1,   // (cell, triangle) pieces of the last build
   C_ERR = 2,      // latched ERR_* bits
-  C_NSTRAY = 3,   // vertices whose cell holds no piece (PPIC binning)
   C_COUNT = 8
 };
 }  // namespace ftc
@@ -55,10 +54,8 @@ struct ftc_cells {
   int32_t* vt_off;        // [nv_cap+1] triangles per vertex -> offsets
   int32_t* vt_cursor;     // [nv_cap]
   int32_t* vt_ids;        // [3*nt_cap] incident triangles, ascending per vertex
-  int32_t* vb_off;        // [cell_cap+1] vertices per interfacial cell -> offsets
-  int32_t* vb_cursor;     // [cell_cap]
-  int32_t* vb_ids;        // [nv_cap] vertices binned by interfacial cell
-  int32_t* stray;         // [nv_cap] vertices in cells without pieces
+  unsigned long long* best_d2;  // [cell_cap] bits of the smallest squared vertex distance
+  int32_t* best_v;              // [cell_cap] lowest vertex attaining it
 
   // optional timing events around the dominant kernel of each call
   int timing;
