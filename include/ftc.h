@@ -84,8 +84,9 @@ typedef struct ftc_cells ftc_cells;
 /* Allocate a workspace on the current HIP device for `grid` [host] and fronts
    of up to nv_capacity vertices and nt_capacity triangles, holding up to
    pair_capacity (cell, triangle) pieces and cell_capacity interfacial
-   cells.  Device memory is about 36 B x pairs + 80 B x cells +
-   24 B x triangles + 8 B x vertices + 8 B x (nx*ny) + nx*ny*nz/4 B.
+   cells (candidates that must be clipped, up to twice pair_capacity, are
+   queued internally).  Device memory is about 104 B x pairs + 96 B x cells +
+   12 B x triangles + 8 B x vertices + 8 B x (nx*ny) + nx*ny*nz/4 B.
    Returns FTC_EINVAL, FTC_ENOMEM or FTC_OK; *out is NULL on failure. */
 ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_capacity,
                             int32_t nt_capacity, int64_t pair_capacity, int32_t cell_capacity);
@@ -99,7 +100,9 @@ void ftc_cells_destroy(ftc_cells* cells);
    intersection with the closed cell has positive area; a triangle lying
    exactly in a grid plane belongs to the cell above that plane.  Result, in
    the workspace: interfacial cells in ascending linear id and, per cell, its
-   triangles in ascending id (CSR).  `grid` must equal the workspace's grid.
+   triangles in ascending id (CSR), together with each piece's two surface
+   integrals used by ftc_volume_fraction (clipping happens once, here).
+   `grid` must equal the workspace's grid.
    Latches FTC_EDOMAIN or FTC_ECAPACITY on the device. */
 ftc_status ftc_build_cell_lists(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
                                 void* stream);
@@ -127,7 +130,8 @@ ftc_status ftc_cells_view(const ftc_cells* cells, const int32_t** cell_ids, cons
    alpha_if[cell_capacity]: alpha of each interfacial cell (cell-list order).
    alpha_dense[nx*ny*nz] or NULL: every cell of the grid is written.
    Latches FTC_EMESH if a column sum is not 0 or h^2 where no piece is
-   (open or inverted front). */
+   (open or inverted front).  Uses the pieces of the last
+   ftc_build_cell_lists on the same workspace (mesh must be that front). */
 ftc_status ftc_volume_fraction(const ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
                                double* alpha_if, double* alpha_dense, void* stream);
 
@@ -183,8 +187,8 @@ ftc_status ftc_last_device_error(ftc_cells* cells, int32_t* code, void* stream);
    ftc_kernel_time then returns the interval of the last such launch.  Keep
    it disabled while capturing a graph (event records are not captured). */
 typedef enum {
-  FTC_KERNEL_TRI_COUNT = 0,   /* cell lists: per-triangle clip and count      */
-  FTC_KERNEL_VF_PIECES = 1,   /* volume fraction: per-piece integrals         */
+  FTC_KERNEL_TRI_PIECES = 0,  /* cell lists: per-triangle clip and integrals  */
+  FTC_KERNEL_PIECE_RANK = 1,  /* cell lists: ordering of each cell's pieces   */
   FTC_KERNEL_COL_WALK = 2,    /* volume fraction: column sums                 */
   FTC_KERNEL_DENSE_ALPHA = 3, /* volume fraction: dense field write           */
   FTC_KERNEL_PPIC = 4,        /* PPIC: closest vertex, ring, fit, curvature   */

@@ -23,7 +23,20 @@ bool same_grid(const Grid& a, const ftc_grid* b) {
          a.h == b->h;
 }
 
-Grid to_grid(const ftc_grid* g) { return Grid{g->nx, g->ny, g->nz, g->x0, g->y0, g->z0, g->h}; }
+Grid to_grid(const ftc_grid* g) {
+  Grid r;
+  r.nx = g->nx;
+  r.ny = g->ny;
+  r.nz = g->nz;
+  r.x0 = g->x0;
+  r.y0 = g->y0;
+  r.z0 = g->z0;
+  r.h = g->h;
+  r.dnx = ftc::FastDiv((uint32_t)g->nx);
+  r.dny = ftc::FastDiv((uint32_t)g->ny);
+  r.dncol = ftc::FastDiv((uint32_t)((int64_t)g->nx * g->ny));
+  return r;
+}
 
 bool mesh_valid(const ftc_mesh* m) {
   return m && m->nv > 0 && m->nt > 0 && m->x && m->y && m->z && m->t0 && m->t1 && m->t2;
@@ -71,7 +84,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   const int64_t nwords = (ncell + 31) / 32;
   const int64_t ncol = (int64_t)grid->nx * grid->ny;
   // int32 cell ids and offsets; every scanned array within the scan limit
-  if (ncell >= ((int64_t)1 << 31) || pair_capacity >= ((int64_t)1 << 31) || nwords > ftc::kScanMax ||
+  if (ncell >= ((int64_t)1 << 31) || 3 * pair_capacity + 1024 >= ((int64_t)1 << 31) || nwords > ftc::kScanMax ||
       ncol > ftc::kScanMax || nt_capacity > ftc::kScanMax || nv_capacity > ftc::kScanMax ||
       cell_capacity > ftc::kScanMax || (int64_t)nt_capacity * 3 >= ((int64_t)1 << 31))
     return FTC_EINVAL;
@@ -102,10 +115,13 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(scan_tmp, ftc::kScanMaxBlocks);
   FTC_ALLOC(bitmap, nwords);
   FTC_ALLOC(word_off, nwords + 1);
-  FTC_ALLOC(tri_off, Tc + 1);
-  FTC_ALLOC(tri_mask, Tc);
-  FTC_ALLOC(pair_cell, P);
-  FTC_ALLOC(pair_tri, P);
+  w.queue_cap = 2 * P + 1024;  // candidates that need clipping can outnumber pieces
+  FTC_ALLOC(pair_cell, P + w.queue_cap);
+  FTC_ALLOC(pair_tri, P + w.queue_cap);
+  FTC_ALLOC(pair_flux, P + w.queue_cap);
+  FTC_ALLOC(pair_vol, P + w.queue_cap);
+  FTC_ALLOC(tmp_tri, P);
+  FTC_ALLOC(tmp_pair, P);
   FTC_ALLOC(cell_ids, Cc);
   FTC_ALLOC(offsets, Cc + 1);
   FTC_ALLOC(cursor, Cc);
@@ -113,6 +129,8 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(slot_cell, P);
   FTC_ALLOC(piece_flux, P);
   FTC_ALLOC(piece_vol, P);
+  FTC_ALLOC(cell_flux, Cc);
+  FTC_ALLOC(cell_vol, Cc);
   FTC_ALLOC(col_off, ncol + 1);
   FTC_ALLOC(col_cursor, ncol);
   FTC_ALLOC(col_cells, Cc);

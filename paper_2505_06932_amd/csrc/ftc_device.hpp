@@ -19,10 +19,37 @@ namespace ftc {
 // Device error latch bits (combined with atomicOr).
 enum : int32_t { ERR_DOMAIN = 1, ERR_MESH = 2, ERR_CAPACITY = 4 };
 
+// Division by a fixed divisor d < 2^31 through a multiply-high (Granlund &
+// Montgomery, PLDI 1994, round-up variant): for 0 <= n < 2^31,
+// n / d == (umulhi(m, n) + n) >> l with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1; the sum cannot overflow 32 bits.
+struct FastDiv {
+  uint32_t d, m, l;
+  __host__ __device__ FastDiv() : d(1), m(1), l(0) {}
+  __host__ explicit FastDiv(uint32_t div) : d(div), m(1), l(0) {
+    while ((1ull << l) < d) ++l;
+    m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  }
+  __device__ uint32_t div(uint32_t n) const { return (__umulhi(m, n) + n) >> l; }
+};
+
 struct Grid {
   int32_t nx, ny, nz;
   double x0, y0, z0, h;
+  FastDiv dnx, dny, dncol;  // divisions by nx, ny and nx*ny
 };
+
+// (i, j, k) of a linear cell id (lin < 2^31).
+struct Cell3 {
+  int32_t i, j, k;
+};
+__device__ inline Cell3 unpack_cell(const Grid& g, int32_t lin) {
+  const uint32_t u = (uint32_t)lin;
+  const uint32_t k = g.dncol.div(u);
+  const uint32_t r = u - k * g.dncol.d;
+  const uint32_t j = g.dnx.div(r);
+  return Cell3{(int32_t)(r - j * g.dnx.d), (int32_t)j, (int32_t)k};
+}
 
 struct Mesh {
   int32_t nv, nt;
@@ -108,115 +135,188 @@ __device__ inline void tri_range(const Grid& g, const Tri& T, int64_t lo[3], int
 // plane on that axis (a triangle in a grid plane belongs to the cell above),
 // (2) at least three corners remain, and (3) the fan-summed vector area
 // sum_j (q_j - q_0) x (q_{j+1} - q_0) is not the zero vector.
+//
+// A stage whose plane leaves every corner inside emits each corner once, in
+// the same cyclic order shifted by one.  A convex polygon gains at most one
+// corner per plane (nine after six planes; the bound checks only guard
+// memory).
 // ---------------------------------------------------------------------------
 
-constexpr int kMaxPoly = 12;
+constexpr int kMaxPoly = 9;
 
-struct Poly {
-  int n;
-  double x[kMaxPoly], y[kMaxPoly], z[kMaxPoly];
+struct Piece {
+  bool keep;
+  double flux;  // integral of n_z dA over the piece
+  double vol;   // integral of (z - zlo) n_z dA over the piece
 };
 
-__device__ inline double poly_coord(const Poly& P, int i, int d) {
-  return d == 0 ? P.x[i] : (d == 1 ? P.y[i] : P.z[i]);
-}
-
-// A convex polygon cut by one plane gains at most one corner, so after six
-// planes a triangle has at most nine; the bound check only guards memory.
-__device__ inline void poly_push(Poly& P, double x, double y, double z) {
-  if (P.n >= kMaxPoly) return;
-  P.x[P.n] = x;
-  P.y[P.n] = y;
-  P.z[P.n] = z;
-  ++P.n;
-}
-
-__device__ inline void poly_push_cut(Poly& out, const Poly& in, int ip, int iq, int d, double c) {
-  double pd = poly_coord(in, ip, d), qd = poly_coord(in, iq, d);
-  int ia = pd < qd ? ip : iq;
-  int ib = pd < qd ? iq : ip;
-  double ad = poly_coord(in, ia, d), bd = poly_coord(in, ib, d);
-  double t = (c - ad) / (bd - ad);
-  double rx = d == 0 ? c : in.x[ia] + t * (in.x[ib] - in.x[ia]);
-  double ry = d == 1 ? c : in.y[ia] + t * (in.y[ib] - in.y[ia]);
-  double rz = d == 2 ? c : in.z[ia] + t * (in.z[ib] - in.z[ia]);
-  poly_push(out, rx, ry, rz);
-}
-
-__device__ inline void clip_plane(const Poly& in, Poly& out, int d, double c, bool upper) {
-  out.n = 0;
-  for (int e = 0; e < in.n; ++e) {
-    int iq = (e + 1 == in.n) ? 0 : e + 1;
-    double pd = poly_coord(in, e, d), qd = poly_coord(in, iq, d);
-    bool pin = upper ? (pd <= c) : (pd >= c);
-    bool qin = upper ? (qd <= c) : (qd >= c);
-    if (pin && qin) {
-      poly_push(out, in.x[iq], in.y[iq], in.z[iq]);
-    } else if (pin) {
-      if (pd != c) poly_push_cut(out, in, e, iq, d, c);
-    } else if (qin) {
-      if (qd != c) poly_push_cut(out, in, e, iq, d, c);
-      poly_push(out, in.x[iq], in.y[iq], in.z[iq]);
-    }
-  }
-}
-
-// Clip T to cell (i, j, k); true if the piece counts.  On return `P` holds
-// the clipped polygon.
-__device__ inline bool clip_cell(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k, Poly& P) {
+// Planes of cell (i, j, k); false if the half-open rule gives the triangle to
+// the next cell (all three corners on an upper plane).
+__device__ inline bool cell_planes(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k, double lo[3],
+                                   double hi[3]) {
   const int64_t ijk[3] = {i, j, k};
-  double lo[3], hi[3];
+  bool ok = true;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     lo[d] = grid_plane(dim_org(g, d), ijk[d], g.h);
     hi[d] = grid_plane(dim_org(g, d), ijk[d] + 1, g.h);
-    if (T.v[0][d] == hi[d] && T.v[1][d] == hi[d] && T.v[2][d] == hi[d]) return false;
+    if (T.v[0][d] == hi[d] && T.v[1][d] == hi[d] && T.v[2][d] == hi[d]) ok = false;
   }
-  Poly A;
-  A.n = 3;
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    A.x[r] = T.v[r][0];
-    A.y[r] = T.v[r][1];
-    A.z[r] = T.v[r][2];
-  }
-  clip_plane(A, P, 0, lo[0], false);
-  if (P.n == 0) return false;
-  clip_plane(P, A, 0, hi[0], true);
-  if (A.n == 0) return false;
-  clip_plane(A, P, 1, lo[1], false);
-  if (P.n == 0) return false;
-  clip_plane(P, A, 1, hi[1], true);
-  if (A.n == 0) return false;
-  clip_plane(A, P, 2, lo[2], false);
-  if (P.n == 0) return false;
-  clip_plane(P, A, 2, hi[2], true);
-  if (A.n < 3) return false;
-  double sx = 0.0, sy = 0.0, sz = 0.0;
-  for (int j2 = 1; j2 + 1 < A.n; ++j2) {
-    double ux = A.x[j2] - A.x[0], uy = A.y[j2] - A.y[0], uz = A.z[j2] - A.z[0];
-    double vx = A.x[j2 + 1] - A.x[0], vy = A.y[j2 + 1] - A.y[0], vz = A.z[j2 + 1] - A.z[0];
-    sx += uy * vz - uz * vy;
-    sy += uz * vx - ux * vz;
-    sz += ux * vy - uy * vx;
-  }
-  if (sx == 0.0 && sy == 0.0 && sz == 0.0) return false;
-  P = A;
-  return true;
+  return ok;
 }
 
-// z-column integrals of a piece: flux = integral of n_z dA (signed projected
-// area, fan from corner 0), vol = integral of (z - zlo) n_z dA (z is linear on
-// the piece, so each fan triangle contributes its area times its corner mean).
-__device__ inline void piece_z_integrals(const Poly& P, double zlo, double& flux, double& vol) {
-  double f = 0.0, v = 0.0;
-  for (int j = 1; j + 1 < P.n; ++j) {
-    double A = 0.5 * ((P.x[j] - P.x[0]) * (P.y[j + 1] - P.y[0]) - (P.x[j + 1] - P.x[0]) * (P.y[j] - P.y[0]));
-    f += A;
-    v += A * ((P.z[0] + P.z[j] + P.z[j + 1]) / 3.0 - zlo);
+// Candidate classes decided from the corners alone, taking exactly the
+// decisions the clipping would take: stages are visited in order while the
+// polygon is still the (rotated) triangle; 0 = no piece (half-open rule, or
+// a stage with every corner strictly outside), 1 = the piece is the whole
+// triangle (no stage cuts), 2 = some stage cuts, so the candidate must be
+// clipped.
+__device__ inline int classify_candidate(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k) {
+  double lo[3], hi[3];
+  if (!cell_planes(g, T, i, j, k, lo, hi)) return 0;
+#pragma unroll
+  for (int stage = 0; stage < 6; ++stage) {
+    const int d = stage >> 1;
+    const bool upper = stage & 1;
+    const double c = upper ? hi[d] : lo[d];
+    const double a = T.v[0][d], b = T.v[1][d], e = T.v[2][d];
+    const bool ia = upper ? a <= c : a >= c, ib = upper ? b <= c : b >= c, ie = upper ? e <= c : e >= c;
+    if (!ia && !ib && !ie) return 0;
+    if (!(ia && ib && ie)) return 2;
   }
-  flux = f;
-  vol = v;
+  return 1;
+}
+
+// Fan integrals of a polygon given by corner accessors (corner 0 is the fan
+// apex): membership by the vector area, flux and vol by the z-column rule.
+template <class CX>
+__device__ inline Piece fan_piece(int n, double zlo, CX cx) {
+  Piece out{false, 0.0, 0.0};
+  if (n < 3) return out;
+  const double x0 = cx(0, 0), y0 = cx(0, 1), z0 = cx(0, 2);
+  double sx = 0.0, sy = 0.0, sz = 0.0, f = 0.0, v = 0.0;
+#pragma unroll
+  for (int jj = 1; jj + 1 < kMaxPoly; ++jj) {
+    if (jj + 1 < n) {
+      const double x1 = cx(jj, 0), y1 = cx(jj, 1), z1 = cx(jj, 2);
+      const double x2 = cx(jj + 1, 0), y2 = cx(jj + 1, 1), z2 = cx(jj + 1, 2);
+      const double ux = x1 - x0, uy = y1 - y0, uz = z1 - z0;
+      const double vx = x2 - x0, vy = y2 - y0, vz = z2 - z0;
+      sx += uy * vz - uz * vy;
+      sy += uz * vx - ux * vz;
+      sz += ux * vy - uy * vx;
+      // the fan triangle's signed area projected on the xy plane, and that
+      // area times the mean of (z - zlo) over its corners
+      const double A = 0.5 * ((x1 - x0) * (y2 - y0) - (x2 - x0) * (y1 - y0));
+      f += A;
+      v += A * ((z0 + z1 + z2) / 3.0 - zlo);
+    }
+  }
+  if (sx == 0.0 && sy == 0.0 && sz == 0.0) return out;
+  out.keep = true;
+  out.flux = f;
+  out.vol = v;
+  return out;
+}
+
+// Piece of a candidate of class 1: the triangle itself (after six stages
+// that cut nothing the corner order is back to t0, t1, t2).
+__device__ inline Piece whole_piece(const Tri& T, double zlo) {
+  return fan_piece(3, zlo, [&](int q, int d) { return q == 0 ? T.v[0][d] : (q == 1 ? T.v[1][d] : T.v[2][d]); });
+}
+
+// Per-lane compaction buffer in LDS: [coordinate][corner][lane].
+template <int LANES>
+struct PolyLDS {
+  double v[3][kMaxPoly][LANES];
+};
+
+// Full clipping of a candidate.  The polygon is held in registers in
+// polygon order (static slots); a stage that cuts emits its output into the
+// lane's LDS buffer (dynamic positions) and reloads it.
+template <int LANES>
+__device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k,
+                                   PolyLDS<LANES>& L, int lane) {
+  Piece none{false, 0.0, 0.0};
+  double lo[3], hi[3];
+  if (!cell_planes(g, T, i, j, k, lo, hi)) return none;
+  double P[3][kMaxPoly];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int q = 0; q < kMaxPoly; ++q) P[d][q] = q < 3 ? T.v[q][d] : 0.0;
+  int n = 3;
+#pragma unroll
+  for (int stage = 0; stage < 6; ++stage) {
+    const int d = stage >> 1;
+    const bool upper = stage & 1;
+    const double c = upper ? hi[d] : lo[d];
+    bool all_in = true, all_out = true;
+#pragma unroll
+    for (int q = 0; q < kMaxPoly; ++q) {
+      if (q < n) {
+        const bool in = upper ? (P[d][q] <= c) : (P[d][q] >= c);
+        all_in = all_in && in;
+        all_out = all_out && !in;
+      }
+    }
+    if (all_out) return none;
+    if (all_in) {
+      // rotate by one corner
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        const double first = P[f][0];
+#pragma unroll
+        for (int q = 0; q + 1 < kMaxPoly; ++q) P[f][q] = (q + 1 < n) ? P[f][q + 1] : (q + 1 == n ? first : P[f][q]);
+        if (n == kMaxPoly) P[f][kMaxPoly - 1] = first;
+      }
+      continue;
+    }
+    int o = 0;
+#pragma unroll
+    for (int e = 0; e < kMaxPoly; ++e) {
+      if (e < n) {
+        // q = corner e + 1, wrapping to corner 0 at the last edge
+        double q0 = P[0][0], q1 = P[1][0], q2 = P[2][0];
+        if (e + 1 < kMaxPoly && e + 1 < n) {
+          q0 = P[0][e + 1];
+          q1 = P[1][e + 1];
+          q2 = P[2][e + 1];
+        }
+        const double pp[3] = {P[0][e], P[1][e], P[2][e]};
+        const double qq[3] = {q0, q1, q2};
+        const double pd = pp[d], qd = qq[d];
+        const bool pin = upper ? (pd <= c) : (pd >= c);
+        const bool qin = upper ? (qd <= c) : (qd >= c);
+        const bool cut = pin != qin && (pin ? pd != c : qd != c);
+        if (cut && o < kMaxPoly) {
+          const bool pa = pd < qd;
+          const double ad = pa ? pd : qd, bd = pa ? qd : pd;
+          const double t = (c - ad) / (bd - ad);
+#pragma unroll
+          for (int f = 0; f < 3; ++f) {
+            const double af = pa ? pp[f] : qq[f], bf = pa ? qq[f] : pp[f];
+            L.v[f][o][lane] = (f == d) ? c : af + t * (bf - af);
+          }
+          ++o;
+        }
+        if (qin && o < kMaxPoly) {
+          L.v[0][o][lane] = q0;
+          L.v[1][o][lane] = q1;
+          L.v[2][o][lane] = q2;
+          ++o;
+        }
+      }
+    }
+    n = o;
+    if (n == 0) return none;
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int q = 0; q < kMaxPoly; ++q)
+        if (q < n) P[f][q] = L.v[f][q][lane];
+  }
+  return fan_piece(n, lo[2], [&](int q, int d) { return P[d][q]; });
 }
 
 }  // namespace ftc

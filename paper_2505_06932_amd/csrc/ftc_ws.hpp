@@ -13,6 +13,8 @@ enum : int {
   C_NIF = 0,      // interfacial cells of the last build
   C_NPAIRS = 1,   // (cell, triangle) pieces of the last build
   C_ERR = 2,      // latched ERR_* bits
+  C_NQUEUE = 3,   // candidates queued for full clipping
+  C_NWHOLE = 4,   // pieces that are whole triangles
   C_COUNT = 8
 };
 }  // namespace ftc
@@ -23,6 +25,7 @@ struct ftc_cells {
   int64_t ncell, nwords, ncol;
   int32_t nv_cap, nt_cap, cell_cap;
   int64_t pair_cap;
+  int64_t queue_cap;  // candidates queued for full clipping (>= pair_cap)
 
   int32_t* counters;  // [C_COUNT]
   int32_t* scan_tmp;  // block partial sums of the device-wide scans
@@ -30,19 +33,25 @@ struct ftc_cells {
   // cell lists
   uint32_t* bitmap;       // [nwords] one bit per grid cell: holds a piece
   int32_t* word_off;      // [nwords+1] exclusive scan of popcount(bitmap)
-  int32_t* tri_off;       // [nt_cap+1] piece count per triangle -> offsets
-  uint32_t* tri_mask;     // [nt_cap] which of the first 32 candidates hold a piece
-  int32_t* pair_cell;     // [pair_cap] compact cell of each piece (triangle order)
-  int32_t* pair_tri;      // [pair_cap] triangle of each piece (triangle order)
+  // pair list: [0, pair_cap) whole-triangle pieces, [pair_cap, pair_cap +
+  // queue_cap) candidates queued for clipping (cell -1 if no piece)
+  int32_t* pair_cell;     // linear, then compact, cell of each piece
+  int32_t* pair_tri;      // triangle of each piece
+  double* pair_flux;      // integral of n_z dA
+  double* pair_vol;       // integral of (z - zlo) n_z dA
+  int32_t* tmp_tri;       // [pair_cap] triangles scattered into their cell's segment
+  int32_t* tmp_pair;      // [pair_cap] pair-list slot of each scattered piece
   int32_t* cell_ids;      // [cell_cap] linear ids, ascending
   int32_t* offsets;       // [cell_cap+1] CSR offsets into tri_ids
   int32_t* cursor;        // [cell_cap] scatter cursors
   int32_t* tri_ids;       // [pair_cap] CSR triangle ids, ascending per cell
   int32_t* slot_cell;     // [pair_cap] compact cell of each CSR slot
-
-  // volume fraction
   double* piece_flux;     // [pair_cap] integral of n_z dA per CSR slot
   double* piece_vol;      // [pair_cap] integral of (z - zlo) n_z dA per CSR slot
+
+  // volume fraction
+  double* cell_flux;      // [cell_cap] sum of the cell's piece fluxes
+  double* cell_vol;       // [cell_cap] sum of the cell's piece volume integrals
   int32_t* col_off;       // [ncol+1] interfacial cells per (i, j) column -> offsets
   int32_t* col_cursor;    // [ncol]
   int32_t* col_cells;     // [cell_cap] compact cells grouped by column, ascending k

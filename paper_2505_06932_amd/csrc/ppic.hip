@@ -123,8 +123,11 @@ __global__ __launch_bounds__(kT) void k_vstar(Grid g, Mesh m, const uint32_t* bi
   const double x = m.x[v], y = m.y[v], z = m.z[v];
   if (!in_margin(g, x, y, z)) return;  // latched as a domain error by the cell-list build
   const int64_t i = cell_index(x, g.x0, g.h), j = cell_index(y, g.y0, g.h), k = cell_index(z, g.z0, g.h);
+#pragma unroll
   for (int dk = -1; dk <= 1; ++dk)
+#pragma unroll
     for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
       for (int di = -1; di <= 1; ++di) {
         const int64_t ii = i + di, jj = j + dj, kk = k + dk;  // inside the grid: the vertex is 2 cells in
         const int32_t ci = cell_rank(bitmap, word_off, ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk));
@@ -220,9 +223,8 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
   for (int32_t base = blockIdx.x * NG; base < nif; base += gridDim.x * NG) {
     const int32_t c = base + grp;
     const bool act = c < nif;
-    const int32_t lin = act ? A.cell_ids[c] : 0;
-    const int64_t ncol = (int64_t)g.nx * g.ny;
-    const int64_t ci = lin % g.nx, cj = (lin / g.nx) % g.ny, ck = lin / ncol;
+    const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
+    const int32_t ci = cc3.i, cj = cc3.j, ck = cc3.k;
     const double xc[3] = {g.x0 + ((double)ci + 0.5) * h, g.y0 + ((double)cj + 0.5) * h,
                           g.z0 + ((double)ck + 0.5) * h};
 
