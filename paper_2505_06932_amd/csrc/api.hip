@@ -140,6 +140,11 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(vt_off, Vc + 1);
   FTC_ALLOC(vt_cursor, Vc);
   FTC_ALLOC(vt_ids, 3 * Tc);
+  FTC_ALLOC(vcell, Vc);
+  FTC_ALLOC(vb_off, Cc + 1);
+  FTC_ALLOC(vb_cursor, Cc);
+  FTC_ALLOC(vb_ids, Vc);
+  FTC_ALLOC(stray, Vc);
   FTC_ALLOC(best_d2, Cc);
   FTC_ALLOC(best_v, Cc);
 #undef FTC_ALLOC

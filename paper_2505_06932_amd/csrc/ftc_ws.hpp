@@ -15,6 +15,7 @@ enum : int {
   C_ERR = 2,      // latched ERR_* bits
   C_NQUEUE = 3,   // candidates queued for full clipping
   C_NWHOLE = 4,   // pieces that are whole triangles
+  C_NSTRAY = 5,   // vertices in cells without pieces
   C_COUNT = 8
 };
 }  // namespace ftc
@@ -63,8 +64,13 @@ struct ftc_cells {
   int32_t* vt_off;        // [nv_cap+1] triangles per vertex -> offsets
   int32_t* vt_cursor;     // [nv_cap]
   int32_t* vt_ids;        // [3*nt_cap] incident triangles, ascending per vertex
-  unsigned long long* best_d2;  // [cell_cap] bits of the smallest squared vertex distance
-  int32_t* best_v;              // [cell_cap] lowest vertex attaining it
+  int32_t* vcell;         // [nv_cap] interfacial cell holding each vertex (-1: none, -2: outside)
+  int32_t* vb_off;        // [cell_cap+1] vertices per interfacial cell -> offsets
+  int32_t* vb_cursor;     // [cell_cap]
+  int32_t* vb_ids;        // [nv_cap] vertices grouped by interfacial cell
+  int32_t* stray;         // [nv_cap] vertices in cells without pieces
+  double* best_d2;        // [cell_cap] smallest squared distance of a vertex in the 27 cells around
+  int32_t* best_v;        // [cell_cap] lowest vertex attaining it
 
   // optional timing events around the dominant kernel of each call
   int timing;
