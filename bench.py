@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (the reference kernel for the "
+                         "FETCH_SIZE / WRITE_SIZE counter scale)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -80,6 +83,9 @@ def main():
         log("no GPU visible")
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        copy_calibration(torch)
+        return
     K, Wm = args.steps, args.warmup
 
     grid, mesh, centre = I.make_workload(args.workload, args.seed)
@@ -206,6 +212,20 @@ def main():
         log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} cells/s on {oracle.threads()} threads; "
             f"errors {out['err_vs_oracle']}")
     print(json.dumps(out), flush=True)
+
+
+COPY_BYTES = 256 << 20
+
+
+def copy_calibration(torch):
+    """Five launches of a plain copy of COPY_BYTES: each reads and writes exactly that many bytes."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 5}), flush=True)
 
 
 def _vpoly(mesh, centre):
