@@ -140,6 +140,9 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(vt_off, Vc + 1);
   FTC_ALLOC(vt_cursor, Vc);
   FTC_ALLOC(vt_ids, 3 * Tc);
+  FTC_ALLOC(tri4, 4 * Tc);
+  FTC_ALLOC(vtx4, 4 * Vc);
+  FTC_ALLOC(ovf_cells, Cc);
   FTC_ALLOC(vcell, Vc);
   FTC_ALLOC(vb_off, Cc + 1);
   FTC_ALLOC(vb_cursor, Cc);

@@ -16,6 +16,7 @@ enum : int {
   C_NQUEUE = 3,   // candidates queued for full clipping
   C_NWHOLE = 4,   // pieces that are whole triangles
   C_NSTRAY = 5,   // vertices in cells without pieces
+  C_NOVF = 6,     // interfacial cells whose ring exceeds the fast PPIC kernel's capacities
   C_COUNT = 8
 };
 }  // namespace ftc
@@ -64,6 +65,9 @@ struct ftc_cells {
   int32_t* vt_off;        // [nv_cap+1] triangles per vertex -> offsets
   int32_t* vt_cursor;     // [nv_cap]
   int32_t* vt_ids;        // [3*nt_cap] incident triangles, ascending per vertex
+  int32_t* tri4;          // [4*nt_cap] corners of each triangle packed (t0, t1, t2, 0)
+  double* vtx4;           // [4*nv_cap] coordinates of each vertex packed (x, y, z, 0)
+  int32_t* ovf_cells;     // [cell_cap] cells queued for the wide PPIC kernel
   int32_t* vcell;         // [nv_cap] interfacial cell holding each vertex (-1: none, -2: outside)
   int32_t* vb_off;        // [cell_cap+1] vertices per interfacial cell -> offsets
   int32_t* vb_cursor;     // [cell_cap]

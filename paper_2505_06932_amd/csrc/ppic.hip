@@ -1,26 +1,33 @@
 // ppic.hip -- PPIC curvature by the volume fit (paper section 3.2).
 //
 // Pre-passes (integer work, once per call):
-//   * vertex -> incident triangles (CSR, ascending triangle id);
-//   * vertices binned by the interfacial cell that holds them; vertices in
-//     cells without pieces go to a short "stray" list;
+//   * vertex -> incident triangles (CSR, ascending triangle id), and the
+//     triangles' corners packed as (t0, t1, t2, 0) so one 16-byte load
+//     fetches a triangle;
+//   * vertex coordinates packed as (x, y, z, 0), and the vertices binned by
+//     the interfacial cell that holds them; vertices in cells without pieces
+//     go to a short "stray" list;
 //   * closest vertex of every interfacial cell: 32 lanes per cell, one per
 //     cell of the 3x3x3 block around it, all of them over the strays; lowest
 //     index on ties.  A vertex outside the block is at least 1.5 h from the
 //     cell centre, so a best squared distance below (1.5 h)^2 is final; any
 //     other cell searches all vertices in the main kernel.
 //
-// Main kernel: 16 lanes per interfacial cell, 4 cells per 64-lane wavefront
-// (one wavefront per workgroup), per-cell state in LDS.  Each phase issues
-// all of its loads before it uses them, so a cell makes few dependent trips
-// to memory.
+// Main kernel, one template for two shapes: the fast shape gives 8 lanes to
+// each interfacial cell (8 cells per wavefront) and holds rings of up to 32
+// vertices and 64 triangles in LDS; cells whose ring is larger are queued
+// for the wide shape (64 lanes per cell, rings of 256 vertices and 512
+// triangles), launched right after it.  Cells are assigned so that each XCD
+// processes a contiguous range, which keeps each L2 on one part of the front.
 //   1. ring neighbourhood: V_0 = {v*}; T_r = triangles with a corner in
 //      V_{r-1}; V_r = V_{r-1} plus the corners of T_r.  The (vertex,
-//      incident triangle) candidates of a ring are spread over the 16 lanes
-//      through prefix sums of the vertex degrees; a triangle is taken once,
+//      incident triangle) candidates of a ring are spread over the lanes
+//      through prefix sums of the vertex degrees.  A triangle is taken once,
 //      from the first of its corners (t0, t1, t2 order) that lies in
-//      V_{r-1}; membership and first occurrence use an open-addressing hash
-//      table; the corner ids of the ring triangles stay in LDS;
+//      V_{r-1}.  Membership uses an open-addressing hash table; the corners
+//      of each kept triangle enter the table at once, marked with their
+//      first occurrence (3 x position + corner), and are then placed in
+//      V_r in that order;
 //   2. normal of v* (area-weighted, summed in ascending triangle order: T_1
 //      is v*'s incident list) and a right-handed tangent frame (Duff et al.,
 //      JCGT 2017);
@@ -32,12 +39,12 @@
 //      (coordinates divided by h for conditioning), its six moments by the
 //      edge-midpoint rule (exact for quadratics) and the integral of its
 //      plane, and the weighted normal equations M a = b accumulated in
-//      registers; butterfly reduction over the 16 lanes;
+//      registers; all-reduce over the cell's lanes with row permutations;
 //   5. in-register Cholesky factorisation of the packed M with one step of
 //      iterative refinement, curvature kappa = 2H at the frame origin and the
 //      interface normal.
-// Every loop bound is uniform over the wavefront (maxima over its 4 cells),
-// so LDS phases are separated by plain workgroup barriers.
+// Every loop bound is uniform over the wavefront (maxima over its cells), so
+// LDS phases are separated by plain workgroup barriers.
 #include <float.h>
 
 #include <algorithm>
@@ -49,15 +56,27 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kStrideBlocks = 4096;
+constexpr int kXCD = 8;          // accelerator complex dies; workgroups are dealt to them in turn
+constexpr int kWideBlocks = 64;  // persistent workgroups of the wide shape
 
-constexpr int G = 16;            // lanes per cell
-constexpr int NG = 64 / G;       // cells per wavefront
-constexpr int kHS = 128;         // hash slots per cell
-constexpr int kVC = 64;          // ring-vertex capacity
-constexpr int kTC = 96;          // ring-triangle capacity
-constexpr int kCR = 8;           // candidates per lane per batch
-constexpr int kBatch = kCR * G;  // candidates per batch
-constexpr int kTR = kTC / G;     // ring triangles per lane
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+template <int G_, int HS_, int VC_, int TC_, int CR_>
+struct Cfg {
+  static constexpr int G = G_;        // lanes per cell
+  static constexpr int NG = 64 / G_;  // cells per wavefront
+  static constexpr int HS = HS_;      // hash slots (power of two)
+  static constexpr int VC = VC_;      // ring-vertex capacity (owner table holds bytes: <= 256)
+  static constexpr int TC = TC_;      // ring-triangle capacity
+  static constexpr int CR = CR_;      // candidates per lane per batch
+  static constexpr int Batch = CR_ * G_;
+  static constexpr int TR = (TC_ + G_ - 1) / G_;
+  static constexpr int FW = (3 * TC_ + 31) / 32;  // words of the first-occurrence bitmap
+  static_assert((HS_ & (HS_ - 1)) == 0 && HS_ >= 2 * VC_, "hash size");
+  static_assert(VC_ <= 256, "owner table holds bytes");
+};
+using Fast = Cfg<8, 64, 32, 64, 8>;
+using Wide = Cfg<64, 512, 256, 512, 4>;
 
 // ----------------------------------------------------------------- pre-passes
 __global__ void k_clear_ppic(int32_t* vt_off, int64_t n1, int32_t* vt_cursor, int64_t n2, int32_t* vb_off,
@@ -68,14 +87,22 @@ __global__ void k_clear_ppic(int32_t* vt_off, int64_t n1, int32_t* vt_cursor, in
   for (int64_t i = g0; i < n2; i += stride) vt_cursor[i] = 0;
   for (int64_t i = g0; i < n3; i += stride) vb_off[i] = 0;
   for (int64_t i = g0; i < n4; i += stride) vb_cursor[i] = 0;
-  if (g0 == 0) counters[C_NSTRAY] = 0;
+  if (g0 == 0) {
+    counters[C_NSTRAY] = 0;
+    counters[C_NOVF] = 0;
+  }
 }
 
-// A triangle is listed once under each of its distinct corners.
-__global__ void k_vt_count(Mesh m, int32_t* vt_cnt) {
+// A triangle is listed once under each of its distinct corners.  Also packs
+// the corners; a triangle with an invalid corner is packed as (0, 0, 0) and
+// listed nowhere.
+__global__ void k_vt_count(Mesh m, int32_t* vt_cnt, int4* tri4) {
   const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m.nt || !tri_ok(m, t)) return;
+  if (t >= m.nt) return;
   const int32_t a = m.t0[t], b = m.t1[t], c = m.t2[t];
+  const bool ok = a >= 0 && b >= 0 && c >= 0 && a < m.nv && b < m.nv && c < m.nv;
+  tri4[t] = ok ? make_int4(a, b, c, 0) : make_int4(0, 0, 0, 0);
+  if (!ok) return;
   atomicAdd(&vt_cnt[a], 1);
   if (b != a) atomicAdd(&vt_cnt[b], 1);
   if (c != a && c != b) atomicAdd(&vt_cnt[c], 1);
@@ -112,14 +139,17 @@ __device__ inline int32_t cell_rank(const uint32_t* bitmap, const int32_t* word_
   return word_off[lin >> 5] + __popc(below);
 }
 
-// Interfacial cell of every vertex (-1: a cell without pieces, the vertex
-// becomes a stray; -2: outside the margin, latched as a domain error by the
-// cell-list build) and the number of vertices per interfacial cell.
-__global__ void k_vb_count(Grid g, Mesh m, const uint32_t* bitmap, const int32_t* word_off, int32_t* vcell,
-                           int32_t* vb_cnt, int32_t* stray, int32_t cell_cap, int32_t* counters) {
+// Packs the coordinates; finds the interfacial cell of every vertex (-1: a
+// cell without pieces, the vertex becomes a stray; -2: outside the margin,
+// latched as a domain error by the cell-list build) and counts the vertices
+// per interfacial cell.
+__global__ void k_vb_count(Grid g, Mesh m, const uint32_t* bitmap, const int32_t* word_off, double2* vtx4,
+                           int32_t* vcell, int32_t* vb_cnt, int32_t* stray, int32_t cell_cap, int32_t* counters) {
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= m.nv) return;
   const double x = m.x[v], y = m.y[v], z = m.z[v];
+  vtx4[2 * (int64_t)v] = make_double2(x, y);
+  vtx4[2 * (int64_t)v + 1] = make_double2(z, 0.0);
   int32_t ci = -2;
   if (in_margin(g, x, y, z)) {
     const int64_t i = cell_index(x, g.x0, g.h), j = cell_index(y, g.y0, g.h), k = cell_index(z, g.z0, g.h);
@@ -145,8 +175,18 @@ __device__ inline bool lex_less(double d, int32_t v, double bd, int32_t bv) {
   return d < bd || (d == bd && v < bv);
 }
 
-__device__ inline void consider(const Mesh& m, int32_t v, const double xc[3], double& bd, int32_t& bv) {
-  const double dx = m.x[v] - xc[0], dy = m.y[v] - xc[1], dz = m.z[v] - xc[2];
+struct P3 {
+  double x, y, z;
+};
+
+__device__ inline P3 vtx(const double2* vtx4, int32_t v) {
+  const double2 a = vtx4[2 * (int64_t)v], b = vtx4[2 * (int64_t)v + 1];
+  return P3{a.x, a.y, b.x};
+}
+
+__device__ inline void consider(const double2* vtx4, int32_t v, const double xc[3], double& bd, int32_t& bv) {
+  const P3 p = vtx(vtx4, v);
+  const double dx = p.x - xc[0], dy = p.y - xc[1], dz = p.z - xc[2];
   const double d2 = dx * dx + dy * dy + dz * dz;
   if (lex_less(d2, v, bd, bv)) {
     bd = d2;
@@ -158,10 +198,10 @@ __device__ inline double cell_centre(double org, int32_t i, double h) { return o
 
 // 32 lanes per interfacial cell: lane l < 27 scans the vertex bin of cell l
 // of the 3x3x3 block around it, every lane a share of the strays.
-__global__ __launch_bounds__(kT) void k_vstar(Grid g, Mesh m, const int32_t* cell_ids, const uint32_t* bitmap,
-                                              const int32_t* word_off, const int32_t* vb_off, const int32_t* vb_ids,
-                                              const int32_t* stray, double* best_d2, int32_t* best_v,
-                                              int32_t cell_cap, const int32_t* counters) {
+__global__ __launch_bounds__(kT) void k_vstar(Grid g, const double2* vtx4, const int32_t* cell_ids,
+                                              const uint32_t* bitmap, const int32_t* word_off, const int32_t* vb_off,
+                                              const int32_t* vb_ids, const int32_t* stray, double* best_d2,
+                                              int32_t* best_v, int32_t cell_cap, const int32_t* counters) {
   const int32_t nif = min(counters[C_NIF], cell_cap);
   const int32_t nstray = counters[C_NSTRAY];
   const int64_t gid = (int64_t)blockIdx.x * kT + threadIdx.x;
@@ -177,10 +217,10 @@ __global__ __launch_bounds__(kT) void k_vstar(Grid g, Mesh m, const int32_t* cel
       if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) {
         const int32_t cr = cell_rank(bitmap, word_off, ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk));
         if (cr >= 0 && cr < cell_cap)
-          for (int32_t p = vb_off[cr], e = vb_off[cr + 1]; p < e; ++p) consider(m, vb_ids[p], xc, bd, bv);
+          for (int32_t p = vb_off[cr], e = vb_off[cr + 1]; p < e; ++p) consider(vtx4, vb_ids[p], xc, bd, bv);
       }
     }
-    for (int32_t q = l; q < nstray; q += 32) consider(m, stray[q], xc, bd, bv);
+    for (int32_t q = l; q < nstray; q += 32) consider(vtx4, stray[q], xc, bd, bv);
   }
 #pragma unroll
   for (int o = 16; o >= 1; o >>= 1) {
@@ -200,69 +240,95 @@ __global__ __launch_bounds__(kT) void k_vstar(Grid g, Mesh m, const int32_t* cel
 // ----------------------------------------------------------------- main kernel
 struct PPICArgs {
   Grid g;
-  Mesh m;
+  int32_t nv;
   PPICParams prm;
+  const int4* tri4;
+  const double2* vtx4;
   const int32_t* cell_ids;
   const int32_t* vt_off;
   const int32_t* vt_ids;
   const double* best_d2;
   const int32_t* best_v;
-  const int32_t* counters;
+  int32_t* counters;
+  int32_t* ovf_cells;
   int32_t cell_cap;
   double *kappa, *nx, *ny, *nz, *coeff;
   int32_t *status, *diag;
 };
 
 // Ring-building state, dead once the rings are complete.
+template <class C>
 struct RingMem {
-  int32_t hkey[kHS];    // hash set of ring vertices (-1: empty slot)
-  int32_t hval[kHS];    // first occurrence among the new corners; -1 - position once in V
-  int32_t V[kVC];       // ring vertices
-  int32_t Vo[kVC];      // offset of their incident-triangle list
-  int32_t Vd[kVC];      // their degrees
-  int32_t Vs[kVC + 1];  // prefix sums of the degrees
-  uint8_t own[kBatch];  // ring vertex of each candidate of the current batch
+  int32_t hkey[C::HS];    // hash set of vertices: -1 empty, v new in this ring, v | kPlaced in V
+  int32_t hval[C::HS];    // first occurrence (3 x position + corner) of a new vertex
+  int32_t V[C::VC];       // ring vertices
+  int32_t Vo[C::VC];      // offset of their incident-triangle lists
+  int32_t Vs[C::VC + 1];  // prefix sums of their degrees
+  uint32_t fbits[C::FW];  // first occurrences of the new vertices of the current ring
+  uint8_t own[C::Batch];  // ring vertex of each candidate of the current batch
 };
 // Fit state, alive after the rings.
+template <class C>
 struct FitMem {
-  double Mres[21];  // normal matrix, kept for the refinement residual
-  double W[kTC];    // weights of the triangles inside the support
-  int32_t S[kTC];   // their positions in the ring list
+  double Mres[21];   // normal matrix, kept for the refinement residual
+  double W[C::TC];   // weights of the triangles inside the support
+  int32_t S[C::TC];  // those triangles
 };
+template <class C>
 struct __align__(8) CellMem {
   union {
-    RingMem r;
-    FitMem f;
+    RingMem<C> r;
+    FitMem<C> f;
   } u;
-  int32_t Tc[3][kTC];  // corners of the ring triangles
+  int32_t T[C::TC];  // ring triangles
 };
 
-__device__ inline int hslot(int32_t key) { return (int)(((uint32_t)key * 2654435761u) >> 25); }  // 128 slots
+constexpr int32_t kPlaced = INT32_MIN;  // vertex ids are below 2^31 - 1, so key | kPlaced != -1
 
-// Insert key (if absent) and return its slot; -1 if the table is full.
-__device__ inline int hinsert(RingMem& M, int32_t key) {
-  int s = hslot(key);
-  for (int p = 0; p < kHS; ++p) {
+template <int HS>
+__device__ inline int hslot(int32_t key) {
+  return (int)(((uint32_t)key * 2654435761u) >> (32 - ilog2(HS)));
+}
+
+// Insert key (if absent, as a new vertex) and return its slot; -1 if the
+// table is full.
+template <class C>
+__device__ inline int hinsert(RingMem<C>& M, int32_t key) {
+  int s = hslot<C::HS>(key);
+  for (int p = 0; p < C::HS; ++p) {
     const int32_t prev = atomicCAS(&M.hkey[s], -1, key);
-    if (prev == -1 || prev == key) return s;
-    s = (s + 1) & (kHS - 1);
+    if (prev == -1 || prev == key || prev == (key | kPlaced)) return s;
+    s = (s + 1) & (C::HS - 1);
   }
   return -1;
 }
 
-__device__ inline int hfind(const RingMem& M, int32_t key) {
-  int s = hslot(key);
-  for (int p = 0; p < kHS; ++p) {
+// Is key a vertex of the previous ring (placed in V)?  home is the table
+// entry at the key's home slot, read beforehand.
+template <class C>
+__device__ inline bool in_ring(const RingMem<C>& M, int32_t key, int32_t home) {
+  const int32_t placed = key | kPlaced;
+  if (home == placed) return true;
+  if (home == -1 || home == key) return false;
+  int s = hslot<C::HS>(key);
+  for (int p = 0; p < C::HS; ++p) {
     const int32_t k = M.hkey[s];
-    if (k == key) return s;
-    if (k == -1) return -1;
-    s = (s + 1) & (kHS - 1);
+    if (k == placed) return true;
+    if (k == -1 || k == key) return false;
+    s = (s + 1) & (C::HS - 1);
   }
-  return -1;
+  return false;
 }
 
-// 16-bit ballot of this lane's group.
-__device__ inline uint32_t gballot(bool p, int grp) { return (uint32_t)((__ballot(p) >> (G * grp)) & 0xFFFFull); }
+// Ballot of this lane's group, in the group's low bits.
+template <int G>
+__device__ inline uint64_t gballot(bool p, int grp) {
+  const uint64_t b = __ballot(p);
+  if constexpr (G == 64)
+    return b;
+  else
+    return (b >> (G * grp)) & ((1ull << G) - 1ull);
+}
 
 __device__ inline int wave_max_i(int v) {
 #pragma unroll
@@ -270,11 +336,28 @@ __device__ inline int wave_max_i(int v) {
   return v;
 }
 
-// Membership of key, given the key stored at its home slot.
-__device__ inline bool member(const RingMem& M, int32_t key, int32_t home) {
-  if (home == key) return true;
-  if (home == -1) return false;
-  return hfind(M, key) >= 0;
+// Lane permutations within rows of 16 lanes (data-parallel primitives):
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror.
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+
+// Sum over each aligned group of G lanes, the same bits in every lane: each
+// step adds a value from a partner lane that adds this lane's value back.
+// Called with all 64 lanes active.
+template <int G>
+__device__ inline double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_d<0xB1>(v);
+  if constexpr (G >= 4) v += dpp_d<0x4E>(v);
+  if constexpr (G >= 8) v += dpp_d<0x141>(v);
+  if constexpr (G >= 16) v += dpp_d<0x140>(v);
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
 }
 
 // x / 3 correctly rounded: a product with the rounded reciprocal, corrected
@@ -288,24 +371,34 @@ __device__ inline double div3(double x) {
 // packed index of entry (a, b), a <= b, of a symmetric 6x6 matrix
 __host__ __device__ constexpr int P6(int a, int b) { return a * 6 - a * (a - 1) / 2 + (b - a); }
 
+// kQueue = false: every interfacial cell, overflowing cells queued.
+// kQueue = true: the queued cells.
+template <class C, bool kQueue>
 __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
-  __shared__ CellMem SM[NG];
+  constexpr int G = C::G, NG = C::NG;
+  __shared__ CellMem<C> SM[NG];
   const Grid& g = A.g;
-  const Mesh& m = A.m;
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
-  CellMem& C = SM[grp];
-  RingMem& RM = C.u.r;
-  FitMem& FM = C.u.f;
-  const int32_t nif = min(A.counters[C_NIF], A.cell_cap);
+  CellMem<C>& CM = SM[grp];
+  RingMem<C>& RM = CM.u.r;
+  FitMem<C>& FM = CM.u.f;
+  const int32_t nitems = kQueue ? min(A.counters[C_NOVF], A.cell_cap) : min(A.counters[C_NIF], A.cell_cap);
   const double h = g.h;
   const int R = A.prm.rings;
   const double reach = 1.5 * h;
   const double reach2 = reach * reach * (1.0 - 1e-12);
-  const uint32_t below_me = (1u << gl) - 1u;
+  const uint64_t below_me = (1ull << gl) - 1ull;
 
-  for (int32_t base = blockIdx.x * NG; base < nif; base += gridDim.x * NG) {
-    const int32_t c = base + grp;
-    const bool act = c < nif;
+  // each XCD takes a contiguous range of cell groups
+  const int32_t ngroups = (nitems + NG - 1) / NG;
+  const int32_t per = (ngroups + kXCD - 1) / kXCD;
+  const int32_t xcd = blockIdx.x % kXCD, nj = gridDim.x / kXCD;
+  for (int32_t q = blockIdx.x / kXCD; q < per; q += nj) {
+    const int32_t gi = xcd * per + q;
+    if (gi >= ngroups) break;
+    const int32_t item = gi * NG + grp;
+    const bool act = item < nitems;
+    const int32_t c = act ? (kQueue ? A.ovf_cells[item] : item) : 0;
     const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
     const double xc[3] = {cell_centre(g.x0, cc3.i, h), cell_centre(g.y0, cc3.j, h), cell_centre(g.z0, cc3.k, h)};
 
@@ -316,7 +409,7 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
       double bd = DBL_MAX;
       int32_t bv = INT_MAX;
       if (need)
-        for (int32_t v = gl; v < m.nv; v += G) consider(m, v, xc, bd, bv);
+        for (int32_t v = gl; v < A.nv; v += G) consider(A.vtx4, v, xc, bd, bv);
 #pragma unroll
       for (int o = G / 2; o >= 1; o >>= 1) {
         const double od = __shfl_xor(bd, o, 64);
@@ -328,124 +421,133 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
       }
       if (need) vs = bv;
     }
-    bool ok = act && vs >= 0 && vs < m.nv;
-    const int32_t vsafe = ok ? vs : 0;  // a valid vertex for branch-free loads
+    bool ok = act && vs >= 0 && vs < A.nv;
 
     // ---- ring neighbourhood
-    for (int s = gl; s < kHS; s += G) {
+    for (int s = gl; s < C::HS; s += G) {
       RM.hkey[s] = -1;
       RM.hval[s] = INT_MAX;
     }
     __syncthreads();
     if (ok && gl == 0) {
-      const int s = hinsert(RM, vs);  // empty table: never fails
-      RM.hval[s] = -1;
+      RM.hkey[hslot<C::HS>(vs)] = vs | kPlaced;  // empty table
       const int32_t o0 = A.vt_off[vs];
       RM.V[0] = vs;
       RM.Vo[0] = o0;
-      RM.Vd[0] = A.vt_off[vs + 1] - o0;
       RM.Vs[0] = 0;
-      RM.Vs[1] = RM.Vd[0];
+      RM.Vs[1] = A.vt_off[vs + 1] - o0;
     }
     __syncthreads();
     int32_t nV = 1, nT = 0;
-    bool overflow = false;
+    bool ovf = false;
     double n0 = 0.0, n1 = 0.0, n2 = 1.0;
     for (int r = 1; r <= R; ++r) {
-      // T_r from the candidates of V_{r-1}, in batches of kBatch
-      const int nVc = min(nV, kVC);
-      const int tot = (ok && !overflow) ? RM.Vs[nVc] : 0;
-      const int nb = wave_max_i((tot + kBatch - 1) / kBatch);
+      for (int w = gl; w < C::FW; w += G) RM.fbits[w] = 0u;
+      // T_r from the candidates of V_{r-1}, in batches
+      const int nVc = min(nV, C::VC);
+      const int tot = (ok && !ovf) ? RM.Vs[nVc] : 0;
+      const int nb = wave_max_i((tot + C::Batch - 1) / C::Batch);
       const int prounds = wave_max_i(tot > 0 ? (nVc + G - 1) / G : 0);
       nT = 0;
+      bool full = false;
       for (int b = 0; b < nb; ++b) {
-        const int b0 = b * kBatch;
-        // owners of the candidates [b0, b0 + kBatch)
+        const int b0 = b * C::Batch;
+        // owners of the candidates [b0, b0 + Batch)
         for (int k = 0; k < prounds; ++k) {
           const int p = k * G + gl;
           if (tot > 0 && p < nVc) {
-            const int lo = max(RM.Vs[p], b0), hi = min(RM.Vs[p + 1], b0 + kBatch);
+            const int lo = max(RM.Vs[p], b0), hi = min(RM.Vs[p + 1], b0 + C::Batch);
             for (int f = lo; f < hi; ++f) RM.own[f - b0] = (uint8_t)p;
           }
         }
         __syncthreads();
-        int32_t ct[kCR], cu[kCR], c0[kCR], c1[kCR], c2[kCR];
+        const int kact = wave_max_i(min(C::CR, max(0, (tot - b0 + G - 1) / G)));
+        int32_t ct[C::CR], cu[C::CR];
 #pragma unroll
-        for (int k = 0; k < kCR; ++k) {
-          const int f = b0 + k * G + gl;
+        for (int k = 0; k < C::CR; ++k) {
           ct[k] = -1;
           cu[k] = -1;
-          if (f < tot) {
-            const int p = RM.own[f - b0];
-            cu[k] = RM.V[p];
-            ct[k] = A.vt_ids[RM.Vo[p] + (f - RM.Vs[p])];
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < kCR; ++k) {
-          const int32_t t = ct[k] >= 0 ? ct[k] : 0;
-          c0[k] = m.t0[t];
-          c1[k] = m.t1[t];
-          c2[k] = m.t2[t];
-        }
-        // a triangle is kept from the first of its corners in V_{r-1}; every
-        // corner before the owner must lie outside V_{r-1}
-        int32_t h0[kCR], h1[kCR];
-#pragma unroll
-        for (int k = 0; k < kCR; ++k) {
-          h0[k] = RM.hkey[hslot(c0[k])];
-          h1[k] = RM.hkey[hslot(c1[k])];
-        }
-#pragma unroll
-        for (int k = 0; k < kCR; ++k) {
-          bool keep = ct[k] >= 0;
-          if (keep && r > 1 && c0[k] != cu[k]) {
-            keep = !member(RM, c0[k], h0[k]);
-            if (keep && c1[k] != cu[k]) keep = !member(RM, c1[k], h1[k]);
-          }
-          const uint32_t bal = gballot(keep, grp);
-          if (keep) {
-            const int pos = nT + __popc(bal & below_me);
-            if (pos < kTC) {
-              C.Tc[0][pos] = c0[k];
-              C.Tc[1][pos] = c1[k];
-              C.Tc[2][pos] = c2[k];
+          if (k < kact) {
+            const int f = b0 + k * G + gl;
+            if (f < tot) {
+              const int p = RM.own[f - b0];
+              cu[k] = RM.V[p];
+              ct[k] = A.vt_ids[RM.Vo[p] + (f - RM.Vs[p])];
             }
           }
-          nT += __popc(bal);
         }
+        int4 cc[C::CR];
+#pragma unroll
+        for (int k = 0; k < C::CR; ++k)
+          if (k < kact) cc[k] = A.tri4[ct[k] >= 0 ? ct[k] : 0];
+        // a triangle is kept from the first of its corners in V_{r-1}: every
+        // corner before the owner must lie outside V_{r-1}
+        int32_t hk0[C::CR], hk1[C::CR];
+#pragma unroll
+        for (int k = 0; k < C::CR; ++k)
+          if (k < kact) {
+            hk0[k] = RM.hkey[hslot<C::HS>(cc[k].x)];
+            hk1[k] = RM.hkey[hslot<C::HS>(cc[k].y)];
+          }
+#pragma unroll
+        for (int k = 0; k < C::CR; ++k)
+          if (k < kact) {
+            bool keep = ct[k] >= 0;
+            if (keep && r > 1 && cc[k].x != cu[k]) {
+              keep = !in_ring<C>(RM, cc[k].x, hk0[k]);
+              if (keep && cc[k].y != cu[k]) keep = !in_ring<C>(RM, cc[k].y, hk1[k]);
+            }
+            const uint64_t bal = gballot<G>(keep, grp);
+            if (keep) {
+              const int pos = nT + __popcll(bal & below_me);
+              if (pos < C::TC) {
+                CM.T[pos] = ct[k];
+                if (r < R) {
+                  // the corners enter the table, marked with their first occurrence
+                  const int32_t cr[3] = {cc[k].x, cc[k].y, cc[k].z};
+#pragma unroll
+                  for (int e = 0; e < 3; ++e) {
+                    const int s = hinsert<C>(RM, cr[e]);
+                    if (s >= 0)
+                      atomicMin(&RM.hval[s], 3 * pos + e);
+                    else
+                      full = true;
+                  }
+                }
+              }
+            }
+            nT += __popcll(bal);
+          }
         __syncthreads();
       }
-      if (nT > kTC) overflow = true;
-      __syncthreads();
+      if (nT > C::TC || gballot<G>(full, grp)) ovf = true;
 
       if (r == 1) {
         // normal of v*: T_1 is v*'s incident list, ascending; the cross
         // products are summed serially in that order
-        const int n1c = (ok && !overflow) ? nT : 0;
+        const int n1c = (ok && !ovf) ? nT : 0;
         const int nr = wave_max_i((n1c + G - 1) / G);
+        const int qn = wave_max_i(min(n1c, G));
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int k = 0; k < nr; ++k) {
           const int i = k * G + gl;
-          const bool valid = i < n1c;
-          const int32_t a = valid ? C.Tc[0][i] : vsafe, bb = valid ? C.Tc[1][i] : vsafe,
-                        e = valid ? C.Tc[2][i] : vsafe;
-          const double ax = m.x[a], ay = m.y[a], az = m.z[a];
-          const double ux = m.x[bb] - ax, uy = m.y[bb] - ay, uz = m.z[bb] - az;
-          const double wx = m.x[e] - ax, wy = m.y[e] - ay, wz = m.z[e] - az;
+          const int4 t4 = A.tri4[i < n1c ? CM.T[i] : 0];
+          const P3 a = vtx(A.vtx4, t4.x), bb = vtx(A.vtx4, t4.y), e = vtx(A.vtx4, t4.z);
+          const double ux = bb.x - a.x, uy = bb.y - a.y, uz = bb.z - a.z;
+          const double wx = e.x - a.x, wy = e.y - a.y, wz = e.z - a.z;
           const double cx = uy * wz - uz * wy;
           const double cy = uz * wx - ux * wz;
           const double cz = ux * wy - uy * wx;
-          for (int q = 0; q < G; ++q) {
-            const double x = __shfl(cx, q, G), y = __shfl(cy, q, G), z = __shfl(cz, q, G);
-            if (k * G + q < n1c) {
+          for (int qq = 0; qq < qn; ++qq) {
+            const double x = __shfl(cx, qq, G), y = __shfl(cy, qq, G), z = __shfl(cz, qq, G);
+            if (k * G + qq < n1c) {
               s0 += x;
               s1 += y;
               s2 += z;
             }
           }
         }
-        if (ok && !overflow) {
+        if (ok && !ovf) {
           const double nl = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
           n0 = s0 / nl;
           n1 = s1 / nl;
@@ -454,66 +556,60 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
       }
       if (r == R) break;
 
-      // V_r: the new corners of T_r, in (triangle, corner) order of first occurrence
-      const int nf = (ok && !overflow) ? 3 * nT : 0;
-      const int frounds = wave_max_i((nf + G - 1) / G);
-      bool full = false;
-      for (int k = 0; k < frounds; ++k) {
-        const int f = k * G + gl;
-        if (f < nf) {
-          const int s = hinsert(RM, C.Tc[f % 3][f / 3]);
-          if (s >= 0)
-            atomicMin(&RM.hval[s], f);
-          else
-            full = true;
-        }
+      // V_r: the new corners of T_r in order of first occurrence
+      const bool go = ok && !ovf;
+      for (int s = gl; s < C::HS; s += G) {
+        const int32_t f = RM.hval[s];
+        if (go && RM.hkey[s] >= 0 && f < 3 * C::TC) atomicOr(&RM.fbits[f >> 5], 1u << (f & 31));
       }
-      if (gballot(full, grp)) overflow = true;
       __syncthreads();
-      for (int k = 0; k < frounds; ++k) {
-        const int f = k * G + gl;
-        bool fresh = false;
-        int s = -1;
-        int32_t cv = 0;
-        if (f < nf) {
-          cv = C.Tc[f % 3][f / 3];
-          s = hfind(RM, cv);
-          fresh = s >= 0 && RM.hval[s] == f;
-        }
-        const uint32_t bal = gballot(fresh, grp);
-        if (fresh) {
-          const int pos = nV + __popc(bal & below_me);
-          if (pos < kVC) {
-            const int32_t o0 = A.vt_off[cv];
-            RM.V[pos] = cv;
+      int nnew = 0;
+#pragma unroll
+      for (int w = 0; w < C::FW; ++w) nnew += __popc(RM.fbits[w]);
+      for (int s = gl; s < C::HS; s += G) {
+        const int32_t f = RM.hval[s], key = RM.hkey[s];
+        if (go && key >= 0 && f < 3 * C::TC) {
+          int rank = __popc(RM.fbits[f >> 5] & ((1u << (f & 31)) - 1u));
+          for (int w = 0; w < (f >> 5); ++w) rank += __popc(RM.fbits[w]);
+          const int pos = nV + rank;
+          if (pos < C::VC) {
+            const int32_t o0 = A.vt_off[key];
+            RM.V[pos] = key;
             RM.Vo[pos] = o0;
-            RM.Vd[pos] = A.vt_off[cv + 1] - o0;
+            RM.Vs[pos + 1] = A.vt_off[key + 1] - o0;  // degree, turned into a prefix sum below
           }
-          RM.hval[s] = -1 - pos;
+          RM.hkey[s] = key | kPlaced;
         }
-        nV += __popc(bal);
       }
-      if (nV > kVC) overflow = true;
+      const int nV0 = nV;
+      if (go) nV += nnew;
+      if (nV > C::VC) ovf = true;
       __syncthreads();
-      // prefix sums of the degrees
-      const int nVs = (ok && !overflow) ? nV : 0;
-      const int vrounds = wave_max_i((nVs + G - 1) / G);
-      int32_t run = 0;
+      // prefix sums of the new degrees, in place
+      const int pend = (ok && !ovf) ? nV : nV0;
+      const int vrounds = wave_max_i((pend - nV0 + G - 1) / G);
+      int32_t run = (ok && !ovf) ? RM.Vs[nV0] : 0;
       for (int k = 0; k < vrounds; ++k) {
-        const int p = k * G + gl;
-        int32_t inc = p < nVs ? RM.Vd[p] : 0;
+        const int p = nV0 + k * G + gl;
+        int32_t inc = p < pend ? RM.Vs[p + 1] : 0;
 #pragma unroll
         for (int o = 1; o < G; o <<= 1) {
           const int32_t t = __shfl_up(inc, o, G);
           if (gl >= o) inc += t;
         }
-        if (p < nVs) RM.Vs[p + 1] = run + inc;
+        if (p < pend) RM.Vs[p + 1] = run + inc;
         run += __shfl(inc, G - 1, G);
       }
       __syncthreads();
     }
-    if (overflow) ok = false;
-    const int nTc = ok ? min(nT, kTC) : 0;
+
+    if (!kQueue && ovf && ok) {
+      // a ring beyond this shape's capacities: the wide shape takes the cell
+      if (gl == 0) A.ovf_cells[atomicAdd(&A.counters[C_NOVF], 1)] = c;
+    }
+    const bool emit = act && !(!kQueue && ovf && ok);
+    if (ovf) ok = false;
+    const int nTc = ok ? min(nT, C::TC) : 0;
 
     const double sg = copysign(1.0, n2);
     const double fa = -1.0 / (sg + n2);
@@ -521,19 +617,22 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
     const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
     const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
 
-    // ---- centre distances, support radius, weights
-    double d2[kTR];
-#pragma unroll
-    for (int k = 0; k < kTR; ++k) {
-      const int i = k * G + gl;
-      const bool valid = i < nTc;
-      const int32_t a = valid ? C.Tc[0][i] : vsafe, b = valid ? C.Tc[1][i] : vsafe,
-                    e = valid ? C.Tc[2][i] : vsafe;
-      const double cx = div3(m.x[a] + m.x[b] + m.x[e]);
-      const double cy = div3(m.y[a] + m.y[b] + m.y[e]);
-      const double cz = div3(m.z[a] + m.z[b] + m.z[e]);
-      const double dx = cx - xc[0], dy = cy - xc[1], dz = cz - xc[2];
-      d2[k] = valid ? dx * dx + dy * dy + dz * dz : DBL_MAX;
+    // ---- centre distances (kept in the weight list's storage), support
+    // radius, weights
+    const int drounds = wave_max_i((nTc + G - 1) / G);
+    {
+      int4 cn = A.tri4[gl < nTc ? CM.T[gl] : 0];
+      for (int k = 0; k < drounds; ++k) {
+        const int i = k * G + gl;
+        const int4 c4 = cn;
+        cn = A.tri4[i + G < nTc ? CM.T[i + G] : 0];
+        const P3 a = vtx(A.vtx4, c4.x), b = vtx(A.vtx4, c4.y), e = vtx(A.vtx4, c4.z);
+        const double cx = div3(a.x + b.x + e.x);
+        const double cy = div3(a.y + b.y + e.y);
+        const double cz = div3(a.z + b.z + e.z);
+        const double dx = cx - xc[0], dy = cy - xc[1], dz = cz - xc[2];
+        if (i < nTc) FM.W[i] = dx * dx + dy * dy + dz * dz;
+      }
     }
     double delta = A.prm.delta_over_h * h;
     int32_t it = 0, cnt = 0;
@@ -541,8 +640,7 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
     for (;;) {
       const double lim = delta * delta;
       int mine = 0;
-#pragma unroll
-      for (int k = 0; k < kTR; ++k) mine += (k * G + gl < nTc && d2[k] < lim) ? 1 : 0;
+      for (int i = gl; i < nTc; i += G) mine += FM.W[i] < lim ? 1 : 0;
 #pragma unroll
       for (int o = G / 2; o >= 1; o >>= 1) mine += __shfl_xor(mine, o, 64);
       if (!done) {
@@ -559,19 +657,23 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
     {
       const double lim = delta * delta;
       const double inv_delta = 1.0 / delta;
+      // compaction in place: an entry moves to a position not after its own,
+      // and every lane reads its round's entries before any lane writes
       int nw = 0;
-#pragma unroll
-      for (int k = 0; k < kTR; ++k) {
-        const bool keep = k * G + gl < nTc && d2[k] < lim;
-        const uint32_t bal = gballot(keep, grp);
+      for (int k = 0; k < drounds; ++k) {
+        const int i = k * G + gl;
+        const double dd = i < nTc ? FM.W[i] : DBL_MAX;
+        const int32_t ti = i < nTc ? CM.T[i] : 0;
+        const bool keep = i < nTc && dd < lim;
+        const uint64_t bal = gballot<G>(keep, grp);
         if (keep) {
-          const int pos = nw + __popc(bal & below_me);
-          const double qq = sqrt(d2[k]) * inv_delta;
+          const int pos = nw + __popcll(bal & below_me);
+          const double qq = sqrt(dd) * inv_delta;
           const double om = 1.0 - qq;
           FM.W[pos] = (1.0 + 4.0 * qq) * (om * om) * (om * om);
-          FM.S[pos] = k * G + gl;
+          FM.S[pos] = ti;
         }
-        nw += __popc(bal);
+        nw += __popcll(bal);
       }
     }
     __syncthreads();
@@ -580,21 +682,27 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
     const double inv_h = 1.0 / h;
     double acc[27];
 #pragma unroll
-    for (int q = 0; q < 27; ++q) acc[q] = 0.0;
+    for (int qa = 0; qa < 27; ++qa) acc[qa] = 0.0;
     const int wrounds = wave_max_i(ok ? (cnt + G - 1) / G : 0);
+    int4 tn = A.tri4[(ok && gl < cnt) ? FM.S[gl] : 0];
     for (int k = 0; k < wrounds; ++k) {
       const int j = k * G + gl;
       const bool valid = ok && j < cnt;
-      const int i = valid ? FM.S[j] : 0;
       const double w = valid ? FM.W[j] : 0.0;
+      const int4 t4 = tn;
+      {
+        const int jn = j + G;
+        tn = A.tri4[(ok && jn < cnt) ? FM.S[jn] : 0];
+      }
+      const int32_t cr[3] = {t4.x, t4.y, t4.z};
       double xi[3], eta[3], zeta[3];
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const int32_t v = valid ? C.Tc[r][i] : vsafe;
-        const double dx = m.x[v] - xc[0], dy = m.y[v] - xc[1], dz = m.z[v] - xc[2];
-        xi[r] = fma(dz, t1z, fma(dy, t1y, dx * t1x)) * inv_h;
-        eta[r] = fma(dz, t2z, fma(dy, t2y, dx * t2x)) * inv_h;
-        zeta[r] = fma(dz, n2, fma(dy, n1, dx * n0)) * inv_h;
+      for (int e = 0; e < 3; ++e) {
+        const P3 p = vtx(A.vtx4, cr[e]);
+        const double dx = p.x - xc[0], dy = p.y - xc[1], dz = p.z - xc[2];
+        xi[e] = fma(dz, t1z, fma(dy, t1y, dx * t1x)) * inv_h;
+        eta[e] = fma(dz, t2z, fma(dy, t2y, dx * t2x)) * inv_h;
+        zeta[e] = fma(dz, n2, fma(dy, n1, dx * n0)) * inv_h;
       }
       const double area = 0.5 * fma(xi[1] - xi[0], eta[2] - eta[0], -((xi[2] - xi[0]) * (eta[1] - eta[0])));
       double sm[6] = {3.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -611,7 +719,7 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
       const double a3 = area * (1.0 / 3.0);
       double mom[6];
 #pragma unroll
-      for (int q = 0; q < 6; ++q) mom[q] = a3 * sm[q];
+      for (int qa = 0; qa < 6; ++qa) mom[qa] = a3 * sm[qa];
       const double wv = w * (a3 * (zeta[0] + zeta[1] + zeta[2]));
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
@@ -622,21 +730,18 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
       }
     }
 #pragma unroll
-    for (int q = 0; q < 27; ++q) {
-#pragma unroll
-      for (int o = G / 2; o >= 1; o >>= 1) acc[q] += __shfl_xor(acc[q], o, 64);
-    }
+    for (int qa = 0; qa < 27; ++qa) acc[qa] = group_sum<G>(acc[qa]);
 
     // ---- solve (every lane of the group holds M and b).  M is kept in LDS
     // for the refinement residual and factorised in place in registers.
     if (gl == 0) {
 #pragma unroll
-      for (int q = 0; q < 21; ++q) FM.Mres[q] = acc[q];
+      for (int qa = 0; qa < 21; ++qa) FM.Mres[qa] = acc[qa];
     }
     __syncthreads();
     double co[6] = {NAN, NAN, NAN, NAN, NAN, NAN};
     double kap = NAN, ni0 = NAN, ni1 = NAN, ni2 = NAN;
-    uint32_t st = overflow ? FTC_CELL_OVERFLOW : 0u;
+    uint32_t st = ovf ? FTC_CELL_OVERFLOW : 0u;
     if (ok) {
       const double trace =
           acc[P6(0, 0)] + acc[P6(1, 1)] + acc[P6(2, 2)] + acc[P6(3, 3)] + acc[P6(4, 4)] + acc[P6(5, 5)];
@@ -711,13 +816,13 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
         ni2 *= il;
       }
     }
-    if (act && gl == 0) {
+    if (emit && gl == 0) {
       A.kappa[c] = kap;
       A.nx[c] = ni0;
       A.ny[c] = ni1;
       A.nz[c] = ni2;
       if (A.coeff)
-        for (int q = 0; q < 6; ++q) A.coeff[(int64_t)q * A.cell_cap + c] = st ? NAN : co[q];
+        for (int qa = 0; qa < 6; ++qa) A.coeff[(int64_t)qa * A.cell_cap + c] = st ? NAN : co[qa];
       if (A.status) A.status[c] = (int32_t)st;
       if (A.diag) {
         A.diag[c] = vs;
@@ -730,40 +835,47 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
   }
 }
 
+inline int32_t round_up(int64_t n, int64_t m) { return (int32_t)((n + m - 1) / m * m); }
+
 }  // namespace
 
 hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, double* kappa, double* nx,
                        double* ny, double* nz, double* coeff, int32_t* cell_status, int32_t* diag, hipStream_t s) {
   const Grid& g = ws->grid;
+  int4* tri4 = reinterpret_cast<int4*>(ws->tri4);
+  double2* vtx4 = reinterpret_cast<double2*>(ws->vtx4);
   const int64_t nclear = std::max<int64_t>((int64_t)m.nv + 1, (int64_t)ws->cell_cap + 1);
   hipLaunchKernelGGL(k_clear_ppic, dim3(grid_blocks(nclear, kT, kStrideBlocks)), dim3(kT), 0, s, ws->vt_off,
                      (int64_t)m.nv + 1, ws->vt_cursor, (int64_t)m.nv, ws->vb_off, (int64_t)ws->cell_cap + 1,
                      ws->vb_cursor, (int64_t)ws->cell_cap, ws->counters);
-  hipLaunchKernelGGL(k_vt_count, dim3(grid_blocks(m.nt, kT)), dim3(kT), 0, s, m, ws->vt_off);
+  hipLaunchKernelGGL(k_vt_count, dim3(grid_blocks(m.nt, kT)), dim3(kT), 0, s, m, ws->vt_off, tri4);
   hipError_t e = scan_exclusive(ws->vt_off, m.nv, ws->scan_tmp, nullptr, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_vt_scatter, dim3(grid_blocks(m.nt, kT)), dim3(kT), 0, s, m, ws->vt_off, ws->vt_cursor,
                      ws->vt_ids);
   hipLaunchKernelGGL(k_vt_sort, dim3(grid_blocks(m.nv, kT)), dim3(kT), 0, s, m.nv, ws->vt_off, ws->vt_ids);
-  hipLaunchKernelGGL(k_vb_count, dim3(grid_blocks(m.nv, kT)), dim3(kT), 0, s, g, m, ws->bitmap, ws->word_off,
+  hipLaunchKernelGGL(k_vb_count, dim3(grid_blocks(m.nv, kT)), dim3(kT), 0, s, g, m, ws->bitmap, ws->word_off, vtx4,
                      ws->vcell, ws->vb_off, ws->stray, ws->cell_cap, ws->counters);
   e = scan_exclusive(ws->vb_off, ws->cell_cap, ws->scan_tmp, nullptr, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_vb_scatter, dim3(grid_blocks(m.nv, kT)), dim3(kT), 0, s, m.nv, ws->vcell, ws->vb_off,
                      ws->vb_cursor, ws->vb_ids);
-  hipLaunchKernelGGL(k_vstar, dim3(grid_blocks((int64_t)ws->cell_cap * 32, kT)), dim3(kT), 0, s, g, m,
+  hipLaunchKernelGGL(k_vstar, dim3(grid_blocks((int64_t)ws->cell_cap * 32, kT)), dim3(kT), 0, s, g, vtx4,
                      ws->cell_ids, ws->bitmap, ws->word_off, ws->vb_off, ws->vb_ids, ws->stray, ws->best_d2,
                      ws->best_v, ws->cell_cap, ws->counters);
   PPICArgs A;
   A.g = g;
-  A.m = m;
+  A.nv = m.nv;
   A.prm = p;
+  A.tri4 = tri4;
+  A.vtx4 = vtx4;
   A.cell_ids = ws->cell_ids;
   A.vt_off = ws->vt_off;
   A.vt_ids = ws->vt_ids;
   A.best_d2 = ws->best_d2;
   A.best_v = ws->best_v;
   A.counters = ws->counters;
+  A.ovf_cells = ws->ovf_cells;
   A.cell_cap = ws->cell_cap;
   A.kappa = kappa;
   A.nx = nx;
@@ -772,10 +884,11 @@ hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, 
   A.coeff = coeff;
   A.status = cell_status;
   A.diag = diag;
-  const int64_t groups = ((int64_t)ws->cell_cap + NG - 1) / NG;
-  const int32_t blocks = (int32_t)std::min<int64_t>(std::max<int64_t>(groups, 1), 65536);
+  const int64_t groups = ((int64_t)ws->cell_cap + Fast::NG - 1) / Fast::NG;
+  const int32_t blocks = round_up(std::min<int64_t>(std::max<int64_t>(groups, 1), 65536), kXCD);
   time_start(ws, FTC_KERNEL_PPIC, s);
-  hipLaunchKernelGGL(k_ppic, dim3(blocks), dim3(64), 0, s, A);
+  hipLaunchKernelGGL((k_ppic<Fast, false>), dim3(blocks), dim3(64), 0, s, A);
+  hipLaunchKernelGGL((k_ppic<Wide, true>), dim3(kWideBlocks), dim3(64), 0, s, A);
   time_stop(ws, FTC_KERNEL_PPIC, s);
   return hipGetLastError();
 }
