@@ -85,8 +85,8 @@ typedef struct ftc_cells ftc_cells;
    of up to nv_capacity vertices and nt_capacity triangles, holding up to
    pair_capacity (cell, triangle) pieces and cell_capacity interfacial
    cells (candidates that must be clipped, up to twice pair_capacity, are
-   queued internally).  Device memory is about 104 B x pairs + 96 B x cells +
-   12 B x triangles + 8 B x vertices + 8 B x (nx*ny) + nx*ny*nz/4 B.
+   queued internally).  Device memory is about 104 B x pairs + 52 B x cells +
+   28 B x triangles + 52 B x vertices + nx*ny*nz/4 B.
    Returns FTC_EINVAL, FTC_ENOMEM or FTC_OK; *out is NULL on failure. */
 ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_capacity,
                             int32_t nt_capacity, int64_t pair_capacity, int32_t cell_capacity);
@@ -189,12 +189,11 @@ ftc_status ftc_last_device_error(ftc_cells* cells, int32_t* code, void* stream);
 typedef enum {
   FTC_KERNEL_TRI_PIECES = 0,  /* cell lists: per-triangle clip and integrals  */
   FTC_KERNEL_PIECE_RANK = 1,  /* cell lists: ordering of each cell's pieces   */
-  FTC_KERNEL_COL_WALK = 2,    /* volume fraction: column sums                 */
-  FTC_KERNEL_DENSE_ALPHA = 3, /* volume fraction: dense field write           */
-  FTC_KERNEL_PPIC = 4,        /* PPIC: closest vertex, ring, fit, curvature   */
-  FTC_KERNEL_CSF = 5,         /* CSF force                                    */
-  FTC_KERNEL_INTERP = 6,      /* vertex velocity interpolation                */
-  FTC_KERNEL_COUNT = 7
+  FTC_KERNEL_COLUMNS = 2,     /* volume fraction: column pass and dense field */
+  FTC_KERNEL_PPIC = 3,        /* PPIC: ring, fit, curvature (both shapes)     */
+  FTC_KERNEL_CSF = 4,         /* CSF force                                    */
+  FTC_KERNEL_INTERP = 5,      /* vertex velocity interpolation                */
+  FTC_KERNEL_COUNT = 6
 } ftc_kernel;
 
 /* Enable (1) or disable (0) the timing events of a workspace. */

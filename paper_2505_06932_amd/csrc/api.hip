@@ -131,12 +131,6 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(piece_vol, P);
   FTC_ALLOC(cell_flux, Cc);
   FTC_ALLOC(cell_vol, Cc);
-  FTC_ALLOC(col_off, ncol + 1);
-  FTC_ALLOC(col_cursor, ncol);
-  FTC_ALLOC(col_cells, Cc);
-  FTC_ALLOC(col_k, Cc);
-  FTC_ALLOC(col_alpha, Cc);
-  FTC_ALLOC(col_below, Cc);
   FTC_ALLOC(vt_off, Vc + 1);
   FTC_ALLOC(vt_cursor, Vc);
   FTC_ALLOC(vt_ids, 3 * Tc);
@@ -163,6 +157,10 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
     if (e == hipSuccess) ++nev;
   }
   if (e == hipSuccess) e = hipMemset(w.counters, 0, sizeof(int32_t) * ftc::C_COUNT);
+  // per-vertex and per-cell counts of the PPIC pre-passes start at zero and
+  // are back at zero after every call
+  if (e == hipSuccess) e = hipMemset(w.vt_cursor, 0, sizeof(int32_t) * Vc);
+  if (e == hipSuccess) e = hipMemset(w.vb_cursor, 0, sizeof(int32_t) * Cc);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     for (int k = 0; k < nev; ++k) {

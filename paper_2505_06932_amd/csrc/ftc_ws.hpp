@@ -54,23 +54,16 @@ struct ftc_cells {
   // volume fraction
   double* cell_flux;      // [cell_cap] sum of the cell's piece fluxes
   double* cell_vol;       // [cell_cap] sum of the cell's piece volume integrals
-  int32_t* col_off;       // [ncol+1] interfacial cells per (i, j) column -> offsets
-  int32_t* col_cursor;    // [ncol]
-  int32_t* col_cells;     // [cell_cap] compact cells grouped by column, ascending k
-  int32_t* col_k;         // [cell_cap] k of each column slot
-  double* col_alpha;      // [cell_cap] alpha of each column slot
-  double* col_below;      // [cell_cap] alpha of the non-interfacial cells below the slot
-
   // PPIC
-  int32_t* vt_off;        // [nv_cap+1] triangles per vertex -> offsets
-  int32_t* vt_cursor;     // [nv_cap]
+  int32_t* vt_off;        // [nv_cap+1] offsets of each vertex's incident triangles
+  int32_t* vt_cursor;     // [nv_cap] triangles per vertex while counting; zero between calls
   int32_t* vt_ids;        // [3*nt_cap] incident triangles, ascending per vertex
   int32_t* tri4;          // [4*nt_cap] corners of each triangle packed (t0, t1, t2, 0)
   double* vtx4;           // [4*nv_cap] coordinates of each vertex packed (x, y, z, 0)
   int32_t* ovf_cells;     // [cell_cap] cells queued for the wide PPIC kernel
   int32_t* vcell;         // [nv_cap] interfacial cell holding each vertex (-1: none, -2: outside)
-  int32_t* vb_off;        // [cell_cap+1] vertices per interfacial cell -> offsets
-  int32_t* vb_cursor;     // [cell_cap]
+  int32_t* vb_off;        // [cell_cap+1] offsets of each interfacial cell's vertices
+  int32_t* vb_cursor;     // [cell_cap] vertices per cell while counting; zero between calls
   int32_t* vb_ids;        // [nv_cap] vertices grouped by interfacial cell
   int32_t* stray;         // [nv_cap] vertices in cells without pieces
   double* best_d2;        // [cell_cap] smallest squared distance of a vertex in the 27 cells around
@@ -94,6 +87,11 @@ hipError_t scan_exclusive(int32_t* data, int64_t n, int32_t* tmp, int32_t* total
 // Same, with inputs popcount(words[i]) (output to out[0..n], total to out[n]).
 hipError_t scan_popcount(const uint32_t* words, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out,
                          hipStream_t s);
+
+// Two independent exclusive scans (a[0..na) -> a_out[0..na], c[0..nc) ->
+// c_out[0..nc], totals last) in one pair of launches; in place is allowed.
+hipError_t scan_exclusive2(const int32_t* a, int32_t* a_out, int64_t na, const int32_t* c, int32_t* c_out, int64_t nc,
+                           int32_t* tmp, hipStream_t s);
 
 hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 

@@ -1,6 +1,6 @@
 // ppic.hip -- PPIC curvature by the volume fit (paper section 3.2).
 //
-// Pre-passes (integer work, once per call):
+// Pre-passes (integer work, once per call, four launches plus a scan):
 //   * vertex -> incident triangles (CSR, ascending triangle id), and the
 //     triangles' corners packed as (t0, t1, t2, 0) so one 16-byte load
 //     fetches a triangle;
@@ -79,58 +79,9 @@ using Fast = Cfg<8, 64, 32, 64, 8>;
 using Wide = Cfg<64, 512, 256, 512, 4>;
 
 // ----------------------------------------------------------------- pre-passes
-__global__ void k_clear_ppic(int32_t* vt_off, int64_t n1, int32_t* vt_cursor, int64_t n2, int32_t* vb_off,
-                             int64_t n3, int32_t* vb_cursor, int64_t n4, int32_t* counters) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = g0; i < n1; i += stride) vt_off[i] = 0;
-  for (int64_t i = g0; i < n2; i += stride) vt_cursor[i] = 0;
-  for (int64_t i = g0; i < n3; i += stride) vb_off[i] = 0;
-  for (int64_t i = g0; i < n4; i += stride) vb_cursor[i] = 0;
-  if (g0 == 0) {
-    counters[C_NSTRAY] = 0;
-    counters[C_NOVF] = 0;
-  }
-}
-
-// A triangle is listed once under each of its distinct corners.  Also packs
-// the corners; a triangle with an invalid corner is packed as (0, 0, 0) and
-// listed nowhere.
-__global__ void k_vt_count(Mesh m, int32_t* vt_cnt, int4* tri4) {
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m.nt) return;
-  const int32_t a = m.t0[t], b = m.t1[t], c = m.t2[t];
-  const bool ok = a >= 0 && b >= 0 && c >= 0 && a < m.nv && b < m.nv && c < m.nv;
-  tri4[t] = ok ? make_int4(a, b, c, 0) : make_int4(0, 0, 0, 0);
-  if (!ok) return;
-  atomicAdd(&vt_cnt[a], 1);
-  if (b != a) atomicAdd(&vt_cnt[b], 1);
-  if (c != a && c != b) atomicAdd(&vt_cnt[c], 1);
-}
-
-__global__ void k_vt_scatter(Mesh m, const int32_t* vt_off, int32_t* vt_cursor, int32_t* vt_ids) {
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= m.nt || !tri_ok(m, t)) return;
-  const int32_t a = m.t0[t], b = m.t1[t], c = m.t2[t];
-  vt_ids[vt_off[a] + atomicAdd(&vt_cursor[a], 1)] = t;
-  if (b != a) vt_ids[vt_off[b] + atomicAdd(&vt_cursor[b], 1)] = t;
-  if (c != a && c != b) vt_ids[vt_off[c] + atomicAdd(&vt_cursor[c], 1)] = t;
-}
-
-__global__ void k_vt_sort(int32_t nv, const int32_t* vt_off, int32_t* vt_ids) {
-  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
-  const int32_t s = vt_off[v], e = vt_off[v + 1];
-  for (int32_t a = s + 1; a < e; ++a) {
-    const int32_t x = vt_ids[a];
-    int32_t b = a - 1;
-    while (b >= s && vt_ids[b] > x) {
-      vt_ids[b + 1] = vt_ids[b];
-      --b;
-    }
-    vt_ids[b + 1] = x;
-  }
-}
+// The per-vertex triangle counts (vt_cnt) and per-cell vertex counts
+// (vb_cnt) are zero between calls: the scatter takes every count back down
+// to zero as it places the entries.
 
 __device__ inline int32_t cell_rank(const uint32_t* bitmap, const int32_t* word_off, int64_t lin) {
   const uint32_t w = bitmap[lin >> 5];
@@ -139,36 +90,76 @@ __device__ inline int32_t cell_rank(const uint32_t* bitmap, const int32_t* word_
   return word_off[lin >> 5] + __popc(below);
 }
 
-// Packs the coordinates; finds the interfacial cell of every vertex (-1: a
-// cell without pieces, the vertex becomes a stray; -2: outside the margin,
-// latched as a domain error by the cell-list build) and counts the vertices
-// per interfacial cell.
-__global__ void k_vb_count(Grid g, Mesh m, const uint32_t* bitmap, const int32_t* word_off, double2* vtx4,
-                           int32_t* vcell, int32_t* vb_cnt, int32_t* stray, int32_t cell_cap, int32_t* counters) {
-  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= m.nv) return;
-  const double x = m.x[v], y = m.y[v], z = m.z[v];
-  vtx4[2 * (int64_t)v] = make_double2(x, y);
-  vtx4[2 * (int64_t)v + 1] = make_double2(z, 0.0);
-  int32_t ci = -2;
-  if (in_margin(g, x, y, z)) {
-    const int64_t i = cell_index(x, g.x0, g.h), j = cell_index(y, g.y0, g.h), k = cell_index(z, g.z0, g.h);
-    ci = cell_rank(bitmap, word_off, i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
-    if (ci >= cell_cap) ci = -1;
-    if (ci >= 0)
-      atomicAdd(&vb_cnt[ci], 1);
-    else
-      stray[atomicAdd(&counters[C_NSTRAY], 1)] = v;
+struct PreArgs {
+  Grid g;
+  Mesh m;
+  const uint32_t* bitmap;
+  const int32_t* word_off;
+  int4* tri4;
+  double2* vtx4;
+  int32_t* vt_cnt;
+  int32_t* vt_off;
+  int32_t* vt_ids;
+  int32_t* vcell;
+  int32_t* vb_cnt;
+  int32_t* vb_off;
+  int32_t* vb_ids;
+  int32_t* stray;
+  int32_t cell_cap;
+  int32_t* counters;
+};
+
+// Thread t: triangle t (packed corners; counted once under each distinct
+// corner; a triangle with an invalid corner is packed as (0, 0, 0) and
+// counted nowhere) and vertex t (packed coordinates; the interfacial cell
+// holding it: -1 for a cell without pieces, which makes it a stray, -2
+// outside the margin, latched as a domain error by the cell-list build).
+__global__ void k_pre_count(PreArgs P) {
+  const Mesh& m = P.m;
+  const Grid& g = P.g;
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) P.counters[C_NOVF] = 0;
+  if (t < m.nt) {
+    const int32_t a = m.t0[t], b = m.t1[t], c = m.t2[t];
+    const bool ok = a >= 0 && b >= 0 && c >= 0 && a < m.nv && b < m.nv && c < m.nv;
+    P.tri4[t] = ok ? make_int4(a, b, c, 0) : make_int4(0, 0, 0, 0);
+    if (ok) {
+      atomicAdd(&P.vt_cnt[a], 1);
+      if (b != a) atomicAdd(&P.vt_cnt[b], 1);
+      if (c != a && c != b) atomicAdd(&P.vt_cnt[c], 1);
+    }
   }
-  vcell[v] = ci;
+  if (t < m.nv) {
+    const double x = m.x[t], y = m.y[t], z = m.z[t];
+    P.vtx4[2 * (int64_t)t] = make_double2(x, y);
+    P.vtx4[2 * (int64_t)t + 1] = make_double2(z, 0.0);
+    int32_t ci = -2;
+    if (in_margin(g, x, y, z)) {
+      const int64_t i = cell_index(x, g.x0, g.h), j = cell_index(y, g.y0, g.h), k = cell_index(z, g.z0, g.h);
+      ci = cell_rank(P.bitmap, P.word_off, i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
+      if (ci >= P.cell_cap) ci = -1;
+      if (ci >= 0)
+        atomicAdd(&P.vb_cnt[ci], 1);
+      else
+        P.stray[atomicAdd(&P.counters[C_NSTRAY], 1)] = t;
+    }
+    P.vcell[t] = ci;
+  }
 }
 
-__global__ void k_vb_scatter(int32_t nv, const int32_t* vcell, const int32_t* vb_off, int32_t* vb_cursor,
-                             int32_t* vb_ids) {
-  const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
-  const int32_t ci = vcell[v];
-  if (ci >= 0) vb_ids[vb_off[ci] + atomicAdd(&vb_cursor[ci], 1)] = v;
+__global__ void k_pre_scatter(PreArgs P) {
+  const Mesh& m = P.m;
+  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < m.nt && tri_ok(m, t)) {
+    const int32_t a = m.t0[t], b = m.t1[t], c = m.t2[t];
+    P.vt_ids[P.vt_off[a] + atomicSub(&P.vt_cnt[a], 1) - 1] = t;
+    if (b != a) P.vt_ids[P.vt_off[b] + atomicSub(&P.vt_cnt[b], 1) - 1] = t;
+    if (c != a && c != b) P.vt_ids[P.vt_off[c] + atomicSub(&P.vt_cnt[c], 1) - 1] = t;
+  }
+  if (t < m.nv) {
+    const int32_t ci = P.vcell[t];
+    if (ci >= 0) P.vb_ids[P.vb_off[ci] + atomicSub(&P.vb_cnt[ci], 1) - 1] = t;
+  }
 }
 
 __device__ inline bool lex_less(double d, int32_t v, double bd, int32_t bv) {
@@ -196,15 +187,34 @@ __device__ inline void consider(const double2* vtx4, int32_t v, const double xc[
 
 __device__ inline double cell_centre(double org, int32_t i, double h) { return org + ((double)i + 0.5) * h; }
 
-// 32 lanes per interfacial cell: lane l < 27 scans the vertex bin of cell l
-// of the 3x3x3 block around it, every lane a share of the strays.
-__global__ __launch_bounds__(kT) void k_vstar(Grid g, const double2* vtx4, const int32_t* cell_ids,
-                                              const uint32_t* bitmap, const int32_t* word_off, const int32_t* vb_off,
-                                              const int32_t* vb_ids, const int32_t* stray, double* best_d2,
-                                              int32_t* best_v, int32_t cell_cap, const int32_t* counters) {
+// Blocks [0, sort_blocks): one vertex per thread, its incident-triangle
+// list sorted ascending.  The other blocks: 32 lanes per interfacial cell,
+// lane l < 27 scans the vertex bin of cell l of the 3x3x3 block around it,
+// every lane a share of the strays; lowest index on ties.
+__global__ __launch_bounds__(kT) void k_sort_vstar(Grid g, int32_t nv, const int32_t* vt_off, int32_t* vt_ids,
+                                                   int32_t sort_blocks, const double2* vtx4, const int32_t* cell_ids,
+                                                   const uint32_t* bitmap, const int32_t* word_off,
+                                                   const int32_t* vb_off, const int32_t* vb_ids, const int32_t* stray,
+                                                   double* best_d2, int32_t* best_v, int32_t cell_cap,
+                                                   const int32_t* counters) {
+  if ((int32_t)blockIdx.x < sort_blocks) {
+    const int32_t v = blockIdx.x * kT + threadIdx.x;
+    if (v >= nv) return;
+    const int32_t s = vt_off[v], e = vt_off[v + 1];
+    for (int32_t a = s + 1; a < e; ++a) {
+      const int32_t x = vt_ids[a];
+      int32_t b = a - 1;
+      while (b >= s && vt_ids[b] > x) {
+        vt_ids[b + 1] = vt_ids[b];
+        --b;
+      }
+      vt_ids[b + 1] = x;
+    }
+    return;
+  }
   const int32_t nif = min(counters[C_NIF], cell_cap);
   const int32_t nstray = counters[C_NSTRAY];
-  const int64_t gid = (int64_t)blockIdx.x * kT + threadIdx.x;
+  const int64_t gid = (int64_t)(blockIdx.x - sort_blocks) * kT + threadIdx.x;
   const int64_t c = gid >> 5;
   const int l = (int)(gid & 31);
   double bd = DBL_MAX;
@@ -388,6 +398,8 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
   const double reach = 1.5 * h;
   const double reach2 = reach * reach * (1.0 - 1e-12);
   const uint64_t below_me = (1ull << gl) - 1ull;
+  // the closest-vertex pass has read the stray count: reset it for the next call
+  if (!kQueue && blockIdx.x == 0 && threadIdx.x == 0) A.counters[C_NSTRAY] = 0;
 
   // each XCD takes a contiguous range of cell groups
   const int32_t ngroups = (nitems + NG - 1) / NG;
@@ -844,25 +856,19 @@ hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, 
   const Grid& g = ws->grid;
   int4* tri4 = reinterpret_cast<int4*>(ws->tri4);
   double2* vtx4 = reinterpret_cast<double2*>(ws->vtx4);
-  const int64_t nclear = std::max<int64_t>((int64_t)m.nv + 1, (int64_t)ws->cell_cap + 1);
-  hipLaunchKernelGGL(k_clear_ppic, dim3(grid_blocks(nclear, kT, kStrideBlocks)), dim3(kT), 0, s, ws->vt_off,
-                     (int64_t)m.nv + 1, ws->vt_cursor, (int64_t)m.nv, ws->vb_off, (int64_t)ws->cell_cap + 1,
-                     ws->vb_cursor, (int64_t)ws->cell_cap, ws->counters);
-  hipLaunchKernelGGL(k_vt_count, dim3(grid_blocks(m.nt, kT)), dim3(kT), 0, s, m, ws->vt_off, tri4);
-  hipError_t e = scan_exclusive(ws->vt_off, m.nv, ws->scan_tmp, nullptr, s);
+  PreArgs P{g,         m,           ws->bitmap, ws->word_off, tri4,      vtx4,         ws->vt_cursor, ws->vt_off,
+            ws->vt_ids, ws->vcell, ws->vb_cursor, ws->vb_off, ws->vb_ids, ws->stray, ws->cell_cap, ws->counters};
+  const int32_t nthr = std::max(m.nt, m.nv);
+  hipLaunchKernelGGL(k_pre_count, dim3(grid_blocks(nthr, kT)), dim3(kT), 0, s, P);
+  hipError_t e = scan_exclusive2(ws->vt_cursor, ws->vt_off, m.nv, ws->vb_cursor, ws->vb_off, ws->cell_cap,
+                                 ws->scan_tmp, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_vt_scatter, dim3(grid_blocks(m.nt, kT)), dim3(kT), 0, s, m, ws->vt_off, ws->vt_cursor,
-                     ws->vt_ids);
-  hipLaunchKernelGGL(k_vt_sort, dim3(grid_blocks(m.nv, kT)), dim3(kT), 0, s, m.nv, ws->vt_off, ws->vt_ids);
-  hipLaunchKernelGGL(k_vb_count, dim3(grid_blocks(m.nv, kT)), dim3(kT), 0, s, g, m, ws->bitmap, ws->word_off, vtx4,
-                     ws->vcell, ws->vb_off, ws->stray, ws->cell_cap, ws->counters);
-  e = scan_exclusive(ws->vb_off, ws->cell_cap, ws->scan_tmp, nullptr, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_vb_scatter, dim3(grid_blocks(m.nv, kT)), dim3(kT), 0, s, m.nv, ws->vcell, ws->vb_off,
-                     ws->vb_cursor, ws->vb_ids);
-  hipLaunchKernelGGL(k_vstar, dim3(grid_blocks((int64_t)ws->cell_cap * 32, kT)), dim3(kT), 0, s, g, vtx4,
-                     ws->cell_ids, ws->bitmap, ws->word_off, ws->vb_off, ws->vb_ids, ws->stray, ws->best_d2,
-                     ws->best_v, ws->cell_cap, ws->counters);
+  hipLaunchKernelGGL(k_pre_scatter, dim3(grid_blocks(nthr, kT)), dim3(kT), 0, s, P);
+  const int32_t sort_blocks = grid_blocks(m.nv, kT);
+  const int32_t vstar_blocks = grid_blocks((int64_t)ws->cell_cap * 32, kT);
+  hipLaunchKernelGGL(k_sort_vstar, dim3(sort_blocks + vstar_blocks), dim3(kT), 0, s, g, m.nv, ws->vt_off, ws->vt_ids,
+                     sort_blocks, vtx4, ws->cell_ids, ws->bitmap, ws->word_off, ws->vb_off, ws->vb_ids, ws->stray,
+                     ws->best_d2, ws->best_v, ws->cell_cap, ws->counters);
   PPICArgs A;
   A.g = g;
   A.nv = m.nv;

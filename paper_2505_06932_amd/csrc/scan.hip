@@ -1,6 +1,9 @@
-// scan.hip -- device-wide exclusive prefix sums (three passes: block totals,
-// scan of the totals in one block, block-local scan plus offset) and small
-// fill kernels.  Used for every count -> offset conversion of the library.
+// scan.hip -- device-wide exclusive prefix sums in two passes (block totals;
+// block-local scan plus the sum of the earlier blocks' totals, which each
+// block reads itself) and small fill kernels.  Used for every count ->
+// offset conversion of the library.
+#include <algorithm>
+
 #include "ftc_ws.hpp"
 
 namespace ftc {
@@ -52,45 +55,37 @@ __device__ inline int32_t block_excl_scan(int32_t v, int32_t* total) {
   return r;
 }
 
+// First pass: the total of each block of kScanBlock inputs.
 template <class L>
-__global__ __launch_bounds__(kThreads) void k_block_totals(L load, int64_t n, int32_t* tmp) {
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kItems;
+__device__ inline void totals_one(L load, int64_t n, int64_t b, int32_t* slot) {
+  const int64_t base = b * kScanBlock + (int64_t)threadIdx.x * kItems;
   int32_t s = 0;
 #pragma unroll
   for (int q = 0; q < kItems; ++q)
     if (base + q < n) s += load(base + q);
   int32_t total;
   block_excl_scan(s, &total);
-  if (threadIdx.x == 0) tmp[blockIdx.x] = total;
+  if (threadIdx.x == 0) *slot = total;
 }
 
-// One block of 1024 threads scans up to kScanMaxBlocks block totals in place.
-__global__ __launch_bounds__(1024) void k_scan_totals(int32_t* tmp, int64_t nb, int32_t* grand, int32_t* grand2) {
-  constexpr int per = (int)(kScanMaxBlocks / 1024);
-  const int64_t base = (int64_t)threadIdx.x * per;
-  int32_t v[per];
+// Sum of tmp[0, nb) over the block (every thread gets it).
+__device__ inline int32_t block_sum_prefix(const int32_t* tmp, int64_t nb) {
   int32_t s = 0;
-#pragma unroll
-  for (int q = 0; q < per; ++q) {
-    v[q] = (base + q < nb) ? tmp[base + q] : 0;
-    s += v[q];
-  }
+  for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) s += tmp[q];
   int32_t total;
-  int32_t run = block_excl_scan(s, &total);
-#pragma unroll
-  for (int q = 0; q < per; ++q) {
-    if (base + q < nb) tmp[base + q] = run;
-    run += v[q];
-  }
-  if (threadIdx.x == 0) {
-    if (grand) *grand = total;
-    if (grand2) *grand2 = total;
-  }
+  block_excl_scan(s, &total);
+  return total;
 }
 
+// Second pass for block b of nblocks: the local scan plus the totals of the
+// blocks before it; the last block also writes the grand total to out[n]
+// and *total_out.  In place is allowed (out == input): every thread reads
+// its inputs before writing them.
 template <class L>
-__global__ __launch_bounds__(kThreads) void k_block_apply(L load, int64_t n, const int32_t* tmp, int32_t* out) {
-  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kItems;
+__device__ inline void apply_one(L load, int64_t n, const int32_t* tmp, int32_t* out, int32_t* total_out, int64_t b,
+                                 int64_t nblocks) {
+  const int32_t prefix = block_sum_prefix(tmp, b);
+  const int64_t base = b * kScanBlock + (int64_t)threadIdx.x * kItems;
   int32_t v[kItems];
   int32_t s = 0;
 #pragma unroll
@@ -99,23 +94,56 @@ __global__ __launch_bounds__(kThreads) void k_block_apply(L load, int64_t n, con
     s += v[q];
   }
   int32_t total;
-  int32_t run = block_excl_scan(s, &total) + tmp[blockIdx.x];
+  int32_t run = block_excl_scan(s, &total) + prefix;
 #pragma unroll
   for (int q = 0; q < kItems; ++q) {
     if (base + q < n) out[base + q] = run;
     run += v[q];
   }
+  if (b == nblocks - 1 && threadIdx.x == 0) {
+    out[n] = prefix + total;
+    if (total_out) *total_out = prefix + total;
+  }
+}
+
+template <class L>
+__global__ __launch_bounds__(kThreads) void k_block_totals(L load, int64_t n, int32_t* tmp) {
+  totals_one(load, n, blockIdx.x, tmp + blockIdx.x);
+}
+
+template <class L>
+__global__ __launch_bounds__(kThreads) void k_block_apply(L load, int64_t n, const int32_t* tmp, int32_t* out,
+                                                          int32_t* total_out, int64_t nb) {
+  apply_one(load, n, tmp, out, total_out, blockIdx.x, nb);
+}
+
+// Two independent arrays in one pair of launches: blocks [0, nb1) work on
+// the first, the others on the second (its block totals follow the first's
+// in tmp).
+__global__ __launch_bounds__(kThreads) void k_block_totals2(const int32_t* a, int64_t na, int64_t nb1,
+                                                            const int32_t* c, int64_t nc, int32_t* tmp) {
+  if (blockIdx.x < nb1)
+    totals_one(LoadI32{a}, na, blockIdx.x, tmp + blockIdx.x);
+  else
+    totals_one(LoadI32{c}, nc, blockIdx.x - nb1, tmp + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_block_apply2(const int32_t* a, int32_t* a_out, int64_t na,
+                                                           int64_t nb1, const int32_t* c, int32_t* c_out, int64_t nc,
+                                                           int64_t nb2, const int32_t* tmp) {
+  if (blockIdx.x < nb1)
+    apply_one(LoadI32{a}, na, tmp, a_out, nullptr, blockIdx.x, nb1);
+  else
+    apply_one(LoadI32{c}, nc, tmp + nb1, c_out, nullptr, blockIdx.x - nb1, nb2);
 }
 
 template <class L>
 hipError_t scan_impl(L load, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out, hipStream_t s) {
   if (n < 0 || n > kScanMax) return hipErrorInvalidValue;
-  int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-  if (nb < 1) nb = 1;
+  const int64_t nb = std::max<int64_t>((n + kScanBlock - 1) / kScanBlock, 1);
   hipLaunchKernelGGL(k_block_totals<L>, dim3((unsigned)nb), dim3(kThreads), 0, s, load, n, tmp);
-  hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, tmp, nb, out + n, total_out);
-  hipLaunchKernelGGL(k_block_apply<L>, dim3((unsigned)nb), dim3(kThreads), 0, s, load, n, (const int32_t*)tmp,
-                     out);
+  hipLaunchKernelGGL(k_block_apply<L>, dim3((unsigned)nb), dim3(kThreads), 0, s, load, n, (const int32_t*)tmp, out,
+                     total_out, nb);
   return hipGetLastError();
 }
 
@@ -133,6 +161,21 @@ hipError_t scan_exclusive(int32_t* data, int64_t n, int32_t* tmp, int32_t* total
 hipError_t scan_popcount(const uint32_t* words, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out,
                          hipStream_t s) {
   return scan_impl(LoadPop{words}, out, n, tmp, total_out, s);
+}
+
+hipError_t scan_exclusive2(const int32_t* a, int32_t* a_out, int64_t na, const int32_t* c, int32_t* c_out, int64_t nc,
+                           int32_t* tmp, hipStream_t s) {
+  if (na < 0 || na > kScanMax || nc < 0 || nc > kScanMax) return hipErrorInvalidValue;
+  const int64_t nb1 = std::max<int64_t>((na + kScanBlock - 1) / kScanBlock, 1);
+  const int64_t nb2 = std::max<int64_t>((nc + kScanBlock - 1) / kScanBlock, 1);
+  if (nb1 + nb2 > kScanMaxBlocks) {
+    hipError_t e = scan_impl(LoadI32{a}, a_out, na, tmp, nullptr, s);
+    return e != hipSuccess ? e : scan_impl(LoadI32{c}, c_out, nc, tmp, nullptr, s);
+  }
+  hipLaunchKernelGGL(k_block_totals2, dim3((unsigned)(nb1 + nb2)), dim3(kThreads), 0, s, a, na, nb1, c, nc, tmp);
+  hipLaunchKernelGGL(k_block_apply2, dim3((unsigned)(nb1 + nb2)), dim3(kThreads), 0, s, a, a_out, na, nb1, c, c_out,
+                     nc, nb2, (const int32_t*)tmp);
+  return hipGetLastError();
 }
 
 hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {

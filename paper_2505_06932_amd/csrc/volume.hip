@@ -9,14 +9,11 @@
 // all pieces strictly above.  Kernels:
 //   sums   : one thread per interfacial cell, its pieces' integrals (computed
 //            while the cell lists were built) summed in CSR order;
-//   columns: interfacial cells grouped by (i, j) column (count, scan,
-//            scatter);
-//   walk   : one thread per column, top to bottom, summing each cell's pieces
-//            in CSR (ascending triangle) order, alpha = (V + h W) / h^3, and
-//            the 0/1 value of the cells between consecutive interfacial
-//            cells; a column whose W is not 0 or h^2 there latches ERR_MESH;
-//   dense  : one thread per grid cell, x fastest (coalesced writes), looks
-//            up its column's short list.
+//   columns: every (i, j) column walked top down over the interfacial-cell
+//            bitmap, split into z chunks whose flux totals are exchanged in
+//            LDS: alpha = (V + h W) / h^3 in interfacial cells, 0 or 1 in
+//            the others (dense field written on the way), ERR_MESH where W
+//            is not 0 or h^2 outside the front.
 #include "ftc_ws.hpp"
 
 namespace ftc {
@@ -41,132 +38,105 @@ __global__ void k_cell_sums(const int32_t* offsets, const double* piece_flux, co
   }
 }
 
-__global__ void k_clear_cols(int32_t* col_off, int64_t n1, int32_t* col_cursor, int64_t n2) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n1; i += stride) {
-    col_off[i] = 0;
-    if (i < n2) col_cursor[i] = 0;
+// Column pass.  A workgroup takes 64 consecutive columns (x) of one y row
+// and splits the z range into 8 chunks, one wavefront each; lanes are
+// columns, so bitmap reads and dense stores are coalesced along x.
+//   1. each wavefront sums the fluxes of the interfacial cells in its chunk,
+//      top down;
+//   2. the chunk totals above give each chunk the wetted area W at its top;
+//   3. each wavefront walks its chunk top down again: an interfacial cell
+//      gets (V + h W) / h^3 and adds its flux to W, any other cell gets
+//      round(W / h^2), which must be 0 or 1 within 1e-9 (else the front is
+//      open: ERR_MESH), as must W below the lowest chunk.
+constexpr int kColLanes = 64;
+constexpr int kChunks = 8;
+constexpr int kSub = 8;  // cells of a chunk read at once
+
+struct ColArgs {
+  Grid g;
+  const uint32_t* bitmap;
+  const int32_t* word_off;
+  const double* cell_flux;
+  const double* cell_vol;
+  double* alpha_if;
+  double* alpha;
+  int32_t* counters;
+};
+
+// Reads kSub cells k1, k1-1, ... (those >= klo) of column (i, j): which are
+// interfacial, their compact ids, fluxes and (if `vol`) volume integrals.
+template <bool kVol>
+__device__ inline void read_sub(const ColArgs& A, bool col_ok, int32_t i, int32_t j, int32_t k1, int32_t klo,
+                                int32_t ci[kSub], double fl[kSub], double vo[kSub]) {
+  const Grid& g = A.g;
+  uint32_t wv[kSub], lin[kSub];  // cell ids fit in 31 bits
+#pragma unroll
+  for (int q = 0; q < kSub; ++q) {
+    const int32_t k = k1 - q;
+    lin[q] = (uint32_t)(i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
+    wv[q] = (col_ok && k >= klo) ? A.bitmap[lin[q] >> 5] : 0u;
+  }
+  int32_t wo[kSub];
+#pragma unroll
+  for (int q = 0; q < kSub; ++q) {
+    const bool set = (wv[q] >> (lin[q] & 31)) & 1u;
+    wo[q] = A.word_off[set ? (lin[q] >> 5) : 0];
+    ci[q] = set ? wo[q] + __popc(wv[q] & ((1u << (lin[q] & 31)) - 1u)) : -1;
+  }
+#pragma unroll
+  for (int q = 0; q < kSub; ++q) {
+    const int32_t c = ci[q] >= 0 ? ci[q] : 0;
+    fl[q] = A.cell_flux[c];
+    if (kVol) vo[q] = A.cell_vol[c];
   }
 }
 
-__global__ void k_col_count(Grid g, const int32_t* cell_ids, int32_t* col_cnt, int32_t cell_cap,
-                            const int32_t* counters) {
-  const int32_t nif = min(counters[C_NIF], cell_cap);
-  for (int32_t ci = blockIdx.x * blockDim.x + threadIdx.x; ci < nif; ci += gridDim.x * blockDim.x) {
-    const uint32_t lin = (uint32_t)cell_ids[ci];
-    atomicAdd(&col_cnt[lin - g.dncol.div(lin) * g.dncol.d], 1);
-  }
-}
-
-__global__ void k_col_scatter(Grid g, const int32_t* cell_ids, const int32_t* col_off, int32_t* col_cursor,
-                              int32_t* col_cells, int32_t cell_cap, const int32_t* counters) {
-  const int32_t nif = min(counters[C_NIF], cell_cap);
-  for (int32_t ci = blockIdx.x * blockDim.x + threadIdx.x; ci < nif; ci += gridDim.x * blockDim.x) {
-    const uint32_t lin = (uint32_t)cell_ids[ci];
-    const uint32_t col = lin - g.dncol.div(lin) * g.dncol.d;
-    col_cells[col_off[col] + atomicAdd(&col_cursor[col], 1)] = ci;
-  }
-}
-
-constexpr int kColReg = 16;  // columns up to this length are handled in registers
-
-__global__ void k_col_walk(Grid g, const int32_t* col_off, int32_t* col_cells, const int32_t* cell_ids,
-                           const double* cell_flux, const double* cell_vol, int32_t* col_k, double* col_alpha,
-                           double* col_below, double* alpha_if, int32_t* counters) {
-  const int64_t ncol = (int64_t)g.nx * g.ny;
+__global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
+  __shared__ double tot_s[kChunks][kColLanes];
+  const Grid& g = A.g;
+  const int lane = threadIdx.x % kColLanes, w = threadIdx.x / kColLanes;
+  const int32_t i = blockIdx.x * kColLanes + lane, j = blockIdx.y;
+  const bool col_ok = i < g.nx;
+  const int32_t len = (g.nz + kChunks - 1) / kChunks;
+  const int32_t klo = min(w * len, g.nz), khi = min(klo + len, g.nz);
   const double h = g.h, h2 = h * h, h3 = h * h * h;
-  for (int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; col < ncol;
-       col += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t s = col_off[col], e = col_off[col + 1];
-    if (s == e) continue;
-    bool bad = false;
-    double W = 0.0;
-    int32_t prev_k = g.nz;
-    // One step of the walk, from the top of the column down: the cells
-    // between this interfacial cell and the one above have wetted area W.
-    auto step = [&](int32_t q, int32_t ci, int32_t k, double f, double v) {
-      if (prev_k - k > 1) {
-        const double r = W / h2, rr = rint(r);
-        if (fabs(r - rr) > 1e-9 || (rr != 0.0 && rr != 1.0)) bad = true;
-      }
-      const double alpha = (v + h * W) / h3;
-      if (alpha_if) alpha_if[ci] = alpha;
-      col_cells[q] = ci;
-      col_k[q] = k;
-      col_alpha[q] = alpha;
-      W += f;
-      const double rb = rint(W / h2);
-      col_below[q] = rb == 1.0 ? 1.0 : 0.0;
-      prev_k = k;
-    };
-    if (e - s <= kColReg) {
-      // load, sort by compact index (== by k within a column), gather, walk
-      int32_t v[kColReg];
-#pragma unroll
-      for (int q = 0; q < kColReg; ++q) v[q] = (s + q < e) ? col_cells[s + q] : INT_MAX;
-#pragma unroll
-      for (int pass = 0; pass < kColReg; ++pass)
-#pragma unroll
-        for (int q = (pass & 1); q + 1 < kColReg; q += 2) {
-          const int32_t a = v[q], b = v[q + 1];
-          v[q] = min(a, b);
-          v[q + 1] = max(a, b);
-        }
-      int32_t kk[kColReg];
-      double ff[kColReg], vv[kColReg];
-#pragma unroll
-      for (int q = 0; q < kColReg; ++q) {
-        const bool live = s + q < e;
-        kk[q] = live ? (int32_t)g.dncol.div((uint32_t)cell_ids[v[q]]) : 0;
-        ff[q] = live ? cell_flux[v[q]] : 0.0;
-        vv[q] = live ? cell_vol[v[q]] : 0.0;
-      }
-#pragma unroll
-      for (int q = kColReg - 1; q >= 0; --q)
-        if (s + q < e) step(s + q, v[q], kk[q], ff[q], vv[q]);
-    } else {
-      for (int32_t a = s + 1; a < e; ++a) {
-        const int32_t x = col_cells[a];
-        int32_t b = a - 1;
-        while (b >= s && col_cells[b] > x) {
-          col_cells[b + 1] = col_cells[b];
-          --b;
-        }
-        col_cells[b + 1] = x;
-      }
-      for (int32_t q = e - 1; q >= s; --q) {
-        const int32_t ci = col_cells[q];
-        step(q, ci, (int32_t)g.dncol.div((uint32_t)cell_ids[ci]), cell_flux[ci], cell_vol[ci]);
-      }
-    }
-    if (fabs(W / h2) > 1e-9) bad = true;  // the column must close below the front
-    if (bad) atomicOr(&counters[C_ERR], ERR_MESH);
-  }
-}
+  int32_t ci[kSub];
+  double fl[kSub], vo[kSub];
 
-// Dense field: one thread per (column, run of kDenseRun cells in z); the
-// threads of a wavefront are consecutive in x, so every store instruction
-// writes 64 consecutive cells.  Each thread finds its place in the column's
-// short list once and walks up.
-constexpr int kDenseRun = 16;
-__global__ __launch_bounds__(kT) void k_dense(Grid g, const int32_t* col_off, const int32_t* col_k,
-                                              const double* col_alpha, const double* col_below, double* alpha) {
-  const int32_t j = blockIdx.y;
-  const int32_t k0 = blockIdx.z * kDenseRun;
-  const int64_t plane = (int64_t)g.nx * g.ny;
-  for (int32_t i = blockIdx.x * kT + threadIdx.x; i < g.nx; i += gridDim.x * kT) {
-    const int64_t col = i + (int64_t)g.nx * j;
-    const int32_t s = col_off[col], e = col_off[col + 1];
-    int32_t q = s;
-    while (q < e && col_k[q] < k0) ++q;
-    const int32_t k1 = min(k0 + kDenseRun, g.nz);
-    for (int32_t k = k0; k < k1; ++k) {
-      while (q < e && col_k[q] < k) ++q;
-      double a = 0.0;
-      if (q < e) a = (col_k[q] == k) ? col_alpha[q] : col_below[q];
-      alpha[col + plane * k] = a;
+  double tot = 0.0;
+  for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSub) {
+    read_sub<false>(A, col_ok, i, j, k1, klo, ci, fl, vo);
+#pragma unroll
+    for (int q = 0; q < kSub; ++q)
+      if (ci[q] >= 0) tot += fl[q];
+  }
+  tot_s[w][lane] = tot;
+  __syncthreads();
+  double W = 0.0;
+  for (int u = kChunks - 1; u > w; --u) W += tot_s[u][lane];
+
+  bool bad = false;
+  for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSub) {
+    read_sub<true>(A, col_ok, i, j, k1, klo, ci, fl, vo);
+#pragma unroll
+    for (int q = 0; q < kSub; ++q) {
+      const int32_t k = k1 - q;
+      if (!col_ok || k < klo) continue;
+      double a;
+      if (ci[q] >= 0) {
+        a = (vo[q] + h * W) / h3;
+        if (A.alpha_if) A.alpha_if[ci[q]] = a;
+        W += fl[q];
+      } else {
+        const double r = W / h2, rr = round(r);
+        if (fabs(r - rr) > 1e-9 || (rr != 0.0 && rr != 1.0)) bad = true;
+        a = rr;
+      }
+      if (A.alpha) A.alpha[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)] = a;
     }
   }
+  if (w == 0 && col_ok && fabs(W / h2) > 1e-9) bad = true;  // the column must close below the front
+  if (bad) atomicOr(&A.counters[C_ERR], ERR_MESH);
 }
 
 }  // namespace
@@ -177,25 +147,10 @@ hipError_t launch_volume_fraction(const ftc_cells* ws, const Mesh& m, double* al
   const Grid& g = ws->grid;
   hipLaunchKernelGGL(k_cell_sums, dim3(grid_blocks(ws->cell_cap, kT, kStrideBlocks)), dim3(kT), 0, s, ws->offsets,
                      ws->piece_flux, ws->piece_vol, ws->cell_flux, ws->cell_vol, ws->cell_cap, ws->counters);
-  hipLaunchKernelGGL(k_clear_cols, dim3(grid_blocks(ws->ncol + 1, kT, kStrideBlocks)), dim3(kT), 0, s, ws->col_off,
-                     ws->ncol + 1, ws->col_cursor, ws->ncol);
-  hipLaunchKernelGGL(k_col_count, dim3(grid_blocks(ws->cell_cap, kT, kStrideBlocks)), dim3(kT), 0, s, g,
-                     ws->cell_ids, ws->col_off, ws->cell_cap, ws->counters);
-  hipError_t e = scan_exclusive(ws->col_off, ws->ncol, ws->scan_tmp, nullptr, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_col_scatter, dim3(grid_blocks(ws->cell_cap, kT, kStrideBlocks)), dim3(kT), 0, s, g,
-                     ws->cell_ids, ws->col_off, ws->col_cursor, ws->col_cells, ws->cell_cap, ws->counters);
-  time_start(ws, FTC_KERNEL_COL_WALK, s);
-  hipLaunchKernelGGL(k_col_walk, dim3(grid_blocks(ws->ncol, 64, 65536)), dim3(64), 0, s, g, ws->col_off,
-                     ws->col_cells, ws->cell_ids, ws->cell_flux, ws->cell_vol, ws->col_k, ws->col_alpha,
-                     ws->col_below, alpha_if, ws->counters);
-  time_stop(ws, FTC_KERNEL_COL_WALK, s);
-  if (alpha_dense) {
-    time_start(ws, FTC_KERNEL_DENSE_ALPHA, s);
-    hipLaunchKernelGGL(k_dense, dim3(grid_blocks(g.nx, kT, 64), g.ny, (g.nz + kDenseRun - 1) / kDenseRun), dim3(kT),
-                       0, s, g, ws->col_off, ws->col_k, ws->col_alpha, ws->col_below, alpha_dense);
-    time_stop(ws, FTC_KERNEL_DENSE_ALPHA, s);
-  }
+  ColArgs A{g, ws->bitmap, ws->word_off, ws->cell_flux, ws->cell_vol, alpha_if, alpha_dense, ws->counters};
+  time_start(ws, FTC_KERNEL_COLUMNS, s);
+  hipLaunchKernelGGL(k_columns, dim3((g.nx + kColLanes - 1) / kColLanes, g.ny), dim3(kColLanes * kChunks), 0, s, A);
+  time_stop(ws, FTC_KERNEL_COLUMNS, s);
   return hipGetLastError();
 }
 

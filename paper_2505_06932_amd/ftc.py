@@ -34,7 +34,7 @@ EXPORTED = ["ftc_cells_create", "ftc_cells_destroy", "ftc_build_cell_lists", "ft
             "ftc_status_str"]
 
 # ftc_kernel values (timing)
-KERNELS = {"tri_pieces": 0, "piece_rank": 1, "col_walk": 2, "dense_alpha": 3, "ppic": 4, "csf": 5, "interp": 6}
+KERNELS = {"tri_pieces": 0, "piece_rank": 1, "columns": 2, "ppic": 3, "csf": 4, "interp": 5}
 
 
 class _CGrid(C.Structure):
