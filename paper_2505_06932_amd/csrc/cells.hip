@@ -8,8 +8,9 @@
 //    cell's bit in a grid-sized occupancy bitmap and is appended, with its
 //    two z-column integrals, to a pair list (one atomic allocation per
 //    workgroup; queued candidates keep their queue slot);
-// 2. popcount prefix sums of the bitmap -> the interfacial cells in
-//    ascending linear id and the compact index (rank) of every cell;
+// 2. popcount prefix sums of the bitmap, listing the interfacial cells in
+//    ascending linear id on the way -> the compact index (rank) of every
+//    cell;
 // 3. per pair: compact cell index and a count per cell; prefix sums of the
 //    counts -> CSR offsets;
 // 4. scatter the pairs into their cell's segment (any order), then place
@@ -26,10 +27,15 @@ constexpr int kT = 256;
 constexpr int kStrideBlocks = 2048;
 constexpr int kPieceLanes = 64;  // k_clip_queue: one wavefront per workgroup
 
+// Clears the per-build state and packs the vertex coordinates as (x, y, z, 0).
 __global__ void k_clear_build(uint32_t* bitmap, int64_t nwords, int32_t* cell_cnt, int64_t ncnt, int32_t* cursor,
-                              int64_t ncur, int32_t* counters) {
+                              int64_t ncur, int32_t* counters, Mesh m, double2* vtx4) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t v = g0; v < m.nv; v += stride) {
+    vtx4[2 * v] = make_double2(m.x[v], m.y[v]);
+    vtx4[2 * v + 1] = make_double2(m.z[v], 0.0);
+  }
   for (int64_t i = g0; i < nwords; i += stride) bitmap[i] = 0u;
   for (int64_t i = g0; i < ncnt; i += stride) cell_cnt[i] = 0;
   for (int64_t i = g0; i < ncur; i += stride) cursor[i] = 0;
@@ -79,19 +85,26 @@ __device__ inline int64_t block_alloc(int32_t v, int32_t* counter, int32_t* sh) 
 // clipping to the second (the clipping queue).  Two passes over the cheap
 // classification: count, allocate, write.
 constexpr int kClassifyT = 1024;
-__global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, uint32_t* bitmap, PairOut P,
-                                                             int64_t q_cap, int32_t* counters) {
+__global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, const double2* vtx4, int4* tri4,
+                                                             uint32_t* bitmap, PairOut P, int64_t q_cap,
+                                                             int32_t* counters) {
   __shared__ int32_t sh[kClassifyT / 64 + 1];
   const int32_t t = blockIdx.x * kClassifyT + threadIdx.x;
   bool valid = t < m.nt;
-  if (valid && !tri_ok(m, t)) {
-    atomicOr(&counters[C_ERR], ERR_MESH);
-    valid = false;
+  if (valid) {
+    const int32_t a = m.t0[t], b = m.t1[t], c = m.t2[t];
+    if (a >= 0 && b >= 0 && c >= 0 && a < m.nv && b < m.nv && c < m.nv) {
+      tri4[t] = make_int4(a, b, c, 0);
+    } else {
+      tri4[t] = make_int4(0, 0, 0, 0);
+      atomicOr(&counters[C_ERR], ERR_MESH);
+      valid = false;
+    }
   }
   Tri T;
   int64_t lo[3] = {0, 0, 0}, hi[3] = {-1, -1, -1};
   if (valid) {
-    T = load_tri(m, t);
+    T = load_tri_packed(tri4, vtx4, t);
     bool ok = true;
 #pragma unroll
     for (int r = 0; r < 3; ++r) ok = ok && in_margin(g, T.v[r][0], T.v[r][1], T.v[r][2]);
@@ -151,8 +164,8 @@ __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, uin
 
 // Per queued candidate (second region of the pair list): full clipping; the
 // result stays in the candidate's slot, with cell -1 when there is no piece.
-__global__ __launch_bounds__(kPieceLanes) void k_clip_queue(Grid g, Mesh m, PairOut P, int64_t q_cap,
-                                                            uint32_t* bitmap, const int32_t* counters) {
+__global__ __launch_bounds__(kPieceLanes) void k_clip_queue(Grid g, const int4* tri4, const double2* vtx4, PairOut P,
+                                                            int64_t q_cap, uint32_t* bitmap, const int32_t* counters) {
   __shared__ PolyLDS<kPieceLanes> L;
   const int lane = threadIdx.x;
   const int64_t nq = min((int64_t)counters[C_NQUEUE], q_cap);
@@ -162,7 +175,7 @@ __global__ __launch_bounds__(kPieceLanes) void k_clip_queue(Grid g, Mesh m, Pair
       const int64_t slot = P.cap + q;
       const int32_t lin = P.lin[slot];
       const Cell3 c = unpack_cell(g, lin);
-      const Tri T = load_tri(m, P.tri[slot]);
+      const Tri T = load_tri_packed(tri4, vtx4, P.tri[slot]);
       const Piece pc = clip_piece(g, T, c.i, c.j, c.k, L, lane);
       if (pc.keep) {
         atomicOr(&bitmap[lin >> 5], 1u << (lin & 31));
@@ -175,22 +188,6 @@ __global__ __launch_bounds__(kPieceLanes) void k_clip_queue(Grid g, Mesh m, Pair
   }
 }
 
-__global__ __launch_bounds__(kT) void k_emit_cells(const uint32_t* bitmap, const int32_t* word_off, int64_t nwords,
-                                                   int32_t* cell_ids, int32_t cell_cap, int32_t* counters) {
-  const int64_t w = (int64_t)blockIdx.x * kT + threadIdx.x;
-  if (w >= nwords) return;
-  uint32_t bits = bitmap[w];
-  int32_t pos = word_off[w];
-  while (bits) {
-    const int b = __ffs(bits) - 1;
-    if (pos < cell_cap)
-      cell_ids[pos] = (int32_t)(w * 32 + b);
-    else
-      atomicOr(&counters[C_ERR], ERR_CAPACITY);
-    ++pos;
-    bits &= bits - 1u;
-  }
-}
 
 __device__ inline int32_t rank_of(const uint32_t* bitmap, const int32_t* word_off, int64_t lin) {
   const uint32_t w = bitmap[lin >> 5];
@@ -223,7 +220,7 @@ __global__ void k_pair_count(int32_t* pair_lin, const uint32_t* bitmap, const in
       pair_lin[p] = ci;
       atomicAdd(&cell_cnt[ci], 1);
     } else {
-      pair_lin[p] = -1;  // its cell did not fit the capacity (latched by k_emit_cells)
+      pair_lin[p] = -1;  // its cell did not fit the capacity (latched while listing the cells)
     }
   }
 }
@@ -273,19 +270,20 @@ __global__ void k_rank_place(const int32_t* tmp_tri, const int32_t* tmp_pair, co
 
 hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
   const Grid& g = ws->grid;
+  int4* tri4 = reinterpret_cast<int4*>(ws->tri4);
+  double2* vtx4 = reinterpret_cast<double2*>(ws->vtx4);
   hipLaunchKernelGGL(k_clear_build, dim3(kStrideBlocks), dim3(kT), 0, s, ws->bitmap, ws->nwords, ws->offsets,
-                     (int64_t)ws->cell_cap + 1, ws->cursor, (int64_t)ws->cell_cap, ws->counters);
+                     (int64_t)ws->cell_cap + 1, ws->cursor, (int64_t)ws->cell_cap, ws->counters, m, vtx4);
   PairOut P{ws->pair_cell, ws->pair_tri, ws->pair_flux, ws->pair_vol, ws->pair_cap};
   time_start(ws, FTC_KERNEL_TRI_PIECES, s);
-  hipLaunchKernelGGL(k_tri_classify, dim3(grid_blocks(m.nt, kClassifyT)), dim3(kClassifyT), 0, s, g, m, ws->bitmap,
-                     P, ws->queue_cap, ws->counters);
+  hipLaunchKernelGGL(k_tri_classify, dim3(grid_blocks(m.nt, kClassifyT)), dim3(kClassifyT), 0, s, g, m, vtx4, tri4,
+                     ws->bitmap, P, ws->queue_cap, ws->counters);
   hipLaunchKernelGGL(k_clip_queue, dim3(grid_blocks(ws->queue_cap, kPieceLanes, 8192)), dim3(kPieceLanes), 0, s, g,
-                     m, P, ws->queue_cap, ws->bitmap, ws->counters);
+                     tri4, vtx4, P, ws->queue_cap, ws->bitmap, ws->counters);
   time_stop(ws, FTC_KERNEL_TRI_PIECES, s);
-  hipError_t e = scan_popcount(ws->bitmap, ws->word_off, ws->nwords, ws->scan_tmp, ws->counters + C_NIF, s);
+  hipError_t e = scan_popcount_emit(ws->bitmap, ws->word_off, ws->nwords, ws->scan_tmp, ws->counters + C_NIF,
+                                    ws->cell_ids, ws->cell_cap, ws->counters, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_emit_cells, dim3(grid_blocks(ws->nwords, kT)), dim3(kT), 0, s, ws->bitmap, ws->word_off,
-                     ws->nwords, ws->cell_ids, ws->cell_cap, ws->counters);
   const int64_t npair_max = ws->pair_cap + ws->queue_cap;
   hipLaunchKernelGGL(k_pair_count, dim3(grid_blocks(npair_max, kT, kStrideBlocks)), dim3(kT), 0, s, ws->pair_cell,
                      ws->bitmap, ws->word_off, ws->offsets, ws->cell_cap, ws->pair_cap, ws->queue_cap,

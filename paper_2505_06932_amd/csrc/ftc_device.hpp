@@ -98,6 +98,22 @@ struct Tri {
   double v[3][3];
 };
 
+// Triangle from the packed records: corners (t0, t1, t2, 0) as one int4,
+// coordinates (x, y, z, 0) as two double2 per vertex.
+__device__ inline Tri load_tri_packed(const int4* tri4, const double2* vtx4, int32_t t) {
+  Tri T;
+  const int4 c = tri4[t];
+  const int32_t cr[3] = {c.x, c.y, c.z};
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double2 a = vtx4[2 * (int64_t)cr[r]], b = vtx4[2 * (int64_t)cr[r] + 1];
+    T.v[r][0] = a.x;
+    T.v[r][1] = a.y;
+    T.v[r][2] = b.x;
+  }
+  return T;
+}
+
 __device__ inline Tri load_tri(const Mesh& m, int32_t t) {
   Tri T;
   const int32_t c[3] = {m.t0[t], m.t1[t], m.t2[t]};

@@ -9,6 +9,8 @@
 
 // Counter slots in ftc_cells::counters (device int32).
 namespace ftc {
+constexpr int kFitSlots = 32;  // doubles per cell in ftc_cells::fit
+constexpr int kFitList = 64;   // weighted-triangle list entries per cell
 enum : int {
   C_NIF = 0,      // interfacial cells of the last build
   C_NPAIRS = 1,   // (cell, triangle) pieces of the last build
@@ -66,6 +68,9 @@ struct ftc_cells {
   int32_t* vb_cursor;     // [cell_cap] vertices per cell while counting; zero between calls
   int32_t* vb_ids;        // [nv_cap] vertices grouped by interfacial cell
   int32_t* stray;         // [nv_cap] vertices in cells without pieces
+  double* fit;            // [kFitSlots * cell_cap] per cell: normal equations (21 + 6), vertex normal (3), weighted count
+  int32_t* wl_tri;        // [4 * cell_cap * kFitList] packed corners of the triangles of each cell's fit
+  double* wl_w;           // [cell_cap * kFitList] their weights
   double* best_d2;        // [cell_cap] smallest squared distance of a vertex in the 27 cells around
   int32_t* best_v;        // [cell_cap] lowest vertex attaining it
 
@@ -87,6 +92,12 @@ hipError_t scan_exclusive(int32_t* data, int64_t n, int32_t* tmp, int32_t* total
 // Same, with inputs popcount(words[i]) (output to out[0..n], total to out[n]).
 hipError_t scan_popcount(const uint32_t* words, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out,
                          hipStream_t s);
+
+// scan_popcount that also lists the set bits in ascending order: bit b of
+// word w goes to ids[out[w] + rank of b in w] as 32 w + b; entries at or
+// past `cap` are dropped and latch ERR_CAPACITY in counters[C_ERR].
+hipError_t scan_popcount_emit(const uint32_t* words, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out,
+                              int32_t* ids, int32_t cap, int32_t* counters, hipStream_t s);
 
 // Two independent exclusive scans (a[0..na) -> a_out[0..na], c[0..nc) ->
 // c_out[0..nc], totals last) in one pair of launches; in place is allowed.

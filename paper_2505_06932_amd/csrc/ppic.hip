@@ -75,7 +75,7 @@ struct Cfg {
   static_assert((HS_ & (HS_ - 1)) == 0 && HS_ >= 2 * VC_, "hash size");
   static_assert(VC_ <= 256, "owner table holds bytes");
 };
-using Fast = Cfg<8, 64, 32, 64, 8>;
+using Fast = Cfg<8, 64, 32, 64, 6>;
 using Wide = Cfg<64, 512, 256, 512, 4>;
 
 // ----------------------------------------------------------------- pre-passes
@@ -187,6 +187,8 @@ __device__ inline void consider(const double2* vtx4, int32_t v, const double xc[
 
 __device__ inline double cell_centre(double org, int32_t i, double h) { return org + ((double)i + 0.5) * h; }
 
+constexpr int kSortReg = 8;  // incident lists up to this length are sorted in registers
+
 // Blocks [0, sort_blocks): one vertex per thread, its incident-triangle
 // list sorted ascending.  The other blocks: 32 lanes per interfacial cell,
 // lane l < 27 scans the vertex bin of cell l of the 3x3x3 block around it,
@@ -201,6 +203,24 @@ __global__ __launch_bounds__(kT) void k_sort_vstar(Grid g, int32_t nv, const int
     const int32_t v = blockIdx.x * kT + threadIdx.x;
     if (v >= nv) return;
     const int32_t s = vt_off[v], e = vt_off[v + 1];
+    if (e - s <= kSortReg) {
+      // in registers: odd-even transposition sort, padding at the end
+      int32_t x[kSortReg];
+#pragma unroll
+      for (int q = 0; q < kSortReg; ++q) x[q] = s + q < e ? vt_ids[s + q] : INT_MAX;
+#pragma unroll
+      for (int pass = 0; pass < kSortReg; ++pass)
+#pragma unroll
+        for (int q = pass & 1; q + 1 < kSortReg; q += 2) {
+          const int32_t lo = min(x[q], x[q + 1]), hi = max(x[q], x[q + 1]);
+          x[q] = lo;
+          x[q + 1] = hi;
+        }
+#pragma unroll
+      for (int q = 0; q < kSortReg; ++q)
+        if (s + q < e) vt_ids[s + q] = x[q];
+      return;
+    }
     for (int32_t a = s + 1; a < e; ++a) {
       const int32_t x = vt_ids[a];
       int32_t b = a - 1;
@@ -261,6 +281,9 @@ struct PPICArgs {
   const int32_t* best_v;
   int32_t* counters;
   int32_t* ovf_cells;
+  double* fit;
+  int4* wl_tri;
+  double* wl_w;
   int32_t cell_cap;
   double *kappa, *nx, *ny, *nz, *coeff;
   int32_t *status, *diag;
@@ -280,7 +303,6 @@ struct RingMem {
 // Fit state, alive after the rings.
 template <class C>
 struct FitMem {
-  double Mres[21];   // normal matrix, kept for the refinement residual
   double W[C::TC];   // weights of the triangles inside the support
   int32_t S[C::TC];  // those triangles
 };
@@ -305,6 +327,7 @@ __device__ inline int hslot(int32_t key) {
 template <class C>
 __device__ inline int hinsert(RingMem<C>& M, int32_t key) {
   int s = hslot<C::HS>(key);
+#pragma unroll 1
   for (int p = 0; p < C::HS; ++p) {
     const int32_t prev = atomicCAS(&M.hkey[s], -1, key);
     if (prev == -1 || prev == key || prev == (key | kPlaced)) return s;
@@ -321,6 +344,7 @@ __device__ inline bool in_ring(const RingMem<C>& M, int32_t key, int32_t home) {
   if (home == placed) return true;
   if (home == -1 || home == key) return false;
   int s = hslot<C::HS>(key);
+#pragma unroll 1
   for (int p = 0; p < C::HS; ++p) {
     const int32_t k = M.hkey[s];
     if (k == placed) return true;
@@ -676,19 +700,46 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
         const int i = k * G + gl;
         const double dd = i < nTc ? FM.W[i] : DBL_MAX;
         const int32_t ti = i < nTc ? CM.T[i] : 0;
+        int4 t4 = make_int4(0, 0, 0, 0);
+        if constexpr (!kQueue) t4 = A.tri4[ti];
         const bool keep = i < nTc && dd < lim;
         const uint64_t bal = gballot<G>(keep, grp);
         if (keep) {
           const int pos = nw + __popcll(bal & below_me);
           const double qq = sqrt(dd) * inv_delta;
           const double om = 1.0 - qq;
-          FM.W[pos] = (1.0 + 4.0 * qq) * (om * om) * (om * om);
-          FM.S[pos] = ti;
+          const double wt = (1.0 + 4.0 * qq) * (om * om) * (om * om);
+          if constexpr (kQueue) {
+            FM.W[pos] = wt;
+            FM.S[pos] = ti;
+          } else {
+            A.wl_w[(int64_t)c * kFitList + pos] = wt;
+            A.wl_tri[(int64_t)c * kFitList + pos] = t4;
+          }
         }
         nw += __popcll(bal);
       }
     }
     __syncthreads();
+
+    if constexpr (!kQueue) {
+      // the fit pass takes the list; a queued cell is marked for it to skip
+      if (act && gl == 0) {
+        const int64_t cs = A.cell_cap;
+        A.fit[27 * cs + c] = n0;
+        A.fit[28 * cs + c] = n1;
+        A.fit[29 * cs + c] = n2;
+        A.fit[30 * cs + c] = !emit ? -3.0 : (ok ? (double)cnt : (ovf ? -1.0 : -2.0));
+        if (A.diag && emit) {
+          A.diag[c] = vs;
+          A.diag[cs + c] = nT;
+          A.diag[2 * cs + c] = cnt;
+          A.diag[3 * cs + c] = it;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
 
     // ---- weighted moments and normal equations
     const double inv_h = 1.0 / h;
@@ -744,21 +795,155 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
 #pragma unroll
     for (int qa = 0; qa < 27; ++qa) acc[qa] = group_sum<G>(acc[qa]);
 
-    // ---- solve (every lane of the group holds M and b).  M is kept in LDS
-    // for the refinement residual and factorised in place in registers.
+    // ---- hand the normal equations to the solve pass (weighted count -1:
+    // ring beyond the capacities, -2: no closest vertex)
+    // (staged through LDS so that each lane stores a few slots)
+    __syncthreads();
     if (gl == 0) {
 #pragma unroll
-      for (int qa = 0; qa < 21; ++qa) FM.Mres[qa] = acc[qa];
+      for (int qa = 0; qa < 27; ++qa) FM.W[qa] = acc[qa];
+      FM.W[27] = n0;
+      FM.W[28] = n1;
+      FM.W[29] = n2;
+      FM.W[30] = ok ? (double)cnt : (ovf ? -1.0 : -2.0);
     }
     __syncthreads();
+    if (emit) {
+      const int64_t cs = A.cell_cap;
+      for (int qa = gl; qa < 31; qa += G) A.fit[qa * cs + c] = FM.W[qa];
+      if (A.diag && gl == 0) {
+        A.diag[c] = vs;
+        A.diag[cs + c] = nT;
+        A.diag[2 * cs + c] = cnt;
+        A.diag[3 * cs + c] = it;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Weighted moments and normal equations of the cells whose ring fitted the
+// fast shape: 8 lanes per cell (8 cells per wavefront) over the cell's
+// weighted-triangle list; sums reduced over the lanes and stored for the
+// solve pass.
+constexpr int kFitG = 8;
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_ppic_fit(PPICArgs A) {
+  constexpr int G = kFitG, NG = 64 / kFitG;
+  __shared__ double stage[NG][28];
+  const Grid& g = A.g;
+  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+  const int32_t nitems = min(A.counters[C_NIF], A.cell_cap);
+  const int64_t cs = A.cell_cap;
+  const double h = g.h, inv_h = 1.0 / h;
+  const int32_t ngroups = (nitems + NG - 1) / NG;
+  const int32_t per = (ngroups + kXCD - 1) / kXCD;
+  const int32_t xcd = blockIdx.x % kXCD, nj = gridDim.x / kXCD;
+  for (int32_t q = blockIdx.x / kXCD; q < per; q += nj) {
+    const int32_t gi = xcd * per + q;
+    if (gi >= ngroups) break;
+    const int32_t c = gi * NG + grp;
+    const bool act = c < nitems;
+    const double wc = act ? A.fit[30 * cs + c] : -2.0;
+    const int cnt = wc > 0.0 ? (int)wc : 0;
+    const double n0 = act ? A.fit[27 * cs + c] : 0.0, n1 = act ? A.fit[28 * cs + c] : 0.0,
+                 n2 = act ? A.fit[29 * cs + c] : 1.0;
+    const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
+    const double xc[3] = {cell_centre(g.x0, cc3.i, h), cell_centre(g.y0, cc3.j, h), cell_centre(g.z0, cc3.k, h)};
+    const double sg = copysign(1.0, n2);
+    const double fa = -1.0 / (sg + n2);
+    const double fb = n0 * n1 * fa;
+    const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
+    const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
+    double acc[27];
+#pragma unroll
+    for (int qa = 0; qa < 27; ++qa) acc[qa] = 0.0;
+    const int wrounds = wave_max_i((cnt + G - 1) / G);
+    const int4* lt = A.wl_tri + (int64_t)(act ? c : 0) * kFitList;
+    const double* lw = A.wl_w + (int64_t)(act ? c : 0) * kFitList;
+    // entries of the next round are loaded while this round is computed
+    int4 tn = lt[gl < cnt ? gl : 0];
+    double wn = gl < cnt ? lw[gl] : 0.0;
+    for (int k = 0; k < wrounds; ++k) {
+      const int j = k * G + gl;
+      const int4 t4 = tn;
+      const double w = wn;
+      if (k + 1 < wrounds) {
+        const int jn = j + G;
+        tn = lt[jn < cnt ? jn : 0];
+        wn = jn < cnt ? lw[jn] : 0.0;
+      }
+      const int32_t cr[3] = {t4.x, t4.y, t4.z};
+      double xi[3], eta[3], zeta[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const P3 p = vtx(A.vtx4, cr[e]);
+        const double dx = p.x - xc[0], dy = p.y - xc[1], dz = p.z - xc[2];
+        xi[e] = fma(dz, t1z, fma(dy, t1y, dx * t1x)) * inv_h;
+        eta[e] = fma(dz, t2z, fma(dy, t2y, dx * t2x)) * inv_h;
+        zeta[e] = fma(dz, n2, fma(dy, n1, dx * n0)) * inv_h;
+      }
+      const double area = 0.5 * fma(xi[1] - xi[0], eta[2] - eta[0], -((xi[2] - xi[0]) * (eta[1] - eta[0])));
+      double sm[6] = {3.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const double mx = 0.5 * (xi[e] + xi[(e + 1) % 3]);
+        const double my = 0.5 * (eta[e] + eta[(e + 1) % 3]);
+        sm[1] += mx;
+        sm[2] += my;
+        sm[3] = fma(mx, mx, sm[3]);
+        sm[4] = fma(mx, my, sm[4]);
+        sm[5] = fma(my, my, sm[5]);
+      }
+      const double a3 = area * (1.0 / 3.0);
+      double mom[6];
+#pragma unroll
+      for (int qa = 0; qa < 6; ++qa) mom[qa] = a3 * sm[qa];
+      const double wv = w * (a3 * (zeta[0] + zeta[1] + zeta[2]));
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const double wa = w * mom[a];
+#pragma unroll
+        for (int b = a; b < 6; ++b) acc[P6(a, b)] = fma(wa, mom[b], acc[P6(a, b)]);
+        acc[21 + a] = fma(wv, mom[a], acc[21 + a]);
+      }
+    }
+#pragma unroll
+    for (int qa = 0; qa < 27; ++qa) acc[qa] = group_sum<G>(acc[qa]);
+    // staged through LDS so that each lane stores a few of the 27 sums
+    if (gl == 0) {
+#pragma unroll
+      for (int qa = 0; qa < 27; ++qa) stage[grp][qa] = acc[qa];
+    }
+    __syncthreads();
+    if (act && wc >= 0.0)
+      for (int qa = gl; qa < 27; qa += G) A.fit[qa * cs + c] = stage[grp][qa];
+    __syncthreads();
+  }
+}
+
+// One thread per interfacial cell: Cholesky factorisation of the packed
+// normal matrix (in place), one step of iterative refinement, the
+// coefficients scaled back from the h-scaled frame, kappa = 2H at the frame
+// origin and the interface normal.
+__global__ __launch_bounds__(kT) void k_ppic_solve(PPICArgs A) {
+  const int32_t nif = min(A.counters[C_NIF], A.cell_cap);
+  const int64_t cs = A.cell_cap;
+  const double h = A.g.h, inv_h = 1.0 / h;
+  for (int32_t c = blockIdx.x * kT + threadIdx.x; c < nif; c += gridDim.x * kT) {
+    const double* F = A.fit + c;
+    const double wcnt = F[30 * cs];
+    const double n0 = F[27 * cs], n1 = F[28 * cs], n2 = F[29 * cs];
     double co[6] = {NAN, NAN, NAN, NAN, NAN, NAN};
     double kap = NAN, ni0 = NAN, ni1 = NAN, ni2 = NAN;
-    uint32_t st = ovf ? FTC_CELL_OVERFLOW : 0u;
-    if (ok) {
+    uint32_t st = wcnt == -1.0 ? FTC_CELL_OVERFLOW : 0u;
+    if (wcnt >= 0.0) {
+      double acc[27];
+#pragma unroll
+      for (int qa = 0; qa < 27; ++qa) acc[qa] = F[qa * cs];
       const double trace =
           acc[P6(0, 0)] + acc[P6(1, 1)] + acc[P6(2, 2)] + acc[P6(3, 3)] + acc[P6(4, 4)] + acc[P6(5, 5)];
       // in place: acc[P6(j, i)] becomes L(i, j) for i >= j
-      bool rank_ok = cnt >= 6;
+      bool rank_ok = wcnt >= 6.0;
       double invd[6];
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
@@ -799,11 +984,12 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
           }
         };
         solve(acc + 21, ah);
+        // residual with the unfactorised matrix, read again
 #pragma unroll
         for (int i2 = 0; i2 < 6; ++i2) {
           double s2 = acc[21 + i2];
 #pragma unroll
-          for (int p = 0; p < 6; ++p) s2 -= FM.Mres[i2 <= p ? P6(i2, p) : P6(p, i2)] * ah[p];
+          for (int p = 0; p < 6; ++p) s2 -= F[(i2 <= p ? P6(i2, p) : P6(p, i2)) * cs] * ah[p];
           r6[i2] = s2;
         }
         solve(r6, r6);
@@ -819,6 +1005,12 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
         const double num = 2.0 * co[3] * (1.0 + gy * gy) - 2.0 * gx * gy * co[4] + 2.0 * co[5] * (1.0 + gx * gx);
         const double sq = 1.0 + gx * gx + gy * gy;
         kap = -num / (sq * sqrt(sq));
+        // the tangents of the frame again (Duff et al.)
+        const double sg = copysign(1.0, n2);
+        const double fa = -1.0 / (sg + n2);
+        const double fb = n0 * n1 * fa;
+        const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
+        const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
         ni0 = n0 - co[1] * t1x - co[2] * t2x;
         ni1 = n1 - co[1] * t1y - co[2] * t2y;
         ni2 = n2 - co[1] * t1z - co[2] * t2z;
@@ -828,22 +1020,13 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
         ni2 *= il;
       }
     }
-    if (emit && gl == 0) {
-      A.kappa[c] = kap;
-      A.nx[c] = ni0;
-      A.ny[c] = ni1;
-      A.nz[c] = ni2;
-      if (A.coeff)
-        for (int qa = 0; qa < 6; ++qa) A.coeff[(int64_t)qa * A.cell_cap + c] = st ? NAN : co[qa];
-      if (A.status) A.status[c] = (int32_t)st;
-      if (A.diag) {
-        A.diag[c] = vs;
-        A.diag[(int64_t)A.cell_cap + c] = nT;
-        A.diag[2 * (int64_t)A.cell_cap + c] = cnt;
-        A.diag[3 * (int64_t)A.cell_cap + c] = it;
-      }
-    }
-    __syncthreads();
+    A.kappa[c] = kap;
+    A.nx[c] = ni0;
+    A.ny[c] = ni1;
+    A.nz[c] = ni2;
+    if (A.coeff)
+      for (int qa = 0; qa < 6; ++qa) A.coeff[qa * cs + c] = st ? NAN : co[qa];
+    if (A.status) A.status[c] = (int32_t)st;
   }
 }
 
@@ -882,6 +1065,9 @@ hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, 
   A.best_v = ws->best_v;
   A.counters = ws->counters;
   A.ovf_cells = ws->ovf_cells;
+  A.fit = ws->fit;
+  A.wl_tri = reinterpret_cast<int4*>(ws->wl_tri);
+  A.wl_w = ws->wl_w;
   A.cell_cap = ws->cell_cap;
   A.kappa = kappa;
   A.nx = nx;
@@ -894,7 +1080,10 @@ hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, 
   const int32_t blocks = round_up(std::min<int64_t>(std::max<int64_t>(groups, 1), 65536), kXCD);
   time_start(ws, FTC_KERNEL_PPIC, s);
   hipLaunchKernelGGL((k_ppic<Fast, false>), dim3(blocks), dim3(64), 0, s, A);
+  hipLaunchKernelGGL(k_ppic_fit, dim3(round_up(std::min<int64_t>(std::max<int64_t>(((int64_t)ws->cell_cap + 7) / 8, 1),
+                                                                  65536), kXCD)), dim3(64), 0, s, A);
   hipLaunchKernelGGL((k_ppic<Wide, true>), dim3(kWideBlocks), dim3(64), 0, s, A);
+  hipLaunchKernelGGL(k_ppic_solve, dim3(grid_blocks(ws->cell_cap, kT)), dim3(kT), 0, s, A);
   time_stop(ws, FTC_KERNEL_PPIC, s);
   return hipGetLastError();
 }

@@ -137,6 +137,46 @@ __global__ __launch_bounds__(kThreads) void k_block_apply2(const int32_t* a, int
     apply_one(LoadI32{c}, nc, tmp + nb1, c_out, nullptr, blockIdx.x - nb1, nb2);
 }
 
+// Second pass of the popcount scan that also lists the set bits: every set
+// bit b of word w becomes entry out[w] + (rank of b in w) of `ids`, with the
+// value 32 w + b (entries at or past `cap` latch a capacity error).
+__global__ __launch_bounds__(kThreads) void k_block_apply_emit(const uint32_t* words, int64_t n, const int32_t* tmp,
+                                                               int32_t* out, int32_t* total_out, int64_t nb,
+                                                               int32_t* ids, int32_t cap, int32_t* counters) {
+  const int64_t b = blockIdx.x;
+  const int32_t prefix = block_sum_prefix(tmp, b);
+  const int64_t base = b * kScanBlock + (int64_t)threadIdx.x * kItems;
+  uint32_t wv[kItems];
+  int32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    wv[q] = (base + q < n) ? words[base + q] : 0u;
+    s += __popc(wv[q]);
+  }
+  int32_t total;
+  int32_t run = block_excl_scan(s, &total) + prefix;
+  bool over = false;
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    if (base + q < n) out[base + q] = run;
+    uint32_t bits = wv[q];
+    while (bits) {
+      const int bit = __ffs(bits) - 1;
+      if (run < cap)
+        ids[run] = (int32_t)((base + q) * 32 + bit);
+      else
+        over = true;
+      ++run;
+      bits &= bits - 1u;
+    }
+  }
+  if (over) atomicOr(&counters[C_ERR], ERR_CAPACITY);
+  if (b == nb - 1 && threadIdx.x == 0) {
+    out[n] = prefix + total;
+    if (total_out) *total_out = prefix + total;
+  }
+}
+
 template <class L>
 hipError_t scan_impl(L load, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out, hipStream_t s) {
   if (n < 0 || n > kScanMax) return hipErrorInvalidValue;
@@ -161,6 +201,16 @@ hipError_t scan_exclusive(int32_t* data, int64_t n, int32_t* tmp, int32_t* total
 hipError_t scan_popcount(const uint32_t* words, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out,
                          hipStream_t s) {
   return scan_impl(LoadPop{words}, out, n, tmp, total_out, s);
+}
+
+hipError_t scan_popcount_emit(const uint32_t* words, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out,
+                              int32_t* ids, int32_t cap, int32_t* counters, hipStream_t s) {
+  if (n < 0 || n > kScanMax) return hipErrorInvalidValue;
+  const int64_t nb = std::max<int64_t>((n + kScanBlock - 1) / kScanBlock, 1);
+  hipLaunchKernelGGL(k_block_totals<LoadPop>, dim3((unsigned)nb), dim3(kThreads), 0, s, LoadPop{words}, n, tmp);
+  hipLaunchKernelGGL(k_block_apply_emit, dim3((unsigned)nb), dim3(kThreads), 0, s, words, n, (const int32_t*)tmp, out,
+                     total_out, nb, ids, cap, counters);
+  return hipGetLastError();
 }
 
 hipError_t scan_exclusive2(const int32_t* a, int32_t* a_out, int64_t na, const int32_t* c, int32_t* c_out, int64_t nc,
