@@ -107,8 +107,9 @@ void ftc_cells_destroy(ftc_cells* cells);
 ftc_status ftc_build_cell_lists(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
                                 void* stream);
 
-/* Copy the interfacial-cell and pair counts of the last build to the host.
-   Synchronises `stream`. */
+/* Copy the interfacial-cell and pair counts of the last build to the host,
+   each clamped to its capacity (a build that exceeded one has latched
+   FTC_ECAPACITY and its lists are truncated).  Synchronises `stream`. */
 ftc_status ftc_cells_count(const ftc_cells* cells, int32_t* n_interfacial /*[host]*/,
                            int64_t* n_pairs /*[host]*/, void* stream);
 

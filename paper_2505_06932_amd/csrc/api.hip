@@ -204,8 +204,10 @@ ftc_status ftc_cells_count(const ftc_cells* cells, int32_t* n_interfacial, int64
   hipError_t e = hipMemcpyAsync(h, cells->counters, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream);
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return FTC_EHIP;
-  if (n_interfacial) *n_interfacial = h[ftc::C_NIF];
-  if (n_pairs) *n_pairs = h[ftc::C_NPAIRS];
+  // clamped to the capacities: past them the lists are truncated (and
+  // FTC_ECAPACITY is latched), so no reader goes past a buffer
+  if (n_interfacial) *n_interfacial = std::min<int32_t>(h[ftc::C_NIF], cells->cell_cap);
+  if (n_pairs) *n_pairs = std::min<int64_t>(h[ftc::C_NPAIRS], cells->pair_cap);
   return FTC_OK;
 }
 

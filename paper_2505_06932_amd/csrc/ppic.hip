@@ -860,8 +860,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     const int wrounds = wave_max_i((cnt + G - 1) / G);
     const int4* lt = A.wl_tri + (int64_t)(act ? c : 0) * kFitList;
     const double* lw = A.wl_w + (int64_t)(act ? c : 0) * kFitList;
-    // entries of the next round are loaded while this round is computed
-    int4 tn = lt[gl < cnt ? gl : 0];
+    // entries of the next round are loaded while this round is computed; a
+    // lane past the list (or a cell with an empty list, whose entries were
+    // never written) takes vertex 0 with weight 0
+    const int4 kNone = make_int4(0, 0, 0, 0);
+    int4 tn = gl < cnt ? lt[gl] : kNone;
     double wn = gl < cnt ? lw[gl] : 0.0;
     for (int k = 0; k < wrounds; ++k) {
       const int j = k * G + gl;
@@ -869,7 +872,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       const double w = wn;
       if (k + 1 < wrounds) {
         const int jn = j + G;
-        tn = lt[jn < cnt ? jn : 0];
+        tn = jn < cnt ? lt[jn] : kNone;
         wn = jn < cnt ? lw[jn] : 0.0;
       }
       const int32_t cr[3] = {t4.x, t4.y, t4.z};

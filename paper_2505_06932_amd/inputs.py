@@ -336,6 +336,39 @@ def subdivided_cube_mesh(lo, size: float, m: int, rotation=None) -> Mesh:
     return Mesh.from_arrays(v, t)
 
 
+def uv_sphere_mesh(centre, radius: float, n_lat: int, n_lon: int, rotation=None) -> Mesh:
+    """Latitude-longitude sphere: n_lat - 1 rings of n_lon vertices between
+    two poles, quads split into two triangles and a fan of n_lon triangles at
+    each pole, so the poles have valence n_lon (high-valence vertices for the
+    ring capacities).  Optionally rotated by the 3x3 matrix ``rotation``.
+    Closed, outward oriented."""
+    centre = np.asarray(centre, dtype=np.float64)
+    verts = [(0.0, 0.0, 1.0)]
+    for i in range(1, n_lat):
+        th = math.pi * i / n_lat
+        for j in range(n_lon):
+            ph = 2.0 * math.pi * j / n_lon
+            verts.append((math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)))
+    verts.append((0.0, 0.0, -1.0))
+    v = np.array(verts, dtype=np.float64)
+    south = len(verts) - 1
+
+    def ring(i, j):
+        return 1 + (i - 1) * n_lon + (j % n_lon)
+
+    t = []
+    for j in range(n_lon):
+        t.append((0, ring(1, j), ring(1, j + 1)))
+        t.append((south, ring(n_lat - 1, j + 1), ring(n_lat - 1, j)))
+        for i in range(1, n_lat - 1):
+            a, b, c, d = ring(i, j), ring(i + 1, j), ring(i + 1, j + 1), ring(i, j + 1)
+            t += [(a, b, c), (a, c, d)]
+    tris = _orient_outward(v, np.array(t, dtype=np.int64))
+    if rotation is not None:
+        v = v @ np.asarray(rotation, dtype=np.float64).T
+    return Mesh.from_arrays(centre + radius * v, tris)
+
+
 # --------------------------------------------------------------------------
 # staggered face velocities
 # --------------------------------------------------------------------------

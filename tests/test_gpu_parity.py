@@ -211,6 +211,43 @@ def test_coarse_front_support_growth(oracle):
     assert g["diag"][:, 3].max() > 0
 
 
+def test_high_valence_rings_take_the_wide_shape(oracle):
+    """Poles of valence 48: the rings around them exceed the fast kernel's
+    capacities (32 vertices, 64 triangles) and are completed by the 64-lane
+    shape; every cell still matches the oracle exactly."""
+    grid = I.Grid(32, 32, 32, 0.0, 0.0, 0.0, 1.0 / 32)
+    mesh = I.uv_sphere_mesh([0.513, 0.493, 0.503], 0.3, 24, 48)
+    step, g, o = run_pair(oracle, "uv sphere 48", grid, mesh)
+    check_lists(g, o)
+    check_alpha(g, o)
+    check_ppic(g, o, grid.h)
+    assert (o["diag"][:, 1] > 64).sum() > 0  # rings beyond the fast capacities were present
+
+
+def test_rings_beyond_every_capacity_are_flagged(oracle):
+    """Poles of valence 300: rings around them exceed even the 64-lane shape
+    (256 vertices, 512 triangles).  Those cells report the overflow status
+    with NaN results; every other cell matches the oracle."""
+    from paper_2505_06932_amd import ftc
+    grid = I.Grid(32, 32, 32, 0.0, 0.0, 0.0, 1.0 / 32)
+    mesh = I.uv_sphere_mesh([0.513, 0.493, 0.503], 0.3, 24, 300)
+    step, g, o = run_pair(oracle, "uv sphere 300", grid, mesh)
+    check_lists(g, o)
+    check_alpha(g, o)
+    ovf = (g["status"] & ftc.FTC_CELL_OVERFLOW) != 0
+    assert ovf.sum() > 0
+    assert np.all(o["diag"][ovf, 1] > 64)  # only large rings overflow
+    assert np.all(np.isnan(g["kappa"][ovf]))
+    assert np.array_equal(g["diag"][:, 0], o["diag"][:, 0])  # closest vertex of every cell
+    keep = ~ovf
+    assert np.array_equal(g["diag"][keep], o["diag"][keep])
+    assert np.array_equal(g["status"][keep], o["status"][keep])
+    ok = keep & (o["status"] == 0)
+    kg, ko = g["kappa"][ok], o["kappa"][ok]
+    assert np.all(np.abs(kg - ko) <= KAPPA_TOL * np.abs(ko))
+    assert (o["diag"][ok, 1] > 64).sum() > 0  # some wide-shape cells completed normally
+
+
 def test_nondefault_fit_parameters(oracle):
     from paper_2505_06932_amd import ftc
     import oracle as O
