@@ -31,10 +31,11 @@ METRIC = "interfacial cells/s (volume fraction+PPIC curvature), err vs FP64 orac
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic FP64 operations of the PPIC kernel (see the design doc for the
-# count): per ring triangle (centre distance), per weighted triangle (weight,
-# projection, moments, normal-equation update), per cell (vertex normal,
-# frame, 6x6 Cholesky with one refinement step, curvature, normal).
+# Algorithmic FP64 operations of the PPIC curvature call (its four kernels
+# are timed together): per ring triangle (centre distance), per weighted
+# triangle (weight, projection, moments, normal-equation update), per cell
+# (vertex normal, frame, 6x6 Cholesky with one refinement step, curvature,
+# normal).
 FLOP_PER_RING_TRI = 17
 FLOP_PER_FIT_TRI = 187
 FLOP_PER_CELL = 530
@@ -159,7 +160,8 @@ def main():
             t = json.load(f)
         if t.get("source_digest") == digest:
             traffic = t.get("bytes_per_launch")
-    roofline = {"kernel": "k_ppic", "bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
+    roofline = {"kernel": "ppic_curvature: k_ppic (ring pass) + k_ppic_fit + k_ppic (wide shape) + k_ppic_solve",
+                "bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": traffic,
                 "flop_per_launch": flops, "avg_launch_ms": kern_ms["ppic"], "source_digest": digest}
 

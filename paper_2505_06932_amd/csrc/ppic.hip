@@ -293,7 +293,7 @@ struct PPICArgs {
 template <class C>
 struct RingMem {
   int32_t hkey[C::HS];    // hash set of vertices: -1 empty, v new in this ring, v | kPlaced in V
-  int32_t hval[C::HS];    // first occurrence (3 x position + corner) of a new vertex
+  int32_t hval[C::HS];    // new vertex: first occurrence (3 x position + corner); placed: its ring
   int32_t V[C::VC];       // ring vertices
   int32_t Vo[C::VC];      // offset of their incident-triangle lists
   int32_t Vs[C::VC + 1];  // prefix sums of their degrees
@@ -322,36 +322,36 @@ __device__ inline int hslot(int32_t key) {
   return (int)(((uint32_t)key * 2654435761u) >> (32 - ilog2(HS)));
 }
 
-// Insert key (if absent, as a new vertex) and return its slot; -1 if the
-// table is full.
+// Insert a key that is not placed (if absent, as a new vertex) and return
+// its slot; -1 if the table is full.
 template <class C>
 __device__ inline int hinsert(RingMem<C>& M, int32_t key) {
   int s = hslot<C::HS>(key);
 #pragma unroll 1
   for (int p = 0; p < C::HS; ++p) {
     const int32_t prev = atomicCAS(&M.hkey[s], -1, key);
-    if (prev == -1 || prev == key || prev == (key | kPlaced)) return s;
+    if (prev == -1 || prev == key) return s;
     s = (s + 1) & (C::HS - 1);
   }
   return -1;
 }
 
-// Is key a vertex of the previous ring (placed in V)?  home is the table
-// entry at the key's home slot, read beforehand.
+// Ring of the vertex key if it is placed in V (0 for v*), else -1.  home is
+// the table entry at the key's home slot, read beforehand.
 template <class C>
-__device__ inline bool in_ring(const RingMem<C>& M, int32_t key, int32_t home) {
+__device__ inline int ring_of(const RingMem<C>& M, int32_t key, int32_t home) {
   const int32_t placed = key | kPlaced;
-  if (home == placed) return true;
-  if (home == -1 || home == key) return false;
   int s = hslot<C::HS>(key);
+  if (home == placed) return M.hval[s];
+  if (home == -1 || home == key) return -1;
 #pragma unroll 1
   for (int p = 0; p < C::HS; ++p) {
-    const int32_t k = M.hkey[s];
-    if (k == placed) return true;
-    if (k == -1 || k == key) return false;
     s = (s + 1) & (C::HS - 1);
+    const int32_t k = M.hkey[s];
+    if (k == placed) return M.hval[s];
+    if (k == -1 || k == key) return -1;
   }
-  return false;
+  return -1;
 }
 
 // Ballot of this lane's group, in the group's low bits.
@@ -467,6 +467,7 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
     __syncthreads();
     if (ok && gl == 0) {
       RM.hkey[hslot<C::HS>(vs)] = vs | kPlaced;  // empty table
+      RM.hval[hslot<C::HS>(vs)] = 0;
       const int32_t o0 = A.vt_off[vs];
       RM.V[0] = vs;
       RM.Vo[0] = o0;
@@ -477,27 +478,30 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
     int32_t nV = 1, nT = 0;
     bool ovf = false;
     double n0 = 0.0, n1 = 0.0, n2 = 1.0;
+    int32_t nVprev = 0;  // V_{r-2} is V[0, nVprev); the vertices new in V_{r-1} are V[nVprev, nV)
     for (int r = 1; r <= R; ++r) {
       for (int w = gl; w < C::FW; w += G) RM.fbits[w] = 0u;
-      // T_r from the candidates of V_{r-1}, in batches
+      // T_r = T_{r-1} plus the triangles at the vertices new in V_{r-1} with
+      // no corner in V_{r-2}; their candidates f in [flo, fhi), in batches
       const int nVc = min(nV, C::VC);
-      const int tot = (ok && !ovf) ? RM.Vs[nVc] : 0;
+      const bool go_r = ok && !ovf;
+      const int flo = go_r ? RM.Vs[nVprev] : 0, fhi = go_r ? RM.Vs[nVc] : 0;
+      const int tot = fhi - flo;
       const int nb = wave_max_i((tot + C::Batch - 1) / C::Batch);
-      const int prounds = wave_max_i(tot > 0 ? (nVc + G - 1) / G : 0);
-      nT = 0;
+      const int prounds = wave_max_i(tot > 0 ? (nVc - nVprev + G - 1) / G : 0);
       bool full = false;
       for (int b = 0; b < nb; ++b) {
-        const int b0 = b * C::Batch;
+        const int b0 = flo + b * C::Batch;
         // owners of the candidates [b0, b0 + Batch)
         for (int k = 0; k < prounds; ++k) {
-          const int p = k * G + gl;
+          const int p = nVprev + k * G + gl;
           if (tot > 0 && p < nVc) {
             const int lo = max(RM.Vs[p], b0), hi = min(RM.Vs[p + 1], b0 + C::Batch);
             for (int f = lo; f < hi; ++f) RM.own[f - b0] = (uint8_t)p;
           }
         }
         __syncthreads();
-        const int kact = wave_max_i(min(C::CR, max(0, (tot - b0 + G - 1) / G)));
+        const int kact = wave_max_i(min(C::CR, max(0, (fhi - b0 + G - 1) / G)));
         int32_t ct[C::CR], cu[C::CR];
 #pragma unroll
         for (int k = 0; k < C::CR; ++k) {
@@ -505,7 +509,7 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
           cu[k] = -1;
           if (k < kact) {
             const int f = b0 + k * G + gl;
-            if (f < tot) {
+            if (f < fhi) {
               const int p = RM.own[f - b0];
               cu[k] = RM.V[p];
               ct[k] = A.vt_ids[RM.Vo[p] + (f - RM.Vs[p])];
@@ -516,22 +520,31 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
 #pragma unroll
         for (int k = 0; k < C::CR; ++k)
           if (k < kact) cc[k] = A.tri4[ct[k] >= 0 ? ct[k] : 0];
-        // a triangle is kept from the first of its corners in V_{r-1}: every
-        // corner before the owner must lie outside V_{r-1}
-        int32_t hk0[C::CR], hk1[C::CR];
+        // kept from the first of its corners that is new in V_{r-1}: corners
+        // before the owner lie outside V_{r-1}, corners after it outside
+        // V_{r-2}
+        int32_t hk0[C::CR], hk1[C::CR], hk2[C::CR];
 #pragma unroll
         for (int k = 0; k < C::CR; ++k)
           if (k < kact) {
             hk0[k] = RM.hkey[hslot<C::HS>(cc[k].x)];
             hk1[k] = RM.hkey[hslot<C::HS>(cc[k].y)];
+            hk2[k] = RM.hkey[hslot<C::HS>(cc[k].z)];
           }
 #pragma unroll
         for (int k = 0; k < C::CR; ++k)
           if (k < kact) {
             bool keep = ct[k] >= 0;
-            if (keep && r > 1 && cc[k].x != cu[k]) {
-              keep = !in_ring<C>(RM, cc[k].x, hk0[k]);
-              if (keep && cc[k].y != cu[k]) keep = !in_ring<C>(RM, cc[k].y, hk1[k]);
+            int l0 = -1, l1 = -1, l2 = -1;  // rings of the corners, -1 outside V_{r-1}
+            if (keep) {
+              const int eu = cc[k].x == cu[k] ? 0 : (cc[k].y == cu[k] ? 1 : 2);
+              l0 = eu == 0 ? r - 1 : ring_of<C>(RM, cc[k].x, hk0[k]);
+              l1 = eu == 1 ? r - 1 : ring_of<C>(RM, cc[k].y, hk1[k]);
+              l2 = eu == 2 ? r - 1 : ring_of<C>(RM, cc[k].z, hk2[k]);
+              if (eu >= 1 && l0 >= 0) keep = false;
+              if (eu >= 2 && l1 >= 0) keep = false;
+              if (eu < 1 && l1 >= 0 && l1 < r - 1) keep = false;
+              if (eu < 2 && l2 >= 0 && l2 < r - 1) keep = false;
             }
             const uint64_t bal = gballot<G>(keep, grp);
             if (keep) {
@@ -539,10 +552,13 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
               if (pos < C::TC) {
                 CM.T[pos] = ct[k];
                 if (r < R) {
-                  // the corners enter the table, marked with their first occurrence
+                  // corners outside V_{r-1} enter the table, marked with
+                  // their first occurrence
                   const int32_t cr[3] = {cc[k].x, cc[k].y, cc[k].z};
+                  const int lv[3] = {l0, l1, l2};
 #pragma unroll
                   for (int e = 0; e < 3; ++e) {
+                    if (lv[e] >= 0) continue;
                     const int s = hinsert<C>(RM, cr[e]);
                     if (s >= 0)
                       atomicMin(&RM.hval[s], 3 * pos + e);
@@ -615,10 +631,12 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
             RM.Vs[pos + 1] = A.vt_off[key + 1] - o0;  // degree, turned into a prefix sum below
           }
           RM.hkey[s] = key | kPlaced;
+          RM.hval[s] = r;
         }
       }
       const int nV0 = nV;
       if (go) nV += nnew;
+      nVprev = nV0;
       if (nV > C::VC) ovf = true;
       __syncthreads();
       // prefix sums of the new degrees, in place
