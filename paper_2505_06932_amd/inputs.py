@@ -31,7 +31,8 @@ import numpy as np
 
 __all__ = [
     "Grid", "Mesh", "icosahedron", "icosphere", "geodesic_sphere",
-    "sphere_workload", "polar_revolution_workload", "box_mesh", "tetra_mesh",
+    "sphere_workload", "polar_revolution_workload", "ellipsoids_workload",
+    "random_rotation", "box_mesh", "tetra_mesh",
     "subdivided_cube_mesh", "psi_face_velocity", "uniform_face_velocity",
     "affine_face_velocity", "mesh_edges_ok", "WORKLOADS",
 ]
@@ -254,14 +255,80 @@ def polar_revolution_workload(n: int, radius: float, freq: int, seed: int,
     return grid, Mesh.from_arrays(verts, tris), centre
 
 
+def random_rotation(rng: np.random.Generator) -> np.ndarray:
+    """Uniformly distributed rotation matrix from a uniform unit quaternion
+    (Shoemake, "Uniform random rotations", Graphics Gems III, 1992): three
+    draws u1, u2, u3 of U[0, 1)."""
+    u1, u2, u3 = rng.uniform(0.0, 1.0, size=3)
+    a, b = math.sqrt(1.0 - u1), math.sqrt(u1)
+    x, y = a * math.sin(2 * math.pi * u2), a * math.cos(2 * math.pi * u2)
+    z, w = b * math.sin(2 * math.pi * u3), b * math.cos(2 * math.pi * u3)
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def ellipsoids_workload(n: int, count: int, seed: int, axis_lo: float = 2.0, axis_hi: float = 12.0,
+                        max_aspect: float = 1.5, gap_over_h: float = 4.0, edge_over_h: float = 0.5,
+                        domain: float = 1.0):
+    """``count`` disjoint ellipsoidal droplets in one mesh on an n^3 grid.
+
+    For each droplet in turn, with ``numpy.random.default_rng(seed)``:
+    semi-axes drawn U[axis_lo h, axis_hi h]^3 until max/min <= max_aspect;
+    an orientation from ``random_rotation``; a centre drawn
+    U[lo, hi]^3 (lo = largest semi-axis + 3h from the domain walls) until
+    its bounding sphere keeps ``gap_over_h`` cells from every earlier one.
+    The surface is the unit geodesic sphere of frequency
+    ceil(1.21 (abc)^(1/3) / (edge_over_h h)) (mean edge near edge_over_h h
+    on the equivalent sphere) mapped by the semi-axes and the rotation, so
+    triangle sizes vary within and between droplets.  Returns the grid, the
+    mesh (droplet after droplet) and a (count, 7) array of centre, semi-axes
+    and frequency per droplet."""
+    h = domain / n
+    rng = np.random.default_rng(seed)
+    cache: dict[int, tuple[np.ndarray, np.ndarray]] = {}
+    verts, tris, info = [], [], []
+    placed: list[tuple[np.ndarray, float]] = []
+    nv = 0
+    for _ in range(count):
+        while True:
+            ax = rng.uniform(axis_lo * h, axis_hi * h, size=3)
+            if ax.max() <= max_aspect * ax.min():
+                break
+        rot = random_rotation(rng)
+        r = float(ax.max())
+        lo, hi = r + 3 * h, domain - r - 3 * h
+        for _attempt in range(100000):
+            c = rng.uniform(lo, hi, size=3)
+            if all(np.linalg.norm(c - c2) >= r + r2 + gap_over_h * h for c2, r2 in placed):
+                break
+        else:
+            raise RuntimeError("could not place the droplets")
+        placed.append((c, r))
+        freq = int(math.ceil(1.21 * float(np.prod(ax)) ** (1.0 / 3.0) / (edge_over_h * h)))
+        if freq not in cache:
+            cache[freq] = geodesic_sphere(freq)
+        unit, t = cache[freq]
+        verts.append(c[None, :] + (unit * ax[None, :]) @ rot.T)
+        tris.append(t + nv)
+        nv += len(unit)
+        info.append([*c, *ax, freq])
+    grid = Grid(n, n, n, 0.0, 0.0, 0.0, h)
+    return grid, Mesh.from_arrays(np.concatenate(verts), np.concatenate(tris)), np.array(info)
+
+
 #: Named workloads: (builder, kwargs).  "sphere_32" is the small plain-FP64
 #: case (R = 0.25, 4 subdivisions, 5,120 triangles, 32^3); "sphere_128" is the
 #: 128^3 sphere of R = 0.3 with 6 subdivisions (81,920 triangles) and radial
-#: noise of 0.01 h; "revolution_512" is the 512^3 surface of revolution with
-#: 1,997,120 triangles.
+#: noise of 0.01 h; "ellipsoids_256" is 64 disjoint ellipsoidal droplets on
+#: 256^3 with edges near h/2; "revolution_512" is the 512^3 surface of
+#: revolution with 1,997,120 triangles.
 WORKLOADS = {
     "sphere_32": (sphere_workload, dict(n=32, radius=0.25, subdivisions=4, noise_over_h=0.0)),
     "sphere_128": (sphere_workload, dict(n=128, radius=0.3, subdivisions=6, noise_over_h=0.01)),
+    "ellipsoids_256": (ellipsoids_workload, dict(n=256, count=64)),
     "revolution_512": (polar_revolution_workload, dict(n=512, radius=0.2, freq=316)),
 }
 

@@ -111,6 +111,66 @@ def test_sphere_workloads_full_parity(oracle, name, seed):
     assert abs(np.mean(g["kappa"]) * R / 2 - 1) < 0.02
 
 
+# ---------------------------------------------------------------- large configurations
+@pytest.mark.timeout(300)
+def test_batched_ellipsoids_full_parity(oracle):
+    """64 disjoint ellipsoids of uneven size and triangle density on 256^3,
+    one mesh and one call per step: every output of every cell against the
+    oracle, and the total volume against the sum of the droplets' enclosed
+    polyhedron volumes."""
+    grid, mesh, info = I.make_workload("ellipsoids_256", 0)
+    U, V, W = I.psi_face_velocity(grid)
+    step, g, o = run_pair(oracle, "ellipsoids_256/0", grid, mesh, U, V, W, sigma=1.0)
+    check_lists(g, o)
+    check_alpha(g, o)
+    check_ppic(g, o, grid.h)
+    check_force(g, o)
+    umax = np.abs(o["u"]).max()
+    assert np.abs(g["u"] - o["u"]).max() <= 1e-12 * umax
+    verts, tris = mesh.verts(), mesh.tris()
+    vpoly, start = 0.0, 0
+    for row in info:
+        f = int(row[6])
+        ntd = 20 * f * f
+        vpoly += pins.polyhedron_volume(verts, tris[start:start + ntd], origin=row[:3])
+        start += ntd
+    assert start == mesh.nt
+    assert abs(math.fsum(g["alpha"].ravel()) * grid.h ** 3 - vpoly) <= 1e-12 * vpoly
+
+
+@pytest.mark.timeout(300)
+def test_large_surface_of_revolution_sampled_parity(oracle):
+    """The 512^3 surface of revolution with 1,997,120 triangles, in the
+    configuration the benchmark times: cell lists and the dense volume
+    fractions exactly against the oracle, curvature, normals, diagnostics
+    and forces on a seeded sample of 4,096 interfacial cells, vertex
+    velocities at every vertex."""
+    grid, mesh, c = I.make_workload("revolution_512", 0)
+    U, V, W = I.psi_face_velocity(grid)
+    _say(f"[gpu parity] case=revolution_512/0 nv={mesh.nv} nt={mesh.nt}")
+    pipeline = _gpu()
+    step = pipeline.CouplingStep(grid, mesh, U, V, W, sigma=1.0)
+    step.run(diagnostics=True)
+    g = step.results()
+    _say(f"[gpu parity] case=revolution_512/0 n_if={g['n_if']} pairs={g['n_pairs']} err={g['error']}")
+    o = {}
+    o["cells"], o["offsets"], o["tris"] = oracle.cell_lists(grid, mesh)
+    check_lists(g, o)
+    o["alpha"], _ = oracle.volume_fraction(grid, mesh)
+    check_alpha(g, o)
+    vpoly = pins.polyhedron_volume(mesh.verts(), mesh.tris(), origin=c)
+    assert abs(math.fsum(g["alpha"].ravel()) * grid.h ** 3 - vpoly) <= 1e-12 * vpoly
+    pick = np.sort(np.random.default_rng(7).choice(g["n_if"], 4096, replace=False))
+    cells = o["cells"][pick]
+    r = oracle.ppic(grid, mesh, cells)
+    sub = {k: g[k][pick] for k in ("kappa", "normal", "coeff", "status", "diag")}
+    check_ppic(sub, r, grid.h)
+    f = oracle.csf(grid, o["alpha"], cells, r["kappa"], 1.0)
+    check_force({"force": g["force"][pick]}, {"force": f, "status": r["status"]})
+    u = oracle.interp(grid, mesh.x, mesh.y, mesh.z, U, V, W)
+    assert np.abs(g["u"] - u).max() <= 1e-12 * np.abs(u).max()
+
+
 def test_determinism_bitwise(oracle):
     grid, mesh, _ = I.make_workload("sphere_32", 3)
     pipeline = _gpu()

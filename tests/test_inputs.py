@@ -51,3 +51,39 @@ def test_psi_field_discretely_divergence_free():
     U, V, W = I.psi_face_velocity(g)
     div = (U[:, :, 1:] - U[:, :, :-1] + V[:, 1:, :] - V[:, :-1, :] + W[1:] - W[:-1]) / g.h
     assert np.abs(div).max() < 1e-12
+
+
+def test_ellipsoid_droplets_as_drawn():
+    g, m, info = I.make_workload("ellipsoids_256", seed=0)
+    g2, m2, info2 = I.make_workload("ellipsoids_256", seed=0)
+    assert np.array_equal(m.x, m2.x) and np.array_equal(info, info2)
+    assert g.nx == 256 and len(info) == 64
+    c, ax, f = info[:, :3], info[:, 3:6], info[:, 6].astype(int)
+    assert np.all(ax >= 2 * g.h) and np.all(ax <= 12 * g.h)
+    assert np.all(ax.max(1) <= 1.5 * ax.min(1))
+    r = ax.max(1)
+    d = np.linalg.norm(c[:, None] - c[None], axis=2) - r[:, None] - r[None]
+    np.fill_diagonal(d, np.inf)
+    assert d.min() >= 4 * g.h  # bounding spheres keep 4 cells apart
+    assert np.all(c - r[:, None] >= 3 * g.h) and np.all(c + r[:, None] <= 1 - 3 * g.h)
+    assert m.nt == int((20 * f * f).sum()) and m.nv == int((10 * f * f + 2).sum())
+    assert I.mesh_edges_ok(m)
+    # every droplet is its affinely mapped geodesic sphere: vertices on the
+    # ellipsoid surface, outward orientation
+    v, t, s = m.verts(), m.tris(), 0
+    for k in range(64):
+        nvk = 10 * f[k] ** 2 + 2
+        ntk = 20 * f[k] ** 2
+        assert polyhedron_volume(v, t[s:s + ntk], origin=c[k]) > 0
+        s += ntk
+    # mean edge near h/2 overall
+    e = np.linalg.norm(v[t[:, 0]] - v[t[:, 1]], axis=1)
+    assert 0.35 * g.h < e.mean() < 0.65 * g.h
+
+
+def test_random_rotation_is_proper_orthogonal():
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        R = I.random_rotation(rng)
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-14)
+        assert abs(np.linalg.det(R) - 1) < 1e-14

@@ -36,6 +36,26 @@ def test_total_volume_equals_enclosed_volume(oracle, name, seed):
     assert abs(vpoly / (4.0 / 3.0 * math.pi * R ** 3) - 1.0) < 3e-3
 
 
+def test_total_volume_of_batched_droplets(oracle):
+    """64 disjoint ellipsoids in one mesh: sum(alpha) h^3 equals the sum of
+    the droplets' enclosed polyhedron volumes to 1e-12 relative.  Each
+    droplet's polyhedron is inscribed in its ellipsoid (convex hull of points
+    on it), so its volume lies below 4/3 pi abc, by at most the coarse
+    faceting's few tenths of a percent."""
+    g, m, info = I.make_workload("ellipsoids_256", 0)
+    alpha, _ = oracle.volume_fraction(g, m)
+    v, t, s, vpoly = m.verts(), m.tris(), 0, 0.0
+    for row in info:
+        ntk = 20 * int(row[6]) ** 2
+        vk = pins.polyhedron_volume(v, t[s:s + ntk], origin=row[:3])
+        deficit = 1.0 - vk / (4.0 / 3.0 * math.pi * np.prod(row[3:6]))
+        assert 0.0 < deficit < 2e-2
+        vpoly += vk
+        s += ntk
+    total = math.fsum(alpha.ravel()) * g.h ** 3
+    assert abs(total - vpoly) <= 1e-12 * vpoly
+
+
 # ---------------------------------------------------------------- P-alpha2
 @pytest.mark.parametrize("seed", range(6))
 def test_box_volume_fraction_is_product_of_overlaps(oracle, seed):
