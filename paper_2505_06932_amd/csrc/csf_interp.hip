@@ -7,7 +7,7 @@
 namespace ftc {
 namespace {
 
-constexpr int kT = 256;
+constexpr int kT = 64;  // one wavefront per workgroup: small launches spread over every CU
 
 __global__ __launch_bounds__(kT) void k_csf(Grid g, const int32_t* cell_ids, const double* alpha,
                                             const double* kappa, double sigma, double* fx, double* fy, double* fz,

@@ -65,7 +65,7 @@ __host__ __device__ inline int32_t dim_n(const Grid& g, int d) {
 }
 
 // Grid plane i along an axis: origin + i * h (one product, one sum).
-__device__ inline double grid_plane(double org, int64_t i, double h) { return org + (double)i * h; }
+__host__ __device__ inline double grid_plane(double org, int64_t i, double h) { return org + (double)i * h; }
 
 // Half-open cell index of coordinate x: plane(i) <= x < plane(i+1), exact
 // with respect to grid_plane.
@@ -168,7 +168,7 @@ struct Piece {
 
 // Planes of cell (i, j, k); false if the half-open rule gives the triangle to
 // the next cell (all three corners on an upper plane).
-__device__ inline bool cell_planes(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k, double lo[3],
+__host__ __device__ inline bool cell_planes(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k, double lo[3],
                                    double hi[3]) {
   const int64_t ijk[3] = {i, j, k};
   bool ok = true;
@@ -187,7 +187,7 @@ __device__ inline bool cell_planes(const Grid& g, const Tri& T, int64_t i, int64
 // a stage with every corner strictly outside), 1 = the piece is the whole
 // triangle (no stage cuts), 2 = some stage cuts, so the candidate must be
 // clipped.
-__device__ inline int classify_candidate(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k) {
+__host__ __device__ inline int classify_candidate(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k) {
   double lo[3], hi[3];
   if (!cell_planes(g, T, i, j, k, lo, hi)) return 0;
 #pragma unroll
@@ -206,7 +206,7 @@ __device__ inline int classify_candidate(const Grid& g, const Tri& T, int64_t i,
 // Fan integrals of a polygon given by corner accessors (corner 0 is the fan
 // apex): membership by the vector area, flux and vol by the z-column rule.
 template <class CX>
-__device__ inline Piece fan_piece(int n, double zlo, CX cx) {
+__host__ __device__ inline Piece fan_piece(int n, double zlo, CX cx) {
   Piece out{false, 0.0, 0.0};
   if (n < 3) return out;
   const double x0 = cx(0, 0), y0 = cx(0, 1), z0 = cx(0, 2);
@@ -237,7 +237,7 @@ __device__ inline Piece fan_piece(int n, double zlo, CX cx) {
 
 // Piece of a candidate of class 1: the triangle itself (after six stages
 // that cut nothing the corner order is back to t0, t1, t2).
-__device__ inline Piece whole_piece(const Tri& T, double zlo) {
+__host__ __device__ inline Piece whole_piece(const Tri& T, double zlo) {
   return fan_piece(3, zlo, [&](int q, int d) { return q == 0 ? T.v[0][d] : (q == 1 ? T.v[1][d] : T.v[2][d]); });
 }
 
@@ -247,12 +247,25 @@ struct PolyLDS {
   double v[3][kMaxPoly][LANES];
 };
 
-// Full clipping of a candidate.  The polygon is held in registers in
-// polygon order (static slots); a stage that cuts emits its output into the
-// lane's LDS buffer (dynamic positions) and reloads it.
+// One of three values by a run-time index, without indexing registers.
+__host__ __device__ inline double sel3(int d, double a, double b, double c) { return d == 0 ? a : (d == 1 ? b : c); }
+
+// Full clipping of a candidate.  The polygon lives in registers (static
+// physical slots) with a copy in the lane's LDS buffer for reads at dynamic
+// positions.  Logical corner i (polygon order) is physical slot
+// (i + rot) mod n, so a stage that cuts nothing only advances rot.  A stage
+// that cuts takes one of two routes with identical results:
+//  * the inside corners form one cyclic run (the case of a convex polygon):
+//    exactly two edges cross the plane; their cut points are computed from
+//    endpoints read from LDS, and each output corner is written to its
+//    position in the emission order, counted with bit masks over the edges;
+//  * otherwise (possible only through rounding): the corners are brought
+//    into logical order and every edge is processed in turn.
+// Either way the output is the stage's emission sequence (first kMaxPoly
+// corners), stored to LDS at positions 0.. and reloaded with rot = 0.
 template <int LANES>
-__device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k,
-                                   PolyLDS<LANES>& L, int lane) {
+__host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k,
+                                            PolyLDS<LANES>& L, int lane) {
   Piece none{false, 0.0, 0.0};
   double lo[3], hi[3];
   if (!cell_planes(g, T, i, j, k, lo, hi)) return none;
@@ -260,77 +273,153 @@ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t i, int64
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
-    for (int q = 0; q < kMaxPoly; ++q) P[d][q] = q < 3 ? T.v[q][d] : 0.0;
-  int n = 3;
-#pragma unroll
+    for (int q = 0; q < kMaxPoly; ++q) {
+      P[d][q] = q < 3 ? T.v[q][d] : 0.0;
+      if (q < 3) L.v[d][q][lane] = T.v[q][d];
+    }
+  int n = 3, rot = 0;
+#pragma unroll 1
   for (int stage = 0; stage < 6; ++stage) {
     const int d = stage >> 1;
     const bool upper = stage & 1;
-    const double c = upper ? hi[d] : lo[d];
-    bool all_in = true, all_out = true;
+    const double c = upper ? sel3(d, hi[0], hi[1], hi[2]) : sel3(d, lo[0], lo[1], lo[2]);
+    uint32_t mp = 0;  // inside corners by physical slot
 #pragma unroll
     for (int q = 0; q < kMaxPoly; ++q) {
-      if (q < n) {
-        const bool in = upper ? (P[d][q] <= c) : (P[d][q] >= c);
-        all_in = all_in && in;
-        all_out = all_out && !in;
-      }
+      const double x = sel3(d, P[0][q], P[1][q], P[2][q]);
+      if (q < n && (upper ? (x <= c) : (x >= c))) mp |= 1u << q;
     }
-    if (all_out) return none;
-    if (all_in) {
-      // rotate by one corner
-#pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        const double first = P[f][0];
-#pragma unroll
-        for (int q = 0; q + 1 < kMaxPoly; ++q) P[f][q] = (q + 1 < n) ? P[f][q + 1] : (q + 1 == n ? first : P[f][q]);
-        if (n == kMaxPoly) P[f][kMaxPoly - 1] = first;
-      }
+    const uint32_t full = (1u << n) - 1u;
+    if (mp == 0u) return none;
+    if (mp == full) {
+      rot = rot + 1 == n ? 0 : rot + 1;
       continue;
     }
-    int o = 0;
+    // by logical corner: m (corner e inside), Qm (corner e + 1 inside)
+    const uint32_t m = rot ? (((mp >> rot) | (mp << (n - rot))) & full) : mp;
+    const uint32_t Qm = ((m >> 1) | (m << (n - 1))) & full;
+    if (__builtin_popcount(m ^ Qm) == 2) {
+      const int e_out = __builtin_ctz(m & ~Qm);  // inside -> outside
+      const int e_in = __builtin_ctz(~m & Qm);   // outside -> inside
+      double X[2][3];
+      bool emit[2];
 #pragma unroll
-    for (int e = 0; e < kMaxPoly; ++e) {
-      if (e < n) {
-        // q = corner e + 1, wrapping to corner 0 at the last edge
-        double q0 = P[0][0], q1 = P[1][0], q2 = P[2][0];
-        if (e + 1 < kMaxPoly && e + 1 < n) {
-          q0 = P[0][e + 1];
-          q1 = P[1][e + 1];
-          q2 = P[2][e + 1];
-        }
-        const double pp[3] = {P[0][e], P[1][e], P[2][e]};
-        const double qq[3] = {q0, q1, q2};
-        const double pd = pp[d], qd = qq[d];
-        const bool pin = upper ? (pd <= c) : (pd >= c);
-        const bool qin = upper ? (qd <= c) : (qd >= c);
-        const bool cut = pin != qin && (pin ? pd != c : qd != c);
-        if (cut && o < kMaxPoly) {
-          const bool pa = pd < qd;
-          const double ad = pa ? pd : qd, bd = pa ? qd : pd;
-          const double t = (c - ad) / (bd - ad);
+      for (int s = 0; s < 2; ++s) {
+        const int e = s ? e_in : e_out;
+        int ps = e + rot;
+        if (ps >= n) ps -= n;
+        const int qs = ps + 1 == n ? 0 : ps + 1;
+        double pp[3], qq[3];
 #pragma unroll
-          for (int f = 0; f < 3; ++f) {
-            const double af = pa ? pp[f] : qq[f], bf = pa ? qq[f] : pp[f];
-            L.v[f][o][lane] = (f == d) ? c : af + t * (bf - af);
-          }
-          ++o;
+        for (int f = 0; f < 3; ++f) {
+          pp[f] = L.v[f][ps][lane];
+          qq[f] = L.v[f][qs][lane];
         }
-        if (qin && o < kMaxPoly) {
-          L.v[0][o][lane] = q0;
-          L.v[1][o][lane] = q1;
-          L.v[2][o][lane] = q2;
-          ++o;
+        const double pd = sel3(d, pp[0], pp[1], pp[2]), qd = sel3(d, qq[0], qq[1], qq[2]);
+        // no cut point where the inside end lies on the plane
+        emit[s] = s ? qd != c : pd != c;
+        const bool pa = pd < qd;
+        const double ad = pa ? pd : qd, bd = pa ? qd : pd;
+        const double t = (c - ad) / (bd - ad);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+          const double af = pa ? pp[f] : qq[f], bf = pa ? qq[f] : pp[f];
+          X[s][f] = (f == d) ? c : af + t * (bf - af);
         }
       }
+      const uint32_t C = ((uint32_t)emit[0] << e_out) | ((uint32_t)emit[1] << e_in);
+      // corner i = e + 1 of edge e follows the cut point of edge e
+#pragma unroll
+      for (int q = 0; q < kMaxPoly; ++q) {
+        if (q < n && ((mp >> q) & 1u)) {
+          int li = q - rot;
+          if (li < 0) li += n;
+          const int e = li == 0 ? n - 1 : li - 1;
+          const int pos = __builtin_popcount(C & ((2u << e) - 1u)) + __builtin_popcount(Qm & ((1u << e) - 1u));
+          if (pos < kMaxPoly) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) L.v[f][pos][lane] = P[f][q];
+          }
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int e = s ? e_in : e_out;
+        const int pos = __builtin_popcount(C & ((1u << e) - 1u)) + __builtin_popcount(Qm & ((1u << e) - 1u));
+        if (emit[s] && pos < kMaxPoly) {
+#pragma unroll
+          for (int f = 0; f < 3; ++f) L.v[f][pos][lane] = X[s][f];
+        }
+      }
+      n = __builtin_popcount(m) + __builtin_popcount(C);
+      if (n > kMaxPoly) n = kMaxPoly;
+    } else {
+      // logical order in registers, then every edge in turn
+      if (rot) {
+#pragma unroll
+        for (int q = 0; q < kMaxPoly; ++q) {
+          int ps = q + rot;
+          if (ps >= n) ps -= n;
+          if (q < n) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f) P[f][q] = L.v[f][ps][lane];
+          }
+        }
+      }
+      int o = 0;
+#pragma unroll
+      for (int e = 0; e < kMaxPoly; ++e) {
+        if (e < n) {
+          double q0 = P[0][0], q1 = P[1][0], q2 = P[2][0];
+          if (e + 1 < kMaxPoly && e + 1 < n) {
+            q0 = P[0][e + 1];
+            q1 = P[1][e + 1];
+            q2 = P[2][e + 1];
+          }
+          const double pp[3] = {P[0][e], P[1][e], P[2][e]};
+          const double qq[3] = {q0, q1, q2};
+          const double pd = sel3(d, pp[0], pp[1], pp[2]), qd = sel3(d, qq[0], qq[1], qq[2]);
+          const bool pin = upper ? (pd <= c) : (pd >= c);
+          const bool qin = upper ? (qd <= c) : (qd >= c);
+          const bool cut = pin != qin && (pin ? pd != c : qd != c);
+          if (cut && o < kMaxPoly) {
+            const bool pa = pd < qd;
+            const double ad = pa ? pd : qd, bd = pa ? qd : pd;
+            const double t = (c - ad) / (bd - ad);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+              const double af = pa ? pp[f] : qq[f], bf = pa ? qq[f] : pp[f];
+              L.v[f][o][lane] = (f == d) ? c : af + t * (bf - af);
+            }
+            ++o;
+          }
+          if (qin && o < kMaxPoly) {
+            L.v[0][o][lane] = q0;
+            L.v[1][o][lane] = q1;
+            L.v[2][o][lane] = q2;
+            ++o;
+          }
+        }
+      }
+      n = o;
+      if (n == 0) return none;
     }
-    n = o;
-    if (n == 0) return none;
+    rot = 0;
 #pragma unroll
     for (int f = 0; f < 3; ++f)
 #pragma unroll
-      for (int q = 0; q < kMaxPoly; ++q)
-        if (q < n) P[f][q] = L.v[f][q][lane];
+      for (int q = 0; q < kMaxPoly; ++q) P[f][q] = L.v[f][q][lane];
+  }
+  if (rot) {
+#pragma unroll
+    for (int q = 0; q < kMaxPoly; ++q) {
+      int ps = q + rot;
+      if (ps >= n) ps -= n;
+      if (q < n) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) P[f][q] = L.v[f][ps][lane];
+      }
+    }
   }
   return fan_piece(n, lo[2], [&](int q, int d) { return P[d][q]; });
 }

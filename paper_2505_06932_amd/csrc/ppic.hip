@@ -13,35 +13,43 @@
 //     cell centre, so a best squared distance below (1.5 h)^2 is final; any
 //     other cell searches all vertices in the main kernel.
 //
-// Main kernel, one template for two shapes: the fast shape gives 8 lanes to
-// each interfacial cell (8 cells per wavefront) and holds rings of up to 32
-// vertices and 64 triangles in LDS; cells whose ring is larger are queued
-// for the wide shape (64 lanes per cell, rings of 256 vertices and 512
-// triangles), launched right after it.  Cells are assigned so that each XCD
+// Ring pass (k_ppic), one template for two shapes: the fast shape gives 8
+// lanes to each interfacial cell (8 cells per wavefront) and holds rings of
+// up to 32 vertices and 64 triangles in LDS; cells whose ring is larger are
+// queued for the wide shape (64 lanes per cell, rings of 256 vertices and
+// 512 triangles), launched after it.  Cells are assigned so that each XCD
 // processes a contiguous range, which keeps each L2 on one part of the front.
 //   1. ring neighbourhood: V_0 = {v*}; T_r = triangles with a corner in
-//      V_{r-1}; V_r = V_{r-1} plus the corners of T_r.  The (vertex,
-//      incident triangle) candidates of a ring are spread over the lanes
-//      through prefix sums of the vertex degrees.  A triangle is taken once,
-//      from the first of its corners (t0, t1, t2 order) that lies in
-//      V_{r-1}.  Membership uses an open-addressing hash table; the corners
-//      of each kept triangle enter the table at once, marked with their
-//      first occurrence (3 x position + corner), and are then placed in
-//      V_r in that order;
+//      V_{r-1}; V_r = V_{r-1} plus the corners of T_r.  Built incrementally:
+//      a triangle with a corner in V_{r-2} is already in T_{r-1}, so the
+//      candidates of ring r are the incident triangles of the vertices new
+//      in V_{r-1}, spread over the lanes through prefix sums of their
+//      degrees.  A candidate is kept from the first of its corners (t0, t1,
+//      t2 order) that is new in V_{r-1}, and only if none of its corners lies
+//      in V_{r-2}; the ring level of every placed vertex is stored with it in
+//      an open-addressing hash table in LDS.  Corners of kept triangles that
+//      are not yet placed enter the table at once, marked with their first
+//      occurrence (3 x position + corner), and are then placed in V_r in that
+//      order;
 //   2. normal of v* (area-weighted, summed in ascending triangle order: T_1
 //      is v*'s incident list) and a right-handed tangent frame (Duff et al.,
 //      JCGT 2017);
 //   3. triangle-centre distances, the support radius grown by `grow` until
 //      `n_min` triangles fall inside (or the ring is exhausted, or
-//      `max_iter` adjustments), Wendland weights of the triangles inside,
-//      which are compacted into a list;
+//      `max_iter` adjustments), Wendland weights of the triangles inside.
+//      The fast shape writes the weighted triangles (packed corners and
+//      weight) to a per-cell list in HBM, with the frame normal and the
+//      count; the wide shape goes on with steps 4 and 5 itself.
+// Fit pass (k_ppic_fit), the cells of the fast shape, 8 lanes per cell:
 //   4. per lane: each listed triangle's projection into the frame
 //      (coordinates divided by h for conditioning), its six moments by the
 //      edge-midpoint rule (exact for quadratics) and the integral of its
 //      plane, and the weighted normal equations M a = b accumulated in
 //      registers; all-reduce over the cell's lanes with row permutations;
-//   5. in-register Cholesky factorisation of the packed M with one step of
-//      iterative refinement, curvature kappa = 2H at the frame origin and the
+//      the 27 sums are stored per cell.
+// Solve pass (k_ppic_solve), one thread per cell:
+//   5. Cholesky factorisation of the packed M with one step of iterative
+//      refinement, curvature kappa = 2H at the frame origin and the
 //      interface normal.
 // Every loop bound is uniform over the wavefront (maxima over its cells), so
 // LDS phases are separated by plain workgroup barriers.
@@ -405,10 +413,119 @@ __device__ inline double div3(double x) {
 // packed index of entry (a, b), a <= b, of a symmetric 6x6 matrix
 __host__ __device__ constexpr int P6(int a, int b) { return a * 6 - a * (a - 1) / 2 + (b - a); }
 
+// One cell, by one thread: Cholesky factorisation of the packed normal
+// matrix (in registers), one step of iterative refinement, the coefficients
+// scaled back from the h-scaled frame, kappa = 2H at the frame origin and
+// the interface normal.  F holds the 31 fit slots (27 sums, frame normal,
+// weighted count) at a stride of fs.
+__device__ inline void solve_cell(const PPICArgs& A, int32_t c, const double* F, int64_t fs) {
+  const int64_t cs = A.cell_cap;
+  const double h = A.g.h, inv_h = 1.0 / h;
+  {
+    const double wcnt = F[30 * fs];
+    const double n0 = F[27 * fs], n1 = F[28 * fs], n2 = F[29 * fs];
+    double co[6] = {NAN, NAN, NAN, NAN, NAN, NAN};
+    double kap = NAN, ni0 = NAN, ni1 = NAN, ni2 = NAN;
+    uint32_t st = wcnt == -1.0 ? FTC_CELL_OVERFLOW : 0u;
+    if (wcnt >= 0.0) {
+      double acc[27];
+#pragma unroll
+      for (int qa = 0; qa < 27; ++qa) acc[qa] = F[qa * fs];
+      const double trace =
+          acc[P6(0, 0)] + acc[P6(1, 1)] + acc[P6(2, 2)] + acc[P6(3, 3)] + acc[P6(4, 4)] + acc[P6(5, 5)];
+      // in place: acc[P6(j, i)] becomes L(i, j) for i >= j
+      bool rank_ok = wcnt >= 6.0;
+      double invd[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        double d = acc[P6(j, j)];
+#pragma unroll
+        for (int p = 0; p < j; ++p) d -= acc[P6(p, j)] * acc[P6(p, j)];
+        if (!(d > 1e-14 * trace)) rank_ok = false;
+        const double ljj = sqrt(fmax(d, DBL_MIN));
+        acc[P6(j, j)] = ljj;
+        const double inv = 1.0 / ljj;
+        invd[j] = inv;
+#pragma unroll
+        for (int i2 = j + 1; i2 < 6; ++i2) {
+          double s2 = acc[P6(j, i2)];
+#pragma unroll
+          for (int p = 0; p < j; ++p) s2 -= acc[P6(p, i2)] * acc[P6(p, j)];
+          acc[P6(j, i2)] = s2 * inv;
+        }
+      }
+      if (!rank_ok) {
+        st |= FTC_CELL_RANK;
+      } else {
+        double ah[6], y[6], r6[6];
+        auto solve = [&](const double* rhs, double* x) {
+#pragma unroll
+          for (int i2 = 0; i2 < 6; ++i2) {
+            double s2 = rhs[i2];
+#pragma unroll
+            for (int p = 0; p < i2; ++p) s2 -= acc[P6(p, i2)] * y[p];
+            y[i2] = s2 * invd[i2];
+          }
+#pragma unroll
+          for (int i2 = 5; i2 >= 0; --i2) {
+            double s2 = y[i2];
+#pragma unroll
+            for (int p = i2 + 1; p < 6; ++p) s2 -= acc[P6(i2, p)] * x[p];
+            x[i2] = s2 * invd[i2];
+          }
+        };
+        solve(acc + 21, ah);
+        // residual with the unfactorised matrix, read again
+#pragma unroll
+        for (int i2 = 0; i2 < 6; ++i2) {
+          double s2 = acc[21 + i2];
+#pragma unroll
+          for (int p = 0; p < 6; ++p) s2 -= F[(i2 <= p ? P6(i2, p) : P6(p, i2)) * fs] * ah[p];
+          r6[i2] = s2;
+        }
+        solve(r6, r6);
+#pragma unroll
+        for (int i2 = 0; i2 < 6; ++i2) ah[i2] += r6[i2];
+        co[0] = h * ah[0];
+        co[1] = ah[1];
+        co[2] = ah[2];
+        co[3] = ah[3] * inv_h;
+        co[4] = ah[4] * inv_h;
+        co[5] = ah[5] * inv_h;
+        const double gx = co[1], gy = co[2];
+        const double num = 2.0 * co[3] * (1.0 + gy * gy) - 2.0 * gx * gy * co[4] + 2.0 * co[5] * (1.0 + gx * gx);
+        const double sq = 1.0 + gx * gx + gy * gy;
+        kap = -num / (sq * sqrt(sq));
+        // the tangents of the frame again (Duff et al.)
+        const double sg = copysign(1.0, n2);
+        const double fa = -1.0 / (sg + n2);
+        const double fb = n0 * n1 * fa;
+        const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
+        const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
+        ni0 = n0 - co[1] * t1x - co[2] * t2x;
+        ni1 = n1 - co[1] * t1y - co[2] * t2y;
+        ni2 = n2 - co[1] * t1z - co[2] * t2z;
+        const double il = 1.0 / sqrt(ni0 * ni0 + ni1 * ni1 + ni2 * ni2);
+        ni0 *= il;
+        ni1 *= il;
+        ni2 *= il;
+      }
+    }
+    A.kappa[c] = kap;
+    A.nx[c] = ni0;
+    A.ny[c] = ni1;
+    A.nz[c] = ni2;
+    if (A.coeff)
+      for (int qa = 0; qa < 6; ++qa) A.coeff[qa * cs + c] = st ? NAN : co[qa];
+    if (A.status) A.status[c] = (int32_t)st;
+  }
+}
+
+// The cells of one shape, processed by workgroup `bid` of `nblk` (64 lanes).
 // kQueue = false: every interfacial cell, overflowing cells queued.
 // kQueue = true: the queued cells.
 template <class C, bool kQueue>
-__global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
+__device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) {
   constexpr int G = C::G, NG = C::NG;
   __shared__ CellMem<C> SM[NG];
   const Grid& g = A.g;
@@ -423,13 +540,13 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
   const double reach2 = reach * reach * (1.0 - 1e-12);
   const uint64_t below_me = (1ull << gl) - 1ull;
   // the closest-vertex pass has read the stray count: reset it for the next call
-  if (!kQueue && blockIdx.x == 0 && threadIdx.x == 0) A.counters[C_NSTRAY] = 0;
+  if (!kQueue && bid == 0 && threadIdx.x == 0) A.counters[C_NSTRAY] = 0;
 
   // each XCD takes a contiguous range of cell groups
   const int32_t ngroups = (nitems + NG - 1) / NG;
   const int32_t per = (ngroups + kXCD - 1) / kXCD;
-  const int32_t xcd = blockIdx.x % kXCD, nj = gridDim.x / kXCD;
-  for (int32_t q = blockIdx.x / kXCD; q < per; q += nj) {
+  const int32_t xcd = bid % kXCD, nj = nblk / kXCD;
+  for (int32_t q = bid / kXCD; q < per; q += nj) {
     const int32_t gi = xcd * per + q;
     if (gi >= ngroups) break;
     const int32_t item = gi * NG + grp;
@@ -813,9 +930,8 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
 #pragma unroll
     for (int qa = 0; qa < 27; ++qa) acc[qa] = group_sum<G>(acc[qa]);
 
-    // ---- hand the normal equations to the solve pass (weighted count -1:
-    // ring beyond the capacities, -2: no closest vertex)
-    // (staged through LDS so that each lane stores a few slots)
+    // ---- the normal equations (weighted count -1: ring beyond the
+    // capacities, -2: no closest vertex), solved by one lane per cell
     __syncthreads();
     if (gl == 0) {
 #pragma unroll
@@ -826,10 +942,10 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
       FM.W[30] = ok ? (double)cnt : (ovf ? -1.0 : -2.0);
     }
     __syncthreads();
-    if (emit) {
+    if (emit && gl == 0) {
       const int64_t cs = A.cell_cap;
-      for (int qa = gl; qa < 31; qa += G) A.fit[qa * cs + c] = FM.W[qa];
-      if (A.diag && gl == 0) {
+      solve_cell(A, c, FM.W, 1);
+      if (A.diag) {
         A.diag[c] = vs;
         A.diag[cs + c] = nT;
         A.diag[2 * cs + c] = cnt;
@@ -839,6 +955,8 @@ __global__ __launch_bounds__(64) void k_ppic(PPICArgs A) {
     __syncthreads();
   }
 }
+
+__global__ __launch_bounds__(64) void k_ppic_rings(PPICArgs A) { ppic_cells<Fast, false>(A, blockIdx.x, gridDim.x); }
 
 // Weighted moments and normal equations of the cells whose ring fitted the
 // fast shape: 8 lanes per cell (8 cells per wavefront) over the cell's
@@ -942,112 +1060,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   }
 }
 
-// One thread per interfacial cell: Cholesky factorisation of the packed
-// normal matrix (in place), one step of iterative refinement, the
-// coefficients scaled back from the h-scaled frame, kappa = 2H at the frame
-// origin and the interface normal.
-__global__ __launch_bounds__(kT) void k_ppic_solve(PPICArgs A) {
+// Blocks [0, kWideBlocks): the cells queued for the wide shape, each solved
+// in its block; the other blocks: one thread per remaining cell.
+__global__ __launch_bounds__(64) void k_ppic_wide_solve(PPICArgs A) {
+  if ((int32_t)blockIdx.x < kWideBlocks) {
+    ppic_cells<Wide, true>(A, blockIdx.x, kWideBlocks);
+    return;
+  }
   const int32_t nif = min(A.counters[C_NIF], A.cell_cap);
   const int64_t cs = A.cell_cap;
-  const double h = A.g.h, inv_h = 1.0 / h;
-  for (int32_t c = blockIdx.x * kT + threadIdx.x; c < nif; c += gridDim.x * kT) {
+  const int32_t nb = gridDim.x - kWideBlocks;
+  for (int32_t c = (blockIdx.x - kWideBlocks) * 64 + threadIdx.x; c < nif; c += nb * 64) {
     const double* F = A.fit + c;
-    const double wcnt = F[30 * cs];
-    const double n0 = F[27 * cs], n1 = F[28 * cs], n2 = F[29 * cs];
-    double co[6] = {NAN, NAN, NAN, NAN, NAN, NAN};
-    double kap = NAN, ni0 = NAN, ni1 = NAN, ni2 = NAN;
-    uint32_t st = wcnt == -1.0 ? FTC_CELL_OVERFLOW : 0u;
-    if (wcnt >= 0.0) {
-      double acc[27];
-#pragma unroll
-      for (int qa = 0; qa < 27; ++qa) acc[qa] = F[qa * cs];
-      const double trace =
-          acc[P6(0, 0)] + acc[P6(1, 1)] + acc[P6(2, 2)] + acc[P6(3, 3)] + acc[P6(4, 4)] + acc[P6(5, 5)];
-      // in place: acc[P6(j, i)] becomes L(i, j) for i >= j
-      bool rank_ok = wcnt >= 6.0;
-      double invd[6];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        double d = acc[P6(j, j)];
-#pragma unroll
-        for (int p = 0; p < j; ++p) d -= acc[P6(p, j)] * acc[P6(p, j)];
-        if (!(d > 1e-14 * trace)) rank_ok = false;
-        const double ljj = sqrt(fmax(d, DBL_MIN));
-        acc[P6(j, j)] = ljj;
-        const double inv = 1.0 / ljj;
-        invd[j] = inv;
-#pragma unroll
-        for (int i2 = j + 1; i2 < 6; ++i2) {
-          double s2 = acc[P6(j, i2)];
-#pragma unroll
-          for (int p = 0; p < j; ++p) s2 -= acc[P6(p, i2)] * acc[P6(p, j)];
-          acc[P6(j, i2)] = s2 * inv;
-        }
-      }
-      if (!rank_ok) {
-        st |= FTC_CELL_RANK;
-      } else {
-        double ah[6], y[6], r6[6];
-        auto solve = [&](const double* rhs, double* x) {
-#pragma unroll
-          for (int i2 = 0; i2 < 6; ++i2) {
-            double s2 = rhs[i2];
-#pragma unroll
-            for (int p = 0; p < i2; ++p) s2 -= acc[P6(p, i2)] * y[p];
-            y[i2] = s2 * invd[i2];
-          }
-#pragma unroll
-          for (int i2 = 5; i2 >= 0; --i2) {
-            double s2 = y[i2];
-#pragma unroll
-            for (int p = i2 + 1; p < 6; ++p) s2 -= acc[P6(i2, p)] * x[p];
-            x[i2] = s2 * invd[i2];
-          }
-        };
-        solve(acc + 21, ah);
-        // residual with the unfactorised matrix, read again
-#pragma unroll
-        for (int i2 = 0; i2 < 6; ++i2) {
-          double s2 = acc[21 + i2];
-#pragma unroll
-          for (int p = 0; p < 6; ++p) s2 -= F[(i2 <= p ? P6(i2, p) : P6(p, i2)) * cs] * ah[p];
-          r6[i2] = s2;
-        }
-        solve(r6, r6);
-#pragma unroll
-        for (int i2 = 0; i2 < 6; ++i2) ah[i2] += r6[i2];
-        co[0] = h * ah[0];
-        co[1] = ah[1];
-        co[2] = ah[2];
-        co[3] = ah[3] * inv_h;
-        co[4] = ah[4] * inv_h;
-        co[5] = ah[5] * inv_h;
-        const double gx = co[1], gy = co[2];
-        const double num = 2.0 * co[3] * (1.0 + gy * gy) - 2.0 * gx * gy * co[4] + 2.0 * co[5] * (1.0 + gx * gx);
-        const double sq = 1.0 + gx * gx + gy * gy;
-        kap = -num / (sq * sqrt(sq));
-        // the tangents of the frame again (Duff et al.)
-        const double sg = copysign(1.0, n2);
-        const double fa = -1.0 / (sg + n2);
-        const double fb = n0 * n1 * fa;
-        const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
-        const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
-        ni0 = n0 - co[1] * t1x - co[2] * t2x;
-        ni1 = n1 - co[1] * t1y - co[2] * t2y;
-        ni2 = n2 - co[1] * t1z - co[2] * t2z;
-        const double il = 1.0 / sqrt(ni0 * ni0 + ni1 * ni1 + ni2 * ni2);
-        ni0 *= il;
-        ni1 *= il;
-        ni2 *= il;
-      }
-    }
-    A.kappa[c] = kap;
-    A.nx[c] = ni0;
-    A.ny[c] = ni1;
-    A.nz[c] = ni2;
-    if (A.coeff)
-      for (int qa = 0; qa < 6; ++qa) A.coeff[qa * cs + c] = st ? NAN : co[qa];
-    if (A.status) A.status[c] = (int32_t)st;
+    if (F[30 * cs] == -3.0) continue;  // queued: solved by the wide shape
+    solve_cell(A, c, F, cs);
   }
 }
 
@@ -1100,11 +1126,10 @@ hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, 
   const int64_t groups = ((int64_t)ws->cell_cap + Fast::NG - 1) / Fast::NG;
   const int32_t blocks = round_up(std::min<int64_t>(std::max<int64_t>(groups, 1), 65536), kXCD);
   time_start(ws, FTC_KERNEL_PPIC, s);
-  hipLaunchKernelGGL((k_ppic<Fast, false>), dim3(blocks), dim3(64), 0, s, A);
+  hipLaunchKernelGGL(k_ppic_rings, dim3(blocks), dim3(64), 0, s, A);
   hipLaunchKernelGGL(k_ppic_fit, dim3(round_up(std::min<int64_t>(std::max<int64_t>(((int64_t)ws->cell_cap + 7) / 8, 1),
                                                                   65536), kXCD)), dim3(64), 0, s, A);
-  hipLaunchKernelGGL((k_ppic<Wide, true>), dim3(kWideBlocks), dim3(64), 0, s, A);
-  hipLaunchKernelGGL(k_ppic_solve, dim3(grid_blocks(ws->cell_cap, kT)), dim3(kT), 0, s, A);
+  hipLaunchKernelGGL(k_ppic_wide_solve, dim3(kWideBlocks + grid_blocks(ws->cell_cap, 64)), dim3(64), 0, s, A);
   time_stop(ws, FTC_KERNEL_PPIC, s);
   return hipGetLastError();
 }

@@ -24,12 +24,15 @@ constexpr int kStrideBlocks = 4096;
 
 // Per interfacial cell: sum of its pieces' integrals in CSR (ascending
 // triangle) order.
+// Pieces past the pair capacity were not stored (a latched capacity error).
 __global__ void k_cell_sums(const int32_t* offsets, const double* piece_flux, const double* piece_vol,
-                            double* cell_flux, double* cell_vol, int32_t cell_cap, const int32_t* counters) {
+                            double* cell_flux, double* cell_vol, int32_t cell_cap, int64_t pair_cap,
+                            const int32_t* counters) {
   const int32_t nif = min(counters[C_NIF], cell_cap);
   for (int32_t ci = blockIdx.x * blockDim.x + threadIdx.x; ci < nif; ci += gridDim.x * blockDim.x) {
     double f = 0.0, v = 0.0;
-    for (int32_t p = offsets[ci]; p < offsets[ci + 1]; ++p) {
+    const int64_t e = min((int64_t)offsets[ci + 1], pair_cap);
+    for (int64_t p = offsets[ci]; p < e; ++p) {
       f += piece_flux[p];
       v += piece_vol[p];
     }
@@ -60,11 +63,14 @@ struct ColArgs {
   const double* cell_vol;
   double* alpha_if;
   double* alpha;
+  int32_t cell_cap;
   int32_t* counters;
 };
 
 // Reads kSub cells k1, k1-1, ... (those >= klo) of column (i, j): which are
-// interfacial, their compact ids, fluxes and (if `vol`) volume integrals.
+// interfacial, their compact ids (-1: not interfacial; -2: interfacial but
+// beyond the cell capacity, a latched capacity error, taken with no
+// pieces), fluxes and (if `vol`) volume integrals.
 template <bool kVol>
 __device__ inline void read_sub(const ColArgs& A, bool col_ok, int32_t i, int32_t j, int32_t k1, int32_t klo,
                                 int32_t ci[kSub], double fl[kSub], double vo[kSub]) {
@@ -81,13 +87,14 @@ __device__ inline void read_sub(const ColArgs& A, bool col_ok, int32_t i, int32_
   for (int q = 0; q < kSub; ++q) {
     const bool set = (wv[q] >> (lin[q] & 31)) & 1u;
     wo[q] = A.word_off[set ? (lin[q] >> 5) : 0];
-    ci[q] = set ? wo[q] + __popc(wv[q] & ((1u << (lin[q] & 31)) - 1u)) : -1;
+    const int32_t r = wo[q] + __popc(wv[q] & ((1u << (lin[q] & 31)) - 1u));
+    ci[q] = !set ? -1 : (r < A.cell_cap ? r : -2);
   }
 #pragma unroll
   for (int q = 0; q < kSub; ++q) {
     const int32_t c = ci[q] >= 0 ? ci[q] : 0;
-    fl[q] = A.cell_flux[c];
-    if (kVol) vo[q] = A.cell_vol[c];
+    fl[q] = ci[q] >= 0 ? A.cell_flux[c] : 0.0;
+    if (kVol) vo[q] = ci[q] >= 0 ? A.cell_vol[c] : 0.0;
   }
 }
 
@@ -123,9 +130,9 @@ __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
       const int32_t k = k1 - q;
       if (!col_ok || k < klo) continue;
       double a;
-      if (ci[q] >= 0) {
+      if (ci[q] != -1) {
         a = (vo[q] + h * W) / h3;
-        if (A.alpha_if) A.alpha_if[ci[q]] = a;
+        if (A.alpha_if && ci[q] >= 0) A.alpha_if[ci[q]] = a;
         W += fl[q];
       } else {
         const double r = W / h2, rr = round(r);
@@ -146,8 +153,10 @@ hipError_t launch_volume_fraction(const ftc_cells* ws, const Mesh& m, double* al
   (void)m;  // the pieces and their integrals come from the cell-list build
   const Grid& g = ws->grid;
   hipLaunchKernelGGL(k_cell_sums, dim3(grid_blocks(ws->cell_cap, kT, kStrideBlocks)), dim3(kT), 0, s, ws->offsets,
-                     ws->piece_flux, ws->piece_vol, ws->cell_flux, ws->cell_vol, ws->cell_cap, ws->counters);
-  ColArgs A{g, ws->bitmap, ws->word_off, ws->cell_flux, ws->cell_vol, alpha_if, alpha_dense, ws->counters};
+                     ws->piece_flux, ws->piece_vol, ws->cell_flux, ws->cell_vol, ws->cell_cap, ws->pair_cap,
+                     ws->counters);
+  ColArgs A{g, ws->bitmap, ws->word_off, ws->cell_flux, ws->cell_vol, alpha_if, alpha_dense, ws->cell_cap,
+            ws->counters};
   time_start(ws, FTC_KERNEL_COLUMNS, s);
   hipLaunchKernelGGL(k_columns, dim3((g.nx + kColLanes - 1) / kColLanes, g.ny), dim3(kColLanes * kChunks), 0, s, A);
   time_stop(ws, FTC_KERNEL_COLUMNS, s);

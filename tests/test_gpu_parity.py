@@ -359,8 +359,15 @@ def test_small_capacity_latches_capacity_error():
     import torch
     torch.cuda.synchronize()
     assert step.cells.last_device_error() == ftc.FTC_ECAPACITY
-    # the outputs beyond the capacity were never touched
-    assert step.kappa.numel() == 300
+    # per-cell outputs given room beyond the capacity: nothing is written there
+    pad = lambda: torch.full((600,), 7.0, dtype=torch.float64, device="cuda")
+    a_if, kap, nx, ny, nz, fx, fy, fz = (pad() for _ in range(8))
+    ftc.volume_fraction(step.cells, grid, step.mesh, a_if, step.alpha)
+    ftc.ppic_curvature(step.cells, grid, step.mesh, kap, nx, ny, nz)
+    ftc.csf_force(step.cells, grid, step.alpha, kap, 1.0, fx, fy, fz)
+    torch.cuda.synchronize()
+    for t in (a_if, kap, nx, ny, nz, fx, fy, fz):
+        assert torch.all(t[300:] == 7.0)
 
 
 def test_host_argument_errors():
