@@ -102,7 +102,10 @@ void ftc_cells_destroy(ftc_cells* cells);
    exactly in a grid plane belongs to the cell above that plane.  Result, in
    the workspace: interfacial cells in ascending linear id and, per cell, its
    triangles in ascending id (CSR), together with each piece's two surface
-   integrals used by ftc_volume_fraction (clipping happens once, here).
+   integrals used by ftc_volume_fraction (clipping happens once, here).  The
+   same launches prepare what ftc_ppic_curvature needs from the front: each
+   vertex's incident triangles, the vertices binned by interfacial cell and
+   the closest front vertex of every interfacial cell.
    `grid` must equal the workspace's grid.
    Latches FTC_EDOMAIN or FTC_ECAPACITY on the device. */
 ftc_status ftc_build_cell_lists(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
@@ -151,7 +154,11 @@ ftc_status ftc_volume_fraction(const ftc_cells* cells, const ftc_grid* grid, con
    world units, frame origin at the cell centre); cell_status or NULL
    (FTC_CELL_* bits); diag [4][cell_capacity] or NULL (closest vertex, ring
    triangle count, triangles with non-zero weight, support adjustments).
-   `params` [host] NULL means the paper's values {2.5, 3, 24, 1.1, 16}. */
+   `params` [host] NULL means the paper's values {2.5, 3, 24, 1.1, 16}.
+   Uses the closest vertices and vertex adjacency of the last
+   ftc_build_cell_lists on the same workspace: mesh must be that front
+   (FTC_EINVAL if its vertex or triangle count differs, or before any
+   build). */
 ftc_status ftc_ppic_curvature(const ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
                               const ftc_ppic_params* params, double* kappa, double* nx, double* ny,
                               double* nz, double* coeff, int32_t* cell_status, int32_t* diag,
@@ -190,7 +197,7 @@ ftc_status ftc_last_device_error(ftc_cells* cells, int32_t* code, void* stream);
    it disabled while capturing a graph (event records are not captured). */
 typedef enum {
   FTC_KERNEL_TRI_PIECES = 0,  /* cell lists: per-triangle clip and integrals  */
-  FTC_KERNEL_PIECE_RANK = 1,  /* cell lists: ordering of each cell's pieces   */
+  FTC_KERNEL_PIECE_RANK = 1,  /* cell lists: piece order, closest vertices    */
   FTC_KERNEL_COLUMNS = 2,     /* volume fraction: column pass and dense field */
   FTC_KERNEL_PPIC = 3,        /* PPIC: ring, fit, curvature (both shapes)     */
   FTC_KERNEL_CSF = 4,         /* CSF force                                    */

@@ -103,6 +103,8 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   w.nv_cap = nv_capacity;
   w.nt_cap = nt_capacity;
   w.cell_cap = cell_capacity;
+  w.built_nv = -1;
+  w.built_nt = -1;
   w.pair_cap = pair_capacity;
   const int64_t P = pair_capacity, Cc = cell_capacity, Tc = nt_capacity, Vc = nv_capacity;
   void** reg = o->buffers;
@@ -235,6 +237,8 @@ ftc_status ftc_ppic_curvature(const ftc_cells* cells, const ftc_grid* grid, cons
                               double* coeff, int32_t* cell_status, int32_t* diag, void* stream) {
   if (!cells || !grid_valid(grid) || !mesh_valid(mesh) || !same_grid(cells->grid, grid)) return FTC_EINVAL;
   if (mesh->nv > cells->nv_cap || mesh->nt > cells->nt_cap || !kappa || !nx || !ny || !nz) return FTC_EINVAL;
+  // the vertex adjacency and closest vertices come from the last build
+  if (mesh->nv != cells->built_nv || mesh->nt != cells->built_nt) return FTC_EINVAL;
   ftc::PPICParams p{2.5, 3, 24, 1.1, 16};
   if (params) {
     p = ftc::PPICParams{params->delta_over_h, params->rings, params->n_min, params->grow, params->max_iter};

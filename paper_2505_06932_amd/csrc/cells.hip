@@ -16,8 +16,18 @@
 // 4. scatter the pairs into their cell's segment (any order), then place
 //    each at its rank by triangle id within the segment, so that the CSR
 //    lists come out in ascending triangle id whatever the scheduling was.
+// The same launches also prepare what the curvature fit needs from the
+// front, as extra work beside the pieces: each vertex's incident triangles
+// (counted while clearing, grouped in step 4, sorted ascending afterwards), the
+// vertices binned by the interfacial cell holding them (counted in step 3,
+// grouped in step 4) and, from those bins, the closest vertex of every
+// interfacial cell.  Per-vertex and per-cell counts are zero between builds:
+// the grouping takes each back down to zero as it places the entries.
 // After step 1 everything is integer work on device-resident counts, so the
 // sequence needs no host round trip and can be captured into a graph.
+#include <float.h>
+#include <limits.h>
+
 #include "ftc_ws.hpp"
 
 namespace ftc {
@@ -27,11 +37,29 @@ constexpr int kT = 256;
 constexpr int kStrideBlocks = 2048;
 constexpr int kPieceLanes = 64;  // k_clip_queue: one wavefront per workgroup
 
-// Clears the per-build state and packs the vertex coordinates as (x, y, z, 0).
+// Corner r of triangle t if it is a valid vertex index distinct from the
+// triangle's earlier corners, else -1 (a triangle is listed once under each
+// distinct corner).
+__device__ inline int32_t distinct_corner(const Mesh& m, int32_t t, int r) {
+  if (!tri_ok(m, t)) return -1;
+  const int32_t a = m.t0[t];
+  if (r == 0) return a;
+  const int32_t b = m.t1[t];
+  if (r == 1) return b != a ? b : -1;
+  const int32_t c = m.t2[t];
+  return (c != a && c != b) ? c : -1;
+}
+
+// Clears the per-build state, packs the vertex coordinates as (x, y, z, 0)
+// and counts each vertex's incident triangles (one thread per corner).
 __global__ void k_clear_build(uint32_t* bitmap, int64_t nwords, int32_t* cell_cnt, int64_t ncnt, int32_t* cursor,
-                              int64_t ncur, int32_t* counters, Mesh m, double2* vtx4) {
+                              int64_t ncur, int32_t* counters, Mesh m, double2* vtx4, int32_t* vt_cnt) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t x = g0; x < 3 * (int64_t)m.nt; x += stride) {
+    const int32_t v = distinct_corner(m, (int32_t)(x / 3), (int)(x % 3));
+    if (v >= 0) atomicAdd(&vt_cnt[v], 1);
+  }
   for (int64_t v = g0; v < m.nv; v += stride) {
     vtx4[2 * v] = make_double2(m.x[v], m.y[v]);
     vtx4[2 * v + 1] = make_double2(m.z[v], 0.0);
@@ -207,10 +235,35 @@ __device__ inline PairRange pair_range(const int32_t* counters, int64_t pair_cap
                    pair_cap};
 }
 
-// pair -> compact cell (in place of its linear id), counted per cell
+struct VertexBins {
+  int32_t nv;
+  const double2* vtx4;
+  int32_t* vcell;   // interfacial cell of each vertex; -1: a cell without pieces (a stray), -2: outside the margin
+  int32_t* vb_cnt;  // vertices per interfacial cell
+  int32_t* stray;
+};
+
+// pair -> compact cell (in place of its linear id), counted per cell; and
+// vertex -> the interfacial cell holding it, counted per cell (or listed as
+// a stray)
 __global__ void k_pair_count(int32_t* pair_lin, const uint32_t* bitmap, const int32_t* word_off, int32_t* cell_cnt,
-                             int32_t cell_cap, int64_t pair_cap, int64_t queue_cap, const int32_t* counters) {
+                             int32_t cell_cap, int64_t pair_cap, int64_t queue_cap, int32_t* counters, Grid g,
+                             VertexBins B) {
   const PairRange R = pair_range(counters, pair_cap, queue_cap);
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < B.nv; v += gridDim.x * blockDim.x) {
+    const P3 p = vtx(B.vtx4, v);
+    int32_t ci = -2;
+    if (in_margin(g, p.x, p.y, p.z)) {
+      const int64_t i = cell_index(p.x, g.x0, g.h), j = cell_index(p.y, g.y0, g.h), k = cell_index(p.z, g.z0, g.h);
+      ci = cell_rank(bitmap, word_off, i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
+      if (ci >= cell_cap) ci = -1;
+      if (ci >= 0)
+        atomicAdd(&B.vb_cnt[ci], 1);
+      else
+        B.stray[atomicAdd(&counters[C_NSTRAY], 1)] = v;
+    }
+    B.vcell[v] = ci;
+  }
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < R.count(); x += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = R.slot(x);
     const int32_t lin = pair_lin[p];
@@ -225,10 +278,32 @@ __global__ void k_pair_count(int32_t* pair_lin, const uint32_t* bitmap, const in
   }
 }
 
+struct Adjacency {
+  const int32_t* vt_off;
+  int32_t* vt_cnt;  // taken back to zero
+  int32_t* vt_ids;
+  const int32_t* vcell;
+  const int32_t* vb_off;
+  int32_t* vb_cnt;  // taken back to zero
+  int32_t* vb_ids;
+};
+
+// Pairs into their cell's segment (any order); triangles into each distinct
+// corner's incident list and vertices into their cell's bin (any order).
 __global__ void k_pair_scatter(const int32_t* pair_ci, const int32_t* pair_tri, const int32_t* offsets,
                                int32_t* cursor, int32_t* tmp_tri, int32_t* tmp_pair, int64_t pair_cap,
-                               int64_t queue_cap, int32_t* counters) {
+                               int64_t queue_cap, int32_t* counters, Mesh m, Adjacency J) {
   const PairRange R = pair_range(counters, pair_cap, queue_cap);
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < 3 * (int64_t)m.nt;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t t = (int32_t)(x / 3);
+    const int32_t v = distinct_corner(m, t, (int)(x % 3));
+    if (v >= 0) J.vt_ids[J.vt_off[v] + atomicSub(&J.vt_cnt[v], 1) - 1] = t;
+  }
+  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < m.nv; v += gridDim.x * blockDim.x) {
+    const int32_t ci = J.vcell[v];
+    if (ci >= 0) J.vb_ids[J.vb_off[ci] + atomicSub(&J.vb_cnt[ci], 1) - 1] = v;
+  }
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < R.count(); x += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = R.slot(x);
     const int32_t ci = pair_ci[p];
@@ -243,15 +318,25 @@ __global__ void k_pair_scatter(const int32_t* pair_ci, const int32_t* pair_tri, 
   }
 }
 
+struct PlaceArgs {
+  const int32_t *tmp_tri, *tmp_pair, *pair_ci;
+  const double *pair_flux, *pair_vol;
+  const int32_t* offsets;
+  int32_t *tri_ids, *slot_cell;
+  double *piece_flux, *piece_vol;
+  int32_t cell_cap;
+  int64_t pair_cap;
+  const int32_t* counters;
+};
+
 // Each scattered piece moves to its rank by triangle id within its cell (a
 // triangle has at most one piece per cell, so the ranks are distinct).
-__global__ void k_rank_place(const int32_t* tmp_tri, const int32_t* tmp_pair, const int32_t* pair_ci,
-                             const double* pair_flux, const double* pair_vol, const int32_t* offsets,
-                             int32_t* tri_ids, int32_t* slot_cell, double* piece_flux, double* piece_vol,
-                             int32_t cell_cap, int64_t pair_cap, const int32_t* counters) {
-  const int32_t nif = min(counters[C_NIF], cell_cap);
-  const int64_t nslot = min((int64_t)offsets[nif], pair_cap);
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nslot; q += (int64_t)gridDim.x * blockDim.x) {
+__device__ inline void rank_place(const PlaceArgs& A, int64_t bid, int64_t nblk) {
+  const int32_t nif = min(A.counters[C_NIF], A.cell_cap);
+  const int64_t nslot = min((int64_t)A.offsets[nif], A.pair_cap);
+  const int32_t *tmp_tri = A.tmp_tri, *tmp_pair = A.tmp_pair, *pair_ci = A.pair_ci, *offsets = A.offsets;
+  const int64_t pair_cap = A.pair_cap;
+  for (int64_t q = bid * blockDim.x + threadIdx.x; q < nslot; q += nblk * blockDim.x) {
     const int32_t p = tmp_pair[q];
     const int32_t ci = pair_ci[p];
     const int32_t t = tmp_tri[q];
@@ -259,10 +344,116 @@ __global__ void k_rank_place(const int32_t* tmp_tri, const int32_t* tmp_pair, co
     int64_t rank = 0;
     for (int64_t u = s; u < e; ++u) rank += tmp_tri[u] < t ? 1 : 0;
     const int64_t dst = s + rank;
-    tri_ids[dst] = t;
-    slot_cell[dst] = ci;
-    piece_flux[dst] = pair_flux[p];
-    piece_vol[dst] = pair_vol[p];
+    A.tri_ids[dst] = t;
+    A.slot_cell[dst] = ci;
+    A.piece_flux[dst] = A.pair_flux[p];
+    A.piece_vol[dst] = A.pair_vol[p];
+  }
+}
+
+constexpr int kSortReg = 8;  // incident lists up to this length are sorted in registers
+
+// Vertex v's incident-triangle list sorted ascending.
+__device__ inline void sort_incident(const int32_t* vt_off, int32_t* vt_ids, int32_t v) {
+  const int32_t s = vt_off[v], e = vt_off[v + 1];
+  if (e - s <= kSortReg) {
+    // in registers: odd-even transposition sort, padding at the end
+    int32_t x[kSortReg];
+#pragma unroll
+    for (int q = 0; q < kSortReg; ++q) x[q] = s + q < e ? vt_ids[s + q] : INT_MAX;
+#pragma unroll
+    for (int pass = 0; pass < kSortReg; ++pass)
+#pragma unroll
+      for (int q = pass & 1; q + 1 < kSortReg; q += 2) {
+        const int32_t lo = min(x[q], x[q + 1]), hi = max(x[q], x[q + 1]);
+        x[q] = lo;
+        x[q + 1] = hi;
+      }
+#pragma unroll
+    for (int q = 0; q < kSortReg; ++q)
+      if (s + q < e) vt_ids[s + q] = x[q];
+    return;
+  }
+  for (int32_t a = s + 1; a < e; ++a) {
+    const int32_t x = vt_ids[a];
+    int32_t b = a - 1;
+    while (b >= s && vt_ids[b] > x) {
+      vt_ids[b + 1] = vt_ids[b];
+      --b;
+    }
+    vt_ids[b + 1] = x;
+  }
+}
+
+struct VstarArgs {
+  const double2* vtx4;
+  const int32_t* cell_ids;
+  const uint32_t* bitmap;
+  const int32_t* word_off;
+  const int32_t *vb_off, *vb_ids, *stray;
+  double* best_d2;
+  int32_t* best_v;
+  int32_t cell_cap;
+  const int32_t* counters;
+};
+
+// Closest vertex of each interfacial cell among the vertices binned in the
+// 3x3x3 block of cells around it and the strays: 32 lanes per cell, lane
+// l < 27 scans the bin of cell l of the block, every lane a share of the
+// strays; lowest index on ties.  A vertex outside the block is at least
+// 1.5 h from the cell centre, so a best squared distance below (1.5 h)^2 is
+// final (the curvature's ring pass searches all vertices for the other
+// cells).
+// Called with all 64 lanes of the wavefront.
+__device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int64_t gid) {
+  const int32_t nif = min(A.counters[C_NIF], A.cell_cap);
+  const int32_t nstray = A.counters[C_NSTRAY];
+  const int64_t c = gid >> 5;
+  const int l = (int)(gid & 31);
+  double bd = DBL_MAX;
+  int32_t bv = INT_MAX;
+  if (c < nif) {
+    const Cell3 cc = unpack_cell(g, A.cell_ids[c]);
+    const double xc[3] = {cell_centre(g.x0, cc.i, g.h), cell_centre(g.y0, cc.j, g.h), cell_centre(g.z0, cc.k, g.h)};
+    if (l < 27) {
+      const int32_t ii = cc.i + l % 3 - 1, jj = cc.j + (l / 3) % 3 - 1, kk = cc.k + l / 9 - 1;
+      if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) {
+        const int32_t cr = cell_rank(A.bitmap, A.word_off, ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk));
+        if (cr >= 0 && cr < A.cell_cap)
+          for (int32_t p = A.vb_off[cr], e = A.vb_off[cr + 1]; p < e; ++p) consider(A.vtx4, A.vb_ids[p], xc, bd, bv);
+      }
+    }
+    for (int32_t q = l; q < nstray; q += 32) consider(A.vtx4, A.stray[q], xc, bd, bv);
+  }
+#pragma unroll
+  for (int o = 16; o >= 1; o >>= 1) {
+    const double od = __shfl_xor(bd, o, 64);
+    const int32_t ov = __shfl_xor(bv, o, 64);
+    if (lex_less(od, ov, bd, bv)) {
+      bd = od;
+      bv = ov;
+    }
+  }
+  if (c < nif && l == 0) {
+    A.best_d2[c] = bd;
+    A.best_v[c] = bv;
+  }
+}
+
+// Blocks [0, nb_place): pieces to their ranks; [nb_place, nb_place +
+// nb_sort): one vertex per thread, its incident list sorted; the rest:
+// closest vertices.
+__global__ __launch_bounds__(kT) void k_place_sort_vstar(PlaceArgs A, int32_t nb_place, int32_t nb_sort, Grid g,
+                                                         int32_t nv, const int32_t* vt_off, int32_t* vt_ids,
+                                                         VstarArgs V) {
+  const int32_t b = blockIdx.x;
+  if (b < nb_place) {
+    rank_place(A, b, nb_place);
+  } else if (b < nb_place + nb_sort) {
+    const int32_t v = (b - nb_place) * kT + threadIdx.x;
+    if (v < nv) sort_incident(vt_off, vt_ids, v);
+  } else {
+    closest_vertex(g, V, (int64_t)(b - nb_place - nb_sort) * kT + threadIdx.x);
   }
 }
 
@@ -273,7 +464,8 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
   int4* tri4 = reinterpret_cast<int4*>(ws->tri4);
   double2* vtx4 = reinterpret_cast<double2*>(ws->vtx4);
   hipLaunchKernelGGL(k_clear_build, dim3(kStrideBlocks), dim3(kT), 0, s, ws->bitmap, ws->nwords, ws->offsets,
-                     (int64_t)ws->cell_cap + 1, ws->cursor, (int64_t)ws->cell_cap, ws->counters, m, vtx4);
+                     (int64_t)ws->cell_cap + 1, ws->cursor, (int64_t)ws->cell_cap, ws->counters, m, vtx4,
+                     ws->vt_cursor);
   PairOut P{ws->pair_cell, ws->pair_tri, ws->pair_flux, ws->pair_vol, ws->pair_cap};
   time_start(ws, FTC_KERNEL_TRI_PIECES, s);
   hipLaunchKernelGGL(k_tri_classify, dim3(grid_blocks(m.nt, kClassifyT)), dim3(kClassifyT), 0, s, g, m, vtx4, tri4,
@@ -285,20 +477,37 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
                                     ws->cell_ids, ws->cell_cap, ws->counters, s);
   if (e != hipSuccess) return e;
   const int64_t npair_max = ws->pair_cap + ws->queue_cap;
+  VertexBins B{m.nv, vtx4, ws->vcell, ws->vb_cursor, ws->stray};
   hipLaunchKernelGGL(k_pair_count, dim3(grid_blocks(npair_max, kT, kStrideBlocks)), dim3(kT), 0, s, ws->pair_cell,
                      ws->bitmap, ws->word_off, ws->offsets, ws->cell_cap, ws->pair_cap, ws->queue_cap,
-                     ws->counters);
-  e = scan_exclusive(ws->offsets, ws->cell_cap, ws->scan_tmp, ws->counters + C_NPAIRS, s);
+                     ws->counters, g, B);
+  const ScanSeg segs[3] = {{ws->offsets, ws->offsets, ws->cell_cap, ws->counters + C_NPAIRS},
+                           {ws->vt_cursor, ws->vt_off, m.nv, nullptr},
+                           {ws->vb_cursor, ws->vb_off, ws->cell_cap, nullptr}};
+  e = scan_exclusive_multi(segs, 3, ws->scan_tmp, s);
   if (e != hipSuccess) return e;
+  Adjacency J{ws->vt_off, ws->vt_cursor, ws->vt_ids, ws->vcell, ws->vb_off, ws->vb_cursor, ws->vb_ids};
   hipLaunchKernelGGL(k_pair_scatter, dim3(grid_blocks(npair_max, kT, kStrideBlocks)), dim3(kT), 0, s, ws->pair_cell,
                      ws->pair_tri, ws->offsets, ws->cursor, ws->tmp_tri, ws->tmp_pair, ws->pair_cap, ws->queue_cap,
-                     ws->counters);
+                     ws->counters, m, J);
+  PlaceArgs A{ws->tmp_tri,  ws->tmp_pair,  ws->pair_cell,  ws->pair_flux, ws->pair_vol, ws->offsets,
+              ws->tri_ids,  ws->slot_cell, ws->piece_flux, ws->piece_vol, ws->cell_cap, ws->pair_cap,
+              ws->counters};
+  VstarArgs V{vtx4,       ws->cell_ids, ws->bitmap,  ws->word_off, ws->vb_off,  ws->vb_ids,
+              ws->stray,  ws->best_d2,  ws->best_v,  ws->cell_cap, ws->counters};
+  const int32_t nb_place = grid_blocks(ws->pair_cap, kT, kStrideBlocks);
+  const int32_t nb_sort = grid_blocks(m.nv, kT);
+  const int32_t nb_vstar = grid_blocks((int64_t)ws->cell_cap * 32, kT);
   time_start(ws, FTC_KERNEL_PIECE_RANK, s);
-  hipLaunchKernelGGL(k_rank_place, dim3(grid_blocks(ws->pair_cap, kT, kStrideBlocks)), dim3(kT), 0, s, ws->tmp_tri,
-                     ws->tmp_pair, ws->pair_cell, ws->pair_flux, ws->pair_vol, ws->offsets, ws->tri_ids,
-                     ws->slot_cell, ws->piece_flux, ws->piece_vol, ws->cell_cap, ws->pair_cap, ws->counters);
+  hipLaunchKernelGGL(k_place_sort_vstar, dim3(nb_place + nb_sort + nb_vstar), dim3(kT), 0, s, A, nb_place, nb_sort, g,
+                     m.nv, ws->vt_off, ws->vt_ids, V);
   time_stop(ws, FTC_KERNEL_PIECE_RANK, s);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e == hipSuccess) {
+    ws->built_nv = m.nv;
+    ws->built_nt = m.nt;
+  }
+  return e;
 }
 
 }  // namespace ftc

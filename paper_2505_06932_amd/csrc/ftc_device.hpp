@@ -181,6 +181,46 @@ __host__ __device__ inline bool cell_planes(const Grid& g, const Tri& T, int64_t
   return ok;
 }
 
+// Compact index of grid cell `lin` among the interfacial cells (its rank in
+// the occupancy bitmap, from the popcount prefix sums), -1 if it holds no
+// piece.
+__device__ inline int32_t cell_rank(const uint32_t* bitmap, const int32_t* word_off, int64_t lin) {
+  const uint32_t w = bitmap[lin >> 5];
+  if (!((w >> (lin & 31)) & 1u)) return -1;
+  const uint32_t below = (lin & 31) ? (w & ((1u << (lin & 31)) - 1u)) : 0u;
+  return word_off[lin >> 5] + __popc(below);
+}
+
+__device__ inline double cell_centre(double org, int32_t i, double h) { return org + ((double)i + 0.5) * h; }
+
+struct P3 {
+  double x, y, z;
+};
+
+// Vertex coordinates from the packed (x, y, z, 0) record.
+__device__ inline P3 vtx(const double2* vtx4, int32_t v) {
+  const double2 a = vtx4[2 * (int64_t)v], b = vtx4[2 * (int64_t)v + 1];
+  return P3{a.x, a.y, b.x};
+}
+
+// (squared distance, vertex) ordered lexicographically: the closest vertex,
+// lowest index on ties.
+__device__ inline bool lex_less(double d, int32_t v, double bd, int32_t bv) {
+  return d < bd || (d == bd && v < bv);
+}
+
+// d^2 = dx dx + dy dy + dz dz (in that order) of vertex v to xc, kept when
+// it beats (bd, bv).
+__device__ inline void consider(const double2* vtx4, int32_t v, const double xc[3], double& bd, int32_t& bv) {
+  const P3 p = vtx(vtx4, v);
+  const double dx = p.x - xc[0], dy = p.y - xc[1], dz = p.z - xc[2];
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  if (lex_less(d2, v, bd, bv)) {
+    bd = d2;
+    bv = v;
+  }
+}
+
 // Candidate classes decided from the corners alone, taking exactly the
 // decisions the clipping would take: stages are visited in order while the
 // polygon is still the (rotated) triangle; 0 = no piece (half-open rule, or

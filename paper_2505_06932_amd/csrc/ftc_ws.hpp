@@ -19,6 +19,7 @@ enum : int {
   C_NWHOLE = 4,   // pieces that are whole triangles
   C_NSTRAY = 5,   // vertices in cells without pieces
   C_NOVF = 6,     // interfacial cells whose ring exceeds the fast PPIC kernel's capacities
+  C_NQUEUED = 7,  // C_NOVF as the wide PPIC shape reads it (moved there by the fit pass)
   C_COUNT = 8
 };
 }  // namespace ftc
@@ -28,6 +29,7 @@ struct ftc_cells {
   ftc::Grid grid;
   int64_t ncell, nwords, ncol;
   int32_t nv_cap, nt_cap, cell_cap;
+  int32_t built_nv, built_nt;  // front sizes of the last build (-1 before the first)
   int64_t pair_cap;
   int64_t queue_cap;  // candidates queued for full clipping (>= pair_cap)
 
@@ -99,10 +101,17 @@ hipError_t scan_popcount(const uint32_t* words, int32_t* out, int64_t n, int32_t
 hipError_t scan_popcount_emit(const uint32_t* words, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out,
                               int32_t* ids, int32_t cap, int32_t* counters, hipStream_t s);
 
-// Two independent exclusive scans (a[0..na) -> a_out[0..na], c[0..nc) ->
-// c_out[0..nc], totals last) in one pair of launches; in place is allowed.
-hipError_t scan_exclusive2(const int32_t* a, int32_t* a_out, int64_t na, const int32_t* c, int32_t* c_out, int64_t nc,
-                           int32_t* tmp, hipStream_t s);
+// Up to three independent exclusive scans in one pair of launches: segment
+// q turns in[0..n) into out[0..n] (total last, and into *total when
+// non-null); in place is allowed.
+struct ScanSeg {
+  const int32_t* in;
+  int32_t* out;
+  int64_t n;
+  int32_t* total;
+};
+constexpr int kMaxSeg = 3;
+hipError_t scan_exclusive_multi(const ScanSeg* segs, int nseg, int32_t* tmp, hipStream_t s);
 
 hipError_t fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 

@@ -1,23 +1,18 @@
 // ppic.hip -- PPIC curvature by the volume fit (paper section 3.2).
 //
-// Pre-passes (integer work, once per call, four launches plus a scan):
-//   * vertex -> incident triangles (CSR, ascending triangle id), and the
-//     triangles' corners packed as (t0, t1, t2, 0) so one 16-byte load
-//     fetches a triangle;
-//   * vertex coordinates packed as (x, y, z, 0), and the vertices binned by
-//     the interfacial cell that holds them; vertices in cells without pieces
-//     go to a short "stray" list;
-//   * closest vertex of every interfacial cell: 32 lanes per cell, one per
-//     cell of the 3x3x3 block around it, all of them over the strays; lowest
-//     index on ties.  A vertex outside the block is at least 1.5 h from the
-//     cell centre, so a best squared distance below (1.5 h)^2 is final; any
-//     other cell searches all vertices in the main kernel.
+// The cell-list build prepares what this needs from the front: each
+// vertex's incident triangles (ascending), the triangles' corners packed as
+// (t0, t1, t2, 0) and the vertex coordinates as (x, y, z, 0), and the
+// closest vertex of every interfacial cell among the vertices of the 3x3x3
+// block of cells around it (lowest index on ties).  A vertex outside the
+// block is at least 1.5 h from the cell centre, so a best squared distance
+// below (1.5 h)^2 is final; any other cell searches all vertices here.
 //
-// Ring pass (k_ppic), one template for two shapes: the fast shape gives 8
-// lanes to each interfacial cell (8 cells per wavefront) and holds rings of
-// up to 32 vertices and 64 triangles in LDS; cells whose ring is larger are
-// queued for the wide shape (64 lanes per cell, rings of 256 vertices and
-// 512 triangles), launched after it.  Cells are assigned so that each XCD
+// Ring pass (k_ppic_rings; ppic_cells, one template for two shapes): the
+// fast shape gives 8 lanes to each interfacial cell (8 cells per wavefront)
+// and holds rings of up to 32 vertices and 64 triangles in LDS; cells whose
+// ring is larger are queued for the wide shape (64 lanes per cell, rings of
+// 256 vertices and 512 triangles), which runs in the solve launch.  Cells are assigned so that each XCD
 // processes a contiguous range, which keeps each L2 on one part of the front.
 //   1. ring neighbourhood: V_0 = {v*}; T_r = triangles with a corner in
 //      V_{r-1}; V_r = V_{r-1} plus the corners of T_r.  Built incrementally:
@@ -47,7 +42,7 @@
 //      plane, and the weighted normal equations M a = b accumulated in
 //      registers; all-reduce over the cell's lanes with row permutations;
 //      the 27 sums are stored per cell.
-// Solve pass (k_ppic_solve), one thread per cell:
+// Solve pass (k_ppic_wide_solve), one thread per cell:
 //   5. Cholesky factorisation of the packed M with one step of iterative
 //      refinement, curvature kappa = 2H at the frame origin and the
 //      interface normal.
@@ -62,8 +57,6 @@
 namespace ftc {
 namespace {
 
-constexpr int kT = 256;
-constexpr int kStrideBlocks = 4096;
 constexpr int kXCD = 8;          // accelerator complex dies; workgroups are dealt to them in turn
 constexpr int kWideBlocks = 64;  // persistent workgroups of the wide shape
 
@@ -85,195 +78,6 @@ struct Cfg {
 };
 using Fast = Cfg<8, 64, 32, 64, 6>;
 using Wide = Cfg<64, 512, 256, 512, 4>;
-
-// ----------------------------------------------------------------- pre-passes
-// The per-vertex triangle counts (vt_cnt) and per-cell vertex counts
-// (vb_cnt) are zero between calls: the scatter takes every count back down
-// to zero as it places the entries.
-
-__device__ inline int32_t cell_rank(const uint32_t* bitmap, const int32_t* word_off, int64_t lin) {
-  const uint32_t w = bitmap[lin >> 5];
-  if (!((w >> (lin & 31)) & 1u)) return -1;
-  const uint32_t below = (lin & 31) ? (w & ((1u << (lin & 31)) - 1u)) : 0u;
-  return word_off[lin >> 5] + __popc(below);
-}
-
-struct PreArgs {
-  Grid g;
-  Mesh m;
-  const uint32_t* bitmap;
-  const int32_t* word_off;
-  int4* tri4;
-  double2* vtx4;
-  int32_t* vt_cnt;
-  int32_t* vt_off;
-  int32_t* vt_ids;
-  int32_t* vcell;
-  int32_t* vb_cnt;
-  int32_t* vb_off;
-  int32_t* vb_ids;
-  int32_t* stray;
-  int32_t cell_cap;
-  int32_t* counters;
-};
-
-// Thread t: triangle t (packed corners; counted once under each distinct
-// corner; a triangle with an invalid corner is packed as (0, 0, 0) and
-// counted nowhere) and vertex t (packed coordinates; the interfacial cell
-// holding it: -1 for a cell without pieces, which makes it a stray, -2
-// outside the margin, latched as a domain error by the cell-list build).
-__global__ void k_pre_count(PreArgs P) {
-  const Mesh& m = P.m;
-  const Grid& g = P.g;
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) P.counters[C_NOVF] = 0;
-  if (t < m.nt) {
-    const int32_t a = m.t0[t], b = m.t1[t], c = m.t2[t];
-    const bool ok = a >= 0 && b >= 0 && c >= 0 && a < m.nv && b < m.nv && c < m.nv;
-    P.tri4[t] = ok ? make_int4(a, b, c, 0) : make_int4(0, 0, 0, 0);
-    if (ok) {
-      atomicAdd(&P.vt_cnt[a], 1);
-      if (b != a) atomicAdd(&P.vt_cnt[b], 1);
-      if (c != a && c != b) atomicAdd(&P.vt_cnt[c], 1);
-    }
-  }
-  if (t < m.nv) {
-    const double x = m.x[t], y = m.y[t], z = m.z[t];
-    P.vtx4[2 * (int64_t)t] = make_double2(x, y);
-    P.vtx4[2 * (int64_t)t + 1] = make_double2(z, 0.0);
-    int32_t ci = -2;
-    if (in_margin(g, x, y, z)) {
-      const int64_t i = cell_index(x, g.x0, g.h), j = cell_index(y, g.y0, g.h), k = cell_index(z, g.z0, g.h);
-      ci = cell_rank(P.bitmap, P.word_off, i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
-      if (ci >= P.cell_cap) ci = -1;
-      if (ci >= 0)
-        atomicAdd(&P.vb_cnt[ci], 1);
-      else
-        P.stray[atomicAdd(&P.counters[C_NSTRAY], 1)] = t;
-    }
-    P.vcell[t] = ci;
-  }
-}
-
-__global__ void k_pre_scatter(PreArgs P) {
-  const Mesh& m = P.m;
-  const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < m.nt && tri_ok(m, t)) {
-    const int32_t a = m.t0[t], b = m.t1[t], c = m.t2[t];
-    P.vt_ids[P.vt_off[a] + atomicSub(&P.vt_cnt[a], 1) - 1] = t;
-    if (b != a) P.vt_ids[P.vt_off[b] + atomicSub(&P.vt_cnt[b], 1) - 1] = t;
-    if (c != a && c != b) P.vt_ids[P.vt_off[c] + atomicSub(&P.vt_cnt[c], 1) - 1] = t;
-  }
-  if (t < m.nv) {
-    const int32_t ci = P.vcell[t];
-    if (ci >= 0) P.vb_ids[P.vb_off[ci] + atomicSub(&P.vb_cnt[ci], 1) - 1] = t;
-  }
-}
-
-__device__ inline bool lex_less(double d, int32_t v, double bd, int32_t bv) {
-  return d < bd || (d == bd && v < bv);
-}
-
-struct P3 {
-  double x, y, z;
-};
-
-__device__ inline P3 vtx(const double2* vtx4, int32_t v) {
-  const double2 a = vtx4[2 * (int64_t)v], b = vtx4[2 * (int64_t)v + 1];
-  return P3{a.x, a.y, b.x};
-}
-
-__device__ inline void consider(const double2* vtx4, int32_t v, const double xc[3], double& bd, int32_t& bv) {
-  const P3 p = vtx(vtx4, v);
-  const double dx = p.x - xc[0], dy = p.y - xc[1], dz = p.z - xc[2];
-  const double d2 = dx * dx + dy * dy + dz * dz;
-  if (lex_less(d2, v, bd, bv)) {
-    bd = d2;
-    bv = v;
-  }
-}
-
-__device__ inline double cell_centre(double org, int32_t i, double h) { return org + ((double)i + 0.5) * h; }
-
-constexpr int kSortReg = 8;  // incident lists up to this length are sorted in registers
-
-// Blocks [0, sort_blocks): one vertex per thread, its incident-triangle
-// list sorted ascending.  The other blocks: 32 lanes per interfacial cell,
-// lane l < 27 scans the vertex bin of cell l of the 3x3x3 block around it,
-// every lane a share of the strays; lowest index on ties.
-__global__ __launch_bounds__(kT) void k_sort_vstar(Grid g, int32_t nv, const int32_t* vt_off, int32_t* vt_ids,
-                                                   int32_t sort_blocks, const double2* vtx4, const int32_t* cell_ids,
-                                                   const uint32_t* bitmap, const int32_t* word_off,
-                                                   const int32_t* vb_off, const int32_t* vb_ids, const int32_t* stray,
-                                                   double* best_d2, int32_t* best_v, int32_t cell_cap,
-                                                   const int32_t* counters) {
-  if ((int32_t)blockIdx.x < sort_blocks) {
-    const int32_t v = blockIdx.x * kT + threadIdx.x;
-    if (v >= nv) return;
-    const int32_t s = vt_off[v], e = vt_off[v + 1];
-    if (e - s <= kSortReg) {
-      // in registers: odd-even transposition sort, padding at the end
-      int32_t x[kSortReg];
-#pragma unroll
-      for (int q = 0; q < kSortReg; ++q) x[q] = s + q < e ? vt_ids[s + q] : INT_MAX;
-#pragma unroll
-      for (int pass = 0; pass < kSortReg; ++pass)
-#pragma unroll
-        for (int q = pass & 1; q + 1 < kSortReg; q += 2) {
-          const int32_t lo = min(x[q], x[q + 1]), hi = max(x[q], x[q + 1]);
-          x[q] = lo;
-          x[q + 1] = hi;
-        }
-#pragma unroll
-      for (int q = 0; q < kSortReg; ++q)
-        if (s + q < e) vt_ids[s + q] = x[q];
-      return;
-    }
-    for (int32_t a = s + 1; a < e; ++a) {
-      const int32_t x = vt_ids[a];
-      int32_t b = a - 1;
-      while (b >= s && vt_ids[b] > x) {
-        vt_ids[b + 1] = vt_ids[b];
-        --b;
-      }
-      vt_ids[b + 1] = x;
-    }
-    return;
-  }
-  const int32_t nif = min(counters[C_NIF], cell_cap);
-  const int32_t nstray = counters[C_NSTRAY];
-  const int64_t gid = (int64_t)(blockIdx.x - sort_blocks) * kT + threadIdx.x;
-  const int64_t c = gid >> 5;
-  const int l = (int)(gid & 31);
-  double bd = DBL_MAX;
-  int32_t bv = INT_MAX;
-  if (c < nif) {
-    const Cell3 cc = unpack_cell(g, cell_ids[c]);
-    const double xc[3] = {cell_centre(g.x0, cc.i, g.h), cell_centre(g.y0, cc.j, g.h), cell_centre(g.z0, cc.k, g.h)};
-    if (l < 27) {
-      const int32_t ii = cc.i + l % 3 - 1, jj = cc.j + (l / 3) % 3 - 1, kk = cc.k + l / 9 - 1;
-      if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) {
-        const int32_t cr = cell_rank(bitmap, word_off, ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk));
-        if (cr >= 0 && cr < cell_cap)
-          for (int32_t p = vb_off[cr], e = vb_off[cr + 1]; p < e; ++p) consider(vtx4, vb_ids[p], xc, bd, bv);
-      }
-    }
-    for (int32_t q = l; q < nstray; q += 32) consider(vtx4, stray[q], xc, bd, bv);
-  }
-#pragma unroll
-  for (int o = 16; o >= 1; o >>= 1) {
-    const double od = __shfl_xor(bd, o, 64);
-    const int32_t ov = __shfl_xor(bv, o, 64);
-    if (lex_less(od, ov, bd, bv)) {
-      bd = od;
-      bv = ov;
-    }
-  }
-  if (c < nif && l == 0) {
-    best_d2[c] = bd;
-    best_v[c] = bv;
-  }
-}
 
 // ----------------------------------------------------------------- main kernel
 struct PPICArgs {
@@ -533,14 +337,12 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
   CellMem<C>& CM = SM[grp];
   RingMem<C>& RM = CM.u.r;
   FitMem<C>& FM = CM.u.f;
-  const int32_t nitems = kQueue ? min(A.counters[C_NOVF], A.cell_cap) : min(A.counters[C_NIF], A.cell_cap);
+  const int32_t nitems = kQueue ? min(A.counters[C_NQUEUED], A.cell_cap) : min(A.counters[C_NIF], A.cell_cap);
   const double h = g.h;
   const int R = A.prm.rings;
   const double reach = 1.5 * h;
   const double reach2 = reach * reach * (1.0 - 1e-12);
   const uint64_t below_me = (1ull << gl) - 1ull;
-  // the closest-vertex pass has read the stray count: reset it for the next call
-  if (!kQueue && bid == 0 && threadIdx.x == 0) A.counters[C_NSTRAY] = 0;
 
   // each XCD takes a contiguous range of cell groups
   const int32_t ngroups = (nitems + NG - 1) / NG;
@@ -971,6 +773,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   const int32_t nitems = min(A.counters[C_NIF], A.cell_cap);
   const int64_t cs = A.cell_cap;
   const double h = g.h, inv_h = 1.0 / h;
+  // the ring pass has finished queueing: hand the count to the wide shape
+  // and start the next call's queue empty
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    A.counters[C_NQUEUED] = A.counters[C_NOVF];
+    A.counters[C_NOVF] = 0;
+  }
   const int32_t ngroups = (nitems + NG - 1) / NG;
   const int32_t per = (ngroups + kXCD - 1) / kXCD;
   const int32_t xcd = blockIdx.x % kXCD, nj = gridDim.x / kXCD;
@@ -1086,19 +894,6 @@ hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, 
   const Grid& g = ws->grid;
   int4* tri4 = reinterpret_cast<int4*>(ws->tri4);
   double2* vtx4 = reinterpret_cast<double2*>(ws->vtx4);
-  PreArgs P{g,         m,           ws->bitmap, ws->word_off, tri4,      vtx4,         ws->vt_cursor, ws->vt_off,
-            ws->vt_ids, ws->vcell, ws->vb_cursor, ws->vb_off, ws->vb_ids, ws->stray, ws->cell_cap, ws->counters};
-  const int32_t nthr = std::max(m.nt, m.nv);
-  hipLaunchKernelGGL(k_pre_count, dim3(grid_blocks(nthr, kT)), dim3(kT), 0, s, P);
-  hipError_t e = scan_exclusive2(ws->vt_cursor, ws->vt_off, m.nv, ws->vb_cursor, ws->vb_off, ws->cell_cap,
-                                 ws->scan_tmp, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pre_scatter, dim3(grid_blocks(nthr, kT)), dim3(kT), 0, s, P);
-  const int32_t sort_blocks = grid_blocks(m.nv, kT);
-  const int32_t vstar_blocks = grid_blocks((int64_t)ws->cell_cap * 32, kT);
-  hipLaunchKernelGGL(k_sort_vstar, dim3(sort_blocks + vstar_blocks), dim3(kT), 0, s, g, m.nv, ws->vt_off, ws->vt_ids,
-                     sort_blocks, vtx4, ws->cell_ids, ws->bitmap, ws->word_off, ws->vb_off, ws->vb_ids, ws->stray,
-                     ws->best_d2, ws->best_v, ws->cell_cap, ws->counters);
   PPICArgs A;
   A.g = g;
   A.nv = m.nv;

@@ -117,24 +117,30 @@ __global__ __launch_bounds__(kThreads) void k_block_apply(L load, int64_t n, con
   apply_one(load, n, tmp, out, total_out, blockIdx.x, nb);
 }
 
-// Two independent arrays in one pair of launches: blocks [0, nb1) work on
-// the first, the others on the second (its block totals follow the first's
-// in tmp).
-__global__ __launch_bounds__(kThreads) void k_block_totals2(const int32_t* a, int64_t na, int64_t nb1,
-                                                            const int32_t* c, int64_t nc, int32_t* tmp) {
-  if (blockIdx.x < nb1)
-    totals_one(LoadI32{a}, na, blockIdx.x, tmp + blockIdx.x);
-  else
-    totals_one(LoadI32{c}, nc, blockIdx.x - nb1, tmp + blockIdx.x);
+// Up to kMaxSeg independent arrays in one pair of launches: the blocks of
+// segment q are [b0[q], b0[q + 1]), and its block totals sit at the same
+// positions of tmp.
+struct MultiSeg {
+  ScanSeg seg[kMaxSeg];
+  int64_t b0[kMaxSeg + 1];
+  int nseg;
+};
+
+__device__ inline int seg_of(const MultiSeg& M, int64_t b) {
+  int q = 0;
+  while (q + 1 < M.nseg && b >= M.b0[q + 1]) ++q;
+  return q;
 }
 
-__global__ __launch_bounds__(kThreads) void k_block_apply2(const int32_t* a, int32_t* a_out, int64_t na,
-                                                           int64_t nb1, const int32_t* c, int32_t* c_out, int64_t nc,
-                                                           int64_t nb2, const int32_t* tmp) {
-  if (blockIdx.x < nb1)
-    apply_one(LoadI32{a}, na, tmp, a_out, nullptr, blockIdx.x, nb1);
-  else
-    apply_one(LoadI32{c}, nc, tmp + nb1, c_out, nullptr, blockIdx.x - nb1, nb2);
+__global__ __launch_bounds__(kThreads) void k_block_totals_multi(MultiSeg M, int32_t* tmp) {
+  const int q = seg_of(M, blockIdx.x);
+  totals_one(LoadI32{M.seg[q].in}, M.seg[q].n, blockIdx.x - M.b0[q], tmp + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kThreads) void k_block_apply_multi(MultiSeg M, const int32_t* tmp) {
+  const int q = seg_of(M, blockIdx.x);
+  apply_one(LoadI32{M.seg[q].in}, M.seg[q].n, tmp + M.b0[q], M.seg[q].out, M.seg[q].total, blockIdx.x - M.b0[q],
+            M.b0[q + 1] - M.b0[q]);
 }
 
 // Second pass of the popcount scan that also lists the set bits: every set
@@ -213,18 +219,27 @@ hipError_t scan_popcount_emit(const uint32_t* words, int32_t* out, int64_t n, in
   return hipGetLastError();
 }
 
-hipError_t scan_exclusive2(const int32_t* a, int32_t* a_out, int64_t na, const int32_t* c, int32_t* c_out, int64_t nc,
-                           int32_t* tmp, hipStream_t s) {
-  if (na < 0 || na > kScanMax || nc < 0 || nc > kScanMax) return hipErrorInvalidValue;
-  const int64_t nb1 = std::max<int64_t>((na + kScanBlock - 1) / kScanBlock, 1);
-  const int64_t nb2 = std::max<int64_t>((nc + kScanBlock - 1) / kScanBlock, 1);
-  if (nb1 + nb2 > kScanMaxBlocks) {
-    hipError_t e = scan_impl(LoadI32{a}, a_out, na, tmp, nullptr, s);
-    return e != hipSuccess ? e : scan_impl(LoadI32{c}, c_out, nc, tmp, nullptr, s);
+hipError_t scan_exclusive_multi(const ScanSeg* segs, int nseg, int32_t* tmp, hipStream_t s) {
+  if (nseg < 1 || nseg > kMaxSeg) return hipErrorInvalidValue;
+  MultiSeg M{};
+  M.nseg = nseg;
+  M.b0[0] = 0;
+  for (int q = 0; q < nseg; ++q) {
+    if (segs[q].n < 0 || segs[q].n > kScanMax) return hipErrorInvalidValue;
+    M.seg[q] = segs[q];
+    M.b0[q + 1] = M.b0[q] + std::max<int64_t>((segs[q].n + kScanBlock - 1) / kScanBlock, 1);
   }
-  hipLaunchKernelGGL(k_block_totals2, dim3((unsigned)(nb1 + nb2)), dim3(kThreads), 0, s, a, na, nb1, c, nc, tmp);
-  hipLaunchKernelGGL(k_block_apply2, dim3((unsigned)(nb1 + nb2)), dim3(kThreads), 0, s, a, a_out, na, nb1, c, c_out,
-                     nc, nb2, (const int32_t*)tmp);
+  for (int q = nseg; q < kMaxSeg; ++q) M.b0[q + 1] = M.b0[nseg];
+  const int64_t nb = M.b0[nseg];
+  if (nb > kScanMaxBlocks) {
+    for (int q = 0; q < nseg; ++q) {
+      hipError_t e = scan_impl(LoadI32{segs[q].in}, segs[q].out, segs[q].n, tmp, segs[q].total, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  hipLaunchKernelGGL(k_block_totals_multi, dim3((unsigned)nb), dim3(kThreads), 0, s, M, tmp);
+  hipLaunchKernelGGL(k_block_apply_multi, dim3((unsigned)nb), dim3(kThreads), 0, s, M, (const int32_t*)tmp);
   return hipGetLastError();
 }
 
