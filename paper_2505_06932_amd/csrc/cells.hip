@@ -111,12 +111,18 @@ __device__ inline int64_t block_alloc(int32_t v, int32_t* counter, int32_t* sh) 
 // Per triangle: classify every candidate cell; whole-triangle pieces go
 // straight to the first region of the pair list, candidates that need
 // clipping to the second (the clipping queue).  Two passes over the cheap
-// classification: count, allocate, write.
+// classification: count, allocate, write.  A workgroup's queued candidates
+// are written grouped by the set of cell planes their triangle crosses, so
+// that the wavefronts of the clipping mostly take the same branches.
 constexpr int kClassifyT = 1024;
 __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, const double2* vtx4, int4* tri4,
                                                              uint32_t* bitmap, PairOut P, int64_t q_cap,
                                                              int32_t* counters) {
   __shared__ int32_t sh[kClassifyT / 64 + 1];
+  __shared__ int32_t qoff[64];  // queued candidates per crossing mask, then their offsets
+  __shared__ int32_t qbase;
+  if (threadIdx.x < 64) qoff[threadIdx.x] = 0;
+  __syncthreads();
   const int32_t t = blockIdx.x * kClassifyT + threadIdx.x;
   bool valid = t < m.nt;
   if (valid) {
@@ -154,11 +160,24 @@ __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, con
             ++n1;
           }
         } else if (cls == 2) {
+          atomicAdd(&qoff[crossing_mask(g, T, i, j, k)], 1);
           ++n2;
         }
       }
   int64_t p = block_alloc<kClassifyT>(n1, &counters[C_NWHOLE], sh);
-  int64_t q = block_alloc<kClassifyT>(n2, &counters[C_NQUEUE], sh);
+  if (threadIdx.x < 64) {
+    // offsets of the mask groups and one allocation for the workgroup
+    const int32_t v = qoff[threadIdx.x];
+    int32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t o = __shfl_up(incl, d, 64);
+      if ((int)threadIdx.x >= d) incl += o;
+    }
+    qoff[threadIdx.x] = incl - v;
+    if (threadIdx.x == 63) qbase = incl > 0 ? atomicAdd(&counters[C_NQUEUE], incl) : 0;
+  }
+  __syncthreads();
   if (n1 + n2 == 0) return;
   for (int64_t k = lo[2]; k <= hi[2]; ++k)
     for (int64_t j = lo[1]; j <= hi[1]; ++j)
@@ -179,13 +198,13 @@ __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, con
             ++p;
           }
         } else if (cls == 2) {
+          const int64_t q = (int64_t)qbase + atomicAdd(&qoff[crossing_mask(g, T, i, j, k)], 1);
           if (q < q_cap) {
             P.lin[P.cap + q] = (int32_t)lin;
             P.tri[P.cap + q] = t;
           } else {
             atomicOr(&counters[C_ERR], ERR_CAPACITY);
           }
-          ++q;
         }
       }
 }
@@ -204,7 +223,7 @@ __global__ __launch_bounds__(kPieceLanes) void k_clip_queue(Grid g, const int4* 
       const int32_t lin = P.lin[slot];
       const Cell3 c = unpack_cell(g, lin);
       const Tri T = load_tri_packed(tri4, vtx4, P.tri[slot]);
-      const Piece pc = clip_piece(g, T, c.i, c.j, c.k, L, lane);
+      const Piece pc = clip_piece(g, T, c.i, c.j, c.k, L, lane, inside_mask(g, T, c.i, c.j, c.k));
       if (pc.keep) {
         atomicOr(&bitmap[lin >> 5], 1u << (lin & 31));
         P.flux[slot] = pc.flux;

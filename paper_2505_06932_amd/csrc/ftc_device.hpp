@@ -243,6 +243,51 @@ __host__ __device__ inline int classify_candidate(const Grid& g, const Tri& T, i
   return 1;
 }
 
+// Stages whose plane has triangle corners on both sides (the closed
+// inside test of the clipping): bit s for stage s.  Candidates with equal
+// masks take the same branches through most of the clipping.
+__host__ __device__ inline uint32_t crossing_mask(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k) {
+  const int64_t ijk[3] = {i, j, k};
+  uint32_t mask = 0u;
+#pragma unroll
+  for (int stage = 0; stage < 6; ++stage) {
+    const int d = stage >> 1;
+    const bool upper = stage & 1;
+    const double c = grid_plane(dim_org(g, d), ijk[d] + (upper ? 1 : 0), g.h);
+    const double a = T.v[0][d], b = T.v[1][d], e = T.v[2][d];
+    const bool ia = upper ? a <= c : a >= c, ib = upper ? b <= c : b >= c, ie = upper ? e <= c : e >= c;
+    if ((ia || ib || ie) && !(ia && ib && ie)) mask |= 1u << stage;
+  }
+  return mask;
+}
+
+// Stages that certainly cut nothing: every triangle corner lies inside the
+// stage's plane by more than 1e-12 (1 + X), X the largest corner coordinate
+// magnitude.  Every point the clipping emits is a rounded interpolation
+// between points it emitted before, within a few units in the last place of
+// X of the triangle's convex hull, so it lies inside such a plane as well:
+// the stage leaves the polygon whole (and only rotates it).
+__host__ __device__ inline uint32_t inside_mask(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k) {
+  const int64_t ijk[3] = {i, j, k};
+  double X = 0.0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) X = fmax(X, fabs(T.v[r][d]));
+  const double tol = 1e-12 * (1.0 + X);
+  uint32_t mask = 0u;
+#pragma unroll
+  for (int stage = 0; stage < 6; ++stage) {
+    const int d = stage >> 1;
+    const bool upper = stage & 1;
+    const double c = grid_plane(dim_org(g, d), ijk[d] + (upper ? 1 : 0), g.h);
+    const double mn = fmin(fmin(T.v[0][d], T.v[1][d]), T.v[2][d]);
+    const double mx = fmax(fmax(T.v[0][d], T.v[1][d]), T.v[2][d]);
+    if (upper ? (mx < c - tol) : (mn > c + tol)) mask |= 1u << stage;
+  }
+  return mask;
+}
+
 // Fan integrals of a polygon given by corner accessors (corner 0 is the fan
 // apex): membership by the vector area, flux and vol by the z-column rule.
 template <class CX>
@@ -303,9 +348,11 @@ __host__ __device__ inline double sel3(int d, double a, double b, double c) { re
 //    into logical order and every edge is processed in turn.
 // Either way the output is the stage's emission sequence (first kMaxPoly
 // corners), stored to LDS at positions 0.. and reloaded with rot = 0.
+// `skip`: stages known to cut nothing (a subset of inside_mask), which then
+// only rotate the polygon.
 template <int LANES>
 __host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k,
-                                            PolyLDS<LANES>& L, int lane) {
+                                            PolyLDS<LANES>& L, int lane, uint32_t skip = 0u) {
   Piece none{false, 0.0, 0.0};
   double lo[3], hi[3];
   if (!cell_planes(g, T, i, j, k, lo, hi)) return none;
@@ -322,6 +369,10 @@ __host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t
   for (int stage = 0; stage < 6; ++stage) {
     const int d = stage >> 1;
     const bool upper = stage & 1;
+    if ((skip >> stage) & 1u) {
+      rot = rot + 1 == n ? 0 : rot + 1;
+      continue;
+    }
     const double c = upper ? sel3(d, hi[0], hi[1], hi[2]) : sel3(d, lo[0], lo[1], lo[2]);
     uint32_t mp = 0;  // inside corners by physical slot
 #pragma unroll
