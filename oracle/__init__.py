@@ -79,6 +79,10 @@ def _load():
     lib.ora_csf.argtypes = [P(_Grid), P(C.c_double), C.c_int64, P(C.c_int64), P(C.c_double),
                             C.c_double, P(C.c_double)]
     lib.ora_csf.restype = C.c_int32
+    lib.ora_csf_band.argtypes = [P(_Grid), P(C.c_double), C.c_int64, P(C.c_int64), P(C.c_double),
+                                 P(C.c_double), C.c_double, C.c_int64, P(C.c_int64), P(C.c_double),
+                                 P(C.c_double)]
+    lib.ora_csf_band.restype = C.c_int64
     lib.ora_interp.argtypes = [P(_Grid), C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double),
                                P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.ora_interp.restype = C.c_int32
@@ -230,6 +234,26 @@ def csf(grid, alpha, cell_ids, kappa, sigma: float):
     if r != 0:
         raise OracleError(r, "csf")
     return f
+
+
+def csf_band(grid, alpha, cell_ids, kappa, normal, sigma: float):
+    """BAND mode: (band_ids, kappa_bar, force[n,3]) for the face neighbours of
+    the interfacial cells that are not interfacial themselves."""
+    lib = _load()
+    k = _Keep(grid)
+    al = _f64(alpha).reshape(-1)
+    ids = np.ascontiguousarray(cell_ids, dtype=np.int64)
+    kp = _f64(kappa)
+    nr = np.ascontiguousarray(normal, dtype=np.float64).reshape(-1)
+    cap = 6 * len(ids)
+    bid = np.empty(cap, np.int64)
+    kb = np.empty(cap)
+    f = np.empty((cap, 3))
+    n = int(lib.ora_csf_band(C.byref(k.g), _dp(al), len(ids), _lp(ids), _dp(kp), _dp(nr), float(sigma), cap,
+                             _lp(bid), _dp(kb), _dp(f)))
+    if n < 0:
+        raise OracleError(n, "csf_band")
+    return bid[:n], kb[:n], f[:n]
 
 
 def interp(grid, x, y, z, U, V, W):

@@ -678,6 +678,92 @@ int32_t ora_csf(const ora_grid* g, const double* alpha, int64_t ncell, const int
   return 0;
 }
 
+/* BAND mode (paper sec. 3.3): the curvature of a cell next to the interface
+   is the average of the curvatures of the interfacial cells around it,
+   weighted by how well the offset to each lines up with its interface
+   normal: kappa_bar_P = sum_Q kappa_Q w_Q / sum_Q w_Q, w_Q = |s_Q . n_Q| /
+   |s_Q|, s_Q from the centre of P to the centre of Q.  Read here as: P runs
+   over the cells sharing a face with an interfacial cell without being
+   interfacial, Q over the interfacial cells among P's 26 neighbours (block
+   order, x fastest) whose curvature is finite; sum w_Q = 0 falls back to the
+   plain mean, no such Q gives NaN.  s_Q = (di, dj, dk) h, so
+   w_Q = |di n_x + dj n_y + dk n_z| / sqrt(di^2 + dj^2 + dk^2). */
+static int64_t find_cell(const int64_t* ids, int64_t n, int64_t c) {
+  int64_t lo = 0, hi = n - 1;
+  while (lo <= hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (ids[mid] == c) return mid;
+    if (ids[mid] < c) lo = mid + 1; else hi = mid - 1;
+  }
+  return -1;
+}
+
+int64_t ora_csf_band(const ora_grid* g, const double* alpha, int64_t ncell, const int64_t* cell_ids,
+                     const double* kappa, const double* nrm, double sigma, int64_t cap, int64_t* band_ids,
+                     double* kappa_band, double* f) {
+  if (!grid_ok(g) || !alpha || ncell < 0 || cap < 0 || (ncell > 0 && (!cell_ids || !kappa || !nrm)) ||
+      (cap > 0 && (!band_ids || !kappa_band || !f)))
+    return -1;
+  const int64_t nx = g->nx, ny = g->ny, nz = g->nz, ntot = nx * ny * nz;
+  for (int64_t q = 1; q < ncell; ++q)
+    if (cell_ids[q] <= cell_ids[q - 1]) return -1; /* ascending, as the cell lists give them */
+  unsigned char* mark = (unsigned char*)calloc((size_t)ntot, 1);
+  if (!mark) return -1;
+  for (int64_t q = 0; q < ncell; ++q) mark[cell_ids[q]] = 1;
+  for (int64_t q = 0; q < ncell; ++q) {
+    const int64_t c = cell_ids[q];
+    const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    const int64_t nb[6][3] = {{i - 1, j, k}, {i + 1, j, k}, {i, j - 1, k}, {i, j + 1, k}, {i, j, k - 1}, {i, j, k + 1}};
+    for (int e = 0; e < 6; ++e) {
+      const int64_t a = nb[e][0], b = nb[e][1], d = nb[e][2];
+      if (a < 0 || b < 0 || d < 0 || a >= nx || b >= ny || d >= nz) continue;
+      const int64_t cn = a + nx * (b + ny * d);
+      if (mark[cn] == 0) mark[cn] = 2;
+    }
+  }
+  int64_t nb_out = 0;
+  int bad = 0;
+  for (int64_t c = 0; c < ntot; ++c) {
+    if (mark[c] != 2) continue;
+    const int64_t i = c % nx, j = (c / nx) % ny, k = c / (nx * ny);
+    if (i < 1 || j < 1 || k < 1 || i > nx - 2 || j > ny - 2 || k > nz - 2) { bad = 1; break; }
+    double sw = 0.0, swk = 0.0, sk = 0.0;
+    int64_t nq = 0;
+    for (int dk = -1; dk <= 1; ++dk)
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          if (di == 0 && dj == 0 && dk == 0) continue;
+          const int64_t cq = (i + di) + nx * ((j + dj) + ny * (k + dk));
+          if (mark[cq] != 1) continue;
+          const int64_t q = find_cell(cell_ids, ncell, cq);
+          if (q < 0 || !isfinite(kappa[q])) continue;
+          const double sn = (double)di * nrm[3 * q] + (double)dj * nrm[3 * q + 1] + (double)dk * nrm[3 * q + 2];
+          const double w = fabs(sn) / sqrt((double)(di * di + dj * dj + dk * dk));
+          sw += w;
+          swk += kappa[q] * w;
+          sk += kappa[q];
+          ++nq;
+        }
+    double kb;
+    if (nq == 0) kb = NAN;
+    else if (sw > 0.0) kb = swk / sw;
+    else kb = sk / (double)nq;
+    if (nb_out < cap) {
+      const double gx = (alpha[c + 1] - alpha[c - 1]) / (2.0 * g->h);
+      const double gy = (alpha[c + nx] - alpha[c - nx]) / (2.0 * g->h);
+      const double gz = (alpha[c + nx * ny] - alpha[c - nx * ny]) / (2.0 * g->h);
+      band_ids[nb_out] = c;
+      kappa_band[nb_out] = kb;
+      f[3 * nb_out + 0] = sigma * kb * gx;
+      f[3 * nb_out + 1] = sigma * kb * gy;
+      f[3 * nb_out + 2] = sigma * kb * gz;
+    }
+    ++nb_out;
+  }
+  free(mark);
+  return bad ? -2 : nb_out;
+}
+
 /* ------------------------------------------------------------------------ */
 /* divergence-preserving interpolation                                      */
 /* ------------------------------------------------------------------------ */

@@ -86,6 +86,20 @@ int32_t ora_csf(const ora_grid* g, const double* alpha, int64_t ncell,
                 const int64_t* cell_ids, const double* kappa, double sigma,
                 double* f);
 
+/* BAND mode of the CSF source (paper sec. 3.3, weighted curvature
+   smoothing): the cells sharing a face with an interfacial cell and not
+   interfacial themselves, ascending linear id, with the weighted average
+   kappa_bar of the finite curvatures of the interfacial cells among their
+   26 neighbours (weights |s.n|/|s|, plain mean if they all vanish, NaN
+   if there is none) and the source sigma kappa_bar grad(alpha).
+   cell_ids ascending; nrm[3*ncell] the interface normals.  Writes the first
+   `cap` band cells; returns their total number, -1 or -2 (a band cell on
+   the grid boundary). */
+int64_t ora_csf_band(const ora_grid* g, const double* alpha, int64_t ncell,
+                     const int64_t* cell_ids, const double* kappa, const double* nrm,
+                     double sigma, int64_t cap, int64_t* band_ids, double* kappa_band,
+                     double* f);
+
 /* Divergence-preserving interpolation (paper sec. 3.1) of the staggered face
    velocities to the points (x, y, z)[n]; u[3*n].  Returns 0 or -2. */
 int32_t ora_interp(const ora_grid* g, int32_t n, const double* x, const double* y,

@@ -22,6 +22,90 @@ def test_csf_is_sigma_kappa_central_gradient(oracle):
     assert np.abs(f - ref).max() <= 1e-14
 
 
+# ------------------------------------------------------------ BAND mode
+def _lin(g, i, j, k):
+    return i + g.nx * (j + g.ny * k)
+
+
+def test_band_set_is_face_neighbours_minus_interfacial(oracle):
+    """The band is exactly the cells sharing a face with an interfacial
+    cell and not interfacial, in ascending linear id (set computed here by
+    brute force over the 6 face offsets)."""
+    g, m, c = I.make_workload("sphere_32", 1)
+    cells, _, _ = oracle.cell_lists(g, m)
+    alpha, _ = oracle.volume_fraction(g, m)
+    r = oracle.ppic(g, m, cells)
+    bid, kb, f = oracle.csf_band(g, alpha, cells, r["kappa"], r["normal"], 1.0)
+    cs = set(int(x) for x in cells)
+    ref = set()
+    for cl in cs:
+        i, j, k = cl % g.nx, (cl // g.nx) % g.ny, cl // (g.nx * g.ny)
+        for di, dj, dk in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+            n = _lin(g, i + di, j + dj, k + dk)
+            if n not in cs:
+                ref.add(n)
+    assert list(bid) == sorted(ref)
+    # on a sphere every kappa is near 2/R, so every weighted mean is too
+    assert np.all(np.abs(kb * 0.25 / 2 - 1) < 0.02)
+
+
+def test_band_weighted_mean_by_hand(oracle):
+    """Two interfacial cells Q1 = (4,4,4) with kappa 1, Q2 = (5,4,4) with
+    kappa 3, both with normal +z.  Band cell P = (4,4,5) (above Q1): offsets
+    s1 = (0,0,-1), s2 = (1,0,-1), weights 1 and 1/sqrt(2).  Band cell
+    (3,4,4) (beside Q1): only Q1 is a neighbour... and Q2 is not (two cells
+    away); its weight |s.n| = 0, so the plain mean, 1."""
+    g = I.Grid(10, 10, 10, 0.0, 0.0, 0.0, 0.1)
+    cells = np.array([_lin(g, 4, 4, 4), _lin(g, 5, 4, 4)])
+    kap = np.array([1.0, 3.0])
+    nrm = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, 1.0]])
+    alpha = np.zeros((g.nz, g.ny, g.nx))
+    bid, kb, f = oracle.csf_band(g, alpha, cells, kap, nrm, 1.0)
+    got = dict(zip(bid.tolist(), kb.tolist()))
+    w2 = 1 / math.sqrt(2)
+    assert got[_lin(g, 4, 4, 5)] == pytest.approx((1 + 3 * w2) / (1 + w2), rel=1e-15)
+    assert got[_lin(g, 5, 4, 5)] == pytest.approx((3 + 1 * w2) / (1 + w2), rel=1e-15)
+    assert got[_lin(g, 3, 4, 4)] == 1.0
+    assert got[_lin(g, 6, 4, 4)] == 3.0
+    # (4,5,4) touches both by an edge or face, all in the plane z = const:
+    # every weight vanishes, plain mean of 1 and 3
+    assert got[_lin(g, 4, 5, 4)] == 2.0
+    assert len(bid) == 10  # 6 + 6 face neighbours minus the two cells themselves
+    assert np.all(f == 0.0)  # alpha is flat
+
+
+def test_band_constant_curvature_and_nan_handling(oracle):
+    """A constant curvature field is reproduced (weighted mean of equal
+    values); a NaN curvature is left out, and a band cell whose only
+    interfacial neighbour has NaN curvature gets NaN; the source is
+    sigma kappa_bar times the central gradient."""
+    g, m, c = I.make_workload("sphere_32", 2)
+    cells, _, _ = oracle.cell_lists(g, m)
+    alpha, _ = oracle.volume_fraction(g, m)
+    r = oracle.ppic(g, m, cells)
+    kap = np.full(len(cells), 3.25)
+    bid, kb, f = oracle.csf_band(g, alpha, cells, kap, r["normal"], 0.5)
+    # a weighted mean of at most 26 equal values: within (2 n + 2) unit
+    # roundoffs of the value
+    assert np.all(np.abs(kb - 3.25) <= 54 * 2.0 ** -53 * 3.25)
+    a = alpha.reshape(-1)
+    gx = (a[bid + 1] - a[bid - 1]) / (2 * g.h)
+    gy = (a[bid + g.nx] - a[bid - g.nx]) / (2 * g.h)
+    gz = (a[bid + g.nx * g.ny] - a[bid - g.nx * g.ny]) / (2 * g.h)
+    assert np.array_equal(f, 0.5 * kb[:, None] * np.stack([gx, gy, gz], 1))
+    g2 = I.Grid(8, 8, 8, 0.0, 0.0, 0.0, 0.125)
+    one = np.array([_lin(g2, 3, 3, 3)])
+    bid2, kb2, _ = oracle.csf_band(g2, np.zeros((8, 8, 8)), one, np.array([np.nan]), np.array([[0.0, 0, 1]]), 1.0)
+    assert len(bid2) == 6 and np.all(np.isnan(kb2))
+    two = np.array([_lin(g2, 3, 3, 3), _lin(g2, 3, 3, 4)])
+    bid3, kb3, _ = oracle.csf_band(g2, np.zeros((8, 8, 8)), two, np.array([np.nan, 2.0]),
+                                   np.array([[0.0, 0, 1], [0.0, 0, 1]]), 1.0)
+    got = dict(zip(bid3.tolist(), kb3.tolist()))
+    assert got[_lin(g2, 3, 3, 5)] == 2.0       # above the finite one
+    assert math.isnan(got[_lin(g2, 3, 3, 2)])  # below the NaN one, the finite one two cells away
+    assert got[_lin(g2, 4, 3, 3)] == 2.0       # beside the NaN one, diagonal to the finite one
+
+
 def test_csf_sphere_force_points_inward_with_magnitude(oracle):
     """On a sphere the CSF force in interfacial cells points to the centre;
     summed over all cells, sum |S| h^3 over interfacial cells stays within the
