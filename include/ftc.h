@@ -172,6 +172,28 @@ ftc_status ftc_csf_force(const ftc_cells* cells, const ftc_grid* grid, const dou
                          const double* kappa, double sigma, double* fx, double* fy, double* fz,
                          void* stream);
 
+/* Band mode of the continuum surface force (paper section 3.3, weighted
+   curvature smoothing in the neighbours of interfacial cells): for every
+   cell P that shares a face with an interfacial cell and is not interfacial
+   itself, kappa_bar_P = sum_Q kappa_Q w_Q / sum_Q w_Q over the interfacial
+   cells Q among P's 26 neighbours whose kappa is finite, with
+   w_Q = |s_Q . n_Q| / |s_Q|, s_Q from P's centre to Q's and n_Q the
+   interface normal of Q (nx, ny, nz from ftc_ppic_curvature); the plain
+   mean of those kappa_Q if every w_Q is 0, NaN if there is no such Q.  The
+   source is S_P = sigma kappa_bar_P grad(alpha)_P (central differences of
+   alpha_dense, as ftc_csf_force; the interfacial cells keep their own kappa
+   and source from ftc_csf_force).  Outputs, each [band_capacity], in
+   ascending linear cell id: band_ids (linear ids), kappa_band, fx, fy, fz;
+   *d_n_band [device int32] receives the number of band cells, which may
+   exceed band_capacity (six times the interfacial cell count always
+   suffices); then FTC_ECAPACITY is latched and only the first
+   band_capacity are written.  Uses the interfacial cells of the last
+   build. */
+ftc_status ftc_csf_force_band(ftc_cells* cells, const ftc_grid* grid, const double* alpha_dense,
+                              const double* kappa, const double* nx, const double* ny, const double* nz,
+                              double sigma, int32_t band_capacity, int32_t* band_ids, double* kappa_band,
+                              double* fx, double* fy, double* fz, int32_t* d_n_band, void* stream);
+
 /* Divergence-preserving interpolation (paper section 3.1) of staggered
    normal face velocities to the front vertices: inside the cell holding the
    vertex, linear interpolation between opposite faces plus transverse-

@@ -117,6 +117,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(scan_tmp, ftc::kScanMaxBlocks);
   FTC_ALLOC(bitmap, nwords);
   FTC_ALLOC(word_off, nwords + 1);
+  FTC_ALLOC(band_off, nwords + 1);
   w.queue_cap = 2 * P + 1024;  // candidates that need clipping can outnumber pieces
   FTC_ALLOC(pair_cell, P + w.queue_cap);
   FTC_ALLOC(pair_tri, P + w.queue_cap);
@@ -258,6 +259,18 @@ ftc_status ftc_csf_force(const ftc_cells* cells, const ftc_grid* grid, const dou
     return FTC_EINVAL;
   if (!on_device(cells)) return FTC_EINVAL;
   return hip_status(ftc::launch_csf(cells, alpha_dense, kappa, sigma, fx, fy, fz, (hipStream_t)stream));
+}
+
+ftc_status ftc_csf_force_band(ftc_cells* cells, const ftc_grid* grid, const double* alpha_dense,
+                              const double* kappa, const double* nx, const double* ny, const double* nz, double sigma,
+                              int32_t band_capacity, int32_t* band_ids, double* kappa_band, double* fx, double* fy,
+                              double* fz, int32_t* d_n_band, void* stream) {
+  if (!cells || !grid_valid(grid) || !same_grid(cells->grid, grid) || !alpha_dense || !kappa || !nx || !ny || !nz ||
+      !band_ids || !kappa_band || !fx || !fy || !fz || !d_n_band || band_capacity <= 0 || !isfinite(sigma))
+    return FTC_EINVAL;
+  if (!on_device(cells)) return FTC_EINVAL;
+  return hip_status(ftc::launch_csf_band(cells, alpha_dense, kappa, nx, ny, nz, sigma, band_capacity, band_ids,
+                                         kappa_band, fx, fy, fz, d_n_band, (hipStream_t)stream));
 }
 
 ftc_status ftc_interp_vertex_velocity(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh, const double* U,

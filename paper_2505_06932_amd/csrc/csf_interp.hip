@@ -29,6 +29,53 @@ __global__ __launch_bounds__(kT) void k_csf(Grid g, const int32_t* cell_ids, con
   }
 }
 
+// Band mode: per band cell (face neighbour of an interfacial cell, not
+// interfacial), the weighted average of the finite curvatures of the
+// interfacial cells among its 26 neighbours (block order, x fastest) with
+// weights |s.n| / |s|, s = (di, dj, dk) h the offset to the neighbour and n
+// its interface normal; the plain mean if every weight vanishes, NaN if
+// there is no such neighbour.  Then sigma kappa_bar grad(alpha).  A band
+// cell is at least one cell inside the grid, so all its neighbours exist.
+__global__ __launch_bounds__(kT) void k_csf_band(Grid g, const uint32_t* bitmap, const int32_t* word_off,
+                                                 const double* alpha, const double* kappa, const double* nx,
+                                                 const double* ny, const double* nz, double sigma,
+                                                 const int32_t* band_ids, const int32_t* n_band, int32_t band_cap,
+                                                 double* kappa_band, double* fx, double* fy, double* fz,
+                                                 int32_t cell_cap) {
+  const int32_t nb = min(*n_band, band_cap);
+  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+  const double inv2h = 1.0 / (2.0 * g.h);
+  for (int32_t b = blockIdx.x * kT + threadIdx.x; b < nb; b += gridDim.x * kT) {
+    const int64_t lin = band_ids[b];
+    double sw = 0.0, swk = 0.0, sk = 0.0;
+    int32_t nq = 0;
+    for (int dk = -1; dk <= 1; ++dk)
+      for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+        for (int di = -1; di <= 1; ++di) {
+          if (di == 0 && dj == 0 && dk == 0) continue;
+          const int32_t q = cell_rank(bitmap, word_off, lin + di + dj * sy + dk * sz);
+          if (q < 0 || q >= cell_cap) continue;
+          const double kq = kappa[q];
+          if (!isfinite(kq)) continue;
+          const double sn = (double)di * nx[q] + (double)dj * ny[q] + (double)dk * nz[q];
+          const double w = fabs(sn) / sqrt((double)(di * di + dj * dj + dk * dk));
+          sw += w;
+          swk += kq * w;
+          sk += kq;
+          ++nq;
+        }
+    const double kb = nq == 0 ? NAN : (sw > 0.0 ? swk / sw : sk / (double)nq);
+    const double gx = (alpha[lin + 1] - alpha[lin - 1]) * inv2h;
+    const double gy = (alpha[lin + sy] - alpha[lin - sy]) * inv2h;
+    const double gz = (alpha[lin + sz] - alpha[lin - sz]) * inv2h;
+    kappa_band[b] = kb;
+    fx[b] = sigma * kb * gx;
+    fy[b] = sigma * kb * gy;
+    fz[b] = sigma * kb * gz;
+  }
+}
+
 __global__ __launch_bounds__(kT) void k_interp(Grid g, Mesh m, const double* U, const double* V, const double* W,
                                                double* ux, double* uy, double* uz, int32_t* counters) {
   const int32_t v = blockIdx.x * kT + threadIdx.x;
@@ -96,6 +143,19 @@ hipError_t launch_csf(const ftc_cells* ws, const double* alpha, const double* ka
   hipLaunchKernelGGL(k_csf, dim3(grid_blocks(ws->cell_cap, kT, 4096)), dim3(kT), 0, s, ws->grid, ws->cell_ids, alpha,
                      kappa, sigma, fx, fy, fz, ws->cell_cap, ws->counters);
   time_stop(ws, FTC_KERNEL_CSF, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const double* kappa, const double* nx,
+                           const double* ny, const double* nz, double sigma, int32_t band_cap, int32_t* band_ids,
+                           double* kappa_band, double* fx, double* fy, double* fz, int32_t* n_band, hipStream_t s) {
+  const Grid& g = ws->grid;
+  hipError_t e = scan_band_emit(ws->bitmap, ws->nwords, ws->ncell, g.nx, (int64_t)g.nx * g.ny, ws->band_off,
+                                ws->scan_tmp, n_band, band_ids, band_cap, ws->counters, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_csf_band, dim3(grid_blocks(band_cap, kT, 4096)), dim3(kT), 0, s, g, ws->bitmap, ws->word_off,
+                     alpha, kappa, nx, ny, nz, sigma, band_ids, n_band, band_cap, kappa_band, fx, fy, fz,
+                     ws->cell_cap);
   return hipGetLastError();
 }
 

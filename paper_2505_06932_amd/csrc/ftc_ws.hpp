@@ -39,6 +39,7 @@ struct ftc_cells {
   // cell lists
   uint32_t* bitmap;       // [nwords] one bit per grid cell: holds a piece
   int32_t* word_off;      // [nwords+1] exclusive scan of popcount(bitmap)
+  int32_t* band_off;      // [nwords+1] the same for the face-neighbour band (CSF band mode)
   // pair list: [0, pair_cap) whole-triangle pieces, [pair_cap, pair_cap +
   // queue_cap) candidates queued for clipping (cell -1 if no piece)
   int32_t* pair_cell;     // linear, then compact, cell of each piece
@@ -101,6 +102,13 @@ hipError_t scan_popcount(const uint32_t* words, int32_t* out, int64_t n, int32_t
 hipError_t scan_popcount_emit(const uint32_t* words, int32_t* out, int64_t n, int32_t* tmp, int32_t* total_out,
                               int32_t* ids, int32_t cap, int32_t* counters, hipStream_t s);
 
+// The same over the face-neighbour band of the occupancy bitmap (cells not
+// in it with a face neighbour in it; sy = nx, sz = nx ny), computed word by
+// word on the fly: out[nwords+1] offsets, ids the band cells' linear ids.
+hipError_t scan_band_emit(const uint32_t* bitmap, int64_t nwords, int64_t ncell, int64_t sy, int64_t sz, int32_t* out,
+                          int32_t* tmp, int32_t* total_out, int32_t* ids, int32_t cap, int32_t* counters,
+                          hipStream_t s);
+
 // Up to three independent exclusive scans in one pair of launches: segment
 // q turns in[0..n) into out[0..n] (total last, and into *total when
 // non-null); in place is allowed.
@@ -130,6 +138,9 @@ hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, 
                        hipStream_t s);
 hipError_t launch_csf(const ftc_cells* ws, const double* alpha, const double* kappa, double sigma, double* fx,
                       double* fy, double* fz, hipStream_t s);
+hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const double* kappa, const double* nx,
+                           const double* ny, const double* nz, double sigma, int32_t band_cap, int32_t* band_ids,
+                           double* kappa_band, double* fx, double* fy, double* fz, int32_t* n_band, hipStream_t s);
 hipError_t launch_interp(const ftc_cells* ws, const Grid& g, const Mesh& m, const double* U, const double* V,
                          const double* W, double* ux, double* uy, double* uz, hipStream_t s);
 

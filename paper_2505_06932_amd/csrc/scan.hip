@@ -22,6 +22,41 @@ struct LoadPop {
   __device__ int32_t operator()(int64_t i) const { return __popc(p[i]); }
 };
 
+// Words of the face-neighbour band of the occupancy bitmap I: bit q of word
+// w is set for cell c = 32 w + q when c is not in I and one of c -+ 1,
+// c -+ sy, c -+ sz is.  Every set cell of I lies at least two cells inside
+// the grid, so these linear shifts reach exactly its face neighbours (a
+// shift that wraps a row or slice lands on a boundary cell, never set).
+struct BandWords {
+  const uint32_t* I;
+  int64_t nwords, ncell, sy, sz;
+  // the 32 bits of I from cell `start` on (zero outside the grid)
+  __device__ uint32_t bits_at(int64_t start) const {
+    const int64_t w = start >= 0 ? start >> 5 : -((-start + 31) >> 5);
+    const int off = (int)(start - 32 * w);
+    const uint32_t lo = (w >= 0 && w < nwords) ? I[w] : 0u;
+    const uint32_t hi = (w + 1 >= 0 && w + 1 < nwords) ? I[w + 1] : 0u;
+    return off == 0 ? lo : ((lo >> off) | (hi << (32 - off)));
+  }
+  __device__ uint32_t word(int64_t w) const {
+    const int64_t b = 32 * w;
+    const uint32_t nb = bits_at(b - 1) | bits_at(b + 1) | bits_at(b - sy) | bits_at(b + sy) | bits_at(b - sz) |
+                        bits_at(b + sz);
+    uint32_t band = nb & ~I[w];
+    const int64_t rest = ncell - b;  // cells of this word inside the grid
+    if (rest < 32) band &= rest > 0 ? ((1u << rest) - 1u) : 0u;
+    return band;
+  }
+};
+struct LoadBandPop {
+  BandWords B;
+  __device__ int32_t operator()(int64_t i) const { return __popc(B.word(i)); }
+};
+struct WordsPlain {
+  const uint32_t* p;
+  __device__ uint32_t word(int64_t i) const { return p[i]; }
+};
+
 // Inclusive scan across one wavefront of 64 lanes.
 __device__ inline int32_t wave_incl_scan(int32_t v) {
   const int lane = threadIdx.x & 63;
@@ -146,9 +181,10 @@ __global__ __launch_bounds__(kThreads) void k_block_apply_multi(MultiSeg M, cons
 // Second pass of the popcount scan that also lists the set bits: every set
 // bit b of word w becomes entry out[w] + (rank of b in w) of `ids`, with the
 // value 32 w + b (entries at or past `cap` latch a capacity error).
-__global__ __launch_bounds__(kThreads) void k_block_apply_emit(const uint32_t* words, int64_t n, const int32_t* tmp,
-                                                               int32_t* out, int32_t* total_out, int64_t nb,
-                                                               int32_t* ids, int32_t cap, int32_t* counters) {
+template <class WL>
+__global__ __launch_bounds__(kThreads) void k_block_apply_emit(WL words, int64_t n, const int32_t* tmp, int32_t* out,
+                                                               int32_t* total_out, int64_t nb, int32_t* ids,
+                                                               int32_t cap, int32_t* counters) {
   const int64_t b = blockIdx.x;
   const int32_t prefix = block_sum_prefix(tmp, b);
   const int64_t base = b * kScanBlock + (int64_t)threadIdx.x * kItems;
@@ -156,7 +192,7 @@ __global__ __launch_bounds__(kThreads) void k_block_apply_emit(const uint32_t* w
   int32_t s = 0;
 #pragma unroll
   for (int q = 0; q < kItems; ++q) {
-    wv[q] = (base + q < n) ? words[base + q] : 0u;
+    wv[q] = (base + q < n) ? words.word(base + q) : 0u;
     s += __popc(wv[q]);
   }
   int32_t total;
@@ -214,8 +250,21 @@ hipError_t scan_popcount_emit(const uint32_t* words, int32_t* out, int64_t n, in
   if (n < 0 || n > kScanMax) return hipErrorInvalidValue;
   const int64_t nb = std::max<int64_t>((n + kScanBlock - 1) / kScanBlock, 1);
   hipLaunchKernelGGL(k_block_totals<LoadPop>, dim3((unsigned)nb), dim3(kThreads), 0, s, LoadPop{words}, n, tmp);
-  hipLaunchKernelGGL(k_block_apply_emit, dim3((unsigned)nb), dim3(kThreads), 0, s, words, n, (const int32_t*)tmp, out,
-                     total_out, nb, ids, cap, counters);
+  hipLaunchKernelGGL(k_block_apply_emit<WordsPlain>, dim3((unsigned)nb), dim3(kThreads), 0, s, WordsPlain{words}, n,
+                     (const int32_t*)tmp, out, total_out, nb, ids, cap, counters);
+  return hipGetLastError();
+}
+
+hipError_t scan_band_emit(const uint32_t* bitmap, int64_t nwords, int64_t ncell, int64_t sy, int64_t sz, int32_t* out,
+                          int32_t* tmp, int32_t* total_out, int32_t* ids, int32_t cap, int32_t* counters,
+                          hipStream_t s) {
+  if (nwords < 0 || nwords > kScanMax) return hipErrorInvalidValue;
+  const BandWords B{bitmap, nwords, ncell, sy, sz};
+  const int64_t nb = std::max<int64_t>((nwords + kScanBlock - 1) / kScanBlock, 1);
+  hipLaunchKernelGGL(k_block_totals<LoadBandPop>, dim3((unsigned)nb), dim3(kThreads), 0, s, LoadBandPop{B}, nwords,
+                     tmp);
+  hipLaunchKernelGGL(k_block_apply_emit<BandWords>, dim3((unsigned)nb), dim3(kThreads), 0, s, B, nwords,
+                     (const int32_t*)tmp, out, total_out, nb, ids, cap, counters);
   return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@ FTC_CELL_RANK, FTC_CELL_OVERFLOW = 1, 2
 EXPORTED = ["ftc_cells_create", "ftc_cells_destroy", "ftc_build_cell_lists", "ftc_cells_count",
             "ftc_cells_view", "ftc_volume_fraction", "ftc_ppic_curvature", "ftc_csf_force",
             "ftc_interp_vertex_velocity", "ftc_last_device_error", "ftc_set_timing", "ftc_kernel_time",
+            "ftc_csf_force_band",
             "ftc_status_str"]
 
 # ftc_kernel values (timing)
@@ -99,6 +100,9 @@ def lib() -> C.CDLL:
     L.ftc_ppic_curvature.restype = C.c_int32
     L.ftc_csf_force.argtypes = [vp, P(_CGrid), vp, vp, C.c_double, vp, vp, vp, vp]
     L.ftc_csf_force.restype = C.c_int32
+    L.ftc_csf_force_band.argtypes = [vp, P(_CGrid), vp, vp, vp, vp, vp, C.c_double, C.c_int32, vp, vp, vp, vp, vp,
+                                     vp, vp]
+    L.ftc_csf_force_band.restype = C.c_int32
     L.ftc_interp_vertex_velocity.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, vp, vp, vp, vp, vp]
     L.ftc_interp_vertex_velocity.restype = C.c_int32
     L.ftc_last_device_error.argtypes = [vp, P(C.c_int32), vp]
@@ -300,6 +304,25 @@ def csf_force(cells: Cells, grid: _inputs.Grid, alpha_dense, kappa, sigma: float
                                _ptr(fx, torch.float64, cap, "fx"), _ptr(fy, torch.float64, cap, "fy"),
                                _ptr(fz, torch.float64, cap, "fz"), _stream(stream)),
            "ftc_csf_force")
+
+
+def csf_force_band(cells: Cells, grid: _inputs.Grid, alpha_dense, kappa, nx, ny, nz, sigma: float, band_ids,
+                   kappa_band, fx, fy, fz, n_band, stream=None) -> None:
+    """Band mode: outputs sized by band_ids.numel() (the band capacity);
+    n_band is a one-element int32 device tensor receiving the band count."""
+    cg = c_grid(grid)
+    cap = cells.cell_capacity
+    bcap = int(band_ids.numel())
+    _check(lib().ftc_csf_force_band(cells.handle, C.byref(cg),
+                                    _ptr(alpha_dense, torch.float64, grid.ncell, "alpha"),
+                                    _ptr(kappa, torch.float64, cap, "kappa"), _ptr(nx, torch.float64, cap, "nx"),
+                                    _ptr(ny, torch.float64, cap, "ny"), _ptr(nz, torch.float64, cap, "nz"),
+                                    float(sigma), bcap, _ptr(band_ids, torch.int32, bcap, "band_ids"),
+                                    _ptr(kappa_band, torch.float64, bcap, "kappa_band"),
+                                    _ptr(fx, torch.float64, bcap, "fx"), _ptr(fy, torch.float64, bcap, "fy"),
+                                    _ptr(fz, torch.float64, bcap, "fz"), _ptr(n_band, torch.int32, 1, "n_band"),
+                                    _stream(stream)),
+           "ftc_csf_force_band")
 
 
 def interp_vertex_velocity(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, U, V, W, ux, uy, uz,

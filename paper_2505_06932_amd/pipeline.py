@@ -14,7 +14,7 @@ from . import inputs as I
 class CouplingStep:
     def __init__(self, grid: I.Grid, mesh: I.Mesh, U=None, V=None, W=None, sigma: float = 1.0,
                  params: ftc.PPICParams | None = None, margin: float = 1.25,
-                 pair_capacity: int | None = None, cell_capacity: int | None = None):
+                 pair_capacity: int | None = None, cell_capacity: int | None = None, band: bool = False):
         self.grid = grid
         self.sigma = float(sigma)
         self.params = params
@@ -53,6 +53,14 @@ class CouplingStep:
         self.diag = z(4 * cap, torch.int32)
         self.fx, self.fy, self.fz = z(cap), z(cap), z(cap)
         self.ux, self.uy, self.uz = z(nv), z(nv), z(nv)
+        self.band = band
+        if band:
+            # every band cell is a face neighbour of an interfacial cell
+            bcap = 6 * cap
+            self.band_ids = z(bcap, torch.int32)
+            self.kappa_band = z(bcap)
+            self.bx, self.by, self.bz = z(bcap), z(bcap), z(bcap)
+            self.n_band = z(1, torch.int32)
 
     # the hot path, split so that callers can time its parts
     def cells_and_alpha(self, stream=None):
@@ -67,6 +75,9 @@ class CouplingStep:
     def forces_and_velocities(self, stream=None):
         ftc.csf_force(self.cells, self.grid, self.alpha, self.kappa, self.sigma, self.fx, self.fy, self.fz,
                       stream)
+        if self.band:
+            ftc.csf_force_band(self.cells, self.grid, self.alpha, self.kappa, self.nx, self.ny, self.nz, self.sigma,
+                               self.band_ids, self.kappa_band, self.bx, self.by, self.bz, self.n_band, stream)
         ftc.interp_vertex_velocity(self.cells, self.grid, self.mesh, self.U, self.V, self.W, self.ux,
                                    self.uy, self.uz, stream)
 
@@ -92,4 +103,11 @@ class CouplingStep:
             diag=h(self.diag).reshape(4, cap)[:, :n_if].T,
             force=np.stack([h(self.fx)[:n_if], h(self.fy)[:n_if], h(self.fz)[:n_if]], 1),
             u=np.stack([h(self.ux), h(self.uy), h(self.uz)], 1),
+            **(self._band_results(h) if self.band else {}),
             error=self.cells.last_device_error())
+
+    def _band_results(self, h):
+        nb = int(h(self.n_band)[0])
+        nb = min(nb, self.band_ids.numel())
+        return dict(n_band=nb, band_ids=h(self.band_ids)[:nb].astype(np.int64), kappa_band=h(self.kappa_band)[:nb],
+                    band_force=np.stack([h(self.bx)[:nb], h(self.by)[:nb], h(self.bz)[:nb]], 1))

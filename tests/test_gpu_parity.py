@@ -111,6 +111,25 @@ def test_sphere_workloads_full_parity(oracle, name, seed):
     assert abs(np.mean(g["kappa"]) * R / 2 - 1) < 0.02
 
 
+# ---------------------------------------------------------------- CSF band mode
+@pytest.mark.parametrize("name,seed", [("sphere_32", 0), ("sphere_128", 0)])
+def test_csf_band_mode_parity(oracle, name, seed):
+    """Band cells listed exactly as the oracle lists them; their weighted
+    curvature within 1e-10 relative and their source within 1e-10 of the
+    largest, from the oracle's own curvatures and normals."""
+    grid, mesh, c = I.make_workload(name, seed)
+    step, g, o = run_pair(oracle, f"band {name}/{seed}", grid, mesh, band=True)
+    check_lists(g, o)
+    bid, kb, f = oracle.csf_band(grid, o["alpha"], o["cells"], o["kappa"], o["normal"], 1.0)
+    assert g["n_band"] == len(bid)
+    assert np.array_equal(g["band_ids"], bid)
+    assert np.array_equal(np.isnan(g["kappa_band"]), np.isnan(kb))
+    ok = ~np.isnan(kb)
+    assert np.all(np.abs(g["kappa_band"][ok] - kb[ok]) <= KAPPA_TOL * np.abs(kb[ok]))
+    scale = np.abs(f[ok]).max()
+    assert np.abs(g["band_force"][ok] - f[ok]).max() <= KAPPA_TOL * scale
+
+
 # ---------------------------------------------------------------- large configurations
 @pytest.mark.timeout(300)
 def test_batched_ellipsoids_full_parity(oracle):
