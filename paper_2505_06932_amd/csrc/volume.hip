@@ -53,7 +53,7 @@ __global__ void k_cell_sums(const int32_t* offsets, const double* piece_flux, co
 //      open: ERR_MESH), as must W below the lowest chunk.
 constexpr int kColLanes = 64;
 constexpr int kChunks = 8;
-constexpr int kSub = 8;  // cells of a chunk read at once
+constexpr int kSub = 16;  // cells of a chunk read at once
 
 struct ColArgs {
   Grid g;
@@ -110,9 +110,14 @@ __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
   int32_t ci[kSub];
   double fl[kSub], vo[kSub];
 
+  // a chunk of at most kSub cells is read once, for both walks
+  const bool once = khi - klo <= kSub;
   double tot = 0.0;
   for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSub) {
-    read_sub<false>(A, col_ok, i, j, k1, klo, ci, fl, vo);
+    if (once)
+      read_sub<true>(A, col_ok, i, j, k1, klo, ci, fl, vo);
+    else
+      read_sub<false>(A, col_ok, i, j, k1, klo, ci, fl, vo);
 #pragma unroll
     for (int q = 0; q < kSub; ++q)
       if (ci[q] >= 0) tot += fl[q];
@@ -124,7 +129,7 @@ __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
 
   bool bad = false;
   for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSub) {
-    read_sub<true>(A, col_ok, i, j, k1, klo, ci, fl, vo);
+    if (!once) read_sub<true>(A, col_ok, i, j, k1, klo, ci, fl, vo);
 #pragma unroll
     for (int q = 0; q < kSub; ++q) {
       const int32_t k = k1 - q;
