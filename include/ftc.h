@@ -85,9 +85,9 @@ typedef struct ftc_cells ftc_cells;
    of up to nv_capacity vertices and nt_capacity triangles, holding up to
    pair_capacity (cell, triangle) pieces and cell_capacity interfacial
    cells (candidates that must be clipped, up to twice pair_capacity, are
-   queued internally).  Device memory is about 104 B x pairs + 1.85 kB x cells
-   + 28 B x triangles + 52 B x vertices + nx*ny*nz/4 B (about 100 MB for a
-   128^3 grid with 82k triangles, 1.1 GB for 512^3 with 2M triangles).
+   queued internally).  Device memory is about 116 B x pairs + 1.85 kB x cells
+   + 40 B x triangles + 56 B x vertices + 3 nx*ny*nz/8 B (about 105 MB for a
+   128^3 grid with 82k triangles, 1.2 GB for 512^3 with 2M triangles).
    Returns FTC_EINVAL, FTC_ENOMEM or FTC_OK; *out is NULL on failure. */
 ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_capacity,
                             int32_t nt_capacity, int64_t pair_capacity, int32_t cell_capacity);

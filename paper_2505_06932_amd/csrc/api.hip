@@ -127,7 +127,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(tmp_pair, P);
   FTC_ALLOC(cell_ids, Cc);
   FTC_ALLOC(offsets, Cc + 1);
-  FTC_ALLOC(cursor, Cc);
+  FTC_ALLOC(pair_local, P + w.queue_cap);
   FTC_ALLOC(tri_ids, P);
   FTC_ALLOC(slot_cell, P);
   FTC_ALLOC(piece_flux, P);
@@ -136,6 +136,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(cell_vol, Cc);
   FTC_ALLOC(vt_off, Vc + 1);
   FTC_ALLOC(vt_cursor, Vc);
+  FTC_ALLOC(vt_loc, 3 * Tc);
   FTC_ALLOC(vt_ids, 3 * Tc);
   FTC_ALLOC(tri4, 4 * Tc);
   FTC_ALLOC(vtx4, 4 * Vc);
@@ -143,6 +144,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(vcell, Vc);
   FTC_ALLOC(vb_off, Cc + 1);
   FTC_ALLOC(vb_cursor, Cc);
+  FTC_ALLOC(vb_loc, Vc);
   FTC_ALLOC(vb_ids, Vc);
   FTC_ALLOC(stray, Vc);
   FTC_ALLOC(fit, ftc::kFitSlots * Cc);

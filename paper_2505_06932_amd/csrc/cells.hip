@@ -22,7 +22,8 @@
 // vertices binned by the interfacial cell holding them (counted in step 3,
 // grouped in step 4) and, from those bins, the closest vertex of every
 // interfacial cell.  Per-vertex and per-cell counts are zero between builds:
-// the grouping takes each back down to zero as it places the entries.
+// the prefix sums clear them as they read them, and each counted entry keeps
+// the index its count gave it, so the grouping needs no atomics.
 // After step 1 everything is integer work on device-resident counts, so the
 // sequence needs no host round trip and can be captured into a graph.
 #include <float.h>
@@ -51,14 +52,15 @@ __device__ inline int32_t distinct_corner(const Mesh& m, int32_t t, int r) {
 }
 
 // Clears the per-build state, packs the vertex coordinates as (x, y, z, 0)
-// and counts each vertex's incident triangles (one thread per corner).
-__global__ void k_clear_build(uint32_t* bitmap, int64_t nwords, int32_t* cell_cnt, int64_t ncnt, int32_t* cursor,
-                              int64_t ncur, int32_t* counters, Mesh m, double2* vtx4, int32_t* vt_cnt) {
+// and counts each vertex's incident triangles (one thread per corner, which
+// keeps its index within the vertex's list).
+__global__ void k_clear_build(uint32_t* bitmap, int64_t nwords, int32_t* cell_cnt, int64_t ncnt, int32_t* counters,
+                              Mesh m, double2* vtx4, int32_t* vt_cnt, int32_t* vt_loc) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t x = g0; x < 3 * (int64_t)m.nt; x += stride) {
     const int32_t v = distinct_corner(m, (int32_t)(x / 3), (int)(x % 3));
-    if (v >= 0) atomicAdd(&vt_cnt[v], 1);
+    if (v >= 0) vt_loc[x] = atomicAdd(&vt_cnt[v], 1);
   }
   for (int64_t v = g0; v < m.nv; v += stride) {
     vtx4[2 * v] = make_double2(m.x[v], m.y[v]);
@@ -66,7 +68,6 @@ __global__ void k_clear_build(uint32_t* bitmap, int64_t nwords, int32_t* cell_cn
   }
   for (int64_t i = g0; i < nwords; i += stride) bitmap[i] = 0u;
   for (int64_t i = g0; i < ncnt; i += stride) cell_cnt[i] = 0;
-  for (int64_t i = g0; i < ncur; i += stride) cursor[i] = 0;
   if (g0 < C_COUNT && g0 != C_ERR) counters[g0] = 0;
 }
 
@@ -259,15 +260,16 @@ struct VertexBins {
   const double2* vtx4;
   int32_t* vcell;   // interfacial cell of each vertex; -1: a cell without pieces (a stray), -2: outside the margin
   int32_t* vb_cnt;  // vertices per interfacial cell
+  int32_t* vb_loc;  // index of each vertex within its cell's bin
   int32_t* stray;
 };
 
-// pair -> compact cell (in place of its linear id), counted per cell; and
-// vertex -> the interfacial cell holding it, counted per cell (or listed as
-// a stray)
-__global__ void k_pair_count(int32_t* pair_lin, const uint32_t* bitmap, const int32_t* word_off, int32_t* cell_cnt,
-                             int32_t cell_cap, int64_t pair_cap, int64_t queue_cap, int32_t* counters, Grid g,
-                             VertexBins B) {
+// pair -> compact cell (in place of its linear id), counted per cell, its
+// index within the cell kept; and vertex -> the interfacial cell holding it,
+// counted per cell with its index kept (or listed as a stray)
+__global__ void k_pair_count(int32_t* pair_lin, int32_t* pair_local, const uint32_t* bitmap, const int32_t* word_off,
+                             int32_t* cell_cnt, int32_t cell_cap, int64_t pair_cap, int64_t queue_cap,
+                             int32_t* counters, Grid g, VertexBins B) {
   const PairRange R = pair_range(counters, pair_cap, queue_cap);
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < B.nv; v += gridDim.x * blockDim.x) {
     const P3 p = vtx(B.vtx4, v);
@@ -277,7 +279,7 @@ __global__ void k_pair_count(int32_t* pair_lin, const uint32_t* bitmap, const in
       ci = cell_rank(bitmap, word_off, i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
       if (ci >= cell_cap) ci = -1;
       if (ci >= 0)
-        atomicAdd(&B.vb_cnt[ci], 1);
+        B.vb_loc[v] = atomicAdd(&B.vb_cnt[ci], 1);
       else
         B.stray[atomicAdd(&counters[C_NSTRAY], 1)] = v;
     }
@@ -290,7 +292,7 @@ __global__ void k_pair_count(int32_t* pair_lin, const uint32_t* bitmap, const in
     const int32_t ci = rank_of(bitmap, word_off, lin);
     if (ci < cell_cap) {
       pair_lin[p] = ci;
-      atomicAdd(&cell_cnt[ci], 1);
+      pair_local[p] = atomicAdd(&cell_cnt[ci], 1);
     } else {
       pair_lin[p] = -1;  // its cell did not fit the capacity (latched while listing the cells)
     }
@@ -299,35 +301,36 @@ __global__ void k_pair_count(int32_t* pair_lin, const uint32_t* bitmap, const in
 
 struct Adjacency {
   const int32_t* vt_off;
-  int32_t* vt_cnt;  // taken back to zero
+  const int32_t* vt_loc;
   int32_t* vt_ids;
   const int32_t* vcell;
   const int32_t* vb_off;
-  int32_t* vb_cnt;  // taken back to zero
+  const int32_t* vb_loc;
   int32_t* vb_ids;
 };
 
-// Pairs into their cell's segment (any order); triangles into each distinct
-// corner's incident list and vertices into their cell's bin (any order).
-__global__ void k_pair_scatter(const int32_t* pair_ci, const int32_t* pair_tri, const int32_t* offsets,
-                               int32_t* cursor, int32_t* tmp_tri, int32_t* tmp_pair, int64_t pair_cap,
+// Pairs into their cell's segment, triangles into each distinct corner's
+// incident list and vertices into their cell's bin, each at the index the
+// counting gave it (an arbitrary order, fixed afterwards where it matters).
+__global__ void k_pair_scatter(const int32_t* pair_ci, const int32_t* pair_tri, const int32_t* pair_local,
+                               const int32_t* offsets, int32_t* tmp_tri, int32_t* tmp_pair, int64_t pair_cap,
                                int64_t queue_cap, int32_t* counters, Mesh m, Adjacency J) {
   const PairRange R = pair_range(counters, pair_cap, queue_cap);
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < 3 * (int64_t)m.nt;
        x += (int64_t)gridDim.x * blockDim.x) {
     const int32_t t = (int32_t)(x / 3);
     const int32_t v = distinct_corner(m, t, (int)(x % 3));
-    if (v >= 0) J.vt_ids[J.vt_off[v] + atomicSub(&J.vt_cnt[v], 1) - 1] = t;
+    if (v >= 0) J.vt_ids[J.vt_off[v] + J.vt_loc[x]] = t;
   }
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < m.nv; v += gridDim.x * blockDim.x) {
     const int32_t ci = J.vcell[v];
-    if (ci >= 0) J.vb_ids[J.vb_off[ci] + atomicSub(&J.vb_cnt[ci], 1) - 1] = v;
+    if (ci >= 0) J.vb_ids[J.vb_off[ci] + J.vb_loc[v]] = v;
   }
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < R.count(); x += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = R.slot(x);
     const int32_t ci = pair_ci[p];
     if (ci < 0) continue;
-    const int64_t pos = (int64_t)offsets[ci] + atomicAdd(&cursor[ci], 1);
+    const int64_t pos = (int64_t)offsets[ci] + pair_local[p];
     if (pos < pair_cap) {
       tmp_tri[pos] = pair_tri[p];
       tmp_pair[pos] = (int32_t)p;
@@ -483,8 +486,7 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
   int4* tri4 = reinterpret_cast<int4*>(ws->tri4);
   double2* vtx4 = reinterpret_cast<double2*>(ws->vtx4);
   hipLaunchKernelGGL(k_clear_build, dim3(kStrideBlocks), dim3(kT), 0, s, ws->bitmap, ws->nwords, ws->offsets,
-                     (int64_t)ws->cell_cap + 1, ws->cursor, (int64_t)ws->cell_cap, ws->counters, m, vtx4,
-                     ws->vt_cursor);
+                     (int64_t)ws->cell_cap + 1, ws->counters, m, vtx4, ws->vt_cursor, ws->vt_loc);
   PairOut P{ws->pair_cell, ws->pair_tri, ws->pair_flux, ws->pair_vol, ws->pair_cap};
   time_start(ws, FTC_KERNEL_TRI_PIECES, s);
   hipLaunchKernelGGL(k_tri_classify, dim3(grid_blocks(m.nt, kClassifyT)), dim3(kClassifyT), 0, s, g, m, vtx4, tri4,
@@ -496,18 +498,18 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
                                     ws->cell_ids, ws->cell_cap, ws->counters, s);
   if (e != hipSuccess) return e;
   const int64_t npair_max = ws->pair_cap + ws->queue_cap;
-  VertexBins B{m.nv, vtx4, ws->vcell, ws->vb_cursor, ws->stray};
+  VertexBins B{m.nv, vtx4, ws->vcell, ws->vb_cursor, ws->vb_loc, ws->stray};
   hipLaunchKernelGGL(k_pair_count, dim3(grid_blocks(npair_max, kT, kStrideBlocks)), dim3(kT), 0, s, ws->pair_cell,
-                     ws->bitmap, ws->word_off, ws->offsets, ws->cell_cap, ws->pair_cap, ws->queue_cap,
-                     ws->counters, g, B);
-  const ScanSeg segs[3] = {{ws->offsets, ws->offsets, ws->cell_cap, ws->counters + C_NPAIRS},
-                           {ws->vt_cursor, ws->vt_off, m.nv, nullptr},
-                           {ws->vb_cursor, ws->vb_off, ws->cell_cap, nullptr}};
+                     ws->pair_local, ws->bitmap, ws->word_off, ws->offsets, ws->cell_cap, ws->pair_cap,
+                     ws->queue_cap, ws->counters, g, B);
+  const ScanSeg segs[3] = {{ws->offsets, ws->offsets, ws->cell_cap, ws->counters + C_NPAIRS, nullptr},
+                           {ws->vt_cursor, ws->vt_off, m.nv, nullptr, ws->vt_cursor},
+                           {ws->vb_cursor, ws->vb_off, ws->cell_cap, nullptr, ws->vb_cursor}};
   e = scan_exclusive_multi(segs, 3, ws->scan_tmp, s);
   if (e != hipSuccess) return e;
-  Adjacency J{ws->vt_off, ws->vt_cursor, ws->vt_ids, ws->vcell, ws->vb_off, ws->vb_cursor, ws->vb_ids};
+  Adjacency J{ws->vt_off, ws->vt_loc, ws->vt_ids, ws->vcell, ws->vb_off, ws->vb_loc, ws->vb_ids};
   hipLaunchKernelGGL(k_pair_scatter, dim3(grid_blocks(npair_max, kT, kStrideBlocks)), dim3(kT), 0, s, ws->pair_cell,
-                     ws->pair_tri, ws->offsets, ws->cursor, ws->tmp_tri, ws->tmp_pair, ws->pair_cap, ws->queue_cap,
+                     ws->pair_tri, ws->pair_local, ws->offsets, ws->tmp_tri, ws->tmp_pair, ws->pair_cap, ws->queue_cap,
                      ws->counters, m, J);
   PlaceArgs A{ws->tmp_tri,  ws->tmp_pair,  ws->pair_cell,  ws->pair_flux, ws->pair_vol, ws->offsets,
               ws->tri_ids,  ws->slot_cell, ws->piece_flux, ws->piece_vol, ws->cell_cap, ws->pair_cap,

@@ -50,7 +50,7 @@ struct ftc_cells {
   int32_t* tmp_pair;      // [pair_cap] pair-list slot of each scattered piece
   int32_t* cell_ids;      // [cell_cap] linear ids, ascending
   int32_t* offsets;       // [cell_cap+1] CSR offsets into tri_ids
-  int32_t* cursor;        // [cell_cap] scatter cursors
+  int32_t* pair_local;    // [pair_cap + queue_cap] index of each pair within its cell, from the counting
   int32_t* tri_ids;       // [pair_cap] CSR triangle ids, ascending per cell
   int32_t* slot_cell;     // [pair_cap] compact cell of each CSR slot
   double* piece_flux;     // [pair_cap] integral of n_z dA per CSR slot
@@ -62,6 +62,7 @@ struct ftc_cells {
   // PPIC
   int32_t* vt_off;        // [nv_cap+1] offsets of each vertex's incident triangles
   int32_t* vt_cursor;     // [nv_cap] triangles per vertex while counting; zero between calls
+  int32_t* vt_loc;        // [3*nt_cap] index of each (triangle, corner) within the corner's list
   int32_t* vt_ids;        // [3*nt_cap] incident triangles, ascending per vertex
   int32_t* tri4;          // [4*nt_cap] corners of each triangle packed (t0, t1, t2, 0)
   double* vtx4;           // [4*nv_cap] coordinates of each vertex packed (x, y, z, 0)
@@ -69,6 +70,7 @@ struct ftc_cells {
   int32_t* vcell;         // [nv_cap] interfacial cell holding each vertex (-1: none, -2: outside)
   int32_t* vb_off;        // [cell_cap+1] offsets of each interfacial cell's vertices
   int32_t* vb_cursor;     // [cell_cap] vertices per cell while counting; zero between calls
+  int32_t* vb_loc;        // [nv_cap] index of each vertex within its cell's bin
   int32_t* vb_ids;        // [nv_cap] vertices grouped by interfacial cell
   int32_t* stray;         // [nv_cap] vertices in cells without pieces
   double* fit;            // [kFitSlots * cell_cap] per cell: normal equations (21 + 6), vertex normal (3), weighted count
@@ -117,6 +119,7 @@ struct ScanSeg {
   int32_t* out;
   int64_t n;
   int32_t* total;
+  int32_t* clear;  // NULL, or `in` again: set to zero once read (counts that must start the next call at zero)
 };
 constexpr int kMaxSeg = 3;
 hipError_t scan_exclusive_multi(const ScanSeg* segs, int nseg, int32_t* tmp, hipStream_t s);

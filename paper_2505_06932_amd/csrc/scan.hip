@@ -174,8 +174,16 @@ __global__ __launch_bounds__(kThreads) void k_block_totals_multi(MultiSeg M, int
 
 __global__ __launch_bounds__(kThreads) void k_block_apply_multi(MultiSeg M, const int32_t* tmp) {
   const int q = seg_of(M, blockIdx.x);
-  apply_one(LoadI32{M.seg[q].in}, M.seg[q].n, tmp + M.b0[q], M.seg[q].out, M.seg[q].total, blockIdx.x - M.b0[q],
+  const int64_t b = blockIdx.x - M.b0[q];
+  apply_one(LoadI32{M.seg[q].in}, M.seg[q].n, tmp + M.b0[q], M.seg[q].out, M.seg[q].total, b,
             M.b0[q + 1] - M.b0[q]);
+  if (M.seg[q].clear) {
+    // this thread's entries, already read by apply_one
+    const int64_t base = b * kScanBlock + (int64_t)threadIdx.x * kItems;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i)
+      if (base + i < M.seg[q].n) M.seg[q].clear[base + i] = 0;
+  }
 }
 
 // Second pass of the popcount scan that also lists the set bits: every set
@@ -283,6 +291,7 @@ hipError_t scan_exclusive_multi(const ScanSeg* segs, int nseg, int32_t* tmp, hip
   if (nb > kScanMaxBlocks) {
     for (int q = 0; q < nseg; ++q) {
       hipError_t e = scan_impl(LoadI32{segs[q].in}, segs[q].out, segs[q].n, tmp, segs[q].total, s);
+      if (e == hipSuccess && segs[q].clear) e = fill_i32(segs[q].clear, segs[q].n, 0, s);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
