@@ -83,6 +83,9 @@ def _load():
                                  P(C.c_double), C.c_double, C.c_int64, P(C.c_int64), P(C.c_double),
                                  P(C.c_double)]
     lib.ora_csf_band.restype = C.c_int64
+    lib.ora_advect_rk4.argtypes = [P(_Grid), C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double),
+                                   P(C.c_double), P(C.c_double), P(C.c_double), C.c_double, P(C.c_double)]
+    lib.ora_advect_rk4.restype = C.c_int32
     lib.ora_interp.argtypes = [P(_Grid), C.c_int32, P(C.c_double), P(C.c_double), P(C.c_double),
                                P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.ora_interp.restype = C.c_int32
@@ -267,6 +270,21 @@ def interp(grid, x, y, z, U, V, W):
     if r != 0:
         raise OracleError(r, "interp")
     return u
+
+
+def advect_rk4(grid, x, y, z, U, V, W, dt: float, check: bool = True):
+    """One RK4 step of the points through the interpolated field: new
+    positions [n, 3] (NaN where a stage point left the grid)."""
+    lib = _load()
+    k = _Keep(grid)
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    U, V, W = _f64(U).reshape(-1), _f64(V).reshape(-1), _f64(W).reshape(-1)
+    out = np.empty((len(x), 3))
+    r = int(lib.ora_advect_rk4(C.byref(k.g), len(x), _dp(x), _dp(y), _dp(z), _dp(U), _dp(V), _dp(W), float(dt),
+                               _dp(out)))
+    if r != 0 and check:
+        raise OracleError(r, "advect_rk4")
+    return out
 
 
 def interp_in_cell(grid, ijk, p, U, V, W):

@@ -828,6 +828,45 @@ int32_t ora_interp(const ora_grid* g, int32_t n, const double* x, const double* 
   return 0;
 }
 
+/* One classical fourth-order Runge-Kutta step (paper sec. 3.1: the front
+   vertices move with the interpolated velocity, dx/dt = u(x)) with the face
+   velocities held fixed over the step:
+     k1 = u(x), k2 = u(x + dt/2 k1), k3 = u(x + dt/2 k2), k4 = u(x + dt k3),
+     x' = x + dt/6 (k1 + 2 k2 + 2 k3 + k4),
+   each u the divergence-preserving interpolant in the cell holding the stage
+   point.  A vertex whose stage point leaves the admissible cells (index 1 to
+   n - 2 on every axis) gets NaN and the call returns -2. */
+static int stage_velocity(const ora_grid* g, const double p[3], const double* U, const double* V, const double* W,
+                          double u[3]) {
+  if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]))) return 0;
+  const int64_t i = cell_of(p[0], g->x0, g->h), j = cell_of(p[1], g->y0, g->h), k = cell_of(p[2], g->z0, g->h);
+  if (i < 1 || j < 1 || k < 1 || i > g->nx - 2 || j > g->ny - 2 || k > g->nz - 2) return 0;
+  ora_interp_in_cell(g, (int32_t)i, (int32_t)j, (int32_t)k, p[0], p[1], p[2], U, V, W, u);
+  return 1;
+}
+
+int32_t ora_advect_rk4(const ora_grid* g, int32_t n, const double* x, const double* y, const double* z,
+                       const double* U, const double* V, const double* W, double dt, double* out) {
+  if (!grid_ok(g) || n < 0 || !isfinite(dt) || (n > 0 && (!x || !y || !z || !U || !V || !W || !out))) return -1;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int32_t q = 0; q < n; ++q) {
+    const double p[3] = {x[q], y[q], z[q]};
+    double k1[3], k2[3], k3[3], k4[3], s[3];
+    int ok = stage_velocity(g, p, U, V, W, k1);
+    for (int d = 0; d < 3; ++d) s[d] = p[d] + (0.5 * dt) * k1[d];
+    ok = ok && stage_velocity(g, s, U, V, W, k2);
+    for (int d = 0; d < 3; ++d) s[d] = p[d] + (0.5 * dt) * k2[d];
+    ok = ok && stage_velocity(g, s, U, V, W, k3);
+    for (int d = 0; d < 3; ++d) s[d] = p[d] + dt * k3[d];
+    ok = ok && stage_velocity(g, s, U, V, W, k4);
+    for (int d = 0; d < 3; ++d)
+      out[3 * q + d] = ok ? p[d] + (dt / 6.0) * (((k1[d] + 2.0 * k2[d]) + 2.0 * k3[d]) + k4[d]) : NAN;
+    if (!ok) bad = 1;
+  }
+  return bad ? -2 : 0;
+}
+
 int32_t ora_threads(void) {
 #ifdef _OPENMP
   return (int32_t)omp_get_max_threads();

@@ -106,6 +106,14 @@ int32_t ora_interp(const ora_grid* g, int32_t n, const double* x, const double* 
                    const double* z, const double* U, const double* V,
                    const double* W, double* u);
 
+/* One classical fourth-order Runge-Kutta step of dx/dt = u(x) for the points
+   (x, y, z)[n], u the divergence-preserving interpolant of the fixed face
+   velocities; out[3*n] the new positions.  Returns 0, or -2 if a stage
+   point left the admissible cells (that point's output is NaN). */
+int32_t ora_advect_rk4(const ora_grid* g, int32_t n, const double* x, const double* y,
+                       const double* z, const double* U, const double* V,
+                       const double* W, double dt, double* out);
+
 /* The same polynomial evaluated in a given cell (i, j, k) at any point. */
 void ora_interp_in_cell(const ora_grid* g, int32_t i, int32_t j, int32_t k,
                         double x, double y, double z, const double* U,
