@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--workload", default="sphere_128")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph")
+    ap.add_argument("--mixed", action="store_true",
+                    help="PPIC normal equations formed in single precision and refined in double")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel for the "
@@ -92,7 +94,8 @@ def main():
     grid, mesh, centre = I.make_workload(args.workload, args.seed)
     U, V, W = I.psi_face_velocity(grid)
     log(f"[bench] workload={args.workload} grid={grid.nx}^3 nv={mesh.nv} nt={mesh.nt}")
-    step = pipeline.CouplingStep(grid, mesh, U, V, W, sigma=1.0)
+    params = ftc.PPICParams(precision=1) if args.mixed else None
+    step = pipeline.CouplingStep(grid, mesh, U, V, W, sigma=1.0, params=params)
     step.run()
     torch.cuda.synchronize()
     n_if, n_pairs = step.cells.count()
@@ -168,7 +171,7 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "interfacial cells/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32+f64" if args.mixed else "f64", "data": "synthetic",
         "config": {"workload": args.workload, "grid": [grid.nx, grid.ny, grid.nz], "triangles": mesh.nt,
                    "vertices": mesh.nv, "interfacial_cells": n_if, "pieces": n_pairs, "seed": args.seed,
                    "launch": launch, "step": "cell_lists+volume_fraction+ppic_curvature+csf_force+"
@@ -186,7 +189,7 @@ def main():
         while True:
             cells, offsets, tris = oracle.cell_lists(grid, mesh)
             alpha, _ = oracle.volume_fraction(grid, mesh)
-            r = oracle.ppic(grid, mesh, cells)
+            r = oracle.ppic(grid, mesh, cells)  # always double precision
             force = oracle.csf(grid, alpha, cells, r["kappa"], 1.0)
             u = oracle.interp(grid, mesh.x, mesh.y, mesh.z, U, V, W)
             reps += 1

@@ -64,13 +64,21 @@ typedef struct {
    support radius delta = delta_over_h * h (paper: 2.5), the `rings`-ring of
    triangles around the closest front vertex (paper: 3), the support grown by
    the factor `grow` at most `max_iter` times until at least `n_min`
-   triangles carry non-zero weight (paper: "24 to 48"). */
+   triangles carry non-zero weight (paper: "24 to 48").  precision: 0 forms
+   and solves the weighted normal equations in double precision; 1 forms and
+   factors them in single precision and refines the solution twice with
+   double-precision residuals of the same triangles (the curvature then
+   agrees with the double-precision solution to about cond(M)^3 times the
+   single-precision roundoff cubed; a single-precision pivot at or below
+   1e-6 of the trace flags the cell rank deficient).  Cells taken by the
+   wide ring shape are always solved in double precision. */
 typedef struct {
   double delta_over_h;
   int32_t rings;
   int32_t n_min;
   double grow;
   int32_t max_iter;
+  int32_t precision;
 } ftc_ppic_params;
 
 /* Per-cell status bits written by ftc_ppic_curvature. */
@@ -207,6 +215,20 @@ ftc_status ftc_csf_force_band(ftc_cells* cells, const ftc_grid* grid, const doub
 ftc_status ftc_interp_vertex_velocity(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
                                       const double* U, const double* V, const double* W, double* ux,
                                       double* uy, double* uz, void* stream);
+
+/* One classical fourth-order Runge-Kutta step of the front vertices through
+   the interpolated velocity (paper section 3.1: the vertices are advected in
+   a Lagrangian manner, dx/dt = u(x), with the fourth-order Runge-Kutta
+   scheme), the face velocities held fixed over the step:
+   k1 = u(x), k2 = u(x + dt/2 k1), k3 = u(x + dt/2 k2), k4 = u(x + dt k3),
+   x' = x + dt/6 (k1 + 2 k2 + 2 k3 + k4), u the interpolant of
+   ftc_interp_vertex_velocity.  x_out, y_out, z_out [mesh->nv] may be the
+   mesh's own coordinate arrays (each vertex is read before it is written).
+   A vertex whose stage point lies within 1 cell of the grid boundary gets
+   NaN and latches FTC_EDOMAIN.  `cells` supplies the error latch only. */
+ftc_status ftc_advect_vertices_rk4(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
+                                   const double* U, const double* V, const double* W, double dt,
+                                   double* x_out, double* y_out, double* z_out, void* stream);
 
 /* Read and clear the device-latched error of the workspace: *code [host]
    receives FTC_OK or the first of FTC_ECAPACITY, FTC_EDOMAIN, FTC_EMESH

@@ -242,11 +242,13 @@ ftc_status ftc_ppic_curvature(const ftc_cells* cells, const ftc_grid* grid, cons
   if (mesh->nv > cells->nv_cap || mesh->nt > cells->nt_cap || !kappa || !nx || !ny || !nz) return FTC_EINVAL;
   // the vertex adjacency and closest vertices come from the last build
   if (mesh->nv != cells->built_nv || mesh->nt != cells->built_nt) return FTC_EINVAL;
-  ftc::PPICParams p{2.5, 3, 24, 1.1, 16};
+  ftc::PPICParams p{2.5, 3, 24, 1.1, 16, 0};
   if (params) {
-    p = ftc::PPICParams{params->delta_over_h, params->rings, params->n_min, params->grow, params->max_iter};
+    p = ftc::PPICParams{params->delta_over_h, params->rings,    params->n_min,
+                        params->grow,         params->max_iter, params->precision};
     if (!(p.delta_over_h > 0.0) || !isfinite(p.delta_over_h) || p.rings < 1 || p.rings > 4 || p.n_min < 1 ||
-        !(p.grow > 1.0) || !isfinite(p.grow) || p.max_iter < 0 || p.max_iter > 64)
+        !(p.grow > 1.0) || !isfinite(p.grow) || p.max_iter < 0 || p.max_iter > 64 || p.mixed < 0 ||
+        p.mixed > 1)
       return FTC_EINVAL;
   }
   if (!on_device(cells)) return FTC_EINVAL;
@@ -283,6 +285,17 @@ ftc_status ftc_interp_vertex_velocity(ftc_cells* cells, const ftc_grid* grid, co
     return FTC_EINVAL;
   if (!on_device(cells)) return FTC_EINVAL;
   return hip_status(ftc::launch_interp(cells, to_grid(grid), to_mesh(mesh), U, V, W, ux, uy, uz, (hipStream_t)stream));
+}
+
+ftc_status ftc_advect_vertices_rk4(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh, const double* U,
+                                   const double* V, const double* W, double dt, double* x_out, double* y_out,
+                                   double* z_out, void* stream) {
+  if (!cells || !grid_valid(grid) || !mesh || mesh->nv <= 0 || !mesh->x || !mesh->y || !mesh->z || !U || !V || !W ||
+      !x_out || !y_out || !z_out || !isfinite(dt))
+    return FTC_EINVAL;
+  if (!on_device(cells)) return FTC_EINVAL;
+  return hip_status(ftc::launch_advect_rk4(cells, to_grid(grid), to_mesh(mesh), U, V, W, dt, x_out, y_out, z_out,
+                                           (hipStream_t)stream));
 }
 
 ftc_status ftc_last_device_error(ftc_cells* cells, int32_t* code, void* stream) {

@@ -351,6 +351,8 @@ struct PlaceArgs {
   const int32_t* counters;
 };
 
+constexpr int kSegReg = 16;  // segments up to this length are read in one batch
+
 // Each scattered piece moves to its rank by triangle id within its cell (a
 // triangle has at most one piece per cell, so the ranks are distinct).
 __device__ inline void rank_place(const PlaceArgs& A, int64_t bid, int64_t nblk) {
@@ -364,7 +366,16 @@ __device__ inline void rank_place(const PlaceArgs& A, int64_t bid, int64_t nblk)
     const int32_t t = tmp_tri[q];
     const int64_t s = offsets[ci], e = min((int64_t)offsets[ci + 1], pair_cap);
     int64_t rank = 0;
-    for (int64_t u = s; u < e; ++u) rank += tmp_tri[u] < t ? 1 : 0;
+    if (e - s <= kSegReg) {
+      // the segment in one batch of loads
+      int32_t seg[kSegReg];
+#pragma unroll
+      for (int u = 0; u < kSegReg; ++u) seg[u] = s + u < e ? tmp_tri[s + u] : INT_MAX;
+#pragma unroll
+      for (int u = 0; u < kSegReg; ++u) rank += seg[u] < t ? 1 : 0;
+    } else {
+      for (int64_t u = s; u < e; ++u) rank += tmp_tri[u] < t ? 1 : 0;
+    }
     const int64_t dst = s + rank;
     A.tri_ids[dst] = t;
     A.slot_cell[dst] = ci;
@@ -441,8 +452,18 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int64_t
       const int32_t ii = cc.i + l % 3 - 1, jj = cc.j + (l / 3) % 3 - 1, kk = cc.k + l / 9 - 1;
       if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) {
         const int32_t cr = cell_rank(A.bitmap, A.word_off, ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk));
-        if (cr >= 0 && cr < A.cell_cap)
-          for (int32_t p = A.vb_off[cr], e = A.vb_off[cr + 1]; p < e; ++p) consider(A.vtx4, A.vb_ids[p], xc, bd, bv);
+        if (cr >= 0 && cr < A.cell_cap) {
+          // the first few of the bin in one batch of loads (the result does
+          // not depend on the order)
+          const int32_t p0 = A.vb_off[cr], p1 = A.vb_off[cr + 1];
+          int32_t vid[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) vid[u] = p0 + u < p1 ? A.vb_ids[p0 + u] : -1;
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (vid[u] >= 0) consider(A.vtx4, vid[u], xc, bd, bv);
+          for (int32_t p = p0 + 4; p < p1; ++p) consider(A.vtx4, A.vb_ids[p], xc, bd, bv);
+        }
       }
     }
     for (int32_t q = l; q < nstray; q += 32) consider(A.vtx4, A.stray[q], xc, bd, bv);

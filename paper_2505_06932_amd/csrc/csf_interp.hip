@@ -1,6 +1,7 @@
-// csf_interp.hip -- CSF source on the interfacial cells (paper Eq. csf) and
-// the divergence-preserving interpolation of staggered face velocities to
-// the front vertices (paper section 3.1).  Both are gather kernels bound by
+// csf_interp.hip -- CSF source on the interfacial cells (paper Eq. csf), its
+// band mode, the divergence-preserving interpolation of staggered face
+// velocities to the front vertices and the RK4 step of the vertices through
+// it (paper section 3.1).  Both are gather kernels bound by
 // memory traffic: one thread per interfacial cell, one thread per vertex.
 #include "ftc_ws.hpp"
 
@@ -76,22 +77,14 @@ __global__ __launch_bounds__(kT) void k_csf_band(Grid g, const uint32_t* bitmap,
   }
 }
 
-__global__ __launch_bounds__(kT) void k_interp(Grid g, Mesh m, const double* U, const double* V, const double* W,
-                                               double* ux, double* uy, double* uz, int32_t* counters) {
-  const int32_t v = blockIdx.x * kT + threadIdx.x;
-  if (v >= m.nv) return;
-  const double x = m.x[v], y = m.y[v], z = m.z[v];
-  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
-    atomicOr(&counters[C_ERR], ERR_DOMAIN);
-    ux[v] = uy[v] = uz[v] = NAN;
-    return;
-  }
+// The divergence-preserving interpolant at (x, y, z), in the half-open cell
+// holding it; false (and nothing written) if the point is not finite or the
+// cell is not at least one cell inside the grid.
+__device__ inline bool interp_at(const Grid& g, const double* U, const double* V, const double* W, double x,
+                                 double y, double z, double out[3]) {
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) return false;
   const int64_t i = cell_index(x, g.x0, g.h), j = cell_index(y, g.y0, g.h), k = cell_index(z, g.z0, g.h);
-  if (!(i >= 1 && j >= 1 && k >= 1 && i <= g.nx - 2 && j <= g.ny - 2 && k <= g.nz - 2)) {
-    atomicOr(&counters[C_ERR], ERR_DOMAIN);
-    ux[v] = uy[v] = uz[v] = NAN;
-    return;
-  }
+  if (!(i >= 1 && j >= 1 && k >= 1 && i <= g.nx - 2 && j <= g.ny - 2 && k <= g.nz - 2)) return false;
   const int64_t nx = g.nx, ny = g.ny;
   // strides of the three staggered arrays (x fastest)
   const int64_t uy_s = nx + 1, uz_s = (nx + 1) * ny;
@@ -127,12 +120,59 @@ __global__ __launch_bounds__(kT) void k_interp(Grid g, Mesh m, const double* U, 
   const double cx = x - 0.5 * (xm + xp), cy = y - 0.5 * (ym + yp), cz = z - 0.5 * (zm + zp);
   const double dx = xp - xm, dy = yp - ym, dz = zp - zm;
 
-  ux[v] = (ax * (Up + cy * Uy_p + cz * Uz_p) + bx * (Um + cy * Uy_m + cz * Uz_m)) / dx +
-          bx * ax / (2.0 * dx) * (Vx_p - Vx_m + Wx_p - Wx_m);
-  uy[v] = (ay * (Vp + cx * Vx_p + cz * Vz_p) + by * (Vm + cx * Vx_m + cz * Vz_m)) / dy +
-          by * ay / (2.0 * dy) * (Uy_p - Uy_m + Wy_p - Wy_m);
-  uz[v] = (az * (Wp + cx * Wx_p + cy * Wy_p) + bz * (Wm + cx * Wx_m + cy * Wy_m)) / dz +
-          bz * az / (2.0 * dz) * (Uz_p - Uz_m + Vz_p - Vz_m);
+  out[0] = (ax * (Up + cy * Uy_p + cz * Uz_p) + bx * (Um + cy * Uy_m + cz * Uz_m)) / dx +
+           bx * ax / (2.0 * dx) * (Vx_p - Vx_m + Wx_p - Wx_m);
+  out[1] = (ay * (Vp + cx * Vx_p + cz * Vz_p) + by * (Vm + cx * Vx_m + cz * Vz_m)) / dy +
+           by * ay / (2.0 * dy) * (Uy_p - Uy_m + Wy_p - Wy_m);
+  out[2] = (az * (Wp + cx * Wx_p + cy * Wy_p) + bz * (Wm + cx * Wx_m + cy * Wy_m)) / dz +
+           bz * az / (2.0 * dz) * (Uz_p - Uz_m + Vz_p - Vz_m);
+  return true;
+}
+
+__global__ __launch_bounds__(kT) void k_interp(Grid g, Mesh m, const double* U, const double* V, const double* W,
+                                               double* ux, double* uy, double* uz, int32_t* counters) {
+  const int32_t v = blockIdx.x * kT + threadIdx.x;
+  if (v >= m.nv) return;
+  double u[3];
+  if (!interp_at(g, U, V, W, m.x[v], m.y[v], m.z[v], u)) {
+    atomicOr(&counters[C_ERR], ERR_DOMAIN);
+    u[0] = u[1] = u[2] = NAN;
+  }
+  ux[v] = u[0];
+  uy[v] = u[1];
+  uz[v] = u[2];
+}
+
+// One classical fourth-order Runge-Kutta step of dx/dt = u(x) per vertex,
+// the face velocities fixed over the step: k1 = u(x), k2 = u(x + dt/2 k1),
+// k3 = u(x + dt/2 k2), k4 = u(x + dt k3), x' = x + dt/6 (k1 + 2 k2 + 2 k3 +
+// k4).  A stage point outside the admissible cells gives NaN and latches
+// ERR_DOMAIN.  Each thread reads its vertex before writing it, so the output
+// may be the input arrays.
+__global__ __launch_bounds__(kT) void k_advect_rk4(Grid g, Mesh m, const double* U, const double* V,
+                                                   const double* W, double dt, double* xo, double* yo, double* zo,
+                                                   int32_t* counters) {
+  const int32_t v = blockIdx.x * kT + threadIdx.x;
+  if (v >= m.nv) return;
+  const double p[3] = {m.x[v], m.y[v], m.z[v]};
+  double k1[3], k2[3], k3[3], k4[3], s[3];
+  bool ok = interp_at(g, U, V, W, p[0], p[1], p[2], k1);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) s[d] = p[d] + (0.5 * dt) * k1[d];
+  ok = ok && interp_at(g, U, V, W, s[0], s[1], s[2], k2);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) s[d] = p[d] + (0.5 * dt) * k2[d];
+  ok = ok && interp_at(g, U, V, W, s[0], s[1], s[2], k3);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) s[d] = p[d] + dt * k3[d];
+  ok = ok && interp_at(g, U, V, W, s[0], s[1], s[2], k4);
+  double o[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) o[d] = ok ? p[d] + (dt / 6.0) * (((k1[d] + 2.0 * k2[d]) + 2.0 * k3[d]) + k4[d]) : NAN;
+  if (!ok) atomicOr(&counters[C_ERR], ERR_DOMAIN);
+  xo[v] = o[0];
+  yo[v] = o[1];
+  zo[v] = o[2];
 }
 
 }  // namespace
@@ -156,6 +196,13 @@ hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const doubl
   hipLaunchKernelGGL(k_csf_band, dim3(grid_blocks(band_cap, kT, 4096)), dim3(kT), 0, s, g, ws->bitmap, ws->word_off,
                      alpha, kappa, nx, ny, nz, sigma, band_ids, n_band, band_cap, kappa_band, fx, fy, fz,
                      ws->cell_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_advect_rk4(const ftc_cells* ws, const Grid& g, const Mesh& m, const double* U, const double* V,
+                             const double* W, double dt, double* xo, double* yo, double* zo, hipStream_t s) {
+  hipLaunchKernelGGL(k_advect_rk4, dim3(grid_blocks(m.nv, kT)), dim3(kT), 0, s, g, m, U, V, W, dt, xo, yo, zo,
+                     ws->counters);
   return hipGetLastError();
 }
 

@@ -135,6 +135,7 @@ struct PPICParams {
   int32_t rings, n_min;
   double grow;
   int32_t max_iter;
+  int32_t mixed;  // 1: normal equations in single precision, refined in double
 };
 hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, double* kappa, double* nx,
                        double* ny, double* nz, double* coeff, int32_t* cell_status, int32_t* diag,
@@ -146,6 +147,8 @@ hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const doubl
                            double* kappa_band, double* fx, double* fy, double* fz, int32_t* n_band, hipStream_t s);
 hipError_t launch_interp(const ftc_cells* ws, const Grid& g, const Mesh& m, const double* U, const double* V,
                          const double* W, double* ux, double* uy, double* uz, hipStream_t s);
+hipError_t launch_advect_rk4(const ftc_cells* ws, const Grid& g, const Mesh& m, const double* U, const double* V,
+                             const double* W, double dt, double* xo, double* yo, double* zo, hipStream_t s);
 
 // Record the start / stop event of kernel `k` when timing is enabled.
 inline void time_start(const ftc_cells* ws, int k, hipStream_t s) {

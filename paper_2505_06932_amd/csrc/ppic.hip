@@ -217,12 +217,64 @@ __device__ inline double div3(double x) {
 // packed index of entry (a, b), a <= b, of a symmetric 6x6 matrix
 __host__ __device__ constexpr int P6(int a, int b) { return a * 6 - a * (a - 1) / 2 + (b - a); }
 
-// One cell, by one thread: Cholesky factorisation of the packed normal
-// matrix (in registers), one step of iterative refinement, the coefficients
-// scaled back from the h-scaled frame, kappa = 2H at the frame origin and
-// the interface normal.  F holds the 31 fit slots (27 sums, frame normal,
-// weighted count) at a stride of fs.
-__device__ inline void solve_cell(const PPICArgs& A, int32_t c, const double* F, int64_t fs) {
+// Lower Cholesky factor of a packed symmetric 6x6 matrix, in place
+// (m[P6(j, i)] becomes L(i, j) for i >= j) with the reciprocal diagonal in
+// invd; false if a pivot is not above tol times the trace (the matrix is
+// then rank deficient for the purpose of the fit).
+template <class T>
+__device__ inline bool chol6(T* m, T* invd, T tol) {
+  const T trace = m[P6(0, 0)] + m[P6(1, 1)] + m[P6(2, 2)] + m[P6(3, 3)] + m[P6(4, 4)] + m[P6(5, 5)];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    T d = m[P6(j, j)];
+#pragma unroll
+    for (int p = 0; p < j; ++p) d -= m[P6(p, j)] * m[P6(p, j)];
+    if (!(d > tol * trace)) ok = false;
+    const T ljj = sqrt(d > T(0) ? d : T(1e-30));
+    m[P6(j, j)] = ljj;
+    const T inv = T(1) / ljj;
+    invd[j] = inv;
+#pragma unroll
+    for (int i2 = j + 1; i2 < 6; ++i2) {
+      T s2 = m[P6(j, i2)];
+#pragma unroll
+      for (int p = 0; p < j; ++p) s2 -= m[P6(p, i2)] * m[P6(p, j)];
+      m[P6(j, i2)] = s2 * inv;
+    }
+  }
+  return ok;
+}
+
+// x = (L L^T)^-1 rhs in double arithmetic, L from chol6 (of either type);
+// rhs and x may alias.
+template <class T>
+__device__ inline void chol6_solve(const T* L, const T* invd, const double* rhs, double* x) {
+  double y[6];
+#pragma unroll
+  for (int i2 = 0; i2 < 6; ++i2) {
+    double s2 = rhs[i2];
+#pragma unroll
+    for (int p = 0; p < i2; ++p) s2 -= (double)L[P6(p, i2)] * y[p];
+    y[i2] = s2 * (double)invd[i2];
+  }
+#pragma unroll
+  for (int i2 = 5; i2 >= 0; --i2) {
+    double s2 = y[i2];
+#pragma unroll
+    for (int p = i2 + 1; p < 6; ++p) s2 -= (double)L[P6(i2, p)] * x[p];
+    x[i2] = s2 * (double)invd[i2];
+  }
+}
+
+// One cell, by one thread: the paraboloid coefficients in the h-scaled
+// frame, scaled back, kappa = 2H at the frame origin and the interface
+// normal.  F holds the fit slots at a stride of fs: the frame normal in 27-29
+// and the weighted count in 30, and either (solved = false) the 27 sums of
+// the normal equations in 0-26, factored here by Cholesky with one step of
+// iterative refinement against the unfactored sums, or (solved = true) the
+// coefficients in 0-5 and 1 or 0 (full rank or not) in 6.
+__device__ inline void solve_cell(const PPICArgs& A, int32_t c, const double* F, int64_t fs, bool solved) {
   const int64_t cs = A.cell_cap;
   const double h = A.g.h, inv_h = 1.0 / h;
   {
@@ -232,64 +284,37 @@ __device__ inline void solve_cell(const PPICArgs& A, int32_t c, const double* F,
     double kap = NAN, ni0 = NAN, ni1 = NAN, ni2 = NAN;
     uint32_t st = wcnt == -1.0 ? FTC_CELL_OVERFLOW : 0u;
     if (wcnt >= 0.0) {
-      double acc[27];
+      double ah[6];
+      bool have = false;
+      if (solved) {
+        have = F[6 * fs] > 0.0;
 #pragma unroll
-      for (int qa = 0; qa < 27; ++qa) acc[qa] = F[qa * fs];
-      const double trace =
-          acc[P6(0, 0)] + acc[P6(1, 1)] + acc[P6(2, 2)] + acc[P6(3, 3)] + acc[P6(4, 4)] + acc[P6(5, 5)];
-      // in place: acc[P6(j, i)] becomes L(i, j) for i >= j
-      bool rank_ok = wcnt >= 6.0;
-      double invd[6];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        double d = acc[P6(j, j)];
-#pragma unroll
-        for (int p = 0; p < j; ++p) d -= acc[P6(p, j)] * acc[P6(p, j)];
-        if (!(d > 1e-14 * trace)) rank_ok = false;
-        const double ljj = sqrt(fmax(d, DBL_MIN));
-        acc[P6(j, j)] = ljj;
-        const double inv = 1.0 / ljj;
-        invd[j] = inv;
-#pragma unroll
-        for (int i2 = j + 1; i2 < 6; ++i2) {
-          double s2 = acc[P6(j, i2)];
-#pragma unroll
-          for (int p = 0; p < j; ++p) s2 -= acc[P6(p, i2)] * acc[P6(p, j)];
-          acc[P6(j, i2)] = s2 * inv;
-        }
-      }
-      if (!rank_ok) {
-        st |= FTC_CELL_RANK;
+        for (int i2 = 0; i2 < 6; ++i2) ah[i2] = F[i2 * fs];
       } else {
-        double ah[6], y[6], r6[6];
-        auto solve = [&](const double* rhs, double* x) {
+        double acc[27];
+#pragma unroll
+        for (int qa = 0; qa < 27; ++qa) acc[qa] = F[qa * fs];
+        double invd[6];
+        have = chol6(acc, invd, 1e-14) && wcnt >= 6.0;
+        if (have) {
+          chol6_solve(acc, invd, acc + 21, ah);
+          // residual with the unfactorised matrix, read again
+          double r6[6];
 #pragma unroll
           for (int i2 = 0; i2 < 6; ++i2) {
-            double s2 = rhs[i2];
+            double s2 = acc[21 + i2];
 #pragma unroll
-            for (int p = 0; p < i2; ++p) s2 -= acc[P6(p, i2)] * y[p];
-            y[i2] = s2 * invd[i2];
+            for (int p = 0; p < 6; ++p) s2 -= F[(i2 <= p ? P6(i2, p) : P6(p, i2)) * fs] * ah[p];
+            r6[i2] = s2;
           }
+          chol6_solve(acc, invd, r6, r6);
 #pragma unroll
-          for (int i2 = 5; i2 >= 0; --i2) {
-            double s2 = y[i2];
-#pragma unroll
-            for (int p = i2 + 1; p < 6; ++p) s2 -= acc[P6(i2, p)] * x[p];
-            x[i2] = s2 * invd[i2];
-          }
-        };
-        solve(acc + 21, ah);
-        // residual with the unfactorised matrix, read again
-#pragma unroll
-        for (int i2 = 0; i2 < 6; ++i2) {
-          double s2 = acc[21 + i2];
-#pragma unroll
-          for (int p = 0; p < 6; ++p) s2 -= F[(i2 <= p ? P6(i2, p) : P6(p, i2)) * fs] * ah[p];
-          r6[i2] = s2;
+          for (int i2 = 0; i2 < 6; ++i2) ah[i2] += r6[i2];
         }
-        solve(r6, r6);
-#pragma unroll
-        for (int i2 = 0; i2 < 6; ++i2) ah[i2] += r6[i2];
+      }
+      if (!have) {
+        st |= FTC_CELL_RANK;
+      } else {
         co[0] = h * ah[0];
         co[1] = ah[1];
         co[2] = ah[2];
@@ -746,7 +771,7 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
     __syncthreads();
     if (emit && gl == 0) {
       const int64_t cs = A.cell_cap;
-      solve_cell(A, c, FM.W, 1);
+      solve_cell(A, c, FM.W, 1, false);
       if (A.diag) {
         A.diag[c] = vs;
         A.diag[cs + c] = nT;
@@ -868,6 +893,153 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
   }
 }
 
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// group_sum in single precision
+template <int G>
+__device__ inline float group_sum_f(float v) {
+  if constexpr (G >= 2) v += dpp_f<0xB1>(v);
+  if constexpr (G >= 4) v += dpp_f<0x4E>(v);
+  if constexpr (G >= 8) v += dpp_f<0x141>(v);
+  if constexpr (G >= 16) v += dpp_f<0x140>(v);
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Mixed precision variant of the fit pass: the weighted normal equations
+// are formed and factored in single precision; the solution is then
+// improved twice by iterative refinement with residuals evaluated in double
+// precision triangle by triangle, g = sum_t w_t (V_t - m_t . a) m_t = b - M a
+// (the double-precision moments of the same weighted triangles), solved with
+// the single-precision factor.  Each step shrinks the error by about
+// cond(M) times the single-precision unit roundoff.  A single-precision
+// pivot at or below 1e-6 of the trace marks the cell rank deficient.  The
+// coefficients (h-scaled frame) and the rank flag go to the fit slots for
+// the solve pass.
+__global__ __launch_bounds__(64) void k_ppic_fit_mixed(PPICArgs A) {
+  constexpr int G = kFitG, NG = 64 / kFitG;
+  const Grid& g = A.g;
+  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+  const int32_t nitems = min(A.counters[C_NIF], A.cell_cap);
+  const int64_t cs = A.cell_cap;
+  const double h = g.h, inv_h = 1.0 / h;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    A.counters[C_NQUEUED] = A.counters[C_NOVF];
+    A.counters[C_NOVF] = 0;
+  }
+  const int32_t ngroups = (nitems + NG - 1) / NG;
+  const int32_t per = (ngroups + kXCD - 1) / kXCD;
+  const int32_t xcd = blockIdx.x % kXCD, nj = gridDim.x / kXCD;
+  for (int32_t q = blockIdx.x / kXCD; q < per; q += nj) {
+    const int32_t gi = xcd * per + q;
+    if (gi >= ngroups) break;
+    const int32_t c = gi * NG + grp;
+    const bool act = c < nitems;
+    const double wc = act ? A.fit[30 * cs + c] : -2.0;
+    const int cnt = wc > 0.0 ? (int)wc : 0;
+    const double n0 = act ? A.fit[27 * cs + c] : 0.0, n1 = act ? A.fit[28 * cs + c] : 0.0,
+                 n2 = act ? A.fit[29 * cs + c] : 1.0;
+    const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
+    const double xc[3] = {cell_centre(g.x0, cc3.i, h), cell_centre(g.y0, cc3.j, h), cell_centre(g.z0, cc3.k, h)};
+    const double sg = copysign(1.0, n2);
+    const double fa = -1.0 / (sg + n2);
+    const double fb = n0 * n1 * fa;
+    const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
+    const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
+    const int wrounds = wave_max_i((cnt + G - 1) / G);
+    const int4* lt = A.wl_tri + (int64_t)(act ? c : 0) * kFitList;
+    const double* lw = A.wl_w + (int64_t)(act ? c : 0) * kFitList;
+    const int4 kNone = make_int4(0, 0, 0, 0);
+
+    // moments of one listed triangle in the h-scaled frame (type T)
+    auto moments = [&](const int4 t4, auto zero, auto* mom, auto& vt) {
+      using T = decltype(zero);
+      const int32_t cr[3] = {t4.x, t4.y, t4.z};
+      T xi[3], eta[3], zeta[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const P3 p = vtx(A.vtx4, cr[e]);
+        const T dx = (T)(p.x - xc[0]), dy = (T)(p.y - xc[1]), dz = (T)(p.z - xc[2]);
+        xi[e] = fma(dz, (T)t1z, fma(dy, (T)t1y, dx * (T)t1x)) * (T)inv_h;
+        eta[e] = fma(dz, (T)t2z, fma(dy, (T)t2y, dx * (T)t2x)) * (T)inv_h;
+        zeta[e] = fma(dz, (T)n2, fma(dy, (T)n1, dx * (T)n0)) * (T)inv_h;
+      }
+      const T area = T(0.5) * fma(xi[1] - xi[0], eta[2] - eta[0], -((xi[2] - xi[0]) * (eta[1] - eta[0])));
+      T sm[6] = {T(3), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const T mx = T(0.5) * (xi[e] + xi[(e + 1) % 3]);
+        const T my = T(0.5) * (eta[e] + eta[(e + 1) % 3]);
+        sm[1] += mx;
+        sm[2] += my;
+        sm[3] = fma(mx, mx, sm[3]);
+        sm[4] = fma(mx, my, sm[4]);
+        sm[5] = fma(my, my, sm[5]);
+      }
+      const T a3 = area * (T(1) / T(3));
+#pragma unroll
+      for (int qa = 0; qa < 6; ++qa) mom[qa] = a3 * sm[qa];
+      vt = a3 * (zeta[0] + zeta[1] + zeta[2]);
+    };
+
+    // ---- single precision: normal equations, factor, first solution
+    float accf[27];
+#pragma unroll
+    for (int qa = 0; qa < 27; ++qa) accf[qa] = 0.0f;
+    for (int k = 0; k < wrounds; ++k) {
+      const int j = k * G + gl;
+      const int4 t4 = j < cnt ? lt[j] : kNone;
+      const float w = j < cnt ? (float)lw[j] : 0.0f;
+      float mom[6], vt;
+      moments(t4, 0.0f, mom, vt);
+      const float wv = w * vt;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const float wa = w * mom[a];
+#pragma unroll
+        for (int b = a; b < 6; ++b) accf[P6(a, b)] = fmaf(wa, mom[b], accf[P6(a, b)]);
+        accf[21 + a] = fmaf(wv, mom[a], accf[21 + a]);
+      }
+    }
+#pragma unroll
+    for (int qa = 0; qa < 27; ++qa) accf[qa] = group_sum_f<G>(accf[qa]);
+    float invf[6];
+    const bool full = chol6(accf, invf, 1e-6f) && cnt >= 6;
+    double ah[6], rhs[6];
+#pragma unroll
+    for (int qa = 0; qa < 6; ++qa) rhs[qa] = (double)accf[21 + qa];
+    chol6_solve(accf, invf, rhs, ah);
+
+    // ---- two refinement steps with double-precision residuals
+    for (int it = 0; it < 2; ++it) {
+      double gr[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < wrounds; ++k) {
+        const int j = k * G + gl;
+        const int4 t4 = j < cnt ? lt[j] : kNone;
+        const double w = j < cnt ? lw[j] : 0.0;
+        double mom[6], vt;
+        moments(t4, 0.0, mom, vt);
+        double r = vt;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) r -= mom[a] * ah[a];
+        const double wr = w * r;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) gr[a] = fma(wr, mom[a], gr[a]);
+      }
+#pragma unroll
+      for (int a = 0; a < 6; ++a) gr[a] = group_sum<G>(gr[a]);
+      chol6_solve(accf, invf, gr, gr);
+#pragma unroll
+      for (int a = 0; a < 6; ++a) ah[a] += gr[a];
+    }
+    if (act && wc >= 0.0 && gl < 7) A.fit[gl * cs + c] = gl < 6 ? ah[gl] : (full ? 1.0 : 0.0);
+  }
+}
+
 // Blocks [0, kWideBlocks): the cells queued for the wide shape, each solved
 // in its block; the other blocks: one thread per remaining cell.
 __global__ __launch_bounds__(64) void k_ppic_wide_solve(PPICArgs A) {
@@ -881,7 +1053,7 @@ __global__ __launch_bounds__(64) void k_ppic_wide_solve(PPICArgs A) {
   for (int32_t c = (blockIdx.x - kWideBlocks) * 64 + threadIdx.x; c < nif; c += nb * 64) {
     const double* F = A.fit + c;
     if (F[30 * cs] == -3.0) continue;  // queued: solved by the wide shape
-    solve_cell(A, c, F, cs);
+    solve_cell(A, c, F, cs, A.prm.mixed != 0);
   }
 }
 
@@ -922,8 +1094,11 @@ hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, 
   const int32_t blocks = round_up(std::min<int64_t>(std::max<int64_t>(groups, 1), 65536), kXCD);
   time_start(ws, FTC_KERNEL_PPIC, s);
   hipLaunchKernelGGL(k_ppic_rings, dim3(blocks), dim3(64), 0, s, A);
-  hipLaunchKernelGGL(k_ppic_fit, dim3(round_up(std::min<int64_t>(std::max<int64_t>(((int64_t)ws->cell_cap + 7) / 8, 1),
-                                                                  65536), kXCD)), dim3(64), 0, s, A);
+  const dim3 fit_grid(round_up(std::min<int64_t>(std::max<int64_t>(((int64_t)ws->cell_cap + 7) / 8, 1), 65536), kXCD));
+  if (p.mixed)
+    hipLaunchKernelGGL(k_ppic_fit_mixed, fit_grid, dim3(64), 0, s, A);
+  else
+    hipLaunchKernelGGL(k_ppic_fit, fit_grid, dim3(64), 0, s, A);
   hipLaunchKernelGGL(k_ppic_wide_solve, dim3(kWideBlocks + grid_blocks(ws->cell_cap, 64)), dim3(64), 0, s, A);
   time_stop(ws, FTC_KERNEL_PPIC, s);
   return hipGetLastError();

@@ -31,7 +31,7 @@ FTC_CELL_RANK, FTC_CELL_OVERFLOW = 1, 2
 EXPORTED = ["ftc_cells_create", "ftc_cells_destroy", "ftc_build_cell_lists", "ftc_cells_count",
             "ftc_cells_view", "ftc_volume_fraction", "ftc_ppic_curvature", "ftc_csf_force",
             "ftc_interp_vertex_velocity", "ftc_last_device_error", "ftc_set_timing", "ftc_kernel_time",
-            "ftc_csf_force_band",
+            "ftc_csf_force_band", "ftc_advect_vertices_rk4",
             "ftc_status_str"]
 
 # ftc_kernel values (timing)
@@ -51,17 +51,20 @@ class _CMesh(C.Structure):
 
 class _CParams(C.Structure):
     _fields_ = [("delta_over_h", C.c_double), ("rings", C.c_int32), ("n_min", C.c_int32),
-                ("grow", C.c_double), ("max_iter", C.c_int32)]
+                ("grow", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32)]
 
 
 @dataclass(frozen=True)
 class PPICParams:
-    """Volume-fit parameters; defaults are the paper's (section 3.2)."""
+    """Volume-fit parameters; defaults are the paper's (section 3.2).
+    precision 0: normal equations in double precision; 1: formed and
+    factored in single precision, refined with double-precision residuals."""
     delta_over_h: float = 2.5
     rings: int = 3
     n_min: int = 24
     grow: float = 1.1
     max_iter: int = 16
+    precision: int = 0
 
 
 class FTCError(RuntimeError):
@@ -105,6 +108,8 @@ def lib() -> C.CDLL:
     L.ftc_csf_force_band.restype = C.c_int32
     L.ftc_interp_vertex_velocity.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, vp, vp, vp, vp, vp]
     L.ftc_interp_vertex_velocity.restype = C.c_int32
+    L.ftc_advect_vertices_rk4.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, vp, C.c_double, vp, vp, vp, vp]
+    L.ftc_advect_vertices_rk4.restype = C.c_int32
     L.ftc_last_device_error.argtypes = [vp, P(C.c_int32), vp]
     L.ftc_last_device_error.restype = C.c_int32
     L.ftc_set_timing.argtypes = [vp, C.c_int32]
@@ -284,7 +289,8 @@ def ppic_curvature(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, kappa, nx
     cap = cells.cell_capacity
     p = None
     if params is not None:
-        p = C.byref(_CParams(params.delta_over_h, params.rings, params.n_min, params.grow, params.max_iter))
+        p = C.byref(_CParams(params.delta_over_h, params.rings, params.n_min, params.grow, params.max_iter,
+                             params.precision))
     _check(lib().ftc_ppic_curvature(cells.handle, C.byref(cg), C.byref(mesh.c), p,
                                     _ptr(kappa, torch.float64, cap, "kappa"),
                                     _ptr(nx, torch.float64, cap, "nx"), _ptr(ny, torch.float64, cap, "ny"),
@@ -323,6 +329,20 @@ def csf_force_band(cells: Cells, grid: _inputs.Grid, alpha_dense, kappa, nx, ny,
                                     _ptr(fz, torch.float64, bcap, "fz"), _ptr(n_band, torch.int32, 1, "n_band"),
                                     _stream(stream)),
            "ftc_csf_force_band")
+
+
+def advect_vertices_rk4(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, U, V, W, dt: float, x_out, y_out, z_out,
+                        stream=None) -> None:
+    cg = c_grid(grid)
+    nx, ny, nz = grid.nx, grid.ny, grid.nz
+    nv = mesh.nv
+    _check(lib().ftc_advect_vertices_rk4(cells.handle, C.byref(cg), C.byref(mesh.c),
+                                         _ptr(U, torch.float64, (nx + 1) * ny * nz, "U"),
+                                         _ptr(V, torch.float64, nx * (ny + 1) * nz, "V"),
+                                         _ptr(W, torch.float64, nx * ny * (nz + 1), "W"), float(dt),
+                                         _ptr(x_out, torch.float64, nv, "x_out"), _ptr(y_out, torch.float64, nv, "y_out"),
+                                         _ptr(z_out, torch.float64, nv, "z_out"), _stream(stream)),
+           "ftc_advect_vertices_rk4")
 
 
 def interp_vertex_velocity(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, U, V, W, ux, uy, uz,

@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_2505_06932_amd", "libftc.so")
 def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ftc_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(ftc_[a-z_0-9]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")

@@ -111,6 +111,31 @@ def test_sphere_workloads_full_parity(oracle, name, seed):
     assert abs(np.mean(g["kappa"]) * R / 2 - 1) < 0.02
 
 
+# ---------------------------------------------------------------- mixed precision
+MIXED_KAPPA_TOL = 1e-9
+
+
+@pytest.mark.parametrize("name,seed", [("sphere_32", 1), ("sphere_128", 0)])
+def test_mixed_precision_fit_against_double_oracle(oracle, name, seed):
+    """Normal equations formed and factored in single precision, refined
+    twice with double-precision residuals: the discrete decisions are those
+    of the double-precision path (the ring pass is shared), the curvature
+    agrees with the double-precision oracle to 1e-9 relative (the measured
+    error is printed), and every cell the oracle solves is solved."""
+    from paper_2505_06932_amd import ftc
+    grid, mesh, c = I.make_workload(name, seed)
+    step, g, o = run_pair(oracle, f"mixed {name}/{seed}", grid, mesh, params=ftc.PPICParams(precision=1))
+    check_lists(g, o)
+    assert np.array_equal(g["diag"], o["diag"])
+    ok = o["status"] == 0
+    assert np.all(g["status"][ok] == 0)
+    err = np.abs(g["kappa"][ok] - o["kappa"][ok]) / np.abs(o["kappa"][ok])
+    _say(f"[gpu parity] mixed precision {name}: max relative kappa error {err.max():.3e}, "
+         f"median {np.median(err):.3e}")
+    assert err.max() <= MIXED_KAPPA_TOL
+    assert np.abs(g["normal"][ok] - o["normal"][ok]).max() <= MIXED_KAPPA_TOL
+
+
 # ---------------------------------------------------------------- CSF band mode
 @pytest.mark.parametrize("name,seed", [("sphere_32", 0), ("sphere_128", 0)])
 def test_csf_band_mode_parity(oracle, name, seed):
@@ -214,6 +239,32 @@ def test_uniform_velocity_exact():
     step.run()
     g = step.results()
     assert np.abs(g["u"] - np.array(u0)[None, :]).max() <= 4e-16 * 1.2
+
+
+@pytest.mark.parametrize("name", ["sphere_32", "sphere_128"])
+def test_rk4_advection_parity(oracle, name):
+    """One RK4 step of every front vertex through the interpolated
+    stream-function field against the oracle's, to 1e-13 (positions of
+    order 1, displacements of order dt |u| = 1e-2); in place (into the mesh's
+    own arrays) equal to out of place."""
+    import torch
+    from paper_2505_06932_amd import ftc
+    grid, mesh, _ = I.make_workload(name, 0)
+    U, V, W = I.psi_face_velocity(grid)
+    pipeline = _gpu()
+    _say(f"[gpu parity] case=rk4 {name}")
+    step = pipeline.CouplingStep(grid, mesh, U, V, W)
+    dt = 0.01
+    out = [torch.empty_like(step.mesh.x) for _ in range(3)]
+    ftc.advect_vertices_rk4(step.cells, grid, step.mesh, step.U, step.V, step.W, dt, *out)
+    dm = ftc.DeviceMesh.from_host(mesh)
+    ftc.advect_vertices_rk4(step.cells, grid, dm, step.U, step.V, step.W, dt, dm.x, dm.y, dm.z)
+    torch.cuda.synchronize()
+    got = np.stack([t.cpu().numpy() for t in out], 1)
+    ref = oracle.advect_rk4(grid, mesh.x, mesh.y, mesh.z, U, V, W, dt)
+    assert np.abs(got - ref).max() <= 1e-13
+    assert np.array_equal(np.stack([dm.x.cpu().numpy(), dm.y.cpu().numpy(), dm.z.cpu().numpy()], 1), got)
+    assert step.cells.last_device_error() == ftc.FTC_OK
 
 
 # ---------------------------------------------------------------- edge cases
