@@ -76,6 +76,9 @@ def _load():
     lib.ora_fit.restype = C.c_int32
     lib.ora_kappa.argtypes = [P(C.c_double)]
     lib.ora_kappa.restype = C.c_double
+    lib.ora_frame_normal.argtypes = [P(_Grid), P(_Mesh), C.c_int64, P(C.c_int64), P(C.c_int32),
+                                     P(C.c_double), P(C.c_double)]
+    lib.ora_frame_normal.restype = C.c_int32
     lib.ora_csf.argtypes = [P(_Grid), P(C.c_double), C.c_int64, P(C.c_int64), P(C.c_double),
                             C.c_double, P(C.c_double)]
     lib.ora_csf.restype = C.c_int32
@@ -207,6 +210,21 @@ def ppic(grid, mesh, cell_ids, params: PPICParams = PPICParams()):
     if r != 0:
         raise OracleError(r, "ppic")
     return dict(kappa=kap, normal=nrm, coeff=co, status=st, diag=dg)
+
+
+def frame_normal(grid, mesh, cell_ids):
+    """Per listed cell: (closest vertex, its squared distance to the cell
+    centre, that vertex's area-weighted normal [n, 3])."""
+    k = _Keep(grid, mesh)
+    ids = np.ascontiguousarray(cell_ids, dtype=np.int64)
+    n = len(ids)
+    vs = np.empty(n, np.int32)
+    d2 = np.empty(n)
+    nrm = np.empty((n, 3))
+    r = int(_load().ora_frame_normal(C.byref(k.g), C.byref(k.m), n, _lp(ids), _ip(vs), _dp(d2), _dp(nrm)))
+    if r != 0:
+        raise OracleError(r, "frame_normal")
+    return vs, d2, nrm
 
 
 def fit(frame, xc, h, tris, w):

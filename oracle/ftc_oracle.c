@@ -660,6 +660,48 @@ int32_t ora_ppic(const ora_grid* g, const ora_mesh* m, const ora_ppic_params* pr
 /* CSF                                                                      */
 /* ------------------------------------------------------------------------ */
 
+int32_t ora_frame_normal(const ora_grid* g, const ora_mesh* m, int64_t ncell,
+                         const int64_t* cell_ids, int32_t* vstar, double* best_d2,
+                         double* nrm) {
+  if (!grid_ok(g) || !mesh_ok(m) || ncell < 0 || (ncell > 0 && !cell_ids)) return -1;
+  const double h = g->h;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t q = 0; q < ncell; ++q) {
+    int64_t cid = cell_ids[q];
+    int64_t i = cid % g->nx, j = (cid / g->nx) % g->ny, k = cid / ((int64_t)g->nx * g->ny);
+    double xc[3] = {g->x0 + ((double)i + 0.5) * h, g->y0 + ((double)j + 0.5) * h,
+                    g->z0 + ((double)k + 0.5) * h};
+    double best = DBL_MAX;
+    int32_t vs = -1;
+    for (int32_t v = 0; v < m->nv; ++v) {
+      double dx = m->x[v] - xc[0], dy = m->y[v] - xc[1], dz = m->z[v] - xc[2];
+      double dd = dx * dx + dy * dy + dz * dz;
+      if (dd < best) {
+        best = dd;
+        vs = v;
+      }
+    }
+    /* the incident triangles of vs in ascending order: a scan of all triangles */
+    double n[3] = {0, 0, 0};
+    for (int32_t t = 0; t < m->nt; ++t) {
+      if (m->t0[t] != vs && m->t1[t] != vs && m->t2[t] != vs) continue;
+      double tr[3][3];
+      load_tri(m, t, tr);
+      double ux = tr[1][0] - tr[0][0], uy = tr[1][1] - tr[0][1], uz = tr[1][2] - tr[0][2];
+      double wx = tr[2][0] - tr[0][0], wy = tr[2][1] - tr[0][1], wz = tr[2][2] - tr[0][2];
+      n[0] += uy * wz - uz * wy;
+      n[1] += uz * wx - ux * wz;
+      n[2] += ux * wy - uy * wx;
+    }
+    double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (vstar) vstar[q] = vs;
+    if (best_d2) best_d2[q] = best;
+    if (nrm)
+      for (int d = 0; d < 3; ++d) nrm[3 * q + d] = n[d] / nl;
+  }
+  return 0;
+}
+
 int32_t ora_csf(const ora_grid* g, const double* alpha, int64_t ncell, const int64_t* cell_ids,
                 const double* kappa, double sigma, double* f) {
   if (!grid_ok(g) || !alpha || ncell < 0 || (ncell > 0 && (!cell_ids || !kappa || !f))) return -1;

@@ -69,6 +69,16 @@ int32_t ora_ppic(const ora_grid* g, const ora_mesh* m, const ora_ppic_params* p,
                  int64_t ncell, const int64_t* cell_ids, double* kappa,
                  double* nrm, double* coeff, int32_t* status, int32_t* diag);
 
+/* Input of the learned curvature surrogate: per listed cell, the front
+   vertex closest to the cell centre (lowest index on ties) and its squared
+   distance, and that vertex's normal, the normalised sum of the cross
+   products (c1 - c0) x (c2 - c0) of its incident triangles in ascending
+   triangle order (the frame normal of the volume fit, paper sec. 3.2).
+   Any output may be NULL.  Returns 0 or -1. */
+int32_t ora_frame_normal(const ora_grid* g, const ora_mesh* m, int64_t ncell,
+                         const int64_t* cell_ids, int32_t* vstar, double* best_d2,
+                         double* nrm);
+
 /* One volume fit (paper Eqs. volumefit / volumefit2) in a given frame:
    frame[9] = {t1, t2, n} (rows), origin xc[3], scale h; tri[9*ntri] the
    triangles' corners in world coordinates, w[ntri] their weights.

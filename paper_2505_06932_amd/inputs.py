@@ -32,6 +32,7 @@ import numpy as np
 __all__ = [
     "Grid", "Mesh", "icosahedron", "icosphere", "geodesic_sphere",
     "sphere_workload", "polar_revolution_workload", "ellipsoids_workload",
+    "sh_spheres_workload", "real_sph_harm",
     "random_rotation", "box_mesh", "tetra_mesh",
     "subdivided_cube_mesh", "psi_face_velocity", "uniform_face_velocity",
     "affine_face_velocity", "mesh_edges_ok", "WORKLOADS",
@@ -319,17 +320,86 @@ def ellipsoids_workload(n: int, count: int, seed: int, axis_lo: float = 2.0, axi
     return grid, Mesh.from_arrays(np.concatenate(verts), np.concatenate(tris)), np.array(info)
 
 
+def real_sph_harm(l: int, m: int, unit: np.ndarray) -> np.ndarray:
+    """Real spherical harmonic of degree l, order m at unit vectors [n, 3]:
+    Y_l^0; sqrt(2) Re Y_l^m for m > 0; sqrt(2) Im Y_l^|m| for m < 0 (complex
+    harmonics of scipy.special.sph_harm_y, polar angle from +z)."""
+    from scipy.special import sph_harm_y
+    theta = np.arccos(np.clip(unit[:, 2], -1.0, 1.0))
+    phi = np.arctan2(unit[:, 1], unit[:, 0])
+    y = sph_harm_y(l, abs(m), theta, phi)
+    if m == 0:
+        return y.real
+    return math.sqrt(2.0) * (y.real if m > 0 else y.imag)
+
+
+def sh_spheres_workload(n: int, count: int, seed: int, r_lo: float = 4.0, r_hi: float = 20.0,
+                        degree: int = 8, amp_max: float = 0.1, edge_over_h: float = 0.5,
+                        gap_over_h: float = 4.0, domain: float = 1.0):
+    """``count`` disjoint spheres with spherical-harmonic perturbations in one
+    mesh on an n^3 grid.
+
+    For each droplet in turn, with ``numpy.random.default_rng(seed)``: the
+    radius R ~ U[r_lo h, r_hi h]; the relative amplitude A ~ U[0, amp_max];
+    coefficients c_lm ~ N(0, 1) / l^2 for 2 <= l <= degree, -l <= m <= l (in
+    that order); a centre drawn U[lo, hi]^3 (lo = 1.1 R + 3h from the walls)
+    until its bounding sphere keeps ``gap_over_h`` cells from every earlier
+    one.  The surface is the unit geodesic sphere of frequency
+    ceil(1.21 R / (edge_over_h h)) mapped radially by
+    r(u) = R (1 + A f(u) / max |f|), f = sum c_lm Y_lm(u) (real harmonics,
+    :func:`real_sph_harm`; the maximum over the mesh vertices), so every
+    radius lies in [(1 - A) R, (1 + A) R].  Returns the grid, the mesh and a
+    (count, 6) array of centre, R, A and frequency per droplet."""
+    h = domain / n
+    rng = np.random.default_rng(seed)
+    cache: dict[int, tuple[np.ndarray, np.ndarray]] = {}
+    verts, tris, info = [], [], []
+    placed: list[tuple[np.ndarray, float]] = []
+    nv = 0
+    for _ in range(count):
+        R = float(rng.uniform(r_lo * h, r_hi * h))
+        A = float(rng.uniform(0.0, amp_max))
+        coef = [(l, m, float(rng.normal()) / (l * l)) for l in range(2, degree + 1) for m in range(-l, l + 1)]
+        rb = 1.1 * R
+        lo, hi = rb + 3 * h, domain - rb - 3 * h
+        for _attempt in range(100000):
+            c = rng.uniform(lo, hi, size=3)
+            if all(np.linalg.norm(c - c2) >= rb + r2 + gap_over_h * h for c2, r2 in placed):
+                break
+        else:
+            raise RuntimeError("could not place the droplets")
+        placed.append((c, rb))
+        freq = int(math.ceil(1.21 * R / (edge_over_h * h)))
+        if freq not in cache:
+            cache[freq] = geodesic_sphere(freq)
+        unit, t = cache[freq]
+        f = np.zeros(len(unit))
+        for l, m, cl in coef:
+            f += cl * real_sph_harm(l, m, unit)
+        fmax = float(np.abs(f).max())
+        r = R * (1.0 + A * f / fmax) if fmax > 0.0 else np.full(len(unit), R)
+        verts.append(c[None, :] + unit * r[:, None])
+        tris.append(t + nv)
+        nv += len(unit)
+        info.append([*c, R, A, freq])
+    grid = Grid(n, n, n, 0.0, 0.0, 0.0, h)
+    return grid, Mesh.from_arrays(np.concatenate(verts), np.concatenate(tris)), np.array(info)
+
+
 #: Named workloads: (builder, kwargs).  "sphere_32" is the small plain-FP64
 #: case (R = 0.25, 4 subdivisions, 5,120 triangles, 32^3); "sphere_128" is the
 #: 128^3 sphere of R = 0.3 with 6 subdivisions (81,920 triangles) and radial
 #: noise of 0.01 h; "ellipsoids_256" is 64 disjoint ellipsoidal droplets on
 #: 256^3 with edges near h/2; "revolution_512" is the 512^3 surface of
-#: revolution with 1,997,120 triangles.
+#: revolution with 1,997,120 triangles; "sh_spheres_128" is 8 disjoint
+#: spheres with spherical-harmonic perturbations (R in [4h, 20h], degree <= 8,
+#: amplitude <= 0.1 R) on 128^3, the learned-curvature workload.
 WORKLOADS = {
     "sphere_32": (sphere_workload, dict(n=32, radius=0.25, subdivisions=4, noise_over_h=0.0)),
     "sphere_128": (sphere_workload, dict(n=128, radius=0.3, subdivisions=6, noise_over_h=0.01)),
     "ellipsoids_256": (ellipsoids_workload, dict(n=256, count=64)),
     "revolution_512": (polar_revolution_workload, dict(n=512, radius=0.2, freq=316)),
+    "sh_spheres_128": (sh_spheres_workload, dict(n=128, count=8)),
 }
 
 

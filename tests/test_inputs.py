@@ -87,3 +87,34 @@ def test_random_rotation_is_proper_orthogonal():
         R = I.random_rotation(rng)
         assert np.allclose(R @ R.T, np.eye(3), atol=1e-14)
         assert abs(np.linalg.det(R) - 1) < 1e-14
+
+
+def test_real_sph_harm_orthonormal():
+    """Gauss-Legendre quadrature in cos(theta) times the trapezoid rule in
+    phi (exact for these degrees): the real harmonics of degree <= 8 are
+    orthonormal on the unit sphere."""
+    x, w = np.polynomial.legendre.leggauss(12)
+    phi = 2 * np.pi * np.arange(24) / 24
+    ct, ph = np.meshgrid(x, phi, indexing="ij")
+    st = np.sqrt(1 - ct * ct)
+    unit = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    wq = np.repeat(w, 24) * (2 * np.pi / 24)
+    Y = np.stack([I.real_sph_harm(l, m, unit) for l in range(9) for m in range(-l, l + 1)])
+    G = (Y * wq) @ Y.T
+    assert np.abs(G - np.eye(len(Y))).max() < 1e-12
+
+
+def test_sh_spheres_workload():
+    grid, mesh, info = I.sh_spheres_workload(64, 3, seed=1, r_lo=4.0, r_hi=10.0)
+    assert I.mesh_edges_ok(mesh)
+    h = grid.h
+    v = mesh.verts()
+    start = 0
+    for c, R, A, freq in zip(info[:, :3], info[:, 3], info[:, 4], info[:, 5]):
+        n = 10 * int(freq) ** 2 + 2
+        r = np.linalg.norm(v[start:start + n] - c, axis=1)
+        assert 4 * h <= R <= 10 * h and 0 <= A <= 0.1
+        assert r.min() >= (1 - A) * R * (1 - 1e-12) and r.max() <= (1 + A) * R * (1 + 1e-12)
+        assert abs(max(r.max() / R - 1, 1 - r.min() / R) - A) < 1e-12  # the amplitude is attained
+        start += n
+    assert start == mesh.nv
