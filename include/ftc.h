@@ -84,6 +84,7 @@ typedef struct {
 /* Per-cell status bits written by ftc_ppic_curvature. */
 #define FTC_CELL_RANK 1u     /* normal equations singular: kappa, n, coeff = NaN */
 #define FTC_CELL_OVERFLOW 2u /* ring larger than the kernel's stencil limit      */
+#define FTC_CELL_SURROGATE 4u /* curvature from the learned surrogate (ftc_learned_curvature) */
 
 /* Opaque workspace: the cell lists and every scratch buffer the calls use,
    allocated once for one grid and maximum front sizes. */
@@ -246,7 +247,8 @@ typedef enum {
   FTC_KERNEL_PPIC = 3,        /* PPIC: ring, fit, curvature (both shapes)     */
   FTC_KERNEL_CSF = 4,         /* CSF force                                    */
   FTC_KERNEL_INTERP = 5,      /* vertex velocity interpolation                */
-  FTC_KERNEL_COUNT = 6
+  FTC_KERNEL_SURROGATE = 6,   /* learned curvature with its PPIC fallback     */
+  FTC_KERNEL_COUNT = 7
 } ftc_kernel;
 
 /* Enable (1) or disable (0) the timing events of a workspace. */
@@ -259,6 +261,91 @@ ftc_status ftc_kernel_time(const ftc_cells* cells, int32_t kernel, float* ms);
 
 /* Static text for a status code. */
 const char* ftc_status_str(int32_t status);
+
+/* ------------------------------------------------------------------------
+   Learned curvature surrogate (an extension of the PPIC fit of paper section
+   3.2: the network learns kappa h from what the fit sees).
+
+   Feature row of an interfacial cell, FTC_MLP_FEATURES floats: the volume
+   fractions of the 3x3x3 block of cells centred on it, entry
+   q = 9 (dk+1) + 3 (dj+1) + (di+1) for the cell (i+di, j+dj, k+dk) (0 outside
+   the grid), then the fit's frame normal (the normalised sum of the cross
+   products (c1 - c0) x (c2 - c0) of the incident triangles of the front
+   vertex closest to the cell centre, in ascending triangle order), then two
+   zeros.
+
+   Network: 30 -> 64 -> 64 -> 1 with tanh hidden units, parameters theta
+   (FTC_MLP_PARAMS floats, device): W1 [64][30] row-major, b1 [64],
+   W2 [64][64] row-major, b2 [64], w3 [64], b3.  Evaluated with weights and
+   hidden activations rounded to bfloat16 and single-precision sums; every
+   input x enters as bf16(x) plus bf16(x - bf16(x)).
+
+   Cube symmetries: sym in [0, 48) is permutation sym / 8 of the axes (in
+   lexicographic order) with axis a negated where bit a of sym % 8 is set,
+   (P x)_a = sign_a x_perm[a]; a feature row mapped by it holds the fractions
+   alpha'(d) = alpha(P^T d) and the normal P n.
+   ------------------------------------------------------------------------ */
+#define FTC_MLP_FEATURES 32
+#define FTC_MLP_PARAMS 6209
+/* work buffer of ftc_mlp_loss_grad, floats (256 partial rows) */
+#define FTC_MLP_WORK_FLOATS (256 * (FTC_MLP_PARAMS + 3))
+
+/* Feature rows of the interfacial cells of the last build:
+   features[cell_capacity][FTC_MLP_FEATURES] (device, row c for compact cell
+   c), from the dense volume fractions alpha_dense [nz][ny][nx] (device,
+   ftc_volume_fraction's output).  final_flags [cell_capacity] (device, or
+   NULL): 0 if the cell's closest front vertex lies within 1.5 h of its
+   centre, else 1 (its normal is then 0).  The mesh must be the one of the
+   last build. */
+ftc_status ftc_curvature_features(const ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
+                                  const double* alpha_dense, float* features, int32_t* final_flags,
+                                  void* stream);
+
+/* Network outputs y[n] (device) for the rows X[rows][FTC_MLP_FEATURES]
+   (device): sample s reads row idx[s] (or s if idx is NULL) mapped by cube
+   symmetry sym[s] (or none if sym is NULL).  A sample whose row lies outside
+   [0, rows) reads zeros; a symmetry outside [0, 48) is taken as 0. */
+ftc_status ftc_mlp_forward(const float* theta, const float* X, int64_t rows, const int32_t* idx,
+                           const int32_t* sym, int32_t n, float* y, void* stream);
+
+/* Mean squared error (1/n) sum_s (y_s - t[row_s])^2 over a batch of n
+   samples chosen as in ftc_mlp_forward, and its gradient grad[FTC_MLP_PARAMS]
+   (device) with respect to theta; loss (device, one float) may be NULL.  The
+   backward pass rounds dz to bfloat16 before each product, takes the
+   derivative of tanh from the rounded activation and sums in single
+   precision; partial sums of up to 256 workgroups are added in workgroup
+   order.  work: FTC_MLP_WORK_FLOATS floats of device memory owned by the
+   caller (overwritten).  n must be positive. */
+ftc_status ftc_mlp_loss_grad(const float* theta, const float* X, int64_t rows, const int32_t* idx,
+                             const int32_t* sym, const float* t, int32_t n, float* grad, float* loss,
+                             float* work, void* stream);
+
+/* One Adam step (Kingma and Ba, ICLR 2015) on theta, with first and second
+   moments m, v (device, FTC_MLP_PARAMS floats each, zero before step 1) and
+   bias correction: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+   theta -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+   step counts from 1. */
+ftc_status ftc_mlp_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr, float beta1,
+                        float beta2, float eps, void* stream);
+
+/* Curvature of every interfacial cell of the last build by the surrogate,
+   with PPIC where it is not trusted.  For each cell the network is evaluated
+   on its feature row mapped by four cube symmetries (0, 17, 24, 7: identity,
+   quarter turn about z, cyclic exchange of the axes, point reflection); the
+   estimate of kappa h is their mean ((y0 + y1) + (y2 + y3)) / 4 and the error
+   estimate their spread (max - min).  A cell with spread <= bound and a
+   closest vertex within 1.5 h gets kappa = mean / h, the frame normal in
+   (nx, ny, nz) and cell_status FTC_CELL_SURROGATE; every other cell is
+   computed by ftc_ppic_curvature's kernels (params as there; coefficients
+   and decisions are not written) and gets its status.  spread
+   [cell_capacity] (device float, or NULL) receives every cell's spread.
+   d_n_fallback (device, one int32, or NULL) receives the number of cells
+   handed to PPIC.  Outputs have cell_capacity entries (device).  The mesh
+   must be the one of the last build. */
+ftc_status ftc_learned_curvature(const ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
+                                 const double* alpha_dense, const float* theta, double bound,
+                                 const ftc_ppic_params* params, double* kappa, double* nx, double* ny, double* nz,
+                                 float* spread, int32_t* cell_status, int32_t* d_n_fallback, void* stream);
 
 #ifdef __cplusplus
 }

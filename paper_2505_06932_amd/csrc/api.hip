@@ -152,6 +152,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(wl_w, ftc::kFitList * Cc);
   FTC_ALLOC(best_d2, Cc);
   FTC_ALLOC(best_v, Cc);
+  FTC_ALLOC(sel_cells, Cc);
 #undef FTC_ALLOC
   w.timing = 0;
   int nev = 0;
@@ -296,6 +297,59 @@ ftc_status ftc_advect_vertices_rk4(ftc_cells* cells, const ftc_grid* grid, const
   if (!on_device(cells)) return FTC_EINVAL;
   return hip_status(ftc::launch_advect_rk4(cells, to_grid(grid), to_mesh(mesh), U, V, W, dt, x_out, y_out, z_out,
                                            (hipStream_t)stream));
+}
+
+ftc_status ftc_curvature_features(const ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
+                                  const double* alpha_dense, float* features, int32_t* final_flags, void* stream) {
+  if (!cells || !grid_valid(grid) || !mesh_valid(mesh) || !same_grid(cells->grid, grid) || !alpha_dense || !features)
+    return FTC_EINVAL;
+  if (mesh->nv != cells->built_nv || mesh->nt != cells->built_nt || !on_device(cells)) return FTC_EINVAL;
+  return hip_status(ftc::launch_features(cells, to_mesh(mesh), alpha_dense, features, final_flags,
+                                         (hipStream_t)stream));
+}
+
+ftc_status ftc_mlp_forward(const float* theta, const float* X, int64_t rows, const int32_t* idx, const int32_t* sym,
+                           int32_t n, float* y, void* stream) {
+  if (!theta || !X || rows <= 0 || n < 0 || !y) return FTC_EINVAL;
+  if (n == 0) return FTC_OK;
+  return hip_status(ftc::launch_mlp_forward(theta, X, rows, idx, sym, n, y, (hipStream_t)stream));
+}
+
+ftc_status ftc_mlp_loss_grad(const float* theta, const float* X, int64_t rows, const int32_t* idx,
+                             const int32_t* sym, const float* t, int32_t n, float* grad, float* loss, float* work,
+                             void* stream) {
+  if (!theta || !X || rows <= 0 || !t || n <= 0 || !grad || !work) return FTC_EINVAL;
+  return hip_status(ftc::launch_mlp_loss_grad(theta, X, rows, idx, sym, t, n, grad, loss, work, (hipStream_t)stream));
+}
+
+ftc_status ftc_mlp_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr, float beta1,
+                        float beta2, float eps, void* stream) {
+  if (!theta || !m || !v || !grad || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return FTC_EINVAL;
+  return hip_status(ftc::launch_mlp_adam(theta, m, v, grad, step, lr, beta1, beta2, eps, (hipStream_t)stream));
+}
+
+ftc_status ftc_learned_curvature(const ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh,
+                                 const double* alpha_dense, const float* theta, double bound,
+                                 const ftc_ppic_params* params, double* kappa, double* nx, double* ny, double* nz,
+                                 float* spread, int32_t* cell_status, int32_t* d_n_fallback, void* stream) {
+  if (!cells || !grid_valid(grid) || !mesh_valid(mesh) || !same_grid(cells->grid, grid) || !alpha_dense || !theta ||
+      !kappa || !nx || !ny || !nz || !(bound >= 0.0))
+    return FTC_EINVAL;
+  if (mesh->nv != cells->built_nv || mesh->nt != cells->built_nt) return FTC_EINVAL;
+  ftc::PPICParams p{2.5, 3, 24, 1.1, 16, 0};
+  if (params) {
+    p = ftc::PPICParams{params->delta_over_h, params->rings,    params->n_min,
+                        params->grow,         params->max_iter, params->precision};
+    if (!(p.delta_over_h > 0.0) || !isfinite(p.delta_over_h) || p.rings < 1 || p.rings > 4 || p.n_min < 1 ||
+        !(p.grow > 1.0) || !isfinite(p.grow) || p.max_iter < 0 || p.max_iter > 64 || p.mixed < 0 ||
+        p.mixed > 1)
+      return FTC_EINVAL;
+  }
+  if (!on_device(cells)) return FTC_EINVAL;
+  return hip_status(ftc::launch_surrogate(cells, to_mesh(mesh), alpha_dense, theta, (float)bound, p, kappa, nx, ny,
+                                          nz, spread, cell_status, d_n_fallback, (hipStream_t)stream));
 }
 
 ftc_status ftc_last_device_error(ftc_cells* cells, int32_t* code, void* stream) {

@@ -20,7 +20,9 @@ enum : int {
   C_NSTRAY = 5,   // vertices in cells without pieces
   C_NOVF = 6,     // interfacial cells whose ring exceeds the fast PPIC kernel's capacities
   C_NQUEUED = 7,  // C_NOVF as the wide PPIC shape reads it (moved there by the fit pass)
-  C_COUNT = 8
+  C_NSEL = 8,      // cells the learned curvature hands to PPIC (cleared by the last workgroup that reads it)
+  C_NSELDONE = 9,  // workgroups of that PPIC kernel that have finished
+  C_COUNT = 10
 };
 }  // namespace ftc
 
@@ -76,6 +78,7 @@ struct ftc_cells {
   double* fit;            // [kFitSlots * cell_cap] per cell: normal equations (21 + 6), vertex normal (3), weighted count
   int32_t* wl_tri;        // [4 * cell_cap * kFitList] packed corners of the triangles of each cell's fit
   double* wl_w;           // [cell_cap * kFitList] their weights
+  int32_t* sel_cells;     // [cell_cap] cells the learned curvature hands to PPIC
   double* best_d2;        // [cell_cap] smallest squared distance of a vertex in the 27 cells around
   int32_t* best_v;        // [cell_cap] lowest vertex attaining it
 
@@ -140,6 +143,23 @@ struct PPICParams {
 hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, double* kappa, double* nx,
                        double* ny, double* nz, double* coeff, int32_t* cell_status, int32_t* diag,
                        hipStream_t s);
+// The PPIC kernels on the cells sel[0, counters[C_NSEL]) only (sel non-null).
+hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParams& p, double* kappa, double* nx,
+                             double* ny, double* nz, double* coeff, int32_t* cell_status, int32_t* diag,
+                             const int32_t* sel, int32_t* n_sel_out, hipStream_t s);
+// Learned curvature (surrogate.hip).
+hipError_t launch_features(const ftc_cells* ws, const Mesh& m, const double* alpha, float* feat, int32_t* fstat,
+                           hipStream_t s);
+hipError_t launch_mlp_forward(const float* theta, const float* X, int64_t rows, const int32_t* idx,
+                              const int32_t* sym, int32_t n, float* y, hipStream_t s);
+hipError_t launch_mlp_loss_grad(const float* theta, const float* X, int64_t rows, const int32_t* idx,
+                                const int32_t* sym, const float* t, int32_t n, float* grad, float* loss, float* work,
+                                hipStream_t s);
+hipError_t launch_mlp_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr, float beta1,
+                           float beta2, float eps, hipStream_t s);
+hipError_t launch_surrogate(const ftc_cells* ws, const Mesh& m, const double* alpha, const float* theta, float bound,
+                            const PPICParams& p, double* kappa, double* nx, double* ny, double* nz, float* spread,
+                            int32_t* status, int32_t* n_fallback, hipStream_t s);
 hipError_t launch_csf(const ftc_cells* ws, const double* alpha, const double* kappa, double sigma, double* fx,
                       double* fy, double* fz, hipStream_t s);
 hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const double* kappa, const double* nx,

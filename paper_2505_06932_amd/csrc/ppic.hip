@@ -99,7 +99,11 @@ struct PPICArgs {
   int32_t cell_cap;
   double *kappa, *nx, *ny, *nz, *coeff;
   int32_t *status, *diag;
+  const int32_t* sel;  // null: every interfacial cell; else the cells sel[0, counters[C_NSEL])
+  int32_t* n_sel_out;  // receives the selection's count (may be null)
 };
+
+
 
 // Ring-building state, dead once the rings are complete.
 template <class C>
@@ -353,7 +357,8 @@ __device__ inline void solve_cell(const PPICArgs& A, int32_t c, const double* F,
 // The cells of one shape, processed by workgroup `bid` of `nblk` (64 lanes).
 // kQueue = false: every interfacial cell, overflowing cells queued.
 // kQueue = true: the queued cells.
-template <class C, bool kQueue>
+// kSel: the cells of the surrogate's selection (with the wide shape).
+template <class C, bool kQueue, bool kSel = false>
 __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) {
   constexpr int G = C::G, NG = C::NG;
   __shared__ CellMem<C> SM[NG];
@@ -362,7 +367,8 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
   CellMem<C>& CM = SM[grp];
   RingMem<C>& RM = CM.u.r;
   FitMem<C>& FM = CM.u.f;
-  const int32_t nitems = kQueue ? min(A.counters[C_NQUEUED], A.cell_cap) : min(A.counters[C_NIF], A.cell_cap);
+  const int32_t nitems = kSel ? min(A.counters[C_NSEL], A.cell_cap)
+                              : (kQueue ? min(A.counters[C_NQUEUED], A.cell_cap) : min(A.counters[C_NIF], A.cell_cap));
   const double h = g.h;
   const int R = A.prm.rings;
   const double reach = 1.5 * h;
@@ -378,7 +384,7 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
     if (gi >= ngroups) break;
     const int32_t item = gi * NG + grp;
     const bool act = item < nitems;
-    const int32_t c = act ? (kQueue ? A.ovf_cells[item] : item) : 0;
+    const int32_t c = act ? (kSel ? A.sel[item] : (kQueue ? A.ovf_cells[item] : item)) : 0;
     const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
     const double xc[3] = {cell_centre(g.x0, cc3.i, h), cell_centre(g.y0, cc3.j, h), cell_centre(g.z0, cc3.k, h)};
 
@@ -784,6 +790,23 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
 }
 
 __global__ __launch_bounds__(64) void k_ppic_rings(PPICArgs A) { ppic_cells<Fast, false>(A, blockIdx.x, gridDim.x); }
+// The cells the learned curvature hands over, sel[0, counters[C_NSEL]), with
+// the wide shape (rings, fit and solve in the workgroup, one cell at a
+// time): a selection is a small part of the cells, and the wide shape's
+// per-cell latency is the lower.  The last workgroup to finish reports the
+// count and clears it for the next call (every workgroup has read it by then).
+__global__ __launch_bounds__(64) void k_ppic_wide_sel(PPICArgs A) {
+  ppic_cells<Wide, true, true>(A, blockIdx.x, gridDim.x);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&A.counters[C_NSELDONE], 1) == (int32_t)gridDim.x - 1) {
+      if (A.n_sel_out) *A.n_sel_out = A.counters[C_NSEL];
+      A.counters[C_NSEL] = 0;
+      A.counters[C_NSELDONE] = 0;
+    }
+  }
+}
 
 // Weighted moments and normal equations of the cells whose ring fitted the
 // fast shape: 8 lanes per cell (8 cells per wavefront) over the cell's
@@ -1047,10 +1070,10 @@ __global__ __launch_bounds__(64) void k_ppic_wide_solve(PPICArgs A) {
     ppic_cells<Wide, true>(A, blockIdx.x, kWideBlocks);
     return;
   }
-  const int32_t nif = min(A.counters[C_NIF], A.cell_cap);
+  const int32_t nitems = min(A.counters[C_NIF], A.cell_cap);
   const int64_t cs = A.cell_cap;
   const int32_t nb = gridDim.x - kWideBlocks;
-  for (int32_t c = (blockIdx.x - kWideBlocks) * 64 + threadIdx.x; c < nif; c += nb * 64) {
+  for (int32_t c = (blockIdx.x - kWideBlocks) * 64 + threadIdx.x; c < nitems; c += nb * 64) {
     const double* F = A.fit + c;
     if (F[30 * cs] == -3.0) continue;  // queued: solved by the wide shape
     solve_cell(A, c, F, cs, A.prm.mixed != 0);
@@ -1063,6 +1086,12 @@ inline int32_t round_up(int64_t n, int64_t m) { return (int32_t)((n + m - 1) / m
 
 hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, double* kappa, double* nx,
                        double* ny, double* nz, double* coeff, int32_t* cell_status, int32_t* diag, hipStream_t s) {
+  return launch_ppic_cells(ws, m, p, kappa, nx, ny, nz, coeff, cell_status, diag, nullptr, nullptr, s);
+}
+
+hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParams& p, double* kappa, double* nx,
+                             double* ny, double* nz, double* coeff, int32_t* cell_status, int32_t* diag,
+                             const int32_t* sel, int32_t* n_sel_out, hipStream_t s) {
   const Grid& g = ws->grid;
   int4* tri4 = reinterpret_cast<int4*>(ws->tri4);
   double2* vtx4 = reinterpret_cast<double2*>(ws->vtx4);
@@ -1090,16 +1119,23 @@ hipError_t launch_ppic(const ftc_cells* ws, const Mesh& m, const PPICParams& p, 
   A.coeff = coeff;
   A.status = cell_status;
   A.diag = diag;
+  A.sel = sel;
+  A.n_sel_out = n_sel_out;
   const int64_t groups = ((int64_t)ws->cell_cap + Fast::NG - 1) / Fast::NG;
   const int32_t blocks = round_up(std::min<int64_t>(std::max<int64_t>(groups, 1), 65536), kXCD);
   time_start(ws, FTC_KERNEL_PPIC, s);
-  hipLaunchKernelGGL(k_ppic_rings, dim3(blocks), dim3(64), 0, s, A);
-  const dim3 fit_grid(round_up(std::min<int64_t>(std::max<int64_t>(((int64_t)ws->cell_cap + 7) / 8, 1), 65536), kXCD));
-  if (p.mixed)
-    hipLaunchKernelGGL(k_ppic_fit_mixed, fit_grid, dim3(64), 0, s, A);
-  else
-    hipLaunchKernelGGL(k_ppic_fit, fit_grid, dim3(64), 0, s, A);
-  hipLaunchKernelGGL(k_ppic_wide_solve, dim3(kWideBlocks + grid_blocks(ws->cell_cap, 64)), dim3(64), 0, s, A);
+  if (sel) {
+    hipLaunchKernelGGL(k_ppic_wide_sel, dim3(round_up(std::min<int64_t>(std::max<int64_t>(ws->cell_cap, 1), 2048), kXCD)),
+                       dim3(64), 0, s, A);
+  } else {
+    hipLaunchKernelGGL(k_ppic_rings, dim3(blocks), dim3(64), 0, s, A);
+    const dim3 fit_grid(round_up(std::min<int64_t>(std::max<int64_t>(((int64_t)ws->cell_cap + 7) / 8, 1), 65536), kXCD));
+    if (p.mixed)
+      hipLaunchKernelGGL(k_ppic_fit_mixed, fit_grid, dim3(64), 0, s, A);
+    else
+      hipLaunchKernelGGL(k_ppic_fit, fit_grid, dim3(64), 0, s, A);
+    hipLaunchKernelGGL(k_ppic_wide_solve, dim3(kWideBlocks + grid_blocks(ws->cell_cap, 64)), dim3(64), 0, s, A);
+  }
   time_stop(ws, FTC_KERNEL_PPIC, s);
   return hipGetLastError();
 }

@@ -26,16 +26,20 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libftc.so")
 
 FTC_OK, FTC_EINVAL, FTC_EDOMAIN, FTC_EMESH, FTC_ECAPACITY, FTC_ENOMEM, FTC_EHIP = 0, -1, -2, -3, -4, -5, -6
-FTC_CELL_RANK, FTC_CELL_OVERFLOW = 1, 2
+FTC_CELL_RANK, FTC_CELL_OVERFLOW, FTC_CELL_SURROGATE = 1, 2, 4
+# learned curvature: feature row width, parameter count, loss-gradient work floats
+MLP_FEATURES, MLP_PARAMS = 32, 6209
+MLP_WORK_FLOATS = 256 * (MLP_PARAMS + 3)
 
 EXPORTED = ["ftc_cells_create", "ftc_cells_destroy", "ftc_build_cell_lists", "ftc_cells_count",
             "ftc_cells_view", "ftc_volume_fraction", "ftc_ppic_curvature", "ftc_csf_force",
             "ftc_interp_vertex_velocity", "ftc_last_device_error", "ftc_set_timing", "ftc_kernel_time",
-            "ftc_csf_force_band", "ftc_advect_vertices_rk4",
+            "ftc_csf_force_band", "ftc_advect_vertices_rk4", "ftc_curvature_features", "ftc_mlp_forward",
+            "ftc_mlp_loss_grad", "ftc_mlp_adam", "ftc_learned_curvature",
             "ftc_status_str"]
 
 # ftc_kernel values (timing)
-KERNELS = {"tri_pieces": 0, "piece_rank": 1, "columns": 2, "ppic": 3, "csf": 4, "interp": 5}
+KERNELS = {"tri_pieces": 0, "piece_rank": 1, "columns": 2, "ppic": 3, "csf": 4, "interp": 5, "surrogate": 6}
 
 
 class _CGrid(C.Structure):
@@ -110,6 +114,17 @@ def lib() -> C.CDLL:
     L.ftc_interp_vertex_velocity.restype = C.c_int32
     L.ftc_advect_vertices_rk4.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, vp, C.c_double, vp, vp, vp, vp]
     L.ftc_advect_vertices_rk4.restype = C.c_int32
+    L.ftc_curvature_features.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, vp, vp]
+    L.ftc_curvature_features.restype = C.c_int32
+    L.ftc_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_int32, vp, vp]
+    L.ftc_mlp_forward.restype = C.c_int32
+    L.ftc_mlp_loss_grad.argtypes = [vp, vp, C.c_int64, vp, vp, vp, C.c_int32, vp, vp, vp, vp]
+    L.ftc_mlp_loss_grad.restype = C.c_int32
+    L.ftc_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    L.ftc_mlp_adam.restype = C.c_int32
+    L.ftc_learned_curvature.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, C.c_double, P(_CParams), vp, vp, vp, vp,
+                                        vp, vp, vp, vp]
+    L.ftc_learned_curvature.restype = C.c_int32
     L.ftc_last_device_error.argtypes = [vp, P(C.c_int32), vp]
     L.ftc_last_device_error.restype = C.c_int32
     L.ftc_set_timing.argtypes = [vp, C.c_int32]
@@ -357,3 +372,71 @@ def interp_vertex_velocity(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, U
                                             _ptr(ux, torch.float64, nv, "ux"), _ptr(uy, torch.float64, nv, "uy"),
                                             _ptr(uz, torch.float64, nv, "uz"), _stream(stream)),
            "ftc_interp_vertex_velocity")
+
+
+# ------------------------------------------------------------ learned curvature
+def curvature_features(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, alpha_dense, features,
+                       final_flags=None, stream=None) -> None:
+    """Feature rows [cell_capacity, 32] (float32) of the interfacial cells."""
+    cg = c_grid(grid)
+    cap = cells.cell_capacity
+    _check(lib().ftc_curvature_features(cells.handle, C.byref(cg), C.byref(mesh.c),
+                                        _ptr(alpha_dense, torch.float64, grid.ncell, "alpha_dense"),
+                                        _ptr(features, torch.float32, cap * MLP_FEATURES, "features"),
+                                        _ptr(final_flags, torch.int32, cap, "final_flags"), _stream(stream)),
+           "ftc_curvature_features")
+
+
+def _rows(X):
+    if X.dim() != 2 or X.shape[1] != MLP_FEATURES:
+        raise ValueError(f"X must be [rows, {MLP_FEATURES}]")
+    return X.shape[0]
+
+
+def mlp_forward(theta, X, y, n=None, idx=None, sym=None, stream=None) -> None:
+    rows = _rows(X)
+    n = rows if n is None and idx is None else (int(idx.numel()) if n is None else int(n))
+    _check(lib().ftc_mlp_forward(_ptr(theta, torch.float32, MLP_PARAMS, "theta"),
+                                 _ptr(X, torch.float32, rows * MLP_FEATURES, "X"), rows,
+                                 _ptr(idx, torch.int32, n, "idx"), _ptr(sym, torch.int32, n, "sym"), n,
+                                 _ptr(y, torch.float32, n, "y"), _stream(stream)), "ftc_mlp_forward")
+
+
+def mlp_loss_grad(theta, X, t, grad, work, loss=None, n=None, idx=None, sym=None, stream=None) -> None:
+    rows = _rows(X)
+    n = rows if n is None and idx is None else (int(idx.numel()) if n is None else int(n))
+    _check(lib().ftc_mlp_loss_grad(_ptr(theta, torch.float32, MLP_PARAMS, "theta"),
+                                   _ptr(X, torch.float32, rows * MLP_FEATURES, "X"), rows,
+                                   _ptr(idx, torch.int32, n, "idx"), _ptr(sym, torch.int32, n, "sym"),
+                                   _ptr(t, torch.float32, rows, "t"), n, _ptr(grad, torch.float32, MLP_PARAMS, "grad"),
+                                   _ptr(loss, torch.float32, 1, "loss"),
+                                   _ptr(work, torch.float32, MLP_WORK_FLOATS, "work"), _stream(stream)),
+           "ftc_mlp_loss_grad")
+
+
+def mlp_adam(theta, m, v, grad, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+             stream=None) -> None:
+    _check(lib().ftc_mlp_adam(_ptr(theta, torch.float32, MLP_PARAMS, "theta"), _ptr(m, torch.float32, MLP_PARAMS, "m"),
+                              _ptr(v, torch.float32, MLP_PARAMS, "v"), _ptr(grad, torch.float32, MLP_PARAMS, "grad"),
+                              int(step), float(lr), float(beta1), float(beta2), float(eps), _stream(stream)),
+           "ftc_mlp_adam")
+
+
+def learned_curvature(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, alpha_dense, theta, bound: float, kappa,
+                      nx, ny, nz, spread=None, cell_status=None, n_fallback=None, params: PPICParams | None = None,
+                      stream=None) -> None:
+    cg = c_grid(grid)
+    cap = cells.cell_capacity
+    p = None
+    if params is not None:
+        p = C.byref(_CParams(params.delta_over_h, params.rings, params.n_min, params.grow, params.max_iter,
+                             params.precision))
+    _check(lib().ftc_learned_curvature(cells.handle, C.byref(cg), C.byref(mesh.c),
+                                       _ptr(alpha_dense, torch.float64, grid.ncell, "alpha_dense"),
+                                       _ptr(theta, torch.float32, MLP_PARAMS, "theta"), float(bound), p,
+                                       _ptr(kappa, torch.float64, cap, "kappa"), _ptr(nx, torch.float64, cap, "nx"),
+                                       _ptr(ny, torch.float64, cap, "ny"), _ptr(nz, torch.float64, cap, "nz"),
+                                       _ptr(spread, torch.float32, cap, "spread"),
+                                       _ptr(cell_status, torch.int32, cap, "cell_status"),
+                                       _ptr(n_fallback, torch.int32, 1, "n_fallback"), _stream(stream)),
+           "ftc_learned_curvature")

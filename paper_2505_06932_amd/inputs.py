@@ -393,13 +393,15 @@ def sh_spheres_workload(n: int, count: int, seed: int, r_lo: float = 4.0, r_hi: 
 #: 256^3 with edges near h/2; "revolution_512" is the 512^3 surface of
 #: revolution with 1,997,120 triangles; "sh_spheres_128" is 8 disjoint
 #: spheres with spherical-harmonic perturbations (R in [4h, 20h], degree <= 8,
-#: amplitude <= 0.1 R) on 128^3, the learned-curvature workload.
+#: amplitude <= 0.1 R) on 128^3, the learned-curvature workload;
+#: "sh_spheres_256" is 64 of them on 256^3 (about 223k interfacial cells).
 WORKLOADS = {
     "sphere_32": (sphere_workload, dict(n=32, radius=0.25, subdivisions=4, noise_over_h=0.0)),
     "sphere_128": (sphere_workload, dict(n=128, radius=0.3, subdivisions=6, noise_over_h=0.01)),
     "ellipsoids_256": (ellipsoids_workload, dict(n=256, count=64)),
     "revolution_512": (polar_revolution_workload, dict(n=512, radius=0.2, freq=316)),
     "sh_spheres_128": (sh_spheres_workload, dict(n=128, count=8)),
+    "sh_spheres_256": (sh_spheres_workload, dict(n=256, count=64)),
 }
 
 

@@ -14,7 +14,11 @@ from . import inputs as I
 class CouplingStep:
     def __init__(self, grid: I.Grid, mesh: I.Mesh, U=None, V=None, W=None, sigma: float = 1.0,
                  params: ftc.PPICParams | None = None, margin: float = 1.25,
-                 pair_capacity: int | None = None, cell_capacity: int | None = None, band: bool = False):
+                 pair_capacity: int | None = None, cell_capacity: int | None = None, band: bool = False,
+                 learned=None, bound: float | None = None):
+        """learned: surrogate parameters (device float32 tensor of
+        ftc.MLP_PARAMS values); the curvature is then the learned surrogate
+        with its PPIC fallback above the spread `bound`."""
         self.grid = grid
         self.sigma = float(sigma)
         self.params = params
@@ -54,6 +58,12 @@ class CouplingStep:
         self.fx, self.fy, self.fz = z(cap), z(cap), z(cap)
         self.ux, self.uy, self.uz = z(nv), z(nv), z(nv)
         self.band = band
+        self.learned = learned
+        if learned is not None:
+            from . import surrogate
+            self.bound = surrogate.DEFAULT_BOUND if bound is None else float(bound)
+            self.spread = z(cap, torch.float32)
+            self.n_fallback = z(1, torch.int32)
         if band:
             # every band cell is a face neighbour of an interfacial cell
             bcap = 6 * cap
@@ -68,6 +78,11 @@ class CouplingStep:
         ftc.volume_fraction(self.cells, self.grid, self.mesh, self.alpha_if, self.alpha, stream)
 
     def curvature(self, stream=None, diagnostics=True):
+        if self.learned is not None:
+            ftc.learned_curvature(self.cells, self.grid, self.mesh, self.alpha, self.learned, self.bound, self.kappa,
+                                  self.nx, self.ny, self.nz, spread=self.spread, cell_status=self.status,
+                                  n_fallback=self.n_fallback, params=self.params, stream=stream)
+            return
         ftc.ppic_curvature(self.cells, self.grid, self.mesh, self.kappa, self.nx, self.ny, self.nz,
                            self.coeff if diagnostics else None, self.status,
                            self.diag if diagnostics else None, self.params, stream)
@@ -104,6 +119,8 @@ class CouplingStep:
             force=np.stack([h(self.fx)[:n_if], h(self.fy)[:n_if], h(self.fz)[:n_if]], 1),
             u=np.stack([h(self.ux), h(self.uy), h(self.uz)], 1),
             **(self._band_results(h) if self.band else {}),
+            **(dict(spread=h(self.spread)[:n_if], n_fallback=int(h(self.n_fallback)[0]))
+               if self.learned is not None else {}),
             error=self.cells.last_device_error())
 
     def _band_results(self, h):

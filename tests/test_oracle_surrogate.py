@@ -270,3 +270,23 @@ def test_learned_curvature_fallback_rule():
     assert np.array_equal(k[fb], ppic[fb])
     mean, _ = S.predict(th, S.features(grid, mesh, alpha, cells)[0])
     assert np.array_equal(k[~fb], mean[~fb] / grid.h)
+
+
+def test_committed_parameters_predict_sphere_curvature():
+    """The trained parameters shipped with the package, evaluated by the
+    oracle's network on the R = 8h sphere (inside the training range): the
+    trusted cells' kappa agrees with the exact 2/R to a few percent."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2505_06932_amd",
+                        "surrogate_theta.npy")
+    th = np.load(path, allow_pickle=False)
+    assert th.shape == (S.NP,) and th.dtype == np.float32 and np.all(np.isfinite(th))
+    grid, mesh, _ = I.make_workload("sphere_32", 0)
+    alpha, _ = oracle.volume_fraction(grid, mesh)
+    cells, _, _ = oracle.cell_lists(grid, mesh)
+    F, final = S.features(grid, mesh, alpha, cells)
+    mean, spread = S.predict(th.astype(np.float64), F)
+    trusted = final & (spread <= 0.01)
+    assert trusted.mean() > 0.5
+    rel = np.abs(mean[trusted] / grid.h / (2.0 / 0.25) - 1.0)
+    assert np.median(rel) < 0.05
