@@ -95,8 +95,8 @@ typedef struct ftc_cells ftc_cells;
    pair_capacity (cell, triangle) pieces and cell_capacity interfacial
    cells (candidates that must be clipped, up to twice pair_capacity, are
    queued internally).  Device memory is about 116 B x pairs + 1.85 kB x cells
-   + 40 B x triangles + 56 B x vertices + 3 nx*ny*nz/8 B (about 105 MB for a
-   128^3 grid with 82k triangles, 1.2 GB for 512^3 with 2M triangles).
+   + 104 B x triangles + 84 B x vertices + 3 nx*ny*nz/8 B (about 110 MB for a
+   128^3 grid with 82k triangles, 1.4 GB for 512^3 with 2M triangles).
    Returns FTC_EINVAL, FTC_ENOMEM or FTC_OK; *out is NULL on failure. */
 ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_capacity,
                             int32_t nt_capacity, int64_t pair_capacity, int32_t cell_capacity);
@@ -346,6 +346,49 @@ ftc_status ftc_learned_curvature(const ftc_cells* cells, const ftc_grid* grid, c
                                  const double* alpha_dense, const float* theta, double bound,
                                  const ftc_ppic_params* params, double* kappa, double* nx, double* ny, double* nz,
                                  float* spread, int32_t* cell_status, int32_t* d_n_fallback, void* stream);
+
+/* ------------------------------------------------------------------------
+   Local roughness detection and smoothing of the front (paper section 3.4).
+   Both calls use the vertex adjacency of the last build (the mesh must be
+   that build's) and treat the front as closed and consistently oriented.
+   ------------------------------------------------------------------------ */
+
+/* Per vertex (device arrays of nv doubles): gl_mag, the length of the
+   geometric Laplacian x_i - sum_j w_ij x_j / sum_j w_ij over the one-ring,
+   w_ij = 1 / |x_i - x_j|; rough, the dihedral roughness max(R^1, R^2),
+   where R_e = 1 - n1 . n2 on each edge (unit normals of its two triangles),
+   G_i and V_i are the mean and the population variance of R_e over the edges
+   at i, R_t = sum G V / sum V over a triangle's corners (the mean of the G if
+   every V is 0), and R^l_i is the mean of A_t R_t over the triangles of the
+   l-ring of i (A_t the area; the two-ring holds the triangles with a corner
+   in i's one-ring or at i). */
+ftc_status ftc_front_roughness(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh, double* gl_mag,
+                               double* rough, void* stream);
+
+/* Volume-conserving smoothing of the rough edges (paper section 3.4, after
+   Kuprat et al. 2001, algorithm 4).  A vertex is rough when gl_mag >
+   gl_threshold and rough > rough_threshold (the paper takes 1.2 to 1.5 times
+   the maxima on the initial front); an edge is smoothed when both its ends
+   are rough.  Its ends move to the simultaneous Laplacian positions
+   x1s = (S2 + n2 S1) / (n1 n2 - 1), x2s = (x1s + S2) / n2 (n_i the one-ring
+   sizes, S_i the one-ring sums without the other end), plus the least common
+   displacement that keeps the enclosed volume: -c g / |g|^2 with
+   g = A1 + A2 + y x (d1 - d2), c = d1.A1 + d2.A2 + d1.(d2 x y), d_i = x_is - x_i,
+   A_i the sum of (a - x_i) x (b - x_i) over the triangles (x_i, a, b) at end
+   i and y the difference of the far corners of the triangles holding the
+   half-edges x1 -> x2 and x2 -> x1 (the enclosed volume then changes by
+   exactly 0; the text prints the last term of c as d1.(y x d1), which
+   vanishes identically).  Edges are processed in up to max_rounds rounds: in
+   each, an edge is taken unless a pending edge ordered before it has an end
+   within one ring of it; edges are ordered by (fmix32(id), id), fmix32 the
+   32-bit finalizer of MurmurHash3 and id = 3 t + k for the half-edge a -> b,
+   a < b, at corners k, k+1 of triangle t; an edge with g = 0 is left in place.
+   New positions go to x_out, y_out, z_out (device, nv each; the mesh's
+   positions where nothing moved).  d_counts (device, 3 int32): edges
+   listed, edges moved, edges still pending after the rounds. */
+ftc_status ftc_smooth_rough_edges(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh, const double* gl_mag,
+                                  const double* rough, double gl_threshold, double rough_threshold, int32_t max_rounds,
+                                  double* x_out, double* y_out, double* z_out, int32_t* d_counts, void* stream);
 
 #ifdef __cplusplus
 }

@@ -42,9 +42,12 @@ volume requires is d_1 . (d_2 x y).)  An edge with g = 0 is left alone.
 
 Schedule: the flagged edges are smoothed in rounds; in each round an edge is
 taken when no other edge still pending lies within one ring of it (an end of
-one is an end or a one-ring vertex of an end of the other) and has a smaller
-id.  Edges of one round move disjoint vertices and read no vertex another
-one moves, so each round is the same as smoothing its edges one by one.
+one is an end or a one-ring vertex of an end of the other) and comes before
+it in the priority order: edges by (fmix32(id), id), fmix32 the 32-bit
+finalizer of MurmurHash3 (Appleby), which scatters neighbouring ids so that
+the rounds stay few.  Edges of one round move disjoint vertices and read no
+vertex another one moves, so each round is the same as smoothing its edges
+one by one.
 """
 from __future__ import annotations
 
@@ -191,25 +194,36 @@ def flagged_edges(topo: Topology, gl_mag, rough, gl_threshold, rough_threshold):
     return [(eid, a, b) for eid, a, b in topo.edges if rough_v[a] and rough_v[b]], rough_v
 
 
+def fmix32(x: int) -> int:
+    """The 32-bit finalizer of MurmurHash3."""
+    x &= 0xFFFFFFFF
+    x ^= x >> 16
+    x = (x * 0x85EBCA6B) & 0xFFFFFFFF
+    x ^= x >> 13
+    x = (x * 0xC2B2AE35) & 0xFFFFFFFF
+    x ^= x >> 16
+    return x
+
+
+def priority(eid: int):
+    return (fmix32(eid), eid)
+
+
 def schedule(topo: Topology, edges):
     """Rounds of the flagged edges (lists of (id, a, b))."""
     pending = list(edges)
     rounds = []
     while pending:
-        near = {}
+        at = {}
         for e in pending:
-            _, a, b = e
-            near[e[0]] = {a, b, *topo.ring[a], *topo.ring[b]}
+            at.setdefault(e[1], []).append(e)
+            at.setdefault(e[2], []).append(e)
         take = []
         for e in pending:
             eid, a, b = e
-            ok = True
-            for f in pending:
-                fid, c, d = f
-                if fid < eid and (c in near[eid] or d in near[eid]):
-                    ok = False
-                    break
-            if ok:
+            pe = priority(eid)
+            near = {a, b, *topo.ring[a], *topo.ring[b]}
+            if not any(priority(f[0]) < pe for u in near for f in at.get(u, ())):
                 take.append(e)
         rounds.append(take)
         ids = {e[0] for e in take}

@@ -153,6 +153,13 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(best_d2, Cc);
   FTC_ALLOC(best_v, Cc);
   FTC_ALLOC(sel_cells, Cc);
+  FTC_ALLOC(r_tn, 4 * (int64_t)nt_capacity);
+  FTC_ALLOC(r_vG, nv_capacity);
+  FTC_ALLOC(r_vV, nv_capacity);
+  FTC_ALLOC(r_rt, nt_capacity);
+  FTC_ALLOC(r_vflag, nv_capacity);
+  FTC_ALLOC(r_estate, 3 * (int64_t)nt_capacity);
+  FTC_ALLOC(r_elist, 3 * (int64_t)nt_capacity);
 #undef FTC_ALLOC
   w.timing = 0;
   int nev = 0;
@@ -350,6 +357,26 @@ ftc_status ftc_learned_curvature(const ftc_cells* cells, const ftc_grid* grid, c
   if (!on_device(cells)) return FTC_EINVAL;
   return hip_status(ftc::launch_surrogate(cells, to_mesh(mesh), alpha_dense, theta, (float)bound, p, kappa, nx, ny,
                                           nz, spread, cell_status, d_n_fallback, (hipStream_t)stream));
+}
+
+ftc_status ftc_front_roughness(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh, double* gl_mag,
+                               double* rough, void* stream) {
+  if (!cells || !grid_valid(grid) || !mesh_valid(mesh) || !same_grid(cells->grid, grid) || !gl_mag || !rough)
+    return FTC_EINVAL;
+  if (mesh->nv != cells->built_nv || mesh->nt != cells->built_nt || !on_device(cells)) return FTC_EINVAL;
+  return hip_status(ftc::launch_roughness(cells, to_mesh(mesh), gl_mag, rough, (hipStream_t)stream));
+}
+
+ftc_status ftc_smooth_rough_edges(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh, const double* gl_mag,
+                                  const double* rough, double gl_threshold, double rough_threshold, int32_t max_rounds,
+                                  double* x_out, double* y_out, double* z_out, int32_t* d_counts, void* stream) {
+  if (!cells || !grid_valid(grid) || !mesh_valid(mesh) || !same_grid(cells->grid, grid) || !gl_mag || !rough || !x_out ||
+      !y_out || !z_out || !d_counts || max_rounds < 0 || max_rounds > 4096 || isnan(gl_threshold) ||
+      isnan(rough_threshold))
+    return FTC_EINVAL;
+  if (mesh->nv != cells->built_nv || mesh->nt != cells->built_nt || !on_device(cells)) return FTC_EINVAL;
+  return hip_status(ftc::launch_smooth(cells, to_mesh(mesh), gl_mag, rough, gl_threshold, rough_threshold, max_rounds,
+                                       x_out, y_out, z_out, d_counts, (hipStream_t)stream));
 }
 
 ftc_status ftc_last_device_error(ftc_cells* cells, int32_t* code, void* stream) {

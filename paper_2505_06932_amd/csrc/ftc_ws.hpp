@@ -22,7 +22,9 @@ enum : int {
   C_NQUEUED = 7,  // C_NOVF as the wide PPIC shape reads it (moved there by the fit pass)
   C_NSEL = 8,      // cells the learned curvature hands to PPIC (cleared by the last workgroup that reads it)
   C_NSELDONE = 9,  // workgroups of that PPIC kernel that have finished
-  C_COUNT = 10
+  C_RFLAG = 10,    // edges listed for roughness smoothing
+  C_RMOVED = 11,   // edges moved by it
+  C_COUNT = 12
 };
 }  // namespace ftc
 
@@ -79,6 +81,14 @@ struct ftc_cells {
   int32_t* wl_tri;        // [4 * cell_cap * kFitList] packed corners of the triangles of each cell's fit
   double* wl_w;           // [cell_cap * kFitList] their weights
   int32_t* sel_cells;     // [cell_cap] cells the learned curvature hands to PPIC
+  // roughness detection and smoothing
+  double* r_tn;           // [4 * nt_cap] unit normal and area of each triangle
+  double* r_vG;           // [nv_cap] mean edge roughness at each vertex
+  double* r_vV;           // [nv_cap] its variance
+  double* r_rt;           // [nt_cap] triangle roughness statistic
+  int32_t* r_vflag;       // [nv_cap] rough vertices
+  int32_t* r_estate;      // [3 * nt_cap] state of each edge (by its owning half-edge)
+  int32_t* r_elist;       // [3 * nt_cap] edges listed for smoothing
   double* best_d2;        // [cell_cap] smallest squared distance of a vertex in the 27 cells around
   int32_t* best_v;        // [cell_cap] lowest vertex attaining it
 
@@ -160,6 +170,11 @@ hipError_t launch_mlp_adam(float* theta, float* m, float* v, const float* grad, 
 hipError_t launch_surrogate(const ftc_cells* ws, const Mesh& m, const double* alpha, const float* theta, float bound,
                             const PPICParams& p, double* kappa, double* nx, double* ny, double* nz, float* spread,
                             int32_t* status, int32_t* n_fallback, hipStream_t s);
+// Roughness (roughness.hip).
+hipError_t launch_roughness(const ftc_cells* ws, const Mesh& m, double* gl_mag, double* rough, hipStream_t s);
+hipError_t launch_smooth(const ftc_cells* ws, const Mesh& m, const double* gl_mag, const double* rough, double gl_thr,
+                         double rough_thr, int32_t max_rounds, double* xo, double* yo, double* zo, int32_t* d_counts,
+                         hipStream_t s);
 hipError_t launch_csf(const ftc_cells* ws, const double* alpha, const double* kappa, double sigma, double* fx,
                       double* fy, double* fz, hipStream_t s);
 hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const double* kappa, const double* nx,

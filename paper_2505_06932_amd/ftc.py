@@ -35,7 +35,8 @@ EXPORTED = ["ftc_cells_create", "ftc_cells_destroy", "ftc_build_cell_lists", "ft
             "ftc_cells_view", "ftc_volume_fraction", "ftc_ppic_curvature", "ftc_csf_force",
             "ftc_interp_vertex_velocity", "ftc_last_device_error", "ftc_set_timing", "ftc_kernel_time",
             "ftc_csf_force_band", "ftc_advect_vertices_rk4", "ftc_curvature_features", "ftc_mlp_forward",
-            "ftc_mlp_loss_grad", "ftc_mlp_adam", "ftc_learned_curvature",
+            "ftc_mlp_loss_grad", "ftc_mlp_adam", "ftc_learned_curvature", "ftc_front_roughness",
+            "ftc_smooth_rough_edges",
             "ftc_status_str"]
 
 # ftc_kernel values (timing)
@@ -125,6 +126,11 @@ def lib() -> C.CDLL:
     L.ftc_learned_curvature.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, C.c_double, P(_CParams), vp, vp, vp, vp,
                                         vp, vp, vp, vp]
     L.ftc_learned_curvature.restype = C.c_int32
+    L.ftc_front_roughness.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, vp]
+    L.ftc_front_roughness.restype = C.c_int32
+    L.ftc_smooth_rough_edges.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, C.c_double, C.c_double, C.c_int32, vp, vp,
+                                         vp, vp, vp]
+    L.ftc_smooth_rough_edges.restype = C.c_int32
     L.ftc_last_device_error.argtypes = [vp, P(C.c_int32), vp]
     L.ftc_last_device_error.restype = C.c_int32
     L.ftc_set_timing.argtypes = [vp, C.c_int32]
@@ -440,3 +446,23 @@ def learned_curvature(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, alpha_
                                        _ptr(cell_status, torch.int32, cap, "cell_status"),
                                        _ptr(n_fallback, torch.int32, 1, "n_fallback"), _stream(stream)),
            "ftc_learned_curvature")
+
+
+# ------------------------------------------------------------------ roughness
+def front_roughness(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, gl_mag, rough, stream=None) -> None:
+    nv = mesh.c.nv
+    _check(lib().ftc_front_roughness(cells.handle, C.byref(c_grid(grid)), C.byref(mesh.c),
+                                     _ptr(gl_mag, torch.float64, nv, "gl_mag"), _ptr(rough, torch.float64, nv, "rough"),
+                                     _stream(stream)), "ftc_front_roughness")
+
+
+def smooth_rough_edges(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, gl_mag, rough, gl_threshold: float,
+                       rough_threshold: float, x_out, y_out, z_out, counts, max_rounds: int = 64, stream=None) -> None:
+    nv = mesh.c.nv
+    _check(lib().ftc_smooth_rough_edges(cells.handle, C.byref(c_grid(grid)), C.byref(mesh.c),
+                                        _ptr(gl_mag, torch.float64, nv, "gl_mag"),
+                                        _ptr(rough, torch.float64, nv, "rough"), float(gl_threshold),
+                                        float(rough_threshold), int(max_rounds),
+                                        _ptr(x_out, torch.float64, nv, "x_out"), _ptr(y_out, torch.float64, nv, "y_out"),
+                                        _ptr(z_out, torch.float64, nv, "z_out"), _ptr(counts, torch.int32, 3, "counts"),
+                                        _stream(stream)), "ftc_smooth_rough_edges")

@@ -156,6 +156,14 @@ def test_smoothing_leaves_a_regular_plane_alone():
             assert np.allclose(r[0], X[a], rtol=0, atol=1e-15) and np.allclose(r[1], X[b], rtol=0, atol=1e-15)
 
 
+def test_fmix32_reference_values():
+    """MurmurHash3's finalizer: 0 maps to 0, and it is a bijection on a sample."""
+    assert RG.fmix32(0) == 0
+    vals = {RG.fmix32(i) for i in range(1, 20000)}
+    assert len(vals) == 19999 and 0 not in vals
+    assert RG.fmix32(1) == 0x514E28B7
+
+
 def test_schedule_rounds_are_independent_and_complete():
     rng = np.random.default_rng(5)
     unit, T = I.icosphere(2)
@@ -165,7 +173,17 @@ def test_schedule_rounds_are_independent_and_complete():
     rounds = RG.schedule(topo, edges)
     seen = [e[0] for rnd in rounds for e in rnd]
     assert sorted(seen) == sorted(e[0] for e in edges)
-    assert rounds[0][0][0] == min(e[0] for e in edges)
+    first = min(edges, key=lambda e: RG.priority(e[0]))
+    assert first in rounds[0]
+    # an edge is taken exactly when no pending edge within one ring comes before it
+    pending = list(edges)
+    for rnd in rounds:
+        taken = {e[0] for e in rnd}
+        for e in pending:
+            near = {e[1], e[2], *topo.ring[e[1]], *topo.ring[e[2]]}
+            blocked = any(RG.priority(f[0]) < RG.priority(e[0]) and (f[1] in near or f[2] in near) for f in pending)
+            assert (e[0] in taken) == (not blocked), e
+        pending = [e for e in pending if e[0] not in taken]
     for rnd in rounds:
         for e in rnd:
             near = {e[1], e[2], *topo.ring[e[1]], *topo.ring[e[2]]}
