@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--learned", action="store_true",
                     help="curvature by the trained surrogate with its PPIC fallback (the learned form)")
     ap.add_argument("--bound", type=float, default=None, help="spread bound of the learned form (kappa h units)")
+    ap.add_argument("--tune", action="store_true",
+                    help="choose the launch shapes with the autotuner (whole-step graph timings) before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel for the "
@@ -113,6 +115,12 @@ def main():
     if err != ftc.FTC_OK:
         raise ftc.FTCError(err, "first step")
     log(f"[bench] interfacial cells={n_if} pieces={n_pairs}")
+    tune_table = None
+    if args.tune:
+        from paper_2505_06932_amd import tune
+        chosen, table = tune.autotune(step, log=log)
+        tune_table = [{**t.__dict__, "us_per_step": round(ms * 1e3, 1)} for t, ms in table]
+        log(f"[bench] tuned shapes: {chosen}")
 
     # ---------------------------------------------------------------- timed
     launch = "eager" if args.eager else "hip_graph"
@@ -176,7 +184,9 @@ def main():
                    "launch": launch,
                    "step": "cell_lists+volume_fraction+" + ("learned_curvature" if args.learned else "ppic_curvature")
                            + "+csf_force+interp_vertex_velocity",
-                   **({"spread_bound": step.bound, "ppic_fallback_cells": res["n_fallback"]} if args.learned else {})},
+                   **({"spread_bound": step.bound, "ppic_fallback_cells": res["n_fallback"]} if args.learned else {}),
+                   "shapes": ftc.get_tuning(step.cells).__dict__,
+                   **({"autotune": tune_table} if tune_table else {})},
         "gpu_ms_per_step_events": gpu_ms / K,
         "kernel_ms": kern_ms,
         "roofline": roofline,

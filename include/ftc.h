@@ -390,6 +390,32 @@ ftc_status ftc_smooth_rough_edges(ftc_cells* cells, const ftc_grid* grid, const 
                                   const double* rough, double gl_threshold, double rough_threshold, int32_t max_rounds,
                                   double* x_out, double* y_out, double* z_out, int32_t* d_counts, void* stream);
 
+/* ------------------------------------------------------------------------
+   Launch shapes of a workspace, for fronts of different sizes and
+   triangle-per-cell counts (an autotuner on top chooses them by timing the
+   whole step: paper_2505_06932_amd/tune.py).  Every choice gives the same
+   cell lists, decisions and PPIC results; the column chunking changes the
+   order in which fluxes are summed, so volume fractions may differ in the
+   last bits.
+     ring_lanes    : lanes per interfacial cell in the PPIC ring pass, 8 or 16;
+     column_chunks : z-chunks (wavefronts) per 64-column block of the
+                     volume-fraction column pass, 4, 8 or 16;
+     ring_blocks   : workgroups of the ring pass, 0 for one per group of
+                     cells, else a persistent grid of that many (<= 65536).
+   Defaults: 8 lanes, 16 chunks for nz <= 256 and 4 above, one workgroup
+   per group (the fastest shapes measured on fronts of 28k to 223k
+   interfacial cells on 128^3 to 512^3).
+   ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t ring_lanes;
+  int32_t column_chunks;
+  int32_t ring_blocks;
+} ftc_tuning;
+
+ftc_status ftc_get_tuning(const ftc_cells* cells, ftc_tuning* out /*[host]*/);
+/* FTC_EINVAL (nothing changed) for a value outside the lists above. */
+ftc_status ftc_set_tuning(ftc_cells* cells, const ftc_tuning* in /*[host]*/);
+
 #ifdef __cplusplus
 }
 #endif

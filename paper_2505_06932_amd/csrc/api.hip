@@ -97,6 +97,8 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
     return FTC_EHIP;
   }
   w.grid = to_grid(grid);
+  // measured best column chunking: 16 chunks up to 256 cells per column, 4 above
+  w.tune.column_chunks = grid->nz > 256 ? 4 : 16;
   w.ncell = ncell;
   w.nwords = nwords;
   w.ncol = ncol;
@@ -377,6 +379,26 @@ ftc_status ftc_smooth_rough_edges(ftc_cells* cells, const ftc_grid* grid, const 
   if (mesh->nv != cells->built_nv || mesh->nt != cells->built_nt || !on_device(cells)) return FTC_EINVAL;
   return hip_status(ftc::launch_smooth(cells, to_mesh(mesh), gl_mag, rough, gl_threshold, rough_threshold, max_rounds,
                                        x_out, y_out, z_out, d_counts, (hipStream_t)stream));
+}
+
+ftc_status ftc_get_tuning(const ftc_cells* cells, ftc_tuning* out) {
+  if (!cells || !out) return FTC_EINVAL;
+  out->ring_lanes = cells->tune.ring_lanes;
+  out->column_chunks = cells->tune.column_chunks;
+  out->ring_blocks = cells->tune.ring_blocks;
+  return FTC_OK;
+}
+
+ftc_status ftc_set_tuning(ftc_cells* cells, const ftc_tuning* in) {
+  if (!cells || !in) return FTC_EINVAL;
+  if ((in->ring_lanes != 8 && in->ring_lanes != 16) ||
+      (in->column_chunks != 4 && in->column_chunks != 8 && in->column_chunks != 16) || in->ring_blocks < 0 ||
+      in->ring_blocks > 65536)
+    return FTC_EINVAL;
+  cells->tune.ring_lanes = in->ring_lanes;
+  cells->tune.column_chunks = in->column_chunks;
+  cells->tune.ring_blocks = in->ring_blocks;
+  return FTC_OK;
 }
 
 ftc_status ftc_last_device_error(ftc_cells* cells, int32_t* code, void* stream) {

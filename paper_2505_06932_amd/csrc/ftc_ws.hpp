@@ -28,8 +28,18 @@ enum : int {
 };
 }  // namespace ftc
 
+namespace ftc {
+// Launch shapes chosen per workspace (ftc_set_tuning; defaults below).
+struct Tuning {
+  int32_t ring_lanes = 8;     // lanes per cell in the PPIC ring pass: 8 or 16
+  int32_t column_chunks = 16;  // z-chunks (wavefronts) per column block: 4, 8 or 16 (set from nz at creation)
+  int32_t ring_blocks = 0;    // workgroups of the ring pass: 0 = one per cell group, else a persistent grid
+};
+}  // namespace ftc
+
 struct ftc_cells {
   int device;
+  ftc::Tuning tune;
   ftc::Grid grid;
   int64_t ncell, nwords, ncol;
   int32_t nv_cap, nt_cap, cell_cap;

@@ -77,6 +77,9 @@ struct Cfg {
   static_assert(VC_ <= 256, "owner table holds bytes");
 };
 using Fast = Cfg<8, 64, 32, 64, 6>;
+// the same capacities with 16 lanes per cell (4 cells per wavefront): the
+// queue to the wide shape, and so every result, is the same as Fast's
+using Fast16 = Cfg<16, 64, 32, 64, 3>;
 using Wide = Cfg<64, 512, 256, 512, 4>;
 
 // ----------------------------------------------------------------- main kernel
@@ -790,6 +793,9 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
 }
 
 __global__ __launch_bounds__(64) void k_ppic_rings(PPICArgs A) { ppic_cells<Fast, false>(A, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(64) void k_ppic_rings16(PPICArgs A) {
+  ppic_cells<Fast16, false>(A, blockIdx.x, gridDim.x);
+}
 // The cells the learned curvature hands over, sel[0, counters[C_NSEL]), with
 // the wide shape (rings, fit and solve in the workgroup, one cell at a
 // time): a selection is a small part of the cells, and the wide shape's
@@ -1121,14 +1127,19 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
   A.diag = diag;
   A.sel = sel;
   A.n_sel_out = n_sel_out;
-  const int64_t groups = ((int64_t)ws->cell_cap + Fast::NG - 1) / Fast::NG;
-  const int32_t blocks = round_up(std::min<int64_t>(std::max<int64_t>(groups, 1), 65536), kXCD);
+  const bool lanes16 = ws->tune.ring_lanes == 16;
+  const int64_t groups = ((int64_t)ws->cell_cap + (lanes16 ? Fast16::NG : Fast::NG) - 1) / (lanes16 ? Fast16::NG : Fast::NG);
+  const int64_t grid_cap = ws->tune.ring_blocks > 0 ? ws->tune.ring_blocks : 65536;
+  const int32_t blocks = round_up(std::min<int64_t>(std::max<int64_t>(groups, 1), grid_cap), kXCD);
   time_start(ws, FTC_KERNEL_PPIC, s);
   if (sel) {
     hipLaunchKernelGGL(k_ppic_wide_sel, dim3(round_up(std::min<int64_t>(std::max<int64_t>(ws->cell_cap, 1), 2048), kXCD)),
                        dim3(64), 0, s, A);
   } else {
-    hipLaunchKernelGGL(k_ppic_rings, dim3(blocks), dim3(64), 0, s, A);
+    if (lanes16)
+      hipLaunchKernelGGL(k_ppic_rings16, dim3(blocks), dim3(64), 0, s, A);
+    else
+      hipLaunchKernelGGL(k_ppic_rings, dim3(blocks), dim3(64), 0, s, A);
     const dim3 fit_grid(round_up(std::min<int64_t>(std::max<int64_t>(((int64_t)ws->cell_cap + 7) / 8, 1), 65536), kXCD));
     if (p.mixed)
       hipLaunchKernelGGL(k_ppic_fit_mixed, fit_grid, dim3(64), 0, s, A);

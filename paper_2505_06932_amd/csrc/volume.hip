@@ -42,7 +42,7 @@ __global__ void k_cell_sums(const int32_t* offsets, const double* piece_flux, co
 }
 
 // Column pass.  A workgroup takes 64 consecutive columns (x) of one y row
-// and splits the z range into 8 chunks, one wavefront each; lanes are
+// and splits the z range into kChunks chunks (4, 8 or 16), one wavefront each; lanes are
 // columns, so bitmap reads and dense stores are coalesced along x.
 //   1. each wavefront sums the fluxes of the interfacial cells in its chunk,
 //      top down;
@@ -52,8 +52,10 @@ __global__ void k_cell_sums(const int32_t* offsets, const double* piece_flux, co
 //      round(W / h^2), which must be 0 or 1 within 1e-9 (else the front is
 //      open: ERR_MESH), as must W below the lowest chunk.
 constexpr int kColLanes = 64;
-constexpr int kChunks = 8;
-constexpr int kSub = 16;  // cells of a chunk read at once
+// cells of a chunk read at once: 16, or 8 with 16 chunks (whose 1024-thread
+// workgroups leave 128 registers per lane)
+template <int kChunks>
+constexpr int sub_of() { return kChunks == 16 ? 8 : 16; }
 
 struct ColArgs {
   Grid g;
@@ -71,7 +73,7 @@ struct ColArgs {
 // interfacial, their compact ids (-1: not interfacial; -2: interfacial but
 // beyond the cell capacity, a latched capacity error, taken with no
 // pieces), fluxes and (if `vol`) volume integrals.
-template <bool kVol>
+template <bool kVol, int kSub>
 __device__ inline void read_sub(const ColArgs& A, bool col_ok, int32_t i, int32_t j, int32_t k1, int32_t klo,
                                 int32_t ci[kSub], double fl[kSub], double vo[kSub]) {
   const Grid& g = A.g;
@@ -98,7 +100,9 @@ __device__ inline void read_sub(const ColArgs& A, bool col_ok, int32_t i, int32_
   }
 }
 
+template <int kChunks>
 __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
+  constexpr int kSub = sub_of<kChunks>();
   __shared__ double tot_s[kChunks][kColLanes];
   const Grid& g = A.g;
   const int lane = threadIdx.x % kColLanes, w = threadIdx.x / kColLanes;
@@ -115,9 +119,9 @@ __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
   double tot = 0.0;
   for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSub) {
     if (once)
-      read_sub<true>(A, col_ok, i, j, k1, klo, ci, fl, vo);
+      read_sub<true, kSub>(A, col_ok, i, j, k1, klo, ci, fl, vo);
     else
-      read_sub<false>(A, col_ok, i, j, k1, klo, ci, fl, vo);
+      read_sub<false, kSub>(A, col_ok, i, j, k1, klo, ci, fl, vo);
 #pragma unroll
     for (int q = 0; q < kSub; ++q)
       if (ci[q] >= 0) tot += fl[q];
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
 
   bool bad = false;
   for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSub) {
-    if (!once) read_sub<true>(A, col_ok, i, j, k1, klo, ci, fl, vo);
+    if (!once) read_sub<true, kSub>(A, col_ok, i, j, k1, klo, ci, fl, vo);
 #pragma unroll
     for (int q = 0; q < kSub; ++q) {
       const int32_t k = k1 - q;
@@ -163,7 +167,13 @@ hipError_t launch_volume_fraction(const ftc_cells* ws, const Mesh& m, double* al
   ColArgs A{g, ws->bitmap, ws->word_off, ws->cell_flux, ws->cell_vol, alpha_if, alpha_dense, ws->cell_cap,
             ws->counters};
   time_start(ws, FTC_KERNEL_COLUMNS, s);
-  hipLaunchKernelGGL(k_columns, dim3((g.nx + kColLanes - 1) / kColLanes, g.ny), dim3(kColLanes * kChunks), 0, s, A);
+  const dim3 cg((g.nx + kColLanes - 1) / kColLanes, g.ny);
+  if (ws->tune.column_chunks == 4)
+    hipLaunchKernelGGL(k_columns<4>, cg, dim3(kColLanes * 4), 0, s, A);
+  else if (ws->tune.column_chunks == 16)
+    hipLaunchKernelGGL(k_columns<16>, cg, dim3(kColLanes * 16), 0, s, A);
+  else
+    hipLaunchKernelGGL(k_columns<8>, cg, dim3(kColLanes * 8), 0, s, A);
   time_stop(ws, FTC_KERNEL_COLUMNS, s);
   return hipGetLastError();
 }

@@ -36,7 +36,7 @@ EXPORTED = ["ftc_cells_create", "ftc_cells_destroy", "ftc_build_cell_lists", "ft
             "ftc_interp_vertex_velocity", "ftc_last_device_error", "ftc_set_timing", "ftc_kernel_time",
             "ftc_csf_force_band", "ftc_advect_vertices_rk4", "ftc_curvature_features", "ftc_mlp_forward",
             "ftc_mlp_loss_grad", "ftc_mlp_adam", "ftc_learned_curvature", "ftc_front_roughness",
-            "ftc_smooth_rough_edges",
+            "ftc_smooth_rough_edges", "ftc_get_tuning", "ftc_set_tuning",
             "ftc_status_str"]
 
 # ftc_kernel values (timing)
@@ -70,6 +70,18 @@ class PPICParams:
     grow: float = 1.1
     max_iter: int = 16
     precision: int = 0
+
+
+class _CTuning(C.Structure):
+    _fields_ = [("ring_lanes", C.c_int32), ("column_chunks", C.c_int32), ("ring_blocks", C.c_int32)]
+
+
+@dataclass(frozen=True)
+class Tuning:
+    """Launch shapes of a workspace (see ftc_tuning in include/ftc.h)."""
+    ring_lanes: int = 8
+    column_chunks: int = 16
+    ring_blocks: int = 0
 
 
 class FTCError(RuntimeError):
@@ -131,6 +143,10 @@ def lib() -> C.CDLL:
     L.ftc_smooth_rough_edges.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, C.c_double, C.c_double, C.c_int32, vp, vp,
                                          vp, vp, vp]
     L.ftc_smooth_rough_edges.restype = C.c_int32
+    L.ftc_get_tuning.argtypes = [vp, P(_CTuning)]
+    L.ftc_get_tuning.restype = C.c_int32
+    L.ftc_set_tuning.argtypes = [vp, P(_CTuning)]
+    L.ftc_set_tuning.restype = C.c_int32
     L.ftc_last_device_error.argtypes = [vp, P(C.c_int32), vp]
     L.ftc_last_device_error.restype = C.c_int32
     L.ftc_set_timing.argtypes = [vp, C.c_int32]
@@ -466,3 +482,15 @@ def smooth_rough_edges(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, gl_ma
                                         _ptr(x_out, torch.float64, nv, "x_out"), _ptr(y_out, torch.float64, nv, "y_out"),
                                         _ptr(z_out, torch.float64, nv, "z_out"), _ptr(counts, torch.int32, 3, "counts"),
                                         _stream(stream)), "ftc_smooth_rough_edges")
+
+
+# -------------------------------------------------------------------- tuning
+def get_tuning(cells: Cells) -> Tuning:
+    t = _CTuning()
+    _check(lib().ftc_get_tuning(cells.handle, C.byref(t)), "ftc_get_tuning")
+    return Tuning(t.ring_lanes, t.column_chunks, t.ring_blocks)
+
+
+def set_tuning(cells: Cells, tuning: Tuning) -> None:
+    _check(lib().ftc_set_tuning(cells.handle, C.byref(_CTuning(tuning.ring_lanes, tuning.column_chunks,
+                                                               tuning.ring_blocks))), "ftc_set_tuning")

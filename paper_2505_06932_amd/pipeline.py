@@ -15,7 +15,7 @@ class CouplingStep:
     def __init__(self, grid: I.Grid, mesh: I.Mesh, U=None, V=None, W=None, sigma: float = 1.0,
                  params: ftc.PPICParams | None = None, margin: float = 1.25,
                  pair_capacity: int | None = None, cell_capacity: int | None = None, band: bool = False,
-                 learned=None, bound: float | None = None):
+                 learned=None, bound: float | None = None, tuning: ftc.Tuning | None = None):
         """learned: surrogate parameters (device float32 tensor of
         ftc.MLP_PARAMS values); the curvature is then the learned surrogate
         with its PPIC fallback above the spread `bound`."""
@@ -47,6 +47,8 @@ class CouplingStep:
             pair_capacity = pair_capacity or int(n_p * margin) + 256
             cell_capacity = cell_capacity or int(min(grid.ncell, n_if * margin + 256))
         self.cells = ftc.Cells(grid, nv, nt, pair_capacity, cell_capacity)
+        if tuning is not None:
+            ftc.set_tuning(self.cells, tuning)
         cap = self.cells.cell_capacity
         z = lambda n, dt=torch.float64: torch.zeros(n, dtype=dt, device=dev)
         self.alpha_if = z(cap)

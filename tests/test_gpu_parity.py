@@ -482,3 +482,35 @@ def test_graph_replay_matches_eager():
         for k in ("alpha", "alpha_if", "kappa", "normal", "coeff", "diag", "force", "u", "tri_ids"):
             assert np.array_equal(got[k], ref[k], equal_nan=True), (rep, k)
         assert got["error"] == 0
+
+
+@pytest.mark.parametrize("shape", [(16, 4, 0), (8, 16, 2048), (16, 8, 8192)])
+@pytest.mark.parametrize("name", ["sphere_32", "sphere_128"])
+def test_launch_shapes_full_parity(oracle, name, shape):
+    """Every launch shape gives the oracle's lists, decisions and curvatures."""
+    from paper_2505_06932_amd import ftc
+    grid, mesh, _ = I.make_workload(name, 0)
+    U, V, W = I.psi_face_velocity(grid)
+    t = ftc.Tuning(*shape)
+    step, g, o = run_pair(oracle, f"{name} shape={shape}", grid, mesh, U, V, W, tuning=t)
+    assert ftc.get_tuning(step.cells) == t
+    check_lists(g, o)
+    check_alpha(g, o)
+    check_ppic(g, o, grid.h)
+    check_force(g, o)
+
+
+def test_autotuner_chooses_a_timed_shape():
+    from paper_2505_06932_amd import ftc, pipeline, tune
+    _gpu()
+    grid, mesh, _ = I.make_workload("sphere_32", 0)
+    step = pipeline.CouplingStep(grid, mesh)
+    best, table = tune.autotune(step, reps=5, warmup=2, log=_say)
+    tried = {t for t, _ in table}
+    assert ftc.Tuning(8, 16, 0) in tried  # the workspace's default shape on 32^3
+    assert len(tried) == 1 + 1 + 2 + 2  # the default, then the other values of each knob
+    assert best in tried and ftc.get_tuning(step.cells) == best
+    assert dict(table)[best] == min(ms for _, ms in table)
+    with pytest.raises(ftc.FTCError):
+        ftc.set_tuning(step.cells, ftc.Tuning(12, 8, 0))
+    assert ftc.get_tuning(step.cells) == best
