@@ -335,7 +335,7 @@ def real_sph_harm(l: int, m: int, unit: np.ndarray) -> np.ndarray:
 
 def sh_spheres_workload(n: int, count: int, seed: int, r_lo: float = 4.0, r_hi: float = 20.0,
                         degree: int = 8, amp_max: float = 0.1, edge_over_h: float = 0.5,
-                        gap_over_h: float = 4.0, domain: float = 1.0):
+                        gap_over_h: float = 4.0, domain: float = 1.0, return_surfaces: bool = False):
     """``count`` disjoint spheres with spherical-harmonic perturbations in one
     mesh on an n^3 grid.
 
@@ -349,11 +349,13 @@ def sh_spheres_workload(n: int, count: int, seed: int, r_lo: float = 4.0, r_hi: 
     r(u) = R (1 + A f(u) / max |f|), f = sum c_lm Y_lm(u) (real harmonics,
     :func:`real_sph_harm`; the maximum over the mesh vertices), so every
     radius lies in [(1 - A) R, (1 + A) R].  Returns the grid, the mesh and a
-    (count, 6) array of centre, R, A and frequency per droplet."""
+    (count, 6) array of centre, R, A and frequency per droplet; with
+    return_surfaces also a list of the droplets' exact surfaces, dicts with
+    centre, R, A, coef [(l, m, c_lm)] and fmax."""
     h = domain / n
     rng = np.random.default_rng(seed)
     cache: dict[int, tuple[np.ndarray, np.ndarray]] = {}
-    verts, tris, info = [], [], []
+    verts, tris, info, surfaces = [], [], [], []
     placed: list[tuple[np.ndarray, float]] = []
     nv = 0
     for _ in range(count):
@@ -382,8 +384,12 @@ def sh_spheres_workload(n: int, count: int, seed: int, r_lo: float = 4.0, r_hi: 
         tris.append(t + nv)
         nv += len(unit)
         info.append([*c, R, A, freq])
+        surfaces.append(dict(centre=c.copy(), R=R, A=A, coef=coef, fmax=fmax))
     grid = Grid(n, n, n, 0.0, 0.0, 0.0, h)
-    return grid, Mesh.from_arrays(np.concatenate(verts), np.concatenate(tris)), np.array(info)
+    mesh = Mesh.from_arrays(np.concatenate(verts), np.concatenate(tris))
+    if return_surfaces:
+        return grid, mesh, np.array(info), surfaces
+    return grid, mesh, np.array(info)
 
 
 #: Named workloads: (builder, kwargs).  "sphere_32" is the small plain-FP64

@@ -357,7 +357,8 @@ def test_trained_surrogate_gain(oracle, workload, faster):
     torch = _torch()
     from paper_2505_06932_amd import ftc, pipeline, surrogate
     theta = surrogate.load_theta()
-    grid, mesh, _ = I.make_workload(workload, 1000)
+    fn, kw = I.WORKLOADS[workload]
+    grid, mesh, _, surfs = fn(seed=1000, return_surfaces=True, **kw)
     _say(f"[surrogate] gain case={workload} seed=1000 nt={mesh.nt}")
     plain = pipeline.CouplingStep(grid, mesh)
     learned = pipeline.CouplingStep(grid, mesh, learned=theta)
@@ -400,6 +401,24 @@ def test_trained_surrogate_gain(oracle, workload, faster):
     _say(f"[surrogate] gain: cells={n} curvature call {t_plain * 1e3:.1f} us (PPIC) -> {t_learned * 1e3:.1f} us "
          f"(surrogate, {fb.mean() * 100:.1f}% to PPIC); surrogate vs PPIC oracle: relative error median {q50:.4f}, "
          f"90% {q90:.4f}")
+    # both against the exact mean curvature of the perturbed spheres, at the
+    # radial projection of the cell centre (a sample of the trusted cells)
+    from oracle import surfaces as SF
+    idx = np.nonzero(tr)[0]
+    idx = idx[np.random.default_rng(0).permutation(len(idx))[:3000]]
+    ijk = np.stack([cells[idx] % grid.nx, (cells[idx] // grid.nx) % grid.ny, cells[idx] // (grid.nx * grid.ny)], 1)
+    xc = (ijk + 0.5) * grid.h + np.array([grid.x0, grid.y0, grid.z0])
+    near = SF.nearest_surface(surfs, xc)
+    kex = np.empty(len(idx))
+    for i, sf in enumerate(surfs):
+        m = near == i
+        if m.any():
+            kex[m] = SF.mean_curvature(sf, SF.project(sf, xc[m]))
+    e_ppic = np.abs(ref["kappa"][idx] / kex - 1)
+    e_sur = np.abs(g["kappa"][idx] / kex - 1)
+    _say(f"[surrogate] against the exact curvature ({len(idx)} trusted cells): PPIC median {np.median(e_ppic):.4f} "
+         f"90% {np.quantile(e_ppic, 0.9):.4f}; surrogate median {np.median(e_sur):.4f} 90% {np.quantile(e_sur, 0.9):.4f}")
+    assert np.median(e_sur) < 0.06
     assert g["n_fallback"] == fb.sum()
     # the fallback cells carry the PPIC curvature
     assert np.all(rel[fb & ok] <= KAPPA_TOL)
