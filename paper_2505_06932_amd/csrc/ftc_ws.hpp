@@ -20,8 +20,8 @@ enum : int {
   C_NSTRAY = 5,   // vertices in cells without pieces
   C_NOVF = 6,     // interfacial cells whose ring exceeds the fast PPIC kernel's capacities
   C_NQUEUED = 7,  // C_NOVF as the wide PPIC shape reads it (moved there by the fit pass)
-  C_NSEL = 8,      // cells the learned curvature hands to PPIC (cleared by the last workgroup that reads it)
-  C_NSELDONE = 9,  // workgroups of that PPIC kernel that have finished
+  C_NSEL = 8,      // cells the learned curvature hands to PPIC (cleared after the PPIC kernel)
+  C_SPARE = 9,     // unused
   C_RFLAG = 10,    // edges listed for roughness smoothing
   C_RMOVED = 11,   // edges moved by it
   C_COUNT = 12

@@ -799,19 +799,15 @@ __global__ __launch_bounds__(64) void k_ppic_rings16(PPICArgs A) {
 // The cells the learned curvature hands over, sel[0, counters[C_NSEL]), with
 // the wide shape (rings, fit and solve in the workgroup, one cell at a
 // time): a selection is a small part of the cells, and the wide shape's
-// per-cell latency is the lower.  The last workgroup to finish reports the
-// count and clears it for the next call (every workgroup has read it by then).
-__global__ __launch_bounds__(64) void k_ppic_wide_sel(PPICArgs A) {
-  ppic_cells<Wide, true, true>(A, blockIdx.x, gridDim.x);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(&A.counters[C_NSELDONE], 1) == (int32_t)gridDim.x - 1) {
-      if (A.n_sel_out) *A.n_sel_out = A.counters[C_NSEL];
-      A.counters[C_NSEL] = 0;
-      A.counters[C_NSELDONE] = 0;
-    }
-  }
+// per-cell latency is the lower.
+__global__ __launch_bounds__(64) void k_ppic_wide_sel(PPICArgs A) { ppic_cells<Wide, true, true>(A, blockIdx.x, gridDim.x); }
+
+// After it: report the selection's count and clear it for the next call (a
+// kernel of its own: a completion count over the selection kernel's
+// workgroups, one same-address atomic each, cost about 40 us).
+__global__ void k_sel_done(int32_t* counters, int32_t* n_sel_out) {
+  if (n_sel_out) *n_sel_out = counters[C_NSEL];
+  counters[C_NSEL] = 0;
 }
 
 // Weighted moments and normal equations of the cells whose ring fitted the
@@ -1135,6 +1131,7 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
   if (sel) {
     hipLaunchKernelGGL(k_ppic_wide_sel, dim3(round_up(std::min<int64_t>(std::max<int64_t>(ws->cell_cap, 1), 2048), kXCD)),
                        dim3(64), 0, s, A);
+    hipLaunchKernelGGL(k_sel_done, dim3(1), dim3(1), 0, s, ws->counters, n_sel_out);
   } else {
     if (lanes16)
       hipLaunchKernelGGL(k_ppic_rings16, dim3(blocks), dim3(64), 0, s, A);
