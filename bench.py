@@ -223,7 +223,7 @@ def main():
             "kind": "oracle",
             "sample": f"{reps} full steps of {args.workload} (cell lists, volume fraction, PPIC, CSF, "
                       f"interpolation), {cpu_s:.1f} s; OpenMP over cells/columns/vertices, "
-                      f"cell lists and piece integrals serial; host nproc={os.cpu_count()}"}
+                      f"cell lists and piece integrals serial; host nproc={os.cpu_count()}, cpu={_cpu_model()}"}
         ok = r["status"] == 0
         same_lists = bool(np.array_equal(res["cell_ids"], cells) and np.array_equal(res["tri_ids"], tris))
         out["err_vs_oracle"] = {
@@ -308,6 +308,17 @@ def copy_calibration(torch):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 5}), flush=True)
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _vpoly(mesh, centre):
