@@ -428,3 +428,21 @@ def test_trained_surrogate_gain(oracle, workload, faster):
     # the call is faster than PPIC on every cell
     if faster:
         assert t_learned < 0.6 * t_plain
+
+
+def test_training_is_deterministic():
+    """Two short trainings from the same seed and data give identical
+    parameters: fixed-order reductions and no atomics in the training kernels."""
+    torch = _torch()
+    from paper_2505_06932_amd import surrogate
+    rng = np.random.default_rng(60)
+    rows = 5000
+    X = np.zeros((rows, 32), np.float32)
+    X[:, :27] = rng.uniform(0, 1, size=(rows, 27))
+    X[:, 27:30] = rng.normal(size=(rows, 3))
+    X[:, 27:30] /= np.linalg.norm(X[:, 27:30], axis=1)[:, None]
+    t = (0.3 * (X[:, 14] - X[:, 12]) + 0.2 * X[:, 29]).astype(np.float32)
+    Xg, tg = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
+    th1, h1 = surrogate.train(Xg, tg, epochs=3, batch=1024, seed=4)
+    th2, h2 = surrogate.train(Xg, tg, epochs=3, batch=1024, seed=4)
+    assert torch.equal(th1, th2) and h1 == h2
