@@ -94,7 +94,7 @@ typedef struct ftc_cells ftc_cells;
    of up to nv_capacity vertices and nt_capacity triangles, holding up to
    pair_capacity (cell, triangle) pieces and cell_capacity interfacial
    cells (candidates that must be clipped, up to twice pair_capacity, are
-   queued internally).  Device memory is about 116 B x pairs + 1.85 kB x cells
+   queued internally).  Device memory is about 116 B x pairs + 1.1 kB x cells
    + 104 B x triangles + 84 B x vertices + 3 nx*ny*nz/8 B (about 110 MB for a
    128^3 grid with 82k triangles, 1.4 GB for 512^3 with 2M triangles).
    Returns FTC_EINVAL, FTC_ENOMEM or FTC_OK; *out is NULL on failure. */

@@ -150,7 +150,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(vb_ids, Vc);
   FTC_ALLOC(stray, Vc);
   FTC_ALLOC(fit, ftc::kFitSlots * Cc);
-  FTC_ALLOC(wl_tri, 4 * ftc::kFitList * Cc);
+  FTC_ALLOC(wl_tri, ftc::kFitList * Cc);
   FTC_ALLOC(wl_w, ftc::kFitList * Cc);
   FTC_ALLOC(best_d2, Cc);
   FTC_ALLOC(best_v, Cc);

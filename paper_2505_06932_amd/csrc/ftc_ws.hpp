@@ -88,7 +88,7 @@ struct ftc_cells {
   int32_t* vb_ids;        // [nv_cap] vertices grouped by interfacial cell
   int32_t* stray;         // [nv_cap] vertices in cells without pieces
   double* fit;            // [kFitSlots * cell_cap] per cell: normal equations (21 + 6), vertex normal (3), weighted count
-  int32_t* wl_tri;        // [4 * cell_cap * kFitList] packed corners of the triangles of each cell's fit
+  int32_t* wl_tri;        // [cell_cap * kFitList] the triangles of each cell's fit
   double* wl_w;           // [cell_cap * kFitList] their weights
   int32_t* sel_cells;     // [cell_cap] cells the learned curvature hands to PPIC
   // roughness detection and smoothing

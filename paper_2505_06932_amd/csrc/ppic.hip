@@ -32,11 +32,12 @@
 //   3. triangle-centre distances, the support radius grown by `grow` until
 //      `n_min` triangles fall inside (or the ring is exhausted, or
 //      `max_iter` adjustments), Wendland weights of the triangles inside.
-//      The fast shape writes the weighted triangles (packed corners and
-//      weight) to a per-cell list in HBM, with the frame normal and the
+//      The fast shape writes the weighted triangles (id and weight, 12
+//      bytes each) to a per-cell list in HBM, with the frame normal and the
 //      count; the wide shape goes on with steps 4 and 5 itself.
 // Fit pass (k_ppic_fit), the cells of the fast shape, 8 lanes per cell:
-//   4. per lane: each listed triangle's projection into the frame
+//   4. per lane: each listed triangle's corners (from the packed corner
+//      array, which stays in L2), its projection into the frame
 //      (coordinates divided by h for conditioning), its six moments by the
 //      edge-midpoint rule (exact for quadratics) and the integral of its
 //      plane, and the weighted normal equations M a = b accumulated in
@@ -97,7 +98,7 @@ struct PPICArgs {
   int32_t* counters;
   int32_t* ovf_cells;
   double* fit;
-  int4* wl_tri;
+  int32_t* wl_tri;  // per cell: the triangles of its fit (ids; the fit pass reads their corners)
   double* wl_w;
   int32_t cell_cap;
   double *kappa, *nx, *ny, *nz, *coeff;
@@ -671,8 +672,6 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
         const int i = k * G + gl;
         const double dd = i < nTc ? FM.W[i] : DBL_MAX;
         const int32_t ti = i < nTc ? CM.T[i] : 0;
-        int4 t4 = make_int4(0, 0, 0, 0);
-        if constexpr (!kQueue) t4 = A.tri4[ti];
         const bool keep = i < nTc && dd < lim;
         const uint64_t bal = gballot<G>(keep, grp);
         if (keep) {
@@ -685,7 +684,7 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
             FM.S[pos] = ti;
           } else {
             A.wl_w[(int64_t)c * kFitList + pos] = wt;
-            A.wl_tri[(int64_t)c * kFitList + pos] = t4;
+            A.wl_tri[(int64_t)c * kFitList + pos] = ti;
           }
         }
         nw += __popcll(bal);
@@ -852,13 +851,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 #pragma unroll
     for (int qa = 0; qa < 27; ++qa) acc[qa] = 0.0;
     const int wrounds = wave_max_i((cnt + G - 1) / G);
-    const int4* lt = A.wl_tri + (int64_t)(act ? c : 0) * kFitList;
+    const int32_t* lt = A.wl_tri + (int64_t)(act ? c : 0) * kFitList;
     const double* lw = A.wl_w + (int64_t)(act ? c : 0) * kFitList;
-    // entries of the next round are loaded while this round is computed; a
-    // lane past the list (or a cell with an empty list, whose entries were
-    // never written) takes vertex 0 with weight 0
+    // entries of the next round (triangle ids, then their corners) are loaded
+    // while this round is computed; a lane past the list (or a cell with an
+    // empty list, whose entries were never written) takes vertex 0 with weight 0
     const int4 kNone = make_int4(0, 0, 0, 0);
-    int4 tn = gl < cnt ? lt[gl] : kNone;
+    int4 tn = gl < cnt ? A.tri4[lt[gl]] : kNone;
     double wn = gl < cnt ? lw[gl] : 0.0;
     for (int k = 0; k < wrounds; ++k) {
       const int j = k * G + gl;
@@ -866,7 +865,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
       const double w = wn;
       if (k + 1 < wrounds) {
         const int jn = j + G;
-        tn = jn < cnt ? lt[jn] : kNone;
+        tn = jn < cnt ? A.tri4[lt[jn]] : kNone;
         wn = jn < cnt ? lw[jn] : 0.0;
       }
       const int32_t cr[3] = {t4.x, t4.y, t4.z};
@@ -976,7 +975,7 @@ __global__ __launch_bounds__(64) void k_ppic_fit_mixed(PPICArgs A) {
     const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
     const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
     const int wrounds = wave_max_i((cnt + G - 1) / G);
-    const int4* lt = A.wl_tri + (int64_t)(act ? c : 0) * kFitList;
+    const int32_t* lt = A.wl_tri + (int64_t)(act ? c : 0) * kFitList;
     const double* lw = A.wl_w + (int64_t)(act ? c : 0) * kFitList;
     const int4 kNone = make_int4(0, 0, 0, 0);
 
@@ -1017,7 +1016,7 @@ __global__ __launch_bounds__(64) void k_ppic_fit_mixed(PPICArgs A) {
     for (int qa = 0; qa < 27; ++qa) accf[qa] = 0.0f;
     for (int k = 0; k < wrounds; ++k) {
       const int j = k * G + gl;
-      const int4 t4 = j < cnt ? lt[j] : kNone;
+      const int4 t4 = j < cnt ? A.tri4[lt[j]] : kNone;
       const float w = j < cnt ? (float)lw[j] : 0.0f;
       float mom[6], vt;
       moments(t4, 0.0f, mom, vt);
@@ -1044,7 +1043,7 @@ __global__ __launch_bounds__(64) void k_ppic_fit_mixed(PPICArgs A) {
       double gr[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       for (int k = 0; k < wrounds; ++k) {
         const int j = k * G + gl;
-        const int4 t4 = j < cnt ? lt[j] : kNone;
+        const int4 t4 = j < cnt ? A.tri4[lt[j]] : kNone;
         const double w = j < cnt ? lw[j] : 0.0;
         double mom[6], vt;
         moments(t4, 0.0, mom, vt);
@@ -1111,7 +1110,7 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
   A.counters = ws->counters;
   A.ovf_cells = ws->ovf_cells;
   A.fit = ws->fit;
-  A.wl_tri = reinterpret_cast<int4*>(ws->wl_tri);
+  A.wl_tri = ws->wl_tri;
   A.wl_w = ws->wl_w;
   A.cell_cap = ws->cell_cap;
   A.kappa = kappa;
