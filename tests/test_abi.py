@@ -70,3 +70,39 @@ def test_null_workspace_rejected(lib):
     assert lib.ftc_build_cell_lists(None, C.byref(g), None, None) == ftc.FTC_EINVAL
     lib.ftc_last_device_error.restype = C.c_int32
     assert lib.ftc_last_device_error(None, None, None) == ftc.FTC_EINVAL
+
+
+@pytest.mark.parametrize("compiler,lang", [("gcc", "c"), ("g++", "c++")])
+def test_header_compiles_standalone(compiler, lang, tmp_path):
+    """include/ftc.h is a plain C header (also valid C++): no HIP or torch types."""
+    import subprocess
+    src = tmp_path / ("t.c" if lang == "c" else "t.cpp")
+    src.write_text('#include "ftc.h"\nint main(void) { ftc_tuning t; (void)t; return (int)FTC_MLP_PARAMS - 6209; }\n')
+    std = "-std=c99" if lang == "c" else "-std=c++14"
+    r = subprocess.run([compiler, std, "-Wall", "-Werror", "-pedantic", "-fsyntax-only", "-I",
+                        os.path.join(ROOT, "include"), str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_learned_and_tuning_entry_points_check_arguments_on_the_host(lib):
+    """Null or out-of-range arguments are refused before any device work."""
+    vp, i32, f32 = C.c_void_p, C.c_int32, C.c_float
+    lib.ftc_mlp_adam.argtypes = [vp, vp, vp, vp, i32, f32, f32, f32, f32, vp]
+    lib.ftc_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, vp, i32, vp, vp]
+    lib.ftc_mlp_loss_grad.argtypes = [vp, vp, C.c_int64, vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.ftc_set_tuning.argtypes = [vp, vp]
+    lib.ftc_get_tuning.argtypes = [vp, vp]
+    EINVAL = -1
+    assert lib.ftc_mlp_adam(None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == EINVAL
+    assert lib.ftc_mlp_forward(None, None, 10, None, None, 5, None, None) == EINVAL
+    assert lib.ftc_mlp_loss_grad(None, None, 10, None, None, None, 5, None, None, None, None) == EINVAL
+    assert lib.ftc_set_tuning(None, None) == EINVAL
+    assert lib.ftc_get_tuning(None, None) == EINVAL
+    # dummy non-null host pointers: the checks on step, rates and counts come first
+    buf = (C.c_float * 8)()
+    p = C.cast(buf, vp)
+    assert lib.ftc_mlp_adam(p, p, p, p, 0, 1e-3, 0.9, 0.999, 1e-8, None) == EINVAL     # step counts from 1
+    assert lib.ftc_mlp_adam(p, p, p, p, 1, -1.0, 0.9, 0.999, 1e-8, None) == EINVAL     # negative rate
+    assert lib.ftc_mlp_adam(p, p, p, p, 1, 1e-3, 1.0, 0.999, 1e-8, None) == EINVAL     # beta1 = 1
+    assert lib.ftc_mlp_loss_grad(p, p, 10, None, None, p, 0, p, None, p, None) == EINVAL  # empty batch
+    assert lib.ftc_mlp_forward(p, p, 0, None, None, 5, p, None) == EINVAL                # no rows

@@ -121,3 +121,26 @@ def test_smoothing_stops_after_max_rounds():
     Xg = np.stack([o.cpu().numpy() for o in out], 1)
     assert np.abs(Xg - Xo).max() <= 1e-12 * np.abs(X).max()
     c.close()
+
+
+def test_workspace_calls_reject_bad_arguments():
+    """Calls tied to the last build refuse another front; out-of-range
+    parameters are refused; nothing is launched for them."""
+    grid, mesh, _ = CASES["noisy_sphere"]()
+    torch, ftc, dm, c = _setup(grid, mesh)
+    nv, cap = mesh.nv, c.cell_capacity
+    z = lambda n, dt=torch.float64: torch.zeros(n, dtype=dt, device="cuda")
+    gl, rough = z(nv), z(nv)
+    other = ftc.DeviceMesh.from_host(I.sphere_workload(32, 0.25, 3, seed=1)[1])  # fewer vertices than the build's
+    for call in (lambda: ftc.front_roughness(c, grid, other, gl, rough),
+                 lambda: ftc.smooth_rough_edges(c, grid, dm, gl, rough, 0.0, 0.0, z(nv), z(nv), z(nv),
+                                                z(3, torch.int32), max_rounds=-1),
+                 lambda: ftc.curvature_features(c, grid, other, z(grid.ncell), z(cap * 32, torch.float32)),
+                 lambda: ftc.learned_curvature(c, grid, dm, z(grid.ncell), z(ftc.MLP_PARAMS, torch.float32), -1.0,
+                                               z(cap), z(cap), z(cap), z(cap))):
+        with pytest.raises(ftc.FTCError) as e:
+            call()
+        assert e.value.code == ftc.FTC_EINVAL
+    torch.cuda.synchronize()
+    assert c.last_device_error() == 0
+    c.close()
