@@ -115,7 +115,7 @@ __device__ inline int64_t block_alloc(int32_t v, int32_t* counter, int32_t* sh) 
 // classification: count, allocate, write.  A workgroup's queued candidates
 // are written grouped by the set of cell planes their triangle crosses, so
 // that the wavefronts of the clipping mostly take the same branches.
-constexpr int kClassifyT = 1024;
+constexpr int kClassifyT = 512;
 __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, const double2* vtx4, int4* tri4,
                                                              uint32_t* bitmap, PairOut P, int64_t q_cap,
                                                              int32_t* counters) {
