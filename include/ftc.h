@@ -203,6 +203,35 @@ ftc_status ftc_csf_force_band(ftc_cells* cells, const ftc_grid* grid, const doub
                               double sigma, int32_t band_capacity, int32_t* band_ids, double* kappa_band,
                               double* fx, double* fy, double* fz, int32_t* d_n_band, void* stream);
 
+/* Surface-tension part of the face flux of the momentum-weighted
+   interpolation (paper section 3.3, Eq. mwi_disc), divided by the solver's
+   coefficients d_f A_f, for the six faces of every interfacial and band
+   cell.  For the face between cells P (lower) and Q (upper) along axis d,
+   oriented along +d:
+     sigma [kbar_f (alpha_Q - alpha_P) / h
+            - rho*_f / 2 (k_P g_P / rho_P + k_Q g_Q / rho_Q)],
+   rho_C = rho_a + alpha_C (rho_b - rho_a) (the mixture density, section 2),
+   rho*_f = 2 rho_P rho_Q / (rho_P + rho_Q) (harmonic, section 2), g_C the
+   d-component of the central-difference gradient of alpha_dense, k_C the
+   curvature the CSF source uses in C (kappa of an interfacial cell,
+   kappa_band of a band cell) and no source in any other cell, kbar_f the mean
+   of k_P and k_Q over those of the two cells that carry a curvature.  With a
+   constant curvature and p = sigma k alpha it equals the pressure term of the
+   same flux (force balance).  kappa [cell_capacity] as from
+   ftc_ppic_curvature; band_ids, kappa_band [band_capacity] and d_n_band
+   [device int32] as written by the last ftc_csf_force_band on this
+   workspace, which must follow its last ftc_build_cell_lists (FTC_EINVAL
+   otherwise).  rho_a, rho_b > 0.  Outputs flux_if [6][cell_capacity]
+   (cell-list order) and flux_band [6][band_capacity] (band order); slot 2d
+   holds the face towards C - e_d, slot 2d + 1 the face towards C + e_d, so a
+   face shared by two listed cells has the same value in both rows.  A NaN
+   curvature propagates to the faces it touches. */
+ftc_status ftc_surface_tension_flux(ftc_cells* cells, const ftc_grid* grid, const double* alpha_dense,
+                                    const double* kappa, int32_t band_capacity, const int32_t* band_ids,
+                                    const double* kappa_band, const int32_t* d_n_band, double rho_a,
+                                    double rho_b, double sigma, double* flux_if, double* flux_band,
+                                    void* stream);
+
 /* Divergence-preserving interpolation (paper section 3.1) of staggered
    normal face velocities to the front vertices: inside the cell holding the
    vertex, linear interpolation between opposite faces plus transverse-

@@ -107,6 +107,8 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   w.cell_cap = cell_capacity;
   w.built_nv = -1;
   w.built_nt = -1;
+  w.builds = 0;
+  w.band_build = -1;
   w.pair_cap = pair_capacity;
   const int64_t P = pair_capacity, Cc = cell_capacity, Tc = nt_capacity, Vc = nv_capacity;
   void** reg = o->buffers;
@@ -283,8 +285,24 @@ ftc_status ftc_csf_force_band(ftc_cells* cells, const ftc_grid* grid, const doub
       !band_ids || !kappa_band || !fx || !fy || !fz || !d_n_band || band_capacity <= 0 || !isfinite(sigma))
     return FTC_EINVAL;
   if (!on_device(cells)) return FTC_EINVAL;
-  return hip_status(ftc::launch_csf_band(cells, alpha_dense, kappa, nx, ny, nz, sigma, band_capacity, band_ids,
-                                         kappa_band, fx, fy, fz, d_n_band, (hipStream_t)stream));
+  const ftc_status st = hip_status(ftc::launch_csf_band(cells, alpha_dense, kappa, nx, ny, nz, sigma, band_capacity,
+                                                        band_ids, kappa_band, fx, fy, fz, d_n_band,
+                                                        (hipStream_t)stream));
+  if (st == FTC_OK) cells->band_build = cells->builds;
+  return st;
+}
+
+ftc_status ftc_surface_tension_flux(ftc_cells* cells, const ftc_grid* grid, const double* alpha_dense,
+                                    const double* kappa, int32_t band_capacity, const int32_t* band_ids,
+                                    const double* kappa_band, const int32_t* d_n_band, double rho_a, double rho_b,
+                                    double sigma, double* flux_if, double* flux_band, void* stream) {
+  if (!cells || !grid_valid(grid) || !same_grid(cells->grid, grid) || !alpha_dense || !kappa || !band_ids ||
+      !kappa_band || !d_n_band || !flux_if || !flux_band || band_capacity <= 0 || !isfinite(sigma) ||
+      !(rho_a > 0.0) || !(rho_b > 0.0) || !isfinite(rho_a) || !isfinite(rho_b))
+    return FTC_EINVAL;
+  if (!on_device(cells) || cells->builds == 0 || cells->band_build != cells->builds) return FTC_EINVAL;
+  return hip_status(ftc::launch_face_flux(cells, alpha_dense, kappa, band_capacity, band_ids, kappa_band, d_n_band,
+                                          rho_a, rho_b, sigma, flux_if, flux_band, (hipStream_t)stream));
 }
 
 ftc_status ftc_interp_vertex_velocity(ftc_cells* cells, const ftc_grid* grid, const ftc_mesh* mesh, const double* U,

@@ -548,6 +548,7 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
   if (e == hipSuccess) {
     ws->built_nv = m.nv;
     ws->built_nt = m.nt;
+    ++ws->builds;
   }
   return e;
 }

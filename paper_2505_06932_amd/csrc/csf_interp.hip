@@ -77,6 +77,86 @@ __global__ __launch_bounds__(kT) void k_csf_band(Grid g, const uint32_t* bitmap,
   }
 }
 
+// The curvature the CSF source uses in cell `lin` (paper section 3.3): the
+// PPIC curvature of an interfacial cell, kappa_bar of a band cell (NaN if its
+// row lies beyond the lists written); false for any other cell, which
+// carries no surface force.
+__device__ inline bool carried_kappa(const BandWords& B, const int32_t* word_off, const int32_t* band_off,
+                                     int64_t lin, const double* kappa, int32_t nif, const double* kappa_band,
+                                     int32_t nb, double& k) {
+  const int64_t w = lin >> 5;
+  const uint32_t bit = 1u << (lin & 31), below = bit - 1u;
+  const uint32_t iw = B.I[w];
+  if (iw & bit) {
+    const int32_t r = word_off[w] + __popc(iw & below);
+    k = r < nif ? kappa[r] : NAN;
+    return true;
+  }
+  const uint32_t bw = B.word(w);
+  if (bw & bit) {
+    const int32_t r = band_off[w] + __popc(bw & below);
+    k = r < nb ? kappa_band[r] : NAN;
+    return true;
+  }
+  return false;
+}
+
+// k g / rho along one axis: the CSF source of a cell over its density, g the
+// central difference of alpha.  One expression for both sides of a face, so
+// that the two cells sharing it compute the same value.
+__device__ inline double source_over_rho(double k, double a_plus, double a_minus, double inv2h, double rho) {
+  return k * ((a_plus - a_minus) * inv2h) / rho;
+}
+
+// Surface-tension part of the face flux of the momentum-weighted
+// interpolation (paper section 3.3, Eq. mwi_disc) divided by d_f A_f, for the
+// six faces of every interfacial and band cell: one thread per cell.  Face
+// between P (lower) and Q (upper) along axis d:
+//   sigma [kbar_f (alpha_Q - alpha_P) / h - rho*_f / 2 (k_P g_P / rho_P + k_Q g_Q / rho_Q)],
+// rho = rho_a + alpha (rho_b - rho_a), rho*_f the harmonic mean of rho_P and
+// rho_Q, kbar_f the mean curvature of the cells of the two that carry one,
+// the source terms only for those.  Listed cells are at least one cell
+// inside the grid and so are the cells carrying a curvature: every alpha
+// read exists.
+__global__ __launch_bounds__(kT) void k_face_flux(Grid g, BandWords B, const int32_t* word_off,
+                                                  const int32_t* band_off, const int32_t* cell_ids,
+                                                  const double* alpha, const double* kappa, const int32_t* band_ids,
+                                                  const double* kappa_band, const int32_t* n_band, int32_t band_cap,
+                                                  double rho_a, double rho_b, double sigma, double* flux_if,
+                                                  double* flux_band, int32_t cell_cap, const int32_t* counters) {
+  const int32_t nif = min(counters[C_NIF], cell_cap), nb = min(*n_band, band_cap);
+  const int64_t st[3] = {1, (int64_t)g.nx, (int64_t)g.nx * g.ny};
+  const double inv_h = 1.0 / g.h, inv2h = 1.0 / (2.0 * g.h), drho = rho_b - rho_a;
+  for (int32_t r = blockIdx.x * kT + threadIdx.x; r < nif + nb; r += gridDim.x * kT) {
+    const bool in_band = r >= nif;
+    const int32_t row = in_band ? r - nif : r;
+    const int64_t c = in_band ? band_ids[row] : cell_ids[row];
+    const double kc = in_band ? kappa_band[row] : kappa[row];
+    double* out = in_band ? flux_band + row : flux_if + row;
+    const int64_t ostride = in_band ? band_cap : cell_cap;
+    const double ac = alpha[c], rc = rho_a + ac * drho;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t s = st[d];
+      const double tc = source_over_rho(kc, alpha[c + s], alpha[c - s], inv2h, rc);
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int64_t n = side ? c + s : c - s;
+        double kn = 0.0;
+        const bool carries = carried_kappa(B, word_off, band_off, n, kappa, nif, kappa_band, nb, kn);
+        const double an = alpha[n], rn = rho_a + an * drho;
+        const double tn = carries ? source_over_rho(kn, alpha[n + s], alpha[n - s], inv2h, rn) : 0.0;
+        const double kf = carries ? 0.5 * (kc + kn) : kc;
+        const double aP = side ? ac : an, aQ = side ? an : ac;
+        const double rP = side ? rc : rn, rQ = side ? rn : rc;
+        const double tP = side ? tc : tn, tQ = side ? tn : tc;
+        const double rs = 2.0 * rP * rQ / (rP + rQ);
+        out[(2 * d + side) * ostride] = sigma * (kf * (aQ - aP) * inv_h - 0.5 * rs * (tP + tQ));
+      }
+    }
+  }
+}
+
 // The divergence-preserving interpolant at (x, y, z), in the half-open cell
 // holding it; false (and nothing written) if the point is not finite or the
 // cell is not at least one cell inside the grid.
@@ -196,6 +276,17 @@ hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const doubl
   hipLaunchKernelGGL(k_csf_band, dim3(grid_blocks(band_cap, kT, 4096)), dim3(kT), 0, s, g, ws->bitmap, ws->word_off,
                      alpha, kappa, nx, ny, nz, sigma, band_ids, n_band, band_cap, kappa_band, fx, fy, fz,
                      ws->cell_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_flux(const ftc_cells* ws, const double* alpha, const double* kappa, int32_t band_cap,
+                            const int32_t* band_ids, const double* kappa_band, const int32_t* n_band, double rho_a,
+                            double rho_b, double sigma, double* flux_if, double* flux_band, hipStream_t s) {
+  const Grid& g = ws->grid;
+  const BandWords B{ws->bitmap, ws->nwords, ws->ncell, g.nx, (int64_t)g.nx * g.ny};
+  hipLaunchKernelGGL(k_face_flux, dim3(grid_blocks((int64_t)ws->cell_cap + band_cap, kT, 4096)), dim3(kT), 0, s, g, B,
+                     ws->word_off, ws->band_off, ws->cell_ids, alpha, kappa, band_ids, kappa_band, n_band, band_cap,
+                     rho_a, rho_b, sigma, flux_if, flux_band, ws->cell_cap, ws->counters);
   return hipGetLastError();
 }
 

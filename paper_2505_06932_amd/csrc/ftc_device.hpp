@@ -181,6 +181,33 @@ __host__ __device__ inline bool cell_planes(const Grid& g, const Tri& T, int64_t
   return ok;
 }
 
+// Words of the face-neighbour band of the occupancy bitmap I: bit q of word
+// w is set for cell c = 32 w + q when c is not in I and one of c -+ 1,
+// c -+ sy, c -+ sz is.  Every set cell of I lies at least two cells inside
+// the grid, so these linear shifts reach exactly its face neighbours (a
+// shift that wraps a row or slice lands on a boundary cell, never set).
+struct BandWords {
+  const uint32_t* I;
+  int64_t nwords, ncell, sy, sz;
+  // the 32 bits of I from cell `start` on (zero outside the grid)
+  __device__ uint32_t bits_at(int64_t start) const {
+    const int64_t w = start >= 0 ? start >> 5 : -((-start + 31) >> 5);
+    const int off = (int)(start - 32 * w);
+    const uint32_t lo = (w >= 0 && w < nwords) ? I[w] : 0u;
+    const uint32_t hi = (w + 1 >= 0 && w + 1 < nwords) ? I[w + 1] : 0u;
+    return off == 0 ? lo : ((lo >> off) | (hi << (32 - off)));
+  }
+  __device__ uint32_t word(int64_t w) const {
+    const int64_t b = 32 * w;
+    const uint32_t nb = bits_at(b - 1) | bits_at(b + 1) | bits_at(b - sy) | bits_at(b + sy) | bits_at(b - sz) |
+                        bits_at(b + sz);
+    uint32_t band = nb & ~I[w];
+    const int64_t rest = ncell - b;  // cells of this word inside the grid
+    if (rest < 32) band &= rest > 0 ? ((1u << rest) - 1u) : 0u;
+    return band;
+  }
+};
+
 // Compact index of grid cell `lin` among the interfacial cells (its rank in
 // the occupancy bitmap, from the popcount prefix sums), -1 if it holds no
 // piece.

@@ -44,6 +44,8 @@ struct ftc_cells {
   int64_t ncell, nwords, ncol;
   int32_t nv_cap, nt_cap, cell_cap;
   int32_t built_nv, built_nt;  // front sizes of the last build (-1 before the first)
+  int64_t builds;      // builds enqueued so far
+  int64_t band_build;  // value of `builds` when the band was last listed (-1: never)
   int64_t pair_cap;
   int64_t queue_cap;  // candidates queued for full clipping (>= pair_cap)
 
@@ -190,6 +192,9 @@ hipError_t launch_csf(const ftc_cells* ws, const double* alpha, const double* ka
 hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const double* kappa, const double* nx,
                            const double* ny, const double* nz, double sigma, int32_t band_cap, int32_t* band_ids,
                            double* kappa_band, double* fx, double* fy, double* fz, int32_t* n_band, hipStream_t s);
+hipError_t launch_face_flux(const ftc_cells* ws, const double* alpha, const double* kappa, int32_t band_cap,
+                            const int32_t* band_ids, const double* kappa_band, const int32_t* n_band, double rho_a,
+                            double rho_b, double sigma, double* flux_if, double* flux_band, hipStream_t s);
 hipError_t launch_interp(const ftc_cells* ws, const Grid& g, const Mesh& m, const double* U, const double* V,
                          const double* W, double* ux, double* uy, double* uz, hipStream_t s);
 hipError_t launch_advect_rk4(const ftc_cells* ws, const Grid& g, const Mesh& m, const double* U, const double* V,

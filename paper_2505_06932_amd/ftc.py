@@ -36,7 +36,7 @@ EXPORTED = ["ftc_cells_create", "ftc_cells_destroy", "ftc_build_cell_lists", "ft
             "ftc_interp_vertex_velocity", "ftc_last_device_error", "ftc_set_timing", "ftc_kernel_time",
             "ftc_csf_force_band", "ftc_advect_vertices_rk4", "ftc_curvature_features", "ftc_mlp_forward",
             "ftc_mlp_loss_grad", "ftc_mlp_adam", "ftc_learned_curvature", "ftc_front_roughness",
-            "ftc_smooth_rough_edges", "ftc_get_tuning", "ftc_set_tuning",
+            "ftc_smooth_rough_edges", "ftc_get_tuning", "ftc_set_tuning", "ftc_surface_tension_flux",
             "ftc_status_str"]
 
 # ftc_kernel values (timing)
@@ -123,6 +123,9 @@ def lib() -> C.CDLL:
     L.ftc_csf_force_band.argtypes = [vp, P(_CGrid), vp, vp, vp, vp, vp, C.c_double, C.c_int32, vp, vp, vp, vp, vp,
                                      vp, vp]
     L.ftc_csf_force_band.restype = C.c_int32
+    L.ftc_surface_tension_flux.argtypes = [vp, P(_CGrid), vp, vp, C.c_int32, vp, vp, vp, C.c_double, C.c_double,
+                                           C.c_double, vp, vp, vp]
+    L.ftc_surface_tension_flux.restype = C.c_int32
     L.ftc_interp_vertex_velocity.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, vp, vp, vp, vp, vp]
     L.ftc_interp_vertex_velocity.restype = C.c_int32
     L.ftc_advect_vertices_rk4.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, vp, C.c_double, vp, vp, vp, vp]
@@ -366,6 +369,25 @@ def csf_force_band(cells: Cells, grid: _inputs.Grid, alpha_dense, kappa, nx, ny,
                                     _ptr(fz, torch.float64, bcap, "fz"), _ptr(n_band, torch.int32, 1, "n_band"),
                                     _stream(stream)),
            "ftc_csf_force_band")
+
+
+def surface_tension_flux(cells: Cells, grid: _inputs.Grid, alpha_dense, kappa, band_ids, kappa_band, n_band,
+                         rho_a: float, rho_b: float, sigma: float, flux_if, flux_band, stream=None) -> None:
+    """Surface-tension part of the face flux (Eq. mwi_disc) over d_f A_f:
+    flux_if [6, cell_capacity], flux_band [6, band capacity]; band_ids,
+    kappa_band and n_band as written by the last csf_force_band."""
+    cg = c_grid(grid)
+    cap = cells.cell_capacity
+    bcap = int(band_ids.numel())
+    _check(lib().ftc_surface_tension_flux(cells.handle, C.byref(cg),
+                                          _ptr(alpha_dense, torch.float64, grid.ncell, "alpha"),
+                                          _ptr(kappa, torch.float64, cap, "kappa"), bcap,
+                                          _ptr(band_ids, torch.int32, bcap, "band_ids"),
+                                          _ptr(kappa_band, torch.float64, bcap, "kappa_band"),
+                                          _ptr(n_band, torch.int32, 1, "n_band"), float(rho_a), float(rho_b),
+                                          float(sigma), _ptr(flux_if, torch.float64, 6 * cap, "flux_if"),
+                                          _ptr(flux_band, torch.float64, 6 * bcap, "flux_band"), _stream(stream)),
+           "ftc_surface_tension_flux")
 
 
 def advect_vertices_rk4(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, U, V, W, dt: float, x_out, y_out, z_out,

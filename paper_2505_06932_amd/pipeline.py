@@ -15,10 +15,15 @@ class CouplingStep:
     def __init__(self, grid: I.Grid, mesh: I.Mesh, U=None, V=None, W=None, sigma: float = 1.0,
                  params: ftc.PPICParams | None = None, margin: float = 1.25,
                  pair_capacity: int | None = None, cell_capacity: int | None = None, band: bool = False,
-                 learned=None, bound: float | None = None, tuning: ftc.Tuning | None = None):
+                 learned=None, bound: float | None = None, tuning: ftc.Tuning | None = None,
+                 densities: tuple[float, float] | None = None):
         """learned: surrogate parameters (device float32 tensor of
         ftc.MLP_PARAMS values); the curvature is then the learned surrogate
-        with its PPIC fallback above the spread `bound`."""
+        with its PPIC fallback above the spread `bound`.  densities: (rho_a,
+        rho_b) adds the surface-tension part of the face flux of every
+        interfacial and band cell (needs band=True)."""
+        if densities is not None and not band:
+            raise ValueError("the face flux needs the band (band=True)")
         self.grid = grid
         self.sigma = float(sigma)
         self.params = params
@@ -73,6 +78,9 @@ class CouplingStep:
             self.kappa_band = z(bcap)
             self.bx, self.by, self.bz = z(bcap), z(bcap), z(bcap)
             self.n_band = z(1, torch.int32)
+        self.densities = densities
+        if densities is not None:
+            self.flux_if, self.flux_band = z(6 * cap), z(6 * bcap)
 
     # the hot path, split so that callers can time its parts
     def cells_and_alpha(self, stream=None):
@@ -95,6 +103,10 @@ class CouplingStep:
         if self.band:
             ftc.csf_force_band(self.cells, self.grid, self.alpha, self.kappa, self.nx, self.ny, self.nz, self.sigma,
                                self.band_ids, self.kappa_band, self.bx, self.by, self.bz, self.n_band, stream)
+        if self.densities is not None:
+            ftc.surface_tension_flux(self.cells, self.grid, self.alpha, self.kappa, self.band_ids, self.kappa_band,
+                                     self.n_band, self.densities[0], self.densities[1], self.sigma, self.flux_if,
+                                     self.flux_band, stream)
         ftc.interp_vertex_velocity(self.cells, self.grid, self.mesh, self.U, self.V, self.W, self.ux,
                                    self.uy, self.uz, stream)
 
@@ -128,5 +140,10 @@ class CouplingStep:
     def _band_results(self, h):
         nb = int(h(self.n_band)[0])
         nb = min(nb, self.band_ids.numel())
-        return dict(n_band=nb, band_ids=h(self.band_ids)[:nb].astype(np.int64), kappa_band=h(self.kappa_band)[:nb],
-                    band_force=np.stack([h(self.bx)[:nb], h(self.by)[:nb], h(self.bz)[:nb]], 1))
+        out = dict(n_band=nb, band_ids=h(self.band_ids)[:nb].astype(np.int64), kappa_band=h(self.kappa_band)[:nb],
+                   band_force=np.stack([h(self.bx)[:nb], h(self.by)[:nb], h(self.bz)[:nb]], 1))
+        if self.densities is not None:
+            n_if = self.cells.count()[0]
+            out["flux_if"] = h(self.flux_if).reshape(6, -1)[:, :n_if].T
+            out["flux_band"] = h(self.flux_band).reshape(6, -1)[:, :nb].T
+        return out

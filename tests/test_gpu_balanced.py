@@ -1,0 +1,127 @@
+"""GPU parity of the surface-tension face flux (paper sec. 3.3, Eq. mwi_disc)
+through the C ABI: against the oracle on the oracle's own curvatures (1e-10
+of the largest value, the curvature bar), the force balance with a constant
+curvature at full size, equal values on both sides of shared faces, and the
+host-side argument checks."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import balanced as B
+from paper_2505_06932_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+SIGMA = 0.07
+RHO = (1.2, 1000.0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _step(name, seed=0):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2505_06932_amd import pipeline
+    grid, mesh, _ = I.make_workload(name, seed)
+    _say(f"[face flux] case={name}/{seed} nv={mesh.nv} nt={mesh.nt}")
+    step = pipeline.CouplingStep(grid, mesh, sigma=SIGMA, band=True, densities=RHO)
+    step.run()
+    return grid, mesh, step, step.results()
+
+
+@pytest.mark.parametrize("name", ["sphere_32", "sphere_128"])
+def test_face_flux_parity(oracle, name):
+    grid, mesh, step, g = _step(name)
+    assert g["error"] == 0
+    cells, _, _ = oracle.cell_lists(grid, mesh)
+    alpha, _ = oracle.volume_fraction(grid, mesh)
+    r = oracle.ppic(grid, mesh, cells)
+    bid, kb, _ = oracle.csf_band(grid, alpha, cells, r["kappa"], r["normal"], 1.0)
+    assert np.array_equal(g["cell_ids"][:g["n_if"]], cells) and np.array_equal(g["band_ids"], bid)
+    fi, fb = B.surface_tension_face_flux(grid, alpha, cells, r["kappa"], bid, kb, RHO[0], RHO[1], SIGMA)
+    ok_i, ok_b = np.isfinite(fi).all(1), np.isfinite(fb).all(1)
+    assert np.array_equal(np.isfinite(g["flux_if"]).all(1), ok_i)
+    assert np.array_equal(np.isfinite(g["flux_band"]).all(1), ok_b)
+    scale = max(np.abs(fi[ok_i]).max(), np.abs(fb[ok_b]).max())
+    err = max(np.abs(g["flux_if"][ok_i] - fi[ok_i]).max(), np.abs(g["flux_band"][ok_b] - fb[ok_b]).max())
+    _say(f"[face flux] {name}: {len(cells)} interfacial + {len(bid)} band rows, max err {err / scale:.2e} of max")
+    assert err <= TOL * scale
+
+
+def _rows(g):
+    ids = np.concatenate([g["cell_ids"][:g["n_if"]], g["band_ids"]])
+    flux = np.concatenate([g["flux_if"], g["flux_band"]])
+    return ids, flux
+
+
+def test_shared_faces_agree_bitwise():
+    """A face shared by two listed cells has the same value in both rows."""
+    grid, mesh, step, g = _step("sphere_128")
+    ids, flux = _rows(g)
+    row = {int(c): k for k, c in enumerate(ids.tolist())}
+    st = (1, grid.nx, grid.nx * grid.ny)
+    pairs = 0
+    for d in range(3):
+        up = ids + st[d]
+        have = np.array([int(u) in row for u in up.tolist()])
+        lo = np.nonzero(have)[0]
+        hi = np.array([row[int(u)] for u in up[lo].tolist()])
+        assert np.array_equal(flux[lo, 2 * d + 1], flux[hi, 2 * d])
+        pairs += len(lo)
+    assert pairs > len(ids)
+
+
+def test_force_balance_at_full_size():
+    """With one curvature in every interfacial and band cell the flux equals
+    the pressure term of the same flux for p = sigma k alpha (central
+    differences, harmonic face density), on the 128^3 sphere."""
+    import torch
+    from paper_2505_06932_amd import ftc
+    grid, mesh, step, g = _step("sphere_128")
+    k0 = 4.0 / 0.25
+    kap = torch.full_like(step.kappa, k0)
+    kb = torch.full_like(step.kappa_band, k0)
+    ftc.surface_tension_flux(step.cells, grid, step.alpha, kap, step.band_ids, kb, step.n_band, RHO[0], RHO[1], SIGMA,
+                             step.flux_if, step.flux_band)
+    g = step.results()
+    ids, flux = _rows(g)
+    a = g["alpha"].reshape(-1)
+    p = SIGMA * k0 * a
+    rho = RHO[0] + a * (RHO[1] - RHO[0])
+    st = (1, grid.nx, grid.nx * grid.ny)
+    h = grid.h
+    worst = 0.0
+    for d in range(3):
+        s = st[d]
+        for side in (0, 1):
+            P = ids - s if side == 0 else ids
+            Q = ids if side == 0 else ids + s
+            gP = (p[P + s] - p[P - s]) / (2 * h)
+            gQ = (p[Q + s] - p[Q - s]) / (2 * h)
+            rf = 2 * rho[P] * rho[Q] / (rho[P] + rho[Q])
+            ref = (p[Q] - p[P]) / h - rf / 2 * (gP / rho[P] + gQ / rho[Q])
+            worst = max(worst, np.abs(flux[:, 2 * d + side] - ref).max())
+    assert worst <= 1e-12 * SIGMA * k0 / h
+
+
+def test_flux_refuses_stale_band_and_bad_densities():
+    """Host checks, no kernel runs: densities must be positive, and the band
+    must have been listed after the last build."""
+    import torch
+    from paper_2505_06932_amd import ftc
+    grid, mesh, step, g = _step("sphere_32")
+    args = (step.cells, grid, step.alpha, step.kappa, step.band_ids, step.kappa_band, step.n_band)
+    outs = (step.flux_if, step.flux_band)
+    for ra, rb in ((0.0, 1.0), (1.0, -2.0), (float("nan"), 1.0), (1.0, float("inf"))):
+        with pytest.raises(ftc.FTCError):
+            ftc.surface_tension_flux(*args, ra, rb, SIGMA, *outs)
+    ftc.build_cell_lists(step.cells, grid, step.mesh)
+    with pytest.raises(ftc.FTCError):
+        ftc.surface_tension_flux(*args, 1.0, 2.0, SIGMA, *outs)
+    torch.cuda.synchronize()
