@@ -1,0 +1,140 @@
+"""Volume fraction under the local paraboloid (paper section 3.2: alpha is the
+volume of the intersection of the cell with the region below the fitted
+paraboloid, over the cell volume): the plain CPU definition the GPU kernel is
+checked against.  Test infrastructure only.
+
+The paraboloid is the one the PPIC fit returns for a cell: in the frame
+(t1, t2, n) with origin at the cell centre x_c, local coordinates
+xi = t1.(x - x_c), eta = t2.(x - x_c), zeta = n.(x - x_c), the surface is
+zeta = a1 + a2 xi + a3 eta + a4 xi^2 + a5 xi eta + a6 eta^2 (world units),
+and the liquid (alpha = 1 side, n points out of it) lies below it.  The frame
+is the PPIC frame: n the area-weighted normal of the front vertex closest to
+the cell centre, (t1, t2) the branchless orthonormal basis of Duff et al.
+(JCGT 2017) completing it.
+
+Definition used here, written out directly: in cell units p = (x - x_c)/h,
+the cell is the cube [-1/2, 1/2]^3 and the liquid is F(p) < 0 with
+F(p) = n.p - Pc(t1.p, t2.p), Pc the paraboloid in cell units
+(a1/h, a2, a3, a4 h, a5 h, a6 h).  Then
+
+    alpha = integral over x in [-1/2, 1/2] of
+            integral over y in [-1/2, 1/2] of |{z in [-1/2, 1/2] : F < 0}| dy dx,
+
+the inner length from the two roots of the quadratic F(x, y, .) in z.  Both
+integrals are adaptive Gauss-Kronrod quadratures (scipy's QUADPACK); the
+inner one is told the y at which its integrand has a kink (F(x, y, -+1/2) =
+0, or a double root in z), which are again roots of quadratics.  Accurate to
+about 1e-14 on the unit cube.
+"""
+from __future__ import annotations
+
+import warnings
+
+import numpy as np
+from scipy import integrate
+
+TOL = 1e-14
+
+
+def duff_frame(n):
+    """Tangents (t1, t2) completing the unit vector n to a right-handed
+    orthonormal frame, by the branchless construction of Duff et al."""
+    n = np.asarray(n, dtype=np.float64)
+    s = np.copysign(1.0, n[2])
+    a = -1.0 / (s + n[2])
+    b = n[0] * n[1] * a
+    return (np.array([1.0 + s * n[0] * n[0] * a, s * b, -s * n[0]]),
+            np.array([b, s + n[1] * n[1] * a, -n[1]]))
+
+
+def _roots(qa, qb, qc):
+    """Real roots of qa t^2 + qb t + qc (the linear case too)."""
+    if qa == 0.0:
+        return [-qc / qb] if qb != 0.0 else []
+    d = qb * qb - 4.0 * qa * qc
+    if d < 0.0:
+        return []
+    q = -0.5 * (qb + np.copysign(np.sqrt(d), qb))
+    out = [q / qa]
+    if q != 0.0:
+        out.append(qc / q)
+    return out
+
+
+class _Quadric:
+    """F(p) = p^T M p + g.p + f0 for the paraboloid in cell units."""
+
+    def __init__(self, n, t1, t2, b):
+        b1, b2, b3, b4, b5, b6 = (float(v) for v in b)
+        n, t1, t2 = (np.asarray(v, dtype=np.float64) for v in (n, t1, t2))
+        self.M = -(b4 * np.outer(t1, t1) + 0.5 * b5 * (np.outer(t1, t2) + np.outer(t2, t1)) + b6 * np.outer(t2, t2))
+        self.g = n - b2 * t1 - b3 * t2
+        self.f0 = -b1
+
+    def z_coeffs(self, x, y):
+        """F(x, y, z) = A z^2 + B z + C."""
+        M, g = self.M, self.g
+        A = M[2, 2]
+        B = 2.0 * (M[0, 2] * x + M[1, 2] * y) + g[2]
+        C = M[0, 0] * x * x + 2.0 * M[0, 1] * x * y + M[1, 1] * y * y + g[0] * x + g[1] * y + self.f0
+        return A, B, C
+
+    def z_length(self, x, y):
+        """|{z in [-1/2, 1/2] : F(x, y, z) < 0}|."""
+        A, B, C = self.z_coeffs(x, y)
+        cuts = sorted([-0.5, 0.5] + [r for r in _roots(A, B, C) if -0.5 < r < 0.5])
+        s = 0.0
+        for lo, hi in zip(cuts[:-1], cuts[1:]):
+            zm = 0.5 * (lo + hi)
+            if (A * zm + B) * zm + C < 0.0:
+                s += hi - lo
+        return s
+
+    def y_kinks(self, x):
+        """y in (-1/2, 1/2) where the z-length may have a kink: F(x, y, -+1/2)
+        = 0, or F(x, y, .) has a double root."""
+        M, g = self.M, self.g
+        out = []
+        for z in (-0.5, 0.5):
+            out += _roots(M[1, 1], 2.0 * M[0, 1] * x + 2.0 * M[1, 2] * z + g[1],
+                          M[0, 0] * x * x + M[2, 2] * z * z + 2.0 * M[0, 2] * x * z + g[0] * x + g[2] * z + self.f0)
+        A = M[2, 2]
+        b1, b0 = 2.0 * M[1, 2], 2.0 * M[0, 2] * x + g[2]
+        c2, c1, c0 = M[1, 1], 2.0 * M[0, 1] * x + g[1], M[0, 0] * x * x + g[0] * x + self.f0
+        out += _roots(b1 * b1 - 4.0 * A * c2, 2.0 * b1 * b0 - 4.0 * A * c1, b0 * b0 - 4.0 * A * c0)
+        return sorted(v for v in out if -0.5 < v < 0.5)
+
+
+def alpha_unit(n, t1, t2, b, tol: float = TOL) -> float:
+    """Liquid fraction of the cube [-1/2, 1/2]^3 below the paraboloid
+    zeta = b1 + b2 xi + b3 eta + b4 xi^2 + b5 xi eta + b6 eta^2 in the frame
+    (t1, t2, n) (all in cell units)."""
+    Q = _Quadric(n, t1, t2, b)
+
+    def area(x):
+        pts = Q.y_kinks(x)
+        return integrate.quad(lambda y: Q.z_length(x, y), -0.5, 0.5, points=pts or None, epsabs=tol, epsrel=tol,
+                              limit=200)[0]
+
+    with warnings.catch_warnings():
+        # QUADPACK reports that round-off stops it short of 1e-14; the result
+        # is then as accurate as double precision allows
+        warnings.simplefilter("ignore", integrate.IntegrationWarning)
+        return integrate.quad(area, -0.5, 0.5, epsabs=tol, epsrel=tol, limit=400)[0]
+
+
+def cell_units(coeff, h):
+    """PPIC coefficients (world units, origin at the cell centre) in cell units."""
+    a1, a2, a3, a4, a5, a6 = (float(v) for v in coeff)
+    return (a1 / h, a2, a3, a4 * h, a5 * h, a6 * h)
+
+
+def alpha_cells(frame_normals, coeffs, h, tol: float = TOL):
+    """alpha under the PPIC paraboloid of each listed cell: frame_normals [n, 3]
+    (the PPIC frame normal of each cell), coeffs [n, 6] (world units, origin
+    at the cell centre)."""
+    out = np.empty(len(coeffs))
+    for i, (nv, co) in enumerate(zip(np.asarray(frame_normals), np.asarray(coeffs))):
+        t1, t2 = duff_frame(nv)
+        out[i] = alpha_unit(nv, t1, t2, cell_units(co, h), tol)
+    return out
