@@ -23,8 +23,9 @@ F(p) = n.p - Pc(t1.p, t2.p), Pc the paraboloid in cell units
 the inner length from the two roots of the quadratic F(x, y, .) in z.  Both
 integrals are adaptive Gauss-Kronrod quadratures (scipy's QUADPACK); the
 inner one is told the y at which its integrand has a kink (F(x, y, -+1/2) =
-0, or a double root in z), which are again roots of quadratics.  Accurate to
-about 1e-14 on the unit cube.
+0, or a double root in z), the outer one the x at which those kink curves
+meet the cube edges, each other, or turn along y; all are roots of
+quadratics.  Accurate to about 1e-15 on the unit cube.
 """
 from __future__ import annotations
 
@@ -105,6 +106,55 @@ class _Quadric:
         return sorted(v for v in out if -0.5 < v < 0.5)
 
 
+    def x_kinks(self):
+        """x in (-1/2, 1/2) where the area of the slice x = const may have a
+        kink: where the curves of y_kinks meet the edges y = -+1/2, have a
+        tangent along y, or meet each other.  Each is a root of a quadratic
+        in x:
+          * F = 0 on a cube edge along x (y, z = -+1/2);
+          * a double root in z on a face y = -+1/2;
+          * F(x, ., z0) = 0 (z0 = -+1/2) tangent along y;
+          * the double-root curve tangent along y;
+          * the double root at z0 (F = dF/dz = 0 there);
+          * F(x, y, -1/2) = F(x, y, 1/2) = 0 (then dF/dz vanishes at z = 0)."""
+        M, g, f0 = self.M, self.g, self.f0
+        A = M[2, 2]
+        out = []
+        for y in (-0.5, 0.5):
+            for z in (-0.5, 0.5):
+                out += _roots(M[0, 0], 2 * M[0, 1] * y + 2 * M[0, 2] * z + g[0],
+                              M[1, 1] * y * y + 2 * M[1, 2] * y * z + M[2, 2] * z * z + g[1] * y + g[2] * z + f0)
+            # B = 2 M02 x + (2 M12 y + g2), C = M00 x^2 + (2 M01 y + g0) x + (M11 y^2 + g1 y + f0)
+            p1, p0 = 2 * M[0, 2], 2 * M[1, 2] * y + g[2]
+            c2, c1, c0 = M[0, 0], 2 * M[0, 1] * y + g[0], M[1, 1] * y * y + g[1] * y + f0
+            out += _roots(p1 * p1 - 4 * A * c2, 2 * p1 * p0 - 4 * A * c1, p0 * p0 - 4 * A * c0)
+        # F(x, y, z0) = M11 y^2 + (2 M01 x + 2 M12 z0 + g1) y + (M00 x^2 + (2 M02 z0 + g0) x + M22 z0^2 + g2 z0 + f0)
+        for z in (-0.5, 0.5):
+            u1, u0 = 2 * M[0, 1], 2 * M[1, 2] * z + g[1]
+            w2, w1, w0 = M[0, 0], 2 * M[0, 2] * z + g[0], M[2, 2] * z * z + g[2] * z + f0
+            out += _roots(u1 * u1 - 4 * M[1, 1] * w2, 2 * u1 * u0 - 4 * M[1, 1] * w1, u0 * u0 - 4 * M[1, 1] * w0)
+        # double-root curve D(x, y) = B^2 - 4 A C = Dy2 y^2 + Dy1(x) y + Dy0(x)
+        b1 = 2 * M[1, 2]
+        Dy2 = b1 * b1 - 4 * A * M[1, 1]
+        # Dy1 = 2 b1 (2 M02 x + g2) - 4 A (2 M01 x + g1) = e1 x + e0
+        e1, e0 = 4 * b1 * M[0, 2] - 8 * A * M[0, 1], 2 * b1 * g[2] - 4 * A * g[1]
+        # Dy0 = (2 M02 x + g2)^2 - 4 A (M00 x^2 + g0 x + f0) = d2 x^2 + d1 x + d0
+        d2, d1, d0 = 4 * M[0, 2] ** 2 - 4 * A * M[0, 0], 4 * M[0, 2] * g[2] - 4 * A * g[0], g[2] ** 2 - 4 * A * f0
+        out += _roots(e1 * e1 - 4 * Dy2 * d2, 2 * e1 * e0 - 4 * Dy2 * d1, e0 * e0 - 4 * Dy2 * d0)
+        # dF/dz = 2 A z + 2 M02 x + 2 M12 y + g2 = 0 at z = zc, together with F(x, y, zc) = 0
+        for zc in (-0.5, 0.5, 0.0):
+            k0 = 2 * A * zc + g[2]
+            if M[1, 2] != 0.0:
+                al, be = -k0 / (2 * M[1, 2]), -M[0, 2] / M[1, 2]  # y = al + be x
+                qa = M[0, 0] + 2 * M[0, 1] * be + M[1, 1] * be * be
+                qb = 2 * M[0, 1] * al + 2 * M[1, 1] * al * be + 2 * M[0, 2] * zc + 2 * M[1, 2] * zc * be + g[0] + g[1] * be
+                qc = M[1, 1] * al * al + 2 * M[1, 2] * al * zc + M[2, 2] * zc * zc + g[1] * al + g[2] * zc + f0
+                out += _roots(qa, qb, qc)
+            elif M[0, 2] != 0.0:
+                out.append(-k0 / (2 * M[0, 2]))
+        return sorted(v for v in out if -0.5 < v < 0.5)
+
+
 def alpha_unit(n, t1, t2, b, tol: float = TOL) -> float:
     """Liquid fraction of the cube [-1/2, 1/2]^3 below the paraboloid
     zeta = b1 + b2 xi + b3 eta + b4 xi^2 + b5 xi eta + b6 eta^2 in the frame
@@ -120,7 +170,7 @@ def alpha_unit(n, t1, t2, b, tol: float = TOL) -> float:
         # QUADPACK reports that round-off stops it short of 1e-14; the result
         # is then as accurate as double precision allows
         warnings.simplefilter("ignore", integrate.IntegrationWarning)
-        return integrate.quad(area, -0.5, 0.5, epsabs=tol, epsrel=tol, limit=400)[0]
+        return integrate.quad(area, -0.5, 0.5, points=Q.x_kinks() or None, epsabs=tol, epsrel=tol, limit=400)[0]
 
 
 def cell_units(coeff, h):

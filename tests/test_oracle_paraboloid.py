@@ -104,7 +104,22 @@ def test_cube_symmetries():
         S = np.zeros((3, 3))
         for r, (c, s) in enumerate(zip(perm, signs)):
             S[r, c] = s
-        assert PB.alpha_unit(S @ n, S @ t1, S @ t2, b) == pytest.approx(a0, abs=1e-13)
+        assert PB.alpha_unit(S @ n, S @ t1, S @ t2, b) == pytest.approx(a0, abs=1e-14)
+
+
+def test_same_volume_with_the_chord_along_each_axis():
+    """A cell of the 32^3 sphere whose nested quadrature needs the slice-area
+    kinks: the volume computed with the inner chord along z, x and y (axes
+    permuted) agrees to 1e-14."""
+    n = np.array([-0.65645707, -0.26770795, -0.70526347])
+    n /= np.linalg.norm(n)
+    t1, t2 = PB.duff_frame(n)
+    b = (0.372184277, -0.0388448336, 0.00384352669, -0.0632620764, -0.000286374076, -0.0634228759)
+    vals = []
+    for perm in ((0, 1, 2), (1, 2, 0), (2, 0, 1)):
+        S = np.eye(3)[list(perm)]
+        vals.append(PB.alpha_unit(S @ n, S @ t1, S @ t2, b))
+    assert max(vals) - min(vals) < 1e-14
 
 
 def test_sphere_cells_close_to_exact_alpha(oracle):
