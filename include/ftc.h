@@ -173,6 +173,22 @@ ftc_status ftc_ppic_curvature(const ftc_cells* cells, const ftc_grid* grid, cons
                               double* nz, double* coeff, int32_t* cell_status, int32_t* diag,
                               void* stream);
 
+/* Volume fraction under the fitted paraboloid (paper section 3.2: alpha is
+   the volume of the cell below the local paraboloid over the cell volume),
+   for every interfacial cell: the paraboloid zeta = a1 + a2 xi + a3 eta +
+   a4 xi^2 + a5 xi eta + a6 eta^2 of the last ftc_ppic_curvature on this
+   workspace, in its frame (t1, t2, n) with origin at the cell centre, where
+   n is the frame normal of that call (kept in the workspace) and the liquid
+   lies below the surface (zeta smaller).  coeff [6][cell_capacity] as that
+   call wrote it; alpha_paraboloid [cell_capacity], cell-list order.  The
+   integral over the cell is exact in one tangential direction and a Gauss
+   rule between the exact breakpoints in the other (error about 1e-14); a
+   cell whose fit failed (NaN coefficients) gets NaN.  FTC_EINVAL unless
+   ftc_ppic_curvature (not the learned curvature) ran after the last
+   ftc_build_cell_lists. */
+ftc_status ftc_paraboloid_volume_fraction(const ftc_cells* cells, const ftc_grid* grid, const double* coeff,
+                                          double* alpha_paraboloid, void* stream);
+
 /* Continuum surface force (paper section 3.3, Eq. csf): S = sigma kappa
    grad(alpha) on the interfacial cells only, grad(alpha) by central
    differences of the dense alpha field (alpha_dense[nx*ny*nz]) with spacing

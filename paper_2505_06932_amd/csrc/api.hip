@@ -109,6 +109,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   w.built_nt = -1;
   w.builds = 0;
   w.band_build = -1;
+  w.ppic_build = -1;
   w.pair_cap = pair_capacity;
   const int64_t P = pair_capacity, Cc = cell_capacity, Tc = nt_capacity, Vc = nv_capacity;
   void** reg = o->buffers;
@@ -264,8 +265,10 @@ ftc_status ftc_ppic_curvature(const ftc_cells* cells, const ftc_grid* grid, cons
       return FTC_EINVAL;
   }
   if (!on_device(cells)) return FTC_EINVAL;
-  return hip_status(ftc::launch_ppic(cells, to_mesh(mesh), p, kappa, nx, ny, nz, coeff, cell_status, diag,
-                                     (hipStream_t)stream));
+  const ftc_status st = hip_status(
+      ftc::launch_ppic(cells, to_mesh(mesh), p, kappa, nx, ny, nz, coeff, cell_status, diag, (hipStream_t)stream));
+  cells->ppic_build = st == FTC_OK ? cells->builds : -1;
+  return st;
 }
 
 ftc_status ftc_csf_force(const ftc_cells* cells, const ftc_grid* grid, const double* alpha_dense, const double* kappa,
@@ -290,6 +293,14 @@ ftc_status ftc_csf_force_band(ftc_cells* cells, const ftc_grid* grid, const doub
                                                         (hipStream_t)stream));
   if (st == FTC_OK) cells->band_build = cells->builds;
   return st;
+}
+
+ftc_status ftc_paraboloid_volume_fraction(const ftc_cells* cells, const ftc_grid* grid, const double* coeff,
+                                          double* alpha_paraboloid, void* stream) {
+  if (!cells || !grid_valid(grid) || !same_grid(cells->grid, grid) || !coeff || !alpha_paraboloid)
+    return FTC_EINVAL;
+  if (!on_device(cells) || cells->builds == 0 || cells->ppic_build != cells->builds) return FTC_EINVAL;
+  return hip_status(ftc::launch_paraboloid_alpha(cells, coeff, alpha_paraboloid, (hipStream_t)stream));
 }
 
 ftc_status ftc_surface_tension_flux(ftc_cells* cells, const ftc_grid* grid, const double* alpha_dense,
@@ -375,6 +386,7 @@ ftc_status ftc_learned_curvature(const ftc_cells* cells, const ftc_grid* grid, c
       return FTC_EINVAL;
   }
   if (!on_device(cells)) return FTC_EINVAL;
+  cells->ppic_build = -1;  // PPIC runs for the fallback cells only
   return hip_status(ftc::launch_surrogate(cells, to_mesh(mesh), alpha_dense, theta, (float)bound, p, kappa, nx, ny,
                                           nz, spread, cell_status, d_n_fallback, (hipStream_t)stream));
 }

@@ -46,6 +46,7 @@ struct ftc_cells {
   int32_t built_nv, built_nt;  // front sizes of the last build (-1 before the first)
   int64_t builds;      // builds enqueued so far
   int64_t band_build;  // value of `builds` when the band was last listed (-1: never)
+  mutable int64_t ppic_build;  // value of `builds` at the last plain PPIC call (-1: none since)
   int64_t pair_cap;
   int64_t queue_cap;  // candidates queued for full clipping (>= pair_cap)
 
@@ -192,6 +193,7 @@ hipError_t launch_csf(const ftc_cells* ws, const double* alpha, const double* ka
 hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const double* kappa, const double* nx,
                            const double* ny, const double* nz, double sigma, int32_t band_cap, int32_t* band_ids,
                            double* kappa_band, double* fx, double* fy, double* fz, int32_t* n_band, hipStream_t s);
+hipError_t launch_paraboloid_alpha(const ftc_cells* ws, const double* coeff, double* alpha_out, hipStream_t s);
 hipError_t launch_face_flux(const ftc_cells* ws, const double* alpha, const double* kappa, int32_t band_cap,
                             const int32_t* band_ids, const double* kappa_band, const int32_t* n_band, double rho_a,
                             double rho_b, double sigma, double* flux_if, double* flux_band, hipStream_t s);
