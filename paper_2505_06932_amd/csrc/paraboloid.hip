@@ -25,56 +25,67 @@
 namespace ftc {
 namespace {
 
-constexpr int kT = 64;         // one wavefront per workgroup and per cell
-constexpr int kQ = 16;         // Gauss nodes per xi interval
-constexpr int kEvents = 38;    // 8 corners + 6 planes x (1 tangency + 4 edges)
-constexpr int kSlots = 80;     // 2 values per event, the two ends, padding
-constexpr int kEta = 32;       // eta breakpoints per G evaluation (26 used)
+constexpr int kT = 64;       // one wavefront per workgroup and per cell
+constexpr int kQ = 16;       // Gauss nodes per xi interval
+constexpr int kEvents = 26;  // 8 corners + 12 edges + 6 face tangencies
+constexpr int kSlots = 56;   // 2 values per event, the two ends, padding
+constexpr int kEta = 24;     // eta breakpoints per G evaluation
 
 struct Nodes {
   double tau[kQ], omega[kQ];  // xi = u0 + (u1 - u0) tau, weight (u1 - u0) omega
 };
 
-// zeta = c0 + cx xi + ce eta: one face plane of the cube in the local frame
-struct Line {
-  double c0, cx, ce;
+// The cell's paraboloid and cube in its local frame, cell units.  The two
+// faces x_k = -+1/2 of axis k (n_k != 0) are the planes
+// zeta = c0 + cx xi + ce eta with the same cx, ce: lo the one below the other
+// along n, hi the one above.
+struct Local {
+  double b[6];  // zeta = b0 + b1 xi + b2 eta + b3 xi^2 + b4 xi eta + b5 eta^2
+  double lo[3], hi[3], cx[3], ce[3];
+  double t1[3], t2[3], n[3];
+  double inv_dce[3];  // 1 / (ce_j - ce_k) for the axis pairs (0,1), (0,2), (1,2); 0 if parallel
+  int has;            // bit k: n_k != 0
 };
 
-// The cell's paraboloid and cube in its local frame, cell units.
-struct Local {
-  double b[6];        // zeta = b0 + b1 xi + b2 eta + b3 xi^2 + b4 xi eta + b5 eta^2
-  Line lo[3], hi[3];  // lower / upper face plane of axis k (where n_k != 0)
-  bool has[3];        // n_k != 0
-  double s1[3], s2[3];  // axis k with n_k == 0: the slab -1/2 <= s1 xi + s2 eta <= 1/2
-  double t1[3];
-};
+__device__ inline bool has_axis(const Local& L, int k) { return (L.has >> k) & 1; }
 
 __device__ inline Local make_local(const double n[3], const double a[6], double h) {
   Local L;
   const double sg = copysign(1.0, n[2]);
   const double fa = -1.0 / (sg + n[2]);
   const double fb = n[0] * n[1] * fa;
-  const double t1[3] = {1.0 + sg * n[0] * n[0] * fa, sg * fb, -sg * n[0]};
-  const double t2[3] = {fb, sg + n[1] * n[1] * fa, -n[1]};
+  L.t1[0] = 1.0 + sg * n[0] * n[0] * fa;
+  L.t1[1] = sg * fb;
+  L.t1[2] = -sg * n[0];
+  L.t2[0] = fb;
+  L.t2[1] = sg + n[1] * n[1] * fa;
+  L.t2[2] = -n[1];
   L.b[0] = a[0] / h;
   L.b[1] = a[1];
   L.b[2] = a[2];
   L.b[3] = a[3] * h;
   L.b[4] = a[4] * h;
   L.b[5] = a[5] * h;
+  L.has = 0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    L.t1[k] = t1[k];
-    L.has[k] = n[k] != 0.0;
-    L.s1[k] = t1[k];
-    L.s2[k] = t2[k];
-    // face x_k = -+1/2: xi t1_k + eta t2_k + zeta n_k = w
-    const double inv = L.has[k] ? 1.0 / n[k] : 0.0;
-    const Line m = {-0.5 * inv, -t1[k] * inv, -t2[k] * inv};
-    const Line p = {0.5 * inv, -t1[k] * inv, -t2[k] * inv};
-    L.lo[k] = n[k] > 0.0 ? m : p;
-    L.hi[k] = n[k] > 0.0 ? p : m;
+    L.n[k] = n[k];
+    // face x_k = w: xi t1_k + eta t2_k + zeta n_k = w
+    const bool hk = n[k] != 0.0;
+    L.has |= hk ? 1 << k : 0;
+    const double inv = hk ? 1.0 / n[k] : 0.0;
+    L.cx[k] = -L.t1[k] * inv;
+    L.ce[k] = -L.t2[k] * inv;
+    L.lo[k] = -0.5 * fabs(inv);
+    L.hi[k] = 0.5 * fabs(inv);
   }
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = j + 1; k < 3; ++k) {
+      const double d = L.ce[j] - L.ce[k];
+      L.inv_dce[j + k - 1] = (has_axis(L, j) && has_axis(L, k) && d != 0.0) ? 1.0 / d : 0.0;
+    }
   return L;
 }
 
@@ -104,73 +115,65 @@ __device__ double eta_integral(const Local& L, double xi) {
   double emin = -1.0, emax = 1.0;  // |eta| <= sqrt(3)/2 inside the cube
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    if (L.has[k]) continue;
-    if (L.s2[k] == 0.0) {
-      if (fabs(L.s1[k] * xi) > 0.5) return 0.0;
+    if (has_axis(L, k)) continue;
+    // n_k == 0: the slab -1/2 <= t1_k xi + t2_k eta <= 1/2 bounds eta (or xi)
+    if (L.t2[k] == 0.0) {
+      if (fabs(L.t1[k] * xi) > 0.5) return 0.0;
     } else {
-      const double r0 = (-0.5 - L.s1[k] * xi) / L.s2[k], r1 = (0.5 - L.s1[k] * xi) / L.s2[k];
+      const double r0 = (-0.5 - L.t1[k] * xi) / L.t2[k], r1 = (0.5 - L.t1[k] * xi) / L.t2[k];
       emin = fmax(emin, fmin(r0, r1));
       emax = fmin(emax, fmax(r0, r1));
     }
   }
   if (!(emax > emin)) return 0.0;
-  double la[3], le[3], ha[3], he[3];
+  // the face planes at this xi: zeta = a + ce eta
+  double la[3], ha[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    la[k] = L.lo[k].c0 + L.lo[k].cx * xi;
-    le[k] = L.lo[k].ce;
-    ha[k] = L.hi[k].c0 + L.hi[k].cx * xi;
-    he[k] = L.hi[k].ce;
+    const double base = L.cx[k] * xi;
+    la[k] = L.lo[k] + base;
+    ha[k] = L.hi[k] + base;
   }
   const double q2 = L.b[5], q1 = L.b[2] + L.b[4] * xi, q0 = L.b[0] + (L.b[1] + L.b[3] * xi) * xi;
-  // candidate breakpoints, each clamped into [emin, emax]; absent ones (NaN)
-  // go to emax, where they bound empty intervals
+  // breakpoints, each clamped into [emin, emax]; absent ones (NaN) go to emax
   double s[kEta];
   auto clampe = [&](double v) { return (v >= emin && v <= emax) ? v : (v < emin ? emin : emax); };
-#pragma unroll
-  for (int i = 0; i < kEta; ++i) s[i] = emax;
-  // slots 0..11: crossings of the planes of two different axes
+  // slots 0..11: where the faces of two different axes cross
 #pragma unroll
   for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int k = j + 1; k < 3; ++k)
+    for (int k = j + 1; k < 3; ++k) {
+      const double inv = L.inv_dce[j + k - 1];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const double aj = (u & 1) ? ha[j] : la[j], ej = (u & 1) ? he[j] : le[j];
-        const double ak = (u & 2) ? ha[k] : la[k], ek = (u & 2) ? he[k] : le[k];
-        const double v = (L.has[j] && L.has[k] && ej != ek) ? (ak - aj) / (ej - ek) : NAN;
-        s[4 * (j + k - 1) + u] = clampe(v);
+        const double aj = (u & 1) ? ha[j] : la[j], ak = (u & 2) ? ha[k] : la[k];
+        s[4 * (j + k - 1) + u] = clampe(inv != 0.0 ? (ak - aj) * inv : NAN);
       }
-  // slots 12..23: roots of P = plane; slot 24: emin
+    }
+  // slots 12..23: where the paraboloid meets a face
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       double r0 = NAN, r1 = NAN;
-      if (L.has[k]) roots2(q2, q1 - (u ? he[k] : le[k]), q0 - (u ? ha[k] : la[k]), r0, r1);
+      if (has_axis(L, k)) roots2(q2, q1 - L.ce[k], q0 - (u ? ha[k] : la[k]), r0, r1);
       s[12 + 4 * k + 2 * u] = clampe(r0);
       s[13 + 4 * k + 2 * u] = clampe(r1);
     }
-  s[24] = emin;
-  // bitonic sort of the 32 values, ascending
+  // Batcher's odd-even merge sort network, ascending
 #pragma unroll
-  for (int size = 2; size <= kEta; size <<= 1)
+  for (int p = 1; p < kEta; p <<= 1)
 #pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1)
+    for (int k = p; k >= 1; k >>= 1)
 #pragma unroll
-      for (int i = 0; i < kEta; ++i) {
-        const int j = i ^ stride;
-        if (j > i) {
-          if ((i & size) == 0)
-            cswap(s[i], s[j]);
-          else
-            cswap(s[j], s[i]);
-        }
-      }
+      for (int j = k % p; j + k < kEta; j += 2 * k)
+#pragma unroll
+        for (int i = 0; i < k; ++i)
+          if (i + j + k < kEta && (i + j) / (2 * p) == (i + j + k) / (2 * p)) cswap(s[i + j], s[i + j + k]);
   double g = 0.0;
 #pragma unroll
-  for (int i = 0; i + 1 < kEta; ++i) {
-    const double a = s[i], c = s[i + 1];
+  for (int i = 0; i <= kEta; ++i) {
+    const double a = i == 0 ? emin : s[i - 1], c = i == kEta ? emax : s[i];
     if (!(c > a)) continue;
     const double m = 0.5 * (a + c), r = 0.5 * (c - a);
     // the active lower and upper faces are the highest and lowest at the
@@ -178,9 +181,9 @@ __device__ double eta_integral(const Local& L, double xi) {
     double zl = -INFINITY, zh = INFINITY;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      if (!L.has[k]) continue;
-      zl = fmax(zl, la[k] + le[k] * m);
-      zh = fmin(zh, ha[k] + he[k] * m);
+      if (!has_axis(L, k)) continue;
+      zl = fmax(zl, la[k] + L.ce[k] * m);
+      zh = fmin(zh, ha[k] + L.ce[k] * m);
     }
     if (!(zl < zh)) continue;
     const double pm = (q2 * m + q1) * m + q0;
@@ -194,18 +197,26 @@ __device__ double eta_integral(const Local& L, double xi) {
   return g;
 }
 
-// The conic P = plane p meets the line eta = al + be xi: its xi.
-__device__ inline void conic_line(const Local& L, const Line& p, double al, double be, double& r0, double& r1) {
+// xi of the points where the curve P = zeta_face of face plane (c0, cx, ce)
+// meets the line eta = al + be xi.
+__device__ inline void conic_line(const Local& L, double c0, double cx, double ce, double al, double be, double& r0,
+                                  double& r1) {
   const double A = L.b[3], B = L.b[4], C = L.b[5];
-  const double D = L.b[1] - p.cx, E = L.b[2] - p.ce, F = L.b[0] - p.c0;
+  const double D = L.b[1] - cx, E = L.b[2] - ce, F = L.b[0] - c0;
   roots2(A + B * be + C * be * be, B * al + 2.0 * C * al * be + D + E * be, C * al * al + E * al + F, r0, r1);
 }
 
-// Event `e` of the xi breakpoints: e < 8 a projected corner; otherwise plane
-// p = (e - 8) / 5 (lo_0, lo_1, lo_2, hi_0, hi_1, hi_2) and kind (e - 8) % 5:
-// 0 the tangency of its conic along eta, 1..4 its conic against the four
-// face lines of the two other axes (their planes' edge lines, or the slab
-// boundaries where n_k == 0).
+// Coordinate w of face lo (hi) of axis k: the face the lower (upper) plane lies in.
+__device__ inline double face_w(const Local& L, int k, bool upper) {
+  return (L.n[k] > 0.0) == upper ? 0.5 : -0.5;
+}
+
+// Event e of the xi breakpoints, at most two values (NaN when absent):
+//   e < 8: projected corner e;
+//   8 <= e < 20: edge (j, k, u) (axis pair j < k, u selects the faces): where
+//     the paraboloid crosses that cube edge, kept only on the edge segment;
+//   20 <= e < 26: face plane (k, upper) = (e - 20) % 3, (e - 20) / 3: where the
+//     curve P = plane has a tangent along eta, kept only inside that face.
 __device__ inline void xi_event(const Local& L, int e, double& v0, double& v1) {
   v0 = NAN;
   v1 = NAN;
@@ -214,25 +225,65 @@ __device__ inline void xi_event(const Local& L, int e, double& v0, double& v1) {
     v0 = L.t1[0] * x + L.t1[1] * y + L.t1[2] * z;
     return;
   }
-  const int q = e - 8, pi = q / 5, kind = q % 5, kp = pi % 3;
-  if (!L.has[kp]) return;
-  const Line p = pi < 3 ? L.lo[kp] : L.hi[kp];
-  if (kind == 0) {
-    const double A = L.b[3], B = L.b[4], C = L.b[5];
-    const double D = L.b[1] - p.cx, E = L.b[2] - p.ce, F = L.b[0] - p.c0;
-    roots2(B * B - 4.0 * C * A, 2.0 * B * E - 4.0 * C * D, E * E - 4.0 * C * F, v0, v1);
+  if (e < 20) {
+    const int q = e - 8, pair = q / 4, u = q % 4;
+    const int j = pair == 2 ? 1 : 0, k = pair == 0 ? 1 : 2, i = 3 - j - k;
+    const bool uj = u & 1, uk = (u & 2) != 0;
+    const double wj = face_w(L, j, uj), wk = face_w(L, k, uk);
+    const bool hj = has_axis(L, j), hk = has_axis(L, k);
+    if (hj && hk) {
+      const double inv = L.inv_dce[pair];
+      if (inv == 0.0) return;  // the edge projects onto xi = const: its ends are corners
+      const double cj = uj ? L.hi[j] : L.lo[j], ck = uk ? L.hi[k] : L.lo[k];
+      // the edge line: c_j + cx_j xi + ce_j eta = c_k + cx_k xi + ce_k eta
+      const double al = (ck - cj) * inv, be = (L.cx[k] - L.cx[j]) * inv;
+      // the crossing lies on both faces' curves; the face of the axis with
+      // the larger |n| has the well-conditioned one (a face almost parallel
+      // to n has coefficients of order 1/n_k)
+      if (fabs(L.n[j]) >= fabs(L.n[k]))
+        conic_line(L, cj, L.cx[j], L.ce[j], al, be, v0, v1);
+      else
+        conic_line(L, ck, L.cx[k], L.ce[k], al, be, v0, v1);
+    } else if (hj || hk) {
+      // one face is a slab boundary t1_m xi + t2_m eta = w_m of an axis with n_m == 0
+      const int f = hj ? j : k, m = hj ? k : j;
+      const double wm = hj ? wk : wj;
+      if (L.t2[m] == 0.0) return;  // a line xi = const: its ends are corners
+      const double cf = (hj ? uj : uk) ? L.hi[f] : L.lo[f];
+      conic_line(L, cf, L.cx[f], L.ce[f], wm / L.t2[m], -L.t1[m] / L.t2[m], v0, v1);
+    } else {
+      return;  // an edge along n: a point in projection, a corner
+    }
+    // keep the crossings on the edge segment x_j = wj, x_k = wk, |x_i| <= 1/2
+    const double c = L.t1[j] * wj + L.t1[k] * wk, d = 0.5 * fabs(L.t1[i]);
+    if (!(v0 >= c - d && v0 <= c + d)) v0 = NAN;
+    if (!(v1 >= c - d && v1 <= c + d)) v1 = NAN;
     return;
   }
-  const int ko = (kp + 1 + (kind - 1) / 2) % 3, side = (kind - 1) & 1;
-  if (L.has[ko]) {
-    const Line o = side ? L.hi[ko] : L.lo[ko];
-    const double dce = p.ce - o.ce;
-    if (dce == 0.0) return;  // the edge line is xi = const: its ends are corners
-    conic_line(L, p, -(p.c0 - o.c0) / dce, -(p.cx - o.cx) / dce, v0, v1);
-  } else {
-    if (L.s2[ko] == 0.0) return;  // the slab bounds xi alone: corners
-    const double w = side ? 0.5 : -0.5;
-    conic_line(L, p, w / L.s2[ko], -L.s1[ko] / L.s2[ko], v0, v1);
+  const int f = (e - 20) % 3;
+  const bool up = (e - 20) >= 3;
+  if (!has_axis(L, f)) return;
+  const double c0 = up ? L.hi[f] : L.lo[f];
+  const double A = L.b[3], B = L.b[4], C = L.b[5];
+  const double D = L.b[1] - L.cx[f], E = L.b[2] - L.ce[f], F = L.b[0] - c0;
+  roots2(B * B - 4.0 * C * A, 2.0 * B * E - 4.0 * C * D, E * E - 4.0 * C * F, v0, v1);
+  if (C == 0.0) return;  // no tangent along eta: keep the candidates as they are
+  // keep a tangency only inside its face: the other two coordinates within 1/2
+  double* v[2] = {&v0, &v1};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const double xi = *v[q];
+    if (isnan(xi)) continue;
+    const double eta = -(B * xi + E) / (2.0 * C);
+    const double zeta = c0 + L.cx[f] * xi + L.ce[f] * eta;
+    bool inside = true;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      if (m == f) continue;
+      const double x = L.t1[m] * xi + L.t2[m] * eta + L.n[m] * zeta;
+      inside = inside && fabs(x) <= 0.5 + 1e-12;
+    }
+    if (!inside) *v[q] = NAN;
   }
 }
 
@@ -265,18 +316,18 @@ __global__ __launch_bounds__(kT) void k_paraboloid_alpha(const double* fit, cons
       ev[2 * lane + 1] = (v1 > xa && v1 < xb) ? v1 : INFINITY;
     } else if (lane < kEvents + 2) {
       ev[2 * kEvents + (lane - kEvents)] = lane == kEvents ? xa : xb;
-    } else if (lane < kEvents + 4) {
+    } else if (2 * kEvents + (lane - kEvents) < kSlots) {
       ev[2 * kEvents + (lane - kEvents)] = INFINITY;
     }
     __syncthreads();
     // rank sort of the finite entries (ties by slot)
     int nf = 0;
-    for (int i = lane; i < kSlots; i += kT) {
-      const double v = ev[i];
+    if (lane < kSlots) {
+      const double v = ev[lane];
       int r = 0;
       for (int j = 0; j < kSlots; ++j) {
         const double u = ev[j];
-        r += (u < v || (u == v && j < i)) ? 1 : 0;
+        r += (u < v || (u == v && j < lane)) ? 1 : 0;
       }
       if (v < INFINITY) xs[r] = v;
     }
