@@ -188,3 +188,150 @@ def alpha_cells(frame_normals, coeffs, h, tol: float = TOL):
         t1, t2 = duff_frame(nv)
         out[i] = alpha_unit(nv, t1, t2, cell_units(co, h), tol)
     return out
+
+
+# ----------------------------------------------------------------------------
+# Surface integrals over the part of the paraboloid inside the cell (paper
+# section 3.2: the cell's curvature and normal are integrated over the
+# surface of the paraboloid within the cell).
+#
+# The surface is the graph zeta = P(xi, eta); with W = sqrt(1 + P_xi^2 +
+# P_eta^2), dA = W dxi deta, the unit normal (pointing away from the liquid,
+# +zeta side) is (-P_xi, -P_eta, 1) / W in the frame, and the mean curvature
+# (kappa = 2H, positive for a sphere seen from outside) is
+#   kappa = -[(1 + P_eta^2) P_xixi - 2 P_xi P_eta P_xieta + (1 + P_xi^2) P_etaeta] / W^3.
+# Over the set R of (xi, eta) whose surface point lies in the cube:
+#   area = int_R W,  K = int_R kappa W,  N = int_R (-P_xi, -P_eta, 1);
+# kappa_cell = K / area, normal_cell = N / |N| (in world axes).  The integrals
+# are nested adaptive quadratures over the disc |(xi, eta)| <= sqrt(3)/2 that
+# holds R; the inner one is told the eta at which the surface point crosses a
+# face plane (roots of quadratics), the outer one the xi at which the surface
+# crosses a cube edge or its curve on a face turns along eta.
+
+def _surface_kinks_xi(n, t1, t2, b):
+    """xi where the slice R cap {xi = const} changes its structure: the surface
+    crossing one of the 12 cube edges, and points of its curve on a face
+    plane with a tangent along eta (where the curve's tangent has no
+    component along t1)."""
+    Q = _Quadric(n, t1, t2, b)
+    M, g, f0 = Q.M, Q.g, Q.f0
+    t1 = np.asarray(t1, dtype=np.float64)
+    out = []
+    # edges: x = e0 + s d, d a unit axis, |s| <= 1/2; F quadratic in s
+    for ax in range(3):
+        d = np.zeros(3)
+        d[ax] = 1.0
+        o1, o2 = [k for k in range(3) if k != ax]
+        for w1 in (-0.5, 0.5):
+            for w2 in (-0.5, 0.5):
+                e0 = np.zeros(3)
+                e0[o1], e0[o2] = w1, w2
+                qa = d @ M @ d
+                qb = 2.0 * (e0 @ M @ d) + g @ d
+                qc = e0 @ M @ e0 + g @ e0 + f0
+                for s in _roots(qa, qb, qc):
+                    if -0.5 <= s <= 0.5:
+                        out.append(float(t1 @ (e0 + s * d)))
+    # face curves x_k = w: F = 0 and t1 . (grad F x e_k) = 0 (grad F = 2 M x + g),
+    # the second linear in x: c . x + c0 = 0 with c = 2 M^T (e_k x t1) ... written out:
+    for k in range(3):
+        ek = np.zeros(3)
+        ek[k] = 1.0
+        u = np.cross(ek, t1)  # t1 . (v x e_k) = v . (e_k x t1)
+        c = 2.0 * M @ u
+        c0 = g @ u
+        o1, o2 = [m for m in range(3) if m != k]
+        for w in (-0.5, 0.5):
+            # on the face: x = w e_k + y e_o1 + z e_o2; linear: c_o1 y + c_o2 z + (c_k w + c0) = 0
+            A1, A2, A0 = c[o1], c[o2], c[k] * w + c0
+            if A2 != 0.0:
+                # z = al + be y
+                al, be = -A0 / A2, -A1 / A2
+                base = w * ek + al * np.eye(3)[o2]
+                dirv = np.eye(3)[o1] + be * np.eye(3)[o2]
+            elif A1 != 0.0:
+                base = w * ek + (-A0 / A1) * np.eye(3)[o1]
+                dirv = np.eye(3)[o2]
+            else:
+                continue
+            qa = dirv @ M @ dirv
+            qb = 2.0 * (base @ M @ dirv) + g @ dirv
+            qc = base @ M @ base + g @ base + f0
+            for s in _roots(qa, qb, qc):
+                x = base + s * dirv
+                if abs(x[o1]) <= 0.5 and abs(x[o2]) <= 0.5:
+                    out.append(float(t1 @ x))
+    R = np.sqrt(3.0) / 2.0
+    return sorted(v for v in out if -R < v < R)
+
+
+def surface_unit(n, t1, t2, b, tol: float = 1e-13):
+    """(area, K, N_local[3]) over the part of the paraboloid in the cube
+    [-1/2, 1/2]^3, cell units, frame (t1, t2, n)."""
+    b0, b1, b2, b3, b4, b5 = (float(v) for v in b)
+    n, t1, t2 = (np.asarray(v, dtype=np.float64) for v in (n, t1, t2))
+    R = np.sqrt(3.0) / 2.0
+
+    def inside(xi, eta):
+        z = b0 + b1 * xi + b2 * eta + b3 * xi * xi + b4 * xi * eta + b5 * eta * eta
+        x = xi * t1 + eta * t2 + z * n
+        return bool(np.all(np.abs(x) <= 0.5))
+
+    def eta_kinks(xi):
+        # x_k = xi t1_k + eta t2_k + P n_k = w: quadratic in eta
+        out = []
+        for k in range(3):
+            for w in (-0.5, 0.5):
+                qa = b5 * n[k]
+                qb = t2[k] + (b2 + b4 * xi) * n[k]
+                qc = xi * t1[k] + (b0 + b1 * xi + b3 * xi * xi) * n[k] - w
+                out += _roots(qa, qb, qc)
+        return sorted(v for v in out if -R < v < R)
+
+    def integrand(xi, eta, what):
+        px = b1 + 2 * b3 * xi + b4 * eta
+        pe = b2 + b4 * xi + 2 * b5 * eta
+        if what == 0:
+            return np.sqrt(1 + px * px + pe * pe)
+        if what == 1:
+            w2 = 1 + px * px + pe * pe
+            return -((1 + pe * pe) * 2 * b3 - 2 * px * pe * b4 + (1 + px * px) * 2 * b5) / w2
+        return (-px, -pe, 1.0)[what - 2]
+
+    def slice_integral(xi, what):
+        cuts = [-R] + eta_kinks(xi) + [R]
+        s = 0.0
+        for a, c in zip(cuts[:-1], cuts[1:]):
+            if c <= a or not inside(xi, 0.5 * (a + c)):
+                continue
+            s += integrate.quad(lambda e: integrand(xi, e, what), a, c, epsabs=tol, epsrel=tol, limit=200)[0]
+        return s
+
+    pts = _surface_kinks_xi(n, t1, t2, b)
+    vals = []
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", integrate.IntegrationWarning)
+        for what in range(5):
+            vals.append(integrate.quad(lambda x: slice_integral(x, what), -R, R, points=pts or None, epsabs=tol,
+                                       epsrel=tol, limit=400)[0])
+    return vals[0], vals[1], np.array(vals[2:])
+
+
+def surface_cells(frame_normals, coeffs, h, tol: float = 1e-13):
+    """(kappa_cell [n], normal_cell [n, 3]) of each listed cell: the
+    area-weighted mean curvature (world units) and the normalised integral of
+    the unit normal (world axes) over its paraboloid inside the cell; NaN
+    where the paraboloid misses the cell."""
+    kap = np.empty(len(coeffs))
+    nrm = np.empty((len(coeffs), 3))
+    for i, (nv, co) in enumerate(zip(np.asarray(frame_normals), np.asarray(coeffs))):
+        t1, t2 = duff_frame(nv)
+        area, K, N = surface_unit(nv, t1, t2, cell_units(co, h), tol)
+        if area > 0.0:
+            kap[i] = K / area / h
+            Nw = N[0] * t1 + N[1] * t2 + N[2] * np.asarray(nv)
+            nrm[i] = Nw / np.linalg.norm(Nw)
+        else:
+            kap[i] = np.nan
+            nrm[i] = np.nan
+    return kap, nrm
