@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="choose the launch shapes with the autotuner (whole-step graph timings) before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--paraboloid", action="store_true",
+                    help="also time the volume fraction under the fitted paraboloid (outside the step)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -169,6 +171,25 @@ def main():
     log("[bench] kernel ms: " + ", ".join(f"{k}={v * 1e3:.1f}us" for k, v in kern_ms.items()))
 
     res = step.results()
+    para = None
+    if args.paraboloid and not args.learned:
+        # alpha under each cell's PPIC paraboloid, after one plain step
+        step.run()
+        a_par = torch.empty_like(step.alpha_if)
+        ftc.paraboloid_cell(step.cells, grid, step.coeff, a_par)
+        torch.cuda.synchronize()
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record()
+        for _ in range(K):
+            ftc.paraboloid_cell(step.cells, grid, step.coeff, a_par)
+        p1.record()
+        torch.cuda.synchronize()
+        pms = p0.elapsed_time(p1) / K
+        ok = res["status"] == 0
+        dev = np.abs(a_par.cpu().numpy()[:n_if][ok] - res["alpha_if"][ok])
+        para = {"ms_per_call": pms, "cells_per_s": n_if / (pms * 1e-3),
+                "max_abs_vs_polyhedral": float(dev.max()), "median_abs_vs_polyhedral": float(np.median(dev))}
+        log(f"[bench] paraboloid alpha: {pms * 1e3:.1f} us per call")
     if args.learned:
         roofline = learned_roofline(res, kern_ms, n_if)
     else:
@@ -190,6 +211,7 @@ def main():
         "gpu_ms_per_step_events": gpu_ms / K,
         "kernel_ms": kern_ms,
         "roofline": roofline,
+        **({"paraboloid_alpha": para} if para else {}),
     }
 
     # ---------------------------------------------------------- CPU oracle

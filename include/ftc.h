@@ -173,21 +173,28 @@ ftc_status ftc_ppic_curvature(const ftc_cells* cells, const ftc_grid* grid, cons
                               double* nz, double* coeff, int32_t* cell_status, int32_t* diag,
                               void* stream);
 
-/* Volume fraction under the fitted paraboloid (paper section 3.2: alpha is
-   the volume of the cell below the local paraboloid over the cell volume),
-   for every interfacial cell: the paraboloid zeta = a1 + a2 xi + a3 eta +
-   a4 xi^2 + a5 xi eta + a6 eta^2 of the last ftc_ppic_curvature on this
-   workspace, in its frame (t1, t2, n) with origin at the cell centre, where
-   n is the frame normal of that call (kept in the workspace) and the liquid
-   lies below the surface (zeta smaller).  coeff [6][cell_capacity] as that
-   call wrote it; alpha_paraboloid [cell_capacity], cell-list order.  The
-   integral over the cell is exact in one tangential direction and a Gauss
-   rule between the exact breakpoints in the other (error about 1e-14); a
-   cell whose fit failed (NaN coefficients) gets NaN.  FTC_EINVAL unless
-   ftc_ppic_curvature (not the learned curvature) ran after the last
-   ftc_build_cell_lists. */
-ftc_status ftc_paraboloid_volume_fraction(const ftc_cells* cells, const ftc_grid* grid, const double* coeff,
-                                          double* alpha_paraboloid, void* stream);
+/* The cell quantities of the fitted paraboloid (paper section 3.2): the
+   volume fraction alpha = |cell below the paraboloid| / |cell|, and the
+   curvature and normal integrated over the part of the paraboloid inside
+   the cell.  For every interfacial cell, the paraboloid is zeta = a1 + a2 xi
+   + a3 eta + a4 xi^2 + a5 xi eta + a6 eta^2 of the last ftc_ppic_curvature
+   on this workspace, in its frame (t1, t2, n) with origin at the cell
+   centre, n the frame normal of that call (kept in the workspace); the
+   liquid lies below the surface (zeta smaller).
+   coeff [6][cell_capacity] as that call wrote it.  Outputs, cell-list order:
+   alpha_paraboloid [cell_capacity]; kappa_cell [cell_capacity] or NULL, the
+   area-weighted mean of kappa = 2H over the surface inside the cell (same
+   sign convention as ftc_ppic_curvature); normal_cell [3][cell_capacity] or
+   NULL, the normalised integral of the unit normal (pointing out of the
+   liquid) over that surface.  The volume is exact in one tangential
+   direction and a Gauss rule between exact breakpoints in the other (about
+   1e-14); the surface integrals add a Gauss rule between the breakpoints in
+   the first.  NaN for a cell whose fit failed, and kappa_cell and
+   normal_cell NaN where the paraboloid does not cross the cell.
+   FTC_EINVAL unless ftc_ppic_curvature (not the learned curvature) ran after
+   the last ftc_build_cell_lists. */
+ftc_status ftc_paraboloid_cell(const ftc_cells* cells, const ftc_grid* grid, const double* coeff,
+                               double* alpha_paraboloid, double* kappa_cell, double* normal_cell, void* stream);
 
 /* Continuum surface force (paper section 3.3, Eq. csf): S = sigma kappa
    grad(alpha) on the interfacial cells only, grad(alpha) by central

@@ -295,12 +295,13 @@ ftc_status ftc_csf_force_band(ftc_cells* cells, const ftc_grid* grid, const doub
   return st;
 }
 
-ftc_status ftc_paraboloid_volume_fraction(const ftc_cells* cells, const ftc_grid* grid, const double* coeff,
-                                          double* alpha_paraboloid, void* stream) {
+ftc_status ftc_paraboloid_cell(const ftc_cells* cells, const ftc_grid* grid, const double* coeff,
+                               double* alpha_paraboloid, double* kappa_cell, double* normal_cell, void* stream) {
   if (!cells || !grid_valid(grid) || !same_grid(cells->grid, grid) || !coeff || !alpha_paraboloid)
     return FTC_EINVAL;
   if (!on_device(cells) || cells->builds == 0 || cells->ppic_build != cells->builds) return FTC_EINVAL;
-  return hip_status(ftc::launch_paraboloid_alpha(cells, coeff, alpha_paraboloid, (hipStream_t)stream));
+  return hip_status(
+      ftc::launch_paraboloid_cell(cells, coeff, alpha_paraboloid, kappa_cell, normal_cell, (hipStream_t)stream));
 }
 
 ftc_status ftc_surface_tension_flux(ftc_cells* cells, const ftc_grid* grid, const double* alpha_dense,

@@ -193,7 +193,8 @@ hipError_t launch_csf(const ftc_cells* ws, const double* alpha, const double* ka
 hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const double* kappa, const double* nx,
                            const double* ny, const double* nz, double sigma, int32_t band_cap, int32_t* band_ids,
                            double* kappa_band, double* fx, double* fy, double* fz, int32_t* n_band, hipStream_t s);
-hipError_t launch_paraboloid_alpha(const ftc_cells* ws, const double* coeff, double* alpha_out, hipStream_t s);
+hipError_t launch_paraboloid_cell(const ftc_cells* ws, const double* coeff, double* alpha_out, double* kappa_out,
+                                  double* normal_out, hipStream_t s);
 hipError_t launch_face_flux(const ftc_cells* ws, const double* alpha, const double* kappa, int32_t band_cap,
                             const int32_t* band_ids, const double* kappa_band, const int32_t* n_band, double rho_a,
                             double rho_b, double sigma, double* flux_if, double* flux_band, hipStream_t s);

@@ -16,6 +16,11 @@
 // a projected cube edge.  Between consecutive events the xi integral is a
 // 16-node Gauss-Legendre rule in theta with xi = u0 + (u1 - u0)(1 - cos
 // theta)/2, which absorbs the square-root behaviour of G at tangencies.
+// The surface integrals (area, curvature, normal over the part of the
+// paraboloid inside the cell) share the same xi rule: at each node the eta
+// intervals where the surface lies in the cube are those between the same
+// breakpoints, the normal integral is polynomial (exact) and the area and
+// curvature take an 8-node Gauss rule per interval.
 // One wavefront per cell: its lanes compute the events, rank-sort them in
 // LDS and share the quadrature nodes.
 #include <math.h>
@@ -31,8 +36,11 @@ constexpr int kEvents = 26;  // 8 corners + 12 edges + 6 face tangencies
 constexpr int kSlots = 56;   // 2 values per event, the two ends, padding
 constexpr int kEta = 24;     // eta breakpoints per G evaluation
 
+constexpr int kS = 8;        // Gauss nodes per eta interval of the surface integrals
+
 struct Nodes {
   double tau[kQ], omega[kQ];  // xi = u0 + (u1 - u0) tau, weight (u1 - u0) omega
+  double sx[kS], sw[kS];      // plain Gauss-Legendre on [0, 1]
 };
 
 // The cell's paraboloid and cube in its local frame, cell units.  The two
@@ -110,22 +118,29 @@ __device__ inline void cswap(double& a, double& b) {
   b = hi;
 }
 
-// G(xi): the exact eta integral of clamp(P - zeta_lo, 0, zeta_hi - zeta_lo).
-__device__ double eta_integral(const Local& L, double xi) {
+// The eta integrals at one xi: out[0] = G(xi), the exact integral of
+// clamp(P - zeta_lo, 0, zeta_hi - zeta_lo); with kSurf, over the eta where
+// the surface point lies in the cube, out[1] = int W, out[2] = int kappa W
+// (Gauss, smooth between the breakpoints) and out[3..5] = int (-P_xi, -P_eta,
+// 1) (exact), W = sqrt(1 + P_xi^2 + P_eta^2) and kappa = 2H.
+template <bool kSurf>
+__device__ void eta_integrals(const Local& L, const Nodes& N, double xi, double out[6]) {
+#pragma unroll
+  for (int q = 0; q < 6; ++q) out[q] = 0.0;
   double emin = -1.0, emax = 1.0;  // |eta| <= sqrt(3)/2 inside the cube
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (has_axis(L, k)) continue;
     // n_k == 0: the slab -1/2 <= t1_k xi + t2_k eta <= 1/2 bounds eta (or xi)
     if (L.t2[k] == 0.0) {
-      if (fabs(L.t1[k] * xi) > 0.5) return 0.0;
+      if (fabs(L.t1[k] * xi) > 0.5) return;
     } else {
       const double r0 = (-0.5 - L.t1[k] * xi) / L.t2[k], r1 = (0.5 - L.t1[k] * xi) / L.t2[k];
       emin = fmax(emin, fmin(r0, r1));
       emax = fmin(emax, fmax(r0, r1));
     }
   }
-  if (!(emax > emin)) return 0.0;
+  if (!(emax > emin)) return;
   // the face planes at this xi: zeta = a + ce eta
   double la[3], ha[3];
 #pragma unroll
@@ -170,7 +185,6 @@ __device__ double eta_integral(const Local& L, double xi) {
 #pragma unroll
         for (int i = 0; i < k; ++i)
           if (i + j + k < kEta && (i + j) / (2 * p) == (i + j + k) / (2 * p)) cswap(s[i + j], s[i + j + k]);
-  double g = 0.0;
 #pragma unroll
   for (int i = 0; i <= kEta; ++i) {
     const double a = i == 0 ? emin : s[i - 1], c = i == kEta ? emax : s[i];
@@ -189,12 +203,32 @@ __device__ double eta_integral(const Local& L, double xi) {
     const double pm = (q2 * m + q1) * m + q0;
     if (!(pm > zl)) continue;
     // over [m - r, m + r]: the integral of a polynomial f is 2r (f(m) + f2 r^2 / 3)
-    if (pm >= zh)
-      g += 2.0 * r * (zh - zl);
-    else
-      g += 2.0 * r * ((pm - zl) + q2 * r * r * (1.0 / 3.0));
+    if (pm >= zh) {
+      out[0] += 2.0 * r * (zh - zl);
+      continue;
+    }
+    out[0] += 2.0 * r * ((pm - zl) + q2 * r * r * (1.0 / 3.0));
+    if (kSurf) {
+      // the surface lies inside the cube on [a, c]
+      const double pxm = L.b[1] + 2.0 * L.b[3] * xi + L.b[4] * m;
+      const double pem = L.b[2] + L.b[4] * xi + 2.0 * L.b[5] * m;
+      out[3] -= 2.0 * r * pxm;
+      out[4] -= 2.0 * r * pem;
+      out[5] += 2.0 * r;
+      double sa = 0.0, sk = 0.0;
+#pragma unroll
+      for (int q = 0; q < kS; ++q) {
+        const double eta = a + (c - a) * N.sx[q];
+        const double px = L.b[1] + 2.0 * L.b[3] * xi + L.b[4] * eta;
+        const double pe = L.b[2] + L.b[4] * xi + 2.0 * L.b[5] * eta;
+        const double w2 = 1.0 + px * px + pe * pe;
+        sa += N.sw[q] * sqrt(w2);
+        sk -= N.sw[q] * ((1.0 + pe * pe) * 2.0 * L.b[3] - 2.0 * px * pe * L.b[4] + (1.0 + px * px) * 2.0 * L.b[5]) / w2;
+      }
+      out[1] += (c - a) * sa;
+      out[2] += (c - a) * sk;
+    }
   }
-  return g;
 }
 
 // xi of the points where the curve P = zeta_face of face plane (c0, cx, ce)
@@ -287,9 +321,10 @@ __device__ inline void xi_event(const Local& L, int e, double& v0, double& v1) {
   }
 }
 
-__global__ __launch_bounds__(kT) void k_paraboloid_alpha(const double* fit, const double* coeff, double h,
-                                                         const int32_t* counters, int32_t cell_cap, Nodes N,
-                                                         double* alpha_out) {
+template <bool kSurf>
+__global__ __launch_bounds__(kT) void k_paraboloid_cell(const double* fit, const double* coeff, double h,
+                                                        const int32_t* counters, int32_t cell_cap, Nodes N,
+                                                        double* alpha_out, double* kappa_out, double* normal_out) {
   __shared__ double ev[kSlots];
   __shared__ double xs[kSlots];
   const int lane = threadIdx.x;
@@ -333,16 +368,40 @@ __global__ __launch_bounds__(kT) void k_paraboloid_alpha(const double* fit, cons
     }
     for (int j = 0; j < kSlots; ++j) nf += ev[j] < INFINITY ? 1 : 0;
     __syncthreads();
-    double acc = 0.0;
+    constexpr int kOut = kSurf ? 6 : 1;
+    double acc[kOut];
+#pragma unroll
+    for (int q = 0; q < kOut; ++q) acc[q] = 0.0;
     const int nodes = (nf - 1) * kQ;
     for (int q = lane; q < nodes; q += kT) {
       const int i = q / kQ, k = q % kQ;
       const double u0 = xs[i], u1 = xs[i + 1];
-      if (u1 > u0) acc += (u1 - u0) * N.omega[k] * eta_integral(L, u0 + (u1 - u0) * N.tau[k]);
+      if (!(u1 > u0)) continue;
+      double g[6];
+      eta_integrals<kSurf>(L, N, u0 + (u1 - u0) * N.tau[k], g);
+      const double wq = (u1 - u0) * N.omega[k];
+#pragma unroll
+      for (int o = 0; o < kOut; ++o) acc[o] += wq * g[o];
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kT);
-    if (lane == 0) alpha_out[c] = acc;
+    for (int o = 0; o < kOut; ++o)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc[o] += __shfl_xor(acc[o], off, kT);
+    if (lane == 0) {
+      alpha_out[c] = acc[0];
+      if (kSurf) {
+        // area acc[1], int kappa W acc[2] (cell units: kappa h), normal integral acc[3..5] in the frame
+        if (kappa_out) kappa_out[c] = acc[1] > 0.0 ? acc[2] / acc[1] / h : NAN;
+        if (normal_out) {
+          double w[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) w[d] = acc[3] * L.t1[d] + acc[4] * L.t2[d] + acc[5] * L.n[d];
+          const double nl = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+#pragma unroll
+          for (int d = 0; d < 3; ++d) normal_out[d * cs + c] = nl > 0.0 ? w[d] / nl : NAN;
+        }
+      }
+    }
     __syncthreads();
   }
 }
@@ -378,15 +437,47 @@ Nodes make_nodes() {
     N.tau[i] = 0.5 * (1.0 - cos(th));
     N.omega[i] = w * (pi / 2.0) * sin(th) * 0.5;
   }
+  for (int i = 0; i < kS; ++i) {
+    double x = cos(pi * (i + 0.75) / (kS + 0.5)), dp = 1.0, p0 = 1.0, p1 = x;
+    for (int it = 0; it < 100; ++it) {
+      p0 = 1.0;
+      p1 = x;
+      for (int k = 2; k <= kS; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = kS * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    p0 = 1.0;
+    p1 = x;
+    for (int k = 2; k <= kS; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = kS * (x * p1 - p0) / (x * x - 1.0);
+    N.sx[i] = 0.5 * (x + 1.0);
+    N.sw[i] = 1.0 / ((1.0 - x * x) * dp * dp);  // half the weight on [-1, 1]
+  }
   return N;
 }
 
 }  // namespace
 
-hipError_t launch_paraboloid_alpha(const ftc_cells* ws, const double* coeff, double* alpha_out, hipStream_t s) {
+hipError_t launch_paraboloid_cell(const ftc_cells* ws, const double* coeff, double* alpha_out, double* kappa_out,
+                                  double* normal_out, hipStream_t s) {
   static const Nodes N = make_nodes();
-  hipLaunchKernelGGL(k_paraboloid_alpha, dim3(grid_blocks(ws->cell_cap, 1, 65535)), dim3(kT), 0, s, ws->fit, coeff,
-                     ws->grid.h, ws->counters, ws->cell_cap, N, alpha_out);
+  const dim3 grid(grid_blocks(ws->cell_cap, 1, 65535));
+  if (kappa_out || normal_out)
+    hipLaunchKernelGGL(k_paraboloid_cell<true>, grid, dim3(kT), 0, s, ws->fit, coeff, ws->grid.h, ws->counters,
+                       ws->cell_cap, N, alpha_out, kappa_out, normal_out);
+  else
+    hipLaunchKernelGGL(k_paraboloid_cell<false>, grid, dim3(kT), 0, s, ws->fit, coeff, ws->grid.h, ws->counters,
+                       ws->cell_cap, N, alpha_out, kappa_out, normal_out);
   return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ EXPORTED = ["ftc_cells_create", "ftc_cells_destroy", "ftc_build_cell_lists", "ft
             "ftc_csf_force_band", "ftc_advect_vertices_rk4", "ftc_curvature_features", "ftc_mlp_forward",
             "ftc_mlp_loss_grad", "ftc_mlp_adam", "ftc_learned_curvature", "ftc_front_roughness",
             "ftc_smooth_rough_edges", "ftc_get_tuning", "ftc_set_tuning", "ftc_surface_tension_flux",
-            "ftc_paraboloid_volume_fraction", "ftc_status_str"]
+            "ftc_paraboloid_cell", "ftc_status_str"]
 
 # ftc_kernel values (timing)
 KERNELS = {"tri_pieces": 0, "piece_rank": 1, "columns": 2, "ppic": 3, "csf": 4, "interp": 5, "surrogate": 6}
@@ -126,8 +126,8 @@ def lib() -> C.CDLL:
     L.ftc_surface_tension_flux.argtypes = [vp, P(_CGrid), vp, vp, C.c_int32, vp, vp, vp, C.c_double, C.c_double,
                                            C.c_double, vp, vp, vp]
     L.ftc_surface_tension_flux.restype = C.c_int32
-    L.ftc_paraboloid_volume_fraction.argtypes = [vp, P(_CGrid), vp, vp, vp]
-    L.ftc_paraboloid_volume_fraction.restype = C.c_int32
+    L.ftc_paraboloid_cell.argtypes = [vp, P(_CGrid), vp, vp, vp, vp, vp]
+    L.ftc_paraboloid_cell.restype = C.c_int32
     L.ftc_interp_vertex_velocity.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, vp, vp, vp, vp, vp]
     L.ftc_interp_vertex_velocity.restype = C.c_int32
     L.ftc_advect_vertices_rk4.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, vp, C.c_double, vp, vp, vp, vp]
@@ -373,14 +373,19 @@ def csf_force_band(cells: Cells, grid: _inputs.Grid, alpha_dense, kappa, nx, ny,
            "ftc_csf_force_band")
 
 
-def paraboloid_volume_fraction(cells: Cells, grid: _inputs.Grid, coeff, alpha_out, stream=None) -> None:
-    """alpha under each interfacial cell's fitted paraboloid; coeff [6,
-    cell_capacity] from the last ppic_curvature, alpha_out [cell_capacity]."""
+def paraboloid_cell(cells: Cells, grid: _inputs.Grid, coeff, alpha_out, kappa_out=None, normal_out=None,
+                    stream=None) -> None:
+    """alpha under each interfacial cell's fitted paraboloid and, if asked,
+    the curvature and normal integrated over its part inside the cell; coeff
+    [6, cell_capacity] from the last ppic_curvature, alpha_out and kappa_out
+    [cell_capacity], normal_out [3, cell_capacity]."""
     cg = c_grid(grid)
     cap = cells.cell_capacity
-    _check(lib().ftc_paraboloid_volume_fraction(cells.handle, C.byref(cg), _ptr(coeff, torch.float64, 6 * cap, "coeff"),
-                                                _ptr(alpha_out, torch.float64, cap, "alpha_out"), _stream(stream)),
-           "ftc_paraboloid_volume_fraction")
+    _check(lib().ftc_paraboloid_cell(cells.handle, C.byref(cg), _ptr(coeff, torch.float64, 6 * cap, "coeff"),
+                                     _ptr(alpha_out, torch.float64, cap, "alpha_out"),
+                                     _ptr(kappa_out, torch.float64, cap, "kappa_out"),
+                                     _ptr(normal_out, torch.float64, 3 * cap, "normal_out"), _stream(stream)),
+           "ftc_paraboloid_cell")
 
 
 def surface_tension_flux(cells: Cells, grid: _inputs.Grid, alpha_dense, kappa, band_ids, kappa_band, n_band,

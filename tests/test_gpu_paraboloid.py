@@ -34,18 +34,29 @@ def _run(name, seed=0):
     return grid, mesh, step
 
 
-def _alpha_gpu(step, grid, coeff_rows):
-    """Run the GPU call with the given coefficients [n_if, 6] (host)."""
+def _cell_gpu(step, grid, coeff_rows, surface=False):
+    """Run the GPU call with the given coefficients [n_if, 6] (host):
+    alpha, or (alpha, kappa_cell, normal_cell [n, 3])."""
     import torch
     from paper_2505_06932_amd import ftc
     cap = step.cells.cell_capacity
+    n = len(coeff_rows)
     co = np.zeros((6, cap))
-    co[:, :len(coeff_rows)] = np.asarray(coeff_rows).T
+    co[:, :n] = np.asarray(coeff_rows).T
     dco = torch.from_numpy(co).to("cuda").reshape(-1)
     out = torch.full((cap,), -1.0, dtype=torch.float64, device="cuda")
-    ftc.paraboloid_volume_fraction(step.cells, grid, dco, out)
+    kap = torch.full((cap,), -1.0, dtype=torch.float64, device="cuda") if surface else None
+    nrm = torch.full((3 * cap,), -1.0, dtype=torch.float64, device="cuda") if surface else None
+    ftc.paraboloid_cell(step.cells, grid, dco, out, kap, nrm)
     torch.cuda.synchronize()
-    return out.cpu().numpy()[:len(coeff_rows)]
+    a = out.cpu().numpy()[:n]
+    if not surface:
+        return a
+    return a, kap.cpu().numpy()[:n], nrm.cpu().numpy().reshape(3, cap)[:, :n].T
+
+
+def _alpha_gpu(step, grid, coeff_rows):
+    return _cell_gpu(step, grid, coeff_rows)
 
 
 @pytest.mark.timeout(300)
@@ -72,6 +83,32 @@ def test_paraboloid_alpha_parity(oracle, name, nsample):
     assert err <= ALPHA_TOL
 
 
+@pytest.mark.timeout(300)
+def test_paraboloid_surface_parity(oracle):
+    """Curvature and normal integrated over each cell's paraboloid patch:
+    sampled cells of the 32^3 sphere (and every one with a tiny normal
+    component, up to 16) within 1e-10 relative (the curvature bar), normals
+    within 1e-10; the volume fractions of the same call match the
+    volume-only call bit for bit."""
+    grid, mesh, step = _run("sphere_32")
+    cells, _, _ = oracle.cell_lists(grid, mesh)
+    r = oracle.ppic(grid, mesh, cells)
+    _, _, fn = oracle.frame_normal(grid, mesh, cells)
+    ok = np.nonzero(r["status"] == 0)[0]
+    a1 = _cell_gpu(step, grid, r["coeff"])
+    a2, kg, ng = _cell_gpu(step, grid, r["coeff"], surface=True)
+    assert np.array_equal(a1, a2)
+    pick = np.random.default_rng(12).choice(ok, 24, replace=False)
+    flat = ok[np.abs(fn[ok]).min(1) < 1e-6]
+    pick = np.union1d(pick, flat[:16])
+    ko, no = PB.surface_cells(fn[pick], r["coeff"][pick], grid.h)
+    assert np.all(np.isfinite(ko))
+    kerr = np.abs(kg[pick] - ko) / np.abs(ko)
+    nerr = np.abs(ng[pick] - no).max()
+    _say(f"[paraboloid] sphere_32 surface: {len(pick)} cells, kappa rel err {kerr.max():.2e}, normal err {nerr:.2e}")
+    assert kerr.max() <= 1e-10 and nerr <= 1e-10
+
+
 def test_paraboloid_alpha_full_size_against_polyhedral():
     """128^3 sphere, the device's own PPIC coefficients: every cell's alpha
     under its paraboloid is within the fit error of the exact polyhedral
@@ -80,7 +117,9 @@ def test_paraboloid_alpha_full_size_against_polyhedral():
     from paper_2505_06932_amd import ftc
     grid, mesh, step = _run("sphere_128")
     out = torch.empty_like(step.alpha_if)
-    ftc.paraboloid_volume_fraction(step.cells, grid, step.coeff, out)
+    kap = torch.empty_like(step.alpha_if)
+    nrm = torch.empty(3 * step.cells.cell_capacity, dtype=torch.float64, device="cuda")
+    ftc.paraboloid_cell(step.cells, grid, step.coeff, out, kap, nrm)
     g = step.results()
     n = g["n_if"]
     ap = out.cpu().numpy()[:n]
@@ -89,6 +128,14 @@ def test_paraboloid_alpha_full_size_against_polyhedral():
     d = np.abs(ap[ok] - g["alpha_if"][ok])
     _say(f"[paraboloid] sphere_128: |alpha_par - alpha_poly| max {d.max():.2e} median {np.median(d):.2e}")
     assert d.max() < 1e-2 and np.median(d) < 1e-3
+    # the curvature averaged over the patch stays close to the same fit's
+    # curvature at the frame origin (the noisy front spreads both around 2/R)
+    kc = kap.cpu().numpy()[:n][ok]
+    fin = np.isfinite(kc)
+    rel = np.abs(kc[fin] / g["kappa"][ok][fin] - 1)
+    _say(f"[paraboloid] sphere_128: kappa_cell finite {fin.mean():.4f}, |kappa_cell / kappa_origin - 1| median "
+         f"{np.median(rel):.2e} q99 {np.quantile(rel, 0.99):.2e}")
+    assert fin.mean() > 0.99 and np.median(rel) < 0.02
 
 
 def test_paraboloid_alpha_preconditions():
@@ -98,8 +145,8 @@ def test_paraboloid_alpha_preconditions():
     from paper_2505_06932_amd import ftc
     grid, mesh, step = _run("sphere_32")
     out = torch.empty_like(step.alpha_if)
-    ftc.paraboloid_volume_fraction(step.cells, grid, step.coeff, out)
+    ftc.paraboloid_cell(step.cells, grid, step.coeff, out)
     ftc.build_cell_lists(step.cells, grid, step.mesh)
     with pytest.raises(ftc.FTCError):
-        ftc.paraboloid_volume_fraction(step.cells, grid, step.coeff, out)
+        ftc.paraboloid_cell(step.cells, grid, step.coeff, out)
     torch.cuda.synchronize()
