@@ -185,11 +185,22 @@ def main():
         p1.record()
         torch.cuda.synchronize()
         pms = p0.elapsed_time(p1) / K
+        # with the curvature and normal integrated over each cell's patch
+        k_par = torch.empty_like(step.alpha_if)
+        n_par = torch.empty(3 * step.cells.cell_capacity, dtype=torch.float64, device="cuda")
+        ftc.paraboloid_cell(step.cells, grid, step.coeff, a_par, k_par, n_par)
+        torch.cuda.synchronize()
+        p0.record()
+        for _ in range(K):
+            ftc.paraboloid_cell(step.cells, grid, step.coeff, a_par, k_par, n_par)
+        p1.record()
+        torch.cuda.synchronize()
+        sms = p0.elapsed_time(p1) / K
         ok = res["status"] == 0
         dev = np.abs(a_par.cpu().numpy()[:n_if][ok] - res["alpha_if"][ok])
-        para = {"ms_per_call": pms, "cells_per_s": n_if / (pms * 1e-3),
+        para = {"ms_per_call": pms, "cells_per_s": n_if / (pms * 1e-3), "ms_per_call_with_surface": sms,
                 "max_abs_vs_polyhedral": float(dev.max()), "median_abs_vs_polyhedral": float(np.median(dev))}
-        log(f"[bench] paraboloid alpha: {pms * 1e3:.1f} us per call")
+        log(f"[bench] paraboloid alpha: {pms * 1e3:.1f} us per call, {sms * 1e3:.1f} us with the surface integrals")
     if args.learned:
         roofline = learned_roofline(res, kern_ms, n_if)
     else:
