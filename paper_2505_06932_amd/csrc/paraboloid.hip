@@ -335,6 +335,18 @@ __global__ __launch_bounds__(kT) void k_paraboloid_cell(const double* fit, const
     double a[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r) a[r] = coeff[r * cs + c];
+    bool finite = isfinite(n[0]) && isfinite(n[1]) && isfinite(n[2]);
+#pragma unroll
+    for (int r = 0; r < 6; ++r) finite = finite && isfinite(a[r]);
+    if (!finite) {  // a failed fit: nothing to integrate (the same for every lane)
+      if (lane == 0) {
+        alpha_out[c] = NAN;
+        if (kSurf && kappa_out) kappa_out[c] = NAN;
+        if (kSurf && normal_out)
+          for (int d = 0; d < 3; ++d) normal_out[d * cs + c] = NAN;
+      }
+      continue;
+    }
     const Local L = make_local(n, a, h);
     double xa = INFINITY, xb = -INFINITY;
 #pragma unroll

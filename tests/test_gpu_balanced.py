@@ -2,7 +2,7 @@
 through the C ABI: against the oracle on the oracle's own curvatures (1e-10
 of the largest value, the curvature bar), the force balance with a constant
 curvature at full size, equal values on both sides of shared faces, and the
-host-side argument checks."""
+host-side argument checks and a band that overflowed its capacity."""
 import sys
 
 import numpy as np
@@ -125,3 +125,32 @@ def test_flux_refuses_stale_band_and_bad_densities():
     with pytest.raises(ftc.FTCError):
         ftc.surface_tension_flux(*args, 1.0, 2.0, SIGMA, *outs)
     torch.cuda.synchronize()
+
+
+def test_flux_with_band_overflow():
+    """A band capacity below the band size latches FTC_ECAPACITY in the band
+    call; the flux call then writes the rows within that capacity, and every
+    value it writes is the full-capacity value, or NaN where a neighbour's
+    band row was not written."""
+    import torch
+    from paper_2505_06932_amd import ftc
+    grid, mesh, step, g = _step("sphere_32")
+    nb, n_if = g["n_band"], g["n_if"]
+    cap = nb // 2
+    z = lambda n, dt=torch.float64: torch.zeros(n, dtype=dt, device="cuda")
+    bid, kb, bx, by, bz, nband = z(cap, torch.int32), z(cap), z(cap), z(cap), z(cap), z(1, torch.int32)
+    ftc.csf_force_band(step.cells, grid, step.alpha, step.kappa, step.nx, step.ny, step.nz, SIGMA, bid, kb, bx, by,
+                       bz, nband)
+    assert int(nband.cpu()[0]) == nb
+    assert step.cells.last_device_error() == ftc.FTC_ECAPACITY
+    cc = step.cells.cell_capacity
+    fi = torch.full((6 * cc,), -7.0, dtype=torch.float64, device="cuda")
+    fb = torch.full((6 * cap,), -7.0, dtype=torch.float64, device="cuda")
+    ftc.surface_tension_flux(step.cells, grid, step.alpha, step.kappa, bid, kb, nband, RHO[0], RHO[1], SIGMA, fi, fb)
+    got_i = fi.cpu().numpy().reshape(6, cc)[:, :n_if].T
+    got_b = fb.cpu().numpy().reshape(6, cap).T
+    for got, ref in ((got_i, g["flux_if"]), (got_b, g["flux_band"][:cap])):
+        assert not (got == -7.0).any()
+        fin = np.isfinite(got)
+        assert np.array_equal(got[fin], ref[fin])
+    assert np.isnan(got_i).any() and np.isfinite(got_i).mean() > 0.5

@@ -150,3 +150,20 @@ def test_paraboloid_alpha_preconditions():
     with pytest.raises(ftc.FTCError):
         ftc.paraboloid_cell(step.cells, grid, step.coeff, out)
     torch.cuda.synchronize()
+
+
+def test_failed_fits_give_nan(oracle):
+    """A cell whose coefficients are NaN (a failed fit) gets NaN for alpha,
+    curvature and normal; its neighbours in the list are unaffected."""
+    grid, mesh, step = _run("sphere_32")
+    cells, _, _ = oracle.cell_lists(grid, mesh)
+    r = oracle.ppic(grid, mesh, cells)
+    co = r["coeff"].copy()
+    a0, k0, n0 = _cell_gpu(step, grid, co, surface=True)
+    bad = [3, 400, len(co) - 1]
+    co[bad] = np.nan
+    a1, k1, n1 = _cell_gpu(step, grid, co, surface=True)
+    assert np.all(np.isnan(a1[bad])) and np.all(np.isnan(k1[bad])) and np.all(np.isnan(n1[bad]))
+    keep = np.setdiff1d(np.arange(len(co)), bad)
+    assert np.array_equal(a1[keep], a0[keep]) and np.array_equal(k1[keep], k0[keep], equal_nan=True)
+    assert np.array_equal(n1[keep], n0[keep], equal_nan=True)
