@@ -165,6 +165,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(r_vflag, nv_capacity);
   FTC_ALLOC(r_estate, 3 * (int64_t)nt_capacity);
   FTC_ALLOC(r_elist, 3 * (int64_t)nt_capacity);
+  FTC_ALLOC(quad_nodes, ftc::kQuadNodes);
 #undef FTC_ALLOC
   w.timing = 0;
   int nev = 0;
@@ -176,6 +177,11 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
       if (e != hipSuccess) (void)hipEventDestroy(w.ev_start[k]);
     }
     if (e == hipSuccess) ++nev;
+  }
+  if (e == hipSuccess) {
+    double nodes[ftc::kQuadNodes];
+    ftc::paraboloid_nodes(nodes);
+    e = hipMemcpy(w.quad_nodes, nodes, sizeof(nodes), hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipMemset(w.counters, 0, sizeof(int32_t) * ftc::C_COUNT);
   // per-vertex and per-cell counts of the PPIC pre-passes start at zero and

@@ -11,6 +11,7 @@
 namespace ftc {
 constexpr int kFitSlots = 32;  // doubles per cell in ftc_cells::fit
 constexpr int kFitList = 64;   // weighted-triangle list entries per cell
+constexpr int kQuadNodes = 48;  // 16 nodes and weights (xi rule) + 8 and 8 (eta rule)
 enum : int {
   C_NIF = 0,      // interfacial cells of the last build
   C_NPAIRS = 1,   // (cell, triangle) pieces of the last build
@@ -93,6 +94,7 @@ struct ftc_cells {
   double* fit;            // [kFitSlots * cell_cap] per cell: normal equations (21 + 6), vertex normal (3), weighted count
   int32_t* wl_tri;        // [cell_cap * kFitList] the triangles of each cell's fit
   double* wl_w;           // [cell_cap * kFitList] their weights
+  double* quad_nodes;     // [kQuadNodes] quadrature nodes and weights of the paraboloid cell integrals
   int32_t* sel_cells;     // [cell_cap] cells the learned curvature hands to PPIC
   // roughness detection and smoothing
   double* r_tn;           // [4 * nt_cap] unit normal and area of each triangle
@@ -193,6 +195,8 @@ hipError_t launch_csf(const ftc_cells* ws, const double* alpha, const double* ka
 hipError_t launch_csf_band(const ftc_cells* ws, const double* alpha, const double* kappa, const double* nx,
                            const double* ny, const double* nz, double sigma, int32_t band_cap, int32_t* band_ids,
                            double* kappa_band, double* fx, double* fy, double* fz, int32_t* n_band, hipStream_t s);
+// The quadrature tables of the paraboloid cell integrals, host side: out[kQuadNodes].
+void paraboloid_nodes(double* out);
 hipError_t launch_paraboloid_cell(const ftc_cells* ws, const double* coeff, double* alpha_out, double* kappa_out,
                                   double* normal_out, hipStream_t s);
 hipError_t launch_face_flux(const ftc_cells* ws, const double* alpha, const double* kappa, int32_t band_cap,

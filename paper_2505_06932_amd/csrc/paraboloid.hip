@@ -38,10 +38,17 @@ constexpr int kEta = 24;     // eta breakpoints per G evaluation
 
 constexpr int kS = 8;        // Gauss nodes per eta interval of the surface integrals
 
+// The quadrature tables, one device array (read through the cache, indexed
+// per lane): tau[kQ], omega[kQ] (xi = u0 + (u1 - u0) tau, weight (u1 - u0)
+// omega), then sx[kS], sw[kS] (plain Gauss-Legendre on [0, 1]).
 struct Nodes {
-  double tau[kQ], omega[kQ];  // xi = u0 + (u1 - u0) tau, weight (u1 - u0) omega
-  double sx[kS], sw[kS];      // plain Gauss-Legendre on [0, 1]
+  const double* p;
+  __device__ double tau(int k) const { return p[k]; }
+  __device__ double omega(int k) const { return p[kQ + k]; }
+  __device__ double sx(int k) const { return p[2 * kQ + k]; }
+  __device__ double sw(int k) const { return p[2 * kQ + kS + k]; }
 };
+static_assert(2 * kQ + 2 * kS == kQuadNodes, "quadrature table size");
 
 // The cell's paraboloid and cube in its local frame, cell units.  The two
 // faces x_k = -+1/2 of axis k (n_k != 0) are the planes
@@ -95,6 +102,34 @@ __device__ inline Local make_local(const double n[3], const double a[6], double 
       L.inv_dce[j + k - 1] = (has_axis(L, j) && has_axis(L, k) && d != 0.0) ? 1.0 / d : 0.0;
     }
   return L;
+}
+
+// The same value in every lane, moved to scalar registers: the per-cell
+// state is computed by every lane of the wavefront alike.
+__device__ inline double uniform(double x) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ inline Local uniform(const Local& L) {
+  Local U;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) U.b[k] = uniform(L.b[k]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    U.lo[k] = uniform(L.lo[k]);
+    U.hi[k] = uniform(L.hi[k]);
+    U.cx[k] = uniform(L.cx[k]);
+    U.ce[k] = uniform(L.ce[k]);
+    U.t1[k] = uniform(L.t1[k]);
+    U.t2[k] = uniform(L.t2[k]);
+    U.n[k] = uniform(L.n[k]);
+    U.inv_dce[k] = uniform(L.inv_dce[k]);
+  }
+  U.has = __builtin_amdgcn_readfirstlane(L.has);
+  return U;
 }
 
 // Real roots of qa t^2 + qb t + qc (linear when qa == 0); absent roots NaN.
@@ -218,12 +253,12 @@ __device__ void eta_integrals(const Local& L, const Nodes& N, double xi, double 
       double sa = 0.0, sk = 0.0;
 #pragma unroll
       for (int q = 0; q < kS; ++q) {
-        const double eta = a + (c - a) * N.sx[q];
+        const double eta = a + (c - a) * N.sx(q);
         const double px = L.b[1] + 2.0 * L.b[3] * xi + L.b[4] * eta;
         const double pe = L.b[2] + L.b[4] * xi + 2.0 * L.b[5] * eta;
         const double w2 = 1.0 + px * px + pe * pe;
-        sa += N.sw[q] * sqrt(w2);
-        sk -= N.sw[q] * ((1.0 + pe * pe) * 2.0 * L.b[3] - 2.0 * px * pe * L.b[4] + (1.0 + px * px) * 2.0 * L.b[5]) / w2;
+        sa += N.sw(q) * sqrt(w2);
+        sk -= N.sw(q) * ((1.0 + pe * pe) * 2.0 * L.b[3] - 2.0 * px * pe * L.b[4] + (1.0 + px * px) * 2.0 * L.b[5]) / w2;
       }
       out[1] += (c - a) * sa;
       out[2] += (c - a) * sk;
@@ -240,9 +275,14 @@ __device__ inline void conic_line(const Local& L, double c0, double cx, double c
   roots2(A + B * be + C * be * be, B * al + 2.0 * C * al * be + D + E * be, C * al * al + E * al + F, r0, r1);
 }
 
+// a[k] for a per-lane k, as selects (indexing the per-cell arrays with a
+// lane-dependent index would move them to scratch memory)
+__device__ inline double pick3(double a0, double a1, double a2, int k) { return k == 0 ? a0 : (k == 1 ? a1 : a2); }
+#define PICK3(arr, k) pick3((arr)[0], (arr)[1], (arr)[2], (k))
+
 // Coordinate w of face lo (hi) of axis k: the face the lower (upper) plane lies in.
 __device__ inline double face_w(const Local& L, int k, bool upper) {
-  return (L.n[k] > 0.0) == upper ? 0.5 : -0.5;
+  return (PICK3(L.n, k) > 0.0) == upper ? 0.5 : -0.5;
 }
 
 // Event e of the xi breakpoints, at most two values (NaN when absent):
@@ -266,30 +306,30 @@ __device__ inline void xi_event(const Local& L, int e, double& v0, double& v1) {
     const double wj = face_w(L, j, uj), wk = face_w(L, k, uk);
     const bool hj = has_axis(L, j), hk = has_axis(L, k);
     if (hj && hk) {
-      const double inv = L.inv_dce[pair];
+      const double inv = PICK3(L.inv_dce, pair);
       if (inv == 0.0) return;  // the edge projects onto xi = const: its ends are corners
-      const double cj = uj ? L.hi[j] : L.lo[j], ck = uk ? L.hi[k] : L.lo[k];
+      const double cj = uj ? PICK3(L.hi, j) : PICK3(L.lo, j), ck = uk ? PICK3(L.hi, k) : PICK3(L.lo, k);
       // the edge line: c_j + cx_j xi + ce_j eta = c_k + cx_k xi + ce_k eta
-      const double al = (ck - cj) * inv, be = (L.cx[k] - L.cx[j]) * inv;
+      const double al = (ck - cj) * inv, be = (PICK3(L.cx, k) - PICK3(L.cx, j)) * inv;
       // the crossing lies on both faces' curves; the face of the axis with
       // the larger |n| has the well-conditioned one (a face almost parallel
       // to n has coefficients of order 1/n_k)
-      if (fabs(L.n[j]) >= fabs(L.n[k]))
-        conic_line(L, cj, L.cx[j], L.ce[j], al, be, v0, v1);
+      if (fabs(PICK3(L.n, j)) >= fabs(PICK3(L.n, k)))
+        conic_line(L, cj, PICK3(L.cx, j), PICK3(L.ce, j), al, be, v0, v1);
       else
-        conic_line(L, ck, L.cx[k], L.ce[k], al, be, v0, v1);
+        conic_line(L, ck, PICK3(L.cx, k), PICK3(L.ce, k), al, be, v0, v1);
     } else if (hj || hk) {
       // one face is a slab boundary t1_m xi + t2_m eta = w_m of an axis with n_m == 0
       const int f = hj ? j : k, m = hj ? k : j;
       const double wm = hj ? wk : wj;
-      if (L.t2[m] == 0.0) return;  // a line xi = const: its ends are corners
-      const double cf = (hj ? uj : uk) ? L.hi[f] : L.lo[f];
-      conic_line(L, cf, L.cx[f], L.ce[f], wm / L.t2[m], -L.t1[m] / L.t2[m], v0, v1);
+      if (PICK3(L.t2, m) == 0.0) return;  // a line xi = const: its ends are corners
+      const double cf = (hj ? uj : uk) ? PICK3(L.hi, f) : PICK3(L.lo, f);
+      conic_line(L, cf, PICK3(L.cx, f), PICK3(L.ce, f), wm / PICK3(L.t2, m), -PICK3(L.t1, m) / PICK3(L.t2, m), v0, v1);
     } else {
       return;  // an edge along n: a point in projection, a corner
     }
     // keep the crossings on the edge segment x_j = wj, x_k = wk, |x_i| <= 1/2
-    const double c = L.t1[j] * wj + L.t1[k] * wk, d = 0.5 * fabs(L.t1[i]);
+    const double c = PICK3(L.t1, j) * wj + PICK3(L.t1, k) * wk, d = 0.5 * fabs(PICK3(L.t1, i));
     if (!(v0 >= c - d && v0 <= c + d)) v0 = NAN;
     if (!(v1 >= c - d && v1 <= c + d)) v1 = NAN;
     return;
@@ -297,28 +337,26 @@ __device__ inline void xi_event(const Local& L, int e, double& v0, double& v1) {
   const int f = (e - 20) % 3;
   const bool up = (e - 20) >= 3;
   if (!has_axis(L, f)) return;
-  const double c0 = up ? L.hi[f] : L.lo[f];
+  const double c0 = up ? PICK3(L.hi, f) : PICK3(L.lo, f);
   const double A = L.b[3], B = L.b[4], C = L.b[5];
-  const double D = L.b[1] - L.cx[f], E = L.b[2] - L.ce[f], F = L.b[0] - c0;
+  const double D = L.b[1] - PICK3(L.cx, f), E = L.b[2] - PICK3(L.ce, f), F = L.b[0] - c0;
   roots2(B * B - 4.0 * C * A, 2.0 * B * E - 4.0 * C * D, E * E - 4.0 * C * F, v0, v1);
   if (C == 0.0) return;  // no tangent along eta: keep the candidates as they are
   // keep a tangency only inside its face: the other two coordinates within 1/2
-  double* v[2] = {&v0, &v1};
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const double xi = *v[q];
-    if (isnan(xi)) continue;
+  auto inside = [&](double xi) {
     const double eta = -(B * xi + E) / (2.0 * C);
-    const double zeta = c0 + L.cx[f] * xi + L.ce[f] * eta;
-    bool inside = true;
+    const double zeta = c0 + PICK3(L.cx, f) * xi + PICK3(L.ce, f) * eta;
+    bool in = true;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       if (m == f) continue;
-      const double x = L.t1[m] * xi + L.t2[m] * eta + L.n[m] * zeta;
-      inside = inside && fabs(x) <= 0.5 + 1e-12;
+      const double x = PICK3(L.t1, m) * xi + PICK3(L.t2, m) * eta + PICK3(L.n, m) * zeta;
+      in = in && fabs(x) <= 0.5 + 1e-12;
     }
-    if (!inside) *v[q] = NAN;
-  }
+    return in;
+  };
+  if (!isnan(v0) && !inside(v0)) v0 = NAN;
+  if (!isnan(v1) && !inside(v1)) v1 = NAN;
 }
 
 template <bool kSurf>
@@ -347,7 +385,7 @@ __global__ __launch_bounds__(kT) void k_paraboloid_cell(const double* fit, const
       }
       continue;
     }
-    const Local L = make_local(n, a, h);
+    const Local L = uniform(make_local(n, a, h));
     double xa = INFINITY, xb = -INFINITY;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -390,8 +428,8 @@ __global__ __launch_bounds__(kT) void k_paraboloid_cell(const double* fit, const
       const double u0 = xs[i], u1 = xs[i + 1];
       if (!(u1 > u0)) continue;
       double g[6];
-      eta_integrals<kSurf>(L, N, u0 + (u1 - u0) * N.tau[k], g);
-      const double wq = (u1 - u0) * N.omega[k];
+      eta_integrals<kSurf>(L, N, u0 + (u1 - u0) * N.tau(k), g);
+      const double wq = (u1 - u0) * N.omega(k);
 #pragma unroll
       for (int o = 0; o < kOut; ++o) acc[o] += wq * g[o];
     }
@@ -420,8 +458,11 @@ __global__ __launch_bounds__(kT) void k_paraboloid_cell(const double* fit, const
 
 // 16-point Gauss-Legendre rule on [-1, 1] by Newton's method on the Legendre
 // recurrence, mapped through theta = (x + 1) pi / 2, u = (1 - cos theta) / 2.
-Nodes make_nodes() {
-  Nodes N;
+void make_nodes(double* out) {
+  double* tau = out;
+  double* omega = out + kQ;
+  double* sx = out + 2 * kQ;
+  double* sw = out + 2 * kQ + kS;
   const double pi = 3.14159265358979323846;
   for (int i = 0; i < kQ; ++i) {
     double x = cos(pi * (i + 0.75) / (kQ + 0.5)), dp = 1.0;
@@ -446,8 +487,8 @@ Nodes make_nodes() {
     dp = kQ * (x * p1 - p0) / (x * x - 1.0);
     const double w = 2.0 / ((1.0 - x * x) * dp * dp);
     const double th = (x + 1.0) * pi / 2.0;
-    N.tau[i] = 0.5 * (1.0 - cos(th));
-    N.omega[i] = w * (pi / 2.0) * sin(th) * 0.5;
+    tau[i] = 0.5 * (1.0 - cos(th));
+    omega[i] = w * (pi / 2.0) * sin(th) * 0.5;
   }
   for (int i = 0; i < kS; ++i) {
     double x = cos(pi * (i + 0.75) / (kS + 0.5)), dp = 1.0, p0 = 1.0, p1 = x;
@@ -472,17 +513,18 @@ Nodes make_nodes() {
       p1 = p2;
     }
     dp = kS * (x * p1 - p0) / (x * x - 1.0);
-    N.sx[i] = 0.5 * (x + 1.0);
-    N.sw[i] = 1.0 / ((1.0 - x * x) * dp * dp);  // half the weight on [-1, 1]
+    sx[i] = 0.5 * (x + 1.0);
+    sw[i] = 1.0 / ((1.0 - x * x) * dp * dp);  // half the weight on [-1, 1]
   }
-  return N;
 }
 
 }  // namespace
 
+void paraboloid_nodes(double* out) { make_nodes(out); }
+
 hipError_t launch_paraboloid_cell(const ftc_cells* ws, const double* coeff, double* alpha_out, double* kappa_out,
                                   double* normal_out, hipStream_t s) {
-  static const Nodes N = make_nodes();
+  const Nodes N{ws->quad_nodes};
   const dim3 grid(grid_blocks(ws->cell_cap, 1, 65535));
   if (kappa_out || normal_out)
     hipLaunchKernelGGL(k_paraboloid_cell<true>, grid, dim3(kT), 0, s, ws->fit, coeff, ws->grid.h, ws->counters,
