@@ -70,8 +70,9 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="choose the launch shapes with the autotuner (whole-step graph timings) before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--paraboloid", action="store_true",
-                    help="also time the volume fraction under the fitted paraboloid (outside the step)")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the calls outside the step: the paraboloid cell quantities, the CSF band mode, "
+                         "the surface-tension face flux, RK4 advection, roughness detection and smoothing")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -171,36 +172,9 @@ def main():
     log("[bench] kernel ms: " + ", ".join(f"{k}={v * 1e3:.1f}us" for k, v in kern_ms.items()))
 
     res = step.results()
-    para = None
-    if args.paraboloid and not args.learned:
-        # alpha under each cell's PPIC paraboloid, after one plain step
-        step.run()
-        a_par = torch.empty_like(step.alpha_if)
-        ftc.paraboloid_cell(step.cells, grid, step.coeff, a_par)
-        torch.cuda.synchronize()
-        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        p0.record()
-        for _ in range(K):
-            ftc.paraboloid_cell(step.cells, grid, step.coeff, a_par)
-        p1.record()
-        torch.cuda.synchronize()
-        pms = p0.elapsed_time(p1) / K
-        # with the curvature and normal integrated over each cell's patch
-        k_par = torch.empty_like(step.alpha_if)
-        n_par = torch.empty(3 * step.cells.cell_capacity, dtype=torch.float64, device="cuda")
-        ftc.paraboloid_cell(step.cells, grid, step.coeff, a_par, k_par, n_par)
-        torch.cuda.synchronize()
-        p0.record()
-        for _ in range(K):
-            ftc.paraboloid_cell(step.cells, grid, step.coeff, a_par, k_par, n_par)
-        p1.record()
-        torch.cuda.synchronize()
-        sms = p0.elapsed_time(p1) / K
-        ok = res["status"] == 0
-        dev = np.abs(a_par.cpu().numpy()[:n_if][ok] - res["alpha_if"][ok])
-        para = {"ms_per_call": pms, "cells_per_s": n_if / (pms * 1e-3), "ms_per_call_with_surface": sms,
-                "max_abs_vs_polyhedral": float(dev.max()), "median_abs_vs_polyhedral": float(np.median(dev))}
-        log(f"[bench] paraboloid alpha: {pms * 1e3:.1f} us per call, {sms * 1e3:.1f} us with the surface integrals")
+    extras = None
+    if args.extras and not args.learned:
+        extras = time_extras(step, grid, mesh, res, n_if, K, log)
     if args.learned:
         roofline = learned_roofline(res, kern_ms, n_if)
     else:
@@ -222,7 +196,7 @@ def main():
         "gpu_ms_per_step_events": gpu_ms / K,
         "kernel_ms": kern_ms,
         "roofline": roofline,
-        **({"paraboloid_alpha": para} if para else {}),
+        **({"extras_ms": extras} if extras else {}),
     }
 
     # ---------------------------------------------------------- CPU oracle
@@ -290,6 +264,64 @@ def main():
         log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} cells/s on {oracle.threads()} threads; "
             f"errors {out['err_vs_oracle']}")
     print(json.dumps(out), flush=True)
+
+
+def time_extras(step, grid, mesh, res, n_if, K, log):
+    """Average times (ms per call, HIP events on the current stream) of the
+    library calls outside the coupling step, on the step's own workspace
+    after one plain step, plus the paraboloid's deviation from the
+    polyhedral alpha."""
+    import numpy as np
+    import torch
+    from paper_2505_06932_amd import ftc
+
+    def timeit(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(K):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / K
+
+    step.run()
+    cap = step.cells.cell_capacity
+    f64 = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")
+    out = {}
+    a_par, k_par, n_par = f64(cap), f64(cap), f64(3 * cap)
+    out["paraboloid_alpha"] = timeit(lambda: ftc.paraboloid_cell(step.cells, grid, step.coeff, a_par))
+    out["paraboloid_alpha_kappa_normal"] = timeit(
+        lambda: ftc.paraboloid_cell(step.cells, grid, step.coeff, a_par, k_par, n_par))
+    ok = res["status"] == 0
+    dev = np.abs(a_par.cpu().numpy()[:n_if][ok] - res["alpha_if"][ok])
+    out["paraboloid_alpha_vs_polyhedral_max"] = float(dev.max())
+    out["paraboloid_alpha_vs_polyhedral_median"] = float(np.median(dev))
+    bcap = 6 * cap
+    bid, kb, bx, by, bz = torch.zeros(bcap, dtype=torch.int32, device="cuda"), f64(bcap), f64(bcap), f64(bcap), \
+        f64(bcap)
+    nb = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out["csf_band"] = timeit(lambda: ftc.csf_force_band(step.cells, grid, step.alpha, step.kappa, step.nx, step.ny,
+                                                        step.nz, step.sigma, bid, kb, bx, by, bz, nb))
+    fi, fb = f64(6 * cap), f64(6 * bcap)
+    out["surface_tension_flux"] = timeit(lambda: ftc.surface_tension_flux(step.cells, grid, step.alpha, step.kappa, bid,
+                                                                          kb, nb, 1.2, 1000.0, step.sigma, fi, fb))
+    nv = mesh.nv
+    xo, yo, zo = f64(nv), f64(nv), f64(nv)
+    out["advect_rk4"] = timeit(lambda: ftc.advect_vertices_rk4(step.cells, grid, step.mesh, step.U, step.V, step.W,
+                                                               1e-3, xo, yo, zo))
+    gl, rough = f64(nv), f64(nv)
+    out["front_roughness"] = timeit(lambda: ftc.front_roughness(step.cells, grid, step.mesh, gl, rough))
+    # smoothing of the roughest tenth of the vertices by both measures
+    glt, rt = float(torch.quantile(gl, 0.9)), float(torch.quantile(rough, 0.9))
+    counts = torch.zeros(3, dtype=torch.int32, device="cuda")
+    out["smooth_rough_edges"] = timeit(lambda: ftc.smooth_rough_edges(step.cells, grid, step.mesh, gl, rough, glt, rt,
+                                                                      xo, yo, zo, counts))
+    cnt = counts.cpu().numpy()
+    out["edges_listed"], out["edges_moved"] = int(cnt[0]), int(cnt[1])
+    log("[bench] extras: " + ", ".join(f"{k}={v:.4g}" for k, v in out.items()))
+    return out
 
 
 def ppic_roofline(res, kern_ms, workload):

@@ -23,7 +23,8 @@
 // Smoothing (after Kuprat et al. 2001, algorithm 4): edges whose two ends
 // have both metrics above the thresholds are listed; in rounds, an edge is
 // taken when no pending edge ordered before it (by fmix32 of the id, then
-// the id) has an end within one ring of it, and its ends move to the simultaneous Laplacian positions plus the
+// the id) has an end within one ring of it (all rounds in one workgroup),
+// and its ends move to the simultaneous Laplacian positions plus the
 // least displacement along g = A1 + A2 + y x (d1 - d2) that keeps the
 // enclosed volume, h n = -(d1.A1 + d2.A2 + d1.(d2 x y)) g / |g|^2 (the
 // volume change of moving both ends is exactly linear in h).
@@ -144,33 +145,70 @@ __device__ inline int32_t order_in_star(const RoughArgs& A, int32_t v, int32_t c
   return INT_MAX;
 }
 
+constexpr int kRing = 16;  // one-ring sizes kept in registers; larger ones take the fan walks
+
 __global__ void k_vertex_rough(RoughArgs A, double* rough) {
   for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < A.nv; v += gridDim.x * blockDim.x) {
-    const int32_t e0 = A.vt_off[v], e1 = A.vt_off[v + 1];
+    const int32_t e0 = A.vt_off[v], e1 = A.vt_off[v + 1], deg = e1 - e0;
     double s1 = 0.0;
     for (int32_t e = e0; e < e1; ++e) {
       const int32_t t = A.vt_ids[e];
       s1 += A.tn[t].w * A.rt[t];
     }
-    const double r1 = s1 / (double)(e1 - e0);
+    const double r1 = s1 / (double)deg;
     // the two-ring: triangles at v or at a one-ring vertex, each at the first
     // of its corners in the order (v, one-ring)
     double s2 = 0.0;
     int32_t n2 = 0;
-    for (int32_t q = -1; q < e1 - e0; ++q) {
-      int32_t u = v;
-      if (q >= 0) {
-        const int4 t = A.tri4[A.vt_ids[e0 + q]];
-        u = corner(t, (corner_of(t, v) + 1) % 3);
+    if (deg <= kRing) {
+      // the one-ring in fan order, in registers (static indices only)
+      int32_t ring[kRing];
+#pragma unroll
+      for (int q = 0; q < kRing; ++q) {
+        int32_t u = -1;
+        if (q < deg) {
+          const int4 t = A.tri4[A.vt_ids[e0 + q]];
+          u = corner(t, (corner_of(t, v) + 1) % 3);
+        }
+        ring[q] = u;
       }
-      const int32_t ou = q + 1;
-      for (int32_t f = A.vt_off[u]; f < A.vt_off[u + 1]; ++f) {
-        const int32_t t = A.vt_ids[f];
-        const int4 c = A.tri4[t];
-        const int32_t o0 = order_in_star(A, v, c.x), o1 = order_in_star(A, v, c.y), o2 = order_in_star(A, v, c.z);
-        if (min(o0, min(o1, o2)) == ou) {
-          s2 += A.tn[t].w * A.rt[t];
-          ++n2;
+      auto order = [&](int32_t c) {
+        int32_t o = c == v ? 0 : INT_MAX;
+#pragma unroll
+        for (int q = kRing - 1; q >= 0; --q) o = (ring[q] == c && c != v) ? 1 + q : o;
+        return o;
+      };
+#pragma unroll
+      for (int q = -1; q < kRing; ++q) {
+        if (q >= deg) break;
+        const int32_t u = q < 0 ? v : ring[q];
+        const int32_t ou = q + 1;
+        for (int32_t f = A.vt_off[u]; f < A.vt_off[u + 1]; ++f) {
+          const int32_t t = A.vt_ids[f];
+          const int4 c = A.tri4[t];
+          if (ou > 0 && (c.x == v || c.y == v || c.z == v)) continue;  // counted at v
+          if (min(order(c.x), min(order(c.y), order(c.z))) == ou) {
+            s2 += A.tn[t].w * A.rt[t];
+            ++n2;
+          }
+        }
+      }
+    } else {
+      for (int32_t q = -1; q < deg; ++q) {
+        int32_t u = v;
+        if (q >= 0) {
+          const int4 t = A.tri4[A.vt_ids[e0 + q]];
+          u = corner(t, (corner_of(t, v) + 1) % 3);
+        }
+        const int32_t ou = q + 1;
+        for (int32_t f = A.vt_off[u]; f < A.vt_off[u + 1]; ++f) {
+          const int32_t t = A.vt_ids[f];
+          const int4 c = A.tri4[t];
+          const int32_t o0 = order_in_star(A, v, c.x), o1 = order_in_star(A, v, c.y), o2 = order_in_star(A, v, c.z);
+          if (min(o0, min(o1, o2)) == ou) {
+            s2 += A.tn[t].w * A.rt[t];
+            ++n2;
+          }
         }
       }
     }
@@ -261,12 +299,16 @@ __device__ inline bool blocked_at(const SmoothArgs& S, int32_t u, int32_t h) {
   return false;
 }
 
-__global__ void k_select(SmoothArgs S) {
+// One round's selection over the flagged edges i0, i0 + stride, ...: true
+// if any of them is still pending.
+__device__ bool select_edges(const SmoothArgs& S, int32_t i0, int32_t stride) {
   const RoughArgs& A = S.R;
   const int32_t n = min(A.counters[C_RFLAG], 3 * A.nt);
-  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  bool pending = false;
+  for (int32_t i = i0; i < n; i += stride) {
     const int32_t h = S.elist[i];
     if (S.estate[h] != E_PENDING) continue;
+    pending = true;
     int32_t a, b;
     edge_ends(A, h, a, b);
     bool blocked = blocked_at(S, a, h) || blocked_at(S, b, h);
@@ -282,6 +324,7 @@ __global__ void k_select(SmoothArgs S) {
     // round cannot change it; they are marked after the round's reads
     if (!blocked) S.elist[i] = h | INT32_MIN;
   }
+  return pending;
 }
 
 // Sum of the one-ring positions of v without w, the ring size, and A_v.
@@ -300,10 +343,11 @@ __device__ inline void ring_sums(const RoughArgs& A, int32_t v, int32_t w, D3& s
   }
 }
 
-__global__ void k_apply(SmoothArgs S, double* xo, double* yo, double* zo) {
+// One round's moves of the selected edges i0, i0 + stride, ...
+__device__ void apply_edges(const SmoothArgs& S, double* xo, double* yo, double* zo, int32_t i0, int32_t stride) {
   const RoughArgs& A = S.R;
   const int32_t n = min(A.counters[C_RFLAG], 3 * A.nt);
-  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  for (int32_t i = i0; i < n; i += stride) {
     const int32_t tag = S.elist[i];
     if (tag >= 0) continue;
     const int32_t h = tag & INT32_MAX;
@@ -340,6 +384,25 @@ __global__ void k_apply(SmoothArgs S, double* xo, double* yo, double* zo) {
     yo[b] = pb.y;
     zo[b] = pb.z;
     atomicAdd(&A.counters[C_RMOVED], 1);
+  }
+}
+
+// All rounds in one workgroup (the flagged edges are few: local roughness):
+// select, barrier, move, barrier, until a round finds nothing pending or
+// max_rounds is reached.  Every thread takes the same number of rounds (the
+// flag is read after a barrier), so every barrier is reached by all.
+constexpr int kRoundT = 1024;
+__global__ __launch_bounds__(kRoundT) void k_rounds(SmoothArgs S, double* xo, double* yo, double* zo,
+                                                    int32_t max_rounds) {
+  __shared__ int32_t pending;
+  for (int32_t r = 0; r < max_rounds; ++r) {
+    if (threadIdx.x == 0) pending = 0;
+    __syncthreads();
+    if (select_edges(S, threadIdx.x, blockDim.x)) atomicOr(&pending, 1);
+    __syncthreads();
+    if (pending == 0) break;
+    apply_edges(S, xo, yo, zo, threadIdx.x, blockDim.x);
+    __syncthreads();
   }
 }
 
@@ -408,12 +471,7 @@ hipError_t launch_smooth(const ftc_cells* ws, const Mesh& m, const double* gl_ma
                      ws->counters);
   hipLaunchKernelGGL(k_vertex_flags, dim3(grid_blocks(m.nv, kT)), dim3(kT), 0, s, S);
   hipLaunchKernelGGL(k_edge_flags, dim3(grid_blocks(3 * (int64_t)m.nt, kT)), dim3(kT), 0, s, S);
-  // the rounds stride over the flagged edges; a round with none pending does nothing
-  const dim3 eg(grid_blocks(3 * (int64_t)m.nt, kT, 2048));
-  for (int32_t r = 0; r < max_rounds; ++r) {
-    hipLaunchKernelGGL(k_select, eg, dim3(kT), 0, s, S);
-    hipLaunchKernelGGL(k_apply, eg, dim3(kT), 0, s, S, xo, yo, zo);
-  }
+  if (max_rounds > 0) hipLaunchKernelGGL(k_rounds, dim3(1), dim3(kRoundT), 0, s, S, xo, yo, zo, max_rounds);
   hipLaunchKernelGGL(k_smooth_end, dim3(1), dim3(kT), 0, s, S, d_counts);
   return hipGetLastError();
 }
