@@ -220,6 +220,18 @@ __device__ void eta_integrals(const Local& L, const Nodes& N, double xi, double 
 #pragma unroll
         for (int i = 0; i < k; ++i)
           if (i + j + k < kEta && (i + j) / (2 * p) == (i + j + k) / (2 * p)) cswap(s[i + j], s[i + j + k]);
+  // runs of adjacent eta intervals where the surface lies in the cube.  There
+  // are at most four: for convex P, {P < zeta_hi} is one interval and
+  // {P > zeta_lo} leaves out at most three (one per lower face); for concave
+  // P the same with the roles exchanged.
+  constexpr int kRuns = 4;
+  double ra[kRuns], rc[kRuns], rlast = 0.0;
+  int nrun = 0;
+#pragma unroll
+  for (int k = 0; k < kRuns; ++k) {
+    ra[k] = 0.0;
+    rc[k] = -1.0;
+  }
 #pragma unroll
   for (int i = 0; i <= kEta; ++i) {
     const double a = i == 0 ? emin : s[i - 1], c = i == kEta ? emax : s[i];
@@ -244,12 +256,32 @@ __device__ void eta_integrals(const Local& L, const Nodes& N, double xi, double 
     }
     out[0] += 2.0 * r * ((pm - zl) + q2 * r * r * (1.0 / 3.0));
     if (kSurf) {
-      // the surface lies inside the cube on [a, c]
+      // the surface lies inside the cube on [a, c]: the normal integral is
+      // exact here; the interval joins the current run of such intervals
       const double pxm = L.b[1] + 2.0 * L.b[3] * xi + L.b[4] * m;
       const double pem = L.b[2] + L.b[4] * xi + 2.0 * L.b[5] * m;
       out[3] -= 2.0 * r * pxm;
       out[4] -= 2.0 * r * pem;
       out[5] += 2.0 * r;
+      const bool extend = nrun > 0 && rlast == a;
+      const int slot = extend ? nrun - 1 : min(nrun, kRuns - 1);
+#pragma unroll
+      for (int k = 0; k < kRuns; ++k) {
+        if (k != slot) continue;
+        if (!extend && nrun < kRuns) ra[k] = a;
+        rc[k] = c;  // a run beyond the last slot (not possible in exact arithmetic) extends it
+      }
+      if (!extend) nrun = min(nrun + 1, kRuns);
+      rlast = c;
+    }
+  }
+  if (kSurf) {
+    // area and curvature over each run: the integrand (W, kappa W) does not
+    // depend on the faces, so it is smooth across the breakpoints inside a run
+#pragma unroll
+    for (int run = 0; run < kRuns; ++run) {
+      const double a = ra[run], c = rc[run];
+      if (!(c > a)) continue;
       double sa = 0.0, sk = 0.0;
 #pragma unroll
       for (int q = 0; q < kS; ++q) {
