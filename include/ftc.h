@@ -243,8 +243,8 @@ ftc_status ftc_csf_force_band(ftc_cells* cells, const ftc_grid* grid, const doub
    same flux (force balance).  kappa [cell_capacity] as from
    ftc_ppic_curvature; band_ids, kappa_band [band_capacity] and d_n_band
    [device int32] as written by the last ftc_csf_force_band on this
-   workspace, which must follow its last ftc_build_cell_lists (FTC_EINVAL
-   otherwise).  rho_a, rho_b > 0.  Outputs flux_if [6][cell_capacity]
+   workspace, which must follow its last ftc_build_cell_lists, with the same
+   band_capacity (FTC_EINVAL otherwise).  rho_a, rho_b > 0.  Outputs flux_if [6][cell_capacity]
    (cell-list order) and flux_band [6][band_capacity] (band order); slot 2d
    holds the face towards C - e_d, slot 2d + 1 the face towards C + e_d, so a
    face shared by two listed cells has the same value in both rows.  A NaN

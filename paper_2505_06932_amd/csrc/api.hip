@@ -109,6 +109,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   w.built_nt = -1;
   w.builds = 0;
   w.band_build = -1;
+  w.band_cap = 0;
   w.ppic_build = -1;
   w.pair_cap = pair_capacity;
   const int64_t P = pair_capacity, Cc = cell_capacity, Tc = nt_capacity, Vc = nv_capacity;
@@ -297,7 +298,10 @@ ftc_status ftc_csf_force_band(ftc_cells* cells, const ftc_grid* grid, const doub
   const ftc_status st = hip_status(ftc::launch_csf_band(cells, alpha_dense, kappa, nx, ny, nz, sigma, band_capacity,
                                                         band_ids, kappa_band, fx, fy, fz, d_n_band,
                                                         (hipStream_t)stream));
-  if (st == FTC_OK) cells->band_build = cells->builds;
+  if (st == FTC_OK) {
+    cells->band_build = cells->builds;
+    cells->band_cap = band_capacity;
+  }
   return st;
 }
 
@@ -318,7 +322,9 @@ ftc_status ftc_surface_tension_flux(ftc_cells* cells, const ftc_grid* grid, cons
       !kappa_band || !d_n_band || !flux_if || !flux_band || band_capacity <= 0 || !isfinite(sigma) ||
       !(rho_a > 0.0) || !(rho_b > 0.0) || !isfinite(rho_a) || !isfinite(rho_b))
     return FTC_EINVAL;
-  if (!on_device(cells) || cells->builds == 0 || cells->band_build != cells->builds) return FTC_EINVAL;
+  if (!on_device(cells) || cells->builds == 0 || cells->band_build != cells->builds ||
+      band_capacity != cells->band_cap)
+    return FTC_EINVAL;
   return hip_status(ftc::launch_face_flux(cells, alpha_dense, kappa, band_capacity, band_ids, kappa_band, d_n_band,
                                           rho_a, rho_b, sigma, flux_if, flux_band, (hipStream_t)stream));
 }

@@ -47,6 +47,7 @@ struct ftc_cells {
   int32_t built_nv, built_nt;  // front sizes of the last build (-1 before the first)
   int64_t builds;      // builds enqueued so far
   int64_t band_build;  // value of `builds` when the band was last listed (-1: never)
+  int32_t band_cap;    // the band capacity of that listing
   mutable int64_t ppic_build;  // value of `builds` at the last plain PPIC call (-1: none since)
   int64_t pair_cap;
   int64_t queue_cap;  // candidates queued for full clipping (>= pair_cap)

@@ -121,6 +121,11 @@ def test_flux_refuses_stale_band_and_bad_densities():
     for ra, rb in ((0.0, 1.0), (1.0, -2.0), (float("nan"), 1.0), (1.0, float("inf"))):
         with pytest.raises(ftc.FTCError):
             ftc.surface_tension_flux(*args, ra, rb, SIGMA, *outs)
+    # a band capacity other than the one the band was listed with
+    short = step.band_ids[: step.band_ids.numel() // 2]
+    with pytest.raises(ftc.FTCError):
+        ftc.surface_tension_flux(step.cells, grid, step.alpha, step.kappa, short, step.kappa_band, step.n_band, 1.0,
+                                 2.0, SIGMA, *outs)
     ftc.build_cell_lists(step.cells, grid, step.mesh)
     with pytest.raises(ftc.FTCError):
         ftc.surface_tension_flux(*args, 1.0, 2.0, SIGMA, *outs)
