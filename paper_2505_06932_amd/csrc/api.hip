@@ -51,9 +51,12 @@ bool on_device(const ftc_cells* c) {
 
 ftc_status hip_status(hipError_t e) { return e == hipSuccess ? FTC_OK : FTC_EHIP; }
 
+constexpr int kMaxBuffers = 64;  // device buffers one workspace owns
+
 template <class T>
 hipError_t alloc(T** p, int64_t n, void** registry, int& nreg) {
   *p = nullptr;
+  if (nreg >= kMaxBuffers) return hipErrorOutOfMemory;  // never writes past the registry
   void* raw = nullptr;
   hipError_t e = hipMalloc(&raw, (size_t)std::max<int64_t>(n, 1) * sizeof(T));
   if (e != hipSuccess) return e;
@@ -61,8 +64,6 @@ hipError_t alloc(T** p, int64_t n, void** registry, int& nreg) {
   *p = static_cast<T*>(raw);
   return hipSuccess;
 }
-
-constexpr int kMaxBuffers = 48;
 
 }  // namespace
 

@@ -106,3 +106,14 @@ def test_learned_and_tuning_entry_points_check_arguments_on_the_host(lib):
     assert lib.ftc_mlp_adam(p, p, p, p, 1, 1e-3, 1.0, 0.999, 1e-8, None) == EINVAL     # beta1 = 1
     assert lib.ftc_mlp_loss_grad(p, p, 10, None, None, p, 0, p, None, p, None) == EINVAL  # empty batch
     assert lib.ftc_mlp_forward(p, p, 0, None, None, 5, p, None) == EINVAL                # no rows
+
+
+def test_workspace_buffers_fit_the_registry():
+    """Every device buffer a workspace allocates is registered for freeing in
+    a fixed-size array: the allocations listed in the library source must
+    not outnumber it (one more once wrote past it and crashed the destroy)."""
+    with open(os.path.join(ROOT, "paper_2505_06932_amd", "csrc", "api.hip")) as f:
+        src = f.read()
+    cap = int(re.search(r"constexpr int kMaxBuffers = (\d+);", src).group(1))
+    n = len(re.findall(r"^\s*FTC_ALLOC\(", src, flags=re.M))
+    assert 0 < n <= cap, (n, cap)
