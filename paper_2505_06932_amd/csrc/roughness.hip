@@ -299,30 +299,32 @@ __device__ inline bool blocked_at(const SmoothArgs& S, int32_t u, int32_t h) {
   return false;
 }
 
-// One round's selection over the flagged edges i0, i0 + stride, ...: true
-// if any of them is still pending.
+// One round's selection over the flagged edges: a pair of adjacent lanes per
+// edge (edge i0/2, then + stride/2, ...), the even lane testing the end a and
+// its one-ring, the odd lane the end b and its one-ring; true if any edge is
+// still pending.  Both lanes of a pair read the same edge and state, so they
+// follow the same path up to the exchange of their results.
 __device__ bool select_edges(const SmoothArgs& S, int32_t i0, int32_t stride) {
   const RoughArgs& A = S.R;
   const int32_t n = min(A.counters[C_RFLAG], 3 * A.nt);
+  const int side = i0 & 1;
   bool pending = false;
-  for (int32_t i = i0; i < n; i += stride) {
+  for (int32_t i = i0 >> 1; i < n; i += stride >> 1) {
     const int32_t h = S.elist[i];
     if (S.estate[h] != E_PENDING) continue;
     pending = true;
     int32_t a, b;
     edge_ends(A, h, a, b);
-    bool blocked = blocked_at(S, a, h) || blocked_at(S, b, h);
-    for (int32_t e = A.vt_off[a]; !blocked && e < A.vt_off[a + 1]; ++e) {
+    const int32_t v = side ? b : a;
+    bool blocked = blocked_at(S, v, h);
+    for (int32_t e = A.vt_off[v]; !blocked && e < A.vt_off[v + 1]; ++e) {
       const int4 c = A.tri4[A.vt_ids[e]];
-      blocked = blocked_at(S, corner(c, (corner_of(c, a) + 1) % 3), h);
+      blocked = blocked_at(S, corner(c, (corner_of(c, v) + 1) % 3), h);
     }
-    for (int32_t e = A.vt_off[b]; !blocked && e < A.vt_off[b + 1]; ++e) {
-      const int4 c = A.tri4[A.vt_ids[e]];
-      blocked = blocked_at(S, corner(c, (corner_of(c, b) + 1) % 3), h);
-    }
+    blocked = (__shfl_xor((int)blocked, 1, 64) != 0) || blocked;
     // the decision reads only pending states, so selections within the
     // round cannot change it; they are marked after the round's reads
-    if (!blocked) S.elist[i] = h | INT32_MIN;
+    if (!blocked && side == 0) S.elist[i] = h | INT32_MIN;
   }
   return pending;
 }
