@@ -346,30 +346,45 @@ __device__ inline void ring_sums(const RoughArgs& A, int32_t v, int32_t w, D3& s
 }
 
 // One round's moves of the selected edges i0, i0 + stride, ...
+// One round's moves of the selected edges, a pair of adjacent lanes per edge
+// as in select_edges: the even lane sums the one-ring of a and finds the
+// triangle holding b -> a, the odd lane sums the one-ring of b; they swap
+// their sums, both compute the same move, and each writes its own end.
+__device__ inline double swap_pair(double v) { return __shfl_xor(v, 1, 64); }
+
 __device__ void apply_edges(const SmoothArgs& S, double* xo, double* yo, double* zo, int32_t i0, int32_t stride) {
   const RoughArgs& A = S.R;
   const int32_t n = min(A.counters[C_RFLAG], 3 * A.nt);
-  for (int32_t i = i0; i < n; i += stride) {
+  const int side = i0 & 1;
+  for (int32_t i = i0 >> 1; i < n; i += stride >> 1) {
     const int32_t tag = S.elist[i];
     if (tag >= 0) continue;
     const int32_t h = tag & INT32_MAX;
-    S.elist[i] = h;
-    S.estate[h] = E_DONE;
     int32_t a, b;
     edge_ends(A, h, a, b);
-    D3 S1, S2, A1, A2;
-    int32_t n1, n2;
-    ring_sums(A, a, b, S1, n1, A1);
-    ring_sums(A, b, a, S2, n2, A2);
+    D3 Sm, Am;
+    int32_t nm;
+    ring_sums(A, side ? b : a, side ? a : b, Sm, nm, Am);
+    const int32_t tb_mine = side ? 0 : twin_in_fan(A, a, b);
+    const D3 So{swap_pair(Sm.x), swap_pair(Sm.y), swap_pair(Sm.z)};
+    const D3 Ao{swap_pair(Am.x), swap_pair(Am.y), swap_pair(Am.z)};
+    const int32_t no = __shfl_xor(nm, 1, 64);
+    const int32_t tb_other = __shfl_xor(tb_mine, 1, 64);  // every exchange runs on both lanes
+    const int32_t tb = side ? tb_other : tb_mine;
+    const D3 S1 = side ? So : Sm, A1 = side ? Ao : Am, S2 = side ? Sm : So, A2 = side ? Am : Ao;
+    const int32_t n1 = side ? no : nm, n2 = side ? nm : no;
+    if (side == 0) {
+      S.elist[i] = h;
+      S.estate[h] = E_DONE;
+    }
     const D3 x1s = scale(add(S2, scale(S1, (double)n2)), 1.0 / (double)(n1 * n2 - 1));
     const D3 x2s = scale(add(x1s, S2), 1.0 / (double)n2);
     const D3 xa = pos(A, a), xb = pos(A, b);
     const D3 d1 = sub(x1s, xa), d2 = sub(x2s, xb);
     // far corners: of the triangle holding a -> b, and of the one holding b -> a
+    if (tb < 0) continue;  // no twin: an open front, left alone
     const int4 ct = A.tri4[h / 3];
     const int32_t ya = corner(ct, (h % 3 + 2) % 3);
-    const int32_t tb = twin_in_fan(A, a, b);
-    if (tb < 0) continue;  // no twin: an open front, left alone
     const int4 cb = A.tri4[tb];
     const int32_t yb = corner(cb, (corner_of(cb, a) + 1) % 3);
     const D3 yv = sub(pos(A, ya), pos(A, yb));
@@ -378,14 +393,12 @@ __device__ void apply_edges(const SmoothArgs& S, double* xo, double* yo, double*
     if (!(gg > 0.0)) continue;
     const double c = dot(d1, A1) + dot(d2, A2) + dot(d1, cross(d2, yv));
     const D3 step = scale(g, -c / gg);
-    const D3 pa = add(x1s, step), pb = add(x2s, step);
-    xo[a] = pa.x;
-    yo[a] = pa.y;
-    zo[a] = pa.z;
-    xo[b] = pb.x;
-    yo[b] = pb.y;
-    zo[b] = pb.z;
-    atomicAdd(&A.counters[C_RMOVED], 1);
+    const D3 p = side ? add(x2s, step) : add(x1s, step);
+    const int32_t v = side ? b : a;
+    xo[v] = p.x;
+    yo[v] = p.y;
+    zo[v] = p.z;
+    if (side == 0) atomicAdd(&A.counters[C_RMOVED], 1);
   }
 }
 
