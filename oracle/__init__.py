@@ -71,6 +71,9 @@ def _load():
     lib.ora_ppic.argtypes = [P(_Grid), P(_Mesh), P(_Params), C.c_int64, P(C.c_int64),
                              P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_int32), P(C.c_int32)]
     lib.ora_ppic.restype = C.c_int32
+    lib.ora_ppic_support.argtypes = [P(_Grid), P(_Mesh), P(_Params), C.c_int64, C.c_int32, P(C.c_int32),
+                                     P(C.c_double), P(C.c_double), P(C.c_double)]
+    lib.ora_ppic_support.restype = C.c_int32
     lib.ora_fit.argtypes = [P(C.c_double), P(C.c_double), C.c_double, C.c_int32, P(C.c_double),
                             P(C.c_double), P(C.c_double)]
     lib.ora_fit.restype = C.c_int32
@@ -210,6 +213,24 @@ def ppic(grid, mesh, cell_ids, params: PPICParams = PPICParams()):
     if r != 0:
         raise OracleError(r, "ppic")
     return dict(kappa=kap, normal=nrm, coeff=co, status=st, diag=dg)
+
+
+def ppic_support(grid, mesh, cell_id, params: PPICParams = PPICParams()):
+    """The support of one cell's volume fit, as ppic computes it: dict(tri
+    [ring triangles, ascending], d2 [squared centre distances], w [Wendland
+    weights], delta [support radius])."""
+    k = _Keep(grid, mesh)
+    p = _Params(params.delta_over_h, params.rings, params.n_min, params.grow, params.max_iter)
+    cap = mesh.nt
+    tri = np.empty(cap, np.int32)
+    d2 = np.empty(cap)
+    w = np.empty(cap)
+    delta = np.empty(1)
+    n = int(_load().ora_ppic_support(C.byref(k.g), C.byref(k.m), C.byref(p), int(cell_id), cap, _ip(tri),
+                                     _dp(d2), _dp(w), _dp(delta)))
+    if n < 0:
+        raise OracleError(n, "ppic_support")
+    return dict(tri=tri[:n].copy(), d2=d2[:n].copy(), w=w[:n].copy(), delta=float(delta[0]))
 
 
 def frame_normal(grid, mesh, cell_ids):

@@ -479,16 +479,10 @@ static int cmp_i32(const void* a, const void* b) {
   return (x > y) - (x < y);
 }
 
-int32_t ora_ppic(const ora_grid* g, const ora_mesh* m, const ora_ppic_params* prm, int64_t ncell,
-                 const int64_t* cell_ids, double* kappa, double* nrm, double* coeff, int32_t* status,
-                 int32_t* diag) {
-  if (!grid_ok(g) || !mesh_ok(m) || !prm || ncell < 0 || (ncell > 0 && !cell_ids)) return -1;
-  if (prm->rings < 1 || prm->n_min < 1 || !(prm->delta_over_h > 0.0) || !(prm->grow > 1.0) ||
-      prm->max_iter < 0)
-    return -1;
+/* Vertex -> incident triangles, ascending triangle id: *off[nv + 1] and
+   *ids[3 nt], allocated here (free both). */
+static void vertex_triangles(const ora_mesh* m, int32_t** off, int32_t** ids) {
   const int32_t nv = m->nv, nt = m->nt;
-  const double h = g->h;
-  /* vertex -> incident triangles, ascending triangle id */
   int32_t* vt_off = (int32_t*)calloc((size_t)nv + 1, sizeof(int32_t));
   int32_t* vt_ids = (int32_t*)malloc(sizeof(int32_t) * 3 * (size_t)nt);
   int32_t* fill = (int32_t*)calloc((size_t)nv, sizeof(int32_t));
@@ -503,157 +497,229 @@ int32_t ora_ppic(const ora_grid* g, const ora_mesh* m, const ora_ppic_params* pr
     for (int r = 0; r < 3; ++r) vt_ids[vt_off[c[r]] + fill[c[r]]++] = t;
   }
   free(fill);
+  *off = vt_off;
+  *ids = vt_ids;
+}
 
+/* Per-thread working storage of the PPIC steps for one cell. */
+typedef struct {
+  int32_t *tmark, *vmark, *tlist, *vlist, *vnext;
+  double *d2, *wts, *tri;
+  int32_t stamp;
+} ppic_scratch;
+
+static void scratch_init(ppic_scratch* s, int32_t nv, int32_t nt) {
+  s->tmark = (int32_t*)calloc((size_t)nt, sizeof(int32_t));
+  s->vmark = (int32_t*)calloc((size_t)nv, sizeof(int32_t));
+  s->tlist = (int32_t*)malloc(sizeof(int32_t) * (size_t)nt);
+  s->vlist = (int32_t*)malloc(sizeof(int32_t) * (size_t)nv);
+  s->vnext = (int32_t*)malloc(sizeof(int32_t) * (size_t)nv);
+  s->d2 = (double*)malloc(sizeof(double) * (size_t)nt);
+  s->wts = (double*)malloc(sizeof(double) * (size_t)nt);
+  s->tri = (double*)malloc(sizeof(double) * 9 * (size_t)nt);
+  s->stamp = 0;
+}
+
+static void scratch_free(ppic_scratch* s) {
+  free(s->tmark);
+  free(s->vmark);
+  free(s->tlist);
+  free(s->vlist);
+  free(s->vnext);
+  free(s->d2);
+  free(s->wts);
+  free(s->tri);
+}
+
+/* The PPIC steps for the cell with linear id cid.  Leaves the ring
+   triangles (ascending) in s->tlist[0, *ntl_out), their centre distances
+   squared in s->d2, their weights in s->wts and the support radius in
+   *delta_out; writes kappa, the interface normal, the coefficients, the
+   status and diag[4] = {closest vertex, ring size, triangles with non-zero
+   weight, support adjustments}. */
+static void ppic_cell(const ora_grid* g, const ora_mesh* m, const ora_ppic_params* prm, const int32_t* vt_off,
+                      const int32_t* vt_ids, int64_t cid, ppic_scratch* s, int32_t* ntl_out, double* delta_out,
+                      double* kap_out, double ni[3], double co[6], int32_t* st_out, int32_t diag[4]) {
+  const int32_t nv = m->nv;
+  const double h = g->h;
+  int32_t *tmark = s->tmark, *vmark = s->vmark, *tlist = s->tlist, *vlist = s->vlist, *vnext = s->vnext;
+  double *d2 = s->d2, *wts = s->wts, *tri = s->tri;
+  int64_t i = cid % g->nx, j = (cid / g->nx) % g->ny, k = cid / ((int64_t)g->nx * g->ny);
+  double xc[3] = {g->x0 + ((double)i + 0.5) * h, g->y0 + ((double)j + 0.5) * h,
+                  g->z0 + ((double)k + 0.5) * h};
+  /* 1. closest front vertex (lowest index on ties) */
+  double best = DBL_MAX;
+  int32_t vs = -1;
+  for (int32_t v = 0; v < nv; ++v) {
+    double dx = m->x[v] - xc[0], dy = m->y[v] - xc[1], dz = m->z[v] - xc[2];
+    double dd = dx * dx + dy * dy + dz * dz;
+    if (dd < best) {
+      best = dd;
+      vs = v;
+    }
+  }
+  /* 2. its normal: area-weighted sum of the incident triangle normals */
+  double n[3] = {0, 0, 0};
+  for (int32_t e = vt_off[vs]; e < vt_off[vs + 1]; ++e) {
+    double tr[3][3];
+    load_tri(m, vt_ids[e], tr);
+    double ux = tr[1][0] - tr[0][0], uy = tr[1][1] - tr[0][1], uz = tr[1][2] - tr[0][2];
+    double wx = tr[2][0] - tr[0][0], wy = tr[2][1] - tr[0][1], wz = tr[2][2] - tr[0][2];
+    n[0] += uy * wz - uz * wy;
+    n[1] += uz * wx - ux * wz;
+    n[2] += ux * wy - uy * wx;
+  }
+  double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  n[0] /= nl;
+  n[1] /= nl;
+  n[2] /= nl;
+  /* 3. tangents completing a right-handed orthonormal frame (Duff et al.,
+     "Building an orthonormal basis, revisited", JCGT 2017) */
+  double sg = copysign(1.0, n[2]);
+  double ca = -1.0 / (sg + n[2]);
+  double cb = n[0] * n[1] * ca;
+  double frame[9] = {1.0 + sg * n[0] * n[0] * ca, sg * cb, -sg * n[0],
+                     cb, sg + n[1] * n[1] * ca, -n[1],
+                     n[0], n[1], n[2]};
+  /* 4. ring neighbourhood: T_1 = triangles at the vertex, T_{r+1} =
+     triangles sharing a vertex with T_r */
+  ++s->stamp;
+  int32_t nvl = 1, ntl = 0;
+  vlist[0] = vs;
+  vmark[vs] = s->stamp;
+  for (int32_t r = 1; r <= prm->rings; ++r) {
+    ntl = 0;
+    ++s->stamp;
+    for (int32_t a = 0; a < nvl; ++a)
+      for (int32_t e = vt_off[vlist[a]]; e < vt_off[vlist[a] + 1]; ++e) {
+        int32_t t = vt_ids[e];
+        if (tmark[t] != s->stamp) {
+          tmark[t] = s->stamp;
+          tlist[ntl++] = t;
+        }
+      }
+    if (r == prm->rings) break;
+    int32_t nn2 = 0;
+    for (int32_t a = 0; a < ntl; ++a) {
+      const int32_t c[3] = {m->t0[tlist[a]], m->t1[tlist[a]], m->t2[tlist[a]]};
+      for (int q = 0; q < 3; ++q)
+        if (vmark[c[q]] != s->stamp) {
+          vmark[c[q]] = s->stamp;
+          vnext[nn2++] = c[q];
+        }
+    }
+    memcpy(vlist, vnext, sizeof(int32_t) * (size_t)nn2);
+    nvl = nn2;
+  }
+  qsort(tlist, (size_t)ntl, sizeof(int32_t), cmp_i32);
+  /* 5. distances of the triangle centres to the cell centre */
+  for (int32_t a = 0; a < ntl; ++a) {
+    double tr[3][3];
+    load_tri(m, tlist[a], tr);
+    memcpy(tri + 9 * a, tr, sizeof(double) * 9);
+    double cx = (tr[0][0] + tr[1][0] + tr[2][0]) / 3.0;
+    double cy = (tr[0][1] + tr[1][1] + tr[2][1]) / 3.0;
+    double cz = (tr[0][2] + tr[1][2] + tr[2][2]) / 3.0;
+    double dx = cx - xc[0], dy = cy - xc[1], dz = cz - xc[2];
+    d2[a] = dx * dx + dy * dy + dz * dz;
+  }
+  /* 6. support radius: grow until enough triangles have non-zero weight */
+  double delta = prm->delta_over_h * h;
+  int32_t it = 0, cnt = 0;
+  for (;;) {
+    double lim = delta * delta;
+    cnt = 0;
+    for (int32_t a = 0; a < ntl; ++a) cnt += d2[a] < lim;
+    if (cnt >= prm->n_min || cnt == ntl || it == prm->max_iter) break;
+    delta = delta * prm->grow;
+    ++it;
+  }
+  /* 7. Wendland C2 weights */
+  double lim = delta * delta;
+  for (int32_t a = 0; a < ntl; ++a) {
+    if (d2[a] < lim) {
+      double qq = sqrt(d2[a]) / delta;
+      double om = 1.0 - qq;
+      wts[a] = (1.0 + 4.0 * qq) * (om * om) * (om * om);
+    } else {
+      wts[a] = 0.0;
+    }
+  }
+  /* 8. volume fit, curvature and interface normal */
+  int32_t st = ora_fit(frame, xc, h, ntl, tri, wts, co);
+  *kap_out = st ? NAN : ora_kappa(co);
+  ni[0] = ni[1] = ni[2] = NAN;
+  if (!st) {
+    for (int d = 0; d < 3; ++d) ni[d] = frame[6 + d] - co[1] * frame[d] - co[2] * frame[3 + d];
+    double l = sqrt(ni[0] * ni[0] + ni[1] * ni[1] + ni[2] * ni[2]);
+    for (int d = 0; d < 3; ++d) ni[d] /= l;
+  }
+  *st_out = st;
+  *ntl_out = ntl;
+  *delta_out = delta;
+  diag[0] = vs;
+  diag[1] = ntl;
+  diag[2] = cnt;
+  diag[3] = it;
+}
+
+static int ppic_params_ok(const ora_ppic_params* prm) {
+  return prm && prm->rings >= 1 && prm->n_min >= 1 && prm->delta_over_h > 0.0 && prm->grow > 1.0 &&
+         prm->max_iter >= 0;
+}
+
+int32_t ora_ppic(const ora_grid* g, const ora_mesh* m, const ora_ppic_params* prm, int64_t ncell,
+                 const int64_t* cell_ids, double* kappa, double* nrm, double* coeff, int32_t* status,
+                 int32_t* diag) {
+  if (!grid_ok(g) || !mesh_ok(m) || !ppic_params_ok(prm) || ncell < 0 || (ncell > 0 && !cell_ids)) return -1;
+  int32_t *vt_off, *vt_ids;
+  vertex_triangles(m, &vt_off, &vt_ids);
 #pragma omp parallel
   {
-    int32_t* tmark = (int32_t*)calloc((size_t)nt, sizeof(int32_t));
-    int32_t* vmark = (int32_t*)calloc((size_t)nv, sizeof(int32_t));
-    int32_t* tlist = (int32_t*)malloc(sizeof(int32_t) * (size_t)nt);
-    int32_t* vlist = (int32_t*)malloc(sizeof(int32_t) * (size_t)nv);
-    int32_t* vnext = (int32_t*)malloc(sizeof(int32_t) * (size_t)nv);
-    double* d2 = (double*)malloc(sizeof(double) * (size_t)nt);
-    double* wts = (double*)malloc(sizeof(double) * (size_t)nt);
-    double* tri = (double*)malloc(sizeof(double) * 9 * (size_t)nt);
-    int32_t stamp = 0;
+    ppic_scratch s;
+    scratch_init(&s, m->nv, m->nt);
 #pragma omp for schedule(dynamic, 16)
     for (int64_t q = 0; q < ncell; ++q) {
-      int64_t cid = cell_ids[q];
-      int64_t i = cid % g->nx, j = (cid / g->nx) % g->ny, k = cid / ((int64_t)g->nx * g->ny);
-      double xc[3] = {g->x0 + ((double)i + 0.5) * h, g->y0 + ((double)j + 0.5) * h,
-                      g->z0 + ((double)k + 0.5) * h};
-      /* 1. closest front vertex (lowest index on ties) */
-      double best = DBL_MAX;
-      int32_t vs = -1;
-      for (int32_t v = 0; v < nv; ++v) {
-        double dx = m->x[v] - xc[0], dy = m->y[v] - xc[1], dz = m->z[v] - xc[2];
-        double dd = dx * dx + dy * dy + dz * dz;
-        if (dd < best) {
-          best = dd;
-          vs = v;
-        }
-      }
-      /* 2. its normal: area-weighted sum of the incident triangle normals */
-      double n[3] = {0, 0, 0};
-      for (int32_t e = vt_off[vs]; e < vt_off[vs + 1]; ++e) {
-        double tr[3][3];
-        load_tri(m, vt_ids[e], tr);
-        double ux = tr[1][0] - tr[0][0], uy = tr[1][1] - tr[0][1], uz = tr[1][2] - tr[0][2];
-        double wx = tr[2][0] - tr[0][0], wy = tr[2][1] - tr[0][1], wz = tr[2][2] - tr[0][2];
-        n[0] += uy * wz - uz * wy;
-        n[1] += uz * wx - ux * wz;
-        n[2] += ux * wy - uy * wx;
-      }
-      double nl = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-      n[0] /= nl;
-      n[1] /= nl;
-      n[2] /= nl;
-      /* 3. tangents completing a right-handed orthonormal frame (Duff et al.,
-         "Building an orthonormal basis, revisited", JCGT 2017) */
-      double sg = copysign(1.0, n[2]);
-      double ca = -1.0 / (sg + n[2]);
-      double cb = n[0] * n[1] * ca;
-      double frame[9] = {1.0 + sg * n[0] * n[0] * ca, sg * cb, -sg * n[0],
-                         cb, sg + n[1] * n[1] * ca, -n[1],
-                         n[0], n[1], n[2]};
-      /* 4. ring neighbourhood: T_1 = triangles at the vertex, T_{r+1} =
-         triangles sharing a vertex with T_r */
-      ++stamp;
-      int32_t nvl = 1, ntl = 0;
-      vlist[0] = vs;
-      vmark[vs] = stamp;
-      for (int32_t r = 1; r <= prm->rings; ++r) {
-        ntl = 0;
-        ++stamp;
-        for (int32_t a = 0; a < nvl; ++a)
-          for (int32_t e = vt_off[vlist[a]]; e < vt_off[vlist[a] + 1]; ++e) {
-            int32_t t = vt_ids[e];
-            if (tmark[t] != stamp) {
-              tmark[t] = stamp;
-              tlist[ntl++] = t;
-            }
-          }
-        if (r == prm->rings) break;
-        int32_t nn2 = 0;
-        for (int32_t a = 0; a < ntl; ++a) {
-          const int32_t c[3] = {m->t0[tlist[a]], m->t1[tlist[a]], m->t2[tlist[a]]};
-          for (int s = 0; s < 3; ++s)
-            if (vmark[c[s]] != stamp) {
-              vmark[c[s]] = stamp;
-              vnext[nn2++] = c[s];
-            }
-        }
-        memcpy(vlist, vnext, sizeof(int32_t) * (size_t)nn2);
-        nvl = nn2;
-      }
-      qsort(tlist, (size_t)ntl, sizeof(int32_t), cmp_i32);
-      /* 5. distances of the triangle centres to the cell centre */
-      for (int32_t a = 0; a < ntl; ++a) {
-        double tr[3][3];
-        load_tri(m, tlist[a], tr);
-        memcpy(tri + 9 * a, tr, sizeof(double) * 9);
-        double cx = (tr[0][0] + tr[1][0] + tr[2][0]) / 3.0;
-        double cy = (tr[0][1] + tr[1][1] + tr[2][1]) / 3.0;
-        double cz = (tr[0][2] + tr[1][2] + tr[2][2]) / 3.0;
-        double dx = cx - xc[0], dy = cy - xc[1], dz = cz - xc[2];
-        d2[a] = dx * dx + dy * dy + dz * dz;
-      }
-      /* 6. support radius: grow until enough triangles have non-zero weight */
-      double delta = prm->delta_over_h * h;
-      int32_t it = 0, cnt = 0;
-      for (;;) {
-        double lim = delta * delta;
-        cnt = 0;
-        for (int32_t a = 0; a < ntl; ++a) cnt += d2[a] < lim;
-        if (cnt >= prm->n_min || cnt == ntl || it == prm->max_iter) break;
-        delta = delta * prm->grow;
-        ++it;
-      }
-      /* 7. Wendland C2 weights */
-      double lim = delta * delta;
-      for (int32_t a = 0; a < ntl; ++a) {
-        if (d2[a] < lim) {
-          double qq = sqrt(d2[a]) / delta;
-          double om = 1.0 - qq;
-          wts[a] = (1.0 + 4.0 * qq) * (om * om) * (om * om);
-        } else {
-          wts[a] = 0.0;
-        }
-      }
-      /* 8. volume fit, curvature and interface normal */
-      double co[6];
-      int32_t st = ora_fit(frame, xc, h, ntl, tri, wts, co);
-      double kap = st ? NAN : ora_kappa(co);
-      double ni[3] = {NAN, NAN, NAN};
-      if (!st) {
-        for (int d = 0; d < 3; ++d) ni[d] = frame[6 + d] - co[1] * frame[d] - co[2] * frame[3 + d];
-        double l = sqrt(ni[0] * ni[0] + ni[1] * ni[1] + ni[2] * ni[2]);
-        for (int d = 0; d < 3; ++d) ni[d] /= l;
-      }
+      int32_t ntl, st, dg[4];
+      double delta, kap, ni[3], co[6];
+      ppic_cell(g, m, prm, vt_off, vt_ids, cell_ids[q], &s, &ntl, &delta, &kap, ni, co, &st, dg);
       if (kappa) kappa[q] = kap;
       if (nrm)
         for (int d = 0; d < 3; ++d) nrm[3 * q + d] = ni[d];
       if (coeff)
         for (int c = 0; c < 6; ++c) coeff[6 * q + c] = co[c];
       if (status) status[q] = st;
-      if (diag) {
-        diag[4 * q + 0] = vs;
-        diag[4 * q + 1] = ntl;
-        diag[4 * q + 2] = cnt;
-        diag[4 * q + 3] = it;
-      }
+      if (diag)
+        for (int d = 0; d < 4; ++d) diag[4 * q + d] = dg[d];
     }
-    free(tmark);
-    free(vmark);
-    free(tlist);
-    free(vlist);
-    free(vnext);
-    free(d2);
-    free(wts);
-    free(tri);
+    scratch_free(&s);
   }
   free(vt_off);
   free(vt_ids);
   return 0;
+}
+
+int32_t ora_ppic_support(const ora_grid* g, const ora_mesh* m, const ora_ppic_params* prm, int64_t cell_id,
+                         int32_t cap, int32_t* tri_out, double* d2_out, double* w_out, double* delta_out) {
+  if (!grid_ok(g) || !mesh_ok(m) || !ppic_params_ok(prm) || cap < 0 || !tri_out || !d2_out || !w_out ||
+      !delta_out || cell_id < 0 || cell_id >= (int64_t)g->nx * g->ny * g->nz)
+    return -1;
+  int32_t *vt_off, *vt_ids;
+  vertex_triangles(m, &vt_off, &vt_ids);
+  ppic_scratch s;
+  scratch_init(&s, m->nv, m->nt);
+  int32_t ntl, st, dg[4];
+  double kap, ni[3], co[6];
+  ppic_cell(g, m, prm, vt_off, vt_ids, cell_id, &s, &ntl, delta_out, &kap, ni, co, &st, dg);
+  for (int32_t a = 0; a < ntl && a < cap; ++a) {
+    tri_out[a] = s.tlist[a];
+    d2_out[a] = s.d2[a];
+    w_out[a] = s.wts[a];
+  }
+  scratch_free(&s);
+  free(vt_off);
+  free(vt_ids);
+  return ntl;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -69,6 +69,17 @@ int32_t ora_ppic(const ora_grid* g, const ora_mesh* m, const ora_ppic_params* p,
                  int64_t ncell, const int64_t* cell_ids, double* kappa,
                  double* nrm, double* coeff, int32_t* status, int32_t* diag);
 
+/* The support of one cell's volume fit (paper sec. 3.2, Eq. Wendland), for
+   tests: the ring triangles in ascending order (tri_out), the squared
+   distances of their centres to the cell centre (d2_out) and their Wendland
+   weights (w_out), at most cap of each, and the final support radius
+   (*delta_out), exactly as ora_ppic computes them for the cell with linear
+   id cell_id.  Returns the ring size (entries past cap are not written) or
+   -1. */
+int32_t ora_ppic_support(const ora_grid* g, const ora_mesh* m, const ora_ppic_params* p,
+                         int64_t cell_id, int32_t cap, int32_t* tri_out, double* d2_out,
+                         double* w_out, double* delta_out);
+
 /* Input of the learned curvature surrogate: per listed cell, the front
    vertex closest to the cell centre (lowest index on ties) and its squared
    distance, and that vertex's normal, the normalised sum of the cross

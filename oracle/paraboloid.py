@@ -26,15 +26,38 @@ inner one is told the y at which its integrand has a kink (F(x, y, -+1/2) =
 0, or a double root in z), the outer one the x at which those kink curves
 meet the cube edges, each other, or turn along y; all are roots of
 quadratics.  Accurate to about 1e-15 on the unit cube.
+
+Every quadrature here goes through _quad, which fails loudly: QUADPACK's own
+estimate of the absolute error of each integral must not exceed
+QUAD_ERR_BOUND (1e-13 in cell units, two orders below the 1e-12 to which
+the GPU's alpha is compared), whatever return code it gives, or the oracle
+raises QuadratureError instead of returning an unconverged value.
 """
 from __future__ import annotations
-
-import warnings
 
 import numpy as np
 from scipy import integrate
 
 TOL = 1e-14
+QUAD_ERR_BOUND = 1e-13
+
+
+class QuadratureError(RuntimeError):
+    """A quadrature of this oracle did not reach its stated accuracy."""
+
+
+def _quad(f, a, b, **kw):
+    """integrate.quad with its error estimate checked: the value, or
+    QuadratureError when the estimate exceeds QUAD_ERR_BOUND or the value is
+    not finite.  QUADPACK stopping short of `tol` because of round-off (its
+    return code 2) is accepted as long as the estimate stays in bound."""
+    r = integrate.quad(f, a, b, full_output=1, **kw)
+    val, err = r[0], r[1]
+    if not (np.isfinite(val) and err <= QUAD_ERR_BOUND):
+        msg = r[3] if len(r) > 3 else ""
+        raise QuadratureError(f"quadrature over [{a}, {b}] gave {val!r} with error estimate {err:.3e} "
+                              f"(bound {QUAD_ERR_BOUND:.0e}): {msg}")
+    return val
 
 
 def duff_frame(n):
@@ -163,14 +186,9 @@ def alpha_unit(n, t1, t2, b, tol: float = TOL) -> float:
 
     def area(x):
         pts = Q.y_kinks(x)
-        return integrate.quad(lambda y: Q.z_length(x, y), -0.5, 0.5, points=pts or None, epsabs=tol, epsrel=tol,
-                              limit=200)[0]
+        return _quad(lambda y: Q.z_length(x, y), -0.5, 0.5, points=pts or None, epsabs=tol, epsrel=tol, limit=200)
 
-    with warnings.catch_warnings():
-        # QUADPACK reports that round-off stops it short of 1e-14; the result
-        # is then as accurate as double precision allows
-        warnings.simplefilter("ignore", integrate.IntegrationWarning)
-        return integrate.quad(area, -0.5, 0.5, points=Q.x_kinks() or None, epsabs=tol, epsrel=tol, limit=400)[0]
+    return _quad(area, -0.5, 0.5, points=Q.x_kinks() or None, epsabs=tol, epsrel=tol, limit=400)
 
 
 def cell_units(coeff, h):
@@ -304,16 +322,12 @@ def surface_unit(n, t1, t2, b, tol: float = 1e-13):
         for a, c in zip(cuts[:-1], cuts[1:]):
             if c <= a or not inside(xi, 0.5 * (a + c)):
                 continue
-            s += integrate.quad(lambda e: integrand(xi, e, what), a, c, epsabs=tol, epsrel=tol, limit=200)[0]
+            s += _quad(lambda e: integrand(xi, e, what), a, c, epsabs=tol, epsrel=tol, limit=200)
         return s
 
     pts = _surface_kinks_xi(n, t1, t2, b)
-    vals = []
-    with warnings.catch_warnings():
-        warnings.simplefilter("ignore", integrate.IntegrationWarning)
-        for what in range(5):
-            vals.append(integrate.quad(lambda x: slice_integral(x, what), -R, R, points=pts or None, epsabs=tol,
-                                       epsrel=tol, limit=400)[0])
+    vals = [_quad(lambda x: slice_integral(x, what), -R, R, points=pts or None, epsabs=tol, epsrel=tol, limit=400)
+            for what in range(5)]
     return vals[0], vals[1], np.array(vals[2:])
 
 

@@ -229,3 +229,14 @@ def test_sphere_cell_curvature_close_to_frame_curvature(oracle):
     kc, nc = PB.surface_cells(fn[pick], r["coeff"][pick], g.h)
     assert np.all(np.abs(kc / r["kappa"][pick] - 1) < 0.05)
     assert np.all(np.einsum("ij,ij->i", nc, r["normal"][pick]) > np.cos(np.radians(5)))
+
+
+def test_unconverged_quadrature_raises():
+    """The oracle's quadratures fail loudly: an integral that QUADPACK cannot
+    bring within the stated error bound (here a kink it is not told about,
+    with a single subinterval allowed) raises instead of returning a value."""
+    with pytest.raises(PB.QuadratureError):
+        PB._quad(lambda x: abs(x - 0.3), -0.5, 0.5, epsabs=1e-14, epsrel=1e-14, limit=1)
+    # told about the kink, the same integral is exact
+    assert abs(PB._quad(lambda x: abs(x - 0.3), -0.5, 0.5, points=[0.3], epsabs=1e-14, epsrel=1e-14)
+               - (0.8 ** 2 + 0.2 ** 2) / 2) < 1e-15
