@@ -449,11 +449,12 @@ ftc_status ftc_smooth_rough_edges(ftc_cells* cells, const ftc_grid* grid, const 
    cell lists, decisions and PPIC results; the column chunking changes the
    order in which fluxes are summed, so volume fractions may differ in the
    last bits.
-     ring_lanes    : lanes per interfacial cell in the PPIC ring pass, 8 or 16;
+     ring_lanes    : lanes per interfacial cell in the fast PPIC shape, 4, 8
+                     or 16;
      column_chunks : z-chunks (wavefronts) per 64-column block of the
                      volume-fraction column pass, 4, 8 or 16;
-     ring_blocks   : workgroups of the ring pass, 0 for one per group of
-                     cells, else a persistent grid of that many (<= 65536).
+     ring_blocks   : workgroups of the fast PPIC shape, 0 for one per group
+                     of cells, else a persistent grid of that many (<= 65536).
    Defaults: 8 lanes, 16 chunks for nz <= 256 and 4 above, one workgroup
    per group (the fastest shapes measured on fronts of 28k to 223k
    interfacial cells on 128^3 to 512^3).

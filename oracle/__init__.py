@@ -148,6 +148,14 @@ def threads() -> int:
     return int(_load().ora_threads())
 
 
+def set_threads(n: int) -> None:
+    """Threads of the following oracle calls (n <= 0: one per processor)."""
+    lib = _load()
+    lib.ora_set_threads.argtypes = [C.c_int32]
+    lib.ora_set_threads.restype = None
+    lib.ora_set_threads(int(n))
+
+
 def candidate_bound(grid, mesh) -> int:
     k = _Keep(grid, mesh)
     return int(_load().ora_candidate_bound(C.byref(k.g), C.byref(k.m)))

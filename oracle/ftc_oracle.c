@@ -982,3 +982,11 @@ int32_t ora_threads(void) {
   return 1;
 #endif
 }
+
+void ora_set_threads(int32_t n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+  (void)n;
+#endif
+}

@@ -142,6 +142,8 @@ void ora_interp_in_cell(const ora_grid* g, int32_t i, int32_t j, int32_t k,
 
 /* Threads the oracle's parallel loops use (OpenMP), for reporting. */
 int32_t ora_threads(void);
+/* Threads of the following calls (n <= 0: one per processor). */
+void ora_set_threads(int32_t n);
 
 #ifdef __cplusplus
 }

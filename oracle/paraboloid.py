@@ -29,8 +29,9 @@ quadratics.  Accurate to about 1e-15 on the unit cube.
 
 Every quadrature here goes through _quad, which fails loudly: QUADPACK's own
 estimate of the absolute error of each integral must not exceed
-QUAD_ERR_BOUND (1e-13 in cell units, two orders below the 1e-12 to which
-the GPU's alpha is compared), whatever return code it gives, or the oracle
+QUAD_ERR_BOUND (1e-13 in cell units, an order below the 1e-12 to which the
+GPU's alpha is compared), or else the same integral over a refined
+partition must agree with it within that bound; otherwise the oracle
 raises QuadratureError instead of returning an unconverged value.
 """
 from __future__ import annotations
@@ -46,18 +47,35 @@ class QuadratureError(RuntimeError):
     """A quadrature of this oracle did not reach its stated accuracy."""
 
 
-def _quad(f, a, b, **kw):
+def _quad(f, a, b, points=None, **kw):
     """integrate.quad with its error estimate checked: the value, or
-    QuadratureError when the estimate exceeds QUAD_ERR_BOUND or the value is
-    not finite.  QUADPACK stopping short of `tol` because of round-off (its
-    return code 2) is accepted as long as the estimate stays in bound."""
-    r = integrate.quad(f, a, b, full_output=1, **kw)
+    QuadratureError.  QUADPACK stopping short of `tol` because of round-off
+    (its return code 2) is accepted when the estimate stays in bound.  Its
+    estimate is pessimistic where the integrand is itself a quadrature
+    (noise at the 1e-16 level between nearby abscissae), so an estimate above
+    the bound is checked once more: the integral is recomputed as the sum of
+    separate quadratures over the breakpoint intervals, each split at its
+    midpoint, and the value is accepted only if both results are finite and
+    agree within QUAD_ERR_BOUND."""
+    pts = sorted(p for p in (points or []) if a < p < b)
+    r = integrate.quad(f, a, b, points=pts or None, full_output=1, **kw)
     val, err = r[0], r[1]
-    if not (np.isfinite(val) and err <= QUAD_ERR_BOUND):
-        msg = r[3] if len(r) > 3 else ""
-        raise QuadratureError(f"quadrature over [{a}, {b}] gave {val!r} with error estimate {err:.3e} "
-                              f"(bound {QUAD_ERR_BOUND:.0e}): {msg}")
-    return val
+    if np.isfinite(val) and err <= QUAD_ERR_BOUND:
+        return val
+    cuts = [a] + pts + [b]
+    fine = []
+    for lo, hi in zip(cuts[:-1], cuts[1:]):
+        fine += [lo, 0.5 * (lo + hi)]
+    fine.append(b)
+    check = 0.0
+    for lo, hi in zip(fine[:-1], fine[1:]):
+        if hi > lo:
+            check += integrate.quad(f, lo, hi, full_output=1, **kw)[0]
+    if np.isfinite(val) and np.isfinite(check) and abs(check - val) <= QUAD_ERR_BOUND:
+        return val
+    msg = r[3] if len(r) > 3 else ""
+    raise QuadratureError(f"quadrature over [{a}, {b}] gave {val!r} with error estimate {err:.3e} and "
+                          f"{check!r} over a refined partition (bound {QUAD_ERR_BOUND:.0e}): {msg}")
 
 
 def duff_frame(n):

@@ -146,6 +146,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(vt_loc, 3 * Tc);
   FTC_ALLOC(vt_ids, 3 * Tc);
   FTC_ALLOC(tri4, 4 * Tc);
+  FTC_ALLOC(vinc, 4 * ftc::kIncSlots * Vc);
   FTC_ALLOC(vtx4, 4 * Vc);
   FTC_ALLOC(ovf_cells, Cc);
   FTC_ALLOC(vcell, Vc);
@@ -154,9 +155,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(vb_loc, Vc);
   FTC_ALLOC(vb_ids, Vc);
   FTC_ALLOC(stray, Vc);
-  FTC_ALLOC(fit, ftc::kFitSlots * Cc);
-  FTC_ALLOC(wl_tri, ftc::kFitList * Cc);
-  FTC_ALLOC(wl_w, ftc::kFitList * Cc);
+  FTC_ALLOC(frame_n, 3 * Cc);
   FTC_ALLOC(best_d2, Cc);
   FTC_ALLOC(best_v, Cc);
   FTC_ALLOC(sel_cells, Cc);
@@ -435,7 +434,7 @@ ftc_status ftc_get_tuning(const ftc_cells* cells, ftc_tuning* out) {
 
 ftc_status ftc_set_tuning(ftc_cells* cells, const ftc_tuning* in) {
   if (!cells || !in) return FTC_EINVAL;
-  if ((in->ring_lanes != 8 && in->ring_lanes != 16) ||
+  if ((in->ring_lanes != 4 && in->ring_lanes != 8 && in->ring_lanes != 16) ||
       (in->column_chunks != 4 && in->column_chunks != 8 && in->column_chunks != 16) || in->ring_blocks < 0 ||
       in->ring_blocks > 65536)
     return FTC_EINVAL;

@@ -9,9 +9,8 @@
 
 // Counter slots in ftc_cells::counters (device int32).
 namespace ftc {
-constexpr int kFitSlots = 32;  // doubles per cell in ftc_cells::fit
-constexpr int kFitList = 64;   // weighted-triangle list entries per cell
-constexpr int kQuadNodes = 48;  // 16 nodes and weights (xi rule) + 8 and 8 (eta rule)
+constexpr int kQuadNodes = 48;
+constexpr int kIncSlots = 8;  // incident triangles of a vertex in its record (ftc_cells::vinc)  // 16 nodes and weights (xi rule) + 8 and 8 (eta rule)
 enum : int {
   C_NIF = 0,      // interfacial cells of the last build
   C_NPAIRS = 1,   // (cell, triangle) pieces of the last build
@@ -19,8 +18,8 @@ enum : int {
   C_NQUEUE = 3,   // candidates queued for full clipping
   C_NWHOLE = 4,   // pieces that are whole triangles
   C_NSTRAY = 5,   // vertices in cells without pieces
-  C_NOVF = 6,     // interfacial cells whose ring exceeds the fast PPIC kernel's capacities
-  C_NQUEUED = 7,  // C_NOVF as the wide PPIC shape reads it (moved there by the fit pass)
+  C_NOVF = 6,     // interfacial cells queued for the wide PPIC shape
+  C_WIDE_DONE = 7,  // workgroups of the wide PPIC shape that have read the queue's count
   C_NSEL = 8,      // cells the learned curvature hands to PPIC (cleared after the PPIC kernel)
   C_SPARE = 9,     // unused
   C_RFLAG = 10,    // edges listed for roughness smoothing
@@ -32,9 +31,9 @@ enum : int {
 namespace ftc {
 // Launch shapes chosen per workspace (ftc_set_tuning; defaults below).
 struct Tuning {
-  int32_t ring_lanes = 8;     // lanes per cell in the PPIC ring pass: 8 or 16
+  int32_t ring_lanes = 8;     // lanes per cell in the fast PPIC shape: 4, 8 or 16
   int32_t column_chunks = 16;  // z-chunks (wavefronts) per column block: 4, 8 or 16 (set from nz at creation)
-  int32_t ring_blocks = 0;    // workgroups of the ring pass: 0 = one per cell group, else a persistent grid
+  int32_t ring_blocks = 0;    // workgroups of the fast PPIC shape: 0 = one per cell group, else a persistent grid
 };
 }  // namespace ftc
 
@@ -84,17 +83,16 @@ struct ftc_cells {
   int32_t* vt_loc;        // [3*nt_cap] index of each (triangle, corner) within the corner's list
   int32_t* vt_ids;        // [3*nt_cap] incident triangles, ascending per vertex
   int32_t* tri4;          // [4*nt_cap] corners of each triangle packed (t0, t1, t2, 0)
+  int32_t* vinc;          // [4*kIncSlots*nv_cap] per vertex: (t0, t1, t2, degree) of its incident triangles, ascending
   double* vtx4;           // [4*nv_cap] coordinates of each vertex packed (x, y, z, 0)
-  int32_t* ovf_cells;     // [cell_cap] cells queued for the wide PPIC kernel
+  int32_t* ovf_cells;     // [cell_cap] cells queued for the wide PPIC shape
   int32_t* vcell;         // [nv_cap] interfacial cell holding each vertex (-1: none, -2: outside)
   int32_t* vb_off;        // [cell_cap+1] offsets of each interfacial cell's vertices
   int32_t* vb_cursor;     // [cell_cap] vertices per cell while counting; zero between calls
   int32_t* vb_loc;        // [nv_cap] index of each vertex within its cell's bin
   int32_t* vb_ids;        // [nv_cap] vertices grouped by interfacial cell
   int32_t* stray;         // [nv_cap] vertices in cells without pieces
-  double* fit;            // [kFitSlots * cell_cap] per cell: normal equations (21 + 6), vertex normal (3), weighted count
-  int32_t* wl_tri;        // [cell_cap * kFitList] the triangles of each cell's fit
-  double* wl_w;           // [cell_cap * kFitList] their weights
+  double* frame_n;        // [3 * cell_cap] frame normal of each cell's volume fit
   double* quad_nodes;     // [kQuadNodes] quadrature nodes and weights of the paraboloid cell integrals
   int32_t* sel_cells;     // [cell_cap] cells the learned curvature hands to PPIC
   // roughness detection and smoothing

@@ -392,7 +392,7 @@ __device__ inline void xi_event(const Local& L, int e, double& v0, double& v1) {
 }
 
 template <bool kSurf>
-__device__ void paraboloid_cells(const double* fit, const double* coeff, double h, const int32_t* counters,
+__device__ void paraboloid_cells(const double* frame_n, const double* coeff, double h, const int32_t* counters,
                                  int32_t cell_cap, Nodes N, double* alpha_out, double* kappa_out, double* normal_out) {
   __shared__ double ev[kSlots];
   __shared__ double xs[kSlots];
@@ -400,7 +400,7 @@ __device__ void paraboloid_cells(const double* fit, const double* coeff, double 
   const int32_t nif = min(counters[C_NIF], cell_cap);
   const int64_t cs = cell_cap;
   for (int32_t c = blockIdx.x; c < nif; c += gridDim.x) {
-    const double n[3] = {fit[27 * cs + c], fit[28 * cs + c], fit[29 * cs + c]};
+    const double n[3] = {frame_n[c], frame_n[cs + c], frame_n[2 * cs + c]};
     double a[6];
 #pragma unroll
     for (int r = 0; r < 6; ++r) a[r] = coeff[r * cs + c];
@@ -491,15 +491,15 @@ __device__ void paraboloid_cells(const double* fit, const double* coeff, double 
 // spilled: 412 -> 373 us on the 128^3 sphere); with the surface integrals
 // the spills cost more than the occupancy gains, so that kernel keeps two.
 __global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(3))) void k_paraboloid_alpha(
-    const double* fit, const double* coeff, double h, const int32_t* counters, int32_t cell_cap, Nodes N,
+    const double* frame_n, const double* coeff, double h, const int32_t* counters, int32_t cell_cap, Nodes N,
     double* alpha_out) {
-  paraboloid_cells<false>(fit, coeff, h, counters, cell_cap, N, alpha_out, nullptr, nullptr);
+  paraboloid_cells<false>(frame_n, coeff, h, counters, cell_cap, N, alpha_out, nullptr, nullptr);
 }
 
-__global__ __launch_bounds__(kT) void k_paraboloid_surface(const double* fit, const double* coeff, double h,
+__global__ __launch_bounds__(kT) void k_paraboloid_surface(const double* frame_n, const double* coeff, double h,
                                                            const int32_t* counters, int32_t cell_cap, Nodes N,
                                                            double* alpha_out, double* kappa_out, double* normal_out) {
-  paraboloid_cells<true>(fit, coeff, h, counters, cell_cap, N, alpha_out, kappa_out, normal_out);
+  paraboloid_cells<true>(frame_n, coeff, h, counters, cell_cap, N, alpha_out, kappa_out, normal_out);
 }
 
 // 16-point Gauss-Legendre rule on [-1, 1] by Newton's method on the Legendre
@@ -573,10 +573,10 @@ hipError_t launch_paraboloid_cell(const ftc_cells* ws, const double* coeff, doub
   const Nodes N{ws->quad_nodes};
   const dim3 grid(grid_blocks(ws->cell_cap, 1, 65535));
   if (kappa_out || normal_out)
-    hipLaunchKernelGGL(k_paraboloid_surface, grid, dim3(kT), 0, s, ws->fit, coeff, ws->grid.h, ws->counters,
+    hipLaunchKernelGGL(k_paraboloid_surface, grid, dim3(kT), 0, s, ws->frame_n, coeff, ws->grid.h, ws->counters,
                        ws->cell_cap, N, alpha_out, kappa_out, normal_out);
   else
-    hipLaunchKernelGGL(k_paraboloid_alpha, grid, dim3(kT), 0, s, ws->fit, coeff, ws->grid.h, ws->counters,
+    hipLaunchKernelGGL(k_paraboloid_alpha, grid, dim3(kT), 0, s, ws->frame_n, coeff, ws->grid.h, ws->counters,
                        ws->cell_cap, N, alpha_out);
   return hipGetLastError();
 }

@@ -8,47 +8,43 @@
 // block is at least 1.5 h from the cell centre, so a best squared distance
 // below (1.5 h)^2 is final; any other cell searches all vertices here.
 //
-// Ring pass (k_ppic_rings; ppic_cells, one template for two shapes): the
-// fast shape gives 8 lanes to each interfacial cell (8 cells per wavefront)
-// and holds rings of up to 32 vertices and 64 triangles in LDS; cells whose
-// ring is larger are queued for the wide shape (64 lanes per cell, rings of
-// 256 vertices and 512 triangles), which runs in the solve launch.  Cells are assigned so that each XCD
-// processes a contiguous range, which keeps each L2 on one part of the front.
-//   1. ring neighbourhood: V_0 = {v*}; T_r = triangles with a corner in
-//      V_{r-1}; V_r = V_{r-1} plus the corners of T_r.  Built incrementally:
-//      a triangle with a corner in V_{r-2} is already in T_{r-1}, so the
-//      candidates of ring r are the incident triangles of the vertices new
-//      in V_{r-1}, spread over the lanes through prefix sums of their
-//      degrees.  A candidate is kept from the first of its corners (t0, t1,
-//      t2 order) that is new in V_{r-1}, and only if none of its corners lies
-//      in V_{r-2}; the ring level of every placed vertex is stored with it in
-//      an open-addressing hash table in LDS.  Corners of kept triangles that
-//      are not yet placed enter the table at once, marked with their first
-//      occurrence (3 x position + corner), and are then placed in V_r in that
-//      order;
-//   2. normal of v* (area-weighted, summed in ascending triangle order: T_1
-//      is v*'s incident list) and a right-handed tangent frame (Duff et al.,
-//      JCGT 2017);
-//   3. triangle-centre distances, the support radius grown by `grow` until
-//      `n_min` triangles fall inside (or the ring is exhausted, or
-//      `max_iter` adjustments), Wendland weights of the triangles inside.
-//      The fast shape writes the weighted triangles (id and weight, 12
-//      bytes each) to a per-cell list in HBM, with the frame normal and the
-//      count; the wide shape goes on with steps 4 and 5 itself.
-// Fit pass (k_ppic_fit), the cells of the fast shape, 8 lanes per cell:
-//   4. per lane: each listed triangle's corners (from the packed corner
-//      array, which stays in L2), its projection into the frame
+// The ring of a cell is T_R, with T_1 the triangles at the closest vertex v*
+// and T_{r+1} the triangles sharing a vertex with T_r.  Writing V_r for the
+// corners of T_r (V_0 = {v*}), T_r is the set of triangles with a corner in
+// V_{r-1}, and V_r is V_{r-1} plus the corners of the triangles at the
+// vertices new in V_{r-1}.
+//
+// Fast shape (k_ppic_fast), G lanes per interfacial cell, one pass:
+//   1. V_0 = {v*}; the triangles at v* give the frame normal (their cross
+//      products summed in ascending triangle order) and, for R >= 2, their
+//      corners join V (a key-only hash set in LDS, insertion order kept);
+//   2. levels 2 .. R-1: each lane takes one vertex new in the previous level
+//      and adds the corners of its triangles to V;
+//   3. the ring T_R: each lane takes vertices u of V_{R-1} and keeps a
+//      triangle at u exactly when u is its first corner (t0, t1, t2 order)
+//      that lies in V_{R-1}, so every triangle is kept once;
+//   4. one pass over the ring: triangle-centre distances, Wendland weights
+//      with delta = delta_over_h h, the triangle's projection into the frame
 //      (coordinates divided by h for conditioning), its six moments by the
 //      edge-midpoint rule (exact for quadratics) and the integral of its
-//      plane, and the weighted normal equations M a = b accumulated in
-//      registers; all-reduce over the cell's lanes with row permutations;
-//      the 27 sums are stored per cell.
-// Solve pass (k_ppic_wide_solve), one thread per cell:
-//   5. Cholesky factorisation of the packed M with one step of iterative
-//      refinement, curvature kappa = 2H at the frame origin and the
-//      interface normal.
-// Every loop bound is uniform over the wavefront (maxima over its cells), so
-// LDS phases are separated by plain workgroup barriers.
+//      plane, accumulated into the weighted normal equations M a = b;
+//      all-reduce over the cell's lanes;
+//   5. when delta needs no adjustment (at least n_min triangles inside it,
+//      or all of them, or no adjustment allowed): Cholesky factorisation of
+//      M with one step of iterative refinement, curvature kappa = 2H at the
+//      frame origin and the interface normal.
+// A cell whose vertex set or ring exceeds the fast capacities, or whose
+// support must grow, is queued for the wide shape.
+//
+// Wide shape (k_ppic_wide; k_ppic_wide_sel for the learned curvature's
+// fallback cells): 64 lanes per cell, one cell per workgroup at a time,
+// rings of up to 256 vertices and 512 triangles kept with their ring level
+// in an open-addressing hash, the support grown as the parameters allow,
+// the fit and the solve in the same workgroup.
+//
+// Every loop bound that encloses a cross-lane operation is uniform over the
+// wavefront (maxima over its cells), so LDS phases are separated by plain
+// workgroup barriers.
 #include <float.h>
 
 #include <algorithm>
@@ -63,6 +59,7 @@ constexpr int kWideBlocks = 64;  // persistent workgroups of the wide shape
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
+// Capacities of the wide shape.
 template <int G_, int HS_, int VC_, int TC_, int CR_>
 struct Cfg {
   static constexpr int G = G_;        // lanes per cell
@@ -72,18 +69,12 @@ struct Cfg {
   static constexpr int TC = TC_;      // ring-triangle capacity
   static constexpr int CR = CR_;      // candidates per lane per batch
   static constexpr int Batch = CR_ * G_;
-  static constexpr int TR = (TC_ + G_ - 1) / G_;
   static constexpr int FW = (3 * TC_ + 31) / 32;  // words of the first-occurrence bitmap
   static_assert((HS_ & (HS_ - 1)) == 0 && HS_ >= 2 * VC_, "hash size");
   static_assert(VC_ <= 256, "owner table holds bytes");
 };
-using Fast = Cfg<8, 64, 32, 64, 6>;
-// the same capacities with 16 lanes per cell (4 cells per wavefront): the
-// queue to the wide shape, and so every result, is the same as Fast's
-using Fast16 = Cfg<16, 64, 32, 64, 3>;
 using Wide = Cfg<64, 512, 256, 512, 4>;
 
-// ----------------------------------------------------------------- main kernel
 struct PPICArgs {
   Grid g;
   int32_t nv;
@@ -93,13 +84,12 @@ struct PPICArgs {
   const int32_t* cell_ids;
   const int32_t* vt_off;
   const int32_t* vt_ids;
+  const int4* vinc;  // per vertex: (t0, t1, t2, degree) of its incident triangles, ascending
   const double* best_d2;
   const int32_t* best_v;
   int32_t* counters;
   int32_t* ovf_cells;
-  double* fit;
-  int32_t* wl_tri;  // per cell: the triangles of its fit (ids; the fit pass reads their corners)
-  double* wl_w;
+  double* frame_n;  // [3][cell_cap] frame normal of each cell (the paraboloid cell integrals read it)
   int32_t cell_cap;
   double *kappa, *nx, *ny, *nz, *coeff;
   int32_t *status, *diag;
@@ -107,71 +97,9 @@ struct PPICArgs {
   int32_t* n_sel_out;  // receives the selection's count (may be null)
 };
 
-
-
-// Ring-building state, dead once the rings are complete.
-template <class C>
-struct RingMem {
-  int32_t hkey[C::HS];    // hash set of vertices: -1 empty, v new in this ring, v | kPlaced in V
-  int32_t hval[C::HS];    // new vertex: first occurrence (3 x position + corner); placed: its ring
-  int32_t V[C::VC];       // ring vertices
-  int32_t Vo[C::VC];      // offset of their incident-triangle lists
-  int32_t Vs[C::VC + 1];  // prefix sums of their degrees
-  uint32_t fbits[C::FW];  // first occurrences of the new vertices of the current ring
-  uint8_t own[C::Batch];  // ring vertex of each candidate of the current batch
-};
-// Fit state, alive after the rings.
-template <class C>
-struct FitMem {
-  double W[C::TC];   // weights of the triangles inside the support
-  int32_t S[C::TC];  // those triangles
-};
-template <class C>
-struct __align__(8) CellMem {
-  union {
-    RingMem<C> r;
-    FitMem<C> f;
-  } u;
-  int32_t T[C::TC];  // ring triangles
-};
-
-constexpr int32_t kPlaced = INT32_MIN;  // vertex ids are below 2^31 - 1, so key | kPlaced != -1
-
 template <int HS>
 __device__ inline int hslot(int32_t key) {
   return (int)(((uint32_t)key * 2654435761u) >> (32 - ilog2(HS)));
-}
-
-// Insert a key that is not placed (if absent, as a new vertex) and return
-// its slot; -1 if the table is full.
-template <class C>
-__device__ inline int hinsert(RingMem<C>& M, int32_t key) {
-  int s = hslot<C::HS>(key);
-#pragma unroll 1
-  for (int p = 0; p < C::HS; ++p) {
-    const int32_t prev = atomicCAS(&M.hkey[s], -1, key);
-    if (prev == -1 || prev == key) return s;
-    s = (s + 1) & (C::HS - 1);
-  }
-  return -1;
-}
-
-// Ring of the vertex key if it is placed in V (0 for v*), else -1.  home is
-// the table entry at the key's home slot, read beforehand.
-template <class C>
-__device__ inline int ring_of(const RingMem<C>& M, int32_t key, int32_t home) {
-  const int32_t placed = key | kPlaced;
-  int s = hslot<C::HS>(key);
-  if (home == placed) return M.hval[s];
-  if (home == -1 || home == key) return -1;
-#pragma unroll 1
-  for (int p = 0; p < C::HS; ++p) {
-    s = (s + 1) & (C::HS - 1);
-    const int32_t k = M.hkey[s];
-    if (k == placed) return M.hval[s];
-    if (k == -1 || k == key) return -1;
-  }
-  return -1;
 }
 
 // Ballot of this lane's group, in the group's low bits.
@@ -212,6 +140,45 @@ __device__ inline double group_sum(double v) {
   if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
   if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
+}
+
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// group_sum in single precision
+template <int G>
+__device__ inline float group_sum_f(float v) {
+  if constexpr (G >= 2) v += dpp_f<0xB1>(v);
+  if constexpr (G >= 4) v += dpp_f<0x4E>(v);
+  if constexpr (G >= 8) v += dpp_f<0x141>(v);
+  if constexpr (G >= 16) v += dpp_f<0x140>(v);
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Integer sum over each aligned group of G lanes.
+template <int G>
+__device__ inline int group_sum_i(int v) {
+#pragma unroll
+  for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Exclusive prefix sum over the lanes of each aligned group of G lanes (gl
+// the lane's index in its group), and the group's total in *total.
+template <int G>
+__device__ inline int group_excl_scan(int v, int gl, int* total) {
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    const int t = __shfl_up(inc, o, G);
+    if (gl >= o) inc += t;
+  }
+  *total = __shfl(inc, G - 1, G);
+  return inc - v;
 }
 
 // x / 3 correctly rounded: a product with the rounded reciprocal, corrected
@@ -275,143 +242,319 @@ __device__ inline void chol6_solve(const T* L, const T* invd, const double* rhs,
   }
 }
 
+// The local frame of a cell: origin xc (the cell centre), tangents t1, t2
+// completing the frame normal n to a right-handed orthonormal basis (Duff
+// et al., JCGT 2017), and 1/h.
+struct Frame {
+  double xc[3];
+  double t1[3], t2[3], n[3];
+  double inv_h;
+};
+
+__device__ inline void duff_tangents(double n0, double n1, double n2, double t1[3], double t2[3]) {
+  const double sg = copysign(1.0, n2);
+  const double fa = -1.0 / (sg + n2);
+  const double fb = n0 * n1 * fa;
+  t1[0] = 1.0 + sg * n0 * n0 * fa;
+  t1[1] = sg * fb;
+  t1[2] = -sg * n0;
+  t2[0] = fb;
+  t2[1] = sg + n1 * n1 * fa;
+  t2[2] = -n1;
+}
+
+// Moments of one triangle (corners a, b, e) in the h-scaled frame, in type
+// T: mom = integrals over its projection of (1, xi, eta, xi^2, xi eta,
+// eta^2) by the edge-midpoint rule, vt = the integral of its plane.  The
+// differences to the frame origin are taken in double precision.
+template <class T>
+__device__ inline void tri_moments(const Frame& F, const P3& a, const P3& b, const P3& e, T mom[6], T& vt) {
+  const P3 p[3] = {a, b, e};
+  T xi[3], eta[3], zeta[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T dx = (T)(p[c].x - F.xc[0]), dy = (T)(p[c].y - F.xc[1]), dz = (T)(p[c].z - F.xc[2]);
+    xi[c] = fma(dz, (T)F.t1[2], fma(dy, (T)F.t1[1], dx * (T)F.t1[0])) * (T)F.inv_h;
+    eta[c] = fma(dz, (T)F.t2[2], fma(dy, (T)F.t2[1], dx * (T)F.t2[0])) * (T)F.inv_h;
+    zeta[c] = fma(dz, (T)F.n[2], fma(dy, (T)F.n[1], dx * (T)F.n[0])) * (T)F.inv_h;
+  }
+  const T area = T(0.5) * fma(xi[1] - xi[0], eta[2] - eta[0], -((xi[2] - xi[0]) * (eta[1] - eta[0])));
+  T sm[6] = {T(3), T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T mx = T(0.5) * (xi[c] + xi[(c + 1) % 3]);
+    const T my = T(0.5) * (eta[c] + eta[(c + 1) % 3]);
+    sm[1] += mx;
+    sm[2] += my;
+    sm[3] = fma(mx, mx, sm[3]);
+    sm[4] = fma(mx, my, sm[4]);
+    sm[5] = fma(my, my, sm[5]);
+  }
+  const T a3 = area * (T(1) / T(3));
+#pragma unroll
+  for (int q = 0; q < 6; ++q) mom[q] = a3 * sm[q];
+  vt = a3 * (zeta[0] + zeta[1] + zeta[2]);
+}
+
+// Weight w of the triangle whose centre lies at squared distance dd, inside
+// the support of squared radius lim: Wendland's C2 function of q = d/delta.
+__device__ inline double wendland(double dd, double inv_delta) {
+  const double qq = sqrt(dd) * inv_delta;
+  const double om = 1.0 - qq;
+  return (1.0 + 4.0 * qq) * (om * om) * (om * om);
+}
+
+// Squared distance of the centre of triangle (a, b, e) to xc, each centre
+// coordinate (c0 + c1 + c2) / 3 in corner order: the support decision.
+__device__ inline double centre_d2(const P3& a, const P3& b, const P3& e, const double xc[3]) {
+  const double cx = div3(a.x + b.x + e.x);
+  const double cy = div3(a.y + b.y + e.y);
+  const double cz = div3(a.z + b.z + e.z);
+  const double dx = cx - xc[0], dy = cy - xc[1], dz = cz - xc[2];
+  return dx * dx + dy * dy + dz * dz;
+}
+
+// Accumulate w m m^T (upper triangle, packed) and w vt m.
+template <class T>
+__device__ inline void accumulate(T* acc, T w, const T mom[6], T vt) {
+  const T wv = w * vt;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    const T wa = w * mom[a];
+#pragma unroll
+    for (int b = a; b < 6; ++b) acc[P6(a, b)] = fma(wa, mom[b], acc[P6(a, b)]);
+    acc[21 + a] = fma(wv, mom[a], acc[21 + a]);
+  }
+}
+
 // One cell, by one thread: the paraboloid coefficients in the h-scaled
 // frame, scaled back, kappa = 2H at the frame origin and the interface
 // normal.  F holds the fit slots at a stride of fs: the frame normal in 27-29
-// and the weighted count in 30, and either (solved = false) the 27 sums of
-// the normal equations in 0-26, factored here by Cholesky with one step of
-// iterative refinement against the unfactored sums, or (solved = true) the
+// and the weighted count in 30 (-1: ring beyond every capacity, -2: no
+// closest vertex), and either (solved = false) the 27 sums of the normal
+// equations in 0-26, factored here by Cholesky with one step of iterative
+// refinement against the unfactored sums, or (solved = true) the
 // coefficients in 0-5 and 1 or 0 (full rank or not) in 6.
 __device__ inline void solve_cell(const PPICArgs& A, int32_t c, const double* F, int64_t fs, bool solved) {
   const int64_t cs = A.cell_cap;
   const double h = A.g.h, inv_h = 1.0 / h;
-  {
-    const double wcnt = F[30 * fs];
-    const double n0 = F[27 * fs], n1 = F[28 * fs], n2 = F[29 * fs];
-    double co[6] = {NAN, NAN, NAN, NAN, NAN, NAN};
-    double kap = NAN, ni0 = NAN, ni1 = NAN, ni2 = NAN;
-    uint32_t st = wcnt == -1.0 ? FTC_CELL_OVERFLOW : 0u;
-    if (wcnt >= 0.0) {
-      double ah[6];
-      bool have = false;
-      if (solved) {
-        have = F[6 * fs] > 0.0;
+  const double wcnt = F[30 * fs];
+  const double n0 = F[27 * fs], n1 = F[28 * fs], n2 = F[29 * fs];
+  double co[6] = {NAN, NAN, NAN, NAN, NAN, NAN};
+  double kap = NAN, ni0 = NAN, ni1 = NAN, ni2 = NAN;
+  uint32_t st = wcnt == -1.0 ? FTC_CELL_OVERFLOW : 0u;
+  if (wcnt >= 0.0) {
+    double ah[6];
+    bool have = false;
+    if (solved) {
+      have = F[6 * fs] > 0.0;
 #pragma unroll
-        for (int i2 = 0; i2 < 6; ++i2) ah[i2] = F[i2 * fs];
-      } else {
-        double acc[27];
+      for (int i2 = 0; i2 < 6; ++i2) ah[i2] = F[i2 * fs];
+    } else {
+      double acc[27];
 #pragma unroll
-        for (int qa = 0; qa < 27; ++qa) acc[qa] = F[qa * fs];
-        double invd[6];
-        have = chol6(acc, invd, 1e-14) && wcnt >= 6.0;
-        if (have) {
-          chol6_solve(acc, invd, acc + 21, ah);
-          // residual with the unfactorised matrix, read again
-          double r6[6];
+      for (int qa = 0; qa < 27; ++qa) acc[qa] = F[qa * fs];
+      double invd[6];
+      have = chol6(acc, invd, 1e-14) && wcnt >= 6.0;
+      if (have) {
+        chol6_solve(acc, invd, acc + 21, ah);
+        // residual with the unfactorised matrix, read again (the compiler
+        // barriers keep the reads of a row next to their use: the solve then
+        // holds few registers beyond the factor)
+        asm volatile("" ::: "memory");
+        double r6[6];
 #pragma unroll
-          for (int i2 = 0; i2 < 6; ++i2) {
-            double s2 = acc[21 + i2];
+        for (int i2 = 0; i2 < 6; ++i2) {
+          double s2 = acc[21 + i2];
 #pragma unroll
-            for (int p = 0; p < 6; ++p) s2 -= F[(i2 <= p ? P6(i2, p) : P6(p, i2)) * fs] * ah[p];
-            r6[i2] = s2;
-          }
-          chol6_solve(acc, invd, r6, r6);
-#pragma unroll
-          for (int i2 = 0; i2 < 6; ++i2) ah[i2] += r6[i2];
+          for (int p = 0; p < 6; ++p) s2 -= F[(i2 <= p ? P6(i2, p) : P6(p, i2)) * fs] * ah[p];
+          r6[i2] = s2;
+          asm volatile("" ::: "memory");
         }
-      }
-      if (!have) {
-        st |= FTC_CELL_RANK;
-      } else {
-        co[0] = h * ah[0];
-        co[1] = ah[1];
-        co[2] = ah[2];
-        co[3] = ah[3] * inv_h;
-        co[4] = ah[4] * inv_h;
-        co[5] = ah[5] * inv_h;
-        const double gx = co[1], gy = co[2];
-        const double num = 2.0 * co[3] * (1.0 + gy * gy) - 2.0 * gx * gy * co[4] + 2.0 * co[5] * (1.0 + gx * gx);
-        const double sq = 1.0 + gx * gx + gy * gy;
-        kap = -num / (sq * sqrt(sq));
-        // the tangents of the frame again (Duff et al.)
-        const double sg = copysign(1.0, n2);
-        const double fa = -1.0 / (sg + n2);
-        const double fb = n0 * n1 * fa;
-        const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
-        const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
-        ni0 = n0 - co[1] * t1x - co[2] * t2x;
-        ni1 = n1 - co[1] * t1y - co[2] * t2y;
-        ni2 = n2 - co[1] * t1z - co[2] * t2z;
-        const double il = 1.0 / sqrt(ni0 * ni0 + ni1 * ni1 + ni2 * ni2);
-        ni0 *= il;
-        ni1 *= il;
-        ni2 *= il;
+        chol6_solve(acc, invd, r6, r6);
+#pragma unroll
+        for (int i2 = 0; i2 < 6; ++i2) ah[i2] += r6[i2];
       }
     }
-    A.kappa[c] = kap;
-    A.nx[c] = ni0;
-    A.ny[c] = ni1;
-    A.nz[c] = ni2;
-    if (A.coeff)
-      for (int qa = 0; qa < 6; ++qa) A.coeff[qa * cs + c] = st ? NAN : co[qa];
-    if (A.status) A.status[c] = (int32_t)st;
+    if (!have) {
+      st |= FTC_CELL_RANK;
+    } else {
+      co[0] = h * ah[0];
+      co[1] = ah[1];
+      co[2] = ah[2];
+      co[3] = ah[3] * inv_h;
+      co[4] = ah[4] * inv_h;
+      co[5] = ah[5] * inv_h;
+      const double gx = co[1], gy = co[2];
+      const double num = 2.0 * co[3] * (1.0 + gy * gy) - 2.0 * gx * gy * co[4] + 2.0 * co[5] * (1.0 + gx * gx);
+      const double sq = 1.0 + gx * gx + gy * gy;
+      kap = -num / (sq * sqrt(sq));
+      double t1[3], t2[3];
+      duff_tangents(n0, n1, n2, t1, t2);
+      ni0 = n0 - co[1] * t1[0] - co[2] * t2[0];
+      ni1 = n1 - co[1] * t1[1] - co[2] * t2[1];
+      ni2 = n2 - co[1] * t1[2] - co[2] * t2[2];
+      const double il = 1.0 / sqrt(ni0 * ni0 + ni1 * ni1 + ni2 * ni2);
+      ni0 *= il;
+      ni1 *= il;
+      ni2 *= il;
+    }
   }
+  A.kappa[c] = kap;
+  A.nx[c] = ni0;
+  A.ny[c] = ni1;
+  A.nz[c] = ni2;
+  A.frame_n[c] = n0;
+  A.frame_n[cs + c] = n1;
+  A.frame_n[2 * cs + c] = n2;
+  if (A.coeff)
+    for (int qa = 0; qa < 6; ++qa) A.coeff[qa * cs + c] = st ? NAN : co[qa];
+  if (A.status) A.status[c] = (int32_t)st;
 }
 
-// The cells of one shape, processed by workgroup `bid` of `nblk` (64 lanes).
-// kQueue = false: every interfacial cell, overflowing cells queued.
-// kQueue = true: the queued cells.
-// kSel: the cells of the surrogate's selection (with the wide shape).
-template <class C, bool kQueue, bool kSel = false>
-__device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) {
-  constexpr int G = C::G, NG = C::NG;
-  __shared__ CellMem<C> SM[NG];
-  const Grid& g = A.g;
-  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
-  CellMem<C>& CM = SM[grp];
-  RingMem<C>& RM = CM.u.r;
-  FitMem<C>& FM = CM.u.f;
-  const int32_t nitems = kSel ? min(A.counters[C_NSEL], A.cell_cap)
-                              : (kQueue ? min(A.counters[C_NQUEUED], A.cell_cap) : min(A.counters[C_NIF], A.cell_cap));
-  const double h = g.h;
-  const int R = A.prm.rings;
-  const double reach = 1.5 * h;
-  const double reach2 = reach * reach * (1.0 - 1e-12);
-  const uint64_t below_me = (1ull << gl) - 1ull;
+__device__ inline void write_diag(const PPICArgs& A, int32_t c, int32_t vs, int32_t nT, int32_t cnt, int32_t it) {
+  if (!A.diag) return;
+  const int64_t cs = A.cell_cap;
+  A.diag[c] = vs;
+  A.diag[cs + c] = nT;
+  A.diag[2 * cs + c] = cnt;
+  A.diag[3 * cs + c] = it;
+}
 
-  // each XCD takes a contiguous range of cell groups
-  const int32_t ngroups = (nitems + NG - 1) / NG;
+// Closest vertex of the cell with centre xc: the pre-pass result when it
+// is final, else (need) a search over all vertices by the G lanes of the
+// cell.  Called by all 64 lanes.
+template <int G>
+__device__ inline int32_t closest_vertex(const PPICArgs& A, int32_t c, bool act, const double xc[3], int gl) {
+  const double reach = 1.5 * A.g.h;
+  const double reach2 = reach * reach * (1.0 - 1e-12);
+  int32_t vs = act ? A.best_v[c] : 0;
+  const bool need = act && !(vs != INT_MAX && A.best_d2[c] < reach2);
+  if (__any(need)) {
+    double bd = DBL_MAX;
+    int32_t bv = INT_MAX;
+    if (need)
+      for (int32_t v = gl; v < A.nv; v += G) consider(A.vtx4, v, xc, bd, bv);
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) {
+      const double od = __shfl_xor(bd, o, 64);
+      const int32_t ov = __shfl_xor(bv, o, 64);
+      if (lex_less(od, ov, bd, bv)) {
+        bd = od;
+        bv = ov;
+      }
+    }
+    if (need) vs = bv;
+  }
+  return vs;
+}
+
+// Cells are dealt out in groups of NG (one group per wavefront and turn);
+// each XCD takes a contiguous range of groups, which keeps each L2 on one
+// part of the front.  Calls body(group) for the groups of workgroup bid.
+template <class Body>
+__device__ inline void for_xcd_groups(int32_t ngroups, int32_t bid, int32_t nblk, Body body) {
   const int32_t per = (ngroups + kXCD - 1) / kXCD;
   const int32_t xcd = bid % kXCD, nj = nblk / kXCD;
   for (int32_t q = bid / kXCD; q < per; q += nj) {
     const int32_t gi = xcd * per + q;
     if (gi >= ngroups) break;
-    const int32_t item = gi * NG + grp;
-    const bool act = item < nitems;
-    const int32_t c = act ? (kSel ? A.sel[item] : (kQueue ? A.ovf_cells[item] : item)) : 0;
-    const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
-    const double xc[3] = {cell_centre(g.x0, cc3.i, h), cell_centre(g.y0, cc3.j, h), cell_centre(g.z0, cc3.k, h)};
+    body(gi);
+  }
+}
 
-    // ---- closest vertex: pre-pass result, else a search over all vertices
-    int32_t vs = act ? A.best_v[c] : 0;
-    const bool need = act && !(vs != INT_MAX && A.best_d2[c] < reach2);
-    if (__any(need)) {
-      double bd = DBL_MAX;
-      int32_t bv = INT_MAX;
-      if (need)
-        for (int32_t v = gl; v < A.nv; v += G) consider(A.vtx4, v, xc, bd, bv);
-#pragma unroll
-      for (int o = G / 2; o >= 1; o >>= 1) {
-        const double od = __shfl_xor(bd, o, 64);
-        const int32_t ov = __shfl_xor(bv, o, 64);
-        if (lex_less(od, ov, bd, bv)) {
-          bd = od;
-          bv = ov;
-        }
-      }
-      if (need) vs = bv;
-    }
-    bool ok = act && vs >= 0 && vs < A.nv;
+// ------------------------------------------------------------ wide shape
+// Ring-building state, dead once the rings are complete.
+template <class C>
+struct RingMem {
+  int32_t hkey[C::HS];    // hash set of vertices: -1 empty, v new in this ring, v | kPlaced in V
+  int32_t hval[C::HS];    // new vertex: first occurrence (3 x position + corner); placed: its ring
+  int32_t V[C::VC];       // ring vertices
+  int32_t Vo[C::VC];      // offset of their incident-triangle lists
+  int32_t Vs[C::VC + 1];  // prefix sums of their degrees
+  uint32_t fbits[C::FW];  // first occurrences of the new vertices of the current ring
+  uint8_t own[C::Batch];  // ring vertex of each candidate of the current batch
+};
+// Fit state, alive after the rings.
+template <class C>
+struct FitMem {
+  double W[C::TC];   // weights of the triangles inside the support
+  int32_t S[C::TC];  // those triangles
+};
+template <class C>
+struct __align__(8) CellMem {
+  union {
+    RingMem<C> r;
+    FitMem<C> f;
+  } u;
+  int32_t T[C::TC];  // ring triangles
+};
+
+constexpr int32_t kPlaced = INT32_MIN;  // vertex ids are below 2^31 - 1, so key | kPlaced != -1
+
+// Insert a key that is not placed (if absent, as a new vertex) and return
+// its slot; -1 if the table is full.
+template <class C>
+__device__ inline int hinsert(RingMem<C>& M, int32_t key) {
+  int s = hslot<C::HS>(key);
+#pragma unroll 1
+  for (int p = 0; p < C::HS; ++p) {
+    const int32_t prev = atomicCAS(&M.hkey[s], -1, key);
+    if (prev == -1 || prev == key) return s;
+    s = (s + 1) & (C::HS - 1);
+  }
+  return -1;
+}
+
+// Ring of the vertex key if it is placed in V (0 for v*), else -1.  home is
+// the table entry at the key's home slot, read beforehand.
+template <class C>
+__device__ inline int ring_of(const RingMem<C>& M, int32_t key, int32_t home) {
+  const int32_t placed = key | kPlaced;
+  int s = hslot<C::HS>(key);
+  if (home == placed) return M.hval[s];
+  if (home == -1 || home == key) return -1;
+#pragma unroll 1
+  for (int p = 0; p < C::HS; ++p) {
+    s = (s + 1) & (C::HS - 1);
+    const int32_t k = M.hkey[s];
+    if (k == placed) return M.hval[s];
+    if (k == -1 || k == key) return -1;
+  }
+  return -1;
+}
+
+// The queued cells (ovf_cells[0, counters[C_NOVF])) or, with kSel, the
+// cells of the surrogate's selection, one at a time per workgroup `bid` of
+// `nblk` (64 lanes): rings built level by level (the candidates of ring r
+// are the incident triangles of the vertices new in V_{r-1}, spread over
+// the lanes through prefix sums of their degrees; a candidate is kept from
+// the first of its corners that is new in V_{r-1}, and only if none of its
+// corners lies in V_{r-2}; corners of kept triangles not yet placed enter
+// the table marked with their first occurrence and are placed in V_r in
+// that order), the support grown by `grow` until `n_min` triangles fall
+// inside it (or the ring is exhausted, or `max_iter` adjustments), the fit
+// and the solve.
+template <class C, bool kSel>
+__device__ inline void ppic_wide_cells(const PPICArgs& A, int32_t bid, int32_t nblk) {
+  constexpr int G = C::G;
+  static_assert(G == 64, "one cell per wavefront");
+  __shared__ CellMem<C> CM;
+  RingMem<C>& RM = CM.u.r;
+  FitMem<C>& FM = CM.u.f;
+  const Grid& g = A.g;
+  const int gl = threadIdx.x;
+  const int32_t nitems = kSel ? min(A.counters[C_NSEL], A.cell_cap) : min(A.counters[C_NOVF], A.cell_cap);
+  const double h = g.h;
+  const int R = A.prm.rings;
+  const uint64_t below_me = (1ull << gl) - 1ull;
+
+  for (int32_t item = bid; item < nitems; item += nblk) {
+    const int32_t c = kSel ? A.sel[item] : A.ovf_cells[item];
+    const Cell3 cc3 = unpack_cell(g, A.cell_ids[c]);
+    const double xc[3] = {cell_centre(g.x0, cc3.i, h), cell_centre(g.y0, cc3.j, h), cell_centre(g.z0, cc3.k, h)};
+    const int32_t vs = closest_vertex<G>(A, c, true, xc, gl);
+    bool ok = vs >= 0 && vs < A.nv;
 
     // ---- ring neighbourhood
     for (int s = gl; s < C::HS; s += G) {
@@ -441,21 +584,21 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
       const bool go_r = ok && !ovf;
       const int flo = go_r ? RM.Vs[nVprev] : 0, fhi = go_r ? RM.Vs[nVc] : 0;
       const int tot = fhi - flo;
-      const int nb = wave_max_i((tot + C::Batch - 1) / C::Batch);
-      const int prounds = wave_max_i(tot > 0 ? (nVc - nVprev + G - 1) / G : 0);
+      const int nb = (tot + C::Batch - 1) / C::Batch;
+      const int prounds = tot > 0 ? (nVc - nVprev + G - 1) / G : 0;
       bool full = false;
       for (int b = 0; b < nb; ++b) {
         const int b0 = flo + b * C::Batch;
         // owners of the candidates [b0, b0 + Batch)
         for (int k = 0; k < prounds; ++k) {
           const int p = nVprev + k * G + gl;
-          if (tot > 0 && p < nVc) {
+          if (p < nVc) {
             const int lo = max(RM.Vs[p], b0), hi = min(RM.Vs[p + 1], b0 + C::Batch);
             for (int f = lo; f < hi; ++f) RM.own[f - b0] = (uint8_t)p;
           }
         }
         __syncthreads();
-        const int kact = wave_max_i(min(C::CR, max(0, (fhi - b0 + G - 1) / G)));
+        const int kact = min(C::CR, max(0, (fhi - b0 + G - 1) / G));
         int32_t ct[C::CR], cu[C::CR];
 #pragma unroll
         for (int k = 0; k < C::CR; ++k) {
@@ -500,7 +643,7 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
               if (eu < 1 && l1 >= 0 && l1 < r - 1) keep = false;
               if (eu < 2 && l2 >= 0 && l2 < r - 1) keep = false;
             }
-            const uint64_t bal = gballot<G>(keep, grp);
+            const uint64_t bal = gballot<G>(keep, 0);
             if (keep) {
               const int pos = nT + __popcll(bal & below_me);
               if (pos < C::TC) {
@@ -526,14 +669,14 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
           }
         __syncthreads();
       }
-      if (nT > C::TC || gballot<G>(full, grp)) ovf = true;
+      if (nT > C::TC || __any(full)) ovf = true;
 
       if (r == 1) {
         // normal of v*: T_1 is v*'s incident list, ascending; the cross
         // products are summed serially in that order
         const int n1c = (ok && !ovf) ? nT : 0;
-        const int nr = wave_max_i((n1c + G - 1) / G);
-        const int qn = wave_max_i(min(n1c, G));
+        const int nr = (n1c + G - 1) / G;
+        const int qn = min(n1c, G);
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         for (int k = 0; k < nr; ++k) {
           const int i = k * G + gl;
@@ -595,7 +738,7 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
       __syncthreads();
       // prefix sums of the new degrees, in place
       const int pend = (ok && !ovf) ? nV : nV0;
-      const int vrounds = wave_max_i((pend - nV0 + G - 1) / G);
+      const int vrounds = (pend - nV0 + G - 1) / G;
       int32_t run = (ok && !ovf) ? RM.Vs[nV0] : 0;
       for (int k = 0; k < vrounds; ++k) {
         const int p = nV0 + k * G + gl;
@@ -611,56 +754,41 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
       __syncthreads();
     }
 
-    if (!kQueue && ovf && ok) {
-      // a ring beyond this shape's capacities: the wide shape takes the cell
-      if (gl == 0) A.ovf_cells[atomicAdd(&A.counters[C_NOVF], 1)] = c;
-    }
-    const bool emit = act && !(!kQueue && ovf && ok);
     if (ovf) ok = false;
     const int nTc = ok ? min(nT, C::TC) : 0;
-
-    const double sg = copysign(1.0, n2);
-    const double fa = -1.0 / (sg + n2);
-    const double fb = n0 * n1 * fa;
-    const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
-    const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
+    Frame F;
+    F.xc[0] = xc[0];
+    F.xc[1] = xc[1];
+    F.xc[2] = xc[2];
+    F.n[0] = n0;
+    F.n[1] = n1;
+    F.n[2] = n2;
+    duff_tangents(n0, n1, n2, F.t1, F.t2);
+    F.inv_h = 1.0 / h;
 
     // ---- centre distances (kept in the weight list's storage), support
     // radius, weights
-    const int drounds = wave_max_i((nTc + G - 1) / G);
-    {
-      int4 cn = A.tri4[gl < nTc ? CM.T[gl] : 0];
-      for (int k = 0; k < drounds; ++k) {
-        const int i = k * G + gl;
-        const int4 c4 = cn;
-        cn = A.tri4[i + G < nTc ? CM.T[i + G] : 0];
-        const P3 a = vtx(A.vtx4, c4.x), b = vtx(A.vtx4, c4.y), e = vtx(A.vtx4, c4.z);
-        const double cx = div3(a.x + b.x + e.x);
-        const double cy = div3(a.y + b.y + e.y);
-        const double cz = div3(a.z + b.z + e.z);
-        const double dx = cx - xc[0], dy = cy - xc[1], dz = cz - xc[2];
-        if (i < nTc) FM.W[i] = dx * dx + dy * dy + dz * dz;
+    const int drounds = (nTc + G - 1) / G;
+    for (int k = 0; k < drounds; ++k) {
+      const int i = k * G + gl;
+      if (i < nTc) {
+        const int4 c4 = A.tri4[CM.T[i]];
+        FM.W[i] = centre_d2(vtx(A.vtx4, c4.x), vtx(A.vtx4, c4.y), vtx(A.vtx4, c4.z), xc);
       }
     }
+    __syncthreads();
     double delta = A.prm.delta_over_h * h;
     int32_t it = 0, cnt = 0;
-    bool done = !ok;
-    for (;;) {
-      const double lim = delta * delta;
-      int mine = 0;
-      for (int i = gl; i < nTc; i += G) mine += FM.W[i] < lim ? 1 : 0;
-#pragma unroll
-      for (int o = G / 2; o >= 1; o >>= 1) mine += __shfl_xor(mine, o, 64);
-      if (!done) {
-        cnt = mine;
-        if (cnt >= A.prm.n_min || cnt == nTc || it == A.prm.max_iter) {
-          done = true;
-        } else {
-          delta = delta * A.prm.grow;
-          ++it;
-        }
+    if (ok) {
+      for (;;) {
+        const double lim = delta * delta;
+        int mine = 0;
+        for (int i = gl; i < nTc; i += G) mine += FM.W[i] < lim ? 1 : 0;
+        cnt = group_sum_i<G>(mine);
+        if (cnt >= A.prm.n_min || cnt == nTc || it == A.prm.max_iter) break;
+        delta = delta * A.prm.grow;
+        ++it;
       }
-      if (!__any(!done)) break;
     }
     {
       const double lim = delta * delta;
@@ -673,100 +801,37 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
         const double dd = i < nTc ? FM.W[i] : DBL_MAX;
         const int32_t ti = i < nTc ? CM.T[i] : 0;
         const bool keep = i < nTc && dd < lim;
-        const uint64_t bal = gballot<G>(keep, grp);
+        const uint64_t bal = gballot<G>(keep, 0);
+        __syncthreads();
         if (keep) {
           const int pos = nw + __popcll(bal & below_me);
-          const double qq = sqrt(dd) * inv_delta;
-          const double om = 1.0 - qq;
-          const double wt = (1.0 + 4.0 * qq) * (om * om) * (om * om);
-          if constexpr (kQueue) {
-            FM.W[pos] = wt;
-            FM.S[pos] = ti;
-          } else {
-            A.wl_w[(int64_t)c * kFitList + pos] = wt;
-            A.wl_tri[(int64_t)c * kFitList + pos] = ti;
-          }
+          FM.W[pos] = wendland(dd, inv_delta);
+          FM.S[pos] = ti;
         }
         nw += __popcll(bal);
+        __syncthreads();
       }
     }
     __syncthreads();
 
-    if constexpr (!kQueue) {
-      // the fit pass takes the list; a queued cell is marked for it to skip
-      if (act && gl == 0) {
-        const int64_t cs = A.cell_cap;
-        A.fit[27 * cs + c] = n0;
-        A.fit[28 * cs + c] = n1;
-        A.fit[29 * cs + c] = n2;
-        A.fit[30 * cs + c] = !emit ? -3.0 : (ok ? (double)cnt : (ovf ? -1.0 : -2.0));
-        if (A.diag && emit) {
-          A.diag[c] = vs;
-          A.diag[cs + c] = nT;
-          A.diag[2 * cs + c] = cnt;
-          A.diag[3 * cs + c] = it;
-        }
-      }
-      __syncthreads();
-      continue;
-    }
-
     // ---- weighted moments and normal equations
-    const double inv_h = 1.0 / h;
     double acc[27];
 #pragma unroll
     for (int qa = 0; qa < 27; ++qa) acc[qa] = 0.0;
-    const int wrounds = wave_max_i(ok ? (cnt + G - 1) / G : 0);
-    int4 tn = A.tri4[(ok && gl < cnt) ? FM.S[gl] : 0];
+    const int wrounds = ok ? (cnt + G - 1) / G : 0;
     for (int k = 0; k < wrounds; ++k) {
       const int j = k * G + gl;
-      const bool valid = ok && j < cnt;
-      const double w = valid ? FM.W[j] : 0.0;
-      const int4 t4 = tn;
-      {
-        const int jn = j + G;
-        tn = A.tri4[(ok && jn < cnt) ? FM.S[jn] : 0];
-      }
-      const int32_t cr[3] = {t4.x, t4.y, t4.z};
-      double xi[3], eta[3], zeta[3];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const P3 p = vtx(A.vtx4, cr[e]);
-        const double dx = p.x - xc[0], dy = p.y - xc[1], dz = p.z - xc[2];
-        xi[e] = fma(dz, t1z, fma(dy, t1y, dx * t1x)) * inv_h;
-        eta[e] = fma(dz, t2z, fma(dy, t2y, dx * t2x)) * inv_h;
-        zeta[e] = fma(dz, n2, fma(dy, n1, dx * n0)) * inv_h;
-      }
-      const double area = 0.5 * fma(xi[1] - xi[0], eta[2] - eta[0], -((xi[2] - xi[0]) * (eta[1] - eta[0])));
-      double sm[6] = {3.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const double mx = 0.5 * (xi[e] + xi[(e + 1) % 3]);
-        const double my = 0.5 * (eta[e] + eta[(e + 1) % 3]);
-        sm[1] += mx;
-        sm[2] += my;
-        sm[3] = fma(mx, mx, sm[3]);
-        sm[4] = fma(mx, my, sm[4]);
-        sm[5] = fma(my, my, sm[5]);
-      }
-      const double a3 = area * (1.0 / 3.0);
-      double mom[6];
-#pragma unroll
-      for (int qa = 0; qa < 6; ++qa) mom[qa] = a3 * sm[qa];
-      const double wv = w * (a3 * (zeta[0] + zeta[1] + zeta[2]));
-#pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        const double wa = w * mom[a];
-#pragma unroll
-        for (int b = a; b < 6; ++b) acc[P6(a, b)] = fma(wa, mom[b], acc[P6(a, b)]);
-        acc[21 + a] = fma(wv, mom[a], acc[21 + a]);
+      if (j < cnt) {
+        const int4 t4 = A.tri4[FM.S[j]];
+        double mom[6], vt;
+        tri_moments(F, vtx(A.vtx4, t4.x), vtx(A.vtx4, t4.y), vtx(A.vtx4, t4.z), mom, vt);
+        accumulate(acc, FM.W[j], mom, vt);
       }
     }
 #pragma unroll
     for (int qa = 0; qa < 27; ++qa) acc[qa] = group_sum<G>(acc[qa]);
 
-    // ---- the normal equations (weighted count -1: ring beyond the
-    // capacities, -2: no closest vertex), solved by one lane per cell
+    // ---- the normal equations, solved by one lane
     __syncthreads();
     if (gl == 0) {
 #pragma unroll
@@ -777,29 +842,33 @@ __device__ inline void ppic_cells(const PPICArgs& A, int32_t bid, int32_t nblk) 
       FM.W[30] = ok ? (double)cnt : (ovf ? -1.0 : -2.0);
     }
     __syncthreads();
-    if (emit && gl == 0) {
-      const int64_t cs = A.cell_cap;
+    if (gl == 0) {
       solve_cell(A, c, FM.W, 1, false);
-      if (A.diag) {
-        A.diag[c] = vs;
-        A.diag[cs + c] = nT;
-        A.diag[2 * cs + c] = cnt;
-        A.diag[3 * cs + c] = it;
-      }
+      write_diag(A, c, vs, nT, cnt, it);
     }
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(64) void k_ppic_rings(PPICArgs A) { ppic_cells<Fast, false>(A, blockIdx.x, gridDim.x); }
-__global__ __launch_bounds__(64) void k_ppic_rings16(PPICArgs A) {
-  ppic_cells<Fast16, false>(A, blockIdx.x, gridDim.x);
+// The cells the fast shape queued.  The queue's count is read by every
+// workgroup before the last one to finish clears it for the next call.
+__global__ __launch_bounds__(64) void k_ppic_wide(PPICArgs A) {
+  ppic_wide_cells<Wide, false>(A, blockIdx.x, gridDim.x);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&A.counters[C_WIDE_DONE], 1) == (int32_t)gridDim.x - 1) {
+      __threadfence();
+      A.counters[C_NOVF] = 0;
+      A.counters[C_WIDE_DONE] = 0;
+    }
+  }
 }
+
 // The cells the learned curvature hands over, sel[0, counters[C_NSEL]), with
-// the wide shape (rings, fit and solve in the workgroup, one cell at a
-// time): a selection is a small part of the cells, and the wide shape's
-// per-cell latency is the lower.
-__global__ __launch_bounds__(64) void k_ppic_wide_sel(PPICArgs A) { ppic_cells<Wide, true, true>(A, blockIdx.x, gridDim.x); }
+// the wide shape: a selection is a small part of the cells, and the wide
+// shape's per-cell latency is the lower.
+__global__ __launch_bounds__(64) void k_ppic_wide_sel(PPICArgs A) { ppic_wide_cells<Wide, true>(A, blockIdx.x, gridDim.x); }
 
 // After it: report the selection's count and clear it for the next call (a
 // kernel of its own: a completion count over the selection kernel's
@@ -809,277 +878,371 @@ __global__ void k_sel_done(int32_t* counters, int32_t* n_sel_out) {
   counters[C_NSEL] = 0;
 }
 
-// Weighted moments and normal equations of the cells whose ring fitted the
-// fast shape: 8 lanes per cell (8 cells per wavefront) over the cell's
-// weighted-triangle list; sums reduced over the lanes and stored for the
-// solve pass.
-constexpr int kFitG = 8;
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_ppic_fit(PPICArgs A) {
-  constexpr int G = kFitG, NG = 64 / kFitG;
-  __shared__ double stage[NG][28];
-  const Grid& g = A.g;
-  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
-  const int32_t nitems = min(A.counters[C_NIF], A.cell_cap);
-  const int64_t cs = A.cell_cap;
-  const double h = g.h, inv_h = 1.0 / h;
-  // the ring pass has finished queueing: hand the count to the wide shape
-  // and start the next call's queue empty
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    A.counters[C_NQUEUED] = A.counters[C_NOVF];
-    A.counters[C_NOVF] = 0;
+// ------------------------------------------------------------ fast shape
+template <int G_>
+struct FastCfg {
+  static constexpr int G = G_;        // lanes per cell
+  static constexpr int NG = 64 / G_;  // cells per wavefront
+  static constexpr int HV = 64;       // slots of the vertex set (power of two)
+  static constexpr int VC = 32;       // vertices of V_{R-1}
+  static constexpr int TC = 64;       // ring triangles
+  static constexpr int IB = 6;        // record slots a lane loads together
+  static_assert(IB * 3 <= 32, "new-corner mask");
+};
+
+// Per cell: the vertex set and the ring, then (after the fit) the sums.
+union FastMem {
+  struct {
+    int32_t hv[64];    // V as an open-addressing hash set, -1 empty
+    int32_t V[32];     // V in insertion order
+    int32_t T[3][64];  // corners of the ring triangles
+  } r;
+  double S[32];  // the 27 sums, the frame normal, the weighted count
+};
+
+// Insert key into the set; true when this lane added it.  full is set if
+// the probe sequence wraps without finding a place.
+template <int HS>
+__device__ inline bool vset_insert(int32_t* hv, int32_t key, bool& full) {
+  int s = hslot<HS>(key);
+#pragma unroll 1
+  for (int p = 0; p < HS; ++p) {
+    // most corners are in the set already: a plain read first
+    const int32_t cur = __hip_atomic_load(&hv[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == key) return false;
+    if (cur == -1) {
+      const int32_t prev = atomicCAS(&hv[s], -1, key);
+      if (prev == -1) return true;
+      if (prev == key) return false;
+    }
+    s = (s + 1) & (HS - 1);
   }
-  const int32_t ngroups = (nitems + NG - 1) / NG;
-  const int32_t per = (ngroups + kXCD - 1) / kXCD;
-  const int32_t xcd = blockIdx.x % kXCD, nj = gridDim.x / kXCD;
-  for (int32_t q = blockIdx.x / kXCD; q < per; q += nj) {
-    const int32_t gi = xcd * per + q;
-    if (gi >= ngroups) break;
-    const int32_t c = gi * NG + grp;
-    const bool act = c < nitems;
-    const double wc = act ? A.fit[30 * cs + c] : -2.0;
-    const int cnt = wc > 0.0 ? (int)wc : 0;
-    const double n0 = act ? A.fit[27 * cs + c] : 0.0, n1 = act ? A.fit[28 * cs + c] : 0.0,
-                 n2 = act ? A.fit[29 * cs + c] : 1.0;
-    const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
-    const double xc[3] = {cell_centre(g.x0, cc3.i, h), cell_centre(g.y0, cc3.j, h), cell_centre(g.z0, cc3.k, h)};
-    const double sg = copysign(1.0, n2);
-    const double fa = -1.0 / (sg + n2);
-    const double fb = n0 * n1 * fa;
-    const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
-    const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
-    double acc[27];
+  full = true;
+  return false;
+}
+
+template <int HS>
+__device__ inline bool vset_has(const int32_t* hv, int32_t key) {
+  int s = hslot<HS>(key);
+#pragma unroll 1
+  for (int p = 0; p < HS; ++p) {
+    const int32_t cur = hv[s];
+    if (cur == key) return true;
+    if (cur == -1) return false;
+    s = (s + 1) & (HS - 1);
+  }
+  return false;
+}
+
+// One pass over the vertices V[lo, hi) through their records: item x is
+// slot x % kIncSlots of vertex V[lo + x / kIncSlots]; lane gl takes items
+// gl, gl + G, ..., kB at a time with their loads issued together (with
+// G = kIncSlots a round reads one record, one cache line, per cell).
+//   kRing = false: the corners of each incident triangle join the vertex
+//     set; the ones this lane adds are appended to V in lane order;
+//   kRing = true: an incident triangle at u is appended to the ring when u
+//     is its first corner (t0, t1, t2 order) in the set.
+// big is set when a vertex has more incident triangles than its record
+// holds.
+template <class C, bool kRing>
+__device__ inline void record_pass(const PPICArgs& A, FastMem& M, int lo, int hi, int gl, int& nV, int& nT,
+                                   bool& full, bool& big) {
+  constexpr int G = C::G, kB = C::IB;
+  const int nitems = (hi - lo) * kIncSlots;
+  const int rounds = wave_max_i((nitems + G - 1) / G);
+  for (int k0 = 0; k0 < rounds; k0 += kB) {
+    int32_t u[kB];
+    int4 rec[kB];
 #pragma unroll
-    for (int qa = 0; qa < 27; ++qa) acc[qa] = 0.0;
-    const int wrounds = wave_max_i((cnt + G - 1) / G);
-    const int32_t* lt = A.wl_tri + (int64_t)(act ? c : 0) * kFitList;
-    const double* lw = A.wl_w + (int64_t)(act ? c : 0) * kFitList;
-    // entries of the next round (triangle ids, then their corners) are loaded
-    // while this round is computed; a lane past the list (or a cell with an
-    // empty list, whose entries were never written) takes vertex 0 with weight 0
-    const int4 kNone = make_int4(0, 0, 0, 0);
-    int4 tn = gl < cnt ? A.tri4[lt[gl]] : kNone;
-    double wn = gl < cnt ? lw[gl] : 0.0;
-    for (int k = 0; k < wrounds; ++k) {
-      const int j = k * G + gl;
-      const int4 t4 = tn;
-      const double w = wn;
-      if (k + 1 < wrounds) {
-        const int jn = j + G;
-        tn = jn < cnt ? A.tri4[lt[jn]] : kNone;
-        wn = jn < cnt ? lw[jn] : 0.0;
-      }
-      const int32_t cr[3] = {t4.x, t4.y, t4.z};
-      double xi[3], eta[3], zeta[3];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const P3 p = vtx(A.vtx4, cr[e]);
-        const double dx = p.x - xc[0], dy = p.y - xc[1], dz = p.z - xc[2];
-        xi[e] = fma(dz, t1z, fma(dy, t1y, dx * t1x)) * inv_h;
-        eta[e] = fma(dz, t2z, fma(dy, t2y, dx * t2x)) * inv_h;
-        zeta[e] = fma(dz, n2, fma(dy, n1, dx * n0)) * inv_h;
-      }
-      const double area = 0.5 * fma(xi[1] - xi[0], eta[2] - eta[0], -((xi[2] - xi[0]) * (eta[1] - eta[0])));
-      double sm[6] = {3.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const double mx = 0.5 * (xi[e] + xi[(e + 1) % 3]);
-        const double my = 0.5 * (eta[e] + eta[(e + 1) % 3]);
-        sm[1] += mx;
-        sm[2] += my;
-        sm[3] = fma(mx, mx, sm[3]);
-        sm[4] = fma(mx, my, sm[4]);
-        sm[5] = fma(my, my, sm[5]);
-      }
-      const double a3 = area * (1.0 / 3.0);
-      double mom[6];
-#pragma unroll
-      for (int qa = 0; qa < 6; ++qa) mom[qa] = a3 * sm[qa];
-      const double wv = w * (a3 * (zeta[0] + zeta[1] + zeta[2]));
-#pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        const double wa = w * mom[a];
-#pragma unroll
-        for (int b = a; b < 6; ++b) acc[P6(a, b)] = fma(wa, mom[b], acc[P6(a, b)]);
-        acc[21 + a] = fma(wv, mom[a], acc[21 + a]);
-      }
+    for (int b = 0; b < kB; ++b) {
+      const int x = (k0 + b) * G + gl;
+      u[b] = x < nitems ? M.r.V[lo + x / kIncSlots] : -1;
     }
 #pragma unroll
-    for (int qa = 0; qa < 27; ++qa) acc[qa] = group_sum<G>(acc[qa]);
-    // staged through LDS so that each lane stores a few of the 27 sums
+    for (int b = 0; b < kB; ++b) {
+      const int x = (k0 + b) * G + gl;
+      rec[b] = u[b] >= 0 ? A.vinc[(int64_t)kIncSlots * u[b] + x % kIncSlots] : make_int4(-1, -1, -1, 0);
+    }
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      if (rec[b].w > kIncSlots) big = true;
+      if (rec[b].x < 0) continue;
+      if constexpr (kRing) {
+        // u is t0, or a later corner with none before it in the set
+        bool keep = rec[b].x == u[b];
+        if (!keep)
+          keep = !vset_has<C::HV>(M.r.hv, rec[b].x) && (rec[b].y == u[b] || !vset_has<C::HV>(M.r.hv, rec[b].y));
+        if (keep) bits |= 1u << b;
+      } else {
+        const int32_t cr[3] = {rec[b].x, rec[b].y, rec[b].z};
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+          if (cr[e] != u[b] && vset_insert<C::HV>(M.r.hv, cr[e], full)) bits |= 1u << (3 * b + e);
+      }
+    }
+    int total;
+    int pos = (kRing ? nT : nV) + group_excl_scan<G>(__popc(bits), gl, &total);
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      if constexpr (kRing) {
+        if ((bits >> b) & 1u) {
+          if (pos < C::TC) {
+            M.r.T[0][pos] = rec[b].x;
+            M.r.T[1][pos] = rec[b].y;
+            M.r.T[2][pos] = rec[b].z;
+          }
+          ++pos;
+        }
+      } else {
+        const int32_t cr[3] = {rec[b].x, rec[b].y, rec[b].z};
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+          if ((bits >> (3 * b + e)) & 1u) {
+            if (pos < C::VC) M.r.V[pos] = cr[e];
+            ++pos;
+          }
+      }
+    }
+    if constexpr (kRing)
+      nT += total;
+    else
+      nV += total;
+  }
+}
+
+// The fast shape over every interfacial cell, G lanes per cell; kMixed:
+// the normal equations formed and factored in single precision, refined
+// twice with double-precision residuals g = sum_t w_t (V_t - m_t . a) m_t
+// = b - M a of the same triangles (moments again in double precision),
+// solved with the single-precision factor; each step shrinks the error by
+// about cond(M) times the single-precision unit roundoff.  A
+// single-precision pivot at or below 1e-6 of the trace marks the cell rank
+// deficient.
+template <int G, bool kMixed>
+__device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
+  using C = FastCfg<G>;
+  constexpr int NG = C::NG;
+  __shared__ FastMem SM[NG];
+  const Grid& g = A.g;
+  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+  FastMem& M = SM[grp];
+  const int32_t nitems = min(A.counters[C_NIF], A.cell_cap);
+  const double h = g.h;
+  const int R = A.prm.rings;
+  const int32_t ngroups = (nitems + NG - 1) / NG;
+
+  for_xcd_groups(ngroups, bid, nblk, [&](int32_t gi) {
+    const int32_t c = gi * NG + grp;
+    const bool act = c < nitems;
+    int32_t vs;
+    {
+      const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
+      const double xc[3] = {cell_centre(g.x0, cc3.i, h), cell_centre(g.y0, cc3.j, h), cell_centre(g.z0, cc3.k, h)};
+      vs = closest_vertex<G>(A, c, act, xc, gl);
+    }
+    const bool ok = act && vs >= 0 && vs < A.nv;
+
+    // ---- V_0 = {v*}
+    for (int s = gl; s < C::HV; s += G) M.r.hv[s] = -1;
+    __syncthreads();
+    if (ok && gl == 0) {
+      M.r.hv[hslot<C::HV>(vs)] = vs;
+      M.r.V[0] = vs;
+    }
+    __syncthreads();
+    int nV = 1;
+    bool full = false;
+    double n0 = 0.0, n1 = 0.0, n2 = 1.0;
+
+    // ---- the triangles at v* (its record, ascending): frame normal (cross
+    // products summed in that order) and, for R >= 2, V_1
+    bool big = false;
+    {
+      constexpr int nr = (kIncSlots + G - 1) / G;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      int deg0 = 0;
+#pragma unroll
+      for (int k = 0; k < nr; ++k) {
+        const int q = k * G + gl;
+        const int4 rec = ok && q < kIncSlots ? A.vinc[(int64_t)kIncSlots * vs + q] : make_int4(-1, -1, -1, 0);
+        deg0 = max(deg0, rec.w);
+        const bool have = rec.x >= 0;
+        const P3 a = vtx(A.vtx4, have ? rec.x : 0), b = vtx(A.vtx4, have ? rec.y : 0), e = vtx(A.vtx4, have ? rec.z : 0);
+        const double ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;
+        const double wx = e.x - a.x, wy = e.y - a.y, wz = e.z - a.z;
+        const double cx = uy * wz - uz * wy;
+        const double cy = uz * wx - ux * wz;
+        const double cz = ux * wy - uy * wx;
+#pragma unroll
+        for (int qq = 0; qq < G; ++qq) {
+          const double x = __shfl(cx, qq, G), y = __shfl(cy, qq, G), z = __shfl(cz, qq, G);
+          const bool h2 = __shfl((int)have, qq, G) != 0;
+          if (h2) {
+            s0 += x;
+            s1 += y;
+            s2 += z;
+          }
+        }
+        if (R >= 2) {
+          uint32_t added = 0u;
+          const int32_t cr[3] = {rec.x, rec.y, rec.z};
+#pragma unroll
+          for (int e2 = 0; e2 < 3; ++e2)
+            if (have && cr[e2] != vs && vset_insert<C::HV>(M.r.hv, cr[e2], full)) added |= 1u << e2;
+          int total;
+          int pos = nV + group_excl_scan<G>(__popc(added), gl, &total);
+#pragma unroll
+          for (int e2 = 0; e2 < 3; ++e2)
+            if ((added >> e2) & 1u) {
+              if (pos < C::VC) M.r.V[pos] = cr[e2];
+              ++pos;
+            }
+          nV += total;
+        }
+      }
+      if (deg0 > kIncSlots) big = true;
+      const double nl = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
+      n0 = s0 / nl;
+      n1 = s1 / nl;
+      n2 = s2 / nl;
+    }
+    bool ovf = nV > C::VC || gballot<G>(full || big, grp) != 0;
+    __syncthreads();
+
+    // ---- V_2 .. V_{R-1}: corners of the triangles at the vertices new in
+    // the previous level
+    int nVprev = 1;
+    for (int r = 2; r <= R - 1; ++r) {
+      const int lo = nVprev, hi = nV;
+      nVprev = nV;
+      const bool go = ok && !ovf;
+      int nT0 = 0;
+      record_pass<C, false>(A, M, go ? lo : 0, go ? hi : 0, gl, nV, nT0, full, big);
+      if (nV > C::VC || gballot<G>(full || big, grp) != 0) ovf = true;
+      __syncthreads();
+    }
+
+    // ---- the ring T_R
+    int nT = 0;
+    {
+      const bool go = ok && !ovf;
+      record_pass<C, true>(A, M, 0, go ? nV : 0, gl, nV, nT, full, big);
+      if (nT > C::TC || gballot<G>(big, grp) != 0) ovf = true;
+    }
+    __syncthreads();
+
+    // ---- one pass over the ring at the first support radius
+    Frame F;
+    {
+      const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
+      F.xc[0] = cell_centre(g.x0, cc3.i, h);
+      F.xc[1] = cell_centre(g.y0, cc3.j, h);
+      F.xc[2] = cell_centre(g.z0, cc3.k, h);
+    }
+    F.n[0] = n0;
+    F.n[1] = n1;
+    F.n[2] = n2;
+    duff_tangents(n0, n1, n2, F.t1, F.t2);
+    F.inv_h = 1.0 / h;
+    const bool fit = ok && !ovf;
+    const int nTc = fit ? nT : 0;
+    const double delta = A.prm.delta_over_h * h;
+    const double lim = delta * delta, inv_delta = 1.0 / delta;
+    const int frounds = wave_max_i((nTc + G - 1) / G);
+    int mine = 0;
+    using AccT = typename std::conditional<kMixed, float, double>::type;
+    AccT acc[27];
+#pragma unroll
+    for (int qa = 0; qa < 27; ++qa) acc[qa] = AccT(0);
+    for (int k = 0; k < frounds; ++k) {
+      const int i = k * G + gl;
+      const bool valid = i < nTc;
+      const int32_t c0 = valid ? M.r.T[0][i] : 0, c1 = valid ? M.r.T[1][i] : 0, c2 = valid ? M.r.T[2][i] : 0;
+      const P3 a = vtx(A.vtx4, c0), b = vtx(A.vtx4, c1), e = vtx(A.vtx4, c2);
+      const double dd = centre_d2(a, b, e, F.xc);
+      const bool in = valid && dd < lim;
+      mine += in ? 1 : 0;
+      const double w = in ? wendland(dd, inv_delta) : 0.0;
+      AccT mom[6], vt;
+      tri_moments(F, a, b, e, mom, vt);
+      accumulate(acc, (AccT)w, mom, vt);
+    }
+    const int cnt = group_sum_i<G>(mine);
+    // the support needs adjusting: the wide shape takes the cell
+    const bool grow = fit && !(cnt >= A.prm.n_min || cnt == nTc || A.prm.max_iter == 0);
+    const bool queue = ok && (ovf || grow);
+    if (queue && gl == 0) A.ovf_cells[atomicAdd(&A.counters[C_NOVF], 1)] = c;
+
+    double ah[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    bool full_rank = false;
+    if constexpr (kMixed) {
+#pragma unroll
+      for (int qa = 0; qa < 27; ++qa) acc[qa] = group_sum_f<G>(acc[qa]);
+      float invf[6];
+      full_rank = chol6(acc, invf, 1e-6f) && cnt >= 6;
+      double rhs[6];
+#pragma unroll
+      for (int qa = 0; qa < 6; ++qa) rhs[qa] = (double)acc[21 + qa];
+      chol6_solve(acc, invf, rhs, ah);
+      for (int pass = 0; pass < 2; ++pass) {
+        double gr[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < frounds; ++k) {
+          const int i = k * G + gl;
+          const bool valid = i < nTc;
+          const int32_t c0 = valid ? M.r.T[0][i] : 0, c1 = valid ? M.r.T[1][i] : 0, c2 = valid ? M.r.T[2][i] : 0;
+          const P3 a = vtx(A.vtx4, c0), b = vtx(A.vtx4, c1), e = vtx(A.vtx4, c2);
+          const double dd = centre_d2(a, b, e, F.xc);
+          const double w = valid && dd < lim ? wendland(dd, inv_delta) : 0.0;
+          double mom[6], vt;
+          tri_moments(F, a, b, e, mom, vt);
+          double rr = vt;
+#pragma unroll
+          for (int q2 = 0; q2 < 6; ++q2) rr -= mom[q2] * ah[q2];
+          const double wr = w * rr;
+#pragma unroll
+          for (int q2 = 0; q2 < 6; ++q2) gr[q2] = fma(wr, mom[q2], gr[q2]);
+        }
+#pragma unroll
+        for (int q2 = 0; q2 < 6; ++q2) gr[q2] = group_sum<G>(gr[q2]);
+        chol6_solve(acc, invf, gr, gr);
+#pragma unroll
+        for (int q2 = 0; q2 < 6; ++q2) ah[q2] += gr[q2];
+      }
+    } else {
+#pragma unroll
+      for (int qa = 0; qa < 27; ++qa) acc[qa] = group_sum<G>(acc[qa]);
+    }
+
+    // ---- solve (one lane per cell) and outputs
+    __syncthreads();
     if (gl == 0) {
+      if constexpr (kMixed) {
 #pragma unroll
-      for (int qa = 0; qa < 27; ++qa) stage[grp][qa] = acc[qa];
+        for (int q2 = 0; q2 < 6; ++q2) M.S[q2] = ah[q2];
+        M.S[6] = full_rank ? 1.0 : 0.0;
+      } else {
+#pragma unroll
+        for (int qa = 0; qa < 27; ++qa) M.S[qa] = acc[qa];
+      }
+      M.S[27] = F.n[0];
+      M.S[28] = F.n[1];
+      M.S[29] = F.n[2];
+      M.S[30] = ok ? (double)cnt : -2.0;
     }
     __syncthreads();
-    if (act && wc >= 0.0)
-      for (int qa = gl; qa < 27; qa += G) A.fit[qa * cs + c] = stage[grp][qa];
+    if (act && !queue && gl == 0) {
+      solve_cell(A, c, M.S, 1, kMixed);
+      write_diag(A, c, vs, nT, cnt, 0);
+    }
     __syncthreads();
-  }
+  });
 }
 
-template <int CTRL>
-__device__ inline float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-
-// group_sum in single precision
-template <int G>
-__device__ inline float group_sum_f(float v) {
-  if constexpr (G >= 2) v += dpp_f<0xB1>(v);
-  if constexpr (G >= 4) v += dpp_f<0x4E>(v);
-  if constexpr (G >= 8) v += dpp_f<0x141>(v);
-  if constexpr (G >= 16) v += dpp_f<0x140>(v);
-  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
-  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
-  return v;
-}
-
-// Mixed precision variant of the fit pass: the weighted normal equations
-// are formed and factored in single precision; the solution is then
-// improved twice by iterative refinement with residuals evaluated in double
-// precision triangle by triangle, g = sum_t w_t (V_t - m_t . a) m_t = b - M a
-// (the double-precision moments of the same weighted triangles), solved with
-// the single-precision factor.  Each step shrinks the error by about
-// cond(M) times the single-precision unit roundoff.  A single-precision
-// pivot at or below 1e-6 of the trace marks the cell rank deficient.  The
-// coefficients (h-scaled frame) and the rank flag go to the fit slots for
-// the solve pass.
-__global__ __launch_bounds__(64) void k_ppic_fit_mixed(PPICArgs A) {
-  constexpr int G = kFitG, NG = 64 / kFitG;
-  const Grid& g = A.g;
-  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
-  const int32_t nitems = min(A.counters[C_NIF], A.cell_cap);
-  const int64_t cs = A.cell_cap;
-  const double h = g.h, inv_h = 1.0 / h;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    A.counters[C_NQUEUED] = A.counters[C_NOVF];
-    A.counters[C_NOVF] = 0;
-  }
-  const int32_t ngroups = (nitems + NG - 1) / NG;
-  const int32_t per = (ngroups + kXCD - 1) / kXCD;
-  const int32_t xcd = blockIdx.x % kXCD, nj = gridDim.x / kXCD;
-  for (int32_t q = blockIdx.x / kXCD; q < per; q += nj) {
-    const int32_t gi = xcd * per + q;
-    if (gi >= ngroups) break;
-    const int32_t c = gi * NG + grp;
-    const bool act = c < nitems;
-    const double wc = act ? A.fit[30 * cs + c] : -2.0;
-    const int cnt = wc > 0.0 ? (int)wc : 0;
-    const double n0 = act ? A.fit[27 * cs + c] : 0.0, n1 = act ? A.fit[28 * cs + c] : 0.0,
-                 n2 = act ? A.fit[29 * cs + c] : 1.0;
-    const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
-    const double xc[3] = {cell_centre(g.x0, cc3.i, h), cell_centre(g.y0, cc3.j, h), cell_centre(g.z0, cc3.k, h)};
-    const double sg = copysign(1.0, n2);
-    const double fa = -1.0 / (sg + n2);
-    const double fb = n0 * n1 * fa;
-    const double t1x = 1.0 + sg * n0 * n0 * fa, t1y = sg * fb, t1z = -sg * n0;
-    const double t2x = fb, t2y = sg + n1 * n1 * fa, t2z = -n1;
-    const int wrounds = wave_max_i((cnt + G - 1) / G);
-    const int32_t* lt = A.wl_tri + (int64_t)(act ? c : 0) * kFitList;
-    const double* lw = A.wl_w + (int64_t)(act ? c : 0) * kFitList;
-    const int4 kNone = make_int4(0, 0, 0, 0);
-
-    // moments of one listed triangle in the h-scaled frame (type T)
-    auto moments = [&](const int4 t4, auto zero, auto* mom, auto& vt) {
-      using T = decltype(zero);
-      const int32_t cr[3] = {t4.x, t4.y, t4.z};
-      T xi[3], eta[3], zeta[3];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const P3 p = vtx(A.vtx4, cr[e]);
-        const T dx = (T)(p.x - xc[0]), dy = (T)(p.y - xc[1]), dz = (T)(p.z - xc[2]);
-        xi[e] = fma(dz, (T)t1z, fma(dy, (T)t1y, dx * (T)t1x)) * (T)inv_h;
-        eta[e] = fma(dz, (T)t2z, fma(dy, (T)t2y, dx * (T)t2x)) * (T)inv_h;
-        zeta[e] = fma(dz, (T)n2, fma(dy, (T)n1, dx * (T)n0)) * (T)inv_h;
-      }
-      const T area = T(0.5) * fma(xi[1] - xi[0], eta[2] - eta[0], -((xi[2] - xi[0]) * (eta[1] - eta[0])));
-      T sm[6] = {T(3), T(0), T(0), T(0), T(0), T(0)};
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        const T mx = T(0.5) * (xi[e] + xi[(e + 1) % 3]);
-        const T my = T(0.5) * (eta[e] + eta[(e + 1) % 3]);
-        sm[1] += mx;
-        sm[2] += my;
-        sm[3] = fma(mx, mx, sm[3]);
-        sm[4] = fma(mx, my, sm[4]);
-        sm[5] = fma(my, my, sm[5]);
-      }
-      const T a3 = area * (T(1) / T(3));
-#pragma unroll
-      for (int qa = 0; qa < 6; ++qa) mom[qa] = a3 * sm[qa];
-      vt = a3 * (zeta[0] + zeta[1] + zeta[2]);
-    };
-
-    // ---- single precision: normal equations, factor, first solution
-    float accf[27];
-#pragma unroll
-    for (int qa = 0; qa < 27; ++qa) accf[qa] = 0.0f;
-    for (int k = 0; k < wrounds; ++k) {
-      const int j = k * G + gl;
-      const int4 t4 = j < cnt ? A.tri4[lt[j]] : kNone;
-      const float w = j < cnt ? (float)lw[j] : 0.0f;
-      float mom[6], vt;
-      moments(t4, 0.0f, mom, vt);
-      const float wv = w * vt;
-#pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        const float wa = w * mom[a];
-#pragma unroll
-        for (int b = a; b < 6; ++b) accf[P6(a, b)] = fmaf(wa, mom[b], accf[P6(a, b)]);
-        accf[21 + a] = fmaf(wv, mom[a], accf[21 + a]);
-      }
-    }
-#pragma unroll
-    for (int qa = 0; qa < 27; ++qa) accf[qa] = group_sum_f<G>(accf[qa]);
-    float invf[6];
-    const bool full = chol6(accf, invf, 1e-6f) && cnt >= 6;
-    double ah[6], rhs[6];
-#pragma unroll
-    for (int qa = 0; qa < 6; ++qa) rhs[qa] = (double)accf[21 + qa];
-    chol6_solve(accf, invf, rhs, ah);
-
-    // ---- two refinement steps with double-precision residuals
-    for (int it = 0; it < 2; ++it) {
-      double gr[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      for (int k = 0; k < wrounds; ++k) {
-        const int j = k * G + gl;
-        const int4 t4 = j < cnt ? A.tri4[lt[j]] : kNone;
-        const double w = j < cnt ? lw[j] : 0.0;
-        double mom[6], vt;
-        moments(t4, 0.0, mom, vt);
-        double r = vt;
-#pragma unroll
-        for (int a = 0; a < 6; ++a) r -= mom[a] * ah[a];
-        const double wr = w * r;
-#pragma unroll
-        for (int a = 0; a < 6; ++a) gr[a] = fma(wr, mom[a], gr[a]);
-      }
-#pragma unroll
-      for (int a = 0; a < 6; ++a) gr[a] = group_sum<G>(gr[a]);
-      chol6_solve(accf, invf, gr, gr);
-#pragma unroll
-      for (int a = 0; a < 6; ++a) ah[a] += gr[a];
-    }
-    if (act && wc >= 0.0 && gl < 7) A.fit[gl * cs + c] = gl < 6 ? ah[gl] : (full ? 1.0 : 0.0);
-  }
-}
-
-// Blocks [0, kWideBlocks): the cells queued for the wide shape, each solved
-// in its block; the other blocks: one thread per remaining cell.
-__global__ __launch_bounds__(64) void k_ppic_wide_solve(PPICArgs A) {
-  if ((int32_t)blockIdx.x < kWideBlocks) {
-    ppic_cells<Wide, true>(A, blockIdx.x, kWideBlocks);
-    return;
-  }
-  const int32_t nitems = min(A.counters[C_NIF], A.cell_cap);
-  const int64_t cs = A.cell_cap;
-  const int32_t nb = gridDim.x - kWideBlocks;
-  for (int32_t c = (blockIdx.x - kWideBlocks) * 64 + threadIdx.x; c < nitems; c += nb * 64) {
-    const double* F = A.fit + c;
-    if (F[30 * cs] == -3.0) continue;  // queued: solved by the wide shape
-    solve_cell(A, c, F, cs, A.prm.mixed != 0);
-  }
-}
+__global__ __launch_bounds__(64) void k_ppic_fast4(PPICArgs A) { ppic_fast<4, false>(A, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_ppic_fast8(PPICArgs A) { ppic_fast<8, false>(A, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(64) void k_ppic_fast16(PPICArgs A) { ppic_fast<16, false>(A, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(64) void k_ppic_fast8_mixed(PPICArgs A) { ppic_fast<8, true>(A, blockIdx.x, gridDim.x); }
 
 inline int32_t round_up(int64_t n, int64_t m) { return (int32_t)((n + m - 1) / m * m); }
 
@@ -1094,24 +1257,21 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
                              double* ny, double* nz, double* coeff, int32_t* cell_status, int32_t* diag,
                              const int32_t* sel, int32_t* n_sel_out, hipStream_t s) {
   const Grid& g = ws->grid;
-  int4* tri4 = reinterpret_cast<int4*>(ws->tri4);
-  double2* vtx4 = reinterpret_cast<double2*>(ws->vtx4);
   PPICArgs A;
   A.g = g;
   A.nv = m.nv;
   A.prm = p;
-  A.tri4 = tri4;
-  A.vtx4 = vtx4;
+  A.tri4 = reinterpret_cast<int4*>(ws->tri4);
+  A.vtx4 = reinterpret_cast<double2*>(ws->vtx4);
   A.cell_ids = ws->cell_ids;
   A.vt_off = ws->vt_off;
   A.vt_ids = ws->vt_ids;
+  A.vinc = reinterpret_cast<const int4*>(ws->vinc);
   A.best_d2 = ws->best_d2;
   A.best_v = ws->best_v;
   A.counters = ws->counters;
   A.ovf_cells = ws->ovf_cells;
-  A.fit = ws->fit;
-  A.wl_tri = ws->wl_tri;
-  A.wl_w = ws->wl_w;
+  A.frame_n = ws->frame_n;
   A.cell_cap = ws->cell_cap;
   A.kappa = kappa;
   A.nx = nx;
@@ -1122,26 +1282,25 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
   A.diag = diag;
   A.sel = sel;
   A.n_sel_out = n_sel_out;
-  const bool lanes16 = ws->tune.ring_lanes == 16;
-  const int64_t groups = ((int64_t)ws->cell_cap + (lanes16 ? Fast16::NG : Fast::NG) - 1) / (lanes16 ? Fast16::NG : Fast::NG);
-  const int64_t grid_cap = ws->tune.ring_blocks > 0 ? ws->tune.ring_blocks : 65536;
-  const int32_t blocks = round_up(std::min<int64_t>(std::max<int64_t>(groups, 1), grid_cap), kXCD);
   time_start(ws, FTC_KERNEL_PPIC, s);
   if (sel) {
     hipLaunchKernelGGL(k_ppic_wide_sel, dim3(round_up(std::min<int64_t>(std::max<int64_t>(ws->cell_cap, 1), 2048), kXCD)),
                        dim3(64), 0, s, A);
     hipLaunchKernelGGL(k_sel_done, dim3(1), dim3(1), 0, s, ws->counters, n_sel_out);
   } else {
-    if (lanes16)
-      hipLaunchKernelGGL(k_ppic_rings16, dim3(blocks), dim3(64), 0, s, A);
-    else
-      hipLaunchKernelGGL(k_ppic_rings, dim3(blocks), dim3(64), 0, s, A);
-    const dim3 fit_grid(round_up(std::min<int64_t>(std::max<int64_t>(((int64_t)ws->cell_cap + 7) / 8, 1), 65536), kXCD));
+    const int lanes = p.mixed ? 8 : ws->tune.ring_lanes;
+    const int64_t groups = ((int64_t)ws->cell_cap * lanes + 63) / 64;
+    const int64_t grid_cap = ws->tune.ring_blocks > 0 ? ws->tune.ring_blocks : 65536;
+    const dim3 grid(round_up(std::min<int64_t>(std::max<int64_t>(groups, 1), grid_cap), kXCD));
     if (p.mixed)
-      hipLaunchKernelGGL(k_ppic_fit_mixed, fit_grid, dim3(64), 0, s, A);
+      hipLaunchKernelGGL(k_ppic_fast8_mixed, grid, dim3(64), 0, s, A);
+    else if (lanes == 4)
+      hipLaunchKernelGGL(k_ppic_fast4, grid, dim3(64), 0, s, A);
+    else if (lanes == 16)
+      hipLaunchKernelGGL(k_ppic_fast16, grid, dim3(64), 0, s, A);
     else
-      hipLaunchKernelGGL(k_ppic_fit, fit_grid, dim3(64), 0, s, A);
-    hipLaunchKernelGGL(k_ppic_wide_solve, dim3(kWideBlocks + grid_blocks(ws->cell_cap, 64)), dim3(64), 0, s, A);
+      hipLaunchKernelGGL(k_ppic_fast8, grid, dim3(64), 0, s, A);
+    hipLaunchKernelGGL(k_ppic_wide, dim3(kWideBlocks), dim3(64), 0, s, A);
   }
   time_stop(ws, FTC_KERNEL_PPIC, s);
   return hipGetLastError();

@@ -42,20 +42,22 @@ __global__ void k_cell_sums(const int32_t* offsets, const double* piece_flux, co
 }
 
 // Column pass.  A workgroup takes 64 consecutive columns (x) of one y row
-// and splits the z range into kChunks chunks (4, 8 or 16), one wavefront each; lanes are
-// columns, so bitmap reads and dense stores are coalesced along x.
-//   1. each wavefront sums the fluxes of the interfacial cells in its chunk,
-//      top down;
+// and splits the z range into kChunks chunks (4, 8 or 16), one wavefront
+// each; lanes are columns, so bitmap reads and dense stores are coalesced
+// along x.  A chunk is walked top down in segments of 32 cells:
+//   1. each wavefront loads the 32 bitmap words of a segment together and
+//      keeps the segment's interfacial bits; only for those cells does it
+//      fetch the compact id and the flux, summed into the chunk total (the
+//      bits of up to kKeepSeg segments stay in registers for step 3);
 //   2. the chunk totals above give each chunk the wetted area W at its top;
 //   3. each wavefront walks its chunk top down again: an interfacial cell
 //      gets (V + h W) / h^3 and adds its flux to W, any other cell gets
 //      round(W / h^2), which must be 0 or 1 within 1e-9 (else the front is
-//      open: ERR_MESH), as must W below the lowest chunk.
+//      open: ERR_MESH), as must W below the lowest chunk.  Between
+//      interfacial cells the walk only stores.
 constexpr int kColLanes = 64;
-// cells of a chunk read at once: 16, or 8 with 16 chunks (whose 1024-thread
-// workgroups leave 128 registers per lane)
-template <int kChunks>
-constexpr int sub_of() { return kChunks == 16 ? 8 : 16; }
+constexpr int kSeg = 32;      // cells per segment: one bit mask
+constexpr int kKeepSeg = 8;   // segment masks kept between the two walks (chunks of up to 256 cells)
 
 struct ColArgs {
   Grid g;
@@ -69,40 +71,37 @@ struct ColArgs {
   int32_t* counters;
 };
 
-// Reads kSub cells k1, k1-1, ... (those >= klo) of column (i, j): which are
-// interfacial, their compact ids (-1: not interfacial; -2: interfacial but
-// beyond the cell capacity, a latched capacity error, taken with no
-// pieces), fluxes and (if `vol`) volume integrals.
-template <bool kVol, int kSub>
-__device__ inline void read_sub(const ColArgs& A, bool col_ok, int32_t i, int32_t j, int32_t k1, int32_t klo,
-                                int32_t ci[kSub], double fl[kSub], double vo[kSub]) {
+// Interfacial bits of cells k1, k1-1, ..., k1-31 (those >= klo) of column
+// (i, j): bit q for cell k1 - q.
+__device__ inline uint32_t segment_mask(const ColArgs& A, bool col_ok, int32_t i, int32_t j, int32_t k1,
+                                        int32_t klo) {
   const Grid& g = A.g;
-  uint32_t wv[kSub], lin[kSub];  // cell ids fit in 31 bits
+  const int64_t col = i + (int64_t)g.nx * j, sz = (int64_t)g.nx * g.ny;
+  uint32_t wv[kSeg];
 #pragma unroll
-  for (int q = 0; q < kSub; ++q) {
-    const int32_t k = k1 - q;
-    lin[q] = (uint32_t)(i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
-    wv[q] = (col_ok && k >= klo) ? A.bitmap[lin[q] >> 5] : 0u;
+  for (int q = 0; q < kSeg; ++q) {
+    const int64_t lin = col + sz * (k1 - q);
+    wv[q] = (col_ok && k1 - q >= klo) ? A.bitmap[lin >> 5] : 0u;
   }
-  int32_t wo[kSub];
+  uint32_t m = 0u;
 #pragma unroll
-  for (int q = 0; q < kSub; ++q) {
-    const bool set = (wv[q] >> (lin[q] & 31)) & 1u;
-    wo[q] = A.word_off[set ? (lin[q] >> 5) : 0];
-    const int32_t r = wo[q] + __popc(wv[q] & ((1u << (lin[q] & 31)) - 1u));
-    ci[q] = !set ? -1 : (r < A.cell_cap ? r : -2);
+  for (int q = 0; q < kSeg; ++q) {
+    const int64_t lin = col + sz * (k1 - q);
+    m |= ((wv[q] >> (lin & 31)) & 1u) << q;
   }
-#pragma unroll
-  for (int q = 0; q < kSub; ++q) {
-    const int32_t c = ci[q] >= 0 ? ci[q] : 0;
-    fl[q] = ci[q] >= 0 ? A.cell_flux[c] : 0.0;
-    if (kVol) vo[q] = ci[q] >= 0 ? A.cell_vol[c] : 0.0;
-  }
+  return m;
+}
+
+// Compact id of the interfacial cell lin (-2: beyond the cell capacity, a
+// latched capacity error, taken with no pieces).
+__device__ inline int32_t compact_id(const ColArgs& A, int64_t lin) {
+  const uint32_t w = A.bitmap[lin >> 5];
+  const int32_t r = A.word_off[lin >> 5] + __popc(w & ((1u << (lin & 31)) - 1u));
+  return r < A.cell_cap ? r : -2;
 }
 
 template <int kChunks>
 __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
-  constexpr int kSub = sub_of<kChunks>();
   __shared__ double tot_s[kChunks][kColLanes];
   const Grid& g = A.g;
   const int lane = threadIdx.x % kColLanes, w = threadIdx.x / kColLanes;
@@ -111,44 +110,66 @@ __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
   const int32_t len = (g.nz + kChunks - 1) / kChunks;
   const int32_t klo = min(w * len, g.nz), khi = min(klo + len, g.nz);
   const double h = g.h, h2 = h * h, h3 = h * h * h;
-  int32_t ci[kSub];
-  double fl[kSub], vo[kSub];
+  const int64_t col = i + (int64_t)g.nx * j, sz = (int64_t)g.nx * g.ny;
 
-  // a chunk of at most kSub cells is read once, for both walks
-  const bool once = khi - klo <= kSub;
+  // ---- 1. interfacial bits and the chunk's flux total
+  uint32_t keep[kKeepSeg];
   double tot = 0.0;
-  for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSub) {
-    if (once)
-      read_sub<true, kSub>(A, col_ok, i, j, k1, klo, ci, fl, vo);
-    else
-      read_sub<false, kSub>(A, col_ok, i, j, k1, klo, ci, fl, vo);
+  {
+    int s = 0;
+    for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSeg, ++s) {
+      uint32_t m = segment_mask(A, col_ok, i, j, k1, klo);
 #pragma unroll
-    for (int q = 0; q < kSub; ++q)
-      if (ci[q] >= 0) tot += fl[q];
+      for (int u = 0; u < kKeepSeg; ++u)
+        if (u == s) keep[u] = m;
+      while (m) {
+        const int q = __ffs(m) - 1;
+        m &= m - 1u;
+        const int32_t ci = compact_id(A, col + sz * (k1 - q));
+        if (ci >= 0) tot += A.cell_flux[ci];
+      }
+    }
   }
   tot_s[w][lane] = tot;
   __syncthreads();
   double W = 0.0;
   for (int u = kChunks - 1; u > w; --u) W += tot_s[u][lane];
 
+  // ---- 3. alpha of every cell of the chunk
   bool bad = false;
-  for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSub) {
-    if (!once) read_sub<true, kSub>(A, col_ok, i, j, k1, klo, ci, fl, vo);
+  double rr = 0.0;     // round(W / h^2) for the cells that are not interfacial
+  bool fresh = false;  // rr (and its check) belongs to the current W
+  int s = 0;
+  for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSeg, ++s) {
+    uint32_t m = 0u;
+    if (s < kKeepSeg) {
 #pragma unroll
-    for (int q = 0; q < kSub; ++q) {
-      const int32_t k = k1 - q;
-      if (!col_ok || k < klo) continue;
+      for (int u = 0; u < kKeepSeg; ++u)
+        if (u == s) m = keep[u];
+    } else {
+      m = segment_mask(A, col_ok, i, j, k1, klo);
+    }
+    const int nq = min(kSeg, k1 - klo + 1);
+    for (int q = 0; q < nq; ++q) {
+      const int64_t lin = col + sz * (k1 - q);
       double a;
-      if (ci[q] != -1) {
-        a = (vo[q] + h * W) / h3;
-        if (A.alpha_if && ci[q] >= 0) A.alpha_if[ci[q]] = a;
-        W += fl[q];
+      if ((m >> q) & 1u) {
+        const int32_t ci = compact_id(A, lin);
+        const double vo = ci >= 0 ? A.cell_vol[ci] : 0.0;
+        a = (vo + h * W) / h3;
+        if (A.alpha_if && ci >= 0) A.alpha_if[ci] = a;
+        if (ci >= 0) W += A.cell_flux[ci];
+        fresh = false;
       } else {
-        const double r = W / h2, rr = round(r);
-        if (fabs(r - rr) > 1e-9 || (rr != 0.0 && rr != 1.0)) bad = true;
+        if (!fresh) {
+          const double r = W / h2;
+          rr = round(r);
+          if (fabs(r - rr) > 1e-9 || (rr != 0.0 && rr != 1.0)) bad = true;
+          fresh = true;
+        }
         a = rr;
       }
-      if (A.alpha) A.alpha[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)] = a;
+      if (A.alpha && col_ok) A.alpha[lin] = a;
     }
   }
   if (w == 0 && col_ok && fabs(W / h2) > 1e-9) bad = true;  // the column must close below the front

@@ -1,8 +1,8 @@
 """Autotuner of the launch shapes (ftc_tuning) for a given front: the whole
 coupling step is captured in a HIP graph for each candidate shape and timed
 by replays; the fastest shape is kept.  The knobs are searched one after
-another (lanes per cell in the PPIC ring pass, z-chunks per column block,
-the ring pass's grid), each with the others at their best so far.  Every
+another (lanes per cell in the fast PPIC shape, z-chunks per column block,
+the fast PPIC shape's grid), each with the others at their best so far.  Every
 shape gives the same cell lists, decisions and curvatures, so the choice is
 a matter of time only."""
 from __future__ import annotations
@@ -14,7 +14,7 @@ import torch
 from . import ftc
 
 CANDIDATES = {
-    "ring_lanes": (8, 16),
+    "ring_lanes": (4, 8, 16),
     "column_chunks": (4, 8, 16),
     "ring_blocks": (0, 2048, 8192),
 }
