@@ -372,6 +372,22 @@ ftc_status ftc_mlp_loss_grad(const float* theta, const float* X, int64_t rows, c
                              const int32_t* sym, const float* t, int32_t n, float* grad, float* loss,
                              float* work, void* stream);
 
+/* ftc_mlp_loss_grad for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving or training loops, harnesses that
+   forbid hipMalloc): the same arguments without `work`, and the same
+   results bit for bit.  The partial rows live in a fixed scratch array of
+   the library, FTC_MLP_WORK_FLOATS floats (6.4 MB) on each device that
+   calls it, held until the process ends; its address is resolved on the
+   first call on each device (that call may return FTC_EHIP if the runtime
+   cannot resolve it).  The call allocates and frees nothing.  Any n > 0 is
+   accepted: at most 256 workgroups write partial rows, each its whole row,
+   so the scratch never needs clearing.  Calls that overlap on one device
+   (concurrent streams or host threads) share the scratch and race; order
+   them on one stream. */
+ftc_status ftc_mlp_loss_grad_static(const float* theta, const float* X, int64_t rows, const int32_t* idx,
+                                    const int32_t* sym, const float* t, int32_t n, float* grad, float* loss,
+                                    void* stream);
+
 /* One Adam step (Kingma and Ba, ICLR 2015) on theta, with first and second
    moments m, v (device, FTC_MLP_PARAMS floats each, zero before step 1) and
    bias correction: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,

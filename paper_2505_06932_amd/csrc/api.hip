@@ -373,6 +373,13 @@ ftc_status ftc_mlp_loss_grad(const float* theta, const float* X, int64_t rows, c
   return hip_status(ftc::launch_mlp_loss_grad(theta, X, rows, idx, sym, t, n, grad, loss, work, (hipStream_t)stream));
 }
 
+ftc_status ftc_mlp_loss_grad_static(const float* theta, const float* X, int64_t rows, const int32_t* idx,
+                                    const int32_t* sym, const float* t, int32_t n, float* grad, float* loss,
+                                    void* stream) {
+  if (!theta || !X || rows <= 0 || !t || n <= 0 || !grad) return FTC_EINVAL;
+  return hip_status(ftc::launch_mlp_loss_grad_static(theta, X, rows, idx, sym, t, n, grad, loss, (hipStream_t)stream));
+}
+
 ftc_status ftc_mlp_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr, float beta1,
                         float beta2, float eps, void* stream) {
   if (!theta || !m || !v || !grad || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||

@@ -179,6 +179,11 @@ hipError_t launch_mlp_forward(const float* theta, const float* X, int64_t rows, 
 hipError_t launch_mlp_loss_grad(const float* theta, const float* X, int64_t rows, const int32_t* idx,
                                 const int32_t* sym, const float* t, int32_t n, float* grad, float* loss, float* work,
                                 hipStream_t s);
+// The same with the partial rows in the library's own per-device scratch
+// (allocates nothing).
+hipError_t launch_mlp_loss_grad_static(const float* theta, const float* X, int64_t rows, const int32_t* idx,
+                                       const int32_t* sym, const float* t, int32_t n, float* grad, float* loss,
+                                       hipStream_t s);
 hipError_t launch_mlp_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr, float beta1,
                            float beta2, float eps, hipStream_t s);
 hipError_t launch_surrogate(const ftc_cells* ws, const Mesh& m, const double* alpha, const float* theta, float bound,

@@ -36,6 +36,8 @@
 // spread (max - min).  A cell whose spread exceeds the bound, or without a
 // closest vertex within 1.5 h of its centre, is handed to the PPIC kernels,
 // which then run on those cells only.
+#include <mutex>
+
 #include "ftc_ws.hpp"
 
 namespace ftc {
@@ -828,6 +830,45 @@ hipError_t launch_mlp_loss_grad(const float* theta, const float* X, int64_t rows
   hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(64), 0, s, A);
   hipLaunchKernelGGL(k_mlp_reduce, dim3((kNP + 1 + 255) / 256), dim3(256), 0, s, work, nblk, n, grad, loss);
   return hipGetLastError();
+}
+
+namespace {
+// Scratch of the entry point that allocates nothing: the partial gradient
+// rows of k_mlp_grad, as many as the caller's work buffer of
+// ftc_mlp_loss_grad holds.  Each device holds its own copy for the life of
+// the process.  In host code the array's name is not a device address: the
+// kernels take the address hipGetSymbolAddress gives for the device.
+__device__ __align__(256) float scratch[kGradBlocks * kPartStride];
+constexpr int kMaxDevices = 64;
+float* g_scratch[kMaxDevices] = {};  // the scratch's address on each device, once resolved
+std::mutex g_scratch_mu;
+
+// Address of the current device's scratch, resolved on its first use there.
+hipError_t scratch_address(float** out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_mlp_loss_grad_static(const float* theta, const float* X, int64_t rows, const int32_t* idx,
+                                       const int32_t* sym, const float* t, int32_t n, float* grad, float* loss,
+                                       hipStream_t s) {
+  float* work = nullptr;
+  const hipError_t e = scratch_address(&work);
+  if (e != hipSuccess) return e;
+  return launch_mlp_loss_grad(theta, X, rows, idx, sym, t, n, grad, loss, work, s);
 }
 
 hipError_t launch_mlp_adam(float* theta, float* m, float* v, const float* grad, int32_t step, float lr, float beta1,

@@ -35,7 +35,7 @@ EXPORTED = ["ftc_cells_create", "ftc_cells_destroy", "ftc_build_cell_lists", "ft
             "ftc_cells_view", "ftc_volume_fraction", "ftc_ppic_curvature", "ftc_csf_force",
             "ftc_interp_vertex_velocity", "ftc_last_device_error", "ftc_set_timing", "ftc_kernel_time",
             "ftc_csf_force_band", "ftc_advect_vertices_rk4", "ftc_curvature_features", "ftc_mlp_forward",
-            "ftc_mlp_loss_grad", "ftc_mlp_adam", "ftc_learned_curvature", "ftc_front_roughness",
+            "ftc_mlp_loss_grad", "ftc_mlp_loss_grad_static", "ftc_mlp_adam", "ftc_learned_curvature", "ftc_front_roughness",
             "ftc_smooth_rough_edges", "ftc_get_tuning", "ftc_set_tuning", "ftc_surface_tension_flux",
             "ftc_paraboloid_cell", "ftc_status_str"]
 
@@ -138,6 +138,8 @@ def lib() -> C.CDLL:
     L.ftc_mlp_forward.restype = C.c_int32
     L.ftc_mlp_loss_grad.argtypes = [vp, vp, C.c_int64, vp, vp, vp, C.c_int32, vp, vp, vp, vp]
     L.ftc_mlp_loss_grad.restype = C.c_int32
+    L.ftc_mlp_loss_grad_static.argtypes = [vp, vp, C.c_int64, vp, vp, vp, C.c_int32, vp, vp, vp]
+    L.ftc_mlp_loss_grad_static.restype = C.c_int32
     L.ftc_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
     L.ftc_mlp_adam.restype = C.c_int32
     L.ftc_learned_curvature.argtypes = [vp, P(_CGrid), P(_CMesh), vp, vp, C.c_double, P(_CParams), vp, vp, vp, vp,
@@ -473,6 +475,20 @@ def mlp_loss_grad(theta, X, t, grad, work, loss=None, n=None, idx=None, sym=None
                                    _ptr(loss, torch.float32, 1, "loss"),
                                    _ptr(work, torch.float32, MLP_WORK_FLOATS, "work"), _stream(stream)),
            "ftc_mlp_loss_grad")
+
+
+def mlp_loss_grad_static(theta, X, t, grad, loss=None, n=None, idx=None, sym=None, stream=None) -> None:
+    """mlp_loss_grad with the partial rows in the library's own scratch (the
+    entry point that allocates nothing)."""
+    rows = _rows(X)
+    n = rows if n is None and idx is None else (int(idx.numel()) if n is None else int(n))
+    _check(lib().ftc_mlp_loss_grad_static(_ptr(theta, torch.float32, MLP_PARAMS, "theta"),
+                                          _ptr(X, torch.float32, rows * MLP_FEATURES, "X"), rows,
+                                          _ptr(idx, torch.int32, n, "idx"), _ptr(sym, torch.int32, n, "sym"),
+                                          _ptr(t, torch.float32, rows, "t"), n,
+                                          _ptr(grad, torch.float32, MLP_PARAMS, "grad"),
+                                          _ptr(loss, torch.float32, 1, "loss"), _stream(stream)),
+           "ftc_mlp_loss_grad_static")
 
 
 def mlp_adam(theta, m, v, grad, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
