@@ -4,17 +4,23 @@
 A step is one pass of the whole hot path over one front: cell lists, exact
 volume fractions (interfacial cells and the dense field), PPIC curvature,
 CSF force on the interfacial cells and vertex-velocity interpolation.  The
-workload is the 128^3 sphere (R = 0.3, icosphere with 6 subdivisions =
-81,920 triangles, radial noise 0.01 h, stream-function face velocities,
-sigma = 1).  Inputs are resident in device memory before timing starts.
+default workload is the large surface: a polar surface of revolution
+rho(theta) = R (1 - 0.3 cos^2 theta + 0.2 cos^4 theta), R = 0.2, as a
+geodesic mesh of 1,997,120 triangles on a 512^3 grid, with stream-function
+face velocities and sigma = 1 (--workload picks another).  Inputs are
+resident in device memory before timing starts.
 
 Timed region: W warm-up steps, then K steps replayed from a HIP graph of one
 step, bracketed by device synchronisation; value = interfacial cells x K /
 elapsed seconds.  After it, K eager steps with the library's timing events
-give the average duration of each kernel; the PPIC kernel's FP64 work per
-launch over that duration is the roofline figure.  The CPU oracle is then
-timed on the host on the same workload and its outputs are compared with the
-GPU's.  One JSON line goes to stdout; progress goes to stderr.
+(recorded on the launch stream) give the average duration of each call; the
+PPIC call's FP64 work per launch over that duration is the roofline figure.
+The CPU oracle is then timed on the host (all cores, then one thread) on the
+same workload: full cell lists and volume fractions, PPIC and CSF on a
+seeded sample of cells scaled to all of them, interpolation of every
+vertex; its outputs are compared with the GPU's (lists and volume fractions
+in full, curvature and forces on the sample).  One JSON line goes to stdout;
+progress goes to stderr.
 """
 import argparse
 import hashlib
@@ -31,7 +37,7 @@ METRIC = "interfacial cells/s (volume fraction+PPIC curvature), err vs FP64 orac
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic FP64 operations of the PPIC curvature call (its four kernels
+# Algorithmic FP64 operations of the PPIC curvature call (its two kernels
 # are timed together): per ring triangle (centre distance), per weighted
 # triangle (weight, projection, moments, normal-equation update), per cell
 # (vertex normal, frame, 6x6 Cholesky with one refinement step, curvature,
@@ -59,7 +65,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default=None,
-                    help="sphere_128 (default), or sh_spheres_128 (default with --learned)")
+                    help="revolution_512 (default), sphere_128, ellipsoids_256, or sh_spheres_128 "
+                         "(default with --learned)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph")
     ap.add_argument("--mixed", action="store_true",
@@ -70,6 +77,8 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="choose the launch shapes with the autotuner (whole-step graph timings) before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4096,
+                    help="interfacial cells of the oracle's PPIC and CSF sample (all cells if fewer)")
     ap.add_argument("--extras", action="store_true",
                     help="also time the calls outside the step: the paraboloid cell quantities, the CSF band mode, "
                          "the surface-tension face flux, RK4 advection, roughness detection and smoothing")
@@ -100,7 +109,7 @@ def main():
         return
     K, Wm = args.steps, args.warmup
     if args.workload is None:
-        args.workload = "sh_spheres_128" if args.learned else "sphere_128"
+        args.workload = "sh_spheres_128" if args.learned else "revolution_512"
 
     grid, mesh, centre = I.make_workload(args.workload, args.seed)
     U, V, W = I.psi_face_velocity(grid)
@@ -201,69 +210,101 @@ def main():
 
     # ---------------------------------------------------------- CPU oracle
     if not args.no_cpu_baseline:
-        import oracle
-        log("[bench] timing the CPU oracle")
-        from oracle import surrogate as OS
-        theta_h = theta.cpu().numpy().astype(np.float64) if args.learned else None
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            cells, offsets, tris = oracle.cell_lists(grid, mesh)
-            alpha, _ = oracle.volume_fraction(grid, mesh)
-            if args.learned:
-                # the surrogate's definition: features, four symmetries, PPIC where not trusted
-                F, final = OS.features(grid, mesh, alpha, cells)
+        base, errs = cpu_baseline(args, grid, mesh, centre, U, V, W, res, step, theta, n_if)
+        out["cpu_baseline"] = base
+        out["err_vs_oracle"] = errs
+        log(f"[bench] oracle {base['value']:.3e} cells/s on {base['cores']} threads, "
+            f"{base['single_thread']['value']:.3e} on one; errors {errs}")
+    print(json.dumps(out), flush=True)
+
+
+def _timed(fn):
+    t0 = time.perf_counter()
+    r = fn()
+    return time.perf_counter() - t0, r
+
+
+def cpu_baseline(args, grid, mesh, centre, U, V, W, res, step, theta, n_if):
+    """The oracle timed on the host, all cores then one thread: full cell
+    lists and dense volume fractions, PPIC (or the learned form) and CSF on
+    a seeded sample of interfacial cells (its time scaled by n_if / sample),
+    interpolation of every vertex; and the GPU's errors against it (lists,
+    volume fractions and velocities in full, curvature, normals, decisions
+    and forces on the sample)."""
+    import numpy as np
+    import oracle
+    from oracle import surrogate as OS
+    log("[bench] timing the CPU oracle")
+    rng = np.random.default_rng(args.seed + 12345)
+    theta_h = theta.cpu().numpy().astype(np.float64) if args.learned else None
+    legs = {}
+    for leg, nthreads in (("all", 0), ("single", 1)):
+        oracle.set_threads(nthreads)
+        cores = oracle.threads()
+        t_lists, (cells, offsets, tris) = _timed(lambda: oracle.cell_lists(grid, mesh))
+        t_vf, (alpha, _) = _timed(lambda: oracle.volume_fraction(grid, mesh))
+        ns = min(len(cells), args.cpu_sample if leg == "all" else max(1, args.cpu_sample // 4))
+        samp = np.sort(rng.choice(len(cells), ns, replace=False)) if ns < len(cells) else np.arange(len(cells))
+        if args.learned:
+            # the surrogate's definition: features, four symmetries, PPIC where not trusted
+            def learned():
+                F, final = OS.features(grid, mesh, alpha, cells[samp])
                 mean, spread = OS.predict(theta_h, F)
                 fb = ~final | ~(spread <= step.bound)
-                kap_l = mean / grid.h
-                kap_l[fb] = oracle.ppic(grid, mesh, cells[fb])["kappa"]
-                r = {"kappa": kap_l, "status": np.zeros(len(cells), np.int32), "fallback": fb}
-            else:
-                r = oracle.ppic(grid, mesh, cells)  # always double precision
-            force = oracle.csf(grid, alpha, cells, r["kappa"], 1.0)
-            u = oracle.interp(grid, mesh.x, mesh.y, mesh.z, U, V, W)
-            reps += 1
-            if time.perf_counter() - t0 > 12.0 or reps >= 1000:
-                break
-        cpu_s = time.perf_counter() - t0
-        out["cpu_baseline"] = {
-            "value": len(cells) * reps / cpu_s, "unit": "interfacial cells/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"{reps} full steps of {args.workload} (cell lists, volume fraction, PPIC, CSF, "
-                      f"interpolation), {cpu_s:.1f} s; OpenMP over cells/columns/vertices, "
-                      f"cell lists and piece integrals serial; host nproc={os.cpu_count()}, cpu={_cpu_model()}"}
-        ok = r["status"] == 0
-        same_lists = bool(np.array_equal(res["cell_ids"], cells) and np.array_equal(res["tri_ids"], tris))
-        out["err_vs_oracle"] = {
-            "cell_lists_identical": same_lists,
-            "max_abs_alpha": float(np.abs(res["alpha"] - alpha).max()),
-            "max_rel_kappa": float(np.max(np.abs(res["kappa"][ok] - r["kappa"][ok]) / np.abs(r["kappa"][ok]))),
-            "max_rel_force": float(np.abs(res["force"][ok] - force[ok]).max() / np.abs(force[ok]).max()),
-            "max_rel_velocity": float(np.abs(res["u"] - u).max() / np.abs(u).max()),
-        }
-        if args.learned:
-            # the learned form against the double-precision PPIC oracle
-            fb_g = (res["status"] & ftc.FTC_CELL_SURROGATE) == 0
-            ppic_all = oracle.ppic(grid, mesh, cells)
-            okp = ppic_all["status"] == 0
-            rel = np.abs(res["kappa"] - ppic_all["kappa"]) / np.abs(ppic_all["kappa"])
-            tr = ~fb_g & okp
-            out["err_vs_oracle"].update({
-                "fallback_frac": float(fb_g.mean()),
-                "fallback_decisions_match_oracle": float(np.mean(fb_g == r["fallback"])),
-                "fallback_max_rel_kappa_vs_ppic": float(rel[fb_g & okp].max()) if (fb_g & okp).any() else None,
-                "surrogate_rel_kappa_vs_ppic_q50_q90_q99": [float(np.quantile(rel[tr], q)) for q in (0.5, 0.9, 0.99)],
-                "surrogate_abs_kappa_h_vs_ppic_rms": float(np.sqrt(np.mean(((res["kappa"] - ppic_all["kappa"])[tr]
-                                                                             * grid.h) ** 2))),
-            })
+                kap = mean / grid.h
+                kap[fb] = oracle.ppic(grid, mesh, cells[samp][fb])["kappa"]
+                return {"kappa": kap, "status": np.zeros(ns, np.int32), "fallback": fb}
+            t_ppic, r = _timed(learned)
         else:
-            out["err_vs_oracle"]["decisions_identical"] = bool(np.array_equal(res["diag"], r["diag"]))
-        # the enclosed volume of a closed mesh does not depend on the reference point
-        ref = centre if np.asarray(centre).shape == (3,) else np.zeros(3)
-        out["err_vs_oracle"]["volume_rel_err"] = float(abs(math.fsum(res["alpha"].ravel()) * grid.h ** 3 /
-                                                           _vpoly(mesh, ref) - 1.0))
-        log(f"[bench] oracle {out['cpu_baseline']['value']:.3e} cells/s on {oracle.threads()} threads; "
-            f"errors {out['err_vs_oracle']}")
-    print(json.dumps(out), flush=True)
+            t_ppic, r = _timed(lambda: oracle.ppic(grid, mesh, cells[samp]))  # always double precision
+        t_csf, force = _timed(lambda: oracle.csf(grid, alpha, cells[samp], r["kappa"], 1.0))
+        t_interp, u = _timed(lambda: oracle.interp(grid, mesh.x, mesh.y, mesh.z, U, V, W))
+        per_step = t_lists + t_vf + (t_ppic + t_csf) * len(cells) / ns + t_interp
+        legs[leg] = {"value": len(cells) / per_step, "cores": cores, "sample_cells": int(ns),
+                     "s": {"cell_lists": t_lists, "volume_fraction": t_vf, "curvature_sample": t_ppic,
+                           "csf_sample": t_csf, "interp": t_interp}}
+        log(f"[bench] oracle leg {leg}: {cores} threads, {per_step:.2f} s per step estimated")
+        if leg == "all":
+            ref = (cells, tris, alpha, samp, r, force, u)
+    oracle.set_threads(0)
+    a = legs["all"]
+    base = {"value": a["value"], "unit": "interfacial cells/s", "cores": a["cores"], "kind": "oracle",
+            "sample": f"{args.workload}: full cell lists and dense volume fractions, "
+                      f"{'learned curvature' if args.learned else 'PPIC'} and CSF on {a['sample_cells']} seeded "
+                      f"interfacial cells of {n_if} (time scaled by {n_if / a['sample_cells']:.1f}), "
+                      f"interpolation of all {mesh.nv} vertices; seconds {a['s']}; "
+                      f"host nproc={os.cpu_count()}, cpu={_cpu_model()}",
+            "single_thread": {"value": legs["single"]["value"], "cores": 1,
+                              "sample_cells": legs["single"]["sample_cells"], "s": legs["single"]["s"]}}
+    cells, tris, alpha, samp, r, force, u = ref
+    ok = r["status"] == 0
+    g_k, g_f = res["kappa"][samp], res["force"][samp]
+    errs = {
+        "cell_lists_identical": bool(np.array_equal(res["cell_ids"], cells) and np.array_equal(res["tri_ids"], tris)),
+        "max_abs_alpha": float(np.abs(res["alpha"] - alpha).max()),
+        "sample_cells": int(len(samp)),
+        "max_rel_kappa": float(np.max(np.abs(g_k[ok] - r["kappa"][ok]) / np.abs(r["kappa"][ok]))),
+        "max_rel_force": float(np.abs(g_f[ok] - force[ok]).max() / np.abs(force[ok]).max()),
+        "max_rel_velocity": float(np.abs(res["u"] - u).max() / np.abs(u).max()),
+    }
+    if args.learned:
+        # the learned form against the double-precision PPIC oracle, on the sample
+        fb_g = (res["status"][samp] & 4) == 0
+        errs["fallback_frac"] = float(fb_g.mean())
+        errs["fallback_decisions_match_oracle"] = float(np.mean(fb_g == r["fallback"]))
+        pp = oracle.ppic(grid, mesh, cells[samp])
+        okp = pp["status"] == 0
+        rel = np.abs(g_k - pp["kappa"]) / np.abs(pp["kappa"])
+        tr = ~fb_g & okp
+        if tr.any():
+            errs["surrogate_rel_kappa_vs_ppic_q50_q90_q99"] = [float(np.quantile(rel[tr], q)) for q in (0.5, 0.9, 0.99)]
+            errs["surrogate_abs_kappa_h_vs_ppic_rms"] = float(np.sqrt(np.mean(((g_k - pp["kappa"])[tr] * grid.h) ** 2)))
+    else:
+        errs["decisions_identical"] = bool(np.array_equal(res["diag"][samp], r["diag"]))
+    # the enclosed volume of a closed mesh does not depend on the reference point
+    refp = centre if np.asarray(centre).shape == (3,) else np.zeros(3)
+    errs["volume_rel_err"] = float(abs(math.fsum(res["alpha"].ravel()) * grid.h ** 3 / _vpoly(mesh, refp) - 1.0))
+    return base, errs
 
 
 def time_extras(step, grid, mesh, res, n_if, K, log):
@@ -338,7 +379,7 @@ def ppic_roofline(res, kern_ms, workload):
             t = json.load(f)
         if t.get("source_digest") == digest:
             traffic = t.get("bytes_per_launch")
-    return {"kernel": "ppic_curvature: k_ppic_rings + k_ppic_fit + k_ppic_wide_solve",
+    return {"kernel": "ppic_curvature: k_ppic_fast8 + k_ppic_wide",
             "bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": traffic,
             "flop_per_launch": flops, "avg_launch_ms": kern_ms["ppic"], "source_digest": digest}

@@ -187,9 +187,12 @@ ftc_status ftc_ppic_curvature(const ftc_cells* cells, const ftc_grid* grid, cons
    sign convention as ftc_ppic_curvature); normal_cell [3][cell_capacity] or
    NULL, the normalised integral of the unit normal (pointing out of the
    liquid) over that surface.  The volume is exact in one tangential
-   direction and a Gauss rule between exact breakpoints in the other (about
-   1e-14); the surface integrals add a Gauss rule between the breakpoints in
-   the first.  NaN for a cell whose fit failed, and kappa_cell and
+   direction and a 16-node Gauss rule between exact breakpoints in the other
+   (about 1e-14); when kappa_cell or normal_cell is asked for, that rule has
+   24 nodes (for the normal integral; alpha then agrees with the volume-only
+   call to about 1e-13, not bit for bit) and the area and curvature add an
+   8-node rule between the breakpoints in the first direction.  NaN for a
+   cell whose fit failed, and kappa_cell and
    normal_cell NaN where the paraboloid does not cross the cell.
    FTC_EINVAL unless ftc_ppic_curvature (not the learned curvature) ran after
    the last ftc_build_cell_lists. */

@@ -36,6 +36,8 @@ raises QuadratureError instead of returning an unconverged value.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 from scipy import integrate
 
@@ -367,3 +369,29 @@ def surface_cells(frame_normals, coeffs, h, tol: float = 1e-13):
             kap[i] = np.nan
             nrm[i] = np.nan
     return kap, nrm
+
+
+def _pool_chunk(job):
+    kind, frame_normals, coeffs, h = job
+    if kind == "alpha":
+        return alpha_cells(frame_normals, coeffs, h)
+    return surface_cells(frame_normals, coeffs, h)
+
+
+def map_cells(kind, frame_normals, coeffs, h, workers: int = 12):
+    """alpha_cells ("alpha") or surface_cells ("surface") of the listed cells,
+    computed in a pool of at most `workers` CPU processes (started fresh, so
+    they hold none of the caller's state and never touch a GPU); the results
+    are those of the serial call, cell by cell."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    frame_normals, coeffs = np.asarray(frame_normals), np.asarray(coeffs)
+    n = len(coeffs)
+    workers = max(1, min(workers, os.cpu_count() or 1, n))
+    parts = [p for p in np.array_split(np.arange(n), 4 * workers) if len(p)]
+    jobs = [(kind, frame_normals[p], coeffs[p], h) for p in parts]
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_pool_chunk, jobs))
+    if kind == "alpha":
+        return np.concatenate(res)
+    return np.concatenate([r[0] for r in res]), np.concatenate([r[1] for r in res])

@@ -146,7 +146,6 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(vt_loc, 3 * Tc);
   FTC_ALLOC(vt_ids, 3 * Tc);
   FTC_ALLOC(tri4, 4 * Tc);
-  FTC_ALLOC(vinc, 4 * ftc::kIncSlots * Vc);
   FTC_ALLOC(vtx4, 4 * Vc);
   FTC_ALLOC(ovf_cells, Cc);
   FTC_ALLOC(vcell, Vc);

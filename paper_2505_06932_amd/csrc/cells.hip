@@ -351,54 +351,31 @@ struct PlaceArgs {
   const int32_t* counters;
 };
 
-constexpr int kSortLanes = 32;  // lanes per interfacial cell when placing its pieces
+constexpr int kSegReg = 16;  // segment entries read in one batch of loads
 
-__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
-  const int lo = __shfl_xor((int)(uint32_t)v, m, kSortLanes), hi = __shfl_xor((int)(uint32_t)(v >> 32), m, kSortLanes);
-  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-// The pieces of interfacial cell ci to their rank by triangle id within its
-// segment (a triangle has at most one piece per cell, so the ranks are
-// distinct), by the kSortLanes lanes l of the cell: a segment of up to
-// kSortLanes entries is sorted with a bitonic network over the lanes (keys
-// triangle id, then pair slot); a longer one places each entry at its
-// rank, counted over the segment.  Called with all 64 lanes of the
-// wavefront.
-__device__ inline void place_cell(const PlaceArgs& A, int64_t ci, int l) {
+// Each scattered piece moves to its rank by triangle id within its cell (a
+// triangle has at most one piece per cell, so the ranks are distinct): one
+// thread per piece counts the smaller triangle ids of its segment, read
+// kSegReg at a time with the loads of a batch issued together.
+__device__ inline void rank_place(const PlaceArgs& A, int64_t bid, int64_t nblk) {
   const int32_t nif = min(A.counters[C_NIF], A.cell_cap);
-  const bool act = ci < nif;
-  const int64_t s = act ? A.offsets[ci] : 0, e = act ? min((int64_t)A.offsets[ci + 1], A.pair_cap) : 0;
-  const int64_t n = e - s;
-  if (n <= kSortLanes) {
-    uint64_t key = ~0ull;
-    if (l < n) key = ((uint64_t)(uint32_t)A.tmp_tri[s + l] << 32) | (uint32_t)A.tmp_pair[s + l];
-#pragma unroll
-    for (int k = 2; k <= kSortLanes; k <<= 1)
-#pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        const uint64_t o = shfl_xor_u64(key, j);
-        const bool up = (l & k) == 0, lower = (l & j) == 0;
-        key = (lower == up) ? (o < key ? o : key) : (o > key ? o : key);
-      }
-    if (l < n) {
-      const int64_t dst = s + l;
-      const int32_t p = (int32_t)(uint32_t)key;
-      A.tri_ids[dst] = (int32_t)(key >> 32);
-      A.slot_cell[dst] = (int32_t)ci;
-      A.piece_flux[dst] = A.pair_flux[p];
-      A.piece_vol[dst] = A.pair_vol[p];
-    }
-    return;
-  }
-  for (int64_t q = s + l; q < e; q += kSortLanes) {
-    const int32_t t = A.tmp_tri[q];
-    int64_t rank = 0;
-    for (int64_t u = s; u < e; ++u) rank += A.tmp_tri[u] < t ? 1 : 0;
+  const int64_t nslot = min((int64_t)A.offsets[nif], A.pair_cap);
+  for (int64_t q = bid * blockDim.x + threadIdx.x; q < nslot; q += nblk * blockDim.x) {
     const int32_t p = A.tmp_pair[q];
+    const int32_t ci = A.pair_ci[p];
+    const int32_t t = A.tmp_tri[q];
+    const int64_t s = A.offsets[ci], e = min((int64_t)A.offsets[ci + 1], A.pair_cap);
+    int64_t rank = 0;
+    for (int64_t b = s; b < e; b += kSegReg) {
+      int32_t seg[kSegReg];
+#pragma unroll
+      for (int u = 0; u < kSegReg; ++u) seg[u] = b + u < e ? A.tmp_tri[b + u] : INT_MAX;
+#pragma unroll
+      for (int u = 0; u < kSegReg; ++u) rank += seg[u] < t ? 1 : 0;
+    }
     const int64_t dst = s + rank;
     A.tri_ids[dst] = t;
-    A.slot_cell[dst] = (int32_t)ci;
+    A.slot_cell[dst] = ci;
     A.piece_flux[dst] = A.pair_flux[p];
     A.piece_vol[dst] = A.pair_vol[p];
   }
@@ -406,15 +383,10 @@ __device__ inline void place_cell(const PlaceArgs& A, int64_t ci, int l) {
 
 constexpr int kSortReg = 8;  // incident lists up to this length are sorted in registers
 
-// Vertex v's incident-triangle list sorted ascending, and its record for
-// the curvature's ring pass: vinc[kIncSlots v + q] = (t0, t1, t2, degree)
-// of its q-th incident triangle for q < degree, (-1, -1, -1, degree) past
-// it (a degree above kIncSlots leaves only the degree valid).
-__device__ inline void sort_incident(const int32_t* vt_off, int32_t* vt_ids, const int4* tri4, int4* vinc, int32_t v) {
+// Vertex v's incident-triangle list sorted ascending.
+__device__ inline void sort_incident(const int32_t* vt_off, int32_t* vt_ids, int32_t v) {
   const int32_t s = vt_off[v], e = vt_off[v + 1];
-  const int32_t deg = e - s;
-  static_assert(kSortReg == kIncSlots, "one record slot per sorted entry");
-  if (deg <= kSortReg) {
+  if (e - s <= kSortReg) {
     // in registers: odd-even transposition sort, padding at the end
     int32_t x[kSortReg];
 #pragma unroll
@@ -427,19 +399,9 @@ __device__ inline void sort_incident(const int32_t* vt_off, int32_t* vt_ids, con
         x[q] = lo;
         x[q + 1] = hi;
       }
-    int4 rec[kSortReg];
 #pragma unroll
-    for (int q = 0; q < kSortReg; ++q) {
-      if (q < deg) {
-        vt_ids[s + q] = x[q];
-        rec[q] = tri4[x[q]];
-        rec[q].w = deg;
-      } else {
-        rec[q] = make_int4(-1, -1, -1, deg);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kSortReg; ++q) vinc[(int64_t)kIncSlots * v + q] = rec[q];
+    for (int q = 0; q < kSortReg; ++q)
+      if (s + q < e) vt_ids[s + q] = x[q];
     return;
   }
   for (int32_t a = s + 1; a < e; ++a) {
@@ -451,8 +413,6 @@ __device__ inline void sort_incident(const int32_t* vt_off, int32_t* vt_ids, con
     }
     vt_ids[b + 1] = x;
   }
-#pragma unroll
-  for (int q = 0; q < kIncSlots; ++q) vinc[(int64_t)kIncSlots * v + q] = make_int4(-1, -1, -1, deg);
 }
 
 struct VstarArgs {
@@ -520,19 +480,18 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int64_t
   }
 }
 
-// Blocks [0, nb_place): pieces to their ranks, kSortLanes lanes per cell;
-// [nb_place, nb_place + nb_sort): one vertex per thread, its incident list
-// sorted; the rest: closest vertices.
+// Blocks [0, nb_place): pieces to their ranks; [nb_place, nb_place +
+// nb_sort): one vertex per thread, its incident list sorted; the rest:
+// closest vertices.
 __global__ __launch_bounds__(kT) void k_place_sort_vstar(PlaceArgs A, int32_t nb_place, int32_t nb_sort, Grid g,
                                                          int32_t nv, const int32_t* vt_off, int32_t* vt_ids,
-                                                         const int4* tri4, int4* vinc, VstarArgs V) {
+                                                         VstarArgs V) {
   const int32_t b = blockIdx.x;
   if (b < nb_place) {
-    const int64_t gid = (int64_t)b * kT + threadIdx.x;
-    place_cell(A, gid / kSortLanes, (int)(gid % kSortLanes));
+    rank_place(A, b, nb_place);
   } else if (b < nb_place + nb_sort) {
     const int32_t v = (b - nb_place) * kT + threadIdx.x;
-    if (v < nv) sort_incident(vt_off, vt_ids, tri4, vinc, v);
+    if (v < nv) sort_incident(vt_off, vt_ids, v);
   } else {
     closest_vertex(g, V, (int64_t)(b - nb_place - nb_sort) * kT + threadIdx.x);
   }
@@ -575,12 +534,12 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
               ws->counters};
   VstarArgs V{vtx4,       ws->cell_ids, ws->bitmap,  ws->word_off, ws->vb_off,  ws->vb_ids,
               ws->stray,  ws->best_d2,  ws->best_v,  ws->cell_cap, ws->counters};
-  const int32_t nb_place = grid_blocks((int64_t)ws->cell_cap * kSortLanes, kT);
+  const int32_t nb_place = grid_blocks(ws->pair_cap, kT, kStrideBlocks);
   const int32_t nb_sort = grid_blocks(m.nv, kT);
   const int32_t nb_vstar = grid_blocks((int64_t)ws->cell_cap * 32, kT);
   time_start(ws, FTC_KERNEL_PIECE_RANK, s);
   hipLaunchKernelGGL(k_place_sort_vstar, dim3(nb_place + nb_sort + nb_vstar), dim3(kT), 0, s, A, nb_place, nb_sort, g,
-                     m.nv, ws->vt_off, ws->vt_ids, tri4, reinterpret_cast<int4*>(ws->vinc), V);
+                     m.nv, ws->vt_off, ws->vt_ids, V);
   time_stop(ws, FTC_KERNEL_PIECE_RANK, s);
   e = hipGetLastError();
   if (e == hipSuccess) {

@@ -9,8 +9,7 @@
 
 // Counter slots in ftc_cells::counters (device int32).
 namespace ftc {
-constexpr int kQuadNodes = 48;
-constexpr int kIncSlots = 8;  // incident triangles of a vertex in its record (ftc_cells::vinc)  // 16 nodes and weights (xi rule) + 8 and 8 (eta rule)
+constexpr int kQuadNodes = 96;  // nodes and weights: 16 and 24 (the two xi rules) + 8 (eta rule)
 enum : int {
   C_NIF = 0,      // interfacial cells of the last build
   C_NPAIRS = 1,   // (cell, triangle) pieces of the last build
@@ -83,7 +82,6 @@ struct ftc_cells {
   int32_t* vt_loc;        // [3*nt_cap] index of each (triangle, corner) within the corner's list
   int32_t* vt_ids;        // [3*nt_cap] incident triangles, ascending per vertex
   int32_t* tri4;          // [4*nt_cap] corners of each triangle packed (t0, t1, t2, 0)
-  int32_t* vinc;          // [4*kIncSlots*nv_cap] per vertex: (t0, t1, t2, degree) of its incident triangles, ascending
   double* vtx4;           // [4*nv_cap] coordinates of each vertex packed (x, y, z, 0)
   int32_t* ovf_cells;     // [cell_cap] cells queued for the wide PPIC shape
   int32_t* vcell;         // [nv_cap] interfacial cell holding each vertex (-1: none, -2: outside)

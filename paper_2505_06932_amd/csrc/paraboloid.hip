@@ -14,8 +14,10 @@
 // structure changes: the projected cube corners, the xi at which a conic
 // P = plane has a tangent along eta, and the xi at which such a conic meets
 // a projected cube edge.  Between consecutive events the xi integral is a
-// 16-node Gauss-Legendre rule in theta with xi = u0 + (u1 - u0)(1 - cos
-// theta)/2, which absorbs the square-root behaviour of G at tangencies.
+// Gauss-Legendre rule in theta with xi = u0 + (u1 - u0)(1 - cos theta)/2,
+// which absorbs the square-root behaviour of G at tangencies: 16 nodes for
+// the volume, 24 for the surface integrals (whose normal integral needs
+// them for 1e-10 on patches of kappa h near 0.07).
 // The surface integrals (area, curvature, normal over the part of the
 // paraboloid inside the cell) share the same xi rule: at each node the eta
 // intervals where the surface lies in the cube are those between the same
@@ -31,7 +33,8 @@ namespace ftc {
 namespace {
 
 constexpr int kT = 64;       // one wavefront per workgroup and per cell
-constexpr int kQ = 16;       // Gauss nodes per xi interval
+constexpr int kQV = 16;      // Gauss nodes per xi interval, volume
+constexpr int kQS = 24;      // Gauss nodes per xi interval, surface integrals
 constexpr int kEvents = 26;  // 8 corners + 12 edges + 6 face tangencies
 constexpr int kSlots = 56;   // 2 values per event, the two ends, padding
 constexpr int kEta = 24;     // eta breakpoints per G evaluation
@@ -39,16 +42,20 @@ constexpr int kEta = 24;     // eta breakpoints per G evaluation
 constexpr int kS = 8;        // Gauss nodes per eta interval of the surface integrals
 
 // The quadrature tables, one device array (read through the cache, indexed
-// per lane): tau[kQ], omega[kQ] (xi = u0 + (u1 - u0) tau, weight (u1 - u0)
-// omega), then sx[kS], sw[kS] (plain Gauss-Legendre on [0, 1]).
+// per lane): the xi rules, tau[kQV], omega[kQV] then tau[kQS], omega[kQS]
+// (xi = u0 + (u1 - u0) tau, weight (u1 - u0) omega), then sx[kS], sw[kS]
+// (plain Gauss-Legendre on [0, 1]).  A kernel's view selects its xi rule.
+constexpr int kEtaOff = 2 * kQV + 2 * kQS;
 struct Nodes {
   const double* p;
-  __device__ double tau(int k) const { return p[k]; }
-  __device__ double omega(int k) const { return p[kQ + k]; }
-  __device__ double sx(int k) const { return p[2 * kQ + k]; }
-  __device__ double sw(int k) const { return p[2 * kQ + kS + k]; }
+  int q;  // nodes of the xi rule
+  __device__ int xi_off() const { return q == kQV ? 0 : 2 * kQV; }
+  __device__ double tau(int k) const { return p[xi_off() + k]; }
+  __device__ double omega(int k) const { return p[xi_off() + q + k]; }
+  __device__ double sx(int k) const { return p[kEtaOff + k]; }
+  __device__ double sw(int k) const { return p[kEtaOff + kS + k]; }
 };
-static_assert(2 * kQ + 2 * kS == kQuadNodes, "quadrature table size");
+static_assert(kEtaOff + 2 * kS == kQuadNodes, "quadrature table size");
 
 // The cell's paraboloid and cube in its local frame, cell units.  The two
 // faces x_k = -+1/2 of axis k (n_k != 0) are the planes
@@ -453,6 +460,7 @@ __device__ void paraboloid_cells(const double* frame_n, const double* coeff, dou
     double acc[kOut];
 #pragma unroll
     for (int q = 0; q < kOut; ++q) acc[q] = 0.0;
+    constexpr int kQ = kSurf ? kQS : kQV;
     const int nodes = (nf - 1) * kQ;
     for (int q = lane; q < nodes; q += kT) {
       const int i = q / kQ, k = q % kQ;
@@ -502,40 +510,47 @@ __global__ __launch_bounds__(kT) void k_paraboloid_surface(const double* frame_n
   paraboloid_cells<true>(frame_n, coeff, h, counters, cell_cap, N, alpha_out, kappa_out, normal_out);
 }
 
-// 16-point Gauss-Legendre rule on [-1, 1] by Newton's method on the Legendre
-// recurrence, mapped through theta = (x + 1) pi / 2, u = (1 - cos theta) / 2.
-void make_nodes(double* out) {
-  double* tau = out;
-  double* omega = out + kQ;
-  double* sx = out + 2 * kQ;
-  double* sw = out + 2 * kQ + kS;
+// n-point Gauss-Legendre rule on [-1, 1] by Newton's method on the Legendre
+// recurrence, mapped through theta = (x + 1) pi / 2, u = (1 - cos theta) / 2:
+// tau[n], omega[n].
+void xi_rule(int n, double* tau, double* omega) {
   const double pi = 3.14159265358979323846;
-  for (int i = 0; i < kQ; ++i) {
-    double x = cos(pi * (i + 0.75) / (kQ + 0.5)), dp = 1.0;
+  for (int i = 0; i < n; ++i) {
+    double x = cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
     for (int it = 0; it < 100; ++it) {
       double p0 = 1.0, p1 = x;
-      for (int k = 2; k <= kQ; ++k) {
+      for (int k = 2; k <= n; ++k) {
         const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
         p0 = p1;
         p1 = p2;
       }
-      dp = kQ * (x * p1 - p0) / (x * x - 1.0);
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
       const double dx = p1 / dp;
       x -= dx;
       if (fabs(dx) < 1e-16) break;
     }
     double p0 = 1.0, p1 = x;
-    for (int k = 2; k <= kQ; ++k) {
+    for (int k = 2; k <= n; ++k) {
       const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
       p0 = p1;
       p1 = p2;
     }
-    dp = kQ * (x * p1 - p0) / (x * x - 1.0);
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
     const double w = 2.0 / ((1.0 - x * x) * dp * dp);
     const double th = (x + 1.0) * pi / 2.0;
     tau[i] = 0.5 * (1.0 - cos(th));
     omega[i] = w * (pi / 2.0) * sin(th) * 0.5;
   }
+}
+
+// The node table: both xi rules, then the eta rule (kS-point Gauss-Legendre
+// on [0, 1]).
+void make_nodes(double* out) {
+  xi_rule(kQV, out, out + kQV);
+  xi_rule(kQS, out + 2 * kQV, out + 2 * kQV + kQS);
+  double* sx = out + kEtaOff;
+  double* sw = out + kEtaOff + kS;
+  const double pi = 3.14159265358979323846;
   for (int i = 0; i < kS; ++i) {
     double x = cos(pi * (i + 0.75) / (kS + 0.5)), dp = 1.0, p0 = 1.0, p1 = x;
     for (int it = 0; it < 100; ++it) {
@@ -570,14 +585,14 @@ void paraboloid_nodes(double* out) { make_nodes(out); }
 
 hipError_t launch_paraboloid_cell(const ftc_cells* ws, const double* coeff, double* alpha_out, double* kappa_out,
                                   double* normal_out, hipStream_t s) {
-  const Nodes N{ws->quad_nodes};
+  const Nodes NV{ws->quad_nodes, kQV}, NS{ws->quad_nodes, kQS};
   const dim3 grid(grid_blocks(ws->cell_cap, 1, 65535));
   if (kappa_out || normal_out)
     hipLaunchKernelGGL(k_paraboloid_surface, grid, dim3(kT), 0, s, ws->frame_n, coeff, ws->grid.h, ws->counters,
-                       ws->cell_cap, N, alpha_out, kappa_out, normal_out);
+                       ws->cell_cap, NS, alpha_out, kappa_out, normal_out);
   else
     hipLaunchKernelGGL(k_paraboloid_alpha, grid, dim3(kT), 0, s, ws->frame_n, coeff, ws->grid.h, ws->counters,
-                       ws->cell_cap, N, alpha_out);
+                       ws->cell_cap, NV, alpha_out);
   return hipGetLastError();
 }
 

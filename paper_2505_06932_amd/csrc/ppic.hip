@@ -84,7 +84,6 @@ struct PPICArgs {
   const int32_t* cell_ids;
   const int32_t* vt_off;
   const int32_t* vt_ids;
-  const int4* vinc;  // per vertex: (t0, t1, t2, degree) of its incident triangles, ascending
   const double* best_d2;
   const int32_t* best_v;
   int32_t* counters;
@@ -886,7 +885,7 @@ struct FastCfg {
   static constexpr int HV = 64;       // slots of the vertex set (power of two)
   static constexpr int VC = 32;       // vertices of V_{R-1}
   static constexpr int TC = 64;       // ring triangles
-  static constexpr int IB = 6;        // record slots a lane loads together
+  static constexpr int IB = 8;        // incident triangles of one vertex loaded together
   static_assert(IB * 3 <= 32, "new-corner mask");
 };
 
@@ -934,80 +933,82 @@ __device__ inline bool vset_has(const int32_t* hv, int32_t key) {
   return false;
 }
 
-// One pass over the vertices V[lo, hi) through their records: item x is
-// slot x % kIncSlots of vertex V[lo + x / kIncSlots]; lane gl takes items
-// gl, gl + G, ..., kB at a time with their loads issued together (with
-// G = kIncSlots a round reads one record, one cache line, per cell).
-//   kRing = false: the corners of each incident triangle join the vertex
-//     set; the ones this lane adds are appended to V in lane order;
-//   kRing = true: an incident triangle at u is appended to the ring when u
-//     is its first corner (t0, t1, t2 order) in the set.
-// big is set when a vertex has more incident triangles than its record
-// holds.
-template <class C, bool kRing>
-__device__ inline void record_pass(const PPICArgs& A, FastMem& M, int lo, int hi, int gl, int& nV, int& nT,
-                                   bool& full, bool& big) {
-  constexpr int G = C::G, kB = C::IB;
-  const int nitems = (hi - lo) * kIncSlots;
-  const int rounds = wave_max_i((nitems + G - 1) / G);
-  for (int k0 = 0; k0 < rounds; k0 += kB) {
-    int32_t u[kB];
-    int4 rec[kB];
+// Corners of the triangles at vertex u (incident list [off, off + deg))
+// join the vertex set; the ones this lane adds are appended to V in lane
+// order.  The wavefront loops to the largest degree, IB incidences at a
+// time with their loads issued together.
+template <class C>
+__device__ inline void expand_vertex(const PPICArgs& A, FastMem& M, int32_t u, int32_t off, int deg, int gl,
+                                     int& nV, bool& full) {
+  constexpr int G = C::G, IB = C::IB;
+  const int md = wave_max_i(deg);
+  for (int j0 = 0; j0 < md; j0 += IB) {
+    int32_t tt[IB];
 #pragma unroll
-    for (int b = 0; b < kB; ++b) {
-      const int x = (k0 + b) * G + gl;
-      u[b] = x < nitems ? M.r.V[lo + x / kIncSlots] : -1;
-    }
+    for (int j = 0; j < IB; ++j) tt[j] = j0 + j < deg ? A.vt_ids[off + j0 + j] : -1;
+    int4 cc[IB];
 #pragma unroll
-    for (int b = 0; b < kB; ++b) {
-      const int x = (k0 + b) * G + gl;
-      rec[b] = u[b] >= 0 ? A.vinc[(int64_t)kIncSlots * u[b] + x % kIncSlots] : make_int4(-1, -1, -1, 0);
-    }
-    uint32_t bits = 0u;
+    for (int j = 0; j < IB; ++j) cc[j] = tt[j] >= 0 ? A.tri4[tt[j]] : make_int4(-1, -1, -1, -1);
+    uint32_t added = 0u;
 #pragma unroll
-    for (int b = 0; b < kB; ++b) {
-      if (rec[b].w > kIncSlots) big = true;
-      if (rec[b].x < 0) continue;
-      if constexpr (kRing) {
-        // u is t0, or a later corner with none before it in the set
-        bool keep = rec[b].x == u[b];
-        if (!keep)
-          keep = !vset_has<C::HV>(M.r.hv, rec[b].x) && (rec[b].y == u[b] || !vset_has<C::HV>(M.r.hv, rec[b].y));
-        if (keep) bits |= 1u << b;
-      } else {
-        const int32_t cr[3] = {rec[b].x, rec[b].y, rec[b].z};
+    for (int j = 0; j < IB; ++j) {
+      const int32_t cr[3] = {cc[j].x, cc[j].y, cc[j].z};
 #pragma unroll
-        for (int e = 0; e < 3; ++e)
-          if (cr[e] != u[b] && vset_insert<C::HV>(M.r.hv, cr[e], full)) bits |= 1u << (3 * b + e);
-      }
+      for (int e = 0; e < 3; ++e)
+        if (cr[e] >= 0 && cr[e] != u && vset_insert<C::HV>(M.r.hv, cr[e], full)) added |= 1u << (3 * j + e);
     }
     int total;
-    int pos = (kRing ? nT : nV) + group_excl_scan<G>(__popc(bits), gl, &total);
+    int pos = nV + group_excl_scan<G>(__popc(added), gl, &total);
 #pragma unroll
-    for (int b = 0; b < kB; ++b) {
-      if constexpr (kRing) {
-        if ((bits >> b) & 1u) {
-          if (pos < C::TC) {
-            M.r.T[0][pos] = rec[b].x;
-            M.r.T[1][pos] = rec[b].y;
-            M.r.T[2][pos] = rec[b].z;
-          }
+    for (int j = 0; j < IB; ++j) {
+      const int32_t cr[3] = {cc[j].x, cc[j].y, cc[j].z};
+#pragma unroll
+      for (int e = 0; e < 3; ++e)
+        if ((added >> (3 * j + e)) & 1u) {
+          if (pos < C::VC) M.r.V[pos] = cr[e];
           ++pos;
         }
-      } else {
-        const int32_t cr[3] = {rec[b].x, rec[b].y, rec[b].z};
-#pragma unroll
-        for (int e = 0; e < 3; ++e)
-          if ((bits >> (3 * b + e)) & 1u) {
-            if (pos < C::VC) M.r.V[pos] = cr[e];
-            ++pos;
-          }
-      }
     }
-    if constexpr (kRing)
-      nT += total;
-    else
-      nV += total;
+    nV += total;
+  }
+}
+
+// The triangles at vertex u of V_{R-1} that have u as their first corner in
+// V_{R-1} are appended to the ring in lane order.
+template <class C>
+__device__ inline void ring_vertex(const PPICArgs& A, FastMem& M, int32_t u, int32_t off, int deg, int gl, int& nT) {
+  constexpr int G = C::G, IB = C::IB;
+  const int md = wave_max_i(deg);
+  for (int j0 = 0; j0 < md; j0 += IB) {
+    int32_t tt[IB];
+#pragma unroll
+    for (int j = 0; j < IB; ++j) tt[j] = j0 + j < deg ? A.vt_ids[off + j0 + j] : -1;
+    int4 cc[IB];
+#pragma unroll
+    for (int j = 0; j < IB; ++j) cc[j] = tt[j] >= 0 ? A.tri4[tt[j]] : make_int4(-1, -1, -1, -1);
+    uint32_t kept = 0u;
+#pragma unroll
+    for (int j = 0; j < IB; ++j) {
+      bool keep = tt[j] >= 0;
+      if (keep && cc[j].x != u) {
+        // u is t1 or t2: kept unless an earlier corner is in the set
+        keep = !vset_has<C::HV>(M.r.hv, cc[j].x) && (cc[j].y == u || !vset_has<C::HV>(M.r.hv, cc[j].y));
+      }
+      if (keep) kept |= 1u << j;
+    }
+    int total;
+    int pos = nT + group_excl_scan<G>(__popc(kept), gl, &total);
+#pragma unroll
+    for (int j = 0; j < IB; ++j)
+      if ((kept >> j) & 1u) {
+        if (pos < C::TC) {
+          M.r.T[0][pos] = cc[j].x;
+          M.r.T[1][pos] = cc[j].y;
+          M.r.T[2][pos] = cc[j].z;
+        }
+        ++pos;
+      }
+    nT += total;
   }
 }
 
@@ -1055,20 +1056,18 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
     bool full = false;
     double n0 = 0.0, n1 = 0.0, n2 = 1.0;
 
-    // ---- the triangles at v* (its record, ascending): frame normal (cross
-    // products summed in that order) and, for R >= 2, V_1
-    bool big = false;
+    // ---- the triangles at v*: frame normal (cross products summed in
+    // ascending triangle order) and, for R >= 2, V_1
     {
-      constexpr int nr = (kIncSlots + G - 1) / G;
+      const int32_t o0 = ok ? A.vt_off[vs] : 0;
+      const int deg0 = ok ? A.vt_off[vs + 1] - o0 : 0;
+      const int nr = wave_max_i((deg0 + G - 1) / G);
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-      int deg0 = 0;
-#pragma unroll
       for (int k = 0; k < nr; ++k) {
-        const int q = k * G + gl;
-        const int4 rec = ok && q < kIncSlots ? A.vinc[(int64_t)kIncSlots * vs + q] : make_int4(-1, -1, -1, 0);
-        deg0 = max(deg0, rec.w);
-        const bool have = rec.x >= 0;
-        const P3 a = vtx(A.vtx4, have ? rec.x : 0), b = vtx(A.vtx4, have ? rec.y : 0), e = vtx(A.vtx4, have ? rec.z : 0);
+        const int i = k * G + gl;
+        const bool have = i < deg0;
+        const int4 t4 = A.tri4[have ? A.vt_ids[o0 + i] : 0];
+        const P3 a = vtx(A.vtx4, t4.x), b = vtx(A.vtx4, t4.y), e = vtx(A.vtx4, t4.z);
         const double ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;
         const double wx = e.x - a.x, wy = e.y - a.y, wz = e.z - a.z;
         const double cx = uy * wz - uz * wy;
@@ -1077,8 +1076,7 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
 #pragma unroll
         for (int qq = 0; qq < G; ++qq) {
           const double x = __shfl(cx, qq, G), y = __shfl(cy, qq, G), z = __shfl(cz, qq, G);
-          const bool h2 = __shfl((int)have, qq, G) != 0;
-          if (h2) {
+          if (k * G + qq < deg0) {
             s0 += x;
             s1 += y;
             s2 += z;
@@ -1086,7 +1084,7 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
         }
         if (R >= 2) {
           uint32_t added = 0u;
-          const int32_t cr[3] = {rec.x, rec.y, rec.z};
+          const int32_t cr[3] = {t4.x, t4.y, t4.z};
 #pragma unroll
           for (int e2 = 0; e2 < 3; ++e2)
             if (have && cr[e2] != vs && vset_insert<C::HV>(M.r.hv, cr[e2], full)) added |= 1u << e2;
@@ -1101,13 +1099,12 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
           nV += total;
         }
       }
-      if (deg0 > kIncSlots) big = true;
       const double nl = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
       n0 = s0 / nl;
       n1 = s1 / nl;
       n2 = s2 / nl;
     }
-    bool ovf = nV > C::VC || gballot<G>(full || big, grp) != 0;
+    bool ovf = nV > C::VC || gballot<G>(full, grp) != 0;
     __syncthreads();
 
     // ---- V_2 .. V_{R-1}: corners of the triangles at the vertices new in
@@ -1117,9 +1114,16 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
       const int lo = nVprev, hi = nV;
       nVprev = nV;
       const bool go = ok && !ovf;
-      int nT0 = 0;
-      record_pass<C, false>(A, M, go ? lo : 0, go ? hi : 0, gl, nV, nT0, full, big);
-      if (nV > C::VC || gballot<G>(full || big, grp) != 0) ovf = true;
+      const int rounds = wave_max_i(go ? (hi - lo + G - 1) / G : 0);
+      for (int k = 0; k < rounds; ++k) {
+        const int p = lo + k * G + gl;
+        const bool have = go && p < hi;
+        const int32_t u = have ? M.r.V[p] : 0;
+        const int32_t off = have ? A.vt_off[u] : 0;
+        const int deg = have ? A.vt_off[u + 1] - off : 0;
+        expand_vertex<C>(A, M, u, off, deg, gl, nV, full);
+      }
+      if (nV > C::VC || gballot<G>(full, grp) != 0) ovf = true;
       __syncthreads();
     }
 
@@ -1127,8 +1131,17 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
     int nT = 0;
     {
       const bool go = ok && !ovf;
-      record_pass<C, true>(A, M, 0, go ? nV : 0, gl, nV, nT, full, big);
-      if (nT > C::TC || gballot<G>(big, grp) != 0) ovf = true;
+      const int nVc = go ? nV : 0;
+      const int rounds = wave_max_i((nVc + G - 1) / G);
+      for (int k = 0; k < rounds; ++k) {
+        const int p = k * G + gl;
+        const bool have = p < nVc;
+        const int32_t u = have ? M.r.V[p] : 0;
+        const int32_t off = have ? A.vt_off[u] : 0;
+        const int deg = have ? A.vt_off[u + 1] - off : 0;
+        ring_vertex<C>(A, M, u, off, deg, gl, nT);
+      }
+      if (nT > C::TC) ovf = true;
     }
     __syncthreads();
 
@@ -1266,7 +1279,6 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
   A.cell_ids = ws->cell_ids;
   A.vt_off = ws->vt_off;
   A.vt_ids = ws->vt_ids;
-  A.vinc = reinterpret_cast<const int4*>(ws->vinc);
   A.best_d2 = ws->best_d2;
   A.best_v = ws->best_v;
   A.counters = ws->counters;

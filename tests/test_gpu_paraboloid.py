@@ -88,8 +88,8 @@ def test_paraboloid_surface_parity(oracle):
     """Curvature and normal integrated over each cell's paraboloid patch:
     sampled cells of the 32^3 sphere (and every one with a tiny normal
     component, up to 16) within 1e-10 relative (the curvature bar), normals
-    within 1e-10; the volume fractions of the same call match the
-    volume-only call bit for bit."""
+    within 1e-10; the volume fractions of the same call (its finer rule in
+    the second direction) match the volume-only call within the alpha bar."""
     grid, mesh, step = _run("sphere_32")
     cells, _, _ = oracle.cell_lists(grid, mesh)
     r = oracle.ppic(grid, mesh, cells)
@@ -97,7 +97,7 @@ def test_paraboloid_surface_parity(oracle):
     ok = np.nonzero(r["status"] == 0)[0]
     a1 = _cell_gpu(step, grid, r["coeff"])
     a2, kg, ng = _cell_gpu(step, grid, r["coeff"], surface=True)
-    assert np.array_equal(a1, a2)
+    assert np.abs(a1 - a2).max() <= ALPHA_TOL
     pick = np.random.default_rng(12).choice(ok, 24, replace=False)
     flat = ok[np.abs(fn[ok]).min(1) < 1e-6]
     pick = np.union1d(pick, flat[:16])
@@ -167,3 +167,42 @@ def test_failed_fits_give_nan(oracle):
     keep = np.setdiff1d(np.arange(len(co)), bad)
     assert np.array_equal(a1[keep], a0[keep]) and np.array_equal(k1[keep], k0[keep], equal_nan=True)
     assert np.array_equal(n1[keep], n0[keep], equal_nan=True)
+
+
+@pytest.mark.timeout(900)
+def test_paraboloid_parity_many_cells_perturbed_spheres(oracle):
+    """Perturbed spheres on 128^3 (non-convex patches, larger kappa h): the
+    volume fraction, the curvature and the normal integrated over the patch,
+    on 1,000 seeded cells plus every cell whose frame normal has a tiny
+    component, against the oracle (run in a pool of CPU processes): alpha
+    within 1e-12, curvature within 1e-10 relative, normal within 1e-10; cells
+    whose patch misses the cell are NaN on both sides."""
+    grid, mesh, step = _run("sh_spheres_128")
+    cells, _, _ = oracle.cell_lists(grid, mesh)
+    g = step.results()
+    assert np.array_equal(g["cell_ids"][:g["n_if"]], cells)
+    r = oracle.ppic(grid, mesh, cells)
+    _, _, fn = oracle.frame_normal(grid, mesh, cells)
+    ok = np.nonzero(r["status"] == 0)[0]
+    pick = np.random.default_rng(13).choice(ok, min(1000, len(ok)), replace=False)
+    flat = ok[np.abs(fn[ok]).min(1) < 1e-6]
+    pick = np.union1d(pick, flat)
+    ag, kg, ng = _cell_gpu(step, grid, r["coeff"], surface=True)
+    ao = PB.map_cells("alpha", fn[pick], r["coeff"][pick], grid.h)
+    ko, no = PB.map_cells("surface", fn[pick], r["coeff"][pick], grid.h)
+    aerr = np.abs(ag[pick] - ao).max()
+    miss = np.isnan(ko)
+    assert np.array_equal(np.isnan(kg[pick]), miss)
+    kerr = (np.abs(kg[pick] - ko) / np.abs(ko))[~miss]
+    nerr = np.abs(ng[pick] - no)[~miss].max()
+    _say(f"[paraboloid] sh_spheres_128: {len(cells)} cells, {len(pick)} checked ({len(flat)} with a tiny normal "
+         f"component, {int(miss.sum())} patches outside their cell): alpha {aerr:.2e}, kappa rel {kerr.max():.2e}, "
+         f"normal {nerr:.2e}")
+    ne = np.abs(ng[pick] - no).max(1)
+    for q in np.argsort(-np.nan_to_num(ne))[:4]:
+        c = pick[q]
+        _say(f"[paraboloid]   cell {c} (id {cells[c]}): normal err {ne[q]:.2e} kappa rel "
+             f"{abs(kg[c] - ko[q]) / abs(ko[q]):.2e} frame n {fn[c].tolist()} coeff {r['coeff'][c].tolist()} "
+             f"gpu n {ng[c].tolist()} oracle n {no[q].tolist()}")
+    assert aerr <= ALPHA_TOL
+    assert kerr.max() <= 1e-10 and nerr <= 1e-10

@@ -31,10 +31,141 @@ from paper_2505_06932_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-FWD_MAX, FWD_MEDIAN = 5e-3, 1e-5
 GRAD_TOL, LOSS_TOL = 2e-3, 1e-4
 KAPPA_TOL = 1e-10
 DECISION_MARGIN = 1e-3
+
+
+# ---- forward validity: every difference from the oracle is explained by a
+# bfloat16 rounding that the device may take the other way
+#
+# The device forms each hidden pre-activation as a single-precision sum of
+# products that are exact in single precision (bfloat16 factors), plus the
+# bias, so |z_dev - z| <= (terms + 1) 2^-24 sum |terms|; its tanh is
+# 1 - 2 / (1 + e^(2z)) with the hardware exponential and reciprocal, within
+# TANH_ERR of tanh(z) absolutely.  An activation whose distance to the
+# nearest bfloat16 rounding boundary exceeds both is rounded identically on
+# both sides; the others are ambiguous.  A row's device output must equal,
+# within the single-precision rounding bound of the last layer, the output
+# of the oracle's arithmetic for some choice of rounding of its ambiguous
+# units (both layers, the second re-examined for every choice in the first).
+TANH_ERR = 5e-7
+U32 = 2.0 ** -24
+MAX_AMBIGUOUS = 10  # units enumerated per layer and row
+
+
+def _boundary(v):
+    """Distance of v to the nearest bfloat16 rounding boundary (the midpoint
+    between the two bfloat16 values around the single-precision value of v)
+    and those two values (signed, nearer zero first)."""
+    v = np.asarray(v, dtype=np.float64)
+    u = np.abs(v).astype(np.float32).view(np.uint32) & np.uint32(0xFFFF0000)
+    lo = u.view(np.float32).astype(np.float64)
+    hi = (u + np.uint32(0x10000)).view(np.float32).astype(np.float64)
+    return np.abs(np.abs(v) - 0.5 * (lo + hi)), np.sign(v) * lo, np.sign(v) * hi
+
+
+def _layer(W, b, h):
+    """Pre-activation, its rounding bound on the device, activation, the
+    ambiguous units and their two candidate roundings."""
+    z = h @ W.T + b
+    e = (W.shape[1] + 1) * U32 * (np.abs(h) @ np.abs(W.T) + np.abs(b))
+    a = np.tanh(z)
+    d, lo, hi = _boundary(a)
+    return a, d <= TANH_ERR + (1.0 - a * a) * e, lo, hi
+
+
+def _explained(P, x, y_dev, tol):
+    """True if y_dev matches the output for some rounding of the ambiguous units of row x."""
+    import itertools
+    W1, b1, W2, b2, w3, b3 = P
+    a1, f1, lo1, hi1 = _layer(W1, b1, x)
+    amb1 = np.nonzero(f1)[0]
+    if len(amb1) > MAX_AMBIGUOUS:
+        return False
+    for c1 in itertools.product((0, 1), repeat=len(amb1)):
+        h1 = S.bf16(a1)
+        h1[amb1] = np.where(np.array(c1, dtype=bool), hi1[amb1], lo1[amb1])
+        a2, f2, lo2, hi2 = _layer(W2, b2, h1)
+        amb2 = np.nonzero(f2)[0]
+        if len(amb2) > MAX_AMBIGUOUS:
+            continue
+        for c2 in itertools.product((0, 1), repeat=len(amb2)):
+            h2 = S.bf16(a2)
+            h2[amb2] = np.where(np.array(c2, dtype=bool), hi2[amb2], lo2[amb2])
+            if abs(y_dev - (h2 @ w3 + b3)) <= tol:
+                return True
+    return False
+
+
+def _forward_flags(th, F):
+    """Oracle output y, the rows with an ambiguous unit, the last layer's
+    rounding bound per row, and the (rounded) parameters and inputs."""
+    p = S.unpack(th.astype(np.float32))
+    x = F.astype(np.float32).astype(np.float64)
+    xh = S.bf16(x)
+    xl = S.bf16(x - xh)
+    W1, W2, w3 = S.bf16(p["W1"]), S.bf16(p["W2"]), S.bf16(p["w3"])
+    # the first layer sees the inputs as (hi, lo) pairs: one product list
+    X2 = np.concatenate([xh, xl], 1)
+    W12 = np.concatenate([W1, W1], 1)
+    a1, f1, _, _ = _layer(W12, p["b1"], X2)
+    h1 = S.bf16(a1)
+    a2, f2, _, s2 = _layer(W2, p["b2"], h1)
+    h2 = S.bf16(a2)
+    y = h2 @ w3 + p["b3"]
+    # the last layer's single-precision sum, with any h2 within one step
+    base = 65 * U32 * ((np.abs(h2) + np.abs(s2)) @ np.abs(w3) + abs(p["b3"]))
+    return y, f1.any(1) | f2.any(1), base, (W12, p["b1"], W2, p["b2"], w3, p["b3"]), X2
+
+
+def _check_forward(y_dev, th, F, what):
+    """The device's outputs y_dev against the oracle's on the rows F: within
+    the last layer's rounding bound where no unit is ambiguous, else equal
+    within it to the output of some rounding of the ambiguous units.
+    Returns the per-row bound."""
+    y, flagged, base, P, X2 = _forward_flags(np.asarray(th, dtype=np.float32), np.asarray(F, dtype=np.float64))
+    y_dev = np.asarray(y_dev, dtype=np.float64)
+    d = np.abs(y_dev - y)
+    close = d <= base
+    _say(f"[surrogate] {what}: {len(y)} rows, {int(flagged.sum())} with an ambiguous unit, "
+         f"{int((~close).sum())} of them off the oracle's rounding (max |dy| {d.max():.2e}; "
+         f"elsewhere {d[close].max():.2e} within {base.min():.1e}..{base.max():.1e})")
+    assert np.all(close | flagged)
+    for r in np.nonzero(~close)[0]:
+        assert _explained(P, X2[r], y_dev[r], base[r]), (what, int(r), float(d[r]))
+    return base
+
+
+def _candidate_range(P, x):
+    """Smallest and largest output of row x over the roundings of its
+    ambiguous units (as in _explained)."""
+    import itertools
+    W1, b1, W2, b2, w3, b3 = P
+    a1, f1, lo1, hi1 = _layer(W1, b1, x)
+    amb1 = np.nonzero(f1)[0][:MAX_AMBIGUOUS]
+    ys = []
+    for c1 in itertools.product((0, 1), repeat=len(amb1)):
+        h1 = S.bf16(a1)
+        h1[amb1] = np.where(np.array(c1, dtype=bool), hi1[amb1], lo1[amb1])
+        a2, f2, lo2, hi2 = _layer(W2, b2, h1)
+        amb2 = np.nonzero(f2)[0][:MAX_AMBIGUOUS]
+        for c2 in itertools.product((0, 1), repeat=len(amb2)):
+            h2 = S.bf16(a2)
+            h2[amb2] = np.where(np.array(c2, dtype=bool), hi2[amb2], lo2[amb2])
+            ys.append(h2 @ w3 + b3)
+    return min(ys), max(ys)
+
+
+def _prediction_ranges(th, F):
+    """Per row of F: the range of each of the error set's four predictions
+    [4, n, 2], widened by the last layer's rounding bound."""
+    out = []
+    for sy in S.ERROR_SET:
+        _, _, base, P, X2 = _forward_flags(np.asarray(th, dtype=np.float32), S.transform(F, sy))
+        r = np.array([_candidate_range(P, X2[i]) for i in range(len(X2))])
+        out.append(np.stack([r[:, 0] - base, r[:, 1] + base], 1))
+    return np.stack(out)
 
 
 def _say(*a):
@@ -116,19 +247,16 @@ def test_mlp_forward_parity():
         y = torch.zeros(n, dtype=torch.float32, device="cuda")
         ftc.mlp_forward(torch.from_numpy(th).cuda(), torch.from_numpy(X).cuda(), y,
                         idx=torch.from_numpy(idx).cuda(), sym=torch.from_numpy(sym).cuda())
-        yo = np.empty(n)
+        Fm = np.empty((n, 30))
         for s in range(48):
             m = sym == s
             if m.any():
-                yo[m] = S.forward(th.astype(np.float64), S.transform(X[idx[m], :30].astype(np.float64), s))
-        d = np.abs(y.cpu().numpy() - yo)
-        _say(f"[surrogate] forward max {d.max():.3e} median {np.median(d):.3e}")
-        assert d.max() <= FWD_MAX and np.median(d) <= FWD_MEDIAN
+                Fm[m] = S.transform(X[idx[m], :30].astype(np.float64), s)
+        _check_forward(y.cpu().numpy(), th, Fm, f"forward seed={seed}")
     # plain rows, no index or symmetry
     y = torch.zeros(rows, dtype=torch.float32, device="cuda")
     ftc.mlp_forward(torch.from_numpy(th).cuda(), torch.from_numpy(X).cuda(), y)
-    d = np.abs(y.cpu().numpy() - S.forward(th.astype(np.float64), X[:, :30].astype(np.float64)))
-    assert d.max() <= FWD_MAX and np.median(d) <= FWD_MEDIAN
+    _check_forward(y.cpu().numpy(), th, X[:, :30].astype(np.float64), "forward plain rows")
 
 
 @pytest.mark.parametrize("n", [300, 20000])
@@ -258,15 +386,23 @@ def test_learned_curvature_parity(oracle, case):
         clear = np.abs(spread_o - bound) > DECISION_MARGIN
         assert np.array_equal(fb[clear], fb_o[clear])
         assert clear.sum() > 0.5 * n and 0 < fb.sum() < n
-        assert np.abs(spread[:n] - spread_o).max() <= 2 * FWD_MAX
+        # the device's four predictions lie in the ranges of the roundings it
+        # may take: spread and mean within the ranges these allow
+        rg = _prediction_ranges(th, Fo)
+        lo, hi = rg[..., 0], rg[..., 1]
+        sp_lo, sp_hi = np.maximum(lo.max(0) - hi.min(0), 0.0), hi.max(0) - lo.min(0)
+        eps32 = 2.0 ** -22 * np.abs(spread_o) + 1e-7
+        assert np.all((spread[:n] >= sp_lo - eps32) & (spread[:n] <= sp_hi + eps32))
         # fallback cells: the PPIC curvature and status
         ok = fb & (ppic["status"] == 0)
         assert np.all(np.abs(kap[:n][ok] - ppic["kappa"][ok]) <= KAPPA_TOL * np.abs(ppic["kappa"][ok]))
         assert np.array_equal(st[:n][fb], ppic["status"][fb])
         # trusted cells: the mean prediction and the frame normal
         s = ~fb
-        dk = np.abs(kap[:n][s] * grid.h - mean_o[s])
-        assert dk.max() <= FWD_MAX and np.median(dk) <= FWD_MEDIAN
+        km = kap[:n][s] * grid.h
+        m_lo, m_hi = lo.mean(0)[s], hi.mean(0)[s]
+        eps = 2.0 ** -22 * np.abs(mean_o[s])
+        assert np.all((km >= m_lo - eps) & (km <= m_hi + eps))
         assert np.array_equal(nrm[:n][s], Fo[s, 27:30])
     # the plain PPIC call afterwards is unaffected
     cap = c.cell_capacity
