@@ -463,25 +463,30 @@ ftc_status ftc_smooth_rough_edges(ftc_cells* cells, const ftc_grid* grid, const 
 
 /* ------------------------------------------------------------------------
    Launch shapes of a workspace, for fronts of different sizes and
-   triangle-per-cell counts (an autotuner on top chooses them by timing the
-   whole step: paper_2505_06932_amd/tune.py).  Every choice gives the same
-   cell lists, decisions and PPIC results; the column chunking changes the
-   order in which fluxes are summed, so volume fractions may differ in the
-   last bits.
-     ring_lanes    : lanes per interfacial cell in the fast PPIC shape, 4, 8
-                     or 16;
+   triangle-per-cell counts (an autotuner on top chooses them by timing:
+   paper_2505_06932_amd/tune.py).  Every choice gives the same cell lists,
+   decisions and PPIC results; the column chunking changes the order in
+   which fluxes are summed, so volume fractions may differ in the last bits.
+     ring_lanes    : lanes per interfacial cell in the fast PPIC shape, 4, 8,
+                     16, 32 or 64 (64 / ring_lanes cells per wavefront);
      column_chunks : z-chunks (wavefronts) per 64-column block of the
                      volume-fraction column pass, 4, 8 or 16;
-     ring_blocks   : workgroups of the fast PPIC shape, 0 for one per group
-                     of cells, else a persistent grid of that many (<= 65536).
+     ring_blocks   : workgroups of the fast PPIC shape, 0 for one per group of
+                     cells (or, with a work queue, as many as the chip holds
+                     at once), else a persistent grid of that many (<= 65536);
+     queue_chunk   : 0 to split the cell groups statically over the
+                     workgroups, else the number of groups (1 to 64) a
+                     workgroup takes at a time from a work queue (one range
+                     per XCD, taken in order, the others' ranges afterwards).
    Defaults: 8 lanes, 16 chunks for nz <= 256 and 4 above, one workgroup
-   per group (the fastest shapes measured on fronts of 28k to 223k
+   per group, no queue (the fastest shapes measured on fronts of 28k to 179k
    interfacial cells on 128^3 to 512^3).
    ------------------------------------------------------------------------ */
 typedef struct {
   int32_t ring_lanes;
   int32_t column_chunks;
   int32_t ring_blocks;
+  int32_t queue_chunk;
 } ftc_tuning;
 
 ftc_status ftc_get_tuning(const ftc_cells* cells, ftc_tuning* out /*[host]*/);

@@ -93,7 +93,8 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   ftc_cells_owner* o = new (std::nothrow) ftc_cells_owner();
   if (!o) return FTC_ENOMEM;
   ftc_cells& w = o->ws;
-  if (hipGetDevice(&w.device) != hipSuccess) {
+  if (hipGetDevice(&w.device) != hipSuccess ||
+      hipDeviceGetAttribute(&w.cu_count, hipDeviceAttributeMultiprocessorCount, w.device) != hipSuccess) {
     delete o;
     return FTC_EHIP;
   }
@@ -435,18 +436,21 @@ ftc_status ftc_get_tuning(const ftc_cells* cells, ftc_tuning* out) {
   out->ring_lanes = cells->tune.ring_lanes;
   out->column_chunks = cells->tune.column_chunks;
   out->ring_blocks = cells->tune.ring_blocks;
+  out->queue_chunk = cells->tune.queue_chunk;
   return FTC_OK;
 }
 
 ftc_status ftc_set_tuning(ftc_cells* cells, const ftc_tuning* in) {
   if (!cells || !in) return FTC_EINVAL;
-  if ((in->ring_lanes != 4 && in->ring_lanes != 8 && in->ring_lanes != 16) ||
+  const int32_t L = in->ring_lanes;
+  if ((L != 4 && L != 8 && L != 16 && L != 32 && L != 64) ||
       (in->column_chunks != 4 && in->column_chunks != 8 && in->column_chunks != 16) || in->ring_blocks < 0 ||
-      in->ring_blocks > 65536)
+      in->ring_blocks > 65536 || in->queue_chunk < 0 || in->queue_chunk > 64)
     return FTC_EINVAL;
   cells->tune.ring_lanes = in->ring_lanes;
   cells->tune.column_chunks = in->column_chunks;
   cells->tune.ring_blocks = in->ring_blocks;
+  cells->tune.queue_chunk = in->queue_chunk;
   return FTC_OK;
 }
 

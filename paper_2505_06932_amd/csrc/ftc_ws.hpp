@@ -23,21 +23,27 @@ enum : int {
   C_SPARE = 9,     // unused
   C_RFLAG = 10,    // edges listed for roughness smoothing
   C_RMOVED = 11,   // edges moved by it
-  C_COUNT = 12
+  C_QUEUE0 = 32,   // [8 x kQStride] next chunk of each XCD's range in the fast PPIC shape's work
+                   // queue, one 128-byte line each
+  C_COUNT = 32 + 8 * 32
 };
+constexpr int kQStride = 32;
 }  // namespace ftc
 
 namespace ftc {
 // Launch shapes chosen per workspace (ftc_set_tuning; defaults below).
 struct Tuning {
-  int32_t ring_lanes = 8;     // lanes per cell in the fast PPIC shape: 4, 8 or 16
+  int32_t ring_lanes = 8;     // lanes per cell in the fast PPIC shape: 4, 8, 16, 32 or 64
   int32_t column_chunks = 16;  // z-chunks (wavefronts) per column block: 4, 8 or 16 (set from nz at creation)
-  int32_t ring_blocks = 0;    // workgroups of the fast PPIC shape: 0 = one per cell group, else a persistent grid
+  int32_t ring_blocks = 0;    // workgroups of the fast PPIC shape: 0 = one per cell group (or, with a work
+                              // queue, the resident wavefronts), else a persistent grid of that many
+  int32_t queue_chunk = 0;    // cell groups per draw from the fast PPIC shape's work queue (0: static split)
 };
 }  // namespace ftc
 
 struct ftc_cells {
   int device;
+  int cu_count;  // compute units of the device
   ftc::Tuning tune;
   ftc::Grid grid;
   int64_t ncell, nwords, ncol;

@@ -92,6 +92,7 @@ struct PPICArgs {
   int32_t cell_cap;
   double *kappa, *nx, *ny, *nz, *coeff;
   int32_t *status, *diag;
+  int32_t queue_chunk;  // fast shape: 0 a static split of the cell groups, else the work queue's chunk
   const int32_t* sel;  // null: every interfacial cell; else the cells sel[0, counters[C_NSEL])
   int32_t* n_sel_out;  // receives the selection's count (may be null)
 };
@@ -448,17 +449,47 @@ __device__ inline int32_t closest_vertex(const PPICArgs& A, int32_t c, bool act,
   return vs;
 }
 
-// Cells are dealt out in groups of NG (one group per wavefront and turn);
-// each XCD takes a contiguous range of groups, which keeps each L2 on one
-// part of the front.  Calls body(group) for the groups of workgroup bid.
+// Cell groups of the fast shape for workgroup `bid` of `nblk`.  The groups
+// are split into kXCD contiguous ranges, one per XCD (workgroups are dealt
+// to the XCDs in turn, so each L2 holds one part of the front).
+//   chunk = 0: a static split, workgroup bid taking groups bid / kXCD,
+//     bid / kXCD + nblk / kXCD, ... of its XCD's range;
+//   chunk > 0: a work queue, the workgroups of an XCD taking `chunk` groups
+//     at a time from their range through its counter qctr[x * kQStride],
+//     then from the other XCDs' ranges in turn once theirs is empty (a
+//     plain read first skips the ranges already taken).  The counters start
+//     at zero; the wide shape's kernel, next in the same stream, clears them.
 template <class Body>
-__device__ inline void for_xcd_groups(int32_t ngroups, int32_t bid, int32_t nblk, Body body) {
+__device__ inline void for_cell_groups(int32_t ngroups, int32_t bid, int32_t nblk, int32_t chunk, int32_t* qctr,
+                                       Body body) {
   const int32_t per = (ngroups + kXCD - 1) / kXCD;
-  const int32_t xcd = bid % kXCD, nj = nblk / kXCD;
-  for (int32_t q = bid / kXCD; q < per; q += nj) {
-    const int32_t gi = xcd * per + q;
-    if (gi >= ngroups) break;
-    body(gi);
+  if (chunk <= 0) {
+    const int32_t xcd = bid % kXCD, nj = nblk / kXCD;
+    for (int32_t q = bid / kXCD; q < per; q += nj) {
+      const int32_t gi = xcd * per + q;
+      if (gi >= ngroups) break;
+      body(gi);
+    }
+    return;
+  }
+  const int32_t x0 = bid % kXCD;
+  for (int32_t d = 0; d < kXCD; ++d) {
+    const int32_t x = (x0 + d) % kXCD;
+    const int32_t lo = x * per, hi = min(lo + per, ngroups);
+    int32_t* ctr = qctr + x * kQStride;
+    if (d > 0) {
+      int32_t seen = 0;
+      if (threadIdx.x == 0) seen = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lo + __shfl(seen, 0, 64) >= hi) continue;
+    }
+    for (;;) {
+      int32_t q0 = 0;
+      if (threadIdx.x == 0) q0 = atomicAdd(ctr, chunk);
+      q0 = __shfl(q0, 0, 64);
+      if (lo + q0 >= hi) break;
+      const int32_t g1 = min(lo + q0 + chunk, hi);
+      for (int32_t gi = lo + q0; gi < g1; ++gi) body(gi);
+    }
   }
 }
 
@@ -850,8 +881,11 @@ __device__ inline void ppic_wide_cells(const PPICArgs& A, int32_t bid, int32_t n
 }
 
 // The cells the fast shape queued.  The queue's count is read by every
-// workgroup before the last one to finish clears it for the next call.
+// workgroup before the last one to finish clears it for the next call; the
+// fast shape's work-queue counters are cleared on the way.
 __global__ __launch_bounds__(64) void k_ppic_wide(PPICArgs A) {
+  // the fast shape's work-queue counters, for the next call
+  if (blockIdx.x == 0 && threadIdx.x < kXCD) A.counters[C_QUEUE0 + threadIdx.x * kQStride] = 0;
   ppic_wide_cells<Wide, false>(A, blockIdx.x, gridDim.x);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1033,7 +1067,7 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
   const int R = A.prm.rings;
   const int32_t ngroups = (nitems + NG - 1) / NG;
 
-  for_xcd_groups(ngroups, bid, nblk, [&](int32_t gi) {
+  for_cell_groups(ngroups, bid, nblk, A.queue_chunk, A.counters + C_QUEUE0, [&](int32_t gi) {
     const int32_t c = gi * NG + grp;
     const bool act = c < nitems;
     int32_t vs;
@@ -1073,8 +1107,9 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
         const double cx = uy * wz - uz * wy;
         const double cy = uz * wx - ux * wz;
         const double cz = ux * wy - uy * wx;
-#pragma unroll
-        for (int qq = 0; qq < G; ++qq) {
+        const int qn = wave_max_i(min(max(deg0 - k * G, 0), G));  // lanes holding a triangle, at most
+#pragma unroll 4
+        for (int qq = 0; qq < qn; ++qq) {
           const double x = __shfl(cx, qq, G), y = __shfl(cy, qq, G), z = __shfl(cz, qq, G);
           if (k * G + qq < deg0) {
             s0 += x;
@@ -1255,6 +1290,8 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
 __global__ __launch_bounds__(64) void k_ppic_fast4(PPICArgs A) { ppic_fast<4, false>(A, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_ppic_fast8(PPICArgs A) { ppic_fast<8, false>(A, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(64) void k_ppic_fast16(PPICArgs A) { ppic_fast<16, false>(A, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(64) void k_ppic_fast32(PPICArgs A) { ppic_fast<32, false>(A, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(64) void k_ppic_fast64(PPICArgs A) { ppic_fast<64, false>(A, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(64) void k_ppic_fast8_mixed(PPICArgs A) { ppic_fast<8, true>(A, blockIdx.x, gridDim.x); }
 
 inline int32_t round_up(int64_t n, int64_t m) { return (int32_t)((n + m - 1) / m * m); }
@@ -1292,6 +1329,7 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
   A.coeff = coeff;
   A.status = cell_status;
   A.diag = diag;
+  A.queue_chunk = ws->tune.queue_chunk;
   A.sel = sel;
   A.n_sel_out = n_sel_out;
   time_start(ws, FTC_KERNEL_PPIC, s);
@@ -1302,7 +1340,10 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
   } else {
     const int lanes = p.mixed ? 8 : ws->tune.ring_lanes;
     const int64_t groups = ((int64_t)ws->cell_cap * lanes + 63) / 64;
-    const int64_t grid_cap = ws->tune.ring_blocks > 0 ? ws->tune.ring_blocks : 65536;
+    // a work queue without a grid of its own: the wavefronts the chip holds
+    // at the fast shape's occupancy (three per SIMD, four SIMDs per CU)
+    const int64_t grid_cap = ws->tune.ring_blocks > 0 ? ws->tune.ring_blocks
+                             : (ws->tune.queue_chunk > 0 ? 12 * (int64_t)ws->cu_count : 65536);
     const dim3 grid(round_up(std::min<int64_t>(std::max<int64_t>(groups, 1), grid_cap), kXCD));
     if (p.mixed)
       hipLaunchKernelGGL(k_ppic_fast8_mixed, grid, dim3(64), 0, s, A);
@@ -1310,6 +1351,10 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
       hipLaunchKernelGGL(k_ppic_fast4, grid, dim3(64), 0, s, A);
     else if (lanes == 16)
       hipLaunchKernelGGL(k_ppic_fast16, grid, dim3(64), 0, s, A);
+    else if (lanes == 32)
+      hipLaunchKernelGGL(k_ppic_fast32, grid, dim3(64), 0, s, A);
+    else if (lanes == 64)
+      hipLaunchKernelGGL(k_ppic_fast64, grid, dim3(64), 0, s, A);
     else
       hipLaunchKernelGGL(k_ppic_fast8, grid, dim3(64), 0, s, A);
     hipLaunchKernelGGL(k_ppic_wide, dim3(kWideBlocks), dim3(64), 0, s, A);

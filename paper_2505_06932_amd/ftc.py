@@ -73,7 +73,8 @@ class PPICParams:
 
 
 class _CTuning(C.Structure):
-    _fields_ = [("ring_lanes", C.c_int32), ("column_chunks", C.c_int32), ("ring_blocks", C.c_int32)]
+    _fields_ = [("ring_lanes", C.c_int32), ("column_chunks", C.c_int32), ("ring_blocks", C.c_int32),
+                ("queue_chunk", C.c_int32)]
 
 
 @dataclass(frozen=True)
@@ -82,6 +83,7 @@ class Tuning:
     ring_lanes: int = 8
     column_chunks: int = 16
     ring_blocks: int = 0
+    queue_chunk: int = 0
 
 
 class FTCError(RuntimeError):
@@ -543,9 +545,10 @@ def smooth_rough_edges(cells: Cells, grid: _inputs.Grid, mesh: DeviceMesh, gl_ma
 def get_tuning(cells: Cells) -> Tuning:
     t = _CTuning()
     _check(lib().ftc_get_tuning(cells.handle, C.byref(t)), "ftc_get_tuning")
-    return Tuning(t.ring_lanes, t.column_chunks, t.ring_blocks)
+    return Tuning(t.ring_lanes, t.column_chunks, t.ring_blocks, t.queue_chunk)
 
 
 def set_tuning(cells: Cells, tuning: Tuning) -> None:
     _check(lib().ftc_set_tuning(cells.handle, C.byref(_CTuning(tuning.ring_lanes, tuning.column_chunks,
-                                                               tuning.ring_blocks))), "ftc_set_tuning")
+                                                               tuning.ring_blocks, tuning.queue_chunk))),
+           "ftc_set_tuning")

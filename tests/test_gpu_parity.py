@@ -487,7 +487,10 @@ def test_graph_replay_matches_eager():
         assert got["error"] == 0
 
 
-@pytest.mark.parametrize("shape", [(16, 4, 0), (8, 16, 2048), (16, 8, 8192), (4, 16, 0)])
+@pytest.mark.parametrize(
+    "shape",
+    [(16, 4, 0), (8, 16, 2048), (16, 8, 8192), (4, 16, 0), (8, 16, 0, 2), (32, 8, 0, 1), (64, 16, 2048, 4)],
+)
 @pytest.mark.parametrize("name", ["sphere_32", "sphere_128"])
 def test_launch_shapes_full_parity(oracle, name, shape):
     """Every launch shape gives the oracle's lists, decisions and curvatures."""
@@ -511,7 +514,9 @@ def test_autotuner_chooses_a_timed_shape():
     best, table = tune.autotune(step, reps=5, warmup=2, log=_say)
     tried = {t for t, _ in table}
     assert ftc.Tuning(8, 16, 0) in tried  # the workspace's default shape on 32^3
-    assert len(tried) == 1 + 2 + 2 + 2  # the default, then the other values of each knob
+    # the default, the lanes x queue-chunk product, then the other values of
+    # the grid and of the column chunks
+    assert len(tried) == 1 + (5 * 5 - 1) + 2 + 2
     assert best in tried and ftc.get_tuning(step.cells) == best
     assert dict(table)[best] == min(ms for _, ms in table)
     with pytest.raises(ftc.FTCError):
