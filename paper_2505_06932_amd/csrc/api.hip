@@ -131,13 +131,11 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(pair_tri, P + w.queue_cap);
   FTC_ALLOC(pair_flux, P + w.queue_cap);
   FTC_ALLOC(pair_vol, P + w.queue_cap);
-  FTC_ALLOC(tmp_tri, P);
-  FTC_ALLOC(tmp_pair, P);
+  FTC_ALLOC(tmp_rec, 4 * P);
   FTC_ALLOC(cell_ids, Cc);
   FTC_ALLOC(offsets, Cc + 1);
   FTC_ALLOC(pair_local, P + w.queue_cap);
   FTC_ALLOC(tri_ids, P);
-  FTC_ALLOC(slot_cell, P);
   FTC_ALLOC(piece_flux, P);
   FTC_ALLOC(piece_vol, P);
   FTC_ALLOC(cell_flux, Cc);

@@ -4,18 +4,27 @@
 // 1. per triangle (k_tri_classify): decide every cell of its bounding box
 //    from the corners alone where the clipping would cut nothing (no piece,
 //    or the whole triangle); queue the others; then per queued candidate
-//    (k_clip_queue): full clipping.  Every piece of positive area sets its
-//    cell's bit in a grid-sized occupancy bitmap and is appended, with its
-//    two z-column integrals, to a pair list (one atomic allocation per
-//    workgroup; queued candidates keep their queue slot);
+//    (k_clip_mark): full clipping.  Every piece of positive area is appended,
+//    with its two z-column integrals, to a pair list (one atomic allocation
+//    per workgroup; queued candidates keep their queue slot) and sets its
+//    cell's bit in a grid-sized occupancy bitmap;
 // 2. popcount prefix sums of the bitmap, listing the interfacial cells in
 //    ascending linear id on the way -> the compact index (rank) of every
 //    cell;
 // 3. per pair: compact cell index and a count per cell; prefix sums of the
 //    counts -> CSR offsets;
-// 4. scatter the pairs into their cell's segment (any order), then place
-//    each at its rank by triangle id within the segment, so that the CSR
-//    lists come out in ascending triangle id whatever the scheduling was.
+// 4. scatter the pairs into their cell's segment (any order) as 32-byte
+//    records carrying everything the next step needs, then place each at
+//    its rank by triangle id within the segment, so that the CSR lists come
+//    out in ascending triangle id whatever the scheduling was.
+// Lanes of one atomic instruction that hit the same address are served one
+// after another, and neighbouring pieces, corners and vertices share cells,
+// words and vertices: every count and every bitmap bit is taken with one
+// atomic instruction per wavefront in which each distinct counter or word
+// appears once (the lanes grouped by key beforehand).  Every walk over
+// triangles, pairs, vertices or cells gives each XCD a contiguous share, so
+// that the mesh records, bitmap words and list segments that neighbours
+// share meet in one L2.
 // The same launches also prepare what the curvature fit needs from the
 // front, as extra work beside the pieces: each vertex's incident triangles
 // (counted while clearing, grouped in step 4, sorted ascending afterwards), the
@@ -30,6 +39,7 @@
 #include <limits.h>
 
 #include "ftc_ws.hpp"
+#include "xcd.hpp"
 
 namespace ftc {
 namespace {
@@ -52,16 +62,18 @@ __device__ inline int32_t distinct_corner(const Mesh& m, int32_t t, int r) {
 }
 
 // Clears the per-build state, packs the vertex coordinates as (x, y, z, 0)
-// and counts each vertex's incident triangles (one thread per corner, which
+// and counts each vertex's incident triangles (one lane per corner, which
 // keeps its index within the vertex's list).
-__global__ void k_clear_build(uint32_t* bitmap, int64_t nwords, int32_t* cell_cnt, int64_t ncnt, int32_t* counters,
-                              Mesh m, double2* vtx4, int32_t* vt_cnt, int32_t* vt_loc) {
+__global__ __launch_bounds__(kT) void k_clear_build(uint32_t* bitmap, int64_t nwords, int32_t* cell_cnt, int64_t ncnt,
+                                                   int32_t* counters, Mesh m, double2* vtx4, int32_t* vt_cnt,
+                                                   int32_t* vt_loc) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t x = g0; x < 3 * (int64_t)m.nt; x += stride) {
-    const int32_t v = distinct_corner(m, (int32_t)(x / 3), (int)(x % 3));
-    if (v >= 0) vt_loc[x] = atomicAdd(&vt_cnt[v], 1);
-  }
+  XcdWalk(3 * (int64_t)m.nt, blockIdx.x, gridDim.x).run([&](int64_t x, bool ok) {
+    const int32_t v = ok ? distinct_corner(m, (int32_t)(x / 3), (int)(x % 3)) : -1;
+    const int32_t loc = wave_count_add(vt_cnt, v, v >= 0);
+    if (v >= 0) vt_loc[x] = loc;
+  });
   for (int64_t v = g0; v < m.nv; v += stride) {
     vtx4[2 * v] = make_double2(m.x[v], m.y[v]);
     vtx4[2 * v + 1] = make_double2(m.z[v], 0.0);
@@ -117,14 +129,15 @@ __device__ inline int64_t block_alloc(int32_t v, int32_t* counter, int32_t* sh) 
 // that the wavefronts of the clipping mostly take the same branches.
 constexpr int kClassifyT = 512;
 __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, const double2* vtx4, int4* tri4,
-                                                             uint32_t* bitmap, PairOut P, int64_t q_cap,
-                                                             int32_t* counters) {
+                                                             PairOut P, int64_t q_cap, int32_t* counters) {
   __shared__ int32_t sh[kClassifyT / 64 + 1];
   __shared__ int32_t qoff[64];  // queued candidates per crossing mask, then their offsets
   __shared__ int32_t qbase;
   if (threadIdx.x < 64) qoff[threadIdx.x] = 0;
   __syncthreads();
-  const int32_t t = blockIdx.x * kClassifyT + threadIdx.x;
+  // the XCDs take contiguous ranges of triangles (the grid is a multiple of kXCD)
+  const int32_t lb = (blockIdx.x % kXCD) * (gridDim.x / kXCD) + blockIdx.x / kXCD;
+  const int32_t t = lb * kClassifyT + threadIdx.x;
   bool valid = t < m.nt;
   if (valid) {
     const int32_t a = m.t0[t], b = m.t1[t], c = m.t2[t];
@@ -155,11 +168,7 @@ __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, con
       for (int64_t i = lo[0]; i <= hi[0]; ++i) {
         const int cls = classify_candidate(g, T, i, j, k);
         if (cls == 1) {
-          if (whole_piece(T, grid_plane(g.z0, k, g.h)).keep) {
-            const int64_t lin = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-            atomicOr(&bitmap[lin >> 5], 1u << (lin & 31));
-            ++n1;
-          }
+          if (whole_piece(T, grid_plane(g.z0, k, g.h)).keep) ++n1;
         } else if (cls == 2) {
           atomicAdd(&qoff[crossing_mask(g, T, i, j, k)], 1);
           ++n2;
@@ -210,32 +219,44 @@ __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, con
       }
 }
 
-// Per queued candidate (second region of the pair list): full clipping; the
-// result stays in the candidate's slot, with cell -1 when there is no piece.
-__global__ __launch_bounds__(kPieceLanes) void k_clip_queue(Grid g, const int4* tri4, const double2* vtx4, PairOut P,
-                                                            int64_t q_cap, uint32_t* bitmap, const int32_t* counters) {
+// Workgroups [0, nb_clip): per queued candidate (second region of the pair
+// list), full clipping; the result stays in the candidate's slot, with cell
+// -1 when there is no piece.  The others: the whole-triangle pieces (first
+// region).  Both set the occupancy bits of their pieces' cells.
+__global__ __launch_bounds__(kPieceLanes) void k_clip_mark(Grid g, const int4* tri4, const double2* vtx4, PairOut P,
+                                                           int64_t q_cap, uint32_t* bitmap, const int32_t* counters,
+                                                           int32_t nb_clip) {
   __shared__ PolyLDS<kPieceLanes> L;
+  __shared__ uint32_t acc[kPieceLanes];
   const int lane = threadIdx.x;
-  const int64_t nq = min((int64_t)counters[C_NQUEUE], q_cap);
-  for (int64_t base = (int64_t)blockIdx.x * kPieceLanes; base < nq; base += (int64_t)gridDim.x * kPieceLanes) {
-    const int64_t q = base + lane;
-    if (q < nq) {
-      const int64_t slot = P.cap + q;
-      const int32_t lin = P.lin[slot];
-      const Cell3 c = unpack_cell(g, lin);
-      const Tri T = load_tri_packed(tri4, vtx4, P.tri[slot]);
-      const Piece pc = clip_piece(g, T, c.i, c.j, c.k, L, lane, inside_mask(g, T, c.i, c.j, c.k));
-      if (pc.keep) {
-        atomicOr(&bitmap[lin >> 5], 1u << (lin & 31));
-        P.flux[slot] = pc.flux;
-        P.vol[slot] = pc.vol;
-      } else {
-        P.lin[slot] = -1;
+  if ((int32_t)blockIdx.x < nb_clip) {
+    const int64_t nq = min((int64_t)counters[C_NQUEUE], q_cap);
+    XcdWalk(nq, blockIdx.x, nb_clip).run([&](int64_t q, bool ok) {
+      int32_t lin = -1;
+      if (ok) {
+        const int64_t slot = P.cap + q;
+        lin = P.lin[slot];
+        const Cell3 c = unpack_cell(g, lin);
+        const Tri T = load_tri_packed(tri4, vtx4, P.tri[slot]);
+        const Piece pc = clip_piece(g, T, c.i, c.j, c.k, L, lane, inside_mask(g, T, c.i, c.j, c.k));
+        if (pc.keep) {
+          P.flux[slot] = pc.flux;
+          P.vol[slot] = pc.vol;
+        } else {
+          P.lin[slot] = -1;
+          lin = -1;
+        }
       }
-    }
+      wave_set_bits(bitmap, lin >> 5, lin & 31, lin >= 0, acc);
+    });
+  } else {
+    const int64_t n1 = min((int64_t)counters[C_NWHOLE], P.cap);
+    XcdWalk(n1, blockIdx.x - nb_clip, gridDim.x - nb_clip).run([&](int64_t p, bool ok) {
+      const int32_t lin = ok ? P.lin[p] : -1;
+      wave_set_bits(bitmap, lin >> 5, lin & 31, lin >= 0, acc);
+    });
   }
 }
-
 
 __device__ inline int32_t rank_of(const uint32_t* bitmap, const int32_t* word_off, int64_t lin) {
   const uint32_t w = bitmap[lin >> 5];
@@ -267,36 +288,44 @@ struct VertexBins {
 // pair -> compact cell (in place of its linear id), counted per cell, its
 // index within the cell kept; and vertex -> the interfacial cell holding it,
 // counted per cell with its index kept (or listed as a stray)
-__global__ void k_pair_count(int32_t* pair_lin, int32_t* pair_local, const uint32_t* bitmap, const int32_t* word_off,
-                             int32_t* cell_cnt, int32_t cell_cap, int64_t pair_cap, int64_t queue_cap,
-                             int32_t* counters, Grid g, VertexBins B) {
+__global__ __launch_bounds__(kT) void k_pair_count(int32_t* pair_lin, int32_t* pair_local, const uint32_t* bitmap,
+                                                  const int32_t* word_off, int32_t* cell_cnt, int32_t cell_cap,
+                                                  int64_t pair_cap, int64_t queue_cap, int32_t* counters, Grid g,
+                                                  VertexBins B) {
   const PairRange R = pair_range(counters, pair_cap, queue_cap);
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < B.nv; v += gridDim.x * blockDim.x) {
-    const P3 p = vtx(B.vtx4, v);
+  XcdWalk(B.nv, blockIdx.x, gridDim.x).run([&](int64_t v, bool ok) {
     int32_t ci = -2;
-    if (in_margin(g, p.x, p.y, p.z)) {
-      const int64_t i = cell_index(p.x, g.x0, g.h), j = cell_index(p.y, g.y0, g.h), k = cell_index(p.z, g.z0, g.h);
-      ci = cell_rank(bitmap, word_off, i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
-      if (ci >= cell_cap) ci = -1;
+    if (ok) {
+      const P3 p = vtx(B.vtx4, (int32_t)v);
+      if (in_margin(g, p.x, p.y, p.z)) {
+        const int64_t i = cell_index(p.x, g.x0, g.h), j = cell_index(p.y, g.y0, g.h), k = cell_index(p.z, g.z0, g.h);
+        ci = cell_rank(bitmap, word_off, i + (int64_t)g.nx * (j + (int64_t)g.ny * k));
+        if (ci >= cell_cap) ci = -1;
+      }
+    }
+    const int32_t loc = wave_count_add(B.vb_cnt, ci, ci >= 0);
+    if (ok) {
       if (ci >= 0)
-        B.vb_loc[v] = atomicAdd(&B.vb_cnt[ci], 1);
-      else
-        B.stray[atomicAdd(&counters[C_NSTRAY], 1)] = v;
+        B.vb_loc[v] = loc;
+      else if (ci == -1)
+        B.stray[atomicAdd(&counters[C_NSTRAY], 1)] = (int32_t)v;
+      B.vcell[v] = ci;
     }
-    B.vcell[v] = ci;
-  }
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < R.count(); x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = R.slot(x);
-    const int32_t lin = pair_lin[p];
-    if (lin < 0) continue;
-    const int32_t ci = rank_of(bitmap, word_off, lin);
-    if (ci < cell_cap) {
+  });
+  XcdWalk(R.count(), blockIdx.x, gridDim.x).run([&](int64_t x, bool ok) {
+    const int64_t p = ok ? R.slot(x) : 0;
+    const int32_t lin = ok ? pair_lin[p] : -1;
+    int32_t ci = -1;
+    if (lin >= 0) {
+      ci = rank_of(bitmap, word_off, lin);
+      if (ci >= cell_cap) ci = -1;  // its cell did not fit the capacity (latched while listing the cells)
+    }
+    const int32_t loc = wave_count_add(cell_cnt, ci, ci >= 0);
+    if (lin >= 0) {
       pair_lin[p] = ci;
-      pair_local[p] = atomicAdd(&cell_cnt[ci], 1);
-    } else {
-      pair_lin[p] = -1;  // its cell did not fit the capacity (latched while listing the cells)
+      if (ci >= 0) pair_local[p] = loc;
     }
-  }
+  });
 }
 
 struct Adjacency {
@@ -309,42 +338,49 @@ struct Adjacency {
   int32_t* vb_ids;
 };
 
-// Pairs into their cell's segment, triangles into each distinct corner's
-// incident list and vertices into their cell's bin, each at the index the
-// counting gave it (an arbitrary order, fixed afterwards where it matters).
-__global__ void k_pair_scatter(const int32_t* pair_ci, const int32_t* pair_tri, const int32_t* pair_local,
-                               const int32_t* offsets, int32_t* tmp_tri, int32_t* tmp_pair, int64_t pair_cap,
-                               int64_t queue_cap, int32_t* counters, Mesh m, Adjacency J) {
+// Pairs into their cell's segment as records, triangles into each distinct
+// corner's incident list and vertices into their cell's bin, each at the
+// index the counting gave it (an arbitrary order, fixed afterwards where it
+// matters).
+__device__ inline void put_rec(double* rec, int64_t i, int32_t tri, int32_t ci, double flux, double vol) {
+  *reinterpret_cast<int4*>(rec + 4 * i) = make_int4(tri, ci, 0, 0);
+  *reinterpret_cast<double2*>(rec + 4 * i + 2) = make_double2(flux, vol);
+}
+
+__global__ __launch_bounds__(kT) void k_pair_scatter(const int32_t* pair_ci, const int32_t* pair_tri,
+                                                    const double* pair_flux, const double* pair_vol,
+                                                    const int32_t* pair_local, const int32_t* offsets, double* rec,
+                                                    int64_t pair_cap, int64_t queue_cap, int32_t* counters, Mesh m,
+                                                    Adjacency J) {
   const PairRange R = pair_range(counters, pair_cap, queue_cap);
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < 3 * (int64_t)m.nt;
-       x += (int64_t)gridDim.x * blockDim.x) {
+  XcdWalk(3 * (int64_t)m.nt, blockIdx.x, gridDim.x).run([&](int64_t x, bool ok) {
+    if (!ok) return;
     const int32_t t = (int32_t)(x / 3);
     const int32_t v = distinct_corner(m, t, (int)(x % 3));
     if (v >= 0) J.vt_ids[J.vt_off[v] + J.vt_loc[x]] = t;
-  }
-  for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < m.nv; v += gridDim.x * blockDim.x) {
+  });
+  XcdWalk(m.nv, blockIdx.x, gridDim.x).run([&](int64_t v, bool ok) {
+    if (!ok) return;
     const int32_t ci = J.vcell[v];
-    if (ci >= 0) J.vb_ids[J.vb_off[ci] + J.vb_loc[v]] = v;
-  }
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < R.count(); x += (int64_t)gridDim.x * blockDim.x) {
+    if (ci >= 0) J.vb_ids[J.vb_off[ci] + J.vb_loc[v]] = (int32_t)v;
+  });
+  XcdWalk(R.count(), blockIdx.x, gridDim.x).run([&](int64_t x, bool ok) {
+    if (!ok) return;
     const int64_t p = R.slot(x);
     const int32_t ci = pair_ci[p];
-    if (ci < 0) continue;
+    if (ci < 0) return;
     const int64_t pos = (int64_t)offsets[ci] + pair_local[p];
-    if (pos < pair_cap) {
-      tmp_tri[pos] = pair_tri[p];
-      tmp_pair[pos] = (int32_t)p;
-    } else {
+    if (pos < pair_cap)
+      put_rec(rec, pos, pair_tri[p], ci, pair_flux[p], pair_vol[p]);
+    else
       atomicOr(&counters[C_ERR], ERR_CAPACITY);
-    }
-  }
+  });
 }
 
 struct PlaceArgs {
-  const int32_t *tmp_tri, *tmp_pair, *pair_ci;
-  const double *pair_flux, *pair_vol;
+  const double* rec;
   const int32_t* offsets;
-  int32_t *tri_ids, *slot_cell;
+  int32_t* tri_ids;
   double *piece_flux, *piece_vol;
   int32_t cell_cap;
   int64_t pair_cap;
@@ -353,32 +389,37 @@ struct PlaceArgs {
 
 constexpr int kSegReg = 16;  // segment entries read in one batch of loads
 
+__device__ inline int32_t rec_tri(const double* rec, int32_t i) { return reinterpret_cast<const int32_t*>(rec + 4 * (int64_t)i)[0]; }
+
 // Each scattered piece moves to its rank by triangle id within its cell (a
 // triangle has at most one piece per cell, so the ranks are distinct): one
-// thread per piece counts the smaller triangle ids of its segment, read
-// kSegReg at a time with the loads of a batch issued together.
-__device__ inline void rank_place(const PlaceArgs& A, int64_t bid, int64_t nblk) {
+// lane per piece counts the smaller triangle ids of its segment, read
+// kSegReg at a time with the loads of a batch issued together.  Every slot
+// below the pieces' total holds a record: the positions of the counted
+// pieces are exactly [0, total).
+__device__ inline void rank_place(const PlaceArgs& A, int64_t group, int64_t ngroup) {
   const int32_t nif = min(A.counters[C_NIF], A.cell_cap);
   const int64_t nslot = min((int64_t)A.offsets[nif], A.pair_cap);
-  for (int64_t q = bid * blockDim.x + threadIdx.x; q < nslot; q += nblk * blockDim.x) {
-    const int32_t p = A.tmp_pair[q];
-    const int32_t ci = A.pair_ci[p];
-    const int32_t t = A.tmp_tri[q];
-    const int64_t s = A.offsets[ci], e = min((int64_t)A.offsets[ci + 1], A.pair_cap);
-    int64_t rank = 0;
-    for (int64_t b = s; b < e; b += kSegReg) {
+  XcdWalk(nslot, group, ngroup).run([&](int64_t q, bool ok) {
+    if (!ok) return;
+    const int4 hd = *reinterpret_cast<const int4*>(A.rec + 4 * q);
+    const double2 fv = *reinterpret_cast<const double2*>(A.rec + 4 * q + 2);
+    const int32_t t = hd.x, ci = hd.y;
+    if ((uint32_t)ci >= (uint32_t)nif) return;
+    const int32_t s = A.offsets[ci], e = (int32_t)min((int64_t)A.offsets[ci + 1], A.pair_cap);
+    int32_t rank = 0;
+    for (int32_t b = s; b < e; b += kSegReg) {
       int32_t seg[kSegReg];
 #pragma unroll
-      for (int u = 0; u < kSegReg; ++u) seg[u] = b + u < e ? A.tmp_tri[b + u] : INT_MAX;
+      for (int u = 0; u < kSegReg; ++u) seg[u] = b + u < e ? rec_tri(A.rec, b + u) : INT_MAX;
 #pragma unroll
       for (int u = 0; u < kSegReg; ++u) rank += seg[u] < t ? 1 : 0;
     }
-    const int64_t dst = s + rank;
+    const int32_t dst = s + rank;
     A.tri_ids[dst] = t;
-    A.slot_cell[dst] = ci;
-    A.piece_flux[dst] = A.pair_flux[p];
-    A.piece_vol[dst] = A.pair_vol[p];
-  }
+    A.piece_flux[dst] = fv.x;
+    A.piece_vol[dst] = fv.y;
+  });
 }
 
 constexpr int kSortReg = 8;  // incident lists up to this length are sorted in registers
@@ -428,45 +469,72 @@ struct VstarArgs {
 };
 
 // Closest vertex of each interfacial cell among the vertices binned in the
-// 3x3x3 block of cells around it and the strays: 32 lanes per cell, lane
-// l < 27 scans the bin of cell l of the block, every lane a share of the
-// strays; lowest index on ties.  A vertex outside the block is at least
-// 1.5 h from the cell centre, so a best squared distance below (1.5 h)^2 is
-// final (the curvature's ring pass searches all vertices for the other
-// cells).
+// 3x3x3 block of cells around it and the strays: kVsLanes lanes per cell,
+// lane l taking cells l, l + kVsLanes, ... of the block, the loads of each
+// level (bitmap words and their offsets, bin bounds, the first bin entries)
+// issued together for all of them; every lane a share of the strays; lowest
+// index on ties.  A vertex outside the block is at least 1.5 h from the
+// cell centre, so a best squared distance below (1.5 h)^2 is final (the
+// curvature's ring pass searches all vertices for the other cells).
 // Called with all 64 lanes of the wavefront.
-__device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int64_t gid) {
-  const int32_t nif = min(A.counters[C_NIF], A.cell_cap);
+constexpr int kVsLanes = 8;                               // lanes per cell
+constexpr int kVsNb = (27 + kVsLanes - 1) / kVsLanes;     // block cells per lane
+constexpr int kVsFirst = 4;                               // bin entries of the first batch
+__device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t nif, int64_t gid, bool ok) {
   const int32_t nstray = A.counters[C_NSTRAY];
-  const int64_t c = gid >> 5;
-  const int l = (int)(gid & 31);
+  const int64_t c = gid / kVsLanes;
+  const int l = (int)(gid % kVsLanes);
   double bd = DBL_MAX;
   int32_t bv = INT_MAX;
-  if (c < nif) {
+  ok = ok && c < nif;
+  if (ok) {
     const Cell3 cc = unpack_cell(g, A.cell_ids[c]);
     const double xc[3] = {cell_centre(g.x0, cc.i, g.h), cell_centre(g.y0, cc.j, g.h), cell_centre(g.z0, cc.k, g.h)};
-    if (l < 27) {
-      const int32_t ii = cc.i + l % 3 - 1, jj = cc.j + (l / 3) % 3 - 1, kk = cc.k + l / 9 - 1;
-      if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz) {
-        const int32_t cr = cell_rank(A.bitmap, A.word_off, ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk));
-        if (cr >= 0 && cr < A.cell_cap) {
-          // the first few of the bin in one batch of loads (the result does
-          // not depend on the order)
-          const int32_t p0 = A.vb_off[cr], p1 = A.vb_off[cr + 1];
-          int32_t vid[4];
+    int64_t wd[kVsNb];
+    int sh[kVsNb];
+    bool in[kVsNb];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) vid[u] = p0 + u < p1 ? A.vb_ids[p0 + u] : -1;
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (vid[u] >= 0) consider(A.vtx4, vid[u], xc, bd, bv);
-          for (int32_t p = p0 + 4; p < p1; ++p) consider(A.vtx4, A.vb_ids[p], xc, bd, bv);
-        }
-      }
+    for (int u = 0; u < kVsNb; ++u) {
+      const int n = l + kVsLanes * u;
+      const int32_t ii = cc.i + n % 3 - 1, jj = cc.j + (n / 3) % 3 - 1, kk = cc.k + n / 9 - 1;
+      in[u] = n < 27 && ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
+      const int64_t lin = in[u] ? ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk) : 0;
+      wd[u] = lin >> 5;
+      sh[u] = (int)(lin & 31);
     }
-    for (int32_t q = l; q < nstray; q += 32) consider(A.vtx4, A.stray[q], xc, bd, bv);
+    uint32_t bits[kVsNb];
+    int32_t wo[kVsNb];
+#pragma unroll
+    for (int u = 0; u < kVsNb; ++u) {
+      bits[u] = in[u] ? A.bitmap[wd[u]] : 0u;
+      wo[u] = in[u] ? A.word_off[wd[u]] : 0;
+    }
+    int32_t p0[kVsNb], p1[kVsNb];
+#pragma unroll
+    for (int u = 0; u < kVsNb; ++u) {
+      const bool set = (bits[u] >> sh[u]) & 1u;
+      const int32_t cr = wo[u] + __popc(bits[u] & ((1u << sh[u]) - 1u));
+      const bool has = set && cr < A.cell_cap;
+      p0[u] = has ? A.vb_off[cr] : 0;
+      p1[u] = has ? A.vb_off[cr + 1] : 0;
+    }
+    int32_t vid[kVsNb][kVsFirst];
+#pragma unroll
+    for (int u = 0; u < kVsNb; ++u)
+#pragma unroll
+      for (int f = 0; f < kVsFirst; ++f) vid[u][f] = p0[u] + f < p1[u] ? A.vb_ids[p0[u] + f] : -1;
+#pragma unroll
+    for (int u = 0; u < kVsNb; ++u)
+#pragma unroll
+      for (int f = 0; f < kVsFirst; ++f)
+        if (vid[u][f] >= 0) consider(A.vtx4, vid[u][f], xc, bd, bv);
+#pragma unroll
+    for (int u = 0; u < kVsNb; ++u)
+      for (int32_t p = p0[u] + kVsFirst; p < p1[u]; ++p) consider(A.vtx4, A.vb_ids[p], xc, bd, bv);
+    for (int32_t q = l; q < nstray; q += kVsLanes) consider(A.vtx4, A.stray[q], xc, bd, bv);
   }
 #pragma unroll
-  for (int o = 16; o >= 1; o >>= 1) {
+  for (int o = kVsLanes / 2; o >= 1; o >>= 1) {
     const double od = __shfl_xor(bd, o, 64);
     const int32_t ov = __shfl_xor(bv, o, 64);
     if (lex_less(od, ov, bd, bv)) {
@@ -474,15 +542,15 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int64_t
       bv = ov;
     }
   }
-  if (c < nif && l == 0) {
+  if (ok && l == 0) {
     A.best_d2[c] = bd;
     A.best_v[c] = bv;
   }
 }
 
-// Blocks [0, nb_place): pieces to their ranks; [nb_place, nb_place +
+// Workgroups [0, nb_place): pieces to their ranks; [nb_place, nb_place +
 // nb_sort): one vertex per thread, its incident list sorted; the rest:
-// closest vertices.
+// closest vertices (nb_place and nb_sort are multiples of kXCD).
 __global__ __launch_bounds__(kT) void k_place_sort_vstar(PlaceArgs A, int32_t nb_place, int32_t nb_sort, Grid g,
                                                          int32_t nv, const int32_t* vt_off, int32_t* vt_ids,
                                                          VstarArgs V) {
@@ -493,7 +561,11 @@ __global__ __launch_bounds__(kT) void k_place_sort_vstar(PlaceArgs A, int32_t nb
     const int32_t v = (b - nb_place) * kT + threadIdx.x;
     if (v < nv) sort_incident(vt_off, vt_ids, v);
   } else {
-    closest_vertex(g, V, (int64_t)(b - nb_place - nb_sort) * kT + threadIdx.x);
+    const int32_t nif = min(V.counters[C_NIF], V.cell_cap);
+    const int32_t nb0 = nb_place + nb_sort;
+    XcdWalk((int64_t)nif * kVsLanes, b - nb0, (int64_t)gridDim.x - nb0).run([&](int64_t gid, bool ok) {
+      closest_vertex(g, V, nif, gid, ok);
+    });
   }
 }
 
@@ -507,36 +579,37 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
                      (int64_t)ws->cell_cap + 1, ws->counters, m, vtx4, ws->vt_cursor, ws->vt_loc);
   PairOut P{ws->pair_cell, ws->pair_tri, ws->pair_flux, ws->pair_vol, ws->pair_cap};
   time_start(ws, FTC_KERNEL_TRI_PIECES, s);
-  hipLaunchKernelGGL(k_tri_classify, dim3(grid_blocks(m.nt, kClassifyT)), dim3(kClassifyT), 0, s, g, m, vtx4, tri4,
-                     ws->bitmap, P, ws->queue_cap, ws->counters);
-  hipLaunchKernelGGL(k_clip_queue, dim3(grid_blocks(ws->queue_cap, kPieceLanes, 8192)), dim3(kPieceLanes), 0, s, g,
-                     tri4, vtx4, P, ws->queue_cap, ws->bitmap, ws->counters);
+  hipLaunchKernelGGL(k_tri_classify, dim3(round_up_xcd(grid_blocks(m.nt, kClassifyT))), dim3(kClassifyT), 0, s, g, m,
+                     vtx4, tri4, P, ws->queue_cap, ws->counters);
+  const int32_t nb_clip = round_up_xcd(grid_blocks(ws->queue_cap, kPieceLanes, 8192));
+  const int32_t nb_mark = round_up_xcd(grid_blocks(ws->pair_cap, kPieceLanes, 4096));
+  hipLaunchKernelGGL(k_clip_mark, dim3(nb_clip + nb_mark), dim3(kPieceLanes), 0, s, g, tri4, vtx4, P, ws->queue_cap,
+                     ws->bitmap, ws->counters, nb_clip);
   time_stop(ws, FTC_KERNEL_TRI_PIECES, s);
   hipError_t e = scan_popcount_emit(ws->bitmap, ws->word_off, ws->nwords, ws->scan_tmp, ws->counters + C_NIF,
                                     ws->cell_ids, ws->cell_cap, ws->counters, s);
   if (e != hipSuccess) return e;
   const int64_t npair_max = ws->pair_cap + ws->queue_cap;
+  const int32_t nb_pairs = round_up_xcd(grid_blocks(npair_max, kT, kStrideBlocks));
   VertexBins B{m.nv, vtx4, ws->vcell, ws->vb_cursor, ws->vb_loc, ws->stray};
-  hipLaunchKernelGGL(k_pair_count, dim3(grid_blocks(npair_max, kT, kStrideBlocks)), dim3(kT), 0, s, ws->pair_cell,
-                     ws->pair_local, ws->bitmap, ws->word_off, ws->offsets, ws->cell_cap, ws->pair_cap,
-                     ws->queue_cap, ws->counters, g, B);
+  hipLaunchKernelGGL(k_pair_count, dim3(nb_pairs), dim3(kT), 0, s, ws->pair_cell, ws->pair_local, ws->bitmap,
+                     ws->word_off, ws->offsets, ws->cell_cap, ws->pair_cap, ws->queue_cap, ws->counters, g, B);
   const ScanSeg segs[3] = {{ws->offsets, ws->offsets, ws->cell_cap, ws->counters + C_NPAIRS, nullptr},
                            {ws->vt_cursor, ws->vt_off, m.nv, nullptr, ws->vt_cursor},
                            {ws->vb_cursor, ws->vb_off, ws->cell_cap, nullptr, ws->vb_cursor}};
   e = scan_exclusive_multi(segs, 3, ws->scan_tmp, s);
   if (e != hipSuccess) return e;
   Adjacency J{ws->vt_off, ws->vt_loc, ws->vt_ids, ws->vcell, ws->vb_off, ws->vb_loc, ws->vb_ids};
-  hipLaunchKernelGGL(k_pair_scatter, dim3(grid_blocks(npair_max, kT, kStrideBlocks)), dim3(kT), 0, s, ws->pair_cell,
-                     ws->pair_tri, ws->pair_local, ws->offsets, ws->tmp_tri, ws->tmp_pair, ws->pair_cap, ws->queue_cap,
+  hipLaunchKernelGGL(k_pair_scatter, dim3(nb_pairs), dim3(kT), 0, s, ws->pair_cell, ws->pair_tri, ws->pair_flux,
+                     ws->pair_vol, ws->pair_local, ws->offsets, ws->tmp_rec, ws->pair_cap, ws->queue_cap,
                      ws->counters, m, J);
-  PlaceArgs A{ws->tmp_tri,  ws->tmp_pair,  ws->pair_cell,  ws->pair_flux, ws->pair_vol, ws->offsets,
-              ws->tri_ids,  ws->slot_cell, ws->piece_flux, ws->piece_vol, ws->cell_cap, ws->pair_cap,
+  PlaceArgs A{ws->tmp_rec, ws->offsets, ws->tri_ids, ws->piece_flux, ws->piece_vol, ws->cell_cap, ws->pair_cap,
               ws->counters};
   VstarArgs V{vtx4,       ws->cell_ids, ws->bitmap,  ws->word_off, ws->vb_off,  ws->vb_ids,
               ws->stray,  ws->best_d2,  ws->best_v,  ws->cell_cap, ws->counters};
-  const int32_t nb_place = grid_blocks(ws->pair_cap, kT, kStrideBlocks);
-  const int32_t nb_sort = grid_blocks(m.nv, kT);
-  const int32_t nb_vstar = grid_blocks((int64_t)ws->cell_cap * 32, kT);
+  const int32_t nb_place = round_up_xcd(grid_blocks(ws->pair_cap, kT, kStrideBlocks));
+  const int32_t nb_sort = round_up_xcd(grid_blocks(m.nv, kT));
+  const int32_t nb_vstar = round_up_xcd(grid_blocks((int64_t)ws->cell_cap * kVsLanes, kT));
   time_start(ws, FTC_KERNEL_PIECE_RANK, s);
   hipLaunchKernelGGL(k_place_sort_vstar, dim3(nb_place + nb_sort + nb_vstar), dim3(kT), 0, s, A, nb_place, nb_sort, g,
                      m.nv, ws->vt_off, ws->vt_ids, V);

@@ -69,13 +69,12 @@ struct ftc_cells {
   int32_t* pair_tri;      // triangle of each piece
   double* pair_flux;      // integral of n_z dA
   double* pair_vol;       // integral of (z - zlo) n_z dA
-  int32_t* tmp_tri;       // [pair_cap] triangles scattered into their cell's segment
-  int32_t* tmp_pair;      // [pair_cap] pair-list slot of each scattered piece
+  double* tmp_rec;        // [4*pair_cap] pieces scattered into their cell's segment, 32-byte records
+                          // (triangle, compact cell, 0, 0 as int32; flux; volume integral)
   int32_t* cell_ids;      // [cell_cap] linear ids, ascending
   int32_t* offsets;       // [cell_cap+1] CSR offsets into tri_ids
   int32_t* pair_local;    // [pair_cap + queue_cap] index of each pair within its cell, from the counting
   int32_t* tri_ids;       // [pair_cap] CSR triangle ids, ascending per cell
-  int32_t* slot_cell;     // [pair_cap] compact cell of each CSR slot
   double* piece_flux;     // [pair_cap] integral of n_z dA per CSR slot
   double* piece_vol;      // [pair_cap] integral of (z - zlo) n_z dA per CSR slot
 
