@@ -151,7 +151,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(vb_off, Cc + 1);
   FTC_ALLOC(vb_cursor, Cc);
   FTC_ALLOC(vb_loc, Vc);
-  FTC_ALLOC(vb_ids, Vc);
+  FTC_ALLOC(vb_rec, 4 * Vc);
   FTC_ALLOC(stray, Vc);
   FTC_ALLOC(frame_n, 3 * Cc);
   FTC_ALLOC(best_d2, Cc);

@@ -335,7 +335,8 @@ struct Adjacency {
   const int32_t* vcell;
   const int32_t* vb_off;
   const int32_t* vb_loc;
-  int32_t* vb_ids;
+  const double2* vtx4;
+  double2* vb_rec;  // per binned vertex: (x, y), (z, index as the bits of a double)
 };
 
 // Pairs into their cell's segment as records, triangles into each distinct
@@ -362,7 +363,11 @@ __global__ __launch_bounds__(kT) void k_pair_scatter(const int32_t* pair_ci, con
   XcdWalk(m.nv, blockIdx.x, gridDim.x).run([&](int64_t v, bool ok) {
     if (!ok) return;
     const int32_t ci = J.vcell[v];
-    if (ci >= 0) J.vb_ids[J.vb_off[ci] + J.vb_loc[v]] = (int32_t)v;
+    if (ci >= 0) {
+      const int64_t pos = (int64_t)J.vb_off[ci] + J.vb_loc[v];
+      J.vb_rec[2 * pos] = J.vtx4[2 * v];
+      J.vb_rec[2 * pos + 1] = make_double2(J.vtx4[2 * v + 1].x, __longlong_as_double((long long)v));
+    }
   });
   XcdWalk(R.count(), blockIdx.x, gridDim.x).run([&](int64_t x, bool ok) {
     if (!ok) return;
@@ -461,7 +466,9 @@ struct VstarArgs {
   const int32_t* cell_ids;
   const uint32_t* bitmap;
   const int32_t* word_off;
-  const int32_t *vb_off, *vb_ids, *stray;
+  const int32_t* vb_off;
+  const double2* vb_rec;
+  const int32_t* stray;
   double* best_d2;
   int32_t* best_v;
   int32_t cell_cap;
@@ -470,16 +477,30 @@ struct VstarArgs {
 
 // Closest vertex of each interfacial cell among the vertices binned in the
 // 3x3x3 block of cells around it and the strays: kVsLanes lanes per cell,
-// lane l taking cells l, l + kVsLanes, ... of the block, the loads of each
-// level (bitmap words and their offsets, bin bounds, the first bin entries)
-// issued together for all of them; every lane a share of the strays; lowest
+// lane l taking cells l, l + kVsLanes, ... of the block; the loads of each
+// level (bitmap words and their offsets, then bin bounds) are issued
+// together for all of them, then the lane's bin entries, kVsBatch records
+// (position and index) at a time; every lane a share of the strays; lowest
 // index on ties.  A vertex outside the block is at least 1.5 h from the
 // cell centre, so a best squared distance below (1.5 h)^2 is final (the
 // curvature's ring pass searches all vertices for the other cells).
 // Called with all 64 lanes of the wavefront.
-constexpr int kVsLanes = 8;                               // lanes per cell
-constexpr int kVsNb = (27 + kVsLanes - 1) / kVsLanes;     // block cells per lane
-constexpr int kVsFirst = 4;                               // bin entries of the first batch
+constexpr int kVsLanes = 8;                            // lanes per cell
+constexpr int kVsNb = (27 + kVsLanes - 1) / kVsLanes;  // block cells per lane
+constexpr int kVsBatch = 8;                            // bin records loaded together
+
+// d^2 to xc of a binned vertex record, kept when it beats (bd, bv); the
+// same arithmetic as consider().
+__device__ inline void consider_rec(double2 r0, double2 r1, const double xc[3], double& bd, int32_t& bv) {
+  const int32_t v = (int32_t)__double_as_longlong(r1.y);
+  const double dx = r0.x - xc[0], dy = r0.y - xc[1], dz = r1.x - xc[2];
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  if (lex_less(d2, v, bd, bv)) {
+    bd = d2;
+    bv = v;
+  }
+}
+
 __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t nif, int64_t gid, bool ok) {
   const int32_t nstray = A.counters[C_NSTRAY];
   const int64_t c = gid / kVsLanes;
@@ -509,28 +530,36 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t
       bits[u] = in[u] ? A.bitmap[wd[u]] : 0u;
       wo[u] = in[u] ? A.word_off[wd[u]] : 0;
     }
-    int32_t p0[kVsNb], p1[kVsNb];
+    int32_t p0[kVsNb], cum[kVsNb + 1];
+    cum[0] = 0;
 #pragma unroll
     for (int u = 0; u < kVsNb; ++u) {
       const bool set = (bits[u] >> sh[u]) & 1u;
       const int32_t cr = wo[u] + __popc(bits[u] & ((1u << sh[u]) - 1u));
       const bool has = set && cr < A.cell_cap;
       p0[u] = has ? A.vb_off[cr] : 0;
-      p1[u] = has ? A.vb_off[cr + 1] : 0;
+      const int32_t p1 = has ? A.vb_off[cr + 1] : 0;
+      cum[u + 1] = cum[u] + (p1 - p0[u]);
     }
-    int32_t vid[kVsNb][kVsFirst];
+    // the lane's bins as one list: entry j is entry j - cum[u] of bin u
+    for (int32_t j0 = 0; j0 < cum[kVsNb]; j0 += kVsBatch) {
+      double2 r0[kVsBatch], r1[kVsBatch];
 #pragma unroll
-    for (int u = 0; u < kVsNb; ++u)
+      for (int q = 0; q < kVsBatch; ++q) {
+        const int32_t j = j0 + q;
+        int32_t p = -1;
 #pragma unroll
-      for (int f = 0; f < kVsFirst; ++f) vid[u][f] = p0[u] + f < p1[u] ? A.vb_ids[p0[u] + f] : -1;
+        for (int u = 0; u < kVsNb; ++u)
+          if (j >= cum[u] && j < cum[u + 1]) p = p0[u] + (j - cum[u]);
+        if (p >= 0) {
+          r0[q] = A.vb_rec[2 * (int64_t)p];
+          r1[q] = A.vb_rec[2 * (int64_t)p + 1];
+        }
+      }
 #pragma unroll
-    for (int u = 0; u < kVsNb; ++u)
-#pragma unroll
-      for (int f = 0; f < kVsFirst; ++f)
-        if (vid[u][f] >= 0) consider(A.vtx4, vid[u][f], xc, bd, bv);
-#pragma unroll
-    for (int u = 0; u < kVsNb; ++u)
-      for (int32_t p = p0[u] + kVsFirst; p < p1[u]; ++p) consider(A.vtx4, A.vb_ids[p], xc, bd, bv);
+      for (int q = 0; q < kVsBatch; ++q)
+        if (j0 + q < cum[kVsNb]) consider_rec(r0[q], r1[q], xc, bd, bv);
+    }
     for (int32_t q = l; q < nstray; q += kVsLanes) consider(A.vtx4, A.stray[q], xc, bd, bv);
   }
 #pragma unroll
@@ -548,25 +577,26 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t
   }
 }
 
-// Workgroups [0, nb_place): pieces to their ranks; [nb_place, nb_place +
-// nb_sort): one vertex per thread, its incident list sorted; the rest:
-// closest vertices (nb_place and nb_sort are multiples of kXCD).
-__global__ __launch_bounds__(kT) void k_place_sort_vstar(PlaceArgs A, int32_t nb_place, int32_t nb_sort, Grid g,
-                                                         int32_t nv, const int32_t* vt_off, int32_t* vt_ids,
-                                                         VstarArgs V) {
+// Workgroups [0, nb_place): pieces to their ranks; the others: one vertex
+// per thread, its incident list sorted.
+__global__ __launch_bounds__(kT) void k_place_sort(PlaceArgs A, int32_t nb_place, int32_t nv, const int32_t* vt_off,
+                                                   int32_t* vt_ids) {
   const int32_t b = blockIdx.x;
   if (b < nb_place) {
     rank_place(A, b, nb_place);
-  } else if (b < nb_place + nb_sort) {
+  } else {
     const int32_t v = (b - nb_place) * kT + threadIdx.x;
     if (v < nv) sort_incident(vt_off, vt_ids, v);
-  } else {
-    const int32_t nif = min(V.counters[C_NIF], V.cell_cap);
-    const int32_t nb0 = nb_place + nb_sort;
-    XcdWalk((int64_t)nif * kVsLanes, b - nb0, (int64_t)gridDim.x - nb0).run([&](int64_t gid, bool ok) {
-      closest_vertex(g, V, nif, gid, ok);
-    });
   }
+}
+
+// Closest vertex of every interfacial cell (its own launch: it needs about
+// twice the registers of the placing).
+__global__ __launch_bounds__(kT) void k_vstar(Grid g, VstarArgs V) {
+  const int32_t nif = min(V.counters[C_NIF], V.cell_cap);
+  XcdWalk((int64_t)nif * kVsLanes, blockIdx.x, gridDim.x).run([&](int64_t gid, bool ok) {
+    closest_vertex(g, V, nif, gid, ok);
+  });
 }
 
 }  // namespace
@@ -599,20 +629,21 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
                            {ws->vb_cursor, ws->vb_off, ws->cell_cap, nullptr, ws->vb_cursor}};
   e = scan_exclusive_multi(segs, 3, ws->scan_tmp, s);
   if (e != hipSuccess) return e;
-  Adjacency J{ws->vt_off, ws->vt_loc, ws->vt_ids, ws->vcell, ws->vb_off, ws->vb_loc, ws->vb_ids};
+  Adjacency J{ws->vt_off, ws->vt_loc, ws->vt_ids, ws->vcell, ws->vb_off, ws->vb_loc, vtx4,
+              reinterpret_cast<double2*>(ws->vb_rec)};
   hipLaunchKernelGGL(k_pair_scatter, dim3(nb_pairs), dim3(kT), 0, s, ws->pair_cell, ws->pair_tri, ws->pair_flux,
                      ws->pair_vol, ws->pair_local, ws->offsets, ws->tmp_rec, ws->pair_cap, ws->queue_cap,
                      ws->counters, m, J);
   PlaceArgs A{ws->tmp_rec, ws->offsets, ws->tri_ids, ws->piece_flux, ws->piece_vol, ws->cell_cap, ws->pair_cap,
               ws->counters};
-  VstarArgs V{vtx4,       ws->cell_ids, ws->bitmap,  ws->word_off, ws->vb_off,  ws->vb_ids,
+  VstarArgs V{vtx4,       ws->cell_ids, ws->bitmap,  ws->word_off, ws->vb_off,  reinterpret_cast<const double2*>(ws->vb_rec),
               ws->stray,  ws->best_d2,  ws->best_v,  ws->cell_cap, ws->counters};
   const int32_t nb_place = round_up_xcd(grid_blocks(ws->pair_cap, kT, kStrideBlocks));
-  const int32_t nb_sort = round_up_xcd(grid_blocks(m.nv, kT));
+  const int32_t nb_sort = grid_blocks(m.nv, kT);
   const int32_t nb_vstar = round_up_xcd(grid_blocks((int64_t)ws->cell_cap * kVsLanes, kT));
   time_start(ws, FTC_KERNEL_PIECE_RANK, s);
-  hipLaunchKernelGGL(k_place_sort_vstar, dim3(nb_place + nb_sort + nb_vstar), dim3(kT), 0, s, A, nb_place, nb_sort, g,
-                     m.nv, ws->vt_off, ws->vt_ids, V);
+  hipLaunchKernelGGL(k_vstar, dim3(nb_vstar), dim3(kT), 0, s, g, V);
+  hipLaunchKernelGGL(k_place_sort, dim3(nb_place + nb_sort), dim3(kT), 0, s, A, nb_place, m.nv, ws->vt_off, ws->vt_ids);
   time_stop(ws, FTC_KERNEL_PIECE_RANK, s);
   e = hipGetLastError();
   if (e == hipSuccess) {

@@ -93,7 +93,8 @@ struct ftc_cells {
   int32_t* vb_off;        // [cell_cap+1] offsets of each interfacial cell's vertices
   int32_t* vb_cursor;     // [cell_cap] vertices per cell while counting; zero between calls
   int32_t* vb_loc;        // [nv_cap] index of each vertex within its cell's bin
-  int32_t* vb_ids;        // [nv_cap] vertices grouped by interfacial cell
+  double* vb_rec;         // [4*nv_cap] vertices grouped by interfacial cell: x, y, z, index (as the bits
+                          // of a double)
   int32_t* stray;         // [nv_cap] vertices in cells without pieces
   double* frame_n;        // [3 * cell_cap] frame normal of each cell's volume fit
   double* quad_nodes;     // [kQuadNodes] quadrature nodes and weights of the paraboloid cell integrals

@@ -180,7 +180,9 @@ __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
         }
         a = rr;
       }
-      if (A.alpha && col_ok) A.alpha[lin] = a;
+      // the dense field is written once and read by later calls only:
+      // streaming stores keep it from evicting the lists the step still uses
+      if (A.alpha && col_ok) __builtin_nontemporal_store(a, &A.alpha[lin]);
     }
   }
   if (w == 0 && col_ok && fabs(W / h2) > 1e-9) bad = true;  // the column must close below the front
