@@ -162,15 +162,25 @@ __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, con
       tri_range(g, T, lo, hi);
     }
   }
-  int32_t n1 = 0, n2 = 0;
+  // Whether a whole-triangle piece counts does not depend on the cell (the
+  // vector area of the triangle itself).  The first pass keeps the class of
+  // the first 32 candidates (2 bits each) and the crossing mask of the first
+  // 8 (6 bits each) for the second.
+  const bool tri_keep = valid && whole_piece(T, 0.0).keep;
+  uint64_t cls_bits = 0u, mask_bits = 0u;
+  int32_t n1 = 0, n2 = 0, idx = 0;
   for (int64_t k = lo[2]; k <= hi[2]; ++k)
     for (int64_t j = lo[1]; j <= hi[1]; ++j)
-      for (int64_t i = lo[0]; i <= hi[0]; ++i) {
-        const int cls = classify_candidate(g, T, i, j, k);
+      for (int64_t i = lo[0]; i <= hi[0]; ++i, ++idx) {
+        int cls = classify_candidate(g, T, i, j, k);
+        if (cls == 1 && !tri_keep) cls = 0;
+        if (idx < 32) cls_bits |= (uint64_t)cls << (2 * idx);
         if (cls == 1) {
-          if (whole_piece(T, grid_plane(g.z0, k, g.h)).keep) ++n1;
+          ++n1;
         } else if (cls == 2) {
-          atomicAdd(&qoff[crossing_mask(g, T, i, j, k)], 1);
+          const uint32_t mk = crossing_mask(g, T, i, j, k);
+          if (idx < 8) mask_bits |= (uint64_t)mk << (6 * idx);
+          atomicAdd(&qoff[mk], 1);
           ++n2;
         }
       }
@@ -189,26 +199,32 @@ __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, con
   }
   __syncthreads();
   if (n1 + n2 == 0) return;
+  idx = 0;
   for (int64_t k = lo[2]; k <= hi[2]; ++k)
     for (int64_t j = lo[1]; j <= hi[1]; ++j)
-      for (int64_t i = lo[0]; i <= hi[0]; ++i) {
-        const int cls = classify_candidate(g, T, i, j, k);
+      for (int64_t i = lo[0]; i <= hi[0]; ++i, ++idx) {
+        int cls;
+        if (idx < 32) {
+          cls = (int)((cls_bits >> (2 * idx)) & 3u);
+        } else {
+          cls = classify_candidate(g, T, i, j, k);
+          if (cls == 1 && !tri_keep) cls = 0;
+        }
         const int64_t lin = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
         if (cls == 1) {
           const Piece pc = whole_piece(T, grid_plane(g.z0, k, g.h));
-          if (pc.keep) {
-            if (p < P.cap) {
-              P.lin[p] = (int32_t)lin;
-              P.tri[p] = t;
-              P.flux[p] = pc.flux;
-              P.vol[p] = pc.vol;
-            } else {
-              atomicOr(&counters[C_ERR], ERR_CAPACITY);
-            }
-            ++p;
+          if (p < P.cap) {
+            P.lin[p] = (int32_t)lin;
+            P.tri[p] = t;
+            P.flux[p] = pc.flux;
+            P.vol[p] = pc.vol;
+          } else {
+            atomicOr(&counters[C_ERR], ERR_CAPACITY);
           }
+          ++p;
         } else if (cls == 2) {
-          const int64_t q = (int64_t)qbase + atomicAdd(&qoff[crossing_mask(g, T, i, j, k)], 1);
+          const uint32_t mk = idx < 8 ? (uint32_t)((mask_bits >> (6 * idx)) & 63u) : crossing_mask(g, T, i, j, k);
+          const int64_t q = (int64_t)qbase + atomicAdd(&qoff[mk], 1);
           if (q < q_cap) {
             P.lin[P.cap + q] = (int32_t)lin;
             P.tri[P.cap + q] = t;
