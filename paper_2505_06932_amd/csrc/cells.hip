@@ -16,7 +16,8 @@
 // 4. scatter the pairs into their cell's segment (any order) as 32-byte
 //    records carrying everything the next step needs, then place each at
 //    its rank by triangle id within the segment, so that the CSR lists come
-//    out in ascending triangle id whatever the scheduling was.
+//    out in ascending triangle id whatever the scheduling was, and sum each
+//    cell's piece integrals in that order (for the volume fraction).
 // Lanes of one atomic instruction that hit the same address are served one
 // after another, and neighbouring pieces, corners and vertices share cells,
 // words and vertices: every count and every bitmap bit is taken with one
@@ -403,43 +404,111 @@ struct PlaceArgs {
   const int32_t* offsets;
   int32_t* tri_ids;
   double *piece_flux, *piece_vol;
+  double *cell_flux, *cell_vol;
   int32_t cell_cap;
   int64_t pair_cap;
   const int32_t* counters;
 };
 
-constexpr int kSegReg = 16;  // segment entries read in one batch of loads
+constexpr int kSegReg = 16;  // segment entries read in one batch of loads (long segments)
+constexpr int kPlLanes = 16;  // lanes per cell
+constexpr int kPlCap = 64;    // segments up to this length are staged in LDS
+constexpr int kPlPer = kPlCap / kPlLanes;
 
 __device__ inline int32_t rec_tri(const double* rec, int32_t i) { return reinterpret_cast<const int32_t*>(rec + 4 * (int64_t)i)[0]; }
 
-// Each scattered piece moves to its rank by triangle id within its cell (a
-// triangle has at most one piece per cell, so the ranks are distinct): one
-// lane per piece counts the smaller triangle ids of its segment, read
-// kSegReg at a time with the loads of a batch issued together.  Every slot
-// below the pieces' total holds a record: the positions of the counted
+// Per interfacial cell, kPlLanes lanes: the cell's scattered pieces move to
+// their ranks by triangle id within its segment (a triangle has at most one
+// piece per cell, so the ranks are distinct), and the cell's two integrals
+// are summed over the placed pieces in a fixed order: lane l takes entries
+// l, l + kPlLanes, ..., then the lanes' sums are added pairwise.  Segments
+// of up to kPlCap pieces are staged in LDS and ranked there; longer ones are
+// ranked from global memory, kSegReg entries per batch of loads.  Every
+// slot below the pieces' total holds a record: the positions of the counted
 // pieces are exactly [0, total).
-__device__ inline void rank_place(const PlaceArgs& A, int64_t group, int64_t ngroup) {
+__device__ inline void place_sums(const PlaceArgs& A, int64_t group, int64_t ngroup) {
+  __shared__ int32_t tri_s[kT / kPlLanes][kPlCap];
+  __shared__ double fv_s[kT / kPlLanes][2][kPlCap];
+  const int grp = threadIdx.x / kPlLanes;
   const int32_t nif = min(A.counters[C_NIF], A.cell_cap);
-  const int64_t nslot = min((int64_t)A.offsets[nif], A.pair_cap);
-  XcdWalk(nslot, group, ngroup).run([&](int64_t q, bool ok) {
-    if (!ok) return;
-    const int4 hd = *reinterpret_cast<const int4*>(A.rec + 4 * q);
-    const double2 fv = *reinterpret_cast<const double2*>(A.rec + 4 * q + 2);
-    const int32_t t = hd.x, ci = hd.y;
-    if ((uint32_t)ci >= (uint32_t)nif) return;
-    const int32_t s = A.offsets[ci], e = (int32_t)min((int64_t)A.offsets[ci + 1], A.pair_cap);
-    int32_t rank = 0;
-    for (int32_t b = s; b < e; b += kSegReg) {
-      int32_t seg[kSegReg];
+  XcdWalk((int64_t)nif * kPlLanes, group, ngroup).run([&](int64_t gid, bool ok) {
+    const int64_t c = gid / kPlLanes;
+    const int l = (int)(gid % kPlLanes);
+    ok = ok && c < nif;
+    const int32_t s = ok ? A.offsets[c] : 0;
+    const int32_t e = ok ? (int32_t)min((int64_t)A.offsets[c + 1], A.pair_cap) : 0;
+    const int32_t len = e - s;
+    double f = 0.0, v = 0.0;
+    if (len <= kPlCap) {
+      int32_t t[kPlPer], rank[kPlPer];
+      double fl[kPlPer], vo[kPlPer];
 #pragma unroll
-      for (int u = 0; u < kSegReg; ++u) seg[u] = b + u < e ? rec_tri(A.rec, b + u) : INT_MAX;
+      for (int m = 0; m < kPlPer; ++m) {
+        const int32_t q = l + m * kPlLanes;
+        t[m] = INT_MAX;
+        fl[m] = vo[m] = 0.0;
+        rank[m] = 0;
+        if (q < len) {
+          const int4 hd = *reinterpret_cast<const int4*>(A.rec + 4 * (int64_t)(s + q));
+          const double2 fv = *reinterpret_cast<const double2*>(A.rec + 4 * (int64_t)(s + q) + 2);
+          t[m] = hd.x;
+          fl[m] = fv.x;
+          vo[m] = fv.y;
+          tri_s[grp][q] = hd.x;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      for (int32_t j = 0; j < len; ++j) {
+        const int32_t tj = tri_s[grp][j];
 #pragma unroll
-      for (int u = 0; u < kSegReg; ++u) rank += seg[u] < t ? 1 : 0;
+        for (int m = 0; m < kPlPer; ++m) rank[m] += tj < t[m] ? 1 : 0;
+      }
+#pragma unroll
+      for (int m = 0; m < kPlPer; ++m)
+        if (l + m * kPlLanes < len) {
+          const int32_t dst = s + rank[m];
+          A.tri_ids[dst] = t[m];
+          A.piece_flux[dst] = fl[m];
+          A.piece_vol[dst] = vo[m];
+          fv_s[grp][0][rank[m]] = fl[m];
+          fv_s[grp][1][rank[m]] = vo[m];
+        }
+      __builtin_amdgcn_wave_barrier();
+      for (int32_t q = l; q < len; q += kPlLanes) {
+        f += fv_s[grp][0][q];
+        v += fv_s[grp][1][q];
+      }
+    } else {
+      for (int32_t q = s + l; q < e; q += kPlLanes) {
+        const int32_t tq = rec_tri(A.rec, q);
+        const double2 fv = *reinterpret_cast<const double2*>(A.rec + 4 * (int64_t)q + 2);
+        int32_t rank = 0;
+        for (int32_t b = s; b < e; b += kSegReg) {
+          int32_t seg[kSegReg];
+#pragma unroll
+          for (int u = 0; u < kSegReg; ++u) seg[u] = b + u < e ? rec_tri(A.rec, b + u) : INT_MAX;
+#pragma unroll
+          for (int u = 0; u < kSegReg; ++u) rank += seg[u] < tq ? 1 : 0;
+        }
+        A.tri_ids[s + rank] = tq;
+        A.piece_flux[s + rank] = fv.x;
+        A.piece_vol[s + rank] = fv.y;
+      }
+      __threadfence_block();  // the placed entries, written by the cell's other lanes
+      for (int32_t q = s + l; q < e; q += kPlLanes) {
+        f += A.piece_flux[q];
+        v += A.piece_vol[q];
+      }
     }
-    const int32_t dst = s + rank;
-    A.tri_ids[dst] = t;
-    A.piece_flux[dst] = fv.x;
-    A.piece_vol[dst] = fv.y;
+#pragma unroll
+    for (int m = kPlLanes / 2; m >= 1; m >>= 1) {
+      f += __shfl_xor(f, m, kPlLanes);
+      v += __shfl_xor(v, m, kPlLanes);
+    }
+    if (ok && l == 0) {
+      A.cell_flux[c] = f;
+      A.cell_vol[c] = v;
+    }
   });
 }
 
@@ -593,13 +662,13 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t
   }
 }
 
-// Workgroups [0, nb_place): pieces to their ranks; the others: one vertex
-// per thread, its incident list sorted.
+// Workgroups [0, nb_place): pieces to their ranks and the cells' sums; the
+// others: one vertex per thread, its incident list sorted.
 __global__ __launch_bounds__(kT) void k_place_sort(PlaceArgs A, int32_t nb_place, int32_t nv, const int32_t* vt_off,
                                                    int32_t* vt_ids) {
   const int32_t b = blockIdx.x;
   if (b < nb_place) {
-    rank_place(A, b, nb_place);
+    place_sums(A, b, nb_place);
   } else {
     const int32_t v = (b - nb_place) * kT + threadIdx.x;
     if (v < nv) sort_incident(vt_off, vt_ids, v);
@@ -650,11 +719,11 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
   hipLaunchKernelGGL(k_pair_scatter, dim3(nb_pairs), dim3(kT), 0, s, ws->pair_cell, ws->pair_tri, ws->pair_flux,
                      ws->pair_vol, ws->pair_local, ws->offsets, ws->tmp_rec, ws->pair_cap, ws->queue_cap,
                      ws->counters, m, J);
-  PlaceArgs A{ws->tmp_rec, ws->offsets, ws->tri_ids, ws->piece_flux, ws->piece_vol, ws->cell_cap, ws->pair_cap,
-              ws->counters};
+  PlaceArgs A{ws->tmp_rec,    ws->offsets,  ws->tri_ids,  ws->piece_flux, ws->piece_vol,
+              ws->cell_flux,  ws->cell_vol, ws->cell_cap, ws->pair_cap,   ws->counters};
   VstarArgs V{vtx4,       ws->cell_ids, ws->bitmap,  ws->word_off, ws->vb_off,  reinterpret_cast<const double2*>(ws->vb_rec),
               ws->stray,  ws->best_d2,  ws->best_v,  ws->cell_cap, ws->counters};
-  const int32_t nb_place = round_up_xcd(grid_blocks(ws->pair_cap, kT, kStrideBlocks));
+  const int32_t nb_place = round_up_xcd(grid_blocks((int64_t)ws->cell_cap * kPlLanes, kT));
   const int32_t nb_sort = grid_blocks(m.nv, kT);
   const int32_t nb_vstar = round_up_xcd(grid_blocks((int64_t)ws->cell_cap * kVsLanes, kT));
   time_start(ws, FTC_KERNEL_PIECE_RANK, s);

@@ -6,10 +6,9 @@
 // integral of (z - zlo) n_z dA, plus h times the wetted area W of the upper
 // face (F . n vanishes on the lower and side faces).  With F = (0, 0, 1) on
 // the column above the cell, W is the sum of the integrals of n_z dA over
-// all pieces strictly above.  Kernels:
-//   sums   : kSumLanes lanes per interfacial cell, its pieces' integrals
-//            (computed while the cell lists were built) summed in a fixed
-//            order: lane partial sums over the CSR entries, then a butterfly;
+// all pieces strictly above.  The pieces' integrals are computed and summed
+// per cell while the cell lists are built (in a fixed order: lane partial
+// sums over the CSR entries, then a butterfly); here
 //   columns: every (i, j) column walked top down over the interfacial-cell
 //            bitmap, split into z chunks whose flux totals are exchanged in
 //            LDS: alpha = (V + h W) / h^3 in interfacial cells, 0 or 1 in
@@ -19,38 +18,6 @@
 
 namespace ftc {
 namespace {
-
-constexpr int kT = 256;
-constexpr int kSumLanes = 16;
-
-// Per interfacial cell, kSumLanes lanes: lane l sums entries l, l + kSumLanes,
-// ... of the cell's CSR segment, then the lanes' sums are added pairwise.
-// Pieces past the pair capacity were not stored (a latched capacity error).
-__global__ __launch_bounds__(kT) void k_cell_sums(const int32_t* offsets, const double* piece_flux,
-                                                  const double* piece_vol, double* cell_flux, double* cell_vol,
-                                                  int32_t cell_cap, int64_t pair_cap, const int32_t* counters) {
-  const int32_t nif = min(counters[C_NIF], cell_cap);
-  const int64_t gid = (int64_t)blockIdx.x * kT + threadIdx.x;
-  const int64_t ci = gid / kSumLanes;
-  const int l = (int)(gid % kSumLanes);
-  double f = 0.0, v = 0.0;
-  if (ci < nif) {
-    const int64_t e = min((int64_t)offsets[ci + 1], pair_cap);
-    for (int64_t p = offsets[ci] + l; p < e; p += kSumLanes) {
-      f += piece_flux[p];
-      v += piece_vol[p];
-    }
-  }
-#pragma unroll
-  for (int m = kSumLanes / 2; m >= 1; m >>= 1) {
-    f += __shfl_xor(f, m, kSumLanes);
-    v += __shfl_xor(v, m, kSumLanes);
-  }
-  if (ci < nif && l == 0) {
-    cell_flux[ci] = f;
-    cell_vol[ci] = v;
-  }
-}
 
 // Column pass.  A workgroup takes 64 consecutive columns (x) of one y row
 // and splits the z range into kChunks chunks (4, 8 or 16), one wavefront
@@ -193,11 +160,8 @@ __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
 
 hipError_t launch_volume_fraction(const ftc_cells* ws, const Mesh& m, double* alpha_if, double* alpha_dense,
                                   hipStream_t s) {
-  (void)m;  // the pieces and their integrals come from the cell-list build
+  (void)m;  // the pieces' integrals and their per-cell sums come from the cell-list build
   const Grid& g = ws->grid;
-  hipLaunchKernelGGL(k_cell_sums, dim3(grid_blocks((int64_t)ws->cell_cap * kSumLanes, kT)), dim3(kT), 0, s,
-                     ws->offsets, ws->piece_flux, ws->piece_vol, ws->cell_flux, ws->cell_vol, ws->cell_cap,
-                     ws->pair_cap, ws->counters);
   ColArgs A{g, ws->bitmap, ws->word_off, ws->cell_flux, ws->cell_vol, alpha_if, alpha_dense, ws->cell_cap,
             ws->counters};
   time_start(ws, FTC_KERNEL_COLUMNS, s);
