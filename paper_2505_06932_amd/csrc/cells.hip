@@ -22,7 +22,8 @@
 // after another, and neighbouring pieces, corners and vertices share cells,
 // words and vertices: every count and every bitmap bit is taken with one
 // atomic instruction per wavefront in which each distinct counter or word
-// appears once (the lanes grouped by key beforehand).  Every walk over
+// appears once (the lanes grouped by key beforehand, in an LDS hash for
+// counts, by a loop over the few distinct words for bitmap bits).  Every walk over
 // triangles, pairs, vertices or cells gives each XCD a contiguous share, so
 // that the mesh records, bitmap words and list segments that neighbours
 // share meet in one L2.
@@ -68,11 +69,12 @@ __device__ inline int32_t distinct_corner(const Mesh& m, int32_t t, int r) {
 __global__ __launch_bounds__(kT) void k_clear_build(uint32_t* bitmap, int64_t nwords, int32_t* cell_cnt, int64_t ncnt,
                                                    int32_t* counters, Mesh m, double2* vtx4, int32_t* vt_cnt,
                                                    int32_t* vt_loc) {
+  __shared__ CountLDS cl[kT / 64];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t g0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   XcdWalk(3 * (int64_t)m.nt, blockIdx.x, gridDim.x).run([&](int64_t x, bool ok) {
     const int32_t v = ok ? distinct_corner(m, (int32_t)(x / 3), (int)(x % 3)) : -1;
-    const int32_t loc = wave_count_add(vt_cnt, v, v >= 0);
+    const int32_t loc = wave_count_add(vt_cnt, v, v >= 0, cl[threadIdx.x >> 6]);
     if (v >= 0) vt_loc[x] = loc;
   });
   for (int64_t v = g0; v < m.nv; v += stride) {
@@ -309,6 +311,8 @@ __global__ __launch_bounds__(kT) void k_pair_count(int32_t* pair_lin, int32_t* p
                                                   const int32_t* word_off, int32_t* cell_cnt, int32_t cell_cap,
                                                   int64_t pair_cap, int64_t queue_cap, int32_t* counters, Grid g,
                                                   VertexBins B) {
+  __shared__ CountLDS cl[kT / 64];
+  CountLDS& L = cl[threadIdx.x >> 6];
   const PairRange R = pair_range(counters, pair_cap, queue_cap);
   XcdWalk(B.nv, blockIdx.x, gridDim.x).run([&](int64_t v, bool ok) {
     int32_t ci = -2;
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(kT) void k_pair_count(int32_t* pair_lin, int32_t* p
         if (ci >= cell_cap) ci = -1;
       }
     }
-    const int32_t loc = wave_count_add(B.vb_cnt, ci, ci >= 0);
+    const int32_t loc = wave_count_add(B.vb_cnt, ci, ci >= 0, L);
     if (ok) {
       if (ci >= 0)
         B.vb_loc[v] = loc;
@@ -337,7 +341,7 @@ __global__ __launch_bounds__(kT) void k_pair_count(int32_t* pair_lin, int32_t* p
       ci = rank_of(bitmap, word_off, lin);
       if (ci >= cell_cap) ci = -1;  // its cell did not fit the capacity (latched while listing the cells)
     }
-    const int32_t loc = wave_count_add(cell_cnt, ci, ci >= 0);
+    const int32_t loc = wave_count_add(cell_cnt, ci, ci >= 0, L);
     if (lin >= 0) {
       pair_lin[p] = ci;
       if (ci >= 0) pair_local[p] = loc;

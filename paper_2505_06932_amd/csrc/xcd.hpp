@@ -40,32 +40,45 @@ struct XcdWalk {
   }
 };
 
+// LDS a wavefront lends wave_count_add: a 128-slot hash of keys, the count
+// and the counter's old value per slot.
+constexpr int kCountSlots = 128;
+struct CountLDS {
+  int32_t key[kCountSlots], cnt[kCountSlots], base[kCountSlots];
+};
+
 // atomicAdd(&ctr[key], 1) for every lane with act: a lane gets the
-// counter's old value plus the number of lanes below it with the same key,
-// i.e. a distinct index per lane as with one atomic each (in another order
-// among equal keys).  Lanes of one atomic instruction that hit the same
-// address are served one after another, so the wavefront first groups its
-// lanes by key (register work only) and then issues a single atomic
-// instruction in which the lowest lane of each group adds the group's size.
-// Called by all 64 lanes.
-__device__ inline int32_t wave_count_add(int32_t* ctr, int32_t key, bool act) {
+// counter's old value plus its rank among the lanes with the same key, i.e.
+// a distinct index per lane as with one atomic each (in another order among
+// equal keys).  Lanes of one atomic instruction that hit the same address
+// are served one after another, so the lanes are grouped by key first: each
+// claims its key's slot in an LDS hash (open addressing, at most 64 keys in
+// 128 slots) and takes its rank there by an LDS atomic; then the first lane
+// of each group adds the group's size to the counter, all groups in one
+// atomic instruction.  Called by all 64 lanes, with L owned by the
+// wavefront.
+__device__ inline int32_t wave_count_add(int32_t* ctr, int32_t key, bool act, CountLDS& L) {
   const int lane = threadIdx.x & 63;
-  uint64_t pend = __ballot(act);
-  int leader_of = lane, below = 0, cnt = 0;
-  while (pend) {
-    const int leader = __builtin_ctzll(pend);
-    const int32_t k = __builtin_amdgcn_readlane(key, leader);
-    const uint64_t same = __ballot(key == k) & pend;
-    if ((same >> lane) & 1ull) {
-      leader_of = leader;
-      below = __popcll(same & ((1ull << lane) - 1ull));
+  L.key[lane] = -1;
+  L.key[lane + 64] = -1;
+  L.cnt[lane] = 0;
+  L.cnt[lane + 64] = 0;
+  __builtin_amdgcn_wave_barrier();
+  int slot = 0, rank = 0;
+  if (act) {
+    int s = (int)(((uint32_t)key * 2654435761u) >> 25);
+    for (int p = 0; p < kCountSlots; ++p) {
+      const int32_t prev = atomicCAS(&L.key[s], -1, key);
+      if (prev == -1 || prev == key) break;
+      s = (s + 1) & (kCountSlots - 1);
     }
-    if (lane == leader) cnt = __popcll(same);
-    pend &= ~same;
+    slot = s;
+    rank = atomicAdd(&L.cnt[slot], 1);
   }
-  int32_t old = 0;
-  if (cnt > 0) old = atomicAdd(&ctr[key], cnt);
-  return __shfl(old, leader_of, 64) + below;
+  __builtin_amdgcn_wave_barrier();
+  if (act && rank == 0) L.base[slot] = atomicAdd(&ctr[key], L.cnt[slot]);
+  __builtin_amdgcn_wave_barrier();
+  return act ? L.base[slot] + rank : 0;
 }
 
 // Sets bit `bit` of word `word` of a bitmap for every lane with act.  The

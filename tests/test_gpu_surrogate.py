@@ -7,19 +7,21 @@ Bars:
   * closest-vertex flags and the fallback count: exact;
   * network outputs: the oracle rounds to bfloat16 at the same points but sums
     in double precision, the kernels in single precision on the matrix cores.
-    A hidden activation whose single-precision pre-image lies within that
-    rounding (about 1e-6 relative) of a bfloat16 rounding boundary can round
-    the other way, which moves the output by about one bfloat16 unit of that
-    activation times two weights (a few 1e-4 with weights of order 0.3 and
-    units near 1); most outputs agree to 1e-6.  Bar: every |dy| <= 5e-3 and
-    the median <= 1e-5.
+    A hidden activation whose device value may lie on the other side of a
+    bfloat16 rounding boundary (within the single-precision error bound of
+    its pre-activation and of the tanh) can round the other way.  Bar: every
+    output equals the oracle's within the last layer's single-precision
+    rounding bound, or, for a row with such ambiguous units, equals within
+    that bound the oracle's output for some choice of their roundings (all
+    choices enumerated, both layers); any other difference fails.
   * gradients: every component within 2e-3 of the largest, loss to 1e-4
     relative (the same rounding points; sums in another order);
   * Adam: parameters to 1e-6 absolute (single-precision arithmetic of one
     update of size lr);
   * learned curvature: cells whose spread is not within 1e-3 of the bound
     take the same decision; the PPIC fallback's curvature to 1e-10 relative;
-    the surrogate's kappa h to the network bar above.
+    the surrogate's kappa h and spread within the ranges the admissible
+    roundings allow.
 """
 import sys
 

@@ -20,10 +20,10 @@ import oracle
 from paper_2505_06932_amd import inputs as I
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SAN_ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:halt_on_error=1",
+# verify_asan_link_order=0: the environment may preload a library ahead of
+# the sanitizer runtime, which the runtime otherwise refuses
+SAN_ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:halt_on_error=1:verify_asan_link_order=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
-# the sanitizer runtime must not inherit a preload from the environment
-SAN_ENV.pop("LD_PRELOAD", None)
 
 
 def _run(cmd, **kw):
