@@ -193,7 +193,9 @@ ftc_status ftc_ppic_curvature(const ftc_cells* cells, const ftc_grid* grid, cons
    call to about 1e-13, not bit for bit) and the area and curvature add an
    8-node rule between the breakpoints in the first direction.  NaN for a
    cell whose fit failed, and kappa_cell and
-   normal_cell NaN where the paraboloid does not cross the cell.
+   normal_cell NaN where the paraboloid does not cross the cell (and where
+   rounding would split the surface inside the cell into more than four
+   runs of eta intervals, which exact arithmetic excludes).
    FTC_EINVAL unless ftc_ppic_curvature (not the learned curvature) ran after
    the last ftc_build_cell_lists. */
 ftc_status ftc_paraboloid_cell(const ftc_cells* cells, const ftc_grid* grid, const double* coeff,

@@ -271,12 +271,19 @@ __device__ void eta_integrals(const Local& L, const Nodes& N, double xi, double 
       out[4] -= 2.0 * r * pem;
       out[5] += 2.0 * r;
       const bool extend = nrun > 0 && rlast == a;
+      if (!extend && nrun == kRuns) {
+        // a fifth run (not possible in exact arithmetic): reported, not
+        // folded into a neighbouring run -- the cell's curvature and normal
+        // become NaN
+        out[1] = NAN;
+        out[5] = NAN;
+      }
       const int slot = extend ? nrun - 1 : min(nrun, kRuns - 1);
 #pragma unroll
       for (int k = 0; k < kRuns; ++k) {
         if (k != slot) continue;
         if (!extend && nrun < kRuns) ra[k] = a;
-        rc[k] = c;  // a run beyond the last slot (not possible in exact arithmetic) extends it
+        rc[k] = c;
       }
       if (!extend) nrun = min(nrun + 1, kRuns);
       rlast = c;
