@@ -379,7 +379,7 @@ def ppic_roofline(res, kern_ms, workload):
             t = json.load(f)
         if t.get("source_digest") == digest:
             traffic = t.get("bytes_per_launch")
-    return {"kernel": "ppic_curvature: k_ppic_fast8 + k_ppic_wide",
+    return {"kernel": "ppic_curvature: k_ppic_fast8 (or its four-wavefront build k_ppic_fast8_w4 on small fronts) + k_ppic_wide",
             "bound": "alu", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 5), "traffic": traffic,
             "flop_per_launch": flops, "avg_launch_ms": kern_ms["ppic"], "source_digest": digest}
