@@ -64,12 +64,23 @@ __device__ inline D3 cross(D3 a, D3 b) { return D3{a.y * b.z - a.z * b.y, a.z * 
 __device__ inline int corner_of(int4 t, int32_t v) { return t.x == v ? 0 : (t.y == v ? 1 : 2); }
 __device__ inline int32_t corner(int4 t, int k) { return k == 0 ? t.x : (k == 1 ? t.y : t.z); }
 
-// The triangle of v's fan whose corner before v is w (the half-edge w -> v), or -1.
+constexpr int kFanBatch = 4;  // incidences of a fan loaded together
+
+// The triangle of v's fan whose corner before v is w (the half-edge w -> v),
+// or -1 (the first in list order); the fan read kFanBatch incidences at a
+// time, their loads issued together.
 __device__ inline int32_t twin_in_fan(const RoughArgs& A, int32_t v, int32_t w) {
-  for (int32_t e = A.vt_off[v]; e < A.vt_off[v + 1]; ++e) {
-    const int32_t t = A.vt_ids[e];
-    const int4 c = A.tri4[t];
-    if (corner(c, (corner_of(c, v) + 2) % 3) == w) return t;
+  const int32_t e1 = A.vt_off[v + 1];
+  for (int32_t b = A.vt_off[v]; b < e1; b += kFanBatch) {
+    int32_t t[kFanBatch];
+#pragma unroll
+    for (int j = 0; j < kFanBatch; ++j) t[j] = b + j < e1 ? A.vt_ids[b + j] : -1;
+    int4 c[kFanBatch];
+#pragma unroll
+    for (int j = 0; j < kFanBatch; ++j) c[j] = t[j] >= 0 ? A.tri4[t[j]] : make_int4(-1, -1, -1, -1);
+#pragma unroll
+    for (int j = 0; j < kFanBatch; ++j)
+      if (t[j] >= 0 && corner(c[j], (corner_of(c[j], v) + 2) % 3) == w) return t[j];
   }
   return -1;
 }
@@ -277,9 +288,9 @@ __device__ inline bool before(int32_t f, uint32_t hf, int32_t h, uint32_t hh) {
   return hf < hh || (hf == hh && f < h);
 }
 
-// Whether a pending edge ordered before h has u as an end (u is an end or a
-// one-ring vertex of an end of h).
-__device__ inline bool blocked_at(const SmoothArgs& S, int32_t u, int32_t h) {
+// A pending edge ordered before h with u as an end (u is an end or a
+// one-ring vertex of an end of h), or -1.
+__device__ inline int32_t blocker_at(const SmoothArgs& S, int32_t u, int32_t h) {
   const uint32_t hh = fmix32((uint32_t)h);
   const RoughArgs& A = S.R;
   for (int32_t f = A.vt_off[u]; f < A.vt_off[u + 1]; ++f) {
@@ -293,18 +304,22 @@ __device__ inline bool blocked_at(const SmoothArgs& S, int32_t u, int32_t h) {
       const int32_t id = 3 * t + ks[q];
       if (id != h && corner(c, ks[q]) < corner(c, (ks[q] + 1) % 3) && S.estate[id] == E_PENDING &&
           before(id, fmix32((uint32_t)id), h, hh))
-        return true;
+        return id;
     }
   }
-  return false;
+  return -1;
 }
 
 // One round's selection over the flagged edges: a pair of adjacent lanes per
 // edge (edge i0/2, then + stride/2, ...), the even lane testing the end a and
 // its one-ring, the odd lane the end b and its one-ring; true if any edge is
 // still pending.  Both lanes of a pair read the same edge and state, so they
-// follow the same path up to the exchange of their results.
-__device__ bool select_edges(const SmoothArgs& S, int32_t i0, int32_t stride) {
+// follow the same path up to the exchange of their results.  Each lane of
+// the first kBlockMemo edges remembers the edge that blocked it (memo, in
+// LDS, -1 for none): while that edge is still pending the test is settled
+// by one load, and the one-ring is searched again only once it is done.
+constexpr int kBlockMemo = 4096;
+__device__ bool select_edges(const SmoothArgs& S, int32_t i0, int32_t stride, int32_t* memo) {
   const RoughArgs& A = S.R;
   const int32_t n = min(A.counters[C_RFLAG], 3 * A.nt);
   const int side = i0 & 1;
@@ -313,14 +328,21 @@ __device__ bool select_edges(const SmoothArgs& S, int32_t i0, int32_t stride) {
     const int32_t h = S.elist[i];
     if (S.estate[h] != E_PENDING) continue;
     pending = true;
-    int32_t a, b;
-    edge_ends(A, h, a, b);
-    const int32_t v = side ? b : a;
-    bool blocked = blocked_at(S, v, h);
-    for (int32_t e = A.vt_off[v]; !blocked && e < A.vt_off[v + 1]; ++e) {
-      const int4 c = A.tri4[A.vt_ids[e]];
-      blocked = blocked_at(S, corner(c, (corner_of(c, v) + 1) % 3), h);
+    const bool kept = i < kBlockMemo;
+    int32_t bf = kept ? memo[2 * i + side] : -1;
+    if (bf >= 0 && S.estate[bf] != E_PENDING) bf = -1;
+    if (bf < 0) {
+      int32_t a, b;
+      edge_ends(A, h, a, b);
+      const int32_t v = side ? b : a;
+      bf = blocker_at(S, v, h);
+      for (int32_t e = A.vt_off[v]; bf < 0 && e < A.vt_off[v + 1]; ++e) {
+        const int4 c = A.tri4[A.vt_ids[e]];
+        bf = blocker_at(S, corner(c, (corner_of(c, v) + 1) % 3), h);
+      }
     }
+    if (kept) memo[2 * i + side] = bf;
+    bool blocked = bf >= 0;
     blocked = (__shfl_xor((int)blocked, 1, 64) != 0) || blocked;
     // the decision reads only pending states, so selections within the
     // round cannot change it; they are marked after the round's reads
@@ -329,19 +351,37 @@ __device__ bool select_edges(const SmoothArgs& S, int32_t i0, int32_t stride) {
   return pending;
 }
 
-// Sum of the one-ring positions of v without w, the ring size, and A_v.
+// Sum of the one-ring positions of v without w, the ring size, and A_v, in
+// list order; the fan read kFanBatch incidences at a time, each level of
+// loads (list entries, triangle records, positions) issued together.
 __device__ inline void ring_sums(const RoughArgs& A, int32_t v, int32_t w, D3& s, int32_t& n, D3& Av) {
   const D3 xv = pos(A, v);
   s = D3{0.0, 0.0, 0.0};
   Av = D3{0.0, 0.0, 0.0};
-  n = A.vt_off[v + 1] - A.vt_off[v];
-  for (int32_t e = A.vt_off[v]; e < A.vt_off[v + 1]; ++e) {
-    const int4 c = A.tri4[A.vt_ids[e]];
-    const int k = corner_of(c, v);
-    const int32_t p = corner(c, (k + 1) % 3), q = corner(c, (k + 2) % 3);
-    const D3 xp = pos(A, p);
-    if (p != w) s = add(s, xp);
-    Av = add(Av, cross(sub(xp, xv), sub(pos(A, q), xv)));
+  const int32_t e0 = A.vt_off[v], e1 = A.vt_off[v + 1];
+  n = e1 - e0;
+  for (int32_t b = e0; b < e1; b += kFanBatch) {
+    int32_t t[kFanBatch];
+#pragma unroll
+    for (int j = 0; j < kFanBatch; ++j) t[j] = b + j < e1 ? A.vt_ids[b + j] : -1;
+    int4 c[kFanBatch];
+#pragma unroll
+    for (int j = 0; j < kFanBatch; ++j) c[j] = t[j] >= 0 ? A.tri4[t[j]] : make_int4(v, v, v, 0);
+    D3 xp[kFanBatch], xq[kFanBatch];
+    int32_t p[kFanBatch];
+#pragma unroll
+    for (int j = 0; j < kFanBatch; ++j) {
+      const int k = corner_of(c[j], v);
+      p[j] = corner(c[j], (k + 1) % 3);
+      xp[j] = pos(A, p[j]);
+      xq[j] = pos(A, corner(c[j], (k + 2) % 3));
+    }
+#pragma unroll
+    for (int j = 0; j < kFanBatch; ++j) {
+      if (t[j] < 0) continue;
+      if (p[j] != w) s = add(s, xp[j]);
+      Av = add(Av, cross(sub(xp[j], xv), sub(xq[j], xv)));
+    }
   }
 }
 
@@ -410,10 +450,12 @@ constexpr int kRoundT = 1024;
 __global__ __launch_bounds__(kRoundT) void k_rounds(SmoothArgs S, double* xo, double* yo, double* zo,
                                                     int32_t max_rounds) {
   __shared__ int32_t pending;
+  __shared__ int32_t memo[2 * kBlockMemo];
+  for (int32_t i = threadIdx.x; i < 2 * kBlockMemo; i += blockDim.x) memo[i] = -1;
   for (int32_t r = 0; r < max_rounds; ++r) {
     if (threadIdx.x == 0) pending = 0;
     __syncthreads();
-    if (select_edges(S, threadIdx.x, blockDim.x)) atomicOr(&pending, 1);
+    if (select_edges(S, threadIdx.x, blockDim.x, memo)) atomicOr(&pending, 1);
     __syncthreads();
     if (pending == 0) break;
     apply_edges(S, xo, yo, zo, threadIdx.x, blockDim.x);
