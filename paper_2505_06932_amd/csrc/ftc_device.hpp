@@ -392,7 +392,9 @@ __host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t
       if (q < 3) L.v[d][q][lane] = T.v[q][d];
     }
   int n = 3, rot = 0;
-#pragma unroll 1
+  // unrolled: the axis and side of every stage are constants, so the
+  // coordinate selects fold away
+#pragma unroll
   for (int stage = 0; stage < 6; ++stage) {
     const int d = stage >> 1;
     const bool upper = stage & 1;
