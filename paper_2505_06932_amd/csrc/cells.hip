@@ -48,7 +48,7 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kStrideBlocks = 2048;
-constexpr int kPieceLanes = 64;  // k_clip_queue: one wavefront per workgroup
+constexpr int kPieceLanes = 64;  // k_clip_mark: one wavefront per workgroup
 
 // Corner r of triangle t if it is a valid vertex index distinct from the
 // triangle's earlier corners, else -1 (a triangle is listed once under each
@@ -572,7 +572,7 @@ struct VstarArgs {
 // (position and index) at a time; every lane a share of the strays; lowest
 // index on ties.  A vertex outside the block is at least 1.5 h from the
 // cell centre, so a best squared distance below (1.5 h)^2 is final (the
-// curvature's ring pass searches all vertices for the other cells).
+// curvature kernel searches all vertices for the other cells).
 // Called with all 64 lanes of the wavefront.
 constexpr int kVsLanes = 8;                            // lanes per cell
 constexpr int kVsNb = (27 + kVsLanes - 1) / kVsLanes;  // block cells per lane

@@ -120,7 +120,7 @@ MIXED_KAPPA_TOL = 1e-9
 def test_mixed_precision_fit_against_double_oracle(oracle, name, seed):
     """Normal equations formed and factored in single precision, refined
     twice with double-precision residuals: the discrete decisions are those
-    of the double-precision path (the ring pass is shared), the curvature
+    of the double-precision path (the rings are built the same way), the curvature
     agrees with the double-precision oracle to 1e-9 relative (the measured
     error is printed), and every cell the oracle solves is solved.  The 64
     ellipsoids on 256^3 are the batched workload this precision is meant
