@@ -124,6 +124,9 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(counters, ftc::C_COUNT);
   FTC_ALLOC(scan_tmp, ftc::kScanMaxBlocks);
   FTC_ALLOC(bitmap, nwords);
+  w.colsum_words = (((int64_t)(grid->nx + ftc::kColBlock - 1) / ftc::kColBlock) * grid->ny *
+                        ((grid->nz + ftc::kSlab - 1) / ftc::kSlab) + 31) / 32;
+  FTC_ALLOC(colsum, w.colsum_words);
   FTC_ALLOC(word_off, nwords + 1);
   FTC_ALLOC(band_off, nwords + 1);
   w.queue_cap = 2 * P + 1024;  // candidates that need clipping can outnumber pieces

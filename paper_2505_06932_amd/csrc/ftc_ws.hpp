@@ -28,6 +28,8 @@ enum : int {
   C_COUNT = 32 + 8 * 32
 };
 constexpr int kQStride = 32;
+constexpr int kColBlock = 64;  // columns along x per bit of the column summary
+constexpr int kSlab = 32;      // planes along z per bit of the column summary
 }  // namespace ftc
 
 namespace ftc {
@@ -61,6 +63,10 @@ struct ftc_cells {
 
   // cell lists
   uint32_t* bitmap;       // [nwords] one bit per grid cell: holds a piece
+  uint32_t* colsum;       // [colsum_words] one bit per (64-column block along x, row j, slab of 32
+                          // planes along z): some cell of it holds a piece; written from the bitmap
+                          // by the volume-fraction call when nx is a multiple of 64
+  int64_t colsum_words;
   int32_t* word_off;      // [nwords+1] exclusive scan of popcount(bitmap)
   int32_t* band_off;      // [nwords+1] the same for the face-neighbour band (CSF band mode)
   // pair list: [0, pair_cap) whole-triangle pieces, [pair_cap, pair_cap +

@@ -9,6 +9,8 @@
 // all pieces strictly above.  The pieces' integrals are computed and summed
 // per cell while the cell lists are built (in a fixed order: lane partial
 // sums over the CSR entries, then a butterfly); here
+//   colsum : one bit per block of 64 columns, row and slab of 32 planes,
+//            set if a cell of it holds a piece (most hold none);
 //   columns: every (i, j) column walked top down over the interfacial-cell
 //            bitmap, split into z chunks whose flux totals are exchanged in
 //            LDS: alpha = (V + h W) / h^3 in interfacial cells, 0 or 1 in
@@ -34,12 +36,14 @@ namespace {
 //      open: ERR_MESH), as must W below the lowest chunk.  Between
 //      interfacial cells the walk only stores.
 constexpr int kColLanes = 64;
+static_assert(kColLanes == kColBlock, "a column block is one block of the column summary");
 constexpr int kSeg = 32;      // cells per segment: one bit mask
 constexpr int kKeepSeg = 8;   // segment masks kept between the two walks (chunks of up to 256 cells)
 
 struct ColArgs {
   Grid g;
   const uint32_t* bitmap;
+  const uint32_t* colsum;  // the column summary, or null
   const int32_t* word_off;
   const double* cell_flux;
   const double* cell_vol;
@@ -70,6 +74,40 @@ __device__ inline uint32_t segment_mask(const ColArgs& A, bool col_ok, int32_t i
   return m;
 }
 
+// The column summary from the occupancy bitmap (nx a multiple of 64): one
+// lane per bitmap word of a row and slab, consecutive lanes on consecutive
+// words of a row (coalesced), each OR-ing its word over the slab's planes
+// (loads issued together); a pair of lanes makes one block of 64 columns,
+// and a ballot over the even lanes packs a wavefront's 32 bits, which are
+// 32 consecutive bits of the summary.
+constexpr int kSumT = 256;
+__global__ __launch_bounds__(kSumT) void k_colsum(Grid g, const uint32_t* bitmap, uint32_t* colsum, int64_t nlanes) {
+  const int64_t wpr = g.nx / 32;  // words per row
+  const int64_t row = (int64_t)g.nx * g.ny / 32;
+  for (int64_t b0 = (int64_t)blockIdx.x * kSumT + (threadIdx.x & ~63); b0 < nlanes;
+       b0 += (int64_t)gridDim.x * kSumT) {
+    const int64_t L = b0 + (threadIdx.x & 63);
+    uint32_t any = 0u;
+    if (L < nlanes) {
+      const int64_t u = L % wpr, rest = L / wpr;
+      const int64_t j = rest % g.ny, k0 = (rest / g.ny) * kSlab;
+      const int64_t base = u + wpr * j;
+      uint32_t w[kSlab];
+#pragma unroll
+      for (int q = 0; q < kSlab; ++q) w[q] = k0 + q < g.nz ? bitmap[base + row * (k0 + q)] : 0u;
+#pragma unroll
+      for (int q = 0; q < kSlab; ++q) any |= w[q];
+    }
+    any |= __shfl_xor(any, 1, 64);
+    const uint64_t bal = __ballot(any != 0u && (threadIdx.x & 1) == 0);
+    // even lane 2q holds bit q of the wavefront's 32
+    uint32_t bits = 0u;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) bits |= (uint32_t)((bal >> (2 * q)) & 1ull) << q;
+    if ((threadIdx.x & 63) == 0 && b0 < nlanes) colsum[b0 >> 6] = bits;
+  }
+}
+
 // Compact id of the interfacial cell lin (-2: beyond the cell capacity, a
 // latched capacity error, taken with no pieces).
 __device__ inline int32_t compact_id(const ColArgs& A, int64_t lin) {
@@ -90,10 +128,24 @@ __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
   const double h = g.h, h2 = h * h, h3 = h * h * h;
   const int64_t col = i + (int64_t)g.nx * j, sz = (int64_t)g.nx * g.ny;
 
+  // a chunk none of whose cells holds a piece (the column summary, one bit
+  // per kSlab planes of this block of columns) skips the bitmap
+  bool empty = false;
+  if (A.colsum) {
+    const int64_t nbx = g.nx / kColBlock;
+    empty = true;
+    for (int32_t kz = klo / kSlab; klo < khi && kz <= (khi - 1) / kSlab; ++kz) {
+      const int64_t cb = ((int64_t)kz * g.ny + j) * nbx + blockIdx.x;
+      if ((A.colsum[cb >> 5] >> (cb & 31)) & 1u) empty = false;
+    }
+  }
+
   // ---- 1. interfacial bits and the chunk's flux total
   uint32_t keep[kKeepSeg];
+#pragma unroll
+  for (int u = 0; u < kKeepSeg; ++u) keep[u] = 0u;
   double tot = 0.0;
-  {
+  if (!empty) {
     int s = 0;
     for (int32_t k1 = khi - 1; k1 >= klo; k1 -= kSeg, ++s) {
       uint32_t m = segment_mask(A, col_ok, i, j, k1, klo);
@@ -124,7 +176,7 @@ __global__ __launch_bounds__(kColLanes* kChunks) void k_columns(ColArgs A) {
 #pragma unroll
       for (int u = 0; u < kKeepSeg; ++u)
         if (u == s) m = keep[u];
-    } else {
+    } else if (!empty) {
       m = segment_mask(A, col_ok, i, j, k1, klo);
     }
     const int nq = min(kSeg, k1 - klo + 1);
@@ -162,7 +214,18 @@ hipError_t launch_volume_fraction(const ftc_cells* ws, const Mesh& m, double* al
                                   hipStream_t s) {
   (void)m;  // the pieces' integrals and their per-cell sums come from the cell-list build
   const Grid& g = ws->grid;
-  ColArgs A{g, ws->bitmap, ws->word_off, ws->cell_flux, ws->cell_vol, alpha_if, alpha_dense, ws->cell_cap,
+  // the summary pays on large grids, where most chunks hold no piece (at
+  // 512^3 the column pass saves 30 us for a 6 us pass over the bitmap; at
+  // 256^3 and below the extra launch costs what it saves)
+  const uint32_t* colsum = nullptr;
+  if (g.nx % kColBlock == 0 && (int64_t)g.nx * g.ny * g.nz >= (int64_t(1) << 26)) {
+    // lanes: words per row x rows x slabs; 32 summary bits per wavefront
+    const int64_t nlanes = (int64_t)(g.nx / 32) * g.ny * ((g.nz + kSlab - 1) / kSlab);
+    hipLaunchKernelGGL(k_colsum, dim3(grid_blocks(nlanes, kSumT, 8192)), dim3(kSumT), 0, s, g, ws->bitmap, ws->colsum,
+                       nlanes);
+    colsum = ws->colsum;
+  }
+  ColArgs A{g, ws->bitmap, colsum, ws->word_off, ws->cell_flux, ws->cell_vol, alpha_if, alpha_dense, ws->cell_cap,
             ws->counters};
   time_start(ws, FTC_KERNEL_COLUMNS, s);
   const dim3 cg((g.nx + kColLanes - 1) / kColLanes, g.ny);
