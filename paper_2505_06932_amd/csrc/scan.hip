@@ -64,14 +64,25 @@ __device__ inline int32_t block_excl_scan(int32_t v, int32_t* total) {
   return r;
 }
 
-// First pass: the total of each block of kScanBlock inputs.
+// Tiles of kScanBlock entries move between global memory and the threads
+// through LDS: global accesses are lane-consecutive (entry q * kThreads +
+// t of the tile for thread t), the scan works on kItems consecutive entries
+// per thread (entries t * kItems + q).  One padding word per 32 spreads a
+// thread's consecutive entries over the LDS banks.
+constexpr int kTilePad = kScanBlock + kScanBlock / 32;
+__device__ inline int tile_ix(int i) { return i + (i >> 5); }
+
+// First pass: the total of each block of kScanBlock inputs (the order of
+// the loads does not matter here).
 template <class L>
 __device__ inline void totals_one(L load, int64_t n, int64_t b, int32_t* slot) {
-  const int64_t base = b * kScanBlock + (int64_t)threadIdx.x * kItems;
+  const int64_t tile = b * kScanBlock;
   int32_t s = 0;
 #pragma unroll
-  for (int q = 0; q < kItems; ++q)
-    if (base + q < n) s += load(base + q);
+  for (int q = 0; q < kItems; ++q) {
+    const int64_t i = tile + q * kThreads + threadIdx.x;
+    if (i < n) s += load(i);
+  }
   int32_t total;
   block_excl_scan(s, &total);
   if (threadIdx.x == 0) *slot = total;
@@ -88,26 +99,39 @@ __device__ inline int32_t block_sum_prefix(const int32_t* tmp, int64_t nb) {
 
 // Second pass for block b of nblocks: the local scan plus the totals of the
 // blocks before it; the last block also writes the grand total to out[n]
-// and *total_out.  In place is allowed (out == input): every thread reads
-// its inputs before writing them.
+// and *total_out.  In place is allowed (out == input): the block reads all
+// of its tile before any thread writes.
 template <class L>
 __device__ inline void apply_one(L load, int64_t n, const int32_t* tmp, int32_t* out, int32_t* total_out, int64_t b,
                                  int64_t nblocks) {
+  __shared__ int32_t st[kTilePad];
   const int32_t prefix = block_sum_prefix(tmp, b);
-  const int64_t base = b * kScanBlock + (int64_t)threadIdx.x * kItems;
+  const int64_t tile = b * kScanBlock;
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    const int i = q * kThreads + threadIdx.x;
+    st[tile_ix(i)] = tile + i < n ? load(tile + i) : 0;
+  }
+  __syncthreads();
   int32_t v[kItems];
   int32_t s = 0;
 #pragma unroll
   for (int q = 0; q < kItems; ++q) {
-    v[q] = (base + q < n) ? load(base + q) : 0;
+    v[q] = st[tile_ix(threadIdx.x * kItems + q)];
     s += v[q];
   }
   int32_t total;
-  int32_t run = block_excl_scan(s, &total) + prefix;
+  int32_t run = block_excl_scan(s, &total) + prefix;  // its barriers end every read of st
 #pragma unroll
   for (int q = 0; q < kItems; ++q) {
-    if (base + q < n) out[base + q] = run;
+    st[tile_ix(threadIdx.x * kItems + q)] = run;
     run += v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    const int i = q * kThreads + threadIdx.x;
+    if (tile + i < n) out[tile + i] = st[tile_ix(i)];
   }
   if (b == nblocks - 1 && threadIdx.x == 0) {
     out[n] = prefix + total;
@@ -152,11 +176,13 @@ __global__ __launch_bounds__(kThreads) void k_block_apply_multi(MultiSeg M, cons
   apply_one(LoadI32{M.seg[q].in}, M.seg[q].n, tmp + M.b0[q], M.seg[q].out, M.seg[q].total, b,
             M.b0[q + 1] - M.b0[q]);
   if (M.seg[q].clear) {
-    // this thread's entries, already read by apply_one
-    const int64_t base = b * kScanBlock + (int64_t)threadIdx.x * kItems;
+    // the block's tile, read in full by apply_one before its barriers
+    const int64_t tile = b * kScanBlock;
 #pragma unroll
-    for (int i = 0; i < kItems; ++i)
-      if (base + i < M.seg[q].n) M.seg[q].clear[base + i] = 0;
+    for (int i = 0; i < kItems; ++i) {
+      const int64_t x = tile + i * kThreads + threadIdx.x;
+      if (x < M.seg[q].n) M.seg[q].clear[x] = 0;
+    }
   }
 }
 
@@ -167,22 +193,30 @@ template <class WL>
 __global__ __launch_bounds__(kThreads) void k_block_apply_emit(WL words, int64_t n, const int32_t* tmp, int32_t* out,
                                                                int32_t* total_out, int64_t nb, int32_t* ids,
                                                                int32_t cap, int32_t* counters) {
+  __shared__ uint32_t st[kTilePad];
   const int64_t b = blockIdx.x;
   const int32_t prefix = block_sum_prefix(tmp, b);
-  const int64_t base = b * kScanBlock + (int64_t)threadIdx.x * kItems;
+  const int64_t tile = b * kScanBlock;
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    const int i = q * kThreads + threadIdx.x;
+    st[tile_ix(i)] = tile + i < n ? words.word(tile + i) : 0u;
+  }
+  __syncthreads();
+  const int64_t base = tile + (int64_t)threadIdx.x * kItems;
   uint32_t wv[kItems];
   int32_t s = 0;
 #pragma unroll
   for (int q = 0; q < kItems; ++q) {
-    wv[q] = (base + q < n) ? words.word(base + q) : 0u;
+    wv[q] = st[tile_ix(threadIdx.x * kItems + q)];
     s += __popc(wv[q]);
   }
   int32_t total;
-  int32_t run = block_excl_scan(s, &total) + prefix;
+  int32_t run = block_excl_scan(s, &total) + prefix;  // its barriers end every read of st
   bool over = false;
 #pragma unroll
   for (int q = 0; q < kItems; ++q) {
-    if (base + q < n) out[base + q] = run;
+    st[tile_ix(threadIdx.x * kItems + q)] = (uint32_t)run;
     uint32_t bits = wv[q];
     while (bits) {
       const int bit = __ffs(bits) - 1;
@@ -195,6 +229,12 @@ __global__ __launch_bounds__(kThreads) void k_block_apply_emit(WL words, int64_t
     }
   }
   if (over) atomicOr(&counters[C_ERR], ERR_CAPACITY);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kItems; ++q) {
+    const int i = q * kThreads + threadIdx.x;
+    if (tile + i < n) out[tile + i] = (int32_t)st[tile_ix(i)];
+  }
   if (b == nb - 1 && threadIdx.x == 0) {
     out[n] = prefix + total;
     if (total_out) *total_out = prefix + total;
