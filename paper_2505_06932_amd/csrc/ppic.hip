@@ -50,11 +50,11 @@
 #include <algorithm>
 
 #include "ftc_ws.hpp"
+#include "xcd.hpp"
 
 namespace ftc {
 namespace {
 
-constexpr int kXCD = 8;          // accelerator complex dies; workgroups are dealt to them in turn
 constexpr int kWideBlocks = 64;  // persistent workgroups of the wide shape
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
