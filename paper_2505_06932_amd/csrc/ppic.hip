@@ -112,10 +112,19 @@ __device__ inline uint64_t gballot(bool p, int grp) {
     return (b >> (G * grp)) & ((1ull << G) - 1ull);
 }
 
+// Maximum of a non-negative value over the wavefront, in every lane: DPP
+// steps within each row of 16 lanes (swap neighbours, swap pairs, mirror
+// the halves, mirror the row), the row broadcasts (lane 15 into rows 1 and
+// 3, then lane 31 into rows 2 and 3; other rows take 0), then lane 63.
+// Called with every lane of the wavefront active.
 __device__ inline int wave_max_i(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false));
+  return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Lane permutations within rows of 16 lanes (data-parallel primitives):
