@@ -168,25 +168,45 @@ __device__ inline float group_sum_f(float v) {
   return v;
 }
 
-// Integer sum over each aligned group of G lanes.
+template <int CTRL>
+__device__ inline int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+// Integer sum over each aligned group of G lanes (the steps of group_sum).
 template <int G>
 __device__ inline int group_sum_i(int v) {
-#pragma unroll
-  for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  if constexpr (G >= 2) v += dpp_i<0xB1>(v);
+  if constexpr (G >= 4) v += dpp_i<0x4E>(v);
+  if constexpr (G >= 8) v += dpp_i<0x141>(v);
+  if constexpr (G >= 16) v += dpp_i<0x140>(v);
+  if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
 // Exclusive prefix sum over the lanes of each aligned group of G lanes (gl
 // the lane's index in its group), and the group's total in *total.
+// Groups of up to 16 lanes shift within rows of 16 lanes (DPP row_shr);
+// a lane takes a shifted value only from its own group.  Called with every
+// lane of the wavefront active.
 template <int G>
 __device__ inline int group_excl_scan(int v, int gl, int* total) {
   int inc = v;
+  if constexpr (G <= 16) {
+    if constexpr (G >= 2) { const int t = dpp_i<0x111>(inc); if (gl >= 1) inc += t; }
+    if constexpr (G >= 4) { const int t = dpp_i<0x112>(inc); if (gl >= 2) inc += t; }
+    if constexpr (G >= 8) { const int t = dpp_i<0x114>(inc); if (gl >= 4) inc += t; }
+    if constexpr (G >= 16) { const int t = dpp_i<0x118>(inc); if (gl >= 8) inc += t; }
+    *total = group_sum_i<G>(v);
+  } else {
 #pragma unroll
-  for (int o = 1; o < G; o <<= 1) {
-    const int t = __shfl_up(inc, o, G);
-    if (gl >= o) inc += t;
+    for (int o = 1; o < G; o <<= 1) {
+      const int t = __shfl_up(inc, o, G);
+      if (gl >= o) inc += t;
+    }
+    *total = __shfl(inc, G - 1, G);
   }
-  *total = __shfl(inc, G - 1, G);
   return inc - v;
 }
 
