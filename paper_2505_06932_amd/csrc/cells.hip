@@ -40,6 +40,7 @@
 #include <float.h>
 #include <limits.h>
 
+#include "dpp.hpp"
 #include "ftc_ws.hpp"
 #include "xcd.hpp"
 
@@ -101,12 +102,7 @@ template <int NT>
 __device__ inline int64_t block_alloc(int32_t v, int32_t* counter, int32_t* sh) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int32_t incl = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int32_t o = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += o;
-  }
+  const int32_t incl = wave_incl_scan_dpp(v);
   if (lane == 63) sh[wid] = incl;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -191,12 +187,7 @@ __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, con
   if (threadIdx.x < 64) {
     // offsets of the mask groups and one allocation for the workgroup
     const int32_t v = qoff[threadIdx.x];
-    int32_t incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int32_t o = __shfl_up(incl, d, 64);
-      if ((int)threadIdx.x >= d) incl += o;
-    }
+    const int32_t incl = wave_incl_scan_dpp(v);
     qoff[threadIdx.x] = incl - v;
     if (threadIdx.x == 63) qbase = incl > 0 ? atomicAdd(&counters[C_NQUEUE], incl) : 0;
   }
@@ -504,11 +495,18 @@ __device__ inline void place_sums(const PlaceArgs& A, int64_t group, int64_t ngr
         v += A.piece_vol[q];
       }
     }
-#pragma unroll
-    for (int m = kPlLanes / 2; m >= 1; m >>= 1) {
-      f += __shfl_xor(f, m, kPlLanes);
-      v += __shfl_xor(v, m, kPlLanes);
-    }
+    // the lanes' sums added pairwise: rotations by 8, 4, 2 and 1 lanes pair
+    // exactly the lanes of a butterfly over the 16, since after each step a
+    // lane's value equals that of the lanes the finer steps reach
+    static_assert(kPlLanes == 16, "one row of 16 lanes per cell");
+    f += dpp_d<kDppRor + 8>(f);
+    v += dpp_d<kDppRor + 8>(v);
+    f += dpp_d<kDppRor + 4>(f);
+    v += dpp_d<kDppRor + 4>(v);
+    f += dpp_d<kDppRor + 2>(f);
+    v += dpp_d<kDppRor + 2>(v);
+    f += dpp_d<kDppRor + 1>(f);
+    v += dpp_d<kDppRor + 1>(v);
     if (ok && l == 0) {
       A.cell_flux[c] = f;
       A.cell_vol[c] = v;
@@ -651,10 +649,23 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t
     }
     for (int32_t q = l; q < nstray; q += kVsLanes) consider(A.vtx4, A.stray[q], xc, bd, bv);
   }
-#pragma unroll
-  for (int o = kVsLanes / 2; o >= 1; o >>= 1) {
-    const double od = __shfl_xor(bd, o, 64);
-    const int32_t ov = __shfl_xor(bv, o, 64);
+  // the minimum over the cell's 8 lanes (exact, so any pairing serves)
+  static_assert(kVsLanes == 8, "8 lanes per cell");
+  {
+    double od = dpp_d<kDppSwap1>(bd);
+    int32_t ov = dpp_i<kDppSwap1>(bv);
+    if (lex_less(od, ov, bd, bv)) {
+      bd = od;
+      bv = ov;
+    }
+    od = dpp_d<kDppSwap2>(bd);
+    ov = dpp_i<kDppSwap2>(bv);
+    if (lex_less(od, ov, bd, bv)) {
+      bd = od;
+      bv = ov;
+    }
+    od = dpp_d<kDppHalfMirror>(bd);
+    ov = dpp_i<kDppHalfMirror>(bv);
     if (lex_less(od, ov, bd, bv)) {
       bd = od;
       bv = ov;

@@ -50,6 +50,7 @@
 #include <algorithm>
 
 #include "ftc_ws.hpp"
+#include "dpp.hpp"
 #include "xcd.hpp"
 
 namespace ftc {
@@ -112,74 +113,39 @@ __device__ inline uint64_t gballot(bool p, int grp) {
     return (b >> (G * grp)) & ((1ull << G) - 1ull);
 }
 
-// Maximum of a non-negative value over the wavefront, in every lane: DPP
-// steps within each row of 16 lanes (swap neighbours, swap pairs, mirror
-// the halves, mirror the row), the row broadcasts (lane 15 into rows 1 and
-// 3, then lane 31 into rows 2 and 3; other rows take 0), then lane 63.
-// Called with every lane of the wavefront active.
-__device__ inline int wave_max_i(int v) {
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false));
-  return __builtin_amdgcn_readlane(v, 63);
-}
-
-// Lane permutations within rows of 16 lanes (data-parallel primitives):
-// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror.
-template <int CTRL>
-__device__ inline double dpp_d(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
-  return __hiloint2double(h2, l2);
-}
-
 // Sum over each aligned group of G lanes, the same bits in every lane: each
 // step adds a value from a partner lane that adds this lane's value back.
 // Called with all 64 lanes active.
 template <int G>
 __device__ inline double group_sum(double v) {
-  if constexpr (G >= 2) v += dpp_d<0xB1>(v);
-  if constexpr (G >= 4) v += dpp_d<0x4E>(v);
-  if constexpr (G >= 8) v += dpp_d<0x141>(v);
-  if constexpr (G >= 16) v += dpp_d<0x140>(v);
+  if constexpr (G >= 2) v += dpp_d<kDppSwap1>(v);
+  if constexpr (G >= 4) v += dpp_d<kDppSwap2>(v);
+  if constexpr (G >= 8) v += dpp_d<kDppHalfMirror>(v);
+  if constexpr (G >= 16) v += dpp_d<kDppMirror>(v);
   if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
   if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
-}
-
-template <int CTRL>
-__device__ inline float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
 // group_sum in single precision
 template <int G>
 __device__ inline float group_sum_f(float v) {
-  if constexpr (G >= 2) v += dpp_f<0xB1>(v);
-  if constexpr (G >= 4) v += dpp_f<0x4E>(v);
-  if constexpr (G >= 8) v += dpp_f<0x141>(v);
-  if constexpr (G >= 16) v += dpp_f<0x140>(v);
+  if constexpr (G >= 2) v += dpp_f<kDppSwap1>(v);
+  if constexpr (G >= 4) v += dpp_f<kDppSwap2>(v);
+  if constexpr (G >= 8) v += dpp_f<kDppHalfMirror>(v);
+  if constexpr (G >= 16) v += dpp_f<kDppMirror>(v);
   if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
   if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
-template <int CTRL>
-__device__ inline int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-
 // Integer sum over each aligned group of G lanes (the steps of group_sum).
 template <int G>
 __device__ inline int group_sum_i(int v) {
-  if constexpr (G >= 2) v += dpp_i<0xB1>(v);
-  if constexpr (G >= 4) v += dpp_i<0x4E>(v);
-  if constexpr (G >= 8) v += dpp_i<0x141>(v);
-  if constexpr (G >= 16) v += dpp_i<0x140>(v);
+  if constexpr (G >= 2) v += dpp_i<kDppSwap1>(v);
+  if constexpr (G >= 4) v += dpp_i<kDppSwap2>(v);
+  if constexpr (G >= 8) v += dpp_i<kDppHalfMirror>(v);
+  if constexpr (G >= 16) v += dpp_i<kDppMirror>(v);
   if constexpr (G >= 32) v += __shfl_xor(v, 16, 64);
   if constexpr (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
@@ -194,10 +160,10 @@ template <int G>
 __device__ inline int group_excl_scan(int v, int gl, int* total) {
   int inc = v;
   if constexpr (G <= 16) {
-    if constexpr (G >= 2) { const int t = dpp_i<0x111>(inc); if (gl >= 1) inc += t; }
-    if constexpr (G >= 4) { const int t = dpp_i<0x112>(inc); if (gl >= 2) inc += t; }
-    if constexpr (G >= 8) { const int t = dpp_i<0x114>(inc); if (gl >= 4) inc += t; }
-    if constexpr (G >= 16) { const int t = dpp_i<0x118>(inc); if (gl >= 8) inc += t; }
+    if constexpr (G >= 2) { const int t = dpp_i<kDppShr + 1>(inc); if (gl >= 1) inc += t; }
+    if constexpr (G >= 4) { const int t = dpp_i<kDppShr + 2>(inc); if (gl >= 2) inc += t; }
+    if constexpr (G >= 8) { const int t = dpp_i<kDppShr + 4>(inc); if (gl >= 4) inc += t; }
+    if constexpr (G >= 16) { const int t = dpp_i<kDppShr + 8>(inc); if (gl >= 8) inc += t; }
     *total = group_sum_i<G>(v);
   } else {
 #pragma unroll
@@ -1004,7 +970,7 @@ template <class C>
 __device__ inline void expand_vertex(const PPICArgs& A, FastMem& M, int32_t u, int32_t off, int deg, int gl,
                                      int& nV, bool& full) {
   constexpr int G = C::G, IB = C::IB;
-  const int md = wave_max_i(deg);
+  const int md = wave_max_dpp(deg);
   for (int j0 = 0; j0 < md; j0 += IB) {
     int32_t tt[IB];
 #pragma unroll
@@ -1041,7 +1007,7 @@ __device__ inline void expand_vertex(const PPICArgs& A, FastMem& M, int32_t u, i
 template <class C>
 __device__ inline void ring_vertex(const PPICArgs& A, FastMem& M, int32_t u, int32_t off, int deg, int gl, int& nT) {
   constexpr int G = C::G, IB = C::IB;
-  const int md = wave_max_i(deg);
+  const int md = wave_max_dpp(deg);
   for (int j0 = 0; j0 < md; j0 += IB) {
     int32_t tt[IB];
 #pragma unroll
@@ -1124,7 +1090,7 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
     {
       const int32_t o0 = ok ? A.vt_off[vs] : 0;
       const int deg0 = ok ? A.vt_off[vs + 1] - o0 : 0;
-      const int nr = wave_max_i((deg0 + G - 1) / G);
+      const int nr = wave_max_dpp((deg0 + G - 1) / G);
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
       for (int k = 0; k < nr; ++k) {
         const int i = k * G + gl;
@@ -1136,7 +1102,7 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
         const double cx = uy * wz - uz * wy;
         const double cy = uz * wx - ux * wz;
         const double cz = ux * wy - uy * wx;
-        const int qn = wave_max_i(min(max(deg0 - k * G, 0), G));  // lanes holding a triangle, at most
+        const int qn = wave_max_dpp(min(max(deg0 - k * G, 0), G));  // lanes holding a triangle, at most
 #pragma unroll 4
         for (int qq = 0; qq < qn; ++qq) {
           const double x = __shfl(cx, qq, G), y = __shfl(cy, qq, G), z = __shfl(cz, qq, G);
@@ -1178,7 +1144,7 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
       const int lo = nVprev, hi = nV;
       nVprev = nV;
       const bool go = ok && !ovf;
-      const int rounds = wave_max_i(go ? (hi - lo + G - 1) / G : 0);
+      const int rounds = wave_max_dpp(go ? (hi - lo + G - 1) / G : 0);
       for (int k = 0; k < rounds; ++k) {
         const int p = lo + k * G + gl;
         const bool have = go && p < hi;
@@ -1196,7 +1162,7 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
     {
       const bool go = ok && !ovf;
       const int nVc = go ? nV : 0;
-      const int rounds = wave_max_i((nVc + G - 1) / G);
+      const int rounds = wave_max_dpp((nVc + G - 1) / G);
       for (int k = 0; k < rounds; ++k) {
         const int p = k * G + gl;
         const bool have = p < nVc;
@@ -1226,7 +1192,7 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
     const int nTc = fit ? nT : 0;
     const double delta = A.prm.delta_over_h * h;
     const double lim = delta * delta, inv_delta = 1.0 / delta;
-    const int frounds = wave_max_i((nTc + G - 1) / G);
+    const int frounds = wave_max_dpp((nTc + G - 1) / G);
     int mine = 0;
     using AccT = typename std::conditional<kMixed, float, double>::type;
     AccT acc[27];

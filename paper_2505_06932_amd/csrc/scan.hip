@@ -4,6 +4,7 @@
 // offset conversion of the library.
 #include <algorithm>
 
+#include "dpp.hpp"
 #include "ftc_ws.hpp"
 
 namespace ftc {
@@ -31,16 +32,6 @@ struct WordsPlain {
   __device__ uint32_t word(int64_t i) const { return p[i]; }
 };
 
-// Inclusive scan across one wavefront of 64 lanes.
-__device__ inline int32_t wave_incl_scan(int32_t v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    int32_t o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
-  return v;
-}
 
 // Exclusive scan of one value per thread over the block; returns the block
 // total in *total.  blockDim.x must be a multiple of 64 and <= 1024.
@@ -48,12 +39,12 @@ __device__ inline int32_t block_excl_scan(int32_t v, int32_t* total) {
   __shared__ int32_t wsum[16];
   __shared__ int32_t wtot;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int32_t inc = wave_incl_scan(v);
+  int32_t inc = wave_incl_scan_dpp(v);
   if (lane == 63) wsum[wid] = inc;
   __syncthreads();
   if (wid == 0) {
     int32_t s = lane < nw ? wsum[lane] : 0;
-    int32_t si = wave_incl_scan(s);
+    int32_t si = wave_incl_scan_dpp(s);
     if (lane < nw) wsum[lane] = si - s;
     if (lane == nw - 1) wtot = si;
   }
