@@ -929,20 +929,17 @@ union FastMem {
 };
 
 // Insert key into the set; true when this lane added it.  full is set if
-// the probe sequence wraps without finding a place.
+// the probe sequence wraps without finding a place.  One LDS round trip
+// per probe: the compare-and-swap returns the slot's previous content,
+// which tells a new key (empty), a present one (key) and a collision.
 template <int HS>
 __device__ inline bool vset_insert(int32_t* hv, int32_t key, bool& full) {
   int s = hslot<HS>(key);
 #pragma unroll 1
   for (int p = 0; p < HS; ++p) {
-    // most corners are in the set already: a plain read first
-    const int32_t cur = __hip_atomic_load(&hv[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (cur == key) return false;
-    if (cur == -1) {
-      const int32_t prev = atomicCAS(&hv[s], -1, key);
-      if (prev == -1) return true;
-      if (prev == key) return false;
-    }
+    const int32_t prev = atomicCAS(&hv[s], -1, key);
+    if (prev == -1) return true;
+    if (prev == key) return false;
     s = (s + 1) & (HS - 1);
   }
   full = true;
