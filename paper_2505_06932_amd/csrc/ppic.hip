@@ -946,15 +946,30 @@ __device__ inline bool vset_insert(int32_t* hv, int32_t key, bool& full) {
   return false;
 }
 
+// The probes after a first one at slot s that found another key: insert
+// (true when this lane added the key) ...
 template <int HS>
-__device__ inline bool vset_has(const int32_t* hv, int32_t key) {
-  int s = hslot<HS>(key);
+__device__ inline bool vset_insert_after(int32_t* hv, int32_t key, int s, bool& full) {
 #pragma unroll 1
-  for (int p = 0; p < HS; ++p) {
+  for (int p = 1; p < HS; ++p) {
+    s = (s + 1) & (HS - 1);
+    const int32_t prev = atomicCAS(&hv[s], -1, key);
+    if (prev == -1) return true;
+    if (prev == key) return false;
+  }
+  full = true;
+  return false;
+}
+
+// ... and lookup.
+template <int HS>
+__device__ inline bool vset_has_after(const int32_t* hv, int32_t key, int s) {
+#pragma unroll 1
+  for (int p = 1; p < HS; ++p) {
+    s = (s + 1) & (HS - 1);
     const int32_t cur = hv[s];
     if (cur == key) return true;
     if (cur == -1) return false;
-    s = (s + 1) & (HS - 1);
   }
   return false;
 }
@@ -975,13 +990,33 @@ __device__ inline void expand_vertex(const PPICArgs& A, FastMem& M, int32_t u, i
     int4 cc[IB];
 #pragma unroll
     for (int j = 0; j < IB; ++j) cc[j] = tt[j] >= 0 ? A.tri4[tt[j]] : make_int4(-1, -1, -1, -1);
+    // the first probes of all corners issued together (a lane's LDS
+    // operations complete in order, so a key repeated in the batch is added
+    // by its first occurrence), then the probe sequences of the collisions
+    // in corner order: the lanes that add each key are those of one insert
+    // after the other
+    int32_t pv[IB][3];
+    uint32_t want = 0u;
+#pragma unroll
+    for (int j = 0; j < IB; ++j) {
+      const int32_t cr[3] = {cc[j].x, cc[j].y, cc[j].z};
+#pragma unroll
+      for (int e = 0; e < 3; ++e) {
+        const bool w = cr[e] >= 0 && cr[e] != u;
+        pv[j][e] = w ? atomicCAS(&M.r.hv[hslot<C::HV>(cr[e])], -1, cr[e]) : cr[e];
+        if (w) want |= 1u << (3 * j + e);
+      }
+    }
     uint32_t added = 0u;
 #pragma unroll
     for (int j = 0; j < IB; ++j) {
       const int32_t cr[3] = {cc[j].x, cc[j].y, cc[j].z};
 #pragma unroll
-      for (int e = 0; e < 3; ++e)
-        if (cr[e] >= 0 && cr[e] != u && vset_insert<C::HV>(M.r.hv, cr[e], full)) added |= 1u << (3 * j + e);
+      for (int e = 0; e < 3; ++e) {
+        const uint32_t bit = 1u << (3 * j + e);
+        if (!(want & bit) || pv[j][e] == cr[e]) continue;
+        if (pv[j][e] == -1 || vset_insert_after<C::HV>(M.r.hv, cr[e], hslot<C::HV>(cr[e]), full)) added |= bit;
+      }
     }
     int total;
     int pos = nV + group_excl_scan<G>(__popc(added), gl, &total);
@@ -1012,13 +1047,23 @@ __device__ inline void ring_vertex(const PPICArgs& A, FastMem& M, int32_t u, int
     int4 cc[IB];
 #pragma unroll
     for (int j = 0; j < IB; ++j) cc[j] = tt[j] >= 0 ? A.tri4[tt[j]] : make_int4(-1, -1, -1, -1);
+    // u is t1 or t2: the triangle is kept unless an earlier corner is in
+    // the set; the home slots of those corners are read together first
+    int32_t hx[IB], hy[IB];
+#pragma unroll
+    for (int j = 0; j < IB; ++j) {
+      const bool nx = tt[j] >= 0 && cc[j].x != u, ny = nx && cc[j].y != u;
+      hx[j] = nx ? M.r.hv[hslot<C::HV>(cc[j].x)] : -1;
+      hy[j] = ny ? M.r.hv[hslot<C::HV>(cc[j].y)] : -1;
+    }
     uint32_t kept = 0u;
 #pragma unroll
     for (int j = 0; j < IB; ++j) {
       bool keep = tt[j] >= 0;
       if (keep && cc[j].x != u) {
-        // u is t1 or t2: kept unless an earlier corner is in the set
-        keep = !vset_has<C::HV>(M.r.hv, cc[j].x) && (cc[j].y == u || !vset_has<C::HV>(M.r.hv, cc[j].y));
+        const int32_t x = cc[j].x, y = cc[j].y;
+        const bool inx = hx[j] == x || (hx[j] != -1 && vset_has_after<C::HV>(M.r.hv, x, hslot<C::HV>(x)));
+        keep = !inx && (y == u || !(hy[j] == y || (hy[j] != -1 && vset_has_after<C::HV>(M.r.hv, y, hslot<C::HV>(y)))));
       }
       if (keep) kept |= 1u << j;
     }
