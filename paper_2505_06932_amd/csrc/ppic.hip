@@ -928,26 +928,13 @@ union FastMem {
   double S[32];  // the 27 sums, the frame normal, the weighted count
 };
 
-// Insert key into the set; true when this lane added it.  full is set if
-// the probe sequence wraps without finding a place.  One LDS round trip
-// per probe: the compare-and-swap returns the slot's previous content,
-// which tells a new key (empty), a present one (key) and a collision.
-template <int HS>
-__device__ inline bool vset_insert(int32_t* hv, int32_t key, bool& full) {
-  int s = hslot<HS>(key);
-#pragma unroll 1
-  for (int p = 0; p < HS; ++p) {
-    const int32_t prev = atomicCAS(&hv[s], -1, key);
-    if (prev == -1) return true;
-    if (prev == key) return false;
-    s = (s + 1) & (HS - 1);
-  }
-  full = true;
-  return false;
-}
-
-// The probes after a first one at slot s that found another key: insert
-// (true when this lane added the key) ...
+// The vertex set is an open-addressing hash in LDS (-1 empty, linear
+// probing from the key's home slot).  Callers take the first probe of a
+// batch of keys together: an insert as one compare-and-swap at the home
+// slot, whose previous content tells a new key (empty), a present one (the
+// key) and a collision (another key); a lookup as one read.  Only a
+// collision continues here with the probes after slot s: insert (true when
+// this lane added the key; full is set if the sequence wraps) ...
 template <int HS>
 __device__ inline bool vset_insert_after(int32_t* hv, int32_t key, int s, bool& full) {
 #pragma unroll 1
@@ -1139,6 +1126,31 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
         const bool have = i < deg0;
         const int4 t4 = A.tri4[have ? A.vt_ids[o0 + i] : 0];
         const P3 a = vtx(A.vtx4, t4.x), b = vtx(A.vtx4, t4.y), e = vtx(A.vtx4, t4.z);
+        if (R >= 2) {
+          // the corners join V while the vertex records are in flight; first
+          // probes together, then the collisions in corner order
+          const int32_t cr[3] = {t4.x, t4.y, t4.z};
+          int32_t pv[3];
+#pragma unroll
+          for (int e2 = 0; e2 < 3; ++e2)
+            pv[e2] = have && cr[e2] != vs ? atomicCAS(&M.r.hv[hslot<C::HV>(cr[e2])], -1, cr[e2]) : cr[e2];
+          uint32_t added = 0u;
+#pragma unroll
+          for (int e2 = 0; e2 < 3; ++e2) {
+            if (!have || cr[e2] == vs || pv[e2] == cr[e2]) continue;
+            if (pv[e2] == -1 || vset_insert_after<C::HV>(M.r.hv, cr[e2], hslot<C::HV>(cr[e2]), full))
+              added |= 1u << e2;
+          }
+          int total;
+          int pos = nV + group_excl_scan<G>(__popc(added), gl, &total);
+#pragma unroll
+          for (int e2 = 0; e2 < 3; ++e2)
+            if ((added >> e2) & 1u) {
+              if (pos < C::VC) M.r.V[pos] = cr[e2];
+              ++pos;
+            }
+          nV += total;
+        }
         const double ux = b.x - a.x, uy = b.y - a.y, uz = b.z - a.z;
         const double wx = e.x - a.x, wy = e.y - a.y, wz = e.z - a.z;
         const double cx = uy * wz - uz * wy;
@@ -1153,22 +1165,6 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
             s1 += y;
             s2 += z;
           }
-        }
-        if (R >= 2) {
-          uint32_t added = 0u;
-          const int32_t cr[3] = {t4.x, t4.y, t4.z};
-#pragma unroll
-          for (int e2 = 0; e2 < 3; ++e2)
-            if (have && cr[e2] != vs && vset_insert<C::HV>(M.r.hv, cr[e2], full)) added |= 1u << e2;
-          int total;
-          int pos = nV + group_excl_scan<G>(__popc(added), gl, &total);
-#pragma unroll
-          for (int e2 = 0; e2 < 3; ++e2)
-            if ((added >> e2) & 1u) {
-              if (pos < C::VC) M.r.V[pos] = cr[e2];
-              ++pos;
-            }
-          nV += total;
         }
       }
       const double nl = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
