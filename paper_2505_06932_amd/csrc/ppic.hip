@@ -1078,7 +1078,7 @@ __device__ inline void ring_vertex(const PPICArgs& A, FastMem& M, int32_t u, int
 // about cond(M) times the single-precision unit roundoff.  A
 // single-precision pivot at or below 1e-6 of the trace marks the cell rank
 // deficient.
-template <int G, bool kMixed>
+template <int G, bool kMixed, bool kPrefetch = true>
 __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
   using C = FastCfg<G>;
   constexpr int NG = C::NG;
@@ -1236,11 +1236,26 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
     AccT acc[27];
 #pragma unroll
     for (int qa = 0; qa < 27; ++qa) acc[qa] = AccT(0);
-    for (int k = 0; k < frounds; ++k) {
+    // kPrefetch: each round's vertex records are loaded during the round
+    // before (the registers they take make a build held to 128 VGPRs spill)
+    auto ring_tri = [&](int k, bool& valid, P3& a, P3& b, P3& e) {
       const int i = k * G + gl;
-      const bool valid = i < nTc;
+      valid = i < nTc;
       const int32_t c0 = valid ? M.r.T[0][i] : 0, c1 = valid ? M.r.T[1][i] : 0, c2 = valid ? M.r.T[2][i] : 0;
-      const P3 a = vtx(A.vtx4, c0), b = vtx(A.vtx4, c1), e = vtx(A.vtx4, c2);
+      a = vtx(A.vtx4, c0);
+      b = vtx(A.vtx4, c1);
+      e = vtx(A.vtx4, c2);
+    };
+    bool valid;
+    P3 a, b, e;
+    if constexpr (kPrefetch) ring_tri(0, valid, a, b, e);
+    for (int k = 0; k < frounds; ++k) {
+      bool valid1;
+      P3 a1, b1, e1;
+      if constexpr (kPrefetch)
+        ring_tri(k + 1, valid1, a1, b1, e1);
+      else
+        ring_tri(k, valid, a, b, e);
       const double dd = centre_d2(a, b, e, F.xc);
       const bool in = valid && dd < lim;
       mine += in ? 1 : 0;
@@ -1248,6 +1263,12 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
       AccT mom[6], vt;
       tri_moments(F, a, b, e, mom, vt);
       accumulate(acc, (AccT)w, mom, vt);
+      if constexpr (kPrefetch) {
+        valid = valid1;
+        a = a1;
+        b = b1;
+        e = e1;
+      }
     }
     const int cnt = group_sum_i<G>(mine);
     // the support needs adjusting: the wide shape takes the cell
@@ -1325,7 +1346,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
 // The same held to four wavefronts per SIMD (128 VGPRs, some spilled): on a
 // front whose cell groups nearly fit the chip at that occupancy, one round
 // of wavefronts instead of two pays for the spills.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_ppic_fast8_w4(PPICArgs A) { ppic_fast<8, false>(A, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_ppic_fast8_w4(PPICArgs A) { ppic_fast<8, false, false>(A, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(64) void k_ppic_fast16(PPICArgs A) { ppic_fast<16, false>(A, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(64) void k_ppic_fast32(PPICArgs A) { ppic_fast<32, false>(A, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(64) void k_ppic_fast64(PPICArgs A) { ppic_fast<64, false>(A, blockIdx.x, gridDim.x); }
