@@ -159,6 +159,7 @@ ftc_status ftc_cells_create(ftc_cells** out, const ftc_grid* grid, int32_t nv_ca
   FTC_ALLOC(frame_n, 3 * Cc);
   FTC_ALLOC(best_d2, Cc);
   FTC_ALLOC(best_v, Cc);
+  FTC_ALLOC(best_inc, 2 * Cc);
   FTC_ALLOC(sel_cells, Cc);
   FTC_ALLOC(r_tn, 4 * (int64_t)nt_capacity);
   FTC_ALLOC(r_vG, nv_capacity);

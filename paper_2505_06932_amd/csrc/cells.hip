@@ -558,6 +558,9 @@ struct VstarArgs {
   const int32_t* stray;
   double* best_d2;
   int32_t* best_v;
+  const int32_t* vt_off;  // the vertices' incident-triangle offsets
+  int2* best_inc;         // (offset, count) of best_v's incident triangles
+  int32_t nv;
   int32_t cell_cap;
   const int32_t* counters;
 };
@@ -674,6 +677,13 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t
   if (ok && l == 0) {
     A.best_d2[c] = bd;
     A.best_v[c] = bv;
+    // the curvature fit's first loads, one dependent level earlier
+    int2 inc = make_int2(0, 0);
+    if (bv >= 0 && bv < A.nv) {
+      inc.x = A.vt_off[bv];
+      inc.y = A.vt_off[bv + 1] - inc.x;
+    }
+    A.best_inc[c] = inc;
   }
 }
 
@@ -737,7 +747,8 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
   PlaceArgs A{ws->tmp_rec,    ws->offsets,  ws->tri_ids,  ws->piece_flux, ws->piece_vol,
               ws->cell_flux,  ws->cell_vol, ws->cell_cap, ws->pair_cap,   ws->counters};
   VstarArgs V{vtx4,       ws->cell_ids, ws->bitmap,  ws->word_off, ws->vb_off,  reinterpret_cast<const double2*>(ws->vb_rec),
-              ws->stray,  ws->best_d2,  ws->best_v,  ws->cell_cap, ws->counters};
+              ws->stray,  ws->best_d2,  ws->best_v,  ws->vt_off,  reinterpret_cast<int2*>(ws->best_inc),
+              m.nv,       ws->cell_cap, ws->counters};
   const int32_t nb_place = round_up_xcd(grid_blocks((int64_t)ws->cell_cap * kPlLanes, kT));
   const int32_t nb_sort = grid_blocks(m.nv, kT);
   const int32_t nb_vstar = round_up_xcd(grid_blocks((int64_t)ws->cell_cap * kVsLanes, kT));

@@ -115,6 +115,7 @@ struct ftc_cells {
   int32_t* r_elist;       // [3 * nt_cap] edges listed for smoothing
   double* best_d2;        // [cell_cap] smallest squared distance of a vertex in the 27 cells around
   int32_t* best_v;        // [cell_cap] lowest vertex attaining it
+  int32_t* best_inc;      // [2 * cell_cap] (offset, count) of best_v's incident-triangle list
 
   // optional timing events around the dominant kernel of each call
   int timing;

@@ -87,6 +87,7 @@ struct PPICArgs {
   const int32_t* vt_ids;
   const double* best_d2;
   const int32_t* best_v;
+  const int2* best_inc;  // (offset, count) of best_v's incident triangles
   int32_t* counters;
   int32_t* ovf_cells;
   double* frame_n;  // [3][cell_cap] frame normal of each cell (the paraboloid cell integrals read it)
@@ -419,12 +420,17 @@ __device__ inline void write_diag(const PPICArgs& A, int32_t c, int32_t vs, int3
 // Closest vertex of the cell with centre xc: the pre-pass result when it
 // is final, else (need) a search over all vertices by the G lanes of the
 // cell.  Called by all 64 lanes.
+// searched: whether the search ran for this cell; inc: the pre-pass's
+// incident-triangle range (offset, count) of its vertex, valid otherwise.
 template <int G>
-__device__ inline int32_t closest_vertex(const PPICArgs& A, int32_t c, bool act, const double xc[3], int gl) {
+__device__ inline int32_t closest_vertex(const PPICArgs& A, int32_t c, bool act, const double xc[3], int gl,
+                                         bool& searched, int2& inc) {
   const double reach = 1.5 * A.g.h;
   const double reach2 = reach * reach * (1.0 - 1e-12);
   int32_t vs = act ? A.best_v[c] : 0;
+  inc = act ? A.best_inc[c] : make_int2(0, 0);
   const bool need = act && !(vs != INT_MAX && A.best_d2[c] < reach2);
+  searched = need;
   if (__any(need)) {
     double bd = DBL_MAX;
     int32_t bv = INT_MAX;
@@ -442,6 +448,13 @@ __device__ inline int32_t closest_vertex(const PPICArgs& A, int32_t c, bool act,
     if (need) vs = bv;
   }
   return vs;
+}
+
+template <int G>
+__device__ inline int32_t closest_vertex(const PPICArgs& A, int32_t c, bool act, const double xc[3], int gl) {
+  bool searched;
+  int2 inc;
+  return closest_vertex<G>(A, c, act, xc, gl, searched, inc);
 }
 
 // Cell groups of the fast shape for workgroup `bid` of `nblk`.  The groups
@@ -1095,10 +1108,12 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
     const int32_t c = gi * NG + grp;
     const bool act = c < nitems;
     int32_t vs;
+    bool searched;
+    int2 inc;
     {
       const Cell3 cc3 = unpack_cell(g, act ? A.cell_ids[c] : 0);
       const double xc[3] = {cell_centre(g.x0, cc3.i, h), cell_centre(g.y0, cc3.j, h), cell_centre(g.z0, cc3.k, h)};
-      vs = closest_vertex<G>(A, c, act, xc, gl);
+      vs = closest_vertex<G>(A, c, act, xc, gl, searched, inc);
     }
     const bool ok = act && vs >= 0 && vs < A.nv;
 
@@ -1117,8 +1132,13 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
     // ---- the triangles at v*: frame normal (cross products summed in
     // ascending triangle order) and, for R >= 2, V_1
     {
-      const int32_t o0 = ok ? A.vt_off[vs] : 0;
-      const int deg0 = ok ? A.vt_off[vs + 1] - o0 : 0;
+      int32_t o0 = inc.x;
+      int deg0 = inc.y;
+      if (searched && ok) {
+        o0 = A.vt_off[vs];
+        deg0 = A.vt_off[vs + 1] - o0;
+      }
+      if (!ok) deg0 = 0;
       const int nr = wave_max_dpp((deg0 + G - 1) / G);
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
       for (int k = 0; k < nr; ++k) {
@@ -1376,6 +1396,7 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
   A.vt_ids = ws->vt_ids;
   A.best_d2 = ws->best_d2;
   A.best_v = ws->best_v;
+  A.best_inc = reinterpret_cast<const int2*>(ws->best_inc);
   A.counters = ws->counters;
   A.ovf_cells = ws->ovf_cells;
   A.frame_n = ws->frame_n;
