@@ -48,7 +48,7 @@ namespace ftc {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kStrideBlocks = 2048;
+constexpr int kStrideBlocks = 8192;  // grid of the clearing and pair walks: eight wavefronts per SIMD
 constexpr int kPieceLanes = 64;  // k_clip_mark: one wavefront per workgroup
 
 // Corner r of triangle t if it is a valid vertex index distinct from the
