@@ -577,7 +577,7 @@ struct VstarArgs {
 // Called with all 64 lanes of the wavefront.
 constexpr int kVsLanes = 8;                            // lanes per cell
 constexpr int kVsNb = (27 + kVsLanes - 1) / kVsLanes;  // block cells per lane
-constexpr int kVsBatch = 8;                            // bin records loaded together
+constexpr int kVsBatch = 4;                            // bin records loaded together
 
 // d^2 to xc of a binned vertex record, kept when it beats (bd, bv); the
 // same arithmetic as consider().
