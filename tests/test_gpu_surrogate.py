@@ -563,8 +563,8 @@ def test_trained_surrogate_gain(oracle, workload, faster):
     # most cells are trusted, and they are close to the fit
     assert fb.mean() <= 0.25
     assert q50 <= 0.03 and q90 <= 0.10
-    # the call is clearly faster than PPIC on every cell (measured 0.59-0.61
-    # of its time since the PPIC call itself came down to about 320 us)
+    # the call is clearly faster than PPIC on every cell (measured at 0.59-0.61
+    # of the PPIC call's time, which is about 320 us)
     if faster:
         assert t_learned < 0.7 * t_plain
 
