@@ -1363,9 +1363,10 @@ __device__ inline void ppic_fast(const PPICArgs& A, int32_t bid, int32_t nblk) {
 
 __global__ __launch_bounds__(64) void k_ppic_fast4(PPICArgs A) { ppic_fast<4, false>(A, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_ppic_fast8(PPICArgs A) { ppic_fast<8, false>(A, blockIdx.x, gridDim.x); }
-// The same held to four wavefronts per SIMD (128 VGPRs, some spilled): on a
-// front whose cell groups nearly fit the chip at that occupancy, one round
-// of wavefronts instead of two pays for the spills.
+// The same held to four wavefronts per SIMD (128 VGPRs, some spilled, the
+// fit without its round-ahead loads): on a front whose cell groups fill the
+// chip at most three times at that occupancy, the fewer rounds of
+// wavefronts pay for the spills.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_ppic_fast8_w4(PPICArgs A) { ppic_fast<8, false, false>(A, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(64) void k_ppic_fast16(PPICArgs A) { ppic_fast<16, false>(A, blockIdx.x, gridDim.x); }
 __global__ __launch_bounds__(64) void k_ppic_fast32(PPICArgs A) { ppic_fast<32, false>(A, blockIdx.x, gridDim.x); }
@@ -1434,7 +1435,7 @@ hipError_t launch_ppic_cells(const ftc_cells* ws, const Mesh& m, const PPICParam
       hipLaunchKernelGGL(k_ppic_fast32, grid, dim3(64), 0, s, A);
     else if (lanes == 64)
       hipLaunchKernelGGL(k_ppic_fast64, grid, dim3(64), 0, s, A);
-    else if (groups <= 2 * 16 * (int64_t)ws->cu_count)  // two rounds at four wavefronts per SIMD
+    else if (groups <= 3 * 16 * (int64_t)ws->cu_count)  // up to three rounds at four wavefronts per SIMD
       hipLaunchKernelGGL(k_ppic_fast8_w4, grid, dim3(64), 0, s, A);
     else
       hipLaunchKernelGGL(k_ppic_fast8, grid, dim3(64), 0, s, A);
