@@ -50,6 +50,18 @@ namespace {
 constexpr int kT = 256;
 constexpr int kStrideBlocks = 8192;  // grid of the clearing and pair walks: eight wavefronts per SIMD
 constexpr int kPieceLanes = 64;  // k_clip_mark: one wavefront per workgroup
+// k_clip_mark's polygon buffer: six corner slots per lane, enough for any
+// candidate that cuts at most one plane of each axis, which keeps the buffer
+// to 9 KB per wavefront (four wavefronts per SIMD).  A lane whose polygon
+// outgrows them is clipped again with kMaxPoly slots, kWideLanes lanes at a
+// time over the same memory.
+constexpr int kFastPoly = 6;
+constexpr int kWideLanes = kPieceLanes * kFastPoly / kMaxPoly;
+union ClipLDS {
+  PolyLDS<kPieceLanes, kFastPoly> fast;
+  PolyLDS<kWideLanes, kMaxPoly> wide;
+};
+static_assert(sizeof(PolyLDS<kWideLanes, kMaxPoly>) <= sizeof(PolyLDS<kPieceLanes, kFastPoly>), "wide view fits");
 
 // Corner r of triangle t if it is a valid vertex index distinct from the
 // triangle's earlier corners, else -1 (a triangle is listed once under each
@@ -233,28 +245,42 @@ __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, con
 // list), full clipping; the result stays in the candidate's slot, with cell
 // -1 when there is no piece.  The others: the whole-triangle pieces (first
 // region).  Both set the occupancy bits of their pieces' cells.
-__global__ __launch_bounds__(kPieceLanes) void k_clip_mark(Grid g, const int4* tri4, const double2* vtx4, PairOut P,
+__global__ __launch_bounds__(kPieceLanes) __attribute__((amdgpu_waves_per_eu(4))) void k_clip_mark(Grid g, const int4* tri4, const double2* vtx4, PairOut P,
                                                            int64_t q_cap, uint32_t* bitmap, const int32_t* counters,
                                                            int32_t nb_clip) {
-  __shared__ PolyLDS<kPieceLanes> L;
+  __shared__ ClipLDS L;
   __shared__ uint32_t acc[kPieceLanes];
   const int lane = threadIdx.x;
   if ((int32_t)blockIdx.x < nb_clip) {
     const int64_t nq = min((int64_t)counters[C_NQUEUE], q_cap);
     XcdWalk(nq, blockIdx.x, nb_clip).run([&](int64_t q, bool ok) {
+      const int64_t slot = P.cap + q;
+      // the candidate's clip with the given buffer view; the lanes clipped
+      // again reload it rather than keep it live across the first clip
+      auto clip = [&](auto& view, int idx) {
+        const Cell3 c = unpack_cell(g, P.lin[slot]);
+        const Tri T = load_tri_packed(tri4, vtx4, P.tri[slot]);
+        return clip_piece(g, T, c.i, c.j, c.k, view, idx, inside_mask(g, T, c.i, c.j, c.k));
+      };
+      Piece pc{false, 0.0, 0.0, false};
+      if (ok) pc = clip(L.fast, lane);
+      // lanes over the six slots: again with nine, ranked among themselves
+      const bool again = pc.over_cap;
+      const uint64_t redo = __ballot(again);
+      if (redo) {
+        const int r = __popcll(redo & ((1ull << lane) - 1ull));
+        const int nr = __popcll(redo);
+        for (int b = 0; b < nr; b += kWideLanes)
+          if (again && r >= b && r < b + kWideLanes) pc = clip(L.wide, r - b);
+      }
       int32_t lin = -1;
       if (ok) {
-        const int64_t slot = P.cap + q;
-        lin = P.lin[slot];
-        const Cell3 c = unpack_cell(g, lin);
-        const Tri T = load_tri_packed(tri4, vtx4, P.tri[slot]);
-        const Piece pc = clip_piece(g, T, c.i, c.j, c.k, L, lane, inside_mask(g, T, c.i, c.j, c.k));
         if (pc.keep) {
+          lin = P.lin[slot];
           P.flux[slot] = pc.flux;
           P.vol[slot] = pc.vol;
         } else {
           P.lin[slot] = -1;
-          lin = -1;
         }
       }
       wave_set_bits(bitmap, lin >> 5, lin & 31, lin >= 0, acc);

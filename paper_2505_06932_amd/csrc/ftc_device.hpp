@@ -164,6 +164,7 @@ struct Piece {
   bool keep;
   double flux;  // integral of n_z dA over the piece
   double vol;   // integral of (z - zlo) n_z dA over the piece
+  bool over_cap;  // a clip with fewer than kMaxPoly corner slots outgrew them: no result, clip again with kMaxPoly
 };
 
 // Planes of cell (i, j, k); false if the half-open rule gives the triangle to
@@ -317,14 +318,15 @@ __host__ __device__ inline uint32_t inside_mask(const Grid& g, const Tri& T, int
 
 // Fan integrals of a polygon given by corner accessors (corner 0 is the fan
 // apex): membership by the vector area, flux and vol by the z-column rule.
-template <class CX>
+// CAP bounds n; the sums do not depend on it.
+template <int CAP = kMaxPoly, class CX>
 __host__ __device__ inline Piece fan_piece(int n, double zlo, CX cx) {
   Piece out{false, 0.0, 0.0};
   if (n < 3) return out;
   const double x0 = cx(0, 0), y0 = cx(0, 1), z0 = cx(0, 2);
   double sx = 0.0, sy = 0.0, sz = 0.0, f = 0.0, v = 0.0;
 #pragma unroll
-  for (int jj = 1; jj + 1 < kMaxPoly; ++jj) {
+  for (int jj = 1; jj + 1 < CAP; ++jj) {
     if (jj + 1 < n) {
       const double x1 = cx(jj, 0), y1 = cx(jj, 1), z1 = cx(jj, 2);
       const double x2 = cx(jj + 1, 0), y2 = cx(jj + 1, 1), z2 = cx(jj + 1, 2);
@@ -353,10 +355,10 @@ __host__ __device__ inline Piece whole_piece(const Tri& T, double zlo) {
   return fan_piece(3, zlo, [&](int q, int d) { return q == 0 ? T.v[0][d] : (q == 1 ? T.v[1][d] : T.v[2][d]); });
 }
 
-// Per-lane compaction buffer in LDS: [coordinate][corner][lane].
-template <int LANES>
+// Per-lane compaction buffer in LDS: [coordinate][corner][lane], CAP corners.
+template <int LANES, int CAP = kMaxPoly>
 struct PolyLDS {
-  double v[3][kMaxPoly][LANES];
+  double v[3][CAP][LANES];
 };
 
 // One of three values by a run-time index, without indexing registers.
@@ -377,17 +379,25 @@ __host__ __device__ inline double sel3(int d, double a, double b, double c) { re
 // corners), stored to LDS at positions 0.. and reloaded with rot = 0.
 // `skip`: stages known to cut nothing (a subset of inside_mask), which then
 // only rotate the polygon.
-template <int LANES>
+// CAP < kMaxPoly builds the same clip with CAP corner slots (fewer
+// registers and LDS): while every stage emits at most CAP corners it does
+// exactly what the kMaxPoly build does; a stage that would emit more returns
+// over_cap instead, and the caller clips that candidate again with
+// kMaxPoly slots.  A triangle that cuts at most one plane of each axis never
+// exceeds six corners.
+template <int LANES, int CAP>
 __host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t i, int64_t j, int64_t k,
-                                            PolyLDS<LANES>& L, int lane, uint32_t skip = 0u) {
-  Piece none{false, 0.0, 0.0};
+                                            PolyLDS<LANES, CAP>& L, int lane, uint32_t skip = 0u) {
+  static_assert(CAP >= 3 && CAP <= kMaxPoly, "polygon capacity");
+  Piece none{false, 0.0, 0.0, false};
+  const Piece grown{false, 0.0, 0.0, true};
   double lo[3], hi[3];
   if (!cell_planes(g, T, i, j, k, lo, hi)) return none;
-  double P[3][kMaxPoly];
+  double P[3][CAP];
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
-    for (int q = 0; q < kMaxPoly; ++q) {
+    for (int q = 0; q < CAP; ++q) {
       P[d][q] = q < 3 ? T.v[q][d] : 0.0;
       if (q < 3) L.v[d][q][lane] = T.v[q][d];
     }
@@ -405,7 +415,7 @@ __host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t
     const double c = upper ? sel3(d, hi[0], hi[1], hi[2]) : sel3(d, lo[0], lo[1], lo[2]);
     uint32_t mp = 0;  // inside corners by physical slot
 #pragma unroll
-    for (int q = 0; q < kMaxPoly; ++q) {
+    for (int q = 0; q < CAP; ++q) {
       const double x = sel3(d, P[0][q], P[1][q], P[2][q]);
       if (q < n && (upper ? (x <= c) : (x >= c))) mp |= 1u << q;
     }
@@ -448,15 +458,17 @@ __host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t
         }
       }
       const uint32_t C = ((uint32_t)emit[0] << e_out) | ((uint32_t)emit[1] << e_in);
+      const int n_out = __builtin_popcount(m) + __builtin_popcount(C);
+      if (CAP < kMaxPoly && n_out > CAP) return grown;
       // corner i = e + 1 of edge e follows the cut point of edge e
 #pragma unroll
-      for (int q = 0; q < kMaxPoly; ++q) {
+      for (int q = 0; q < CAP; ++q) {
         if (q < n && ((mp >> q) & 1u)) {
           int li = q - rot;
           if (li < 0) li += n;
           const int e = li == 0 ? n - 1 : li - 1;
           const int pos = __builtin_popcount(C & ((2u << e) - 1u)) + __builtin_popcount(Qm & ((1u << e) - 1u));
-          if (pos < kMaxPoly) {
+          if (pos < CAP) {
 #pragma unroll
             for (int f = 0; f < 3; ++f) L.v[f][pos][lane] = P[f][q];
           }
@@ -466,18 +478,17 @@ __host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t
       for (int s = 0; s < 2; ++s) {
         const int e = s ? e_in : e_out;
         const int pos = __builtin_popcount(C & ((1u << e) - 1u)) + __builtin_popcount(Qm & ((1u << e) - 1u));
-        if (emit[s] && pos < kMaxPoly) {
+        if (emit[s] && pos < CAP) {
 #pragma unroll
           for (int f = 0; f < 3; ++f) L.v[f][pos][lane] = X[s][f];
         }
       }
-      n = __builtin_popcount(m) + __builtin_popcount(C);
-      if (n > kMaxPoly) n = kMaxPoly;
+      n = n_out > CAP ? CAP : n_out;
     } else {
       // logical order in registers, then every edge in turn
       if (rot) {
 #pragma unroll
-        for (int q = 0; q < kMaxPoly; ++q) {
+        for (int q = 0; q < CAP; ++q) {
           int ps = q + rot;
           if (ps >= n) ps -= n;
           if (q < n) {
@@ -486,12 +497,12 @@ __host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t
           }
         }
       }
-      int o = 0;
+      int o = 0;  // corners emitted, also those beyond the CAP slots
 #pragma unroll
-      for (int e = 0; e < kMaxPoly; ++e) {
+      for (int e = 0; e < CAP; ++e) {
         if (e < n) {
           double q0 = P[0][0], q1 = P[1][0], q2 = P[2][0];
-          if (e + 1 < kMaxPoly && e + 1 < n) {
+          if (e + 1 < CAP && e + 1 < n) {
             q0 = P[0][e + 1];
             q1 = P[1][e + 1];
             q2 = P[2][e + 1];
@@ -502,37 +513,42 @@ __host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t
           const bool pin = upper ? (pd <= c) : (pd >= c);
           const bool qin = upper ? (qd <= c) : (qd >= c);
           const bool cut = pin != qin && (pin ? pd != c : qd != c);
-          if (cut && o < kMaxPoly) {
-            const bool pa = pd < qd;
-            const double ad = pa ? pd : qd, bd = pa ? qd : pd;
-            const double t = (c - ad) / (bd - ad);
+          if (cut) {
+            if (o < CAP) {
+              const bool pa = pd < qd;
+              const double ad = pa ? pd : qd, bd = pa ? qd : pd;
+              const double t = (c - ad) / (bd - ad);
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-              const double af = pa ? pp[f] : qq[f], bf = pa ? qq[f] : pp[f];
-              L.v[f][o][lane] = (f == d) ? c : af + t * (bf - af);
+              for (int f = 0; f < 3; ++f) {
+                const double af = pa ? pp[f] : qq[f], bf = pa ? qq[f] : pp[f];
+                L.v[f][o][lane] = (f == d) ? c : af + t * (bf - af);
+              }
             }
             ++o;
           }
-          if (qin && o < kMaxPoly) {
-            L.v[0][o][lane] = q0;
-            L.v[1][o][lane] = q1;
-            L.v[2][o][lane] = q2;
+          if (qin) {
+            if (o < CAP) {
+              L.v[0][o][lane] = q0;
+              L.v[1][o][lane] = q1;
+              L.v[2][o][lane] = q2;
+            }
             ++o;
           }
         }
       }
-      n = o;
+      if (CAP < kMaxPoly && o > CAP) return grown;
+      n = o > CAP ? CAP : o;
       if (n == 0) return none;
     }
     rot = 0;
 #pragma unroll
     for (int f = 0; f < 3; ++f)
 #pragma unroll
-      for (int q = 0; q < kMaxPoly; ++q) P[f][q] = L.v[f][q][lane];
+      for (int q = 0; q < CAP; ++q) P[f][q] = L.v[f][q][lane];
   }
   if (rot) {
 #pragma unroll
-    for (int q = 0; q < kMaxPoly; ++q) {
+    for (int q = 0; q < CAP; ++q) {
       int ps = q + rot;
       if (ps >= n) ps -= n;
       if (q < n) {
@@ -541,7 +557,7 @@ __host__ __device__ inline Piece clip_piece(const Grid& g, const Tri& T, int64_t
       }
     }
   }
-  return fan_piece(n, lo[2], [&](int q, int d) { return P[d][q]; });
+  return fan_piece<CAP>(n, lo[2], [&](int q, int d) { return P[d][q]; });
 }
 
 }  // namespace ftc

@@ -32,7 +32,7 @@ struct XcdWalk {
     step = (ngroup / kXCD) * blockDim.x;
   }
   template <class Body>
-  __device__ void run(Body body) const {
+  __device__ __forceinline__ void run(Body body) const {
     for (int64_t b = base; b < end; b += step) {
       const int64_t x = b + lane;
       body(x, x < end);

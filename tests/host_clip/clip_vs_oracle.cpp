@@ -1,10 +1,14 @@
 // Host build of the library's candidate classification and clipping
 // (paper_2505_06932_amd/csrc/ftc_device.hpp, compiled for the CPU) against
 // the oracle's per-piece clip: whether a (triangle, cell) pair has a piece,
-// and its two integrals, must agree bit for bit.  Test infrastructure only.
+// and its two integrals, must agree bit for bit.  Both builds of the clip
+// are checked: the one with kMaxPoly corner slots, and the six-slot one the
+// clipping kernel runs first, with its candidates over capacity clipped
+// again by the former as the kernel does.  Test infrastructure only.
 //
 // usage: clip_vs_oracle <triangles> <seed>
-// Prints "candidates <n> kept <k> differences <d>" and exits with d != 0.
+// Prints "candidates <n> kept <k> redone <r> differences <d>" and exits
+// with d != 0.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -24,7 +28,8 @@ int main(int argc, char** argv) {
   std::mt19937_64 rng(seed);
   std::uniform_real_distribution<double> U(0.0, 1.0);
   PolyLDS<1> L;
-  long cand = 0, kept = 0, diff = 0;
+  PolyLDS<1, 6> L6;
+  long cand = 0, kept = 0, redone = 0, diff = 0;
   const double hs[] = {1.0 / 32, 1.0 / 128, 0.1, 1.0 / 7, 0.25, 1.0 / 512, 3.0};
   for (long it = 0; it < n; ++it) {
     Grid g{};
@@ -74,23 +79,34 @@ int main(int argc, char** argv) {
       for (int64_t j = lo[1]; j <= hi[1]; ++j)
         for (int64_t i = lo[0]; i <= hi[0]; ++i) {
           ++cand;
-          Piece pc{false, 0.0, 0.0};
+          Piece pc{false, 0.0, 0.0, false}, p6{false, 0.0, 0.0, false};
           const int cls = classify_candidate(g, T, i, j, k);
-          if (cls == 1) pc = whole_piece(T, grid_plane(g.z0, k, g.h));
-          if (cls == 2) pc = clip_piece(g, T, i, j, k, L, 0, inside_mask(g, T, i, j, k));
+          if (cls == 1) pc = p6 = whole_piece(T, grid_plane(g.z0, k, g.h));
+          if (cls == 2) {
+            const uint32_t skip = inside_mask(g, T, i, j, k);
+            pc = clip_piece(g, T, i, j, k, L, 0, skip);
+            p6 = clip_piece(g, T, i, j, k, L6, 0, skip);
+            if (p6.over_cap) {
+              ++redone;
+              p6 = clip_piece(g, T, i, j, k, L, 0, skip);
+            }
+          }
           double out[2];
           const bool ok = ora_piece(&og, tri, (int32_t)i, (int32_t)j, (int32_t)k, 2, out) != 0;
           kept += ok ? 1 : 0;
-          if (ok != pc.keep || (ok && (!same(out[0], pc.flux) || !same(out[1], pc.vol)))) {
-            if (diff < 5)
-              std::printf("difference: triangle %ld mode %d cell %ld %ld %ld class %d oracle %d %.17g %.17g "
-                          "library %d %.17g %.17g\n",
-                          it, mode, (long)i, (long)j, (long)k, cls, (int)ok, out[0], out[1], (int)pc.keep, pc.flux,
-                          pc.vol);
-            ++diff;
+          for (int b = 0; b < 2; ++b) {
+            const Piece& r = b ? p6 : pc;
+            if (ok != r.keep || (ok && (!same(out[0], r.flux) || !same(out[1], r.vol)))) {
+              if (diff < 5)
+                std::printf("difference (%s slots): triangle %ld mode %d cell %ld %ld %ld class %d oracle %d %.17g "
+                            "%.17g library %d %.17g %.17g\n",
+                            b ? "six" : "nine", it, mode, (long)i, (long)j, (long)k, cls, (int)ok, out[0], out[1],
+                            (int)r.keep, r.flux, r.vol);
+              ++diff;
+            }
           }
         }
   }
-  std::printf("candidates %ld kept %ld differences %ld\n", cand, kept, diff);
+  std::printf("candidates %ld kept %ld redone %ld differences %ld\n", cand, kept, redone, diff);
   return diff != 0;
 }
