@@ -332,6 +332,10 @@ def test_rotated_subdivided_cube_plane_curvature(oracle):
 
 
 def test_coarse_front_support_growth(oracle):
+    """Triangles a few cells across: cells whose support must grow, and
+    about 250 clip candidates whose polygons pass six corners, which the
+    clipping kernel clips again with nine slots (counted on the CPU by
+    test_host_clip.py on this same front)."""
     grid = I.Grid(64, 64, 64, 0.0, 0.0, 0.0, 1.0 / 64)
     rng = np.random.default_rng(2)
     c = 0.5 + rng.uniform(-grid.h, grid.h, 3)
