@@ -593,17 +593,38 @@ struct VstarArgs {
 
 // Closest vertex of each interfacial cell among the vertices binned in the
 // 3x3x3 block of cells around it and the strays: kVsLanes lanes per cell,
-// lane l taking cells l, l + kVsLanes, ... of the block; the loads of each
+// each taking kVsNb cells of the block in the order below; the loads of each
 // level (bitmap words and their offsets, then bin bounds) are issued
 // together for all of them, then the lane's bin entries, kVsBatch records
 // (position and index) at a time; every lane a share of the strays; lowest
 // index on ties.  A vertex outside the block is at least 1.5 h from the
 // cell centre, so a best squared distance below (1.5 h)^2 is final (the
 // curvature kernel searches all vertices for the other cells).
+// The cell and its six face neighbours are searched first (the first block
+// cell of lanes 0-6), then the cell's lanes take their minimum; a block
+// cell with m non-zero offsets lies at least m (h/2)^2 (squared) from the
+// centre, so the edge and corner neighbours are searched only where that
+// bound, less a relative 1e-6 that covers the rounding of the binning and
+// of the centre, does not exceed the best so far (a skipped bin holds no
+// vertex that could win or tie).
 // Called with all 64 lanes of the wavefront.
 constexpr int kVsLanes = 8;                            // lanes per cell
 constexpr int kVsNb = (27 + kVsLanes - 1) / kVsLanes;  // block cells per lane
 constexpr int kVsBatch = 4;                            // bin records loaded together
+// block cells n = (di + 1) + 3 (dj + 1) + 9 (dk + 1) in the order searched:
+// the cell, its face, edge and corner neighbours
+constexpr int kVsOrder[27] = {13, 4, 10, 12, 14, 16, 22, 1, 3, 5, 7, 9, 11, 15, 17, 19, 21, 23, 25, 0, 2, 6, 8, 18, 20, 24, 26};
+// entries kVsLanes u .. kVsLanes u + 7 of the order, 5 bits each (31: none),
+// so that lane l's block cell of slot u is a shift of a constant
+constexpr uint64_t vs_slot(int u) {
+  uint64_t v = 0;
+  for (int l = 0; l < kVsLanes; ++l) {
+    const int p = l + kVsLanes * u;
+    v |= (uint64_t)(p < 27 ? kVsOrder[p] : 31) << (5 * l);
+  }
+  return v;
+}
+static_assert(kVsLanes == 8 && kVsOrder[0] == 13, "the cell and its face neighbours fill slot 0 of lanes 0-6");
 
 // d^2 to xc of a binned vertex record, kept when it beats (bd, bv); the
 // same arithmetic as consider().
@@ -617,6 +638,59 @@ __device__ inline void consider_rec(double2 r0, double2 r1, const double xc[3], 
   }
 }
 
+// The records of the lane's bins of slots [U0, U1) as one list: entry j is
+// entry j - cum[u] of bin u.
+template <int U0, int U1>
+__device__ inline void scan_bins(const VstarArgs& A, const int32_t (&p0)[kVsNb], const int32_t (&cnt)[kVsNb],
+                                 const double xc[3], double& bd, int32_t& bv) {
+  int32_t cum[U1 - U0 + 1];
+  cum[0] = 0;
+#pragma unroll
+  for (int u = U0; u < U1; ++u) cum[u - U0 + 1] = cum[u - U0] + cnt[u];
+  for (int32_t j0 = 0; j0 < cum[U1 - U0]; j0 += kVsBatch) {
+    double2 r0[kVsBatch], r1[kVsBatch];
+#pragma unroll
+    for (int q = 0; q < kVsBatch; ++q) {
+      const int32_t j = j0 + q;
+      int32_t p = -1;
+#pragma unroll
+      for (int u = U0; u < U1; ++u)
+        if (j >= cum[u - U0] && j < cum[u - U0 + 1]) p = p0[u] + (j - cum[u - U0]);
+      if (p >= 0) {
+        r0[q] = A.vb_rec[2 * (int64_t)p];
+        r1[q] = A.vb_rec[2 * (int64_t)p + 1];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kVsBatch; ++q)
+      if (j0 + q < cum[U1 - U0]) consider_rec(r0[q], r1[q], xc, bd, bv);
+  }
+}
+
+// The minimum over a cell's 8 lanes, in all of them (exact, so any pairing
+// serves).
+__device__ inline void vs_min8(double& bd, int32_t& bv) {
+  static_assert(kVsLanes == 8, "8 lanes per cell");
+  double od = dpp_d<kDppSwap1>(bd);
+  int32_t ov = dpp_i<kDppSwap1>(bv);
+  if (lex_less(od, ov, bd, bv)) {
+    bd = od;
+    bv = ov;
+  }
+  od = dpp_d<kDppSwap2>(bd);
+  ov = dpp_i<kDppSwap2>(bv);
+  if (lex_less(od, ov, bd, bv)) {
+    bd = od;
+    bv = ov;
+  }
+  od = dpp_d<kDppHalfMirror>(bd);
+  ov = dpp_i<kDppHalfMirror>(bv);
+  if (lex_less(od, ov, bd, bv)) {
+    bd = od;
+    bv = ov;
+  }
+}
+
 __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t nif, int64_t gid, bool ok) {
   const int32_t nstray = A.counters[C_NSTRAY];
   const int64_t c = gid / kVsLanes;
@@ -624,16 +698,22 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t
   double bd = DBL_MAX;
   int32_t bv = INT_MAX;
   ok = ok && c < nif;
+  double xc[3] = {0.0, 0.0, 0.0};
+  int32_t p0[kVsNb], cnt[kVsNb], nzo[kVsNb];
   if (ok) {
     const Cell3 cc = unpack_cell(g, A.cell_ids[c]);
-    const double xc[3] = {cell_centre(g.x0, cc.i, g.h), cell_centre(g.y0, cc.j, g.h), cell_centre(g.z0, cc.k, g.h)};
+    xc[0] = cell_centre(g.x0, cc.i, g.h);
+    xc[1] = cell_centre(g.y0, cc.j, g.h);
+    xc[2] = cell_centre(g.z0, cc.k, g.h);
     int64_t wd[kVsNb];
     int sh[kVsNb];
     bool in[kVsNb];
 #pragma unroll
     for (int u = 0; u < kVsNb; ++u) {
-      const int n = l + kVsLanes * u;
-      const int32_t ii = cc.i + n % 3 - 1, jj = cc.j + (n / 3) % 3 - 1, kk = cc.k + n / 9 - 1;
+      const int n = (int)((vs_slot(u) >> (5 * l)) & 31u);
+      const int di = n % 3 - 1, dj = (n / 3) % 3 - 1, dk = n / 9 - 1;
+      const int32_t ii = cc.i + di, jj = cc.j + dj, kk = cc.k + dk;
+      nzo[u] = (di != 0) + (dj != 0) + (dk != 0);
       in[u] = n < 27 && ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
       const int64_t lin = in[u] ? ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk) : 0;
       wd[u] = lin >> 5;
@@ -646,60 +726,26 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t
       bits[u] = in[u] ? A.bitmap[wd[u]] : 0u;
       wo[u] = in[u] ? A.word_off[wd[u]] : 0;
     }
-    int32_t p0[kVsNb], cum[kVsNb + 1];
-    cum[0] = 0;
 #pragma unroll
     for (int u = 0; u < kVsNb; ++u) {
       const bool set = (bits[u] >> sh[u]) & 1u;
       const int32_t cr = wo[u] + __popc(bits[u] & ((1u << sh[u]) - 1u));
       const bool has = set && cr < A.cell_cap;
       p0[u] = has ? A.vb_off[cr] : 0;
-      const int32_t p1 = has ? A.vb_off[cr + 1] : 0;
-      cum[u + 1] = cum[u] + (p1 - p0[u]);
+      cnt[u] = has ? A.vb_off[cr + 1] - p0[u] : 0;
     }
-    // the lane's bins as one list: entry j is entry j - cum[u] of bin u
-    for (int32_t j0 = 0; j0 < cum[kVsNb]; j0 += kVsBatch) {
-      double2 r0[kVsBatch], r1[kVsBatch];
+    scan_bins<0, 1>(A, p0, cnt, xc, bd, bv);
+  }
+  vs_min8(bd, bv);
+  if (ok) {
+    const double q2 = 0.25 * g.h * g.h * (1.0 - 1e-6);
 #pragma unroll
-      for (int q = 0; q < kVsBatch; ++q) {
-        const int32_t j = j0 + q;
-        int32_t p = -1;
-#pragma unroll
-        for (int u = 0; u < kVsNb; ++u)
-          if (j >= cum[u] && j < cum[u + 1]) p = p0[u] + (j - cum[u]);
-        if (p >= 0) {
-          r0[q] = A.vb_rec[2 * (int64_t)p];
-          r1[q] = A.vb_rec[2 * (int64_t)p + 1];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < kVsBatch; ++q)
-        if (j0 + q < cum[kVsNb]) consider_rec(r0[q], r1[q], xc, bd, bv);
-    }
+    for (int u = 1; u < kVsNb; ++u)
+      if (bd < (double)nzo[u] * q2) cnt[u] = 0;
+    scan_bins<1, kVsNb>(A, p0, cnt, xc, bd, bv);
     for (int32_t q = l; q < nstray; q += kVsLanes) consider(A.vtx4, A.stray[q], xc, bd, bv);
   }
-  // the minimum over the cell's 8 lanes (exact, so any pairing serves)
-  static_assert(kVsLanes == 8, "8 lanes per cell");
-  {
-    double od = dpp_d<kDppSwap1>(bd);
-    int32_t ov = dpp_i<kDppSwap1>(bv);
-    if (lex_less(od, ov, bd, bv)) {
-      bd = od;
-      bv = ov;
-    }
-    od = dpp_d<kDppSwap2>(bd);
-    ov = dpp_i<kDppSwap2>(bv);
-    if (lex_less(od, ov, bd, bv)) {
-      bd = od;
-      bv = ov;
-    }
-    od = dpp_d<kDppHalfMirror>(bd);
-    ov = dpp_i<kDppHalfMirror>(bv);
-    if (lex_less(od, ov, bd, bv)) {
-      bd = od;
-      bv = ov;
-    }
-  }
+  vs_min8(bd, bv);
   if (ok && l == 0) {
     A.best_d2[c] = bd;
     A.best_v[c] = bv;
