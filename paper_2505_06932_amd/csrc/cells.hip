@@ -640,17 +640,17 @@ __device__ inline void consider_rec(double2 r0, double2 r1, const double xc[3], 
 
 // The records of the lane's bins of slots [U0, U1) as one list: entry j is
 // entry j - cum[u] of bin u.
-template <int U0, int U1>
+template <int U0, int U1, int B = kVsBatch>
 __device__ inline void scan_bins(const VstarArgs& A, const int32_t (&p0)[kVsNb], const int32_t (&cnt)[kVsNb],
                                  const double xc[3], double& bd, int32_t& bv) {
   int32_t cum[U1 - U0 + 1];
   cum[0] = 0;
 #pragma unroll
   for (int u = U0; u < U1; ++u) cum[u - U0 + 1] = cum[u - U0] + cnt[u];
-  for (int32_t j0 = 0; j0 < cum[U1 - U0]; j0 += kVsBatch) {
-    double2 r0[kVsBatch], r1[kVsBatch];
+  for (int32_t j0 = 0; j0 < cum[U1 - U0]; j0 += B) {
+    double2 r0[B], r1[B];
 #pragma unroll
-    for (int q = 0; q < kVsBatch; ++q) {
+    for (int q = 0; q < B; ++q) {
       const int32_t j = j0 + q;
       int32_t p = -1;
 #pragma unroll
@@ -662,7 +662,7 @@ __device__ inline void scan_bins(const VstarArgs& A, const int32_t (&p0)[kVsNb],
       }
     }
 #pragma unroll
-    for (int q = 0; q < kVsBatch; ++q)
+    for (int q = 0; q < B; ++q)
       if (j0 + q < cum[U1 - U0]) consider_rec(r0[q], r1[q], xc, bd, bv);
   }
 }
@@ -699,7 +699,7 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t
   int32_t bv = INT_MAX;
   ok = ok && c < nif;
   double xc[3] = {0.0, 0.0, 0.0};
-  int32_t p0[kVsNb], cnt[kVsNb], nzo[kVsNb];
+  int32_t p0[kVsNb], cnt[kVsNb];
   if (ok) {
     const Cell3 cc = unpack_cell(g, A.cell_ids[c]);
     xc[0] = cell_centre(g.x0, cc.i, g.h);
@@ -713,7 +713,6 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t
       const int n = (int)((vs_slot(u) >> (5 * l)) & 31u);
       const int di = n % 3 - 1, dj = (n / 3) % 3 - 1, dk = n / 9 - 1;
       const int32_t ii = cc.i + di, jj = cc.j + dj, kk = cc.k + dk;
-      nzo[u] = (di != 0) + (dj != 0) + (dk != 0);
       in[u] = n < 27 && ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
       const int64_t lin = in[u] ? ii + (int64_t)g.nx * (jj + (int64_t)g.ny * kk) : 0;
       wd[u] = lin >> 5;
@@ -740,8 +739,11 @@ __device__ inline void closest_vertex(const Grid& g, const VstarArgs& A, int32_t
   if (ok) {
     const double q2 = 0.25 * g.h * g.h * (1.0 - 1e-6);
 #pragma unroll
-    for (int u = 1; u < kVsNb; ++u)
-      if (bd < (double)nzo[u] * q2) cnt[u] = 0;
+    for (int u = 1; u < kVsNb; ++u) {
+      const int n = (int)((vs_slot(u) >> (5 * l)) & 31u);
+      const int nzo = (n % 3 != 1) + ((n / 3) % 3 != 1) + (n / 9 != 1);
+      if (bd < (double)nzo * q2) cnt[u] = 0;
+    }
     scan_bins<1, kVsNb>(A, p0, cnt, xc, bd, bv);
     for (int32_t q = l; q < nstray; q += kVsLanes) consider(A.vtx4, A.stray[q], xc, bd, bv);
   }
@@ -774,7 +776,7 @@ __global__ __launch_bounds__(kT) void k_place_sort(PlaceArgs A, int32_t nb_place
 
 // Closest vertex of every interfacial cell (its own launch: it needs about
 // twice the registers of the placing).
-__global__ __launch_bounds__(kT) void k_vstar(Grid g, VstarArgs V) {
+__global__ __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(7))) void k_vstar(Grid g, VstarArgs V) {
   const int32_t nif = min(V.counters[C_NIF], V.cell_cap);
   XcdWalk((int64_t)nif * kVsLanes, blockIdx.x, gridDim.x).run([&](int64_t gid, bool ok) {
     closest_vertex(g, V, nif, gid, ok);
