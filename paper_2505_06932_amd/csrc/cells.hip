@@ -137,8 +137,11 @@ __device__ inline int64_t block_alloc(int32_t v, int32_t* counter, int32_t* sh) 
 // clipping to the second (the clipping queue).  Two passes over the cheap
 // classification: count, allocate, write.  A workgroup's queued candidates
 // are written grouped by the set of cell planes their triangle crosses, so
-// that the wavefronts of the clipping mostly take the same branches.
-constexpr int kClassifyT = 512;
+// that the wavefronts of the clipping mostly take the same branches.  768
+// triangles per workgroup make those groups larger than 512 do while two
+// workgroups still fit a CU at this kernel's register count (six wavefronts
+// per SIMD); 1,024 would leave one.
+constexpr int kClassifyT = 768;
 __global__ __launch_bounds__(kClassifyT) void k_tri_classify(Grid g, Mesh m, const double2* vtx4, int4* tri4,
                                                              PairOut P, int64_t q_cap, int32_t* counters) {
   __shared__ int32_t sh[kClassifyT / 64 + 1];
