@@ -335,7 +335,11 @@ def test_coarse_front_support_growth(oracle):
     """Triangles a few cells across: cells whose support must grow, and
     about 250 clip candidates whose polygons pass six corners, which the
     clipping kernel clips again with nine slots (counted on the CPU by
-    test_host_clip.py on this same front)."""
+    test_host_clip.py on this same front).  Most cells' closest vertex lies
+    beyond their face neighbours (at least (h/2)^2 * 2 or * 3 squared), so
+    the closest-vertex search reads their edge and corner bins, and some lie
+    beyond 1.5 h, where the curvature kernel searches all vertices; the
+    closest vertices are compared exactly (diag column 0)."""
     grid = I.Grid(64, 64, 64, 0.0, 0.0, 0.0, 1.0 / 64)
     rng = np.random.default_rng(2)
     c = 0.5 + rng.uniform(-grid.h, grid.h, 3)
@@ -346,6 +350,12 @@ def test_coarse_front_support_growth(oracle):
     check_alpha(g, o)
     check_ppic(g, o, grid.h)
     assert g["diag"][:, 3].max() > 0
+    cells = o["cells"]
+    ijk = np.stack([cells % grid.nx, (cells // grid.nx) % grid.ny, cells // (grid.nx * grid.ny)], 1)
+    centre = np.array([grid.x0, grid.y0, grid.z0]) + (ijk + 0.5) * grid.h
+    vs = o["diag"][:, 0]
+    q = (((np.stack([mesh.x, mesh.y, mesh.z], 1)[vs] - centre) ** 2).sum(1)) / grid.h**2
+    assert (q >= 0.75).sum() > 1000 and q.max() > 2.25
 
 
 def test_high_valence_rings_take_the_wide_shape(oracle):
