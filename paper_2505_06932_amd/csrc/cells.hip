@@ -798,7 +798,10 @@ hipError_t launch_cell_lists(ftc_cells* ws, const Mesh& m, hipStream_t s) {
   time_start(ws, FTC_KERNEL_TRI_PIECES, s);
   hipLaunchKernelGGL(k_tri_classify, dim3(round_up_xcd(grid_blocks(m.nt, kClassifyT))), dim3(kClassifyT), 0, s, g, m,
                      vtx4, tri4, P, ws->queue_cap, ws->counters);
-  const int32_t nb_clip = round_up_xcd(grid_blocks(ws->queue_cap, kPieceLanes, 8192));
+  // up to 16,384 one-wavefront clip workgroups, four rounds at four per SIMD:
+  // shorter walks per workgroup even out the candidates' uneven cost
+  // (8,192 and 4,096 were slower at 512^3)
+  const int32_t nb_clip = round_up_xcd(grid_blocks(ws->queue_cap, kPieceLanes, 16384));
   const int32_t nb_mark = round_up_xcd(grid_blocks(ws->pair_cap, kPieceLanes, 4096));
   hipLaunchKernelGGL(k_clip_mark, dim3(nb_clip + nb_mark), dim3(kPieceLanes), 0, s, g, tri4, vtx4, P, ws->queue_cap,
                      ws->bitmap, ws->counters, nb_clip);
